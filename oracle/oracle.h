@@ -1,0 +1,121 @@
+/* FP64 CPU oracle of the normalized-RRS wavefront path tracer.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code with
+ * the HIP path: everything here (random numbers, intersection, sampling,
+ * normalization, roulette, network) is written separately from the paper's
+ * definitions, in double precision, with plain loops.
+ *
+ * Paper references (NRRS, arXiv 2510.07868):
+ *   rendering equation / MC estimator          Sec. 3, Eqs. (1)-(2)
+ *   stochastic rounding of the RRS factor      Sec. 3, Eq. (8)
+ *   wavefront stages, terminate on light/miss  Sec. 3, "Wavefront Architecture"
+ *   per-depth normalization                    Sec. 4.1.2, Eqs. (9)-(11)
+ *   rate control / adaptive alpha              Sec. 4.1.4, Eqs. (12)-(14)
+ *   downscale-only compromise                  Sec. 5, "Compromise"
+ *   modified softplus output                   Sec. 5, Eq. (22)
+ *   Box-Cox / roughness remap input encodings  Sec. 5, "Input Encoding"
+ *   ADRRS ratio for q                          Sec. 2.2 (ADRRS paragraph)
+ */
+#ifndef NRRS_ORACLE_H
+#define NRRS_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OR_NPARAM 9729   /* 20-64-64-64-1 MLP */
+#define OR_NFEAT 20
+#define OR_MAXD 64
+
+enum { OR_MODE_OFF = 0, OR_MODE_HEUR = 1, OR_MODE_NET = 2 };
+enum { OR_NORM_TWO_SIDED = 0, OR_NORM_DOWNSCALE = 1 };
+
+typedef struct or_scene or_scene;
+
+typedef struct {
+  uint32_t width, height, s_batch, max_depth;
+  uint32_t pass_begin, n_passes;
+  int32_t mode, norm_mode, net_max_depth, frozen;
+  double cap_factor, f_rate;
+  uint64_t seed;
+  double alpha;          /* in: adaptive rate alpha; out: value after the render */
+  double p_train;        /* probability that a primary path records training vertices */
+  uint32_t rec_cap;      /* capacity of the record arrays (0 = no records) */
+  uint32_t update_guide; /* 1: refresh the guide image from the running mean after each pass */
+  double tau;            /* near-tie margin for the fragile-pixel flags */
+} or_cfg;
+
+typedef struct {
+  uint64_t n[OR_MAXD + 1];        /* queue entries entering extend at depth d (summed over passes) */
+  uint64_t active[OR_MAXD + 1];   /* entries with q > 0 */
+  uint64_t S[OR_MAXD + 1];        /* children emitted at depth d (summed) */
+  uint64_t retries[OR_MAXD + 1];  /* overflow-guard retries */
+  double sumq[OR_MAXD + 1];       /* last pass: FP64 sum of q_orig */
+  double F[OR_MAXD + 1];          /* last pass: normalization factor */
+  uint64_t rays;                  /* rays traced (non-dead entries extended) */
+  uint64_t n_records;             /* records written (<= rec_cap) */
+  int32_t status;                 /* 0 ok, -5 alpha fell below 1e-3 */
+} or_stats;
+
+/* Scene from the generator's arrays; build_bvh=0 forces brute-force closest hit. */
+or_scene* or_scene_create(const float* verts, uint64_t nv, const uint32_t* tris, uint64_t nt,
+                          const uint32_t* tri_mat, const uint32_t* mat_type, const float* mat_params,
+                          uint32_t nm, const float* camera, const float* env, int32_t build_bvh);
+void or_scene_destroy(or_scene* s);
+
+/* Philox4x32-10 (Salmon et al., SC'11). */
+void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Closest hit for n rays (origin xyz, dir xyz, exclude prim) -> prim (0xffffffff = miss), t, b1, b2. */
+void or_trace(const or_scene* s, const double* rays, const uint32_t* exclude, uint64_t n,
+              uint32_t* prim, double* t, double* b1, double* b2, int32_t use_bvh);
+
+/* Normalization + roulette + exclusive scan on a host array of q_orig (Eqs. 8-14).
+ * Outputs X, offsets, parent_of_child[S], S, F, q_norm (FP32 values as doubles),
+ * the alpha after the overflow guard and the retry count.  u[i] are the uniforms.
+ * Returns 0, or -5 when alpha falls below 1e-3. */
+int32_t or_rrs_expand(const double* q_orig, const double* u, uint64_t n, double budget_base,
+                      double f_rate, double* alpha, int32_t norm_mode, uint64_t cap,
+                      uint32_t* X, uint64_t* offset, uint32_t* parent_of_child, uint64_t* S,
+                      double* F, float* q_norm, uint32_t* retries);
+
+/* Full render: accumulates radiance sums into image[W*H*3] (not divided by spp). */
+int32_t or_render(const or_scene* s, or_cfg* cfg, const double* params, double* guide,
+                  double* image, uint8_t* fragile, or_stats* stats,
+                  double* rec_feat, double* rec_lumt, double* rec_acc, uint32_t* rec_depth,
+                  uint32_t* rec_pix, uint64_t* rec_id);
+
+/* Exhaustive expectation over all roulette outcomes with frozen continuous samples
+ * (every child of a vertex reuses the sample of child 0).  Writes the outcome-weighted
+ * mean image of one pass and the OFF-mode image on the same samples.  Also returns the
+ * largest S seen on any branch and the number of branches. */
+int32_t or_enumerate(const or_scene* s, const or_cfg* cfg, double* image_expect, double* image_off,
+                     uint64_t* max_S, uint64_t* branches);
+
+/* Network (Sec. 5): 20 -> 64 -> 64 -> 64 (ReLU) -> 1, modified softplus output. */
+void or_mlp_forward(const double* params, const double* x, uint64_t n, double* y, double* z);
+/* Loss mean((ln(y+eps) - ln(L+eps))^2); gradient w.r.t. all parameters. */
+double or_mlp_loss_grad(const double* params, const double* x, const double* target, uint64_t n,
+                        double eps, double* grad);
+void or_adam(double* params, double* m, double* v, const double* grad, uint64_t np, uint64_t step,
+             double lr, double b1, double b2, double eps);
+double or_softplus_mod(double z);
+int32_t or_num_threads(void);
+double or_softplus_mod_grad(double z);
+
+/* BSDF helpers exposed for the closed-form pins.  Directions are in the local frame (n = +z). */
+double or_ggx_D(double alpha, const double h[3]);
+double or_ggx_G1(double alpha, const double w[3]);
+double or_ggx_G2(double alpha, const double wo[3], const double wi[3]);
+/* Sample: returns 1 if wi is above the surface; w_out = f*cos/pdf (scalar F0 channel). */
+int32_t or_ggx_sample(double alpha, double f0, const double wo[3], double u1, double u2,
+                      double wi[3], double* weight, double* pdf);
+double or_ggx_eval_cos(double alpha, double f0, const double wo[3], const double wi[3]);
+void or_lambert_sample(double u1, double u2, double wi[3], double* pdf);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
