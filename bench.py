@@ -1,0 +1,191 @@
+"""Benchmark of the normalized-RRS wavefront path tracer on one MI355X.
+
+A step is one NRRS frame over the 512x512 heightfield workload (about 1.05 M triangles,
+16 spp traced as one 4.19 M-path wavefront, max depth 16): the full bounce loop
+(camera, extend, shade, RRS network at depth <= 4, FP64 normalization, roulette/split
+expansion, FP64 pixel accumulation, training-record capture) followed by one train_step
+on 2^18 records.  `value` is rays extended per second (Mpaths/s) over the timed steps.
+
+Also reported, outside the timed region: the render efficiency 1/(relMSE * t) of the
+trained network (NRRS) and of plain heuristic normalized RRS at equal spp against a
+high-spp reference, the roofline of the dominant kernel from HIP events recorded on the
+render stream, and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "render efficiency 1/(relMSE·s) + Mpaths/s, NRRS vs plain norm. RRS, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+LUM = np.array([0.2126, 0.7152, 0.0722])
+
+
+def relmse(img, ref):
+    return float(np.mean((img - ref) ** 2 / (ref ** 2 + 0.01)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--width", type=int, default=512)
+    ap.add_argument("--spp", type=int, default=16)
+    ap.add_argument("--depth", type=int, default=16)
+    ap.add_argument("--ref-spp", type=int, default=1024)
+    ap.add_argument("--eval-renders", type=int, default=4)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-eff", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU sharding of the "
+              "render is described in DESIGN.md and is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2510_07868_amd import nrrs, scenes
+
+    prec = {"fp32": nrrs.PREC_FP32, "bf16": nrrs.PREC_BF16, "fp8": nrrs.PREC_FP8}[args.precision]
+    W = H = args.width
+    spp = args.spp
+    D = args.depth
+    nprim = W * H * spp
+    rec_n = 1 << 18
+    minibatch = 1 << 14
+    p_train = min(1.0, 0.025 * (4194304 / nprim))
+    t_scene = time.time()
+    sc = scenes.heightfield(0)
+    r = nrrs.Renderer(W, H, s_batch=spp, cap_factor=2.0, seed=0, net_max_depth=4, precision=prec,
+                      records_cap=rec_n, p_train=p_train, max_tris=sc.n_tris, max_materials=len(sc.mat_type))
+    r.upload_scene(sc)
+    t_upload = time.time() - t_scene
+    r.set_timing(True)
+    print(f"# scene {sc.n_tris} tris, setup+BVH {t_upload:.1f}s, workspace {r.workspace_bytes / 2**30:.2f} GiB",
+          flush=True)
+
+    def step():
+        st = r.render(spp, D, nrrs.MODE_NET)
+        n = min(st["records"], rec_n) // minibatch * minibatch
+        loss = r.train_step(n, minibatch, 5e-3) if n > 0 else float("nan")
+        return st, loss, n
+
+    for w in range(args.warmup):
+        st, loss, n = step()
+        print(f"# warmup {w}: rays {st['rays']}, records {st['records']}, loss {loss:.4f}", flush=True)
+    r.reset_image()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rays = 0
+    stage_ms = {k: 0.0 for k in nrrs.STAGES}
+    stage_n = {k: 0 for k in nrrs.STAGES}
+    nodes = tris = 0
+    for k in range(args.steps):
+        st, loss, n = step()
+        rays += st["rays"]
+        nodes += st["nodes_visited"]
+        tris += st["tris_tested"]
+        for s in nrrs.STAGES:
+            stage_ms[s] += st["stage_ms"][s]
+            stage_n[s] += st["stage_launches"][s]
+        print(f"# step {k}: rays {st['rays']}, loss {loss:.4f}, trained on {n}", flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    secs = t1 - t0
+    mpaths = rays / secs / 1e6
+
+    # roofline of the dominant kernel (traversal): bytes the algorithm reads and writes per
+    # launch = 64 B of queue I/O per ray + 64 B per BVH node visited + 48 B per triangle tested
+    dom = max(nrrs.STAGES, key=lambda s: stage_ms[s])
+    ext_launches = max(stage_n["extend"], 1)
+    ext_ms = stage_ms["extend"] / ext_launches
+    ext_bytes = (64.0 * rays + 64.0 * nodes + 48.0 * tris) / ext_launches
+    achieved = ext_bytes / (ext_ms * 1e-3) / 1e9
+    roofline = {"kernel": "k_extend", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_ms": round(ext_ms, 4), "algorithmic_bytes_per_launch": int(ext_bytes),
+                "nodes_per_ray": round(nodes / max(rays, 1), 2), "tris_per_ray": round(tris / max(rays, 1), 2),
+                "grays_per_s": round(rays / (stage_ms["extend"] * 1e-3) / 1e9, 3),
+                "dominant_stage": dom}
+
+    out = {
+        "metric": METRIC, "value": round(mpaths, 2), "unit": "Mpaths/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(secs / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == nrrs.PREC_FP32 else args.precision + "+f32",
+        "data": "synthetic",
+        "config": {"workload": f"heightfield {sc.n_tris} tris, {W}x{H}, {spp} spp in one {nprim}-path wavefront, "
+                               f"max depth {D}, NRRS (network at depth<=4) + train_step(2^18 records)",
+                   "width": W, "height": H, "spp": spp, "max_depth": D, "triangles": sc.n_tris,
+                   "queue_capacity": 2 * nprim, "parallelism": "single GPU"},
+        "stage_ms_per_step": {s: round(stage_ms[s] / args.steps, 3) for s in nrrs.STAGES},
+        "roofline": roofline,
+    }
+
+    if not args.no_eff:
+        out["efficiency"] = efficiency(r, nrrs, spp, D, args.ref_spp, args.eval_renders)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(sc, W, H, D)
+    print(json.dumps(out), flush=True)
+
+
+def efficiency(r, nrrs, spp, D, ref_spp, renders):
+    """relMSE and 1/(relMSE * t) of NRRS and heuristic normalized RRS at equal spp."""
+    import torch
+
+    res = {}
+    for name, mode in (("nrrs", nrrs.MODE_NET), ("heuristic", nrrs.MODE_HEURISTIC)):
+        errs, times, imgs = [], [], []
+        guide = r.get_guide()
+        for k in range(renders):
+            r.set_guide(guide)          # every evaluation render sees the same previous frame
+            r.reset_image()             # the pass counter keeps counting: fresh random numbers
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r.render(spp, D, mode, stats=False)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            img, _ = r.read_image()
+            imgs.append(img)
+        res[name] = {"times": times, "imgs": imgs}
+        r.set_guide(guide)
+    r.reset_image()
+    t0 = time.perf_counter()
+    r.render(ref_spp, D, nrrs.MODE_OFF, stats=False)
+    ref, _ = r.read_image()
+    t_ref = time.perf_counter() - t0
+    out = {"reference": f"plain path tracing, {ref_spp} spp, same depth", "reference_s": round(t_ref, 2),
+           "spp": spp}
+    for name, d in res.items():
+        rm = float(np.mean([relmse(i, ref) for i in d["imgs"]]))
+        t = float(np.median(d["times"]))
+        out[name] = {"relmse": rm, "render_s": round(t, 5), "efficiency": 1.0 / (rm * t)}
+    out["nrrs_over_heuristic"] = out["nrrs"]["efficiency"] / out["heuristic"]["efficiency"]
+    return out
+
+
+def cpu_baseline(sc, W, H, D):
+    import oracle
+
+    osc = oracle.OracleScene(sc)
+    cfg = oracle.make_cfg(W, H, 1, D, n_passes=1, mode=oracle.MODE_HEUR, tau=0.0)
+    t0 = time.perf_counter()
+    o = oracle.render(osc, cfg)
+    secs = time.perf_counter() - t0
+    return {"value": round(o["rays"] / secs / 1e6, 3), "unit": "Mpaths/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "seconds": round(secs, 2),
+            "sample": f"1 spp of the same {W}x{H} heightfield workload (one {W * H}-path wavefront, max depth {D}, "
+                      "heuristic normalized RRS), FP64 C oracle with OpenMP; BVH build excluded"}
+
+
+if __name__ == "__main__":
+    main()

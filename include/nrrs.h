@@ -1,0 +1,226 @@
+/* nrrs.h -- C ABI of the MI355X (gfx950) normalized-RRS wavefront path tracer.
+ *
+ * The library renders with unidirectional path tracing in a wavefront loop
+ * (extend -> shade -> [RRS network] -> normalization -> roulette/split ->
+ * compaction), following NRRS: Neural Russian Roulette and Splitting
+ * (arXiv 2510.07868):
+ *   - one-sample estimator of the rendering equation      Sec. 3, Eqs. (1)-(2)
+ *   - stochastic rounding of an RRS factor into children  Sec. 3, Eq. (8)
+ *   - per-depth normalization of the factors              Sec. 4.1.2, Eqs. (9)-(11)
+ *   - rate control and adaptive alpha on overflow          Sec. 4.1.4, Eqs. (12)-(14)
+ *   - downscale-only normalization                         Sec. 5, "Compromise"
+ *   - RRS network output activation (modified softplus)    Sec. 5, Eq. (22)
+ *   - depth-gated use of the network (Mix-Depth)           Sec. 4.3
+ *   - ADRRS ratio for the factor from a radiance estimate  Sec. 2.2
+ *
+ * Conventions common to every call:
+ *   - Every call returns an nrrs_status (0 = NRRS_OK, negative = error).  On
+ *     error the context is left as it was before the call unless stated.
+ *   - No C++ exception crosses this boundary.  A context is used from one host
+ *     thread at a time.
+ *   - "host" pointers are ordinary CPU memory owned by the caller and only read
+ *     or written during the call.  "device" pointers are HIP device memory owned
+ *     by the caller.
+ *   - Work is queued on the HIP stream given to nrrs_create; calls that return
+ *     host data synchronize that stream first.
+ */
+#ifndef NRRS_H
+#define NRRS_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nrrs_ctx nrrs_ctx;
+
+enum nrrs_status {
+  NRRS_OK = 0,
+  NRRS_EINVAL = -1,      /* bad argument; context unchanged */
+  NRRS_ESTATE = -2,      /* call out of order (e.g. render before upload) */
+  NRRS_ENOMEM = -3,      /* bound workspace too small for the request */
+  NRRS_EHIP = -4,        /* HIP runtime error; nrrs_last_error has the message */
+  NRRS_EOVERFLOW = -5,   /* the overflow guard could not fit the queue (see nrrs_render) */
+  NRRS_EUNSUPPORTED = -6 /* device is not gfx950, or feature not available */
+};
+
+enum nrrs_mode {
+  NRRS_MODE_OFF = 0,       /* plain path tracing: factor 1, no normalization */
+  NRRS_MODE_HEURISTIC = 1, /* normalized RRS with q = lum(throughput * albedo) */
+  NRRS_MODE_NET = 2        /* normalized RRS with the network factor at depth <= net_max_depth */
+};
+
+enum nrrs_norm { NRRS_NORM_TWO_SIDED = 0, NRRS_NORM_DOWNSCALE = 1 };
+
+enum nrrs_precision { NRRS_PREC_FP32 = 0, NRRS_PREC_BF16 = 1, NRRS_PREC_FP8 = 2 };
+
+enum nrrs_material_type { NRRS_MAT_LAMBERT = 0, NRRS_MAT_GGX = 1, NRRS_MAT_EMITTER = 2 };
+
+#define NRRS_MAX_DEPTH 64
+#define NRRS_NSTAGES 8 /* camera, extend, shade, network, sum, roulette+scan, expand, pass end */
+#define NRRS_NPARAM 9729 /* 20-64-64-64-1 network: weights and biases */
+
+typedef struct {
+  uint32_t width, height; /* image size in pixels, each >= 1 */
+  uint32_t s_batch;       /* samples per pixel traced together in one wavefront pass (>= 1) */
+  double cap_factor;      /* queue capacity C = floor(cap_factor * W * H * s_batch), >= 1 */
+  double f_rate;          /* rate-control factor of Eq. (12); 1.0 = plain normalization */
+  int32_t norm_mode;      /* nrrs_norm */
+  uint64_t seed;          /* Philox4x32-10 key */
+  int32_t net_max_depth;  /* vertices at depth <= this use the network in NET mode (0..4) */
+  int32_t precision;      /* nrrs_precision of network inference */
+  uint32_t records_cap;   /* capacity of the training-record buffer (0 = no records) */
+  double p_train;         /* probability that a primary path records training vertices */
+} nrrs_config;
+
+typedef struct {
+  uint32_t max_depth, passes;
+  uint64_t n[NRRS_MAX_DEPTH + 1];       /* queue entries entering depth d, summed over passes */
+  uint64_t S[NRRS_MAX_DEPTH + 1];       /* children emitted at depth d, summed over passes */
+  uint64_t retries[NRRS_MAX_DEPTH + 1]; /* overflow-guard alpha reductions at depth d */
+  double sumq[NRRS_MAX_DEPTH + 1];      /* FP64 sum of the raw factors at depth d (last pass) */
+  double F[NRRS_MAX_DEPTH + 1];         /* normalization factor at depth d (last pass) */
+  double alpha;                         /* adaptive-rate alpha after the render */
+  uint64_t rays;                        /* rays traced (queue entries that were not dead) */
+  uint64_t nodes_visited;               /* BVH nodes visited by all traversals */
+  uint64_t tris_tested;                 /* ray-triangle tests by all traversals */
+  uint64_t records;                     /* training records held after the render */
+  uint32_t overflow;                    /* 1 if the guard could not fit a depth (pass truncated) */
+  uint32_t timed;                       /* 1 if stage_ms / stage_launches were measured */
+  double stage_ms[NRRS_NSTAGES];        /* GPU time per stage (HIP events on the context stream) */
+  uint64_t stage_launches[NRRS_NSTAGES];/* launches (kernel groups) per stage */
+} nrrs_render_stats;
+
+/* Create a context.  cfg: see nrrs_config (copied).  hip_stream: a hipStream_t owned by
+ * the caller (may be NULL for the null stream); it must outlive the context.  *out
+ * receives the context.  EINVAL on a bad config, EUNSUPPORTED if the current device is
+ * not gfx950, EHIP on a runtime failure. */
+int32_t nrrs_create(const nrrs_config* cfg, void* hip_stream, nrrs_ctx** out);
+
+/* Bytes of device workspace needed for scenes of up to max_tris triangles and
+ * max_materials materials.  The caller allocates it (any HIP allocator). */
+int32_t nrrs_workspace_size(const nrrs_ctx* ctx, uint64_t max_tris, uint32_t max_materials,
+                            uint64_t* bytes);
+
+/* Bind caller-owned device memory of `bytes` bytes (256-byte aligned) as the workspace.
+ * The library never allocates device memory itself.  The memory must stay valid until
+ * nrrs_destroy or the next bind.  Binding clears the image, records and guide. */
+int32_t nrrs_bind_workspace(nrrs_ctx* ctx, void* device_ptr, uint64_t bytes, uint64_t max_tris,
+                            uint32_t max_materials);
+
+/* Upload a triangle scene (host arrays, copied during the call; nothing is retained):
+ *   verts[nv*3] float xyz; tris[nt*3] vertex indices; tri_mat[nt] material per triangle;
+ *   mat_type[nm] nrrs_material_type; mat_params[nm*7] = (rho rgb, ggx alpha, Le rgb) where
+ *   rho is the Lambertian albedo or the GGX F0; camera[10] = eye xyz, look-at xyz, up xyz,
+ *   vertical fov in degrees; env[3] constant radiance seen by rays that miss.
+ * A triangle emits (Le) on the side of cross(v1-v0, v2-v0).  Builds a BVH on the host
+ * (binned SAH) and copies it to the workspace.  EINVAL on out-of-range indices,
+ * non-finite values or nt == 0; ENOMEM if nt or nm exceed the bound workspace. */
+int32_t nrrs_upload_scene(nrrs_ctx* ctx, const float* verts, uint64_t nv, const uint32_t* tris,
+                          uint64_t nt, const uint32_t* tri_mat, const uint32_t* mat_type,
+                          const float* mat_params, uint32_t nm, const float* camera, const float* env);
+
+/* Render spp samples per pixel (spp a multiple of s_batch: spp / s_batch wavefront passes)
+ * with paths of at most max_depth vertices (1..64) and the given nrrs_mode.  Radiance is
+ * accumulated in FP64 per pixel across calls until nrrs_reset_image.  In HEURISTIC and
+ * NET modes training records are captured when records_cap > 0.  Asynchronous unless
+ * stats is non-NULL, in which case the stream is synchronized and the per-depth
+ * statistics of this call are written.  NET mode without a guide image (no earlier
+ * render, nor nrrs_set_guide) uses the heuristic factor.  EOVERFLOW is returned (with
+ * stats) when at some depth no alpha among 32 successive reductions fit the queue;
+ * that pass was truncated at that depth. */
+int32_t nrrs_render(nrrs_ctx* ctx, uint32_t spp, uint32_t max_depth, int32_t mode,
+                    nrrs_render_stats* stats);
+
+/* One training epoch of the network on the first n_records records of the last render
+ * (records are cleared by each render that captures them): minibatches of `minibatch`
+ * records, one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) each, loss
+ * mean((ln(y+0.01) - ln(L+0.01))^2) with L the record's reflected-radiance target.
+ * *loss_or_null receives the mean loss of the epoch (synchronizes).  ESTATE if fewer than
+ * n_records records exist; EINVAL if minibatch is 0 or does not divide n_records. */
+int32_t nrrs_train_step(nrrs_ctx* ctx, uint32_t n_records, uint32_t minibatch, float lr,
+                        float* loss_or_null);
+
+/* Copy the mean radiance (sum / spp_total, W*H*3 doubles, row-major from the top image row)
+ * to host_rgb, and the samples per pixel so far to *spp_total.  Synchronizes. */
+int32_t nrrs_read_image(nrrs_ctx* ctx, double* host_rgb, uint64_t* spp_total);
+
+/* Zero the image accumulator and the sample count and reset alpha to 1.  The guide is kept,
+ * and the pass counter that keys the random numbers keeps counting (a new render after a
+ * reset draws fresh random numbers). */
+int32_t nrrs_reset_image(nrrs_ctx* ctx);
+
+/* Guide image: per-pixel luminance of the previous mean radiance, used as the pixel
+ * estimate in the NET factor (Sec. 5 "Compromise").  set: host lum[W*H] (negative = no
+ * history for that pixel).  get: copies it out.  Each render pass refreshes it. */
+int32_t nrrs_set_guide(nrrs_ctx* ctx, const float* host_lum);
+int32_t nrrs_get_guide(nrrs_ctx* ctx, float* host_lum);
+
+/* Network state: FP32 master parameters[NRRS_NPARAM], Adam m and v (same size) and the
+ * Adam step count.  Layout of the parameter vector: W1[64][20], b1[64], W2[64][64], b2[64],
+ * W3[64][64], b3[64], W4[64], b4.  Any pointer may be NULL to skip that part.  set also
+ * refreshes the BF16 / FP8 inference copies. */
+int32_t nrrs_get_params(nrrs_ctx* ctx, float* master, float* adam_m, float* adam_v, uint64_t* step);
+int32_t nrrs_set_params(nrrs_ctx* ctx, const float* master, const float* adam_m,
+                        const float* adam_v, const uint64_t* step);
+
+/* Enable (1) or disable (0) per-stage GPU timing of nrrs_render with HIP events recorded on
+ * the context stream between the stages; results appear in nrrs_render_stats. */
+int32_t nrrs_set_timing(nrrs_ctx* ctx, int32_t enabled);
+
+/* Training records of the last render: count, and optionally (each may be NULL)
+ * features[n*20], lum_t[n], acc[n] (descendant emission luminance), depth[n], pix[n],
+ * lineage id[n] (64-bit).  The record order is not deterministic. */
+int32_t nrrs_read_records(nrrs_ctx* ctx, uint64_t* n, float* features, float* lum_t, float* acc,
+                          uint32_t* depth, uint32_t* pix, uint64_t* lineage);
+
+/* --- test entry points: the same kernels on caller-provided inputs (host arrays) ----- */
+
+/* Normalization, stochastic rounding, overflow guard and exclusive scan (Eqs. 8-14) of
+ * n raw factors q_orig[n] whose uniforms come from Philox keyed by lineage ids
+ * id_lo[n], id_hi[n] at `depth` (purpose 1).  budget_base is N_px; *alpha in/out.
+ * Outputs X[n], offset[n], parent_of_child[S] (parent-major compaction), *S, *F,
+ * q_norm[n] (may be NULL), *retries.  cap is the queue capacity (<= n * 64). */
+int32_t nrrs_debug_rrs_expand(nrrs_ctx* ctx, const float* q_orig, const uint32_t* id_lo,
+                              const uint32_t* id_hi, uint32_t n, uint32_t depth, double budget_base,
+                              double f_rate, double* alpha, int32_t norm_mode, uint32_t cap,
+                              uint32_t* X, uint32_t* offset, uint32_t* parent_of_child,
+                              uint32_t* S, double* F, float* q_norm, uint32_t* retries);
+
+/* Replace the record buffer with n host records: features[n*20], lum_t[n], acc[n] (the
+ * target is acc / lum_t).  ENOMEM if n > records_cap. */
+int32_t nrrs_debug_load_records(nrrs_ctx* ctx, const float* features, const float* lum_t,
+                                const float* acc, uint32_t n);
+
+/* Closest hit of n rays[n*6] (origin, unit direction) against the uploaded scene, skipping
+ * triangle exclude[n] (original index; 0xffffffff = none).  Outputs the original triangle
+ * index (0xffffffff = miss), t, and barycentrics b1, b2. */
+int32_t nrrs_debug_trace(nrrs_ctx* ctx, const float* rays, const uint32_t* exclude, uint32_t n,
+                         uint32_t* prim, float* t, float* b1, float* b2);
+
+/* Philox4x32-10 on n counters ctr[n*4] with key[2] -> out[n*4]. */
+int32_t nrrs_debug_philox(nrrs_ctx* ctx, const uint32_t* ctr, const uint32_t* key, uint32_t n,
+                          uint32_t* out);
+
+/* Network forward y[n] (and raw output z[n], may be NULL) of features x[n*20] with the
+ * current parameters in the given nrrs_precision. */
+int32_t nrrs_debug_mlp_forward(nrrs_ctx* ctx, const float* x, uint32_t n, int32_t precision,
+                               float* y, float* z);
+
+/* Loss and its gradient grad[NRRS_NPARAM] over n (features x[n*20], target[n]) rows with the
+ * current FP32 masters; no parameter update. */
+int32_t nrrs_debug_mlp_grad(nrrs_ctx* ctx, const float* x, const float* target, uint32_t n,
+                            float* grad, float* loss);
+
+/* Status text (static storage) and the context's last error message (valid until the next
+ * call on ctx). */
+const char* nrrs_status_string(int32_t status);
+const char* nrrs_last_error(const nrrs_ctx* ctx);
+
+/* Destroy a context (NULL is ignored).  Does not free the caller's workspace. */
+void nrrs_destroy(nrrs_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NRRS_H */

@@ -67,7 +67,8 @@ def lib():
         L.or_scene_create.argtypes = [P, C.c_uint64, P, C.c_uint64, P, P, P, C.c_uint32, P, P, C.c_int32]
         L.or_scene_destroy.argtypes = [P]
         L.or_philox.argtypes = [P, P, P]
-        L.or_trace.argtypes = [P, P, P, C.c_uint64, P, P, P, P, C.c_int32]
+        L.or_philox_batch.argtypes = [P, P, C.c_uint64, P]
+        L.or_trace.argtypes = [P, P, P, C.c_uint64, P, P, P, P, C.c_int32, C.c_double, P]
         L.or_rrs_expand.restype = C.c_int32
         L.or_rrs_expand.argtypes = [P, P, C.c_uint64, C.c_double, C.c_double, P, C.c_int32, C.c_uint64,
                                     P, P, P, P, P, P, P]
@@ -139,14 +140,26 @@ def philox(ctr, key) -> np.ndarray:
     return out
 
 
-def trace(sc: OracleScene, rays: np.ndarray, exclude=None, bvh=None):
+def philox_batch(ctr, key) -> np.ndarray:
+    c = _c(ctr, np.uint32).reshape(-1, 4)
+    k = _c(key, np.uint32)
+    out = np.zeros_like(c)
+    lib().or_philox_batch(_p(c), _p(k), c.shape[0], _p(out))
+    return out
+
+
+def trace(sc: OracleScene, rays: np.ndarray, exclude=None, bvh=None, tau=0.0, with_fragile=False):
     rays = _c(rays, np.float64).reshape(-1, 6)
     n = rays.shape[0]
     ex = _c(exclude if exclude is not None else np.full(n, MISS), np.uint32)
     prim = np.zeros(n, np.uint32)
     t, b1, b2 = (np.zeros(n) for _ in range(3))
+    frag = np.zeros(n, np.uint8)
     use = sc.bvh if bvh is None else bvh
-    lib().or_trace(sc.h, _p(rays), _p(ex), n, _p(prim), _p(t), _p(b1), _p(b2), 1 if use else 0)
+    lib().or_trace(sc.h, _p(rays), _p(ex), n, _p(prim), _p(t), _p(b1), _p(b2), 1 if use else 0, float(tau),
+                   _p(frag))
+    if with_fragile:
+        return prim, t, b1, b2, frag.astype(bool)
     return prim, t, b1, b2
 
 

@@ -54,6 +54,10 @@ void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
   out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
+void or_philox_batch(const uint32_t* ctr, const uint32_t key[2], uint64_t n, uint32_t* out) {
+  for (uint64_t i = 0; i < n; ++i) or_philox(ctr + 4 * i, key, out + 4 * i);
+}
+
 static double u01(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
 
 static void rng_block(uint64_t seed, uint32_t id_lo, uint32_t id_hi, uint32_t purpose, uint32_t depth,
@@ -341,12 +345,13 @@ static int trace_one(const or_scene* s, const double o[3], const double d[3], ui
 }
 
 void or_trace(const or_scene* s, const double* rays, const uint32_t* exclude, uint64_t n, uint32_t* prim,
-              double* t, double* b1, double* b2, int32_t use_bvh) {
+              double* t, double* b1, double* b2, int32_t use_bvh, double tau, uint8_t* fragile) {
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t i = 0; i < (int64_t)n; ++i) {
     double o[3] = {rays[6 * i], rays[6 * i + 1], rays[6 * i + 2]};
     double d[3] = {rays[6 * i + 3], rays[6 * i + 4], rays[6 * i + 5]};
-    trace_one(s, o, d, exclude ? exclude[i] : MISS, use_bvh, 0.0, &prim[i], &t[i], &b1[i], &b2[i]);
+    int f = trace_one(s, o, d, exclude ? exclude[i] : MISS, use_bvh, tau, &prim[i], &t[i], &b1[i], &b2[i]);
+    if (fragile) fragile[i] = (uint8_t)f;
   }
 }
 

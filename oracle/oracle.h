@@ -67,10 +67,13 @@ void or_scene_destroy(or_scene* s);
 
 /* Philox4x32-10 (Salmon et al., SC'11). */
 void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void or_philox_batch(const uint32_t* ctr, const uint32_t key[2], uint64_t n, uint32_t* out);
 
-/* Closest hit for n rays (origin xyz, dir xyz, exclude prim) -> prim (0xffffffff = miss), t, b1, b2. */
+/* Closest hit for n rays (origin xyz, dir xyz, exclude prim) -> prim (0xffffffff = miss), t, b1, b2.
+ * fragile[i] (may be NULL) flags decisions within tau of changing (near-ties). */
 void or_trace(const or_scene* s, const double* rays, const uint32_t* exclude, uint64_t n,
-              uint32_t* prim, double* t, double* b1, double* b2, int32_t use_bvh);
+              uint32_t* prim, double* t, double* b1, double* b2, int32_t use_bvh, double tau,
+              uint8_t* fragile);
 
 /* Normalization + roulette + exclusive scan on a host array of q_orig (Eqs. 8-14).
  * Outputs X, offsets, parent_of_child[S], S, F, q_norm (FP32 values as doubles),

@@ -1,0 +1,840 @@
+// Host runtime of the C ABI declared in include/nrrs.h: workspace carving, scene upload
+// (host BVH build), the per-pass launch sequence of the wavefront bounce loop, training
+// steps and the test entry points.  No device memory is allocated here: every buffer is
+// carved out of the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/nrrs.h"
+#include "bvh.hpp"
+#include "launch.hpp"
+
+using namespace nrrs;
+
+namespace {
+
+constexpr uint32_t kMaxMinibatch = 65536;
+
+struct Carve {
+  uint8_t* base;
+  uint64_t off = 0;
+  template <typename T>
+  T* take(uint64_t count) {
+    off = (off + 255) & ~uint64_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * count;
+    return p;
+  }
+};
+
+}  // namespace
+
+struct nrrs_ctx {
+  nrrs_config cfg{};
+  hipStream_t stream = nullptr;
+  uint64_t npx = 0, nprim = 0, cap = 0;
+  // workspace
+  uint8_t* ws = nullptr;
+  uint64_t ws_bytes = 0, max_tris = 0;
+  uint32_t max_mats = 0;
+  float4 *tri = nullptr, *node = nullptr, *mat = nullptr;
+  Queue qa{}, qb{};
+  uint8_t* qb_pool = nullptr;  // queue B's bytes double as scratch for the test entry points
+  uint64_t qb_pool_bytes = 0;
+  float4 *hit = nullptr, *vpos = nullptr, *vnrm = nullptr;
+  float* q = nullptr;
+  uint32_t* offs = nullptr;
+  double* partial = nullptr;
+  uint32_t *bsum = nullptr, *boff = nullptr, *gsum = nullptr;
+  DepthCtl* ctl = nullptr;
+  double* alpha = nullptr;
+  uint32_t* overflow = nullptr;
+  unsigned long long* rays = nullptr;
+  unsigned long long *st_n = nullptr, *st_s = nullptr, *st_r = nullptr;
+  double *st_sumq = nullptr, *st_f = nullptr;
+  double* image = nullptr;
+  float* guide = nullptr;
+  Records rec{};
+  float* target = nullptr;
+  float *master = nullptr, *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;
+  uint16_t* bf16 = nullptr;
+  uint8_t* fp8 = nullptr;
+  float* fp8_scale = nullptr;
+  float *grad_partial = nullptr, *loss_partial = nullptr, *loss_accum = nullptr;
+  // scene
+  bool bound = false, scene = false;
+  DevScene sc{};
+  std::vector<uint32_t> bvh_order, orig_to_bvh;
+  // counters on the host
+  uint64_t spp_total = 0, passes_done = 0, adam_step = 0;
+  std::string err;
+  // stage timing
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  std::vector<int> event_stage;
+  ~nrrs_ctx() {
+    for (hipEvent_t e : events) hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+int32_t fail(nrrs_ctx* c, int32_t code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPC(ctx, expr)                                                                          \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) return fail(ctx, NRRS_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats) {
+  Carve k{base};
+  const uint64_t C = c->cap, npx = c->npx, rc = c->cfg.records_cap;
+  c->tri = k.take<float4>(3 * max_tris);
+  c->node = k.take<float4>(4 * (max_tris + 2));
+  c->mat = k.take<float4>(2 * (uint64_t)max_mats);
+  for (Queue* qq : {&c->qa, &c->qb}) {
+    uint64_t start = (k.off + 255) & ~uint64_t(255);
+    qq->orig = k.take<float4>(C);
+    qq->dir = k.take<float4>(C);
+    qq->thr = k.take<float4>(C);
+    qq->id = k.take<uint2>(C);
+    qq->rec = k.take<int4>(C);
+    if (qq == &c->qb) {
+      c->qb_pool = base ? base + start : nullptr;
+      c->qb_pool_bytes = k.off - start;
+    }
+  }
+  c->hit = k.take<float4>(C);
+  c->vpos = k.take<float4>(C);
+  c->vnrm = k.take<float4>(C);
+  c->q = k.take<float>(C);
+  c->offs = k.take<uint32_t>(C);
+  c->partial = k.take<double>(kScanBlocks);
+  c->bsum = k.take<uint32_t>(kScanBlocks);
+  c->boff = k.take<uint32_t>(kScanBlocks);
+  c->gsum = k.take<uint32_t>((uint64_t)kScanBlocks * kGuardSteps);
+  c->ctl = k.take<DepthCtl>(NRRS_MAX_DEPTH + 2);
+  c->alpha = k.take<double>(1);
+  c->overflow = k.take<uint32_t>(1);
+  c->rays = k.take<unsigned long long>(3);
+  c->st_n = k.take<unsigned long long>(NRRS_MAX_DEPTH + 1);
+  c->st_s = k.take<unsigned long long>(NRRS_MAX_DEPTH + 1);
+  c->st_r = k.take<unsigned long long>(NRRS_MAX_DEPTH + 1);
+  c->st_sumq = k.take<double>(NRRS_MAX_DEPTH + 1);
+  c->st_f = k.take<double>(NRRS_MAX_DEPTH + 1);
+  c->image = k.take<double>(3 * npx);
+  c->guide = k.take<float>(npx);
+  c->rec.feat = k.take<float>(20 * rc);
+  c->rec.lum_t = k.take<float>(rc);
+  c->rec.acc = k.take<float>(rc);
+  c->rec.depth = k.take<uint32_t>(rc);
+  c->rec.pix = k.take<uint32_t>(rc);
+  c->rec.lineage = k.take<uint2>(rc);
+  c->rec.count = k.take<uint32_t>(1);
+  c->rec.cap = (uint32_t)rc;
+  c->target = k.take<float>(rc);
+  c->master = k.take<float>(kNParam);
+  c->adam_m = k.take<float>(kNParam);
+  c->adam_v = k.take<float>(kNParam);
+  c->grad = k.take<float>(kNParam);
+  c->bf16 = k.take<uint16_t>(kNParam);
+  c->fp8 = k.take<uint8_t>(kNParam);
+  c->fp8_scale = k.take<float>(4);
+  const uint64_t gb = mlp_grad_blocks(kMaxMinibatch);
+  c->grad_partial = k.take<float>(gb * kNParam);
+  c->loss_partial = k.take<float>(gb);
+  c->loss_accum = k.take<float>(1);
+  return (k.off + 255) & ~uint64_t(255);
+}
+
+// Host Philox4x32-10 for the weight initialisation (counter = (index, 0, 5, 0)).
+void philox_host(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t pa = (uint64_t)0xD2511F53u * c[0], pb = (uint64_t)0xCD9E8D57u * c[2];
+    uint32_t n0 = (uint32_t)(pb >> 32) ^ c[1] ^ k0, n2 = (uint32_t)(pa >> 32) ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = (uint32_t)pb;
+    c[2] = n2;
+    c[3] = (uint32_t)pa;
+  }
+}
+
+// He-uniform weights, zero biases, output layer scaled by 0.1.
+void init_params(uint64_t seed, std::vector<float>& w) {
+  w.assign(kNParam, 0.0f);
+  struct L {
+    int off, n, fan_in;
+    float extra;
+  } layers[] = {{kW1, 1280, 20, 1.0f}, {kW2, 4096, 64, 1.0f}, {kW3, 4096, 64, 1.0f}, {kW4, 64, 64, 0.1f}};
+  for (const L& l : layers) {
+    const float lim = std::sqrt(6.0f / (float)l.fan_in) * l.extra;
+    for (int k = 0; k < l.n; ++k) {
+      uint32_t c[4] = {(uint32_t)(l.off + k), 0u, 5u, 0u};
+      philox_host(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+      float u = (float)(c[0] >> 8) * 0x1.0p-24f;
+      w[l.off + k] = (2.0f * u - 1.0f) * lim;
+    }
+  }
+}
+
+RenderArgs base_args(nrrs_ctx* c) {
+  RenderArgs a{};
+  a.sc = c->sc;
+  a.qin = c->qa;
+  a.qout = c->qb;
+  a.hit = c->hit;
+  a.vpos = c->vpos;
+  a.vnrm = c->vnrm;
+  a.q = c->q;
+  a.offs = c->offs;
+  a.partial = c->partial;
+  a.bsum = c->bsum;
+  a.boff = c->boff;
+  a.gsum = c->gsum;
+  a.ctl = c->ctl;
+  a.alpha = c->alpha;
+  a.overflow = c->overflow;
+  a.rays = c->rays;
+  a.image = c->image;
+  a.guide = c->guide;
+  a.rec = c->rec;
+  a.key = make_uint2((uint32_t)c->cfg.seed, (uint32_t)(c->cfg.seed >> 32));
+  a.width = c->cfg.width;
+  a.height = c->cfg.height;
+  a.nprim = (uint32_t)c->nprim;
+  a.cap = (uint32_t)c->cap;
+  a.norm_mode = (uint32_t)c->cfg.norm_mode;
+  a.net_max_depth = (uint32_t)c->cfg.net_max_depth;
+  a.p_train = (float)c->cfg.p_train;
+  a.f_rate = c->cfg.f_rate;
+  a.budget_base = (double)c->nprim;
+  a.dbg_parent = nullptr;
+  return a;
+}
+
+NetArgs net_args(nrrs_ctx* c, int32_t precision) {
+  NetArgs n{};
+  n.master = c->master;
+  n.bf16 = c->bf16;
+  n.fp8 = c->fp8;
+  n.fp8_scale = c->fp8_scale;
+  n.precision = precision;
+  return n;
+}
+
+bool finite_all(const float* p, uint64_t n) {
+  for (uint64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nrrs_status_string(int32_t s) {
+  switch (s) {
+    case NRRS_OK: return "ok";
+    case NRRS_EINVAL: return "invalid argument";
+    case NRRS_ESTATE: return "call out of order";
+    case NRRS_ENOMEM: return "workspace too small";
+    case NRRS_EHIP: return "HIP runtime error";
+    case NRRS_EOVERFLOW: return "queue overflow guard exhausted";
+    case NRRS_EUNSUPPORTED: return "unsupported device or feature";
+    default: return "unknown status";
+  }
+}
+
+const char* nrrs_last_error(const nrrs_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int32_t nrrs_create(const nrrs_config* cfg, void* hip_stream, nrrs_ctx** out) {
+  if (!cfg || !out) return NRRS_EINVAL;
+  *out = nullptr;
+  if (cfg->width == 0 || cfg->height == 0 || cfg->s_batch == 0 || !(cfg->cap_factor >= 1.0) ||
+      !(cfg->f_rate > 0.0) || cfg->net_max_depth < 0 || cfg->net_max_depth > kMaxRec ||
+      (cfg->norm_mode != NRRS_NORM_TWO_SIDED && cfg->norm_mode != NRRS_NORM_DOWNSCALE) ||
+      cfg->precision < NRRS_PREC_FP32 || cfg->precision > NRRS_PREC_FP8 || !(cfg->p_train >= 0.0) ||
+      cfg->p_train > 1.0)
+    return NRRS_EINVAL;
+  const uint64_t npx = (uint64_t)cfg->width * cfg->height;
+  const uint64_t nprim = npx * cfg->s_batch;
+  const uint64_t cap = (uint64_t)std::floor(cfg->cap_factor * (double)nprim);
+  if (nprim > 0x40000000ull || cap > 0x7fffffffull) return NRRS_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return NRRS_EHIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return NRRS_EHIP;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return NRRS_EUNSUPPORTED;
+  nrrs_ctx* c = new (std::nothrow) nrrs_ctx();
+  if (!c) return NRRS_EINVAL;
+  c->cfg = *cfg;
+  c->stream = (hipStream_t)hip_stream;
+  c->npx = npx;
+  c->nprim = nprim;
+  c->cap = cap;
+  *out = c;
+  return NRRS_OK;
+}
+
+void nrrs_destroy(nrrs_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->bound) hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+int32_t nrrs_workspace_size(const nrrs_ctx* ctx, uint64_t max_tris, uint32_t max_materials, uint64_t* bytes) {
+  if (!ctx || !bytes || max_tris == 0 || max_materials == 0 || max_tris > (1ull << 28)) return NRRS_EINVAL;
+  nrrs_ctx tmp = *ctx;
+  *bytes = carve(&tmp, nullptr, max_tris, max_materials);
+  return NRRS_OK;
+}
+
+int32_t nrrs_bind_workspace(nrrs_ctx* c, void* device_ptr, uint64_t bytes, uint64_t max_tris, uint32_t max_materials) {
+  if (!c || !device_ptr || max_tris == 0 || max_materials == 0 || max_tris > (1ull << 28)) return NRRS_EINVAL;
+  if (((uintptr_t)device_ptr & 255u) != 0) return fail(c, NRRS_EINVAL, "workspace must be 256-byte aligned");
+  nrrs_ctx tmp = *c;
+  const uint64_t need = carve(&tmp, nullptr, max_tris, max_materials);
+  if (bytes < need) return fail(c, NRRS_ENOMEM, "workspace smaller than nrrs_workspace_size");
+  carve(c, (uint8_t*)device_ptr, max_tris, max_materials);
+  c->ws = (uint8_t*)device_ptr;
+  c->ws_bytes = bytes;
+  c->max_tris = max_tris;
+  c->max_mats = max_materials;
+  c->bound = true;
+  c->scene = false;
+  hipStream_t s = c->stream;
+  launch_zero_f64(c->image, 3 * c->npx, s);
+  launch_fill_f32(c->guide, c->npx, -1.0f, s);
+  launch_zero_u32(c->rec.count, 1, s);
+  launch_set_f64(c->alpha, 1.0, s);
+  launch_zero_u32((uint32_t*)c->ctl, (sizeof(DepthCtl) * (NRRS_MAX_DEPTH + 2)) / 4, s);
+  launch_zero_u32((uint32_t*)c->adam_m, kNParam, s);
+  launch_zero_u32((uint32_t*)c->adam_v, kNParam, s);
+  std::vector<float> w;
+  init_params(c->cfg.seed, w);
+  HIPC(c, hipMemcpyAsync(c->master, w.data(), sizeof(float) * kNParam, hipMemcpyHostToDevice, s));
+  launch_quantize(c->master, c->bf16, c->fp8, c->fp8_scale, s);
+  HIPC(c, hipStreamSynchronize(s));
+  HIPC(c, hipGetLastError());
+  c->spp_total = 0;
+  c->passes_done = 0;
+  c->adam_step = 0;
+  return NRRS_OK;
+}
+
+int32_t nrrs_upload_scene(nrrs_ctx* c, const float* verts, uint64_t nv, const uint32_t* tris, uint64_t nt,
+                          const uint32_t* tri_mat, const uint32_t* mat_type, const float* mat_params, uint32_t nm,
+                          const float* camera, const float* env) {
+  if (!c) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "bind a workspace first");
+  if (!verts || !tris || !tri_mat || !mat_type || !mat_params || !camera || !env || nt == 0 || nv == 0 || nm == 0)
+    return fail(c, NRRS_EINVAL, "null array or empty scene");
+  if (nt > c->max_tris || nm > c->max_mats) return fail(c, NRRS_ENOMEM, "scene larger than the bound workspace");
+  if (!finite_all(verts, 3 * nv) || !finite_all(mat_params, 7ull * nm) || !finite_all(camera, 10) ||
+      !finite_all(env, 3))
+    return fail(c, NRRS_EINVAL, "non-finite scene value");
+  for (uint64_t i = 0; i < 3 * nt; ++i)
+    if (tris[i] >= nv) return fail(c, NRRS_EINVAL, "triangle vertex index out of range");
+  for (uint64_t i = 0; i < nt; ++i)
+    if (tri_mat[i] >= nm) return fail(c, NRRS_EINVAL, "triangle material out of range");
+  for (uint32_t m = 0; m < nm; ++m)
+    if (mat_type[m] > NRRS_MAT_EMITTER) return fail(c, NRRS_EINVAL, "unknown material type");
+  if (!(camera[9] > 0.0f && camera[9] < 180.0f)) return fail(c, NRRS_EINVAL, "camera fov out of range");
+  BvhOut bvh;
+  build_bvh(verts, tris, nt, bvh);
+  if (bvh.n_nodes > c->max_tris + 2) return fail(c, NRRS_ENOMEM, "BVH larger than reserved");
+  // triangles in BVH order: (v0, original index), (e1, material), (e2, 0)
+  std::vector<float> tri(12 * nt);
+  float amin[3] = {INFINITY, INFINITY, INFINITY}, amax[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (uint64_t k = 0; k < nt; ++k) {
+    const uint32_t t = bvh.order[k];
+    const float* v0 = verts + 3ull * tris[3 * t];
+    const float* v1 = verts + 3ull * tris[3 * t + 1];
+    const float* v2 = verts + 3ull * tris[3 * t + 2];
+    float* o = &tri[12 * k];
+    for (int a = 0; a < 3; ++a) {
+      o[a] = v0[a];
+      o[4 + a] = v1[a] - v0[a];
+      o[8 + a] = v2[a] - v0[a];
+      amin[a] = std::fmin(amin[a], std::fmin(v0[a], std::fmin(v1[a], v2[a])));
+      amax[a] = std::fmax(amax[a], std::fmax(v0[a], std::fmax(v1[a], v2[a])));
+    }
+    std::memcpy(&o[3], &t, 4);
+    std::memcpy(&o[7], &tri_mat[t], 4);
+    o[11] = 0.0f;
+  }
+  std::vector<float> mats(8ull * nm);
+  for (uint32_t m = 0; m < nm; ++m) {
+    for (int k = 0; k < 4; ++k) mats[8ull * m + k] = mat_params[7ull * m + k];
+    for (int k = 0; k < 3; ++k) mats[8ull * m + 4 + k] = mat_params[7ull * m + 4 + k];
+    std::memcpy(&mats[8ull * m + 7], &mat_type[m], 4);
+  }
+  hipStream_t s = c->stream;
+  HIPC(c, hipStreamSynchronize(s));
+  HIPC(c, hipMemcpy(c->tri, tri.data(), sizeof(float) * tri.size(), hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(c->node, bvh.nodes.data(), sizeof(float) * bvh.nodes.size(), hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(c->mat, mats.data(), sizeof(float) * mats.size(), hipMemcpyHostToDevice));
+  DevScene& d = c->sc;
+  d.tri = c->tri;
+  d.node = c->node;
+  d.mat = c->mat;
+  d.nt = (uint32_t)nt;
+  d.nn = (uint32_t)bvh.n_nodes;
+  d.nm = nm;
+  d.amin_x = amin[0];
+  d.amin_y = amin[1];
+  d.amin_z = amin[2];
+  const double ex = amax[0] - amin[0], ey = amax[1] - amin[1], ez = amax[2] - amin[2];
+  d.extent = (float)std::fmax(ex, std::fmax(ey, ez));
+  d.tmin = (float)(1e-5 * std::sqrt(ex * ex + ey * ey + ez * ez));
+  d.env_r = env[0];
+  d.env_g = env[1];
+  d.env_b = env[2];
+  // camera basis in double, then handed to the kernels in float
+  const double eye[3] = {camera[0], camera[1], camera[2]};
+  double fwd[3] = {camera[3] - eye[0], camera[4] - eye[1], camera[5] - eye[2]};
+  const double up[3] = {camera[6], camera[7], camera[8]};
+  double l = std::sqrt(fwd[0] * fwd[0] + fwd[1] * fwd[1] + fwd[2] * fwd[2]);
+  if (!(l > 0.0)) return fail(c, NRRS_EINVAL, "camera eye equals look-at point");
+  for (double& x : fwd) x /= l;
+  double r[3] = {fwd[1] * up[2] - fwd[2] * up[1], fwd[2] * up[0] - fwd[0] * up[2], fwd[0] * up[1] - fwd[1] * up[0]};
+  l = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  if (!(l > 0.0)) return fail(c, NRRS_EINVAL, "camera up is parallel to the view direction");
+  for (double& x : r) x /= l;
+  const double u[3] = {r[1] * fwd[2] - r[2] * fwd[1], r[2] * fwd[0] - r[0] * fwd[2], r[0] * fwd[1] - r[1] * fwd[0]};
+  const double th = std::tan((double)camera[9] * M_PI / 360.0);
+  const double aspect = (double)c->cfg.width / (double)c->cfg.height;
+  d.eye_x = (float)eye[0]; d.eye_y = (float)eye[1]; d.eye_z = (float)eye[2];
+  d.fwd_x = (float)fwd[0]; d.fwd_y = (float)fwd[1]; d.fwd_z = (float)fwd[2];
+  d.rx = (float)(r[0] * th * aspect); d.ry = (float)(r[1] * th * aspect); d.rz = (float)(r[2] * th * aspect);
+  d.ux = (float)(u[0] * th); d.uy = (float)(u[1] * th); d.uz = (float)(u[2] * th);
+  c->bvh_order = bvh.order;
+  c->orig_to_bvh.assign(nt, 0);
+  for (uint64_t k = 0; k < nt; ++k) c->orig_to_bvh[bvh.order[k]] = (uint32_t)k;
+  c->scene = true;
+  return NRRS_OK;
+}
+
+int32_t nrrs_set_timing(nrrs_ctx* c, int32_t enabled) {
+  if (!c) return NRRS_EINVAL;
+  c->timing = enabled != 0;
+  return NRRS_OK;
+}
+
+int32_t nrrs_render(nrrs_ctx* c, uint32_t spp, uint32_t max_depth, int32_t mode, nrrs_render_stats* stats) {
+  if (!c) return NRRS_EINVAL;
+  if (!c->scene) return fail(c, NRRS_ESTATE, "upload a scene first");
+  if (spp == 0 || spp % c->cfg.s_batch != 0) return fail(c, NRRS_EINVAL, "spp must be a positive multiple of s_batch");
+  if (max_depth < 1 || max_depth > NRRS_MAX_DEPTH) return fail(c, NRRS_EINVAL, "max_depth out of range");
+  if (mode < NRRS_MODE_OFF || mode > NRRS_MODE_NET) return fail(c, NRRS_EINVAL, "unknown mode");
+  hipStream_t s = c->stream;
+  const uint32_t passes = spp / c->cfg.s_batch;
+  RenderArgs a = base_args(c);
+  a.max_depth = max_depth;
+  a.mode = (uint32_t)mode;
+  a.records_on = (mode != NRRS_MODE_OFF && c->cfg.records_cap > 0 && c->cfg.p_train > 0.0) ? 1u : 0u;
+  const NetArgs net = net_args(c, c->cfg.precision);
+  if (a.records_on) launch_zero_u32(a.rec.count, 1, s);
+  launch_zero_u32((uint32_t*)c->st_n, 2 * (NRRS_MAX_DEPTH + 1), s);
+  launch_zero_u32((uint32_t*)c->st_s, 2 * (NRRS_MAX_DEPTH + 1), s);
+  launch_zero_u32((uint32_t*)c->st_r, 2 * (NRRS_MAX_DEPTH + 1), s);
+  launch_zero_u32((uint32_t*)c->rays, 6, s);
+  launch_zero_u32(c->overflow, 1, s);
+  // stage timing: one event before the first launch and one after every stage
+  size_t n_ev = 0;
+  auto mark = [&](int stage) -> int32_t {
+    if (!c->timing) return NRRS_OK;
+    if (n_ev == c->events.size()) {
+      hipEvent_t e;
+      HIPC(c, hipEventCreate(&e));
+      c->events.push_back(e);
+      c->event_stage.push_back(stage);
+    }
+    c->event_stage[n_ev] = stage;
+    HIPC(c, hipEventRecord(c->events[n_ev], s));
+    ++n_ev;
+    return NRRS_OK;
+  };
+#define MARK(stage)                    \
+  do {                                 \
+    int32_t r_ = mark(stage);          \
+    if (r_ != NRRS_OK) return r_;      \
+  } while (0)
+  MARK(-1);
+  for (uint32_t p = 0; p < passes; ++p) {
+    a.pass = (uint32_t)(c->passes_done + p);
+    a.qin = c->qa;
+    a.qout = c->qb;
+    launch_camera(a, s);
+    MARK(0);
+    for (uint32_t d = 1; d <= max_depth; ++d) {
+      a.depth = d;
+      launch_extend(a, s);
+      MARK(1);
+      launch_shade(a, s);
+      MARK(2);
+      if (d == max_depth) break;
+      if (mode == NRRS_MODE_NET && d <= (uint32_t)c->cfg.net_max_depth) {
+        launch_rrsnet(a, net, s);
+        MARK(3);
+      }
+      launch_sum_q(a, s);
+      MARK(4);
+      launch_roulette(a, s);
+      MARK(5);
+      launch_expand(a, s);
+      MARK(6);
+      std::swap(a.qin, a.qout);
+    }
+    launch_accumulate_stats(c->ctl, max_depth, c->st_n, c->st_s, c->st_r, c->st_sumq, c->st_f, s);
+    c->spp_total += c->cfg.s_batch;
+    launch_guide(a, (double)c->spp_total, c->guide, s);
+    MARK(7);
+  }
+#undef MARK
+  c->passes_done += passes;
+  HIPC(c, hipGetLastError());
+  if (stats) {
+    HIPC(c, hipStreamSynchronize(s));
+    std::memset(stats, 0, sizeof(*stats));
+    stats->max_depth = max_depth;
+    stats->passes = passes;
+    HIPC(c, hipMemcpy(stats->n, c->st_n, sizeof(uint64_t) * (NRRS_MAX_DEPTH + 1), hipMemcpyDeviceToHost));
+    HIPC(c, hipMemcpy(stats->S, c->st_s, sizeof(uint64_t) * (NRRS_MAX_DEPTH + 1), hipMemcpyDeviceToHost));
+    HIPC(c, hipMemcpy(stats->retries, c->st_r, sizeof(uint64_t) * (NRRS_MAX_DEPTH + 1), hipMemcpyDeviceToHost));
+    HIPC(c, hipMemcpy(stats->sumq, c->st_sumq, sizeof(double) * (NRRS_MAX_DEPTH + 1), hipMemcpyDeviceToHost));
+    HIPC(c, hipMemcpy(stats->F, c->st_f, sizeof(double) * (NRRS_MAX_DEPTH + 1), hipMemcpyDeviceToHost));
+    HIPC(c, hipMemcpy(&stats->alpha, c->alpha, sizeof(double), hipMemcpyDeviceToHost));
+    unsigned long long work[3] = {0, 0, 0};
+    HIPC(c, hipMemcpy(work, c->rays, sizeof(work), hipMemcpyDeviceToHost));
+    stats->rays = work[0];
+    stats->nodes_visited = work[1];
+    stats->tris_tested = work[2];
+    if (c->timing && n_ev > 1) {
+      stats->timed = 1;
+      for (size_t k = 1; k < n_ev; ++k) {
+        float ms = 0.0f;
+        HIPC(c, hipEventElapsedTime(&ms, c->events[k - 1], c->events[k]));
+        const int st = c->event_stage[k];
+        stats->stage_ms[st] += ms;
+        stats->stage_launches[st] += 1;
+      }
+    }
+    uint32_t cnt = 0, of = 0;
+    HIPC(c, hipMemcpy(&cnt, c->rec.count, 4, hipMemcpyDeviceToHost));
+    HIPC(c, hipMemcpy(&of, c->overflow, 4, hipMemcpyDeviceToHost));
+    stats->records = a.records_on ? std::min<uint64_t>(cnt, c->cfg.records_cap) : 0;
+    stats->overflow = of;
+    if (of) return fail(c, NRRS_EOVERFLOW, "overflow guard found no alpha that fits the queue");
+  }
+  return NRRS_OK;
+}
+
+int32_t nrrs_read_image(nrrs_ctx* c, double* host_rgb, uint64_t* spp_total) {
+  if (!c || !host_rgb) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  HIPC(c, hipStreamSynchronize(c->stream));
+  HIPC(c, hipMemcpy(host_rgb, c->image, sizeof(double) * 3 * c->npx, hipMemcpyDeviceToHost));
+  if (c->spp_total > 0)
+    for (uint64_t i = 0; i < 3 * c->npx; ++i) host_rgb[i] /= (double)c->spp_total;
+  if (spp_total) *spp_total = c->spp_total;
+  return NRRS_OK;
+}
+
+int32_t nrrs_reset_image(nrrs_ctx* c) {
+  if (!c) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  launch_zero_f64(c->image, 3 * c->npx, c->stream);
+  launch_set_f64(c->alpha, 1.0, c->stream);
+  c->spp_total = 0;
+  HIPC(c, hipGetLastError());
+  return NRRS_OK;
+}
+
+int32_t nrrs_set_guide(nrrs_ctx* c, const float* host_lum) {
+  if (!c || !host_lum) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  HIPC(c, hipStreamSynchronize(c->stream));
+  HIPC(c, hipMemcpy(c->guide, host_lum, sizeof(float) * c->npx, hipMemcpyHostToDevice));
+  return NRRS_OK;
+}
+
+int32_t nrrs_get_guide(nrrs_ctx* c, float* host_lum) {
+  if (!c || !host_lum) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  HIPC(c, hipStreamSynchronize(c->stream));
+  HIPC(c, hipMemcpy(host_lum, c->guide, sizeof(float) * c->npx, hipMemcpyDeviceToHost));
+  return NRRS_OK;
+}
+
+int32_t nrrs_get_params(nrrs_ctx* c, float* master, float* adam_m, float* adam_v, uint64_t* step) {
+  if (!c) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  HIPC(c, hipStreamSynchronize(c->stream));
+  if (master) HIPC(c, hipMemcpy(master, c->master, sizeof(float) * kNParam, hipMemcpyDeviceToHost));
+  if (adam_m) HIPC(c, hipMemcpy(adam_m, c->adam_m, sizeof(float) * kNParam, hipMemcpyDeviceToHost));
+  if (adam_v) HIPC(c, hipMemcpy(adam_v, c->adam_v, sizeof(float) * kNParam, hipMemcpyDeviceToHost));
+  if (step) *step = c->adam_step;
+  return NRRS_OK;
+}
+
+int32_t nrrs_set_params(nrrs_ctx* c, const float* master, const float* adam_m, const float* adam_v,
+                        const uint64_t* step) {
+  if (!c) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  HIPC(c, hipStreamSynchronize(c->stream));
+  if (master) HIPC(c, hipMemcpy(c->master, master, sizeof(float) * kNParam, hipMemcpyHostToDevice));
+  if (adam_m) HIPC(c, hipMemcpy(c->adam_m, adam_m, sizeof(float) * kNParam, hipMemcpyHostToDevice));
+  if (adam_v) HIPC(c, hipMemcpy(c->adam_v, adam_v, sizeof(float) * kNParam, hipMemcpyHostToDevice));
+  if (step) c->adam_step = *step;
+  launch_quantize(c->master, c->bf16, c->fp8, c->fp8_scale, c->stream);
+  HIPC(c, hipGetLastError());
+  return NRRS_OK;
+}
+
+int32_t nrrs_read_records(nrrs_ctx* c, uint64_t* n, float* features, float* lum_t, float* acc, uint32_t* depth,
+                          uint32_t* pix, uint64_t* lineage) {
+  if (!c || !n) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  HIPC(c, hipStreamSynchronize(c->stream));
+  uint32_t cnt = 0;
+  HIPC(c, hipMemcpy(&cnt, c->rec.count, 4, hipMemcpyDeviceToHost));
+  const uint64_t k = std::min<uint64_t>(cnt, c->cfg.records_cap);
+  *n = k;
+  if (k == 0) return NRRS_OK;
+  if (features) HIPC(c, hipMemcpy(features, c->rec.feat, sizeof(float) * 20 * k, hipMemcpyDeviceToHost));
+  if (lum_t) HIPC(c, hipMemcpy(lum_t, c->rec.lum_t, sizeof(float) * k, hipMemcpyDeviceToHost));
+  if (acc) HIPC(c, hipMemcpy(acc, c->rec.acc, sizeof(float) * k, hipMemcpyDeviceToHost));
+  if (depth) HIPC(c, hipMemcpy(depth, c->rec.depth, sizeof(uint32_t) * k, hipMemcpyDeviceToHost));
+  if (pix) HIPC(c, hipMemcpy(pix, c->rec.pix, sizeof(uint32_t) * k, hipMemcpyDeviceToHost));
+  if (lineage) HIPC(c, hipMemcpy(lineage, c->rec.lineage, sizeof(uint64_t) * k, hipMemcpyDeviceToHost));
+  return NRRS_OK;
+}
+
+int32_t nrrs_train_step(nrrs_ctx* c, uint32_t n_records, uint32_t minibatch, float lr, float* loss_or_null) {
+  if (!c) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (n_records == 0 || minibatch == 0 || minibatch > kMaxMinibatch || n_records % minibatch != 0 ||
+      !(lr > 0.0f) || !std::isfinite(lr))
+    return fail(c, NRRS_EINVAL, "n_records must be a positive multiple of minibatch (<= 65536), lr > 0");
+  if (n_records > c->cfg.records_cap) return fail(c, NRRS_ESTATE, "more records requested than the buffer holds");
+  hipStream_t s = c->stream;
+  HIPC(c, hipStreamSynchronize(s));
+  uint32_t cnt = 0;
+  HIPC(c, hipMemcpy(&cnt, c->rec.count, 4, hipMemcpyDeviceToHost));
+  if (std::min<uint32_t>(cnt, c->cfg.records_cap) < n_records)
+    return fail(c, NRRS_ESTATE, "fewer records captured than requested");
+  launch_record_targets(c->rec, c->target, n_records, s);
+  launch_zero_u32((uint32_t*)c->loss_accum, 1, s);
+  const uint32_t batches = n_records / minibatch;
+  for (uint32_t b = 0; b < batches; ++b) {
+    uint32_t nb = 0;
+    launch_mlp_grad(c->rec.feat + 20ull * b * minibatch, c->target + (uint64_t)b * minibatch, nullptr, minibatch,
+                    c->master, c->grad_partial, c->loss_partial, &nb, s);
+    launch_grad_reduce(c->grad_partial, nb, c->grad, c->loss_partial, c->loss_accum, minibatch, s);
+    c->adam_step += 1;
+    launch_adam(c->master, c->adam_m, c->adam_v, c->grad, c->adam_step, lr, s);
+  }
+  launch_quantize(c->master, c->bf16, c->fp8, c->fp8_scale, s);
+  HIPC(c, hipGetLastError());
+  if (loss_or_null) {
+    HIPC(c, hipStreamSynchronize(s));
+    float l = 0.0f;
+    HIPC(c, hipMemcpy(&l, c->loss_accum, 4, hipMemcpyDeviceToHost));
+    *loss_or_null = l / (float)batches;
+  }
+  return NRRS_OK;
+}
+
+// ------------------------------------------------------------------------- test entry points
+int32_t nrrs_debug_rrs_expand(nrrs_ctx* c, const float* q_orig, const uint32_t* id_lo, const uint32_t* id_hi,
+                              uint32_t n, uint32_t depth, double budget_base, double f_rate, double* alpha,
+                              int32_t norm_mode, uint32_t cap, uint32_t* X, uint32_t* offset,
+                              uint32_t* parent_of_child, uint32_t* S, double* F, float* q_norm, uint32_t* retries) {
+  if (!c || !alpha || !X || !offset || !S || !F || !retries || (n && (!q_orig || !id_lo || !id_hi))) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (n > c->cap || cap > c->cap || depth < 1 || depth >= NRRS_MAX_DEPTH || !(budget_base >= 0.0) ||
+      !(f_rate > 0.0) || !(*alpha > 0.0) || (norm_mode != NRRS_NORM_TWO_SIDED && norm_mode != NRRS_NORM_DOWNSCALE))
+    return fail(c, NRRS_EINVAL, "debug_rrs_expand: argument out of range");
+  if (!finite_all(q_orig, n)) return fail(c, NRRS_EINVAL, "non-finite factor");
+  for (uint32_t i = 0; i < n; ++i)
+    if (q_orig[i] < 0.0f) return fail(c, NRRS_EINVAL, "negative factor");
+  hipStream_t s = c->stream;
+  HIPC(c, hipStreamSynchronize(s));
+  std::vector<uint2> ids(n);
+  for (uint32_t i = 0; i < n; ++i) ids[i] = make_uint2(id_lo[i], id_hi[i]);
+  DepthCtl ctl[2];
+  std::memset(ctl, 0, sizeof(ctl));
+  ctl[0].n = n;
+  if (n) {
+    HIPC(c, hipMemcpy(c->q, q_orig, sizeof(float) * n, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->qa.id, ids.data(), sizeof(uint2) * n, hipMemcpyHostToDevice));
+  }
+  HIPC(c, hipMemcpy(c->ctl + depth, ctl, sizeof(ctl), hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(c->alpha, alpha, sizeof(double), hipMemcpyHostToDevice));
+  uint32_t of0 = 0;
+  HIPC(c, hipMemcpy(c->overflow, &of0, 4, hipMemcpyHostToDevice));
+  RenderArgs a = base_args(c);
+  a.depth = depth;
+  a.max_depth = depth + 1;
+  a.mode = NRRS_MODE_HEURISTIC;
+  a.norm_mode = (uint32_t)norm_mode;
+  a.f_rate = f_rate;
+  a.budget_base = budget_base;
+  a.cap = cap;
+  a.dbg_parent = (uint32_t*)c->qb_pool;
+  if ((uint64_t)cap * 4 > c->qb_pool_bytes) return fail(c, NRRS_ENOMEM, "scratch too small");
+  launch_sum_q(a, s);
+  launch_roulette(a, s);
+  launch_parents(a, s);
+  HIPC(c, hipStreamSynchronize(s));
+  HIPC(c, hipGetLastError());
+  HIPC(c, hipMemcpy(ctl, c->ctl + depth, sizeof(ctl), hipMemcpyDeviceToHost));
+  HIPC(c, hipMemcpy(alpha, c->alpha, sizeof(double), hipMemcpyDeviceToHost));
+  uint32_t of = 0;
+  HIPC(c, hipMemcpy(&of, c->overflow, 4, hipMemcpyDeviceToHost));
+  *S = ctl[0].S;
+  *F = ctl[0].F;
+  *retries = ctl[0].retries;
+  if (n) HIPC(c, hipMemcpy(offset, c->offs, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
+  for (uint32_t i = 0; i < n; ++i) X[i] = (i + 1 < n ? offset[i + 1] : *S) - offset[i];
+  if (parent_of_child && *S)
+    HIPC(c, hipMemcpy(parent_of_child, c->qb_pool, sizeof(uint32_t) * (*S), hipMemcpyDeviceToHost));
+  if (q_norm)
+    for (uint32_t i = 0; i < n; ++i) q_norm[i] = (float)(ctl[0].F * (double)q_orig[i]);
+  if (of) return fail(c, NRRS_EOVERFLOW, "overflow guard found no alpha that fits");
+  return NRRS_OK;
+}
+
+int32_t nrrs_debug_load_records(nrrs_ctx* c, const float* features, const float* lum_t, const float* acc,
+                                uint32_t n) {
+  if (!c || (n && (!features || !lum_t || !acc))) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (n > c->cfg.records_cap) return fail(c, NRRS_ENOMEM, "more records than records_cap");
+  HIPC(c, hipStreamSynchronize(c->stream));
+  if (n) {
+    HIPC(c, hipMemcpy(c->rec.feat, features, sizeof(float) * 20 * n, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->rec.lum_t, lum_t, sizeof(float) * n, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->rec.acc, acc, sizeof(float) * n, hipMemcpyHostToDevice));
+  }
+  HIPC(c, hipMemcpy(c->rec.count, &n, 4, hipMemcpyHostToDevice));
+  return NRRS_OK;
+}
+
+int32_t nrrs_debug_trace(nrrs_ctx* c, const float* rays, const uint32_t* exclude, uint32_t n, uint32_t* prim,
+                         float* t, float* b1, float* b2) {
+  if (!c || (n && (!rays || !prim || !t || !b1 || !b2))) return NRRS_EINVAL;
+  if (!c->scene) return fail(c, NRRS_ESTATE, "upload a scene first");
+  if ((uint64_t)n * 48 > c->qb_pool_bytes) return fail(c, NRRS_ENOMEM, "too many rays for the scratch space");
+  if (n == 0) return NRRS_OK;
+  std::vector<float> o(4ull * n), d(4ull * n);
+  for (uint32_t i = 0; i < n; ++i) {
+    uint32_t ex = exclude ? exclude[i] : 0xffffffffu;
+    if (ex != 0xffffffffu) {
+      if (ex >= c->orig_to_bvh.size()) return fail(c, NRRS_EINVAL, "exclude index out of range");
+      ex = c->orig_to_bvh[ex];
+    }
+    for (int k = 0; k < 3; ++k) {
+      o[4ull * i + k] = rays[6ull * i + k];
+      d[4ull * i + k] = rays[6ull * i + 3 + k];
+    }
+    std::memcpy(&o[4ull * i + 3], &ex, 4);
+    d[4ull * i + 3] = 0.0f;
+  }
+  hipStream_t s = c->stream;
+  HIPC(c, hipStreamSynchronize(s));
+  float4* po = (float4*)c->qb_pool;
+  float4* pd = po + n;
+  float4* ph = pd + n;
+  HIPC(c, hipMemcpy(po, o.data(), sizeof(float4) * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(pd, d.data(), sizeof(float4) * n, hipMemcpyHostToDevice));
+  launch_trace_rays(c->sc, po, pd, ph, n, s);
+  HIPC(c, hipStreamSynchronize(s));
+  HIPC(c, hipGetLastError());
+  std::vector<float> h(4ull * n);
+  HIPC(c, hipMemcpy(h.data(), ph, sizeof(float4) * n, hipMemcpyDeviceToHost));
+  for (uint32_t i = 0; i < n; ++i) {
+    uint32_t p;
+    std::memcpy(&p, &h[4ull * i + 3], 4);
+    prim[i] = p == 0xffffffffu ? p : c->bvh_order[p];
+    t[i] = h[4ull * i];
+    b1[i] = h[4ull * i + 1];
+    b2[i] = h[4ull * i + 2];
+  }
+  return NRRS_OK;
+}
+
+int32_t nrrs_debug_philox(nrrs_ctx* c, const uint32_t* ctr, const uint32_t* key, uint32_t n, uint32_t* out) {
+  if (!c || !key || (n && (!ctr || !out))) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if ((uint64_t)n * 32 > c->qb_pool_bytes) return fail(c, NRRS_ENOMEM, "too many counters for the scratch space");
+  if (n == 0) return NRRS_OK;
+  hipStream_t s = c->stream;
+  HIPC(c, hipStreamSynchronize(s));
+  uint4* pc = (uint4*)c->qb_pool;
+  uint4* po = pc + n;
+  HIPC(c, hipMemcpy(pc, ctr, 16ull * n, hipMemcpyHostToDevice));
+  launch_philox(pc, make_uint2(key[0], key[1]), po, n, s);
+  HIPC(c, hipStreamSynchronize(s));
+  HIPC(c, hipGetLastError());
+  HIPC(c, hipMemcpy(out, po, 16ull * n, hipMemcpyDeviceToHost));
+  return NRRS_OK;
+}
+
+int32_t nrrs_debug_mlp_forward(nrrs_ctx* c, const float* x, uint32_t n, int32_t precision, float* y, float* z) {
+  if (!c || (n && (!x || !y))) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (precision < NRRS_PREC_FP32 || precision > NRRS_PREC_FP8) return fail(c, NRRS_EINVAL, "precision");
+  if ((uint64_t)n * 88 + 1024 > c->qb_pool_bytes) return fail(c, NRRS_ENOMEM, "too many rows for the scratch space");
+  if (n == 0) return NRRS_OK;
+  hipStream_t s = c->stream;
+  HIPC(c, hipStreamSynchronize(s));
+  float* px = (float*)c->qb_pool;
+  float* py = px + 20ull * n;
+  float* pz = py + n;
+  HIPC(c, hipMemcpy(px, x, sizeof(float) * 20 * n, hipMemcpyHostToDevice));
+  launch_mlp_forward_rows(px, n, net_args(c, precision), py, pz, s);
+  HIPC(c, hipStreamSynchronize(s));
+  HIPC(c, hipGetLastError());
+  HIPC(c, hipMemcpy(y, py, sizeof(float) * n, hipMemcpyDeviceToHost));
+  if (z) HIPC(c, hipMemcpy(z, pz, sizeof(float) * n, hipMemcpyDeviceToHost));
+  return NRRS_OK;
+}
+
+int32_t nrrs_debug_mlp_grad(nrrs_ctx* c, const float* x, const float* target, uint32_t n, float* grad, float* loss) {
+  if (!c || !grad || !loss || n == 0 || !x || !target) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (n > kMaxMinibatch) return fail(c, NRRS_EINVAL, "at most 65536 rows");
+  if ((uint64_t)n * 84 + 1024 > c->qb_pool_bytes) return fail(c, NRRS_ENOMEM, "too many rows for the scratch space");
+  hipStream_t s = c->stream;
+  HIPC(c, hipStreamSynchronize(s));
+  float* px = (float*)c->qb_pool;
+  float* pt = px + 20ull * n;
+  HIPC(c, hipMemcpy(px, x, sizeof(float) * 20 * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(pt, target, sizeof(float) * n, hipMemcpyHostToDevice));
+  launch_zero_u32((uint32_t*)c->loss_accum, 1, s);
+  uint32_t nb = 0;
+  launch_mlp_grad(px, pt, nullptr, n, c->master, c->grad_partial, c->loss_partial, &nb, s);
+  launch_grad_reduce(c->grad_partial, nb, c->grad, c->loss_partial, c->loss_accum, n, s);
+  HIPC(c, hipStreamSynchronize(s));
+  HIPC(c, hipGetLastError());
+  HIPC(c, hipMemcpy(grad, c->grad, sizeof(float) * kNParam, hipMemcpyDeviceToHost));
+  HIPC(c, hipMemcpy(loss, c->loss_accum, 4, hipMemcpyDeviceToHost));
+  return NRRS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Host-side launchers of the gfx950 kernels (one translation unit per kernel family).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.hpp"
+
+namespace nrrs {
+
+// Everything the per-depth kernels read about the render in progress.
+struct RenderArgs {
+  DevScene sc;
+  Queue qin, qout;
+  float4* hit;        // per slot: t, b1, b2, triangle (BVH index) bits
+  float4* vpos;       // per slot: hit point, triangle bits
+  float4* vnrm;       // per slot: face-forwarded normal, material bits
+  float* q;           // per slot: raw RRS factor (0 = no children)
+  uint32_t* offs;     // per slot: first child slot
+  double* partial;    // [kScanBlocks] FP64 partial sums of q
+  uint32_t* bsum;     // [kScanBlocks] children per block
+  uint32_t* boff;     // [kScanBlocks] exclusive scan of bsum
+  uint32_t* gsum;     // [kScanBlocks * kGuardSteps] guard candidate counts
+  DepthCtl* ctl;      // [max_depth + 2]
+  double* alpha;      // persistent adaptive-rate alpha
+  uint32_t* overflow; // set when no guard candidate fits
+  unsigned long long* rays;  // [3] rays traced, BVH nodes visited, triangles tested (accumulated)
+  double* image;      // [npx * 3] FP64 radiance sums
+  const float* guide; // [npx] luminance of the previous mean (negative = none)
+  Records rec;
+  uint2 key;
+  uint32_t width, height, nprim, cap, depth, max_depth, pass, mode, norm_mode, net_max_depth;
+  uint32_t records_on;
+  float p_train;
+  double f_rate;
+  double budget_base;   // N_px of Eq. (10): primary paths of the pass
+  uint32_t* dbg_parent; // when set, the expansion also writes each child's parent index
+};
+
+void launch_camera(const RenderArgs& a, hipStream_t s);
+void launch_extend(const RenderArgs& a, hipStream_t s);
+void launch_shade(const RenderArgs& a, hipStream_t s);
+void launch_sum_q(const RenderArgs& a, hipStream_t s);
+void launch_roulette(const RenderArgs& a, hipStream_t s);  // count, scan, guard, offsets
+void launch_expand(const RenderArgs& a, hipStream_t s);
+void launch_parents(const RenderArgs& a, hipStream_t s);  // parent map only (test entry point)
+void launch_guide(const RenderArgs& a, double spp_total, float* guide, hipStream_t s);
+void launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s);
+void launch_zero_f64(double* p, uint64_t n, hipStream_t s);
+void launch_fill_f32(float* p, uint64_t n, float v, hipStream_t s);
+void launch_set_f64(double* p, double v, hipStream_t s);
+void launch_accumulate_stats(const DepthCtl* ctl, uint32_t max_depth, unsigned long long* n_sum,
+                             unsigned long long* s_sum, unsigned long long* r_sum, double* sumq_last,
+                             double* f_last, hipStream_t s);
+
+// Debug / test launchers.
+void launch_trace_rays(const DevScene& sc, const float4* orig, const float4* dir, float4* hit, uint32_t n,
+                       hipStream_t s);
+void launch_philox(const uint4* ctr, uint2 key, uint4* out, uint32_t n, hipStream_t s);
+
+// Network (mlp.hip).
+struct NetArgs {
+  const float* master;       // FP32 parameters
+  const uint16_t* bf16;      // BF16 copy (RNE), same layout
+  const uint8_t* fp8;        // FP8 E4M3 copy, same layout
+  const float* fp8_scale;    // per-layer dequantization scales [4]
+  int32_t precision;
+};
+void launch_rrsnet(const RenderArgs& a, const NetArgs& n, hipStream_t s);
+void launch_mlp_forward_rows(const float* x, uint32_t n, const NetArgs& net, float* y, float* z, hipStream_t s);
+void launch_mlp_grad(const float* x, const float* target, const uint32_t* index, uint32_t n, const float* master,
+                     float* grad_partial, float* loss_partial, uint32_t* nblocks_out, hipStream_t s);
+void launch_grad_reduce(const float* grad_partial, uint32_t nblocks, float* grad, const float* loss_partial,
+                        float* loss_accum, uint32_t n_rows_total, hipStream_t s);
+void launch_adam(float* master, float* m, float* v, const float* grad, uint64_t step, float lr, hipStream_t s);
+void launch_quantize(const float* master, uint16_t* bf16, uint8_t* fp8, float* fp8_scale, hipStream_t s);
+void launch_record_targets(const Records& r, float* target, uint32_t n, hipStream_t s);
+uint32_t mlp_grad_blocks(uint32_t n);
+
+}  // namespace nrrs

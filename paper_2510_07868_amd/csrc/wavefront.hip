@@ -1,0 +1,657 @@
+// gfx950 kernels of one wavefront bounce: camera spawn, BVH closest hit (extend), shading,
+// FP64 sum of the RRS factors, normalization + stochastic rounding + overflow guard +
+// exclusive scan, and the split/compaction expansion into the next queue.
+//
+// Method (NRRS, arXiv 2510.07868): per-depth normalization q_norm = F q, F = N / sum q
+// (Sec. 4.1.2, Eqs. 9-11) with rate control and adaptive alpha (Sec. 4.1.4, Eqs. 12-14),
+// child counts by stochastic rounding (Sec. 3, Eq. 8), lights and misses end paths
+// (Sec. 3 "Wavefront Architecture").  The entry counts of every depth live on the device,
+// so a whole pass is launched without a host round trip.
+#include <algorithm>
+
+#include "features.hpp"
+#include "launch.hpp"
+
+namespace nrrs {
+
+namespace {
+
+constexpr int kEntryThreads = 256;
+constexpr int kTraceThreads = 128;
+constexpr int kStackDepth = 48;  // the builder caps the BVH depth at 44
+constexpr uint32_t kLeafBit = 0x80000000u;
+
+__device__ __forceinline__ uint32_t bits(float f) { return __float_as_uint(f); }
+
+// ------------------------------------------------------------------------------ camera
+__global__ __launch_bounds__(kEntryThreads) void k_camera(RenderArgs a) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0) {
+    a.ctl[1].n = a.nprim;
+    a.ctl[a.max_depth].S = 0;
+  }
+  if (k >= a.nprim) return;
+  const uint32_t npx = a.width * a.height;
+  const uint32_t pix = k % npx;
+  const uint32_t px = pix % a.width, py = pix / a.width;
+  const uint2 lin = make_uint2(k, a.pass);
+  const uint4 r = draw(a.key, lin, kPurposeCamera, 0, 0);
+  const float sx = 2.0f * ((float)px + unit(r.x)) / (float)a.width - 1.0f;
+  const float sy = 1.0f - 2.0f * ((float)py + unit(r.y)) / (float)a.height;
+  const DevScene& c = a.sc;
+  const V3 d = normalized(v3(c.fwd_x + sx * c.rx + sy * c.ux, c.fwd_y + sx * c.ry + sy * c.uy,
+                             c.fwd_z + sx * c.rz + sy * c.uz));
+  uint32_t flags = 0;
+  if (a.records_on) {
+    const uint4 rt = draw(a.key, lin, kPurposeTrain, 0, 0);
+    if (unit(rt.x) < a.p_train) flags |= kFlagTrain;
+  }
+  a.qin.orig[k] = make_float4(c.eye_x, c.eye_y, c.eye_z, __uint_as_float(kMiss));
+  a.qin.dir[k] = pack(d, pix);
+  a.qin.thr[k] = make_float4(1.0f, 1.0f, 1.0f, __uint_as_float(flags));
+  a.qin.id[k] = lin;
+  a.qin.rec[k] = make_int4(-1, -1, -1, -1);
+}
+
+// ------------------------------------------------------------------------------ extend
+// Robust slab test: the far distance is widened by 2^-20 so that rounding never culls a box
+// that the exact ray touches.
+__device__ __forceinline__ bool slab(float lx, float ly, float lz, float hx, float hy, float hz, V3 inv, V3 oi,
+                                     float tmax, float& tnear) {
+  const float t0x = fmaf(lx, inv.x, oi.x), t1x = fmaf(hx, inv.x, oi.x);
+  const float t0y = fmaf(ly, inv.y, oi.y), t1y = fmaf(hy, inv.y, oi.y);
+  const float t0z = fmaf(lz, inv.z, oi.z), t1z = fmaf(hz, inv.z, oi.z);
+  const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+  const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+  tnear = tn;
+  return tn <= tf * 1.00000095367431640625f;
+}
+
+struct HitState {
+  float t, b1, b2;
+  uint32_t prim, orig;
+};
+
+// Moller-Trumbore with inclusive edges; closest t > tmin wins, equal t goes to the smaller
+// original triangle index.
+__device__ __forceinline__ void test_leaf(const DevScene& sc, uint32_t link, V3 o, V3 d, uint32_t excl,
+                                          HitState& h, uint32_t& tris) {
+  const uint32_t first = (link >> 3) & 0x0fffffffu;
+  const uint32_t count = (link & 7u) + 1u;
+  tris += count;
+  for (uint32_t k = first; k < first + count; ++k) {
+    if (k == excl) continue;
+    const float4 a0 = sc.tri[3 * k], a1 = sc.tri[3 * k + 1], a2 = sc.tri[3 * k + 2];
+    const V3 e1 = xyz(a1), e2 = xyz(a2);
+    const V3 p = cross(d, e2);
+    const float det = dot(e1, p);
+    if (det == 0.0f) continue;
+    const float inv = 1.0f / det;
+    const V3 s = o - xyz(a0);
+    const float b1 = dot(s, p) * inv;
+    if (b1 < 0.0f || b1 > 1.0f) continue;
+    const V3 qv = cross(s, e1);
+    const float b2 = dot(d, qv) * inv;
+    if (b2 < 0.0f || b1 + b2 > 1.0f) continue;
+    const float t = dot(e2, qv) * inv;
+    const uint32_t og = bits(a0.w);
+    if (t > sc.tmin && (t < h.t || (t == h.t && og < h.orig))) {
+      h.t = t;
+      h.b1 = b1;
+      h.b2 = b2;
+      h.prim = k;
+      h.orig = og;
+    }
+  }
+}
+
+// Stack-based BVH2 traversal, near child first; the per-thread stack lives in LDS laid out
+// [depth][thread] so that a wave's pushes and pops hit distinct banks.
+__device__ __forceinline__ HitState traverse(const DevScene& sc, V3 o, V3 d, uint32_t excl,
+                                             uint32_t (*stack)[kTraceThreads], uint32_t& nodes, uint32_t& tris) {
+  const int tid = threadIdx.x;
+  const V3 dd = v3(fabsf(d.x) > 1e-20f ? d.x : copysignf(1e-20f, d.x),
+                   fabsf(d.y) > 1e-20f ? d.y : copysignf(1e-20f, d.y),
+                   fabsf(d.z) > 1e-20f ? d.z : copysignf(1e-20f, d.z));
+  const V3 inv = v3(1.0f / dd.x, 1.0f / dd.y, 1.0f / dd.z);
+  const V3 oi = v3(-o.x * inv.x, -o.y * inv.y, -o.z * inv.z);
+  HitState h;
+  h.t = __builtin_inff();
+  h.b1 = h.b2 = 0.0f;
+  h.prim = kMiss;
+  h.orig = kMiss;
+  int sp = 0;
+  uint32_t ni = 0;
+  for (;;) {
+    ++nodes;
+    const float4 n0 = sc.node[4 * ni], n1 = sc.node[4 * ni + 1], n2 = sc.node[4 * ni + 2], n3 = sc.node[4 * ni + 3];
+    float tn0, tn1;
+    bool h0 = slab(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, inv, oi, h.t, tn0);
+    bool h1 = slab(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, inv, oi, h.t, tn1);
+    const uint32_t l0 = bits(n3.x), l1 = bits(n3.y);
+    if (h0 && (l0 & kLeafBit)) {
+      test_leaf(sc, l0, o, d, excl, h, tris);
+      h0 = false;
+    }
+    if (h1 && (l1 & kLeafBit)) {
+      test_leaf(sc, l1, o, d, excl, h, tris);
+      h1 = false;
+    }
+    if (h0 && h1) {
+      const bool first0 = tn0 <= tn1;
+      if (sp < kStackDepth) stack[sp++][tid] = first0 ? l1 : l0;
+      ni = first0 ? l0 : l1;
+    } else if (h0) {
+      ni = l0;
+    } else if (h1) {
+      ni = l1;
+    } else {
+      if (sp == 0) break;
+      ni = stack[--sp][tid];
+    }
+  }
+  return h;
+}
+
+__global__ __launch_bounds__(kTraceThreads) void k_extend(RenderArgs a) {
+  __shared__ uint32_t stack[kStackDepth][kTraceThreads];
+  __shared__ uint32_t cnt[3];  // rays traced, nodes visited, triangles tested
+  if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t n = a.ctl[a.depth].n;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const float4 th = a.qin.thr[i];
+    if (__float_as_uint(th.w) & kFlagDead) {
+      a.hit[i] = make_float4(__builtin_inff(), 0.0f, 0.0f, __uint_as_float(kMiss));
+    } else {
+      const float4 og = a.qin.orig[i], dr = a.qin.dir[i];
+      uint32_t nodes = 0, tris = 0;
+      const HitState h = traverse(a.sc, xyz(og), xyz(dr), bits(og.w), stack, nodes, tris);
+      a.hit[i] = make_float4(h.t, h.b1, h.b2, __uint_as_float(h.prim));
+      atomicAdd(&cnt[0], 1u);
+      atomicAdd(&cnt[1], nodes);
+      atomicAdd(&cnt[2], tris);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && cnt[0]) {
+    atomicAdd(a.rays, (unsigned long long)cnt[0]);
+    atomicAdd(a.rays + 1, (unsigned long long)cnt[1]);
+    atomicAdd(a.rays + 2, (unsigned long long)cnt[2]);
+  }
+}
+
+// ------------------------------------------------------------------------------- shade
+__device__ __forceinline__ void emit(const RenderArgs& a, uint32_t pix, V3 t, V3 le, int4 rec) {
+  const V3 c = mul(t, le);
+  double* px = a.image + 3ull * pix;
+  atomicAdd(px + 0, (double)c.x);
+  atomicAdd(px + 1, (double)c.y);
+  atomicAdd(px + 2, (double)c.z);
+  if (a.records_on) {
+    const float l = lum(c);
+    if (rec.x >= 0) atomicAdd(a.rec.acc + rec.x, l);
+    if (rec.y >= 0) atomicAdd(a.rec.acc + rec.y, l);
+    if (rec.z >= 0) atomicAdd(a.rec.acc + rec.z, l);
+    if (rec.w >= 0) atomicAdd(a.rec.acc + rec.w, l);
+  }
+}
+
+__global__ __launch_bounds__(kEntryThreads) void k_shade(RenderArgs a) {
+  const uint32_t n = a.ctl[a.depth].n;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 th = a.qin.thr[i];
+  const uint32_t flags = bits(th.w);
+  float q = 0.0f;
+  if (!(flags & kFlagDead)) {
+    const V3 t = xyz(th);
+    const float4 dr = a.qin.dir[i];
+    const uint32_t pix = bits(dr.w);
+    const float4 hh = a.hit[i];
+    const uint32_t prim = bits(hh.w);
+    int4 rec = a.records_on ? a.qin.rec[i] : make_int4(-1, -1, -1, -1);
+    if (prim == kMiss) {
+      emit(a, pix, t, v3(a.sc.env_r, a.sc.env_g, a.sc.env_b), rec);
+    } else {
+      const float4 a0 = a.sc.tri[3 * prim], a1 = a.sc.tri[3 * prim + 1], a2 = a.sc.tri[3 * prim + 2];
+      const V3 e1 = xyz(a1), e2 = xyz(a2);
+      const uint32_t mid = bits(a1.w);
+      const V3 ng = normalized(cross(e1, e2));
+      const V3 p = xyz(a0) + hh.y * e1 + hh.z * e2;
+      const V3 wo = v3(-dr.x, -dr.y, -dr.z);
+      const bool front = dot(ng, wo) > 0.0f;
+      const V3 nrm = front ? ng : v3(-ng.x, -ng.y, -ng.z);
+      const float4 m0 = a.sc.mat[2 * mid], m1 = a.sc.mat[2 * mid + 1];
+      const uint32_t type = bits(m1.w);
+      if (front && (m1.x != 0.0f || m1.y != 0.0f || m1.z != 0.0f)) emit(a, pix, t, xyz(m1), rec);
+      if (a.depth < a.max_depth && type != 2u) {
+        q = a.mode == 0u ? 1.0f : lum(mul(t, xyz(m0)));
+        if (a.records_on && (flags & kFlagTrain) && a.depth <= a.net_max_depth && a.depth <= (uint32_t)kMaxRec) {
+          const uint32_t slot = atomicAdd(a.rec.count, 1u);
+          if (slot < a.rec.cap) {
+            float f[20];
+            vertex_features(a.sc, p, nrm, wo, t, m0, type, a.depth, a.max_depth, f);
+            float* dst = a.rec.feat + 20ull * slot;
+#pragma unroll
+            for (int k = 0; k < 20; ++k) dst[k] = f[k];
+            a.rec.lum_t[slot] = lum(t);
+            a.rec.acc[slot] = 0.0f;
+            a.rec.depth[slot] = a.depth;
+            a.rec.pix[slot] = pix;
+            a.rec.lineage[slot] = a.qin.id[i];
+            if (a.depth == 1) rec.x = (int)slot;
+            else if (a.depth == 2) rec.y = (int)slot;
+            else if (a.depth == 3) rec.z = (int)slot;
+            else rec.w = (int)slot;
+            a.qin.rec[i] = rec;
+          }
+        }
+      }
+      a.vpos[i] = pack(p, prim);
+      a.vnrm[i] = pack(nrm, mid);
+    }
+  }
+  a.q[i] = q;
+}
+
+// -------------------------------------------------------------------- FP64 sum of q
+// Chunked: block b owns entries [b*chunk, (b+1)*chunk); a fixed grid and fixed reduction
+// tree make the FP64 sum the same on every run.
+__device__ __forceinline__ uint32_t chunk_of(uint32_t n) {
+  uint32_t c = (n + kScanBlocks - 1) / kScanBlocks;
+  return (c + kScanThreads - 1) / kScanThreads * kScanThreads;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = kScanThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] += sh[tid + s];
+    __syncthreads();
+  }
+  T r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_sum_q_partial(RenderArgs a) {
+  __shared__ double sh[kScanThreads];
+  const uint32_t n = a.ctl[a.depth].n;
+  const uint32_t chunk = chunk_of(n);
+  const uint32_t beg = blockIdx.x * chunk;
+  double acc = 0.0;
+  for (uint32_t base = beg; base < beg + chunk && base < n; base += kScanThreads) {
+    const uint32_t i = base + threadIdx.x;
+    if (i < n && i < beg + chunk) acc += (double)a.q[i];
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_sum_q_final(RenderArgs a) {
+  __shared__ double sh[kScanThreads];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < kScanBlocks; b += kScanThreads) acc += a.partial[b];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) a.ctl[a.depth].sumq = s;
+}
+
+// ------------------------------------------------------------ roulette and scan
+// Normalization factor for a given alpha (Eqs. 10, 12-14; Sec. 5 downscale variant).
+__device__ __forceinline__ double norm_factor(const RenderArgs& a, double sumq, double alpha) {
+  if (a.mode == 0u) return 1.0;
+  if (!(sumq > 0.0)) return 0.0;
+  double F = (a.f_rate * alpha) * a.budget_base / sumq;
+  if (a.norm_mode == 1u && F > 1.0) F = 1.0;
+  return F;
+}
+
+// Eq. (8): X = floor(q_norm) + [u < q_norm - floor(q_norm)] with q_norm rounded to float.
+__device__ __forceinline__ uint32_t child_count(float q, double F, float u) {
+  const float qn = (float)(F * (double)q);
+  const float k = floorf(qn);
+  return (uint32_t)k + (u < qn - k ? 1u : 0u);
+}
+
+__device__ __forceinline__ float roulette_u(const RenderArgs& a, uint32_t i) {
+  return unit(draw(a.key, a.qin.id[i], kPurposeRoulette, a.depth, 0).x);
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_roulette_count(RenderArgs a) {
+  __shared__ uint32_t sh[kScanThreads];
+  const uint32_t n = a.ctl[a.depth].n;
+  const uint32_t chunk = chunk_of(n);
+  const uint32_t beg = blockIdx.x * chunk;
+  const double F = norm_factor(a, a.ctl[a.depth].sumq, *a.alpha);
+  uint32_t acc = 0;
+  for (uint32_t base = beg; base < beg + chunk && base < n; base += kScanThreads) {
+    const uint32_t i = base + threadIdx.x;
+    if (i < n && i < beg + chunk) {
+      const float q = a.q[i];
+      if (q > 0.0f) acc += child_count(q, F, roulette_u(a, i));
+    }
+  }
+  const uint32_t s = block_sum(acc, sh);
+  if (threadIdx.x == 0) a.bsum[blockIdx.x] = s;
+}
+
+// Exclusive scan of kScanBlocks values by one block of kScanThreads threads (4 per thread).
+__device__ __forceinline__ uint64_t scan_blocks(const uint32_t* in, uint32_t* out, uint64_t* sh) {
+  const int tid = threadIdx.x;
+  constexpr int per = kScanBlocks / kScanThreads;
+  uint64_t local[per];
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < per; ++k) {
+    local[k] = in[tid * per + k];
+    s += local[k];
+  }
+  sh[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    uint64_t v = tid >= off ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += v;
+    __syncthreads();
+  }
+  const uint64_t total = sh[kScanThreads - 1];
+  uint64_t run = sh[tid] - s;
+  if (out) {
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+      out[tid * per + k] = (uint32_t)run;
+      run += local[k];
+    }
+  }
+  __syncthreads();
+  return total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_roulette_scan(RenderArgs a) {
+  __shared__ uint64_t sh[kScanThreads];
+  const uint64_t S = scan_blocks(a.bsum, a.boff, sh);
+  if (threadIdx.x == 0) {
+    DepthCtl& c = a.ctl[a.depth];
+    c.retries = 0;
+    c.F = norm_factor(a, c.sumq, *a.alpha);
+    if (S > a.cap) {
+      c.guard = 1;
+    } else {
+      c.guard = 0;
+      c.S = (uint32_t)S;
+      a.ctl[a.depth + 1].n = (uint32_t)S;
+    }
+  }
+}
+
+// Overflow guard, only active when the first count overflowed: counts for the next
+// kGuardSteps values alpha * 0.99^k, k = 1..kGuardSteps (Eq. 14 applied repeatedly).
+__global__ __launch_bounds__(kScanThreads) void k_guard_count(RenderArgs a) {
+  if (a.ctl[a.depth].guard == 0) return;
+  __shared__ uint32_t sh[kScanThreads];
+  const uint32_t n = a.ctl[a.depth].n;
+  const uint32_t chunk = chunk_of(n);
+  const uint32_t beg = blockIdx.x * chunk;
+  const double sumq = a.ctl[a.depth].sumq;
+  double alpha = *a.alpha;
+  for (int k = 0; k < kGuardSteps; ++k) {
+    alpha *= 0.99;
+    const double F = norm_factor(a, sumq, alpha);
+    uint32_t acc = 0;
+    for (uint32_t base = beg; base < beg + chunk && base < n; base += kScanThreads) {
+      const uint32_t i = base + threadIdx.x;
+      if (i < n && i < beg + chunk) {
+        const float q = a.q[i];
+        if (q > 0.0f) acc += child_count(q, F, roulette_u(a, i));
+      }
+    }
+    const uint32_t s = block_sum(acc, sh);
+    if (threadIdx.x == 0) a.gsum[kScanBlocks * k + blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_guard_select(RenderArgs a) {
+  if (a.ctl[a.depth].guard == 0) return;
+  __shared__ uint64_t sh[kScanThreads];
+  __shared__ int chosen;
+  DepthCtl& c = a.ctl[a.depth];
+  if (threadIdx.x == 0) chosen = -1;
+  __syncthreads();
+  for (int k = 0; k < kGuardSteps; ++k) {
+    const uint64_t S = scan_blocks(a.gsum + kScanBlocks * k, nullptr, sh);
+    if (S <= a.cap) {
+      scan_blocks(a.gsum + kScanBlocks * k, a.boff, sh);
+      if (threadIdx.x == 0) {
+        chosen = k;
+        double alpha = *a.alpha;
+        for (int j = 0; j <= k; ++j) alpha *= 0.99;
+        *a.alpha = alpha;
+        c.F = norm_factor(a, c.sumq, alpha);
+        c.S = (uint32_t)S;
+        c.retries = (uint32_t)(k + 1);
+        a.ctl[a.depth + 1].n = (uint32_t)S;
+      }
+      break;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && chosen < 0) {
+    // no candidate fits: end this pass at this depth and report it
+    double alpha = *a.alpha;
+    for (int j = 0; j < kGuardSteps; ++j) alpha *= 0.99;
+    *a.alpha = alpha;
+    c.F = 0.0;
+    c.S = 0;
+    c.retries = kGuardSteps;
+    a.ctl[a.depth + 1].n = 0;
+    *a.overflow = 1;
+  }
+  if (chosen < 0)
+    for (int b = threadIdx.x; b < kScanBlocks; b += kScanThreads) a.boff[b] = 0;
+}
+
+// First child slot of every entry: per-tile exclusive scan plus the block's offset.
+__global__ __launch_bounds__(kScanThreads) void k_offsets(RenderArgs a) {
+  __shared__ uint32_t sh[kScanThreads];
+  const uint32_t n = a.ctl[a.depth].n;
+  const uint32_t chunk = chunk_of(n);
+  const uint32_t beg = blockIdx.x * chunk;
+  const double F = a.ctl[a.depth].F;
+  uint32_t run = a.boff[blockIdx.x];
+  const int tid = threadIdx.x;
+  for (uint32_t base = beg; base < beg + chunk && base < n; base += kScanThreads) {
+    const uint32_t i = base + tid;
+    uint32_t x = 0;
+    if (i < n && i < beg + chunk) {
+      const float q = a.q[i];
+      if (q > 0.0f) x = child_count(q, F, roulette_u(a, i));
+    }
+    sh[tid] = x;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+      const uint32_t v = tid >= off ? sh[tid - off] : 0u;
+      __syncthreads();
+      sh[tid] += v;
+      __syncthreads();
+    }
+    if (i < n && i < beg + chunk) a.offs[i] = run + sh[tid] - x;
+    run += sh[kScanThreads - 1];
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------ expand
+// One thread per child slot: find the parent by binary search over the offsets, sample
+// the BSDF with the child's own random numbers and write the child densely.
+// Largest i with offs[i] <= s: the parent of child slot s under parent-major compaction.
+__device__ __forceinline__ uint32_t find_parent(const uint32_t* offs, uint32_t n, uint32_t s) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (offs[mid] <= s) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kEntryThreads) void k_parents(RenderArgs a) {
+  const uint32_t S = a.ctl[a.depth].S;
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S) a.dbg_parent[s] = find_parent(a.offs, a.ctl[a.depth].n, s);
+}
+
+__global__ __launch_bounds__(kEntryThreads) void k_expand(RenderArgs a) {
+  const uint32_t S = a.ctl[a.depth].S;
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const uint32_t i = find_parent(a.offs, a.ctl[a.depth].n, s);
+  const uint32_t j = s - a.offs[i];
+  const float qn = (float)(a.ctl[a.depth].F * (double)a.q[i]);
+  const float4 vp = a.vpos[i], vn = a.vnrm[i], dr = a.qin.dir[i], th = a.qin.thr[i];
+  const uint2 lin = a.qin.id[i];
+  const uint32_t mid = bits(vn.w);
+  const float4 m0 = a.sc.mat[2 * mid], m1 = a.sc.mat[2 * mid + 1];
+  const V3 nrm = xyz(vn);
+  V3 tb, bb;
+  basis(nrm, tb, bb);
+  const V3 wo = v3(-dr.x, -dr.y, -dr.z);
+  const V3 wol = v3(dot(wo, tb), dot(wo, bb), dot(wo, nrm));
+  const uint4 r = draw(a.key, lin, kPurposeChild, a.depth, j);
+  const float u2 = unit(r.x), u3 = unit(r.y);
+  V3 wil, w;
+  bool alive = true;
+  if (bits(m1.w) == 1u) {
+    alive = sample_ggx(m0.w, xyz(m0), wol, u2, u3, wil, w);
+  } else {
+    wil = sample_cosine(u2, u3);
+    w = xyz(m0);
+  }
+  const V3 wi = normalized(wil.x * tb + wil.y * bb + wil.z * nrm);
+  const float inv_q = 1.0f / qn;
+  const V3 tc = alive ? v3(th.x * w.x * inv_q, th.y * w.y * inv_q, th.z * w.z * inv_q) : v3(0.0f, 0.0f, 0.0f);
+  const uint32_t flags = (bits(th.w) & kFlagTrain) | (alive ? 0u : kFlagDead);
+  a.qout.orig[s] = make_float4(vp.x, vp.y, vp.z, vp.w);
+  a.qout.dir[s] = pack(wi, bits(dr.w));
+  a.qout.thr[s] = pack(tc, flags);
+  a.qout.id[s] = make_uint2(r.z, r.w);
+  if (a.records_on) a.qout.rec[s] = a.qin.rec[i];
+}
+
+// ------------------------------------------------------------------------------ misc
+__global__ void k_guide(const double* image, uint32_t npx, double spp, float* guide) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npx) return;
+  const double* c = image + 3ull * p;
+  guide[p] = (float)((0.2126 * c[0] + 0.7152 * c[1] + 0.0722 * c[2]) / spp);
+}
+
+__global__ void k_zero_u32(uint32_t* p, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+__global__ void k_zero_f64(double* p, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+__global__ void k_fill_f32(float* p, uint64_t n, float v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_set_f64(double* p, double v) { *p = v; }
+
+__global__ void k_accumulate_stats(const DepthCtl* ctl, uint32_t D, unsigned long long* n_sum,
+                                   unsigned long long* s_sum, unsigned long long* r_sum, double* sumq_last,
+                                   double* f_last) {
+  const uint32_t d = threadIdx.x + 1;
+  if (d > D) return;
+  n_sum[d] += ctl[d].n;
+  if (d < D) {
+    s_sum[d] += ctl[d].S;
+    r_sum[d] += ctl[d].retries;
+    sumq_last[d] = ctl[d].sumq;
+    f_last[d] = ctl[d].F;
+  }
+}
+
+__global__ __launch_bounds__(kTraceThreads) void k_trace_rays(DevScene sc, const float4* orig, const float4* dir,
+                                                             float4* hit, uint32_t n) {
+  __shared__ uint32_t stack[kStackDepth][kTraceThreads];
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 og = orig[i], dr = dir[i];
+  uint32_t nodes = 0, tris = 0;
+  const HitState h = traverse(sc, xyz(og), xyz(dr), bits(og.w), stack, nodes, tris);
+  hit[i] = make_float4(h.t, h.b1, h.b2, __uint_as_float(h.prim));
+}
+
+__global__ void k_philox(const uint4* ctr, uint2 key, uint4* out, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = philox(ctr[i], key);
+}
+
+inline uint32_t blocks_for(uint64_t n, int threads) { return (uint32_t)((n + threads - 1) / threads); }
+
+}  // namespace
+
+void launch_camera(const RenderArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_camera, dim3(blocks_for(a.nprim, kEntryThreads)), dim3(kEntryThreads), 0, s, a);
+}
+void launch_extend(const RenderArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_extend, dim3(blocks_for(a.cap, kTraceThreads)), dim3(kTraceThreads), 0, s, a);
+}
+void launch_shade(const RenderArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_shade, dim3(blocks_for(a.cap, kEntryThreads)), dim3(kEntryThreads), 0, s, a);
+}
+void launch_sum_q(const RenderArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_q_partial, dim3(kScanBlocks), dim3(kScanThreads), 0, s, a);
+  hipLaunchKernelGGL(k_sum_q_final, dim3(1), dim3(kScanThreads), 0, s, a);
+}
+void launch_roulette(const RenderArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_roulette_count, dim3(kScanBlocks), dim3(kScanThreads), 0, s, a);
+  hipLaunchKernelGGL(k_roulette_scan, dim3(1), dim3(kScanThreads), 0, s, a);
+  hipLaunchKernelGGL(k_guard_count, dim3(kScanBlocks), dim3(kScanThreads), 0, s, a);
+  hipLaunchKernelGGL(k_guard_select, dim3(1), dim3(kScanThreads), 0, s, a);
+  hipLaunchKernelGGL(k_offsets, dim3(kScanBlocks), dim3(kScanThreads), 0, s, a);
+}
+void launch_expand(const RenderArgs& a, hipStream_t s) {
+  if (a.cap == 0) return;
+  hipLaunchKernelGGL(k_expand, dim3(blocks_for(a.cap, kEntryThreads)), dim3(kEntryThreads), 0, s, a);
+}
+void launch_parents(const RenderArgs& a, hipStream_t s) {
+  if (a.cap == 0) return;
+  hipLaunchKernelGGL(k_parents, dim3(blocks_for(a.cap, kEntryThreads)), dim3(kEntryThreads), 0, s, a);
+}
+void launch_guide(const RenderArgs& a, double spp_total, float* guide, hipStream_t s) {
+  const uint32_t npx = a.width * a.height;
+  hipLaunchKernelGGL(k_guide, dim3(blocks_for(npx, 256)), dim3(256), 0, s, a.image, npx, spp_total, guide);
+}
+void launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_zero_u32, dim3(std::min<uint64_t>(blocks_for(n, 256), 4096)), dim3(256), 0, s, p, n);
+}
+void launch_zero_f64(double* p, uint64_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_zero_f64, dim3(std::min<uint64_t>(blocks_for(n, 256), 4096)), dim3(256), 0, s, p, n);
+}
+void launch_fill_f32(float* p, uint64_t n, float v, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill_f32, dim3(std::min<uint64_t>(blocks_for(n, 256), 4096)), dim3(256), 0, s, p, n, v);
+}
+void launch_set_f64(double* p, double v, hipStream_t s) { hipLaunchKernelGGL(k_set_f64, dim3(1), dim3(1), 0, s, p, v); }
+void launch_accumulate_stats(const DepthCtl* ctl, uint32_t max_depth, unsigned long long* n_sum,
+                             unsigned long long* s_sum, unsigned long long* r_sum, double* sumq_last,
+                             double* f_last, hipStream_t s) {
+  hipLaunchKernelGGL(k_accumulate_stats, dim3(1), dim3(64), 0, s, ctl, max_depth, n_sum, s_sum, r_sum, sumq_last,
+                     f_last);
+}
+void launch_trace_rays(const DevScene& sc, const float4* orig, const float4* dir, float4* hit, uint32_t n,
+                       hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_trace_rays, dim3(blocks_for(n, kTraceThreads)), dim3(kTraceThreads), 0, s, sc, orig, dir, hit, n);
+}
+void launch_philox(const uint4* ctr, uint2 key, uint4* out, uint32_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_philox, dim3(blocks_for(n, 256)), dim3(256), 0, s, ctr, key, out, n);
+}
+
+}  // namespace nrrs

@@ -1,0 +1,306 @@
+"""Thin ctypes binding of libnrrs.so (the C ABI of include/nrrs.h).
+
+Argument marshalling only: every step of the render and of training runs in the
+library's HIP kernels.  PyTorch provides the device workspace (one uint8 tensor) and
+the HIP stream.  Importing this module does not touch the GPU; creating a Renderer
+raises if the library is not built or no gfx950 device is present.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnrrs.so")
+NPARAM = 9729
+MAX_DEPTH = 64
+MODE_OFF, MODE_HEURISTIC, MODE_NET = 0, 1, 2
+NORM_TWO_SIDED, NORM_DOWNSCALE = 0, 1
+PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
+MISS = 0xFFFFFFFF
+NSTAGES = 8
+STAGES = ["camera", "extend", "shade", "network", "sum_q", "roulette_scan", "expand", "pass_end"]
+
+EXPORTS = [
+    "nrrs_create", "nrrs_workspace_size", "nrrs_bind_workspace", "nrrs_upload_scene", "nrrs_render",
+    "nrrs_set_timing", "nrrs_train_step", "nrrs_read_image", "nrrs_reset_image", "nrrs_set_guide", "nrrs_get_guide",
+    "nrrs_get_params", "nrrs_set_params", "nrrs_read_records", "nrrs_debug_rrs_expand",
+    "nrrs_debug_load_records", "nrrs_debug_trace",
+    "nrrs_debug_philox", "nrrs_debug_mlp_forward", "nrrs_debug_mlp_grad", "nrrs_status_string",
+    "nrrs_last_error", "nrrs_destroy",
+]
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("width", C.c_uint32), ("height", C.c_uint32), ("s_batch", C.c_uint32),
+        ("cap_factor", C.c_double), ("f_rate", C.c_double), ("norm_mode", C.c_int32), ("seed", C.c_uint64),
+        ("net_max_depth", C.c_int32), ("precision", C.c_int32), ("records_cap", C.c_uint32),
+        ("p_train", C.c_double),
+    ]
+
+
+class RenderStats(C.Structure):
+    _fields_ = [
+        ("max_depth", C.c_uint32), ("passes", C.c_uint32),
+        ("n", C.c_uint64 * (MAX_DEPTH + 1)), ("S", C.c_uint64 * (MAX_DEPTH + 1)),
+        ("retries", C.c_uint64 * (MAX_DEPTH + 1)), ("sumq", C.c_double * (MAX_DEPTH + 1)),
+        ("F", C.c_double * (MAX_DEPTH + 1)), ("alpha", C.c_double), ("rays", C.c_uint64),
+        ("nodes_visited", C.c_uint64), ("tris_tested", C.c_uint64),
+        ("records", C.c_uint64), ("overflow", C.c_uint32), ("timed", C.c_uint32),
+        ("stage_ms", C.c_double * NSTAGES), ("stage_launches", C.c_uint64 * NSTAGES),
+    ]
+
+
+class NrrsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"nrrs error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libnrrs.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2510_07868_amd.build.build()")
+    # torch first: its HIP runtime (SONAME libamdhip64.so.7) is then the one libnrrs binds to, so
+    # the library, torch's allocator and torch's streams all live in one runtime instance.
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    P, U32, U64, I32, D = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32, C.c_double
+    sig = {
+        "nrrs_create": [P, P, P],
+        "nrrs_workspace_size": [P, U64, U32, P],
+        "nrrs_bind_workspace": [P, P, U64, U64, U32],
+        "nrrs_upload_scene": [P, P, U64, P, U64, P, P, P, U32, P, P],
+        "nrrs_render": [P, U32, U32, I32, P],
+        "nrrs_set_timing": [P, I32],
+        "nrrs_train_step": [P, U32, U32, C.c_float, P],
+        "nrrs_read_image": [P, P, P],
+        "nrrs_reset_image": [P],
+        "nrrs_set_guide": [P, P],
+        "nrrs_get_guide": [P, P],
+        "nrrs_get_params": [P, P, P, P, P],
+        "nrrs_set_params": [P, P, P, P, P],
+        "nrrs_read_records": [P, P, P, P, P, P, P, P],
+        "nrrs_debug_rrs_expand": [P, P, P, P, U32, U32, D, D, P, I32, U32, P, P, P, P, P, P, P],
+        "nrrs_debug_load_records": [P, P, P, P, U32],
+        "nrrs_debug_trace": [P, P, P, U32, P, P, P, P],
+        "nrrs_debug_philox": [P, P, P, U32, P],
+        "nrrs_debug_mlp_forward": [P, P, U32, I32, P, P],
+        "nrrs_debug_mlp_grad": [P, P, P, U32, P, P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = I32
+    L.nrrs_status_string.argtypes = [I32]
+    L.nrrs_status_string.restype = C.c_char_p
+    L.nrrs_last_error.argtypes = [P]
+    L.nrrs_last_error.restype = C.c_char_p
+    L.nrrs_destroy.argtypes = [P]
+    L.nrrs_destroy.restype = None
+    _lib = L
+    return L
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class Renderer:
+    """One rendering context bound to a torch-allocated workspace on ``device``."""
+
+    def __init__(self, width, height, s_batch=1, cap_factor=2.0, f_rate=1.0, norm_mode=NORM_TWO_SIDED, seed=0,
+                 net_max_depth=4, precision=PREC_FP32, records_cap=0, p_train=0.0, max_tris=1 << 16,
+                 max_materials=4096, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.L = load()
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.cfg = Config(width, height, s_batch, cap_factor, f_rate, norm_mode, seed, net_max_depth, precision,
+                          records_cap, p_train)
+        self.width, self.height, self.s_batch = width, height, s_batch
+        self.records_cap = records_cap
+        h = C.c_void_p()
+        self._check(self.L.nrrs_create(C.byref(self.cfg), C.c_void_p(self.stream.cuda_stream), C.byref(h)), None)
+        self.h = h
+        nbytes = C.c_uint64()
+        self._check(self.L.nrrs_workspace_size(self.h, max_tris, max_materials, C.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self._check(self.L.nrrs_bind_workspace(self.h, C.c_void_p(self.workspace.data_ptr()), int(nbytes.value),
+                                               max_tris, max_materials))
+        self.max_tris = max_tris
+        self.workspace_bytes = int(nbytes.value)
+
+    # ---------------------------------------------------------------- plumbing
+    def _check(self, code, h="self"):
+        if code != 0:
+            L = self.L
+            msg = L.nrrs_status_string(code).decode()
+            if h is not None and getattr(self, "h", None):
+                msg += ": " + L.nrrs_last_error(self.h).decode()
+            raise NrrsError(code, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.nrrs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- API
+    def upload_scene(self, scene):
+        v = _c(scene.verts, np.float32)
+        t = _c(scene.tris, np.uint32)
+        tm = _c(scene.tri_mat, np.uint32)
+        mt = _c(scene.mat_type, np.uint32)
+        mp = _c(scene.mat_params, np.float32)
+        cam = _c(scene.camera, np.float32)
+        env = _c(scene.env, np.float32)
+        self._check(self.L.nrrs_upload_scene(self.h, _p(v), v.shape[0], _p(t), t.shape[0], _p(tm), _p(mt), _p(mp),
+                                             mt.shape[0], _p(cam), _p(env)))
+
+    def render(self, spp, max_depth, mode, stats=True):
+        st = RenderStats()
+        code = self.L.nrrs_render(self.h, spp, max_depth, mode, C.byref(st) if stats else None)
+        if code != 0 and not (stats and code == -5):
+            self._check(code)
+        if not stats:
+            return None
+        D = max_depth
+        return dict(status=int(code), n=np.array(st.n[: D + 1], np.uint64), S=np.array(st.S[: D + 1], np.uint64),
+                    retries=np.array(st.retries[: D + 1], np.uint64), sumq=np.array(st.sumq[: D + 1]),
+                    F=np.array(st.F[: D + 1]), alpha=st.alpha, rays=int(st.rays), records=int(st.records),
+                    nodes_visited=int(st.nodes_visited), tris_tested=int(st.tris_tested),
+                    overflow=int(st.overflow), passes=int(st.passes), timed=bool(st.timed),
+                    stage_ms={k: float(st.stage_ms[i]) for i, k in enumerate(STAGES)},
+                    stage_launches={k: int(st.stage_launches[i]) for i, k in enumerate(STAGES)})
+
+    def set_timing(self, enabled=True):
+        self._check(self.L.nrrs_set_timing(self.h, 1 if enabled else 0))
+
+    def read_image(self):
+        img = np.zeros(self.width * self.height * 3)
+        spp = C.c_uint64()
+        self._check(self.L.nrrs_read_image(self.h, _p(img), C.byref(spp)))
+        return img, int(spp.value)
+
+    def reset_image(self):
+        self._check(self.L.nrrs_reset_image(self.h))
+
+    def set_guide(self, lum):
+        g = _c(lum, np.float32)
+        assert g.size == self.width * self.height
+        self._check(self.L.nrrs_set_guide(self.h, _p(g)))
+
+    def get_guide(self):
+        g = np.zeros(self.width * self.height, np.float32)
+        self._check(self.L.nrrs_get_guide(self.h, _p(g)))
+        return g
+
+    def get_params(self):
+        w, m, v = (np.zeros(NPARAM, np.float32) for _ in range(3))
+        step = C.c_uint64()
+        self._check(self.L.nrrs_get_params(self.h, _p(w), _p(m), _p(v), C.byref(step)))
+        return w, m, v, int(step.value)
+
+    def set_params(self, master=None, m=None, v=None, step=None):
+        arrs = [None if a is None else _c(a, np.float32) for a in (master, m, v)]
+        for a in arrs:
+            assert a is None or a.size == NPARAM
+        st = None if step is None else C.byref(C.c_uint64(int(step)))
+        self._check(self.L.nrrs_set_params(self.h, *[None if a is None else _p(a) for a in arrs], st))
+
+    def read_records(self):
+        n = C.c_uint64()
+        self._check(self.L.nrrs_read_records(self.h, C.byref(n), None, None, None, None, None, None))
+        k = int(n.value)
+        f = np.zeros((max(k, 1), 20), np.float32)
+        lt, acc = np.zeros(max(k, 1), np.float32), np.zeros(max(k, 1), np.float32)
+        d, px = np.zeros(max(k, 1), np.uint32), np.zeros(max(k, 1), np.uint32)
+        lin = np.zeros(max(k, 1), np.uint64)
+        self._check(self.L.nrrs_read_records(self.h, C.byref(n), _p(f), _p(lt), _p(acc), _p(d), _p(px), _p(lin)))
+        return dict(feat=f[:k], lum_t=lt[:k], acc=acc[:k], depth=d[:k], pix=px[:k], id=lin[:k])
+
+    def train_step(self, n_records, minibatch, lr):
+        loss = C.c_float()
+        self._check(self.L.nrrs_train_step(self.h, n_records, minibatch, C.c_float(lr), C.byref(loss)))
+        return float(loss.value)
+
+    # ---------------------------------------------------------------- test entry points
+    def debug_rrs_expand(self, q, id_lo, id_hi, depth, budget_base, f_rate=1.0, alpha=1.0,
+                         norm_mode=NORM_TWO_SIDED, cap=None):
+        q = _c(q, np.float32)
+        lo, hi = _c(id_lo, np.uint32), _c(id_hi, np.uint32)
+        n = q.size
+        cap = int(2 * budget_base) if cap is None else int(cap)
+        X = np.zeros(max(n, 1), np.uint32)
+        off = np.zeros(max(n, 1), np.uint32)
+        par = np.zeros(max(cap, 1), np.uint32)
+        S = C.c_uint32()
+        F = C.c_double()
+        a = C.c_double(alpha)
+        qn = np.zeros(max(n, 1), np.float32)
+        r = C.c_uint32()
+        code = self.L.nrrs_debug_rrs_expand(self.h, _p(q), _p(lo), _p(hi), n, depth, float(budget_base),
+                                            float(f_rate), C.byref(a), norm_mode, cap, _p(X), _p(off), _p(par),
+                                            C.byref(S), C.byref(F), _p(qn), C.byref(r))
+        if code not in (0, -5):
+            self._check(code)
+        return dict(status=int(code), X=X[:n], offset=off[:n], parent=par[: S.value].copy(), S=int(S.value),
+                    F=float(F.value), q_norm=qn[:n], alpha=float(a.value), retries=int(r.value))
+
+    def debug_load_records(self, feat, lum_t, acc):
+        f = _c(feat, np.float32).reshape(-1, 20)
+        lt, ac = _c(lum_t, np.float32), _c(acc, np.float32)
+        assert lt.size == ac.size == f.shape[0]
+        self._check(self.L.nrrs_debug_load_records(self.h, _p(f), _p(lt), _p(ac), f.shape[0]))
+
+    def debug_trace(self, rays, exclude=None):
+        rays = _c(rays, np.float32).reshape(-1, 6)
+        n = rays.shape[0]
+        ex = _c(exclude if exclude is not None else np.full(n, MISS), np.uint32)
+        prim = np.zeros(n, np.uint32)
+        t, b1, b2 = (np.zeros(n, np.float32) for _ in range(3))
+        self._check(self.L.nrrs_debug_trace(self.h, _p(rays), _p(ex), n, _p(prim), _p(t), _p(b1), _p(b2)))
+        return prim, t, b1, b2
+
+    def debug_philox(self, ctr, key):
+        ctr = _c(ctr, np.uint32).reshape(-1, 4)
+        out = np.zeros_like(ctr)
+        k = _c(key, np.uint32)
+        self._check(self.L.nrrs_debug_philox(self.h, _p(ctr), _p(k), ctr.shape[0], _p(out)))
+        return out
+
+    def debug_mlp_forward(self, x, precision=PREC_FP32):
+        x = _c(x, np.float32).reshape(-1, 20)
+        n = x.shape[0]
+        y, z = np.zeros(n, np.float32), np.zeros(n, np.float32)
+        self._check(self.L.nrrs_debug_mlp_forward(self.h, _p(x), n, precision, _p(y), _p(z)))
+        return y, z
+
+    def debug_mlp_grad(self, x, target):
+        x = _c(x, np.float32).reshape(-1, 20)
+        tg = _c(target, np.float32)
+        g = np.zeros(NPARAM, np.float32)
+        loss = C.c_float()
+        self._check(self.L.nrrs_debug_mlp_grad(self.h, _p(x), _p(tg), x.shape[0], _p(g), C.byref(loss)))
+        return float(loss.value), g
