@@ -56,6 +56,11 @@ enum nrrs_precision { NRRS_PREC_FP32 = 0, NRRS_PREC_BF16 = 1, NRRS_PREC_FP8 = 2 
 
 enum nrrs_material_type { NRRS_MAT_LAMBERT = 0, NRRS_MAT_GGX = 1, NRRS_MAT_EMITTER = 2 };
 
+/* Training loss of the network's radiance estimate y against a record's one-sample target L:
+ * relative L2 (y - L)^2 / (sg(y)^2 + 0.01), the statistic loss of Sec. 4.2.2 Eq. (15) whose
+ * minimiser is the mean radiance; or (ln(y + 0.01) - ln(L + 0.01))^2. */
+enum nrrs_loss { NRRS_LOSS_REL_L2 = 0, NRRS_LOSS_LOG_MSE = 1 };
+
 #define NRRS_MAX_DEPTH 64
 #define NRRS_NSTAGES 8 /* camera, extend, shade, network, sum, roulette+scan, expand, pass end */
 #define NRRS_NPARAM 9729 /* 20-64-64-64-1 network: weights and biases */
@@ -71,6 +76,9 @@ typedef struct {
   int32_t precision;      /* nrrs_precision of network inference */
   uint32_t records_cap;   /* capacity of the training-record buffer (0 = no records) */
   double p_train;         /* probability that a primary path records training vertices */
+  int32_t loss;           /* nrrs_loss used by nrrs_train_step */
+  double ema_decay;       /* inference uses an exponential moving average of the weights with this
+                             decay per Adam step (Sec. 5 "Training"); 0 = the latest weights */
 } nrrs_config;
 
 typedef struct {
@@ -134,8 +142,9 @@ int32_t nrrs_render(nrrs_ctx* ctx, uint32_t spp, uint32_t max_depth, int32_t mod
 
 /* One training epoch of the network on the first n_records records of the last render
  * (records are cleared by each render that captures them): minibatches of `minibatch`
- * records, one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) each, loss
- * mean((ln(y+0.01) - ln(L+0.01))^2) with L the record's reflected-radiance target.
+ * records, one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) each, with the
+ * configured nrrs_loss (mean over the minibatch) and L = acc / lum_t the record's reflected-
+ * radiance target.
  * *loss_or_null receives the mean loss of the epoch (synchronizes).  ESTATE if fewer than
  * n_records records exist; EINVAL if minibatch is 0 or does not divide n_records. */
 int32_t nrrs_train_step(nrrs_ctx* ctx, uint32_t n_records, uint32_t minibatch, float lr,
@@ -159,6 +168,7 @@ int32_t nrrs_get_guide(nrrs_ctx* ctx, float* host_lum);
 /* Network state: FP32 master parameters[NRRS_NPARAM], Adam m and v (same size) and the
  * Adam step count.  Layout of the parameter vector: W1[64][20], b1[64], W2[64][64], b2[64],
  * W3[64][64], b3[64], W4[64], b4.  Any pointer may be NULL to skip that part.  set also
+ * resets the inference weights (and their moving average) to the given master and
  * refreshes the BF16 / FP8 inference copies. */
 int32_t nrrs_get_params(nrrs_ctx* ctx, float* master, float* adam_m, float* adam_v, uint64_t* step);
 int32_t nrrs_set_params(nrrs_ctx* ctx, const float* master, const float* adam_m,
@@ -192,6 +202,13 @@ int32_t nrrs_debug_rrs_expand(nrrs_ctx* ctx, const float* q_orig, const uint32_t
 int32_t nrrs_debug_load_records(nrrs_ctx* ctx, const float* features, const float* lum_t,
                                 const float* acc, uint32_t n);
 
+/* Copy the first n entries of queue `which` (0 or 1; a render's passes start in queue 0 and
+ * the queues alternate by depth) and of the per-slot hit buffer of the last extended depth:
+ * orig[n*4] (origin, excluded triangle bits), dir[n*4] (direction, pixel bits), thr[n*4]
+ * (throughput, flag bits), hit[n*4] (t, b1, b2, triangle bits).  Any pointer may be NULL. */
+int32_t nrrs_debug_read_queue(nrrs_ctx* ctx, int32_t which, uint32_t n, float* orig, float* dir,
+                              float* thr, float* hit);
+
 /* Closest hit of n rays[n*6] (origin, unit direction) against the uploaded scene, skipping
  * triangle exclude[n] (original index; 0xffffffff = none).  Outputs the original triangle
  * index (0xffffffff = miss), t, and barycentrics b1, b2. */
@@ -207,8 +224,8 @@ int32_t nrrs_debug_philox(nrrs_ctx* ctx, const uint32_t* ctr, const uint32_t* ke
 int32_t nrrs_debug_mlp_forward(nrrs_ctx* ctx, const float* x, uint32_t n, int32_t precision,
                                float* y, float* z);
 
-/* Loss and its gradient grad[NRRS_NPARAM] over n (features x[n*20], target[n]) rows with the
- * current FP32 masters; no parameter update. */
+/* Loss (the configured nrrs_loss) and its gradient grad[NRRS_NPARAM] over n (features x[n*20],
+ * target[n]) rows with the current FP32 masters; no parameter update. */
 int32_t nrrs_debug_mlp_grad(nrrs_ctx* ctx, const float* x, const float* target, uint32_t n,
                             float* grad, float* loss);
 

@@ -77,8 +77,13 @@ def lib():
         L.or_enumerate.restype = C.c_int32
         L.or_enumerate.argtypes = [P, P, P, P, P, P]
         L.or_mlp_forward.argtypes = [P, P, C.c_uint64, P, P]
+        L.or_mlp_forward_quant.argtypes = [P, P, C.c_uint64, C.c_int32, P, P, P]
+        L.or_round_bf16.restype = C.c_double
+        L.or_round_bf16.argtypes = [C.c_double]
+        L.or_round_e4m3.restype = C.c_double
+        L.or_round_e4m3.argtypes = [C.c_double]
         L.or_mlp_loss_grad.restype = C.c_double
-        L.or_mlp_loss_grad.argtypes = [P, P, P, C.c_uint64, C.c_double, P]
+        L.or_mlp_loss_grad.argtypes = [P, P, P, C.c_uint64, C.c_double, C.c_int32, P]
         L.or_adam.argtypes = [P, P, P, P, C.c_uint64, C.c_uint64, C.c_double, C.c_double, C.c_double,
                               C.c_double]
         L.or_softplus_mod.restype = C.c_double
@@ -242,12 +247,35 @@ def mlp_forward(params, x):
     return y, z
 
 
-def mlp_loss_grad(params, x, target, eps=0.01):
+LOSS_REL_L2, LOSS_LOG_MSE = 0, 1
+
+
+def round_bf16(x):
+    return float(lib().or_round_bf16(float(x)))
+
+
+def round_e4m3(x):
+    return float(lib().or_round_e4m3(float(x)))
+
+
+def mlp_forward_quant(params, x, prec, with_fragile=False):
+    P = _c(params, np.float64)
+    x = _c(x, np.float64).reshape(-1, 20)
+    n = x.shape[0]
+    y, z = np.zeros(n), np.zeros(n)
+    frag = np.zeros(n, np.uint8)
+    lib().or_mlp_forward_quant(_p(P), _p(x), n, int(prec), _p(y), _p(z), _p(frag))
+    if with_fragile:
+        return y, z, frag.astype(bool)
+    return y, z
+
+
+def mlp_loss_grad(params, x, target, eps=0.01, kind=LOSS_LOG_MSE):
     P = _c(params, np.float64)
     x = _c(x, np.float64).reshape(-1, 20)
     tg = _c(target, np.float64)
     g = np.zeros(NPARAM)
-    loss = lib().or_mlp_loss_grad(_p(P), _p(x), _p(tg), x.shape[0], float(eps), _p(g))
+    loss = lib().or_mlp_loss_grad(_p(P), _p(x), _p(tg), x.shape[0], float(eps), int(kind), _p(g))
     return float(loss), g
 
 

@@ -107,7 +107,7 @@ struct or_scene {
   double* mpar;     /* nm * 7 */
   double cam[10];
   double env[3];
-  double amin[3], amax[3], extent, diag, tmin;
+  double amin[3], amax[3], extent, diag, tmin, offset;
   bnode* nodes;
   uint64_t nnodes;
   uint32_t* order;
@@ -216,7 +216,8 @@ or_scene* or_scene_create(const float* verts, uint64_t nv, const uint32_t* tris,
   sub3(s->amax, s->amin, e);
   s->extent = fmax(e[0], fmax(e[1], e[2]));
   s->diag = sqrt(dot3(e, e));
-  s->tmin = 1e-5 * s->diag;
+  s->tmin = 0.0;                   /* hits count for t > 0; child origins are offset instead */
+  s->offset = 1e-5 * s->extent;     /* origin offset along the face-forwarded normal */
   if (build_bvh) {
     s->order = (uint32_t*)malloc(sizeof(uint32_t) * nt);
     for (uint64_t i = 0; i < nt; ++i) s->order[i] = (uint32_t)i;
@@ -489,7 +490,7 @@ void or_mlp_forward(const double* params, const double* x, uint64_t n, double* y
 }
 
 double or_mlp_loss_grad(const double* params, const double* x, const double* target, uint64_t n, double eps,
-                        double* grad) {
+                        int32_t kind, double* grad) {
   memset(grad, 0, sizeof(double) * OR_NPARAM);
   double loss = 0.0;
   for (uint64_t r = 0; r < n; ++r) {
@@ -497,9 +498,20 @@ double or_mlp_loss_grad(const double* params, const double* x, const double* tar
     double a1[64], a2[64], a3[64], z;
     mlp_row(params, xr, a1, a2, a3, &z);
     double y = or_softplus_mod(z);
-    double diff = log(y + eps) - log(target[r] + eps);
-    loss += diff * diff;
-    double dz = (2.0 * diff / (y + eps)) / (double)n * or_softplus_mod_grad(z);
+    double dy;
+    if (kind == OR_LOSS_LOG_MSE) {
+      /* (ln(y + eps) - ln(L + eps))^2 */
+      double diff = log(y + eps) - log(target[r] + eps);
+      loss += diff * diff;
+      dy = 2.0 * diff / (y + eps);
+    } else {
+      /* relative L2 with the prediction held constant in the denominator (Sec. 4.2.2, Eq. 15) */
+      double den = y * y + eps;
+      double diff = y - target[r];
+      loss += diff * diff / den;
+      dy = 2.0 * diff / den;
+    }
+    double dz = dy / (double)n * or_softplus_mod_grad(z);
     double d3[64], d2[64], d1[64];
     grad[B4] += dz;
     for (int i = 0; i < 64; ++i) {
@@ -530,6 +542,152 @@ double or_mlp_loss_grad(const double* params, const double* x, const double* tar
     }
   }
   return loss / (double)n;
+}
+
+/* ---------------------------------------------- reduced-precision network evaluation */
+/* float -> bfloat16 -> float with round to nearest, ties to even (on the float's bits). */
+double or_round_bf16(double x) {
+  float f = (float)x;
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  uint32_t lower = u & 0xFFFFu, upper = u >> 16;
+  if (lower > 0x8000u || (lower == 0x8000u && (upper & 1u))) upper += 1;
+  u = upper << 16;
+  memcpy(&f, &u, 4);
+  return (double)f;
+}
+
+/* Value of the nearest OCP E4M3 number (max 448, 3 mantissa bits, subnormals 2^-9 apart)
+ * to x, ties to even, saturating at +-448. */
+double or_round_e4m3(double x) {
+  double a = fabs(x);
+  double s = x < 0 ? -1.0 : 1.0;
+  if (a >= 448.0) return s * 448.0;
+  if (a < ldexp(1.0, -6)) {  /* subnormal grid */
+    double q = a / ldexp(1.0, -9);
+    double r = nearbyint(q);  /* default rounding mode: ties to even */
+    return s * r * ldexp(1.0, -9);
+  }
+  int e;
+  frexp(a, &e);               /* a = m 2^e, m in [0.5, 1) -> a in [2^(e-1), 2^e) */
+  double ulp = ldexp(1.0, e - 1 - 3);
+  double r = nearbyint(a / ulp) * ulp;
+  if (r > 448.0) r = 448.0;
+  return s * r;
+}
+
+/* Distance of x to the nearest rounding midpoint of the bfloat16 / E4M3 grids, in units of
+ * the grid spacing at x (0 = exactly on a midpoint, 0.5 = on a grid point). */
+static double midpoint_gap_bf16(double x) {
+  double a = fabs(x);
+  if (a == 0.0) return 0.5;
+  int e;
+  frexp(a, &e);
+  double ulp = ldexp(1.0, e - 1 - 7);
+  double f = a / ulp - floor(a / ulp);
+  return fabs(f - 0.5);
+}
+static double midpoint_gap_e4m3(double x) {
+  double a = fabs(x);
+  if (a >= 448.0 || a == 0.0) return 0.5;
+  double ulp;
+  if (a < ldexp(1.0, -6)) ulp = ldexp(1.0, -9);
+  else {
+    int e;
+    frexp(a, &e);
+    ulp = ldexp(1.0, e - 1 - 3);
+  }
+  double f = a / ulp - floor(a / ulp);
+  return fabs(f - 0.5);
+}
+
+/* Power-of-two scale 2^e, e the smallest integer with 2^e >= amax / 448 (float quotient). */
+static double block_scale(double amax) {
+  float r = (float)amax / 448.0f;
+  if (!(r > 0.0f)) return 1.0;
+  int ex;
+  float m = frexpf(r, &ex);
+  int e = (m == 0.5f) ? ex - 1 : ex;
+  if (e < -120) e = -120;
+  if (e > 120) e = 120;
+  return ldexp(1.0, e);
+}
+
+void or_mlp_forward_quant(const double* params, const double* x, uint64_t n, int32_t prec, double* y, double* z,
+                          uint8_t* fragile) {
+  /* rounding decisions this close to a midpoint (in grid steps) are near-ties: a few times the
+   * float32 accumulation error relative to each grid's spacing */
+  const double gap = prec == 1 ? 2e-4 : 5e-5;
+  /* quantized weight copies */
+  static const int woff[3] = {W1, W2, W3}, wcnt[3] = {1280, 4096, 4096};
+  double* Wq = (double*)malloc(sizeof(double) * OR_NPARAM);
+  memcpy(Wq, params, sizeof(double) * OR_NPARAM);
+  double wscale[3] = {1.0, 1.0, 1.0};
+  for (int L = 0; L < 3; ++L) {
+    if (prec == 1) {
+      for (int k = 0; k < wcnt[L]; ++k) Wq[woff[L] + k] = or_round_bf16(params[woff[L] + k]);
+    } else {
+      float amax = 0.0f;
+      for (int k = 0; k < wcnt[L]; ++k) amax = fmaxf(amax, fabsf((float)params[woff[L] + k]));
+      float sc = amax > 0.0f ? amax / 448.0f : 1.0f;
+      wscale[L] = (double)sc;
+      for (int k = 0; k < wcnt[L]; ++k) Wq[woff[L] + k] = or_round_e4m3((double)((float)params[woff[L] + k] / sc));
+    }
+  }
+  for (uint64_t r = 0; r < n; ++r) {
+    double in[64], out[64];
+    int kin = 20;
+    int near = 0;
+    for (int i = 0; i < 20; ++i) in[i] = (double)(float)x[20 * r + i];
+    if (prec == 1) {
+      for (int i = 0; i < 20; ++i) in[i] = or_round_bf16(in[i]);
+    } else {
+      double amax = 0.0;
+      for (int i = 0; i < 20; ++i) amax = fmax(amax, fabs(in[i]));
+      double bs = block_scale(amax);
+      for (int i = 0; i < 20; ++i) in[i] = or_round_e4m3(in[i] / bs) * bs;
+    }
+    for (int L = 0; L < 3; ++L) {
+      const double* Wl = Wq + woff[L];
+      const double* bl = params + (L == 0 ? B1 : (L == 1 ? B2 : B3));
+      for (int o = 0; o < 64; ++o) {
+        double acc = 0.0;
+        for (int i = 0; i < kin; ++i) acc += Wl[kin * o + i] * in[i];
+        out[o] = acc * wscale[L] + bl[o];
+      }
+      for (int o = 0; o < 64; ++o) out[o] = fmax(out[o], 0.0);
+      if (L < 2) {
+        if (prec == 1) {
+          for (int o = 0; o < 64; ++o) {
+            if (out[o] > 0.0 && midpoint_gap_bf16(out[o]) < gap) near = 1;
+            in[o] = or_round_bf16(out[o]);
+          }
+        } else {
+          /* one power-of-two scale for the vertex's 64 activations */
+          double amax = 0.0;
+          for (int o = 0; o < 64; ++o) amax = fmax(amax, out[o]);
+          double bs = block_scale(amax);
+          double ratio = amax / 448.0;
+          if (ratio > 0.0) {
+            int e;
+            double m = frexp(ratio, &e);
+            if (fabs(m - 0.5) < 1e-5 || 1.0 - m < 1e-5) near = 1; /* scale choice near a power of two */
+          }
+          for (int o = 0; o < 64; ++o) {
+            if (out[o] > 0.0 && midpoint_gap_e4m3(out[o] / bs) < gap) near = 1;
+            in[o] = or_round_e4m3(out[o] / bs) * bs;
+          }
+        }
+        kin = 64;
+      }
+    }
+    double zz = params[B4];
+    for (int i = 0; i < 64; ++i) zz += params[W4 + i] * out[i];
+    if (z) z[r] = zz;
+    y[r] = or_softplus_mod(zz);
+    if (fragile) fragile[r] = (uint8_t)near;
+  }
+  free(Wq);
 }
 
 /* Adam (Kingma & Ba) with bias correction; `step` is the 1-based update count. */
@@ -794,7 +952,7 @@ static void expand_children(rctx* c, const entry* Q, const vstate* V, uint64_t n
       for (int k = 0; k < 3; ++k) wi[k] = wil[0] * tb[k] + wil[1] * bb[k] + wil[2] * v->n[k];
       normalize3(wi);
       for (int k = 0; k < 3; ++k) {
-        ch->o[k] = v->p[k];
+        ch->o[k] = v->p[k] + s->offset * v->n[k];
         ch->d[k] = wi[k];
         ch->t[k] = alive ? e->t[k] * w[k] / (double)v->q32 : 0.0;
       }

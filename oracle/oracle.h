@@ -99,9 +99,29 @@ int32_t or_enumerate(const or_scene* s, const or_cfg* cfg, double* image_expect,
 
 /* Network (Sec. 5): 20 -> 64 -> 64 -> 64 (ReLU) -> 1, modified softplus output. */
 void or_mlp_forward(const double* params, const double* x, uint64_t n, double* y, double* z);
-/* Loss mean((ln(y+eps) - ln(L+eps))^2); gradient w.r.t. all parameters. */
+/* The same network evaluated with the quantization of the matrix-core paths (test reading):
+ * prec 1: weights, inputs and hidden activations rounded to bfloat16 (ties to even);
+ * prec 2: weights as OCP E4M3 with one scale per layer (amax / 448), inputs and hidden
+ *         activations as E4M3 with one power-of-two scale per vertex and layer (the smallest
+ *         2^e >= amax / 448).  Arithmetic otherwise in double.
+ * fragile[r] (may be NULL) flags rows where a hidden activation lies within 2e-4 (BF16) or
+ * 5e-5 (E4M3) grid steps of
+ * a rounding midpoint (or the scale choice is near a power of two): a float32 evaluation may
+ * round those the other way. */
+double or_round_bf16(double x);
+double or_round_e4m3(double x);
+void or_mlp_forward_quant(const double* params, const double* x, uint64_t n, int32_t prec, double* y, double* z,
+                          uint8_t* fragile);
+
+/* Training losses of the radiance estimate y against the one-sample target L:
+ *   OR_LOSS_REL_L2:  mean((y - L)^2 / (sg(y)^2 + eps)), the relative L2 of Sec. 4.2.2 (Eq. 15)
+ *                    with the prediction held constant in the denominator (its minimiser is the
+ *                    mean of L);
+ *   OR_LOSS_LOG_MSE: mean((ln(y + eps) - ln(L + eps))^2).
+ * Returns the loss and writes the gradient w.r.t. all parameters. */
+enum { OR_LOSS_REL_L2 = 0, OR_LOSS_LOG_MSE = 1 };
 double or_mlp_loss_grad(const double* params, const double* x, const double* target, uint64_t n,
-                        double eps, double* grad);
+                        double eps, int32_t kind, double* grad);
 void or_adam(double* params, double* m, double* v, const double* grad, uint64_t np, uint64_t step,
              double lr, double b1, double b2, double eps);
 double or_softplus_mod(double z);

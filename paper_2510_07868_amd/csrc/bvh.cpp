@@ -41,7 +41,7 @@ struct Box {
 constexpr int kBins = 16;
 constexpr uint32_t kLeafMax = 8;   // encoding limit
 constexpr uint32_t kLeafTarget = 4;
-constexpr int kMaxDepth = 44;      // traversal stack is sized for this
+constexpr int kSahDepth = 32;      // beyond this depth, median splits bound the tree depth
 
 struct Builder {
   const std::vector<Box>* tb;
@@ -70,7 +70,7 @@ struct Builder {
       if (n <= kLeafMax) return a;
       return a + n / 2;  // identical centroids: split the range in two
     }
-    if (depth >= kMaxDepth - 1) {
+    if (depth >= kSahDepth) {
       // depth limit: median split along the longest axis keeps the tree shallow
       uint32_t m = a + n / 2;
       std::nth_element(order->begin() + a, order->begin() + m, order->begin() + b, [&](uint32_t x, uint32_t y) {
@@ -142,8 +142,11 @@ struct Builder {
     return r;
   }
 
+  int max_depth = 0;
+
   // Builds the subtree of [a, b) and returns its link (leaf link or node index).
   uint32_t build(uint32_t a, uint32_t b, const Box& bounds, int depth) {
+    if (depth > max_depth) max_depth = depth;
     uint32_t m = split(a, b, bounds, depth);
     if (m == a) return leaf_link(a, b - a);
     uint32_t id = (uint32_t)nodes.size();
@@ -185,6 +188,7 @@ int build_bvh(const float* verts, const uint32_t* tris, uint64_t nt, BvhOut& out
     B.nodes.insert(B.nodes.begin(), r);
   }
   out.n_nodes = B.nodes.size();
+  out.max_depth = B.max_depth + 1;
   out.nodes.resize(16 * out.n_nodes);
   for (size_t i = 0; i < B.nodes.size(); ++i) {
     const auto& n = B.nodes[i];

@@ -10,6 +10,7 @@ struct BvhOut {
   std::vector<float> nodes;      // 16 floats per node: child0 lo/hi, child1 lo/hi, links
   std::vector<uint32_t> order;   // BVH position -> original triangle index
   uint64_t n_nodes = 0;
+  int max_depth = 0;             // levels from the root to the deepest leaf
 };
 
 // Child link: bit 31 set = leaf with first = (link >> 3) & 0x0fffffff and count = (link & 7) + 1

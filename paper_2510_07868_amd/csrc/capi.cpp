@@ -39,6 +39,8 @@ struct nrrs_ctx {
   nrrs_config cfg{};
   hipStream_t stream = nullptr;
   uint64_t npx = 0, nprim = 0, cap = 0;
+  uint32_t trace_blocks = 0;  // persistent traversal grid
+  uint32_t* spill = nullptr;
   // workspace
   uint8_t* ws = nullptr;
   uint64_t ws_bytes = 0, max_tris = 0;
@@ -63,6 +65,7 @@ struct nrrs_ctx {
   Records rec{};
   float* target = nullptr;
   float *master = nullptr, *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;
+  float* infer = nullptr;  // inference weights: moving average of master (or master itself)
   uint16_t* bf16 = nullptr;
   uint8_t* fp8 = nullptr;
   float* fp8_scale = nullptr;
@@ -114,6 +117,7 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
       c->qb_pool_bytes = k.off - start;
     }
   }
+  c->spill = k.take<uint32_t>((uint64_t)extend_spill_depth() * c->trace_blocks * extend_threads_per_block());
   c->hit = k.take<float4>(C);
   c->vpos = k.take<float4>(C);
   c->vnrm = k.take<float4>(C);
@@ -144,11 +148,12 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
   c->rec.cap = (uint32_t)rc;
   c->target = k.take<float>(rc);
   c->master = k.take<float>(kNParam);
+  c->infer = k.take<float>(kNParam);
   c->adam_m = k.take<float>(kNParam);
   c->adam_v = k.take<float>(kNParam);
   c->grad = k.take<float>(kNParam);
-  c->bf16 = k.take<uint16_t>(kNParam);
-  c->fp8 = k.take<uint8_t>(kNParam);
+  c->bf16 = k.take<uint16_t>(packed_bf16_elems());
+  c->fp8 = k.take<uint8_t>(packed_fp8_bytes());
   c->fp8_scale = k.take<float>(4);
   const uint64_t gb = mlp_grad_blocks(kMaxMinibatch);
   c->grad_partial = k.take<float>(gb * kNParam);
@@ -223,12 +228,14 @@ RenderArgs base_args(nrrs_ctx* c) {
   a.f_rate = c->cfg.f_rate;
   a.budget_base = (double)c->nprim;
   a.dbg_parent = nullptr;
+  a.spill = c->spill;
+  a.trace_blocks = c->trace_blocks;
   return a;
 }
 
 NetArgs net_args(nrrs_ctx* c, int32_t precision) {
   NetArgs n{};
-  n.master = c->master;
+  n.master = c->infer;
   n.bf16 = c->bf16;
   n.fp8 = c->fp8;
   n.fp8_scale = c->fp8_scale;
@@ -268,7 +275,8 @@ int32_t nrrs_create(const nrrs_config* cfg, void* hip_stream, nrrs_ctx** out) {
       !(cfg->f_rate > 0.0) || cfg->net_max_depth < 0 || cfg->net_max_depth > kMaxRec ||
       (cfg->norm_mode != NRRS_NORM_TWO_SIDED && cfg->norm_mode != NRRS_NORM_DOWNSCALE) ||
       cfg->precision < NRRS_PREC_FP32 || cfg->precision > NRRS_PREC_FP8 || !(cfg->p_train >= 0.0) ||
-      cfg->p_train > 1.0)
+      cfg->p_train > 1.0 || (cfg->loss != NRRS_LOSS_REL_L2 && cfg->loss != NRRS_LOSS_LOG_MSE) ||
+      !(cfg->ema_decay >= 0.0) || cfg->ema_decay >= 1.0)
     return NRRS_EINVAL;
   const uint64_t npx = (uint64_t)cfg->width * cfg->height;
   const uint64_t nprim = npx * cfg->s_batch;
@@ -286,6 +294,7 @@ int32_t nrrs_create(const nrrs_config* cfg, void* hip_stream, nrrs_ctx** out) {
   c->npx = npx;
   c->nprim = nprim;
   c->cap = cap;
+  c->trace_blocks = (uint32_t)prop.multiProcessorCount * extend_blocks_per_cu();
   *out = c;
   return NRRS_OK;
 }
@@ -327,7 +336,8 @@ int32_t nrrs_bind_workspace(nrrs_ctx* c, void* device_ptr, uint64_t bytes, uint6
   std::vector<float> w;
   init_params(c->cfg.seed, w);
   HIPC(c, hipMemcpyAsync(c->master, w.data(), sizeof(float) * kNParam, hipMemcpyHostToDevice, s));
-  launch_quantize(c->master, c->bf16, c->fp8, c->fp8_scale, s);
+  HIPC(c, hipMemcpyAsync(c->infer, w.data(), sizeof(float) * kNParam, hipMemcpyHostToDevice, s));
+  launch_quantize(c->infer, c->bf16, c->fp8, c->fp8_scale, s);
   HIPC(c, hipStreamSynchronize(s));
   HIPC(c, hipGetLastError());
   c->spp_total = 0;
@@ -357,6 +367,7 @@ int32_t nrrs_upload_scene(nrrs_ctx* c, const float* verts, uint64_t nv, const ui
   BvhOut bvh;
   build_bvh(verts, tris, nt, bvh);
   if (bvh.n_nodes > c->max_tris + 2) return fail(c, NRRS_ENOMEM, "BVH larger than reserved");
+  if (bvh.max_depth > 62) return fail(c, NRRS_EINVAL, "BVH deeper than the traversal stack");
   // triangles in BVH order: (v0, original index), (e1, material), (e2, 0)
   std::vector<float> tri(12 * nt);
   float amin[3] = {INFINITY, INFINITY, INFINITY}, amax[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -400,7 +411,8 @@ int32_t nrrs_upload_scene(nrrs_ctx* c, const float* verts, uint64_t nv, const ui
   d.amin_z = amin[2];
   const double ex = amax[0] - amin[0], ey = amax[1] - amin[1], ez = amax[2] - amin[2];
   d.extent = (float)std::fmax(ex, std::fmax(ey, ez));
-  d.tmin = (float)(1e-5 * std::sqrt(ex * ex + ey * ey + ez * ez));
+  d.tmin = 0.0f;                                  // hits count for t > 0 ...
+  d.offset = (float)(1e-5 * d.extent);             // ... because child origins leave the surface
   d.env_r = env[0];
   d.env_g = env[1];
   d.env_b = env[2];
@@ -597,11 +609,14 @@ int32_t nrrs_set_params(nrrs_ctx* c, const float* master, const float* adam_m, c
   if (!c) return NRRS_EINVAL;
   if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
   HIPC(c, hipStreamSynchronize(c->stream));
-  if (master) HIPC(c, hipMemcpy(c->master, master, sizeof(float) * kNParam, hipMemcpyHostToDevice));
+  if (master) {
+    HIPC(c, hipMemcpy(c->master, master, sizeof(float) * kNParam, hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->infer, master, sizeof(float) * kNParam, hipMemcpyHostToDevice));
+  }
   if (adam_m) HIPC(c, hipMemcpy(c->adam_m, adam_m, sizeof(float) * kNParam, hipMemcpyHostToDevice));
   if (adam_v) HIPC(c, hipMemcpy(c->adam_v, adam_v, sizeof(float) * kNParam, hipMemcpyHostToDevice));
   if (step) c->adam_step = *step;
-  launch_quantize(c->master, c->bf16, c->fp8, c->fp8_scale, c->stream);
+  launch_quantize(c->infer, c->bf16, c->fp8, c->fp8_scale, c->stream);
   HIPC(c, hipGetLastError());
   return NRRS_OK;
 }
@@ -644,12 +659,13 @@ int32_t nrrs_train_step(nrrs_ctx* c, uint32_t n_records, uint32_t minibatch, flo
   for (uint32_t b = 0; b < batches; ++b) {
     uint32_t nb = 0;
     launch_mlp_grad(c->rec.feat + 20ull * b * minibatch, c->target + (uint64_t)b * minibatch, nullptr, minibatch,
-                    c->master, c->grad_partial, c->loss_partial, &nb, s);
+                    c->master, c->cfg.loss, c->grad_partial, c->loss_partial, &nb, s);
     launch_grad_reduce(c->grad_partial, nb, c->grad, c->loss_partial, c->loss_accum, minibatch, s);
     c->adam_step += 1;
     launch_adam(c->master, c->adam_m, c->adam_v, c->grad, c->adam_step, lr, s);
+    launch_ema(c->infer, c->master, (float)c->cfg.ema_decay, s);
   }
-  launch_quantize(c->master, c->bf16, c->fp8, c->fp8_scale, s);
+  launch_quantize(c->infer, c->bf16, c->fp8, c->fp8_scale, s);
   HIPC(c, hipGetLastError());
   if (loss_or_null) {
     HIPC(c, hipStreamSynchronize(s));
@@ -735,11 +751,25 @@ int32_t nrrs_debug_load_records(nrrs_ctx* c, const float* features, const float*
   return NRRS_OK;
 }
 
+int32_t nrrs_debug_read_queue(nrrs_ctx* c, int32_t which, uint32_t n, float* orig, float* dir, float* thr,
+                              float* hit) {
+  if (!c || (which != 0 && which != 1)) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (n > c->cap) return fail(c, NRRS_EINVAL, "n exceeds the queue capacity");
+  if (n == 0) return NRRS_OK;
+  const Queue& q = which == 0 ? c->qa : c->qb;
+  HIPC(c, hipStreamSynchronize(c->stream));
+  if (orig) HIPC(c, hipMemcpy(orig, q.orig, sizeof(float4) * n, hipMemcpyDeviceToHost));
+  if (dir) HIPC(c, hipMemcpy(dir, q.dir, sizeof(float4) * n, hipMemcpyDeviceToHost));
+  if (thr) HIPC(c, hipMemcpy(thr, q.thr, sizeof(float4) * n, hipMemcpyDeviceToHost));
+  if (hit) HIPC(c, hipMemcpy(hit, c->hit, sizeof(float4) * n, hipMemcpyDeviceToHost));
+  return NRRS_OK;
+}
+
 int32_t nrrs_debug_trace(nrrs_ctx* c, const float* rays, const uint32_t* exclude, uint32_t n, uint32_t* prim,
                          float* t, float* b1, float* b2) {
   if (!c || (n && (!rays || !prim || !t || !b1 || !b2))) return NRRS_EINVAL;
   if (!c->scene) return fail(c, NRRS_ESTATE, "upload a scene first");
-  if ((uint64_t)n * 48 > c->qb_pool_bytes) return fail(c, NRRS_ENOMEM, "too many rays for the scratch space");
   if (n == 0) return NRRS_OK;
   std::vector<float> o(4ull * n), d(4ull * n);
   for (uint32_t i = 0; i < n; ++i) {
@@ -757,14 +787,24 @@ int32_t nrrs_debug_trace(nrrs_ctx* c, const float* rays, const uint32_t* exclude
   }
   hipStream_t s = c->stream;
   HIPC(c, hipStreamSynchronize(s));
-  float4* po = (float4*)c->qb_pool;
-  float4* pd = po + n;
-  float4* ph = pd + n;
-  HIPC(c, hipMemcpy(po, o.data(), sizeof(float4) * n, hipMemcpyHostToDevice));
-  HIPC(c, hipMemcpy(pd, d.data(), sizeof(float4) * n, hipMemcpyHostToDevice));
-  launch_trace_rays(c->sc, po, pd, ph, n, s);
+  if (n > c->cap) return fail(c, NRRS_ENOMEM, "more rays than the queue capacity");
+  // the rays go through the render's own traversal kernel as queue entries of depth 1
+  std::vector<float> th(4ull * n, 1.0f);
+  for (uint32_t i = 0; i < n; ++i) th[4ull * i + 3] = 0.0f;  // flags = 0
+  HIPC(c, hipMemcpy(c->qa.orig, o.data(), sizeof(float4) * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(c->qa.dir, d.data(), sizeof(float4) * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(c->qa.thr, th.data(), sizeof(float4) * n, hipMemcpyHostToDevice));
+  DepthCtl ctl;
+  std::memset(&ctl, 0, sizeof(ctl));
+  ctl.n = n;
+  HIPC(c, hipMemcpy(c->ctl + 1, &ctl, sizeof(ctl), hipMemcpyHostToDevice));
+  RenderArgs a = base_args(c);
+  a.depth = 1;
+  a.max_depth = 2;
+  launch_extend(a, s);
   HIPC(c, hipStreamSynchronize(s));
   HIPC(c, hipGetLastError());
+  float4* ph = c->hit;
   std::vector<float> h(4ull * n);
   HIPC(c, hipMemcpy(h.data(), ph, sizeof(float4) * n, hipMemcpyDeviceToHost));
   for (uint32_t i = 0; i < n; ++i) {
@@ -828,7 +868,7 @@ int32_t nrrs_debug_mlp_grad(nrrs_ctx* c, const float* x, const float* target, ui
   HIPC(c, hipMemcpy(pt, target, sizeof(float) * n, hipMemcpyHostToDevice));
   launch_zero_u32((uint32_t*)c->loss_accum, 1, s);
   uint32_t nb = 0;
-  launch_mlp_grad(px, pt, nullptr, n, c->master, c->grad_partial, c->loss_partial, &nb, s);
+  launch_mlp_grad(px, pt, nullptr, n, c->master, c->cfg.loss, c->grad_partial, c->loss_partial, &nb, s);
   launch_grad_reduce(c->grad_partial, nb, c->grad, c->loss_partial, c->loss_accum, n, s);
   HIPC(c, hipStreamSynchronize(s));
   HIPC(c, hipGetLastError());

@@ -129,7 +129,7 @@ struct DevScene {
   const float4* node;   // 4 float4 per BVH2 node (two child boxes + child links)
   const float4* mat;    // 2 float4 per material: (rho rgb, ggx alpha), (Le rgb, type)
   uint32_t nt, nn, nm;
-  float amin_x, amin_y, amin_z, extent, tmin;
+  float amin_x, amin_y, amin_z, extent, tmin, offset;
   float env_r, env_g, env_b;
   float eye_x, eye_y, eye_z, fwd_x, fwd_y, fwd_z, rx, ry, rz, ux, uy, uz;  // R, U pre-scaled
 };
@@ -161,6 +161,25 @@ struct DepthCtl {
   uint32_t retries;    // alpha reductions applied
   double sumq;         // FP64 sum of the raw factors
   double F;            // normalization factor finally used
+  uint32_t work;       // next queue entry to hand to a traversal lane (persistent extend)
+  uint32_t pad;
 };
+
+// ---------------------------------------------------------------------------------------
+// Wave64 helpers.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// One atomic per wave: lanes with `pred` receive consecutive slots from *counter.
+__device__ __forceinline__ uint32_t wave_alloc(uint32_t* counter, bool pred) {
+  const uint64_t m = __ballot(pred);
+  if (m == 0) return 0;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0;
+  if ((int)__lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+  base = __shfl(base, leader);
+  return base + lanes_below(m);
+}
 
 }  // namespace nrrs

@@ -34,6 +34,8 @@ struct RenderArgs {
   double f_rate;
   double budget_base;   // N_px of Eq. (10): primary paths of the pass
   uint32_t* dbg_parent; // when set, the expansion also writes each child's parent index
+  uint32_t* spill;      // traversal stack spill area [spill depth][trace_blocks * threads]
+  uint32_t trace_blocks;
 };
 
 void launch_camera(const RenderArgs& a, hipStream_t s);
@@ -52,28 +54,39 @@ void launch_accumulate_stats(const DepthCtl* ctl, uint32_t max_depth, unsigned l
                              unsigned long long* s_sum, unsigned long long* r_sum, double* sumq_last,
                              double* f_last, hipStream_t s);
 
+uint32_t extend_blocks_per_cu();
+uint32_t extend_threads_per_block();
+uint32_t extend_spill_depth();
+
 // Debug / test launchers.
-void launch_trace_rays(const DevScene& sc, const float4* orig, const float4* dir, float4* hit, uint32_t n,
-                       hipStream_t s);
 void launch_philox(const uint4* ctr, uint2 key, uint4* out, uint32_t n, hipStream_t s);
 
 // Network (mlp.hip).
 struct NetArgs {
-  const float* master;       // FP32 parameters
-  const uint16_t* bf16;      // BF16 copy (RNE), same layout
-  const uint8_t* fp8;        // FP8 E4M3 copy, same layout
-  const float* fp8_scale;    // per-layer dequantization scales [4]
+  const float* master;       // FP32 inference parameters
+  const uint16_t* bf16;      // BF16 weights (RNE) packed in matrix-core operand order
+  const uint8_t* fp8;        // FP8 E4M3 weights packed in matrix-core operand order
+  const float* fp8_scale;    // per-layer FP8 weight scales [3]
   int32_t precision;
 };
 void launch_rrsnet(const RenderArgs& a, const NetArgs& n, hipStream_t s);
 void launch_mlp_forward_rows(const float* x, uint32_t n, const NetArgs& net, float* y, float* z, hipStream_t s);
 void launch_mlp_grad(const float* x, const float* target, const uint32_t* index, uint32_t n, const float* master,
-                     float* grad_partial, float* loss_partial, uint32_t* nblocks_out, hipStream_t s);
+                     int32_t loss_kind, float* grad_partial, float* loss_partial, uint32_t* nblocks_out,
+                     hipStream_t s);
 void launch_grad_reduce(const float* grad_partial, uint32_t nblocks, float* grad, const float* loss_partial,
                         float* loss_accum, uint32_t n_rows_total, hipStream_t s);
 void launch_adam(float* master, float* m, float* v, const float* grad, uint64_t step, float lr, hipStream_t s);
+// infer = decay * infer + (1 - decay) * master (decay 0: copy)
+void launch_ema(float* infer, const float* master, float decay, hipStream_t s);
 void launch_quantize(const float* master, uint16_t* bf16, uint8_t* fp8, float* fp8_scale, hipStream_t s);
 void launch_record_targets(const Records& r, float* target, uint32_t n, hipStream_t s);
+// Matrix-core inference (mlp_mfma.hip): precision 1 = BF16, 2 = FP8-E4M3.
+uint32_t packed_bf16_elems();
+uint32_t packed_fp8_bytes();
+void launch_pack_weights(const float* master, uint16_t* bf16, uint8_t* fp8, float* fp8_scale, hipStream_t s);
+void launch_rrsnet_mfma(const RenderArgs& a, const NetArgs& n, hipStream_t s);
+void launch_rows_mfma(const float* x, uint32_t n, const NetArgs& net, float* y, float* z, hipStream_t s);
 uint32_t mlp_grad_blocks(uint32_t n);
 
 }  // namespace nrrs

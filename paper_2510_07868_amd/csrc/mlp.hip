@@ -98,8 +98,8 @@ __global__ __launch_bounds__(kNetThreads) void k_forward_rows_f32(const float* x
 // the block's partial weight gradients summed over its rows (fixed order, deterministic).
 __global__ __launch_bounds__(kGradThreads) void k_mlp_grad(const float* x, const float* target,
                                                           const uint32_t* index, uint32_t n, uint32_t n_total,
-                                                          const float* master, float* grad_partial,
-                                                          float* loss_partial) {
+                                                          const float* master, int32_t loss_kind,
+                                                          float* grad_partial, float* loss_partial) {
   extern __shared__ float lds[];
   float* W = lds;                              // kNParam
   float* X = W + kNParam + 3;                  // [64][20]
@@ -152,9 +152,19 @@ __global__ __launch_bounds__(kGradThreads) void k_mlp_grad(const float* x, const
       for (int i = 0; i < 64; ++i) z = fmaf(W[kW4 + i], fmaxf(A3[r * 64 + i], 0.0f), z);
       const float y = softplus_mod(z);
       const uint32_t src = index ? index[row0 + r] : row0 + r;
-      const float diff = logf(y + 0.01f) - logf(target[src] + 0.01f);
-      ls = diff * diff;
-      dz = (2.0f * diff / (y + 0.01f)) / (float)n_total * softplus_mod_grad(z);
+      const float L = target[src];
+      float dy;
+      if (loss_kind == 1) {  // squared error of log radiance
+        const float diff = logf(y + 0.01f) - logf(L + 0.01f);
+        ls = diff * diff;
+        dy = 2.0f * diff / (y + 0.01f);
+      } else {               // relative L2 with the prediction held constant in the denominator
+        const float den = y * y + 0.01f;
+        const float diff = y - L;
+        ls = diff * diff / den;
+        dy = 2.0f * diff / den;
+      }
+      dz = dy / (float)n_total * softplus_mod_grad(z);
     }
     DZ[r] = dz;
     LS[r] = ls;
@@ -244,24 +254,16 @@ __global__ void k_adam(float* w, float* m, float* v, const float* g, uint64_t st
   w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + 1e-8f);
 }
 
+__global__ void k_ema(float* infer, const float* master, float decay) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < (uint32_t)kNParam) infer[k] = decay > 0.0f ? fmaf(decay, infer[k] - master[k], master[k]) : master[k];
+}
+
 __global__ void k_record_targets(Records r, float* target, uint32_t n) {
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const float lt = r.lum_t[k];
   target[k] = lt > 0.0f ? fmaxf(r.acc[k], 0.0f) / lt : 0.0f;
-}
-
-// Round-to-nearest-even float -> bfloat16 bits.
-__device__ __forceinline__ uint16_t to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
-__global__ void k_quantize_bf16(const float* w, uint16_t* out) {
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < (uint32_t)kNParam) out[k] = to_bf16(w[k]);
 }
 
 }  // namespace
@@ -273,18 +275,27 @@ static size_t grad_lds_bytes() {
 }
 
 void launch_rrsnet(const RenderArgs& a, const NetArgs& n, hipStream_t s) {
+  if (n.precision != 0) {
+    launch_rrsnet_mfma(a, n, s);
+    return;
+  }
   const uint32_t blocks = (a.cap + kNetThreads - 1) / kNetThreads;
   hipLaunchKernelGGL(k_rrsnet_f32, dim3(blocks), dim3(kNetThreads), 0, s, a, n.master);
 }
 
 void launch_mlp_forward_rows(const float* x, uint32_t n, const NetArgs& net, float* y, float* z, hipStream_t s) {
   if (!n) return;
+  if (net.precision != 0) {
+    launch_rows_mfma(x, n, net, y, z, s);
+    return;
+  }
   hipLaunchKernelGGL(k_forward_rows_f32, dim3((n + kNetThreads - 1) / kNetThreads), dim3(kNetThreads), 0, s, x, n,
                      net.master, y, z);
 }
 
 void launch_mlp_grad(const float* x, const float* target, const uint32_t* index, uint32_t n, const float* master,
-                     float* grad_partial, float* loss_partial, uint32_t* nblocks_out, hipStream_t s) {
+                     int32_t loss_kind, float* grad_partial, float* loss_partial, uint32_t* nblocks_out,
+                     hipStream_t s) {
   const uint32_t nb = mlp_grad_blocks(n);
   *nblocks_out = nb;
   static bool attr = false;
@@ -293,7 +304,7 @@ void launch_mlp_grad(const float* x, const float* target, const uint32_t* index,
     attr = true;
   }
   hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(kGradThreads), grad_lds_bytes(), s, x, target, index, n, n, master,
-                     grad_partial, loss_partial);
+                     loss_kind, grad_partial, loss_partial);
 }
 
 void launch_grad_reduce(const float* grad_partial, uint32_t nblocks, float* grad, const float* loss_partial,
@@ -306,10 +317,12 @@ void launch_adam(float* master, float* m, float* v, const float* grad, uint64_t 
   hipLaunchKernelGGL(k_adam, dim3((kNParam + 255) / 256), dim3(256), 0, s, master, m, v, grad, step, lr);
 }
 
+void launch_ema(float* infer, const float* master, float decay, hipStream_t s) {
+  hipLaunchKernelGGL(k_ema, dim3((kNParam + 255) / 256), dim3(256), 0, s, infer, master, decay);
+}
+
 void launch_quantize(const float* master, uint16_t* bf16, uint8_t* fp8, float* fp8_scale, hipStream_t s) {
-  (void)fp8;
-  (void)fp8_scale;
-  hipLaunchKernelGGL(k_quantize_bf16, dim3((kNParam + 255) / 256), dim3(256), 0, s, master, bf16);
+  launch_pack_weights(master, bf16, fp8, fp8_scale, s);
 }
 
 void launch_record_targets(const Records& r, float* target, uint32_t n, hipStream_t s) {

@@ -18,7 +18,9 @@ namespace {
 
 constexpr int kEntryThreads = 256;
 constexpr int kTraceThreads = 128;
-constexpr int kStackDepth = 48;  // the builder caps the BVH depth at 44
+constexpr int kLdsStack = 16;     // stack entries per lane kept in LDS
+constexpr int kStackMax = 64;     // total stack entries per lane (the builder keeps the BVH shallower)
+constexpr int kRefillLanes = 16;  // a wave fetches new rays once this many lanes are idle
 constexpr uint32_t kLeafBit = 0x80000000u;
 
 __device__ __forceinline__ uint32_t bits(float f) { return __float_as_uint(f); }
@@ -30,6 +32,7 @@ __global__ __launch_bounds__(kEntryThreads) void k_camera(RenderArgs a) {
     a.ctl[1].n = a.nprim;
     a.ctl[a.max_depth].S = 0;
   }
+  if (k <= a.max_depth) a.ctl[k].work = 0;
   if (k >= a.nprim) return;
   const uint32_t npx = a.width * a.height;
   const uint32_t pix = k % npx;
@@ -105,81 +108,111 @@ __device__ __forceinline__ void test_leaf(const DevScene& sc, uint32_t link, V3 
   }
 }
 
-// Stack-based BVH2 traversal, near child first; the per-thread stack lives in LDS laid out
-// [depth][thread] so that a wave's pushes and pops hit distinct banks.
-__device__ __forceinline__ HitState traverse(const DevScene& sc, V3 o, V3 d, uint32_t excl,
-                                             uint32_t (*stack)[kTraceThreads], uint32_t& nodes, uint32_t& tris) {
+// Persistent BVH2 traversal.  Each lane holds one ray and advances it one node per loop
+// iteration (near child first); when a quarter of a wave's lanes are idle the wave takes a
+// new batch of queue entries from a per-depth counter with one atomic, so long rays do
+// not hold a whole wave idle.  The traversal stack keeps its top kLdsStack entries in LDS
+// ([depth][lane] layout: no bank conflicts) and deeper entries in a global spill area.
+__global__ __launch_bounds__(kTraceThreads) void k_extend(RenderArgs a) {
+  __shared__ uint32_t stack[kLdsStack][kTraceThreads];
+  __shared__ unsigned long long cnt[3];  // rays traced, nodes visited, triangles tested
   const int tid = threadIdx.x;
-  const V3 dd = v3(fabsf(d.x) > 1e-20f ? d.x : copysignf(1e-20f, d.x),
-                   fabsf(d.y) > 1e-20f ? d.y : copysignf(1e-20f, d.y),
-                   fabsf(d.z) > 1e-20f ? d.z : copysignf(1e-20f, d.z));
-  const V3 inv = v3(1.0f / dd.x, 1.0f / dd.y, 1.0f / dd.z);
-  const V3 oi = v3(-o.x * inv.x, -o.y * inv.y, -o.z * inv.z);
-  HitState h;
-  h.t = __builtin_inff();
-  h.b1 = h.b2 = 0.0f;
-  h.prim = kMiss;
-  h.orig = kMiss;
+  if (tid < 3) cnt[tid] = 0;
+  __syncthreads();
+  const DevScene& sc = a.sc;
+  const uint32_t n = a.ctl[a.depth].n;
+  uint32_t* work = &a.ctl[a.depth].work;
+  const uint32_t gthreads = gridDim.x * kTraceThreads;
+  uint32_t* spill = a.spill + blockIdx.x * kTraceThreads + tid;  // entry k at spill[k * gthreads]
+  bool active = false, exhausted = false;
+  uint32_t ray = 0, excl = 0, ni = 0;
   int sp = 0;
-  uint32_t ni = 0;
+  V3 o = v3(0, 0, 0), d = o, inv = o, oi = o;
+  HitState h;
+  uint32_t c_rays = 0, c_nodes = 0, c_tris = 0;
   for (;;) {
-    ++nodes;
+    if (!exhausted) {
+      const uint64_t idle = __ballot(!active);
+      if (idle != 0 && (__popcll(idle) >= kRefillLanes || idle == __ballot(true))) {
+        const int leader = __ffsll((unsigned long long)idle) - 1;
+        uint32_t base = 0;
+        if ((int)__lane_id() == leader) base = atomicAdd(work, (uint32_t)__popcll(idle));
+        base = __shfl(base, leader);
+        if ((uint64_t)base + __popcll(idle) >= n) exhausted = true;
+        if (!active) {
+          const uint32_t my = base + lanes_below(idle);
+          if (my < n) {
+            const float4 th = a.qin.thr[my];
+            if (bits(th.w) & kFlagDead) {
+              a.hit[my] = make_float4(__builtin_inff(), 0.0f, 0.0f, __uint_as_float(kMiss));
+            } else {
+              const float4 og = a.qin.orig[my], dr = a.qin.dir[my];
+              o = xyz(og);
+              d = xyz(dr);
+              excl = bits(og.w);
+              const V3 dd = v3(fabsf(d.x) > 1e-20f ? d.x : copysignf(1e-20f, d.x),
+                               fabsf(d.y) > 1e-20f ? d.y : copysignf(1e-20f, d.y),
+                               fabsf(d.z) > 1e-20f ? d.z : copysignf(1e-20f, d.z));
+              inv = v3(1.0f / dd.x, 1.0f / dd.y, 1.0f / dd.z);
+              oi = v3(-o.x * inv.x, -o.y * inv.y, -o.z * inv.z);
+              h.t = __builtin_inff();
+              h.b1 = h.b2 = 0.0f;
+              h.prim = kMiss;
+              h.orig = kMiss;
+              ni = 0;
+              sp = 0;
+              ray = my;
+              active = true;
+              ++c_rays;
+            }
+          }
+        }
+      }
+    }
+    if (__ballot(active) == 0) {
+      if (exhausted) break;
+      continue;
+    }
+    if (!active) continue;
+    // one node: test both child boxes, intersect leaf children, descend or pop
+    ++c_nodes;
     const float4 n0 = sc.node[4 * ni], n1 = sc.node[4 * ni + 1], n2 = sc.node[4 * ni + 2], n3 = sc.node[4 * ni + 3];
     float tn0, tn1;
     bool h0 = slab(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, inv, oi, h.t, tn0);
     bool h1 = slab(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, inv, oi, h.t, tn1);
     const uint32_t l0 = bits(n3.x), l1 = bits(n3.y);
     if (h0 && (l0 & kLeafBit)) {
-      test_leaf(sc, l0, o, d, excl, h, tris);
+      test_leaf(sc, l0, o, d, excl, h, c_tris);
       h0 = false;
     }
     if (h1 && (l1 & kLeafBit)) {
-      test_leaf(sc, l1, o, d, excl, h, tris);
+      test_leaf(sc, l1, o, d, excl, h, c_tris);
       h1 = false;
     }
     if (h0 && h1) {
       const bool first0 = tn0 <= tn1;
-      if (sp < kStackDepth) stack[sp++][tid] = first0 ? l1 : l0;
+      const uint32_t far = first0 ? l1 : l0;
+      if (sp < kLdsStack) stack[sp][tid] = far;
+      else if (sp < kStackMax) spill[(uint64_t)(sp - kLdsStack) * gthreads] = far;
+      sp = min(sp + 1, kStackMax);
       ni = first0 ? l0 : l1;
     } else if (h0) {
       ni = l0;
     } else if (h1) {
       ni = l1;
+    } else if (sp > 0) {
+      --sp;
+      ni = sp < kLdsStack ? stack[sp][tid] : spill[(uint64_t)(sp - kLdsStack) * gthreads];
     } else {
-      if (sp == 0) break;
-      ni = stack[--sp][tid];
+      a.hit[ray] = make_float4(h.t, h.b1, h.b2, __uint_as_float(h.prim));
+      active = false;
     }
   }
-  return h;
-}
-
-__global__ __launch_bounds__(kTraceThreads) void k_extend(RenderArgs a) {
-  __shared__ uint32_t stack[kStackDepth][kTraceThreads];
-  __shared__ uint32_t cnt[3];  // rays traced, nodes visited, triangles tested
-  if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
+  atomicAdd(&cnt[0], (unsigned long long)c_rays);
+  atomicAdd(&cnt[1], (unsigned long long)c_nodes);
+  atomicAdd(&cnt[2], (unsigned long long)c_tris);
   __syncthreads();
-  const uint32_t n = a.ctl[a.depth].n;
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    const float4 th = a.qin.thr[i];
-    if (__float_as_uint(th.w) & kFlagDead) {
-      a.hit[i] = make_float4(__builtin_inff(), 0.0f, 0.0f, __uint_as_float(kMiss));
-    } else {
-      const float4 og = a.qin.orig[i], dr = a.qin.dir[i];
-      uint32_t nodes = 0, tris = 0;
-      const HitState h = traverse(a.sc, xyz(og), xyz(dr), bits(og.w), stack, nodes, tris);
-      a.hit[i] = make_float4(h.t, h.b1, h.b2, __uint_as_float(h.prim));
-      atomicAdd(&cnt[0], 1u);
-      atomicAdd(&cnt[1], nodes);
-      atomicAdd(&cnt[2], tris);
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0 && cnt[0]) {
-    atomicAdd(a.rays, (unsigned long long)cnt[0]);
-    atomicAdd(a.rays + 1, (unsigned long long)cnt[1]);
-    atomicAdd(a.rays + 2, (unsigned long long)cnt[2]);
-  }
+  if (tid < 3 && cnt[tid]) atomicAdd(a.rays + tid, cnt[tid]);
 }
 
 // ------------------------------------------------------------------------------- shade
@@ -205,13 +238,17 @@ __global__ __launch_bounds__(kEntryThreads) void k_shade(RenderArgs a) {
   const float4 th = a.qin.thr[i];
   const uint32_t flags = bits(th.w);
   float q = 0.0f;
+  bool want_rec = false;
+  V3 t = xyz(th), p = v3(0, 0, 0), nrm = p, wo = p;
+  float4 m0 = make_float4(0, 0, 0, 0);
+  uint32_t type = 0, pix = 0;
+  int4 rec = make_int4(-1, -1, -1, -1);
   if (!(flags & kFlagDead)) {
-    const V3 t = xyz(th);
     const float4 dr = a.qin.dir[i];
-    const uint32_t pix = bits(dr.w);
+    pix = bits(dr.w);
     const float4 hh = a.hit[i];
     const uint32_t prim = bits(hh.w);
-    int4 rec = a.records_on ? a.qin.rec[i] : make_int4(-1, -1, -1, -1);
+    if (a.records_on) rec = a.qin.rec[i];
     if (prim == kMiss) {
       emit(a, pix, t, v3(a.sc.env_r, a.sc.env_g, a.sc.env_b), rec);
     } else {
@@ -219,41 +256,44 @@ __global__ __launch_bounds__(kEntryThreads) void k_shade(RenderArgs a) {
       const V3 e1 = xyz(a1), e2 = xyz(a2);
       const uint32_t mid = bits(a1.w);
       const V3 ng = normalized(cross(e1, e2));
-      const V3 p = xyz(a0) + hh.y * e1 + hh.z * e2;
-      const V3 wo = v3(-dr.x, -dr.y, -dr.z);
+      p = xyz(a0) + hh.y * e1 + hh.z * e2;
+      wo = v3(-dr.x, -dr.y, -dr.z);
       const bool front = dot(ng, wo) > 0.0f;
-      const V3 nrm = front ? ng : v3(-ng.x, -ng.y, -ng.z);
-      const float4 m0 = a.sc.mat[2 * mid], m1 = a.sc.mat[2 * mid + 1];
-      const uint32_t type = bits(m1.w);
+      nrm = front ? ng : v3(-ng.x, -ng.y, -ng.z);
+      m0 = a.sc.mat[2 * mid];
+      const float4 m1 = a.sc.mat[2 * mid + 1];
+      type = bits(m1.w);
       if (front && (m1.x != 0.0f || m1.y != 0.0f || m1.z != 0.0f)) emit(a, pix, t, xyz(m1), rec);
       if (a.depth < a.max_depth && type != 2u) {
         q = a.mode == 0u ? 1.0f : lum(mul(t, xyz(m0)));
-        if (a.records_on && (flags & kFlagTrain) && a.depth <= a.net_max_depth && a.depth <= (uint32_t)kMaxRec) {
-          const uint32_t slot = atomicAdd(a.rec.count, 1u);
-          if (slot < a.rec.cap) {
-            float f[20];
-            vertex_features(a.sc, p, nrm, wo, t, m0, type, a.depth, a.max_depth, f);
-            float* dst = a.rec.feat + 20ull * slot;
-#pragma unroll
-            for (int k = 0; k < 20; ++k) dst[k] = f[k];
-            a.rec.lum_t[slot] = lum(t);
-            a.rec.acc[slot] = 0.0f;
-            a.rec.depth[slot] = a.depth;
-            a.rec.pix[slot] = pix;
-            a.rec.lineage[slot] = a.qin.id[i];
-            if (a.depth == 1) rec.x = (int)slot;
-            else if (a.depth == 2) rec.y = (int)slot;
-            else if (a.depth == 3) rec.z = (int)slot;
-            else rec.w = (int)slot;
-            a.qin.rec[i] = rec;
-          }
-        }
+        want_rec = a.records_on && (flags & kFlagTrain) && a.depth <= a.net_max_depth && a.depth <= (uint32_t)kMaxRec;
       }
       a.vpos[i] = pack(p, prim);
       a.vnrm[i] = pack(nrm, mid);
     }
   }
   a.q[i] = q;
+  // training record: one counter atomic per wave (converged code)
+  if (a.records_on) {
+    const uint32_t slot = wave_alloc(a.rec.count, want_rec);
+    if (want_rec && slot < a.rec.cap) {
+      float f[20];
+      vertex_features(a.sc, p, nrm, wo, t, m0, type, a.depth, a.max_depth, f);
+      float* dst = a.rec.feat + 20ull * slot;
+#pragma unroll
+      for (int k = 0; k < 20; ++k) dst[k] = f[k];
+      a.rec.lum_t[slot] = lum(t);
+      a.rec.acc[slot] = 0.0f;
+      a.rec.depth[slot] = a.depth;
+      a.rec.pix[slot] = pix;
+      a.rec.lineage[slot] = a.qin.id[i];
+      if (a.depth == 1) rec.x = (int)slot;
+      else if (a.depth == 2) rec.y = (int)slot;
+      else if (a.depth == 3) rec.z = (int)slot;
+      else rec.w = (int)slot;
+      a.qin.rec[i] = rec;
+    }
+  }
 }
 
 // -------------------------------------------------------------------- FP64 sum of q
@@ -535,7 +575,9 @@ __global__ __launch_bounds__(kEntryThreads) void k_expand(RenderArgs a) {
   const float inv_q = 1.0f / qn;
   const V3 tc = alive ? v3(th.x * w.x * inv_q, th.y * w.y * inv_q, th.z * w.z * inv_q) : v3(0.0f, 0.0f, 0.0f);
   const uint32_t flags = (bits(th.w) & kFlagTrain) | (alive ? 0u : kFlagDead);
-  a.qout.orig[s] = make_float4(vp.x, vp.y, vp.z, vp.w);
+  // the child leaves the surface from a point offset along the face-forwarded normal
+  const float eps = a.sc.offset;
+  a.qout.orig[s] = make_float4(fmaf(eps, nrm.x, vp.x), fmaf(eps, nrm.y, vp.y), fmaf(eps, nrm.z, vp.z), vp.w);
   a.qout.dir[s] = pack(wi, bits(dr.w));
   a.qout.thr[s] = pack(tc, flags);
   a.qout.id[s] = make_uint2(r.z, r.w);
@@ -578,17 +620,6 @@ __global__ void k_accumulate_stats(const DepthCtl* ctl, uint32_t D, unsigned lon
   }
 }
 
-__global__ __launch_bounds__(kTraceThreads) void k_trace_rays(DevScene sc, const float4* orig, const float4* dir,
-                                                             float4* hit, uint32_t n) {
-  __shared__ uint32_t stack[kStackDepth][kTraceThreads];
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float4 og = orig[i], dr = dir[i];
-  uint32_t nodes = 0, tris = 0;
-  const HitState h = traverse(sc, xyz(og), xyz(dr), bits(og.w), stack, nodes, tris);
-  hit[i] = make_float4(h.t, h.b1, h.b2, __uint_as_float(h.prim));
-}
-
 __global__ void k_philox(const uint4* ctr, uint2 key, uint4* out, uint32_t n) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = philox(ctr[i], key);
@@ -602,8 +633,15 @@ void launch_camera(const RenderArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_camera, dim3(blocks_for(a.nprim, kEntryThreads)), dim3(kEntryThreads), 0, s, a);
 }
 void launch_extend(const RenderArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_extend, dim3(blocks_for(a.cap, kTraceThreads)), dim3(kTraceThreads), 0, s, a);
+  hipLaunchKernelGGL(k_extend, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
 }
+uint32_t extend_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend, kTraceThreads, 0) != hipSuccess || nb < 1) nb = 1;
+  return (uint32_t)nb;
+}
+uint32_t extend_threads_per_block() { return kTraceThreads; }
+uint32_t extend_spill_depth() { return kStackMax - kLdsStack; }
 void launch_shade(const RenderArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_shade, dim3(blocks_for(a.cap, kEntryThreads)), dim3(kEntryThreads), 0, s, a);
 }
@@ -645,10 +683,6 @@ void launch_accumulate_stats(const DepthCtl* ctl, uint32_t max_depth, unsigned l
                              double* f_last, hipStream_t s) {
   hipLaunchKernelGGL(k_accumulate_stats, dim3(1), dim3(64), 0, s, ctl, max_depth, n_sum, s_sum, r_sum, sumq_last,
                      f_last);
-}
-void launch_trace_rays(const DevScene& sc, const float4* orig, const float4* dir, float4* hit, uint32_t n,
-                       hipStream_t s) {
-  if (n) hipLaunchKernelGGL(k_trace_rays, dim3(blocks_for(n, kTraceThreads)), dim3(kTraceThreads), 0, s, sc, orig, dir, hit, n);
 }
 void launch_philox(const uint4* ctr, uint2 key, uint4* out, uint32_t n, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_philox, dim3(blocks_for(n, 256)), dim3(256), 0, s, ctr, key, out, n);

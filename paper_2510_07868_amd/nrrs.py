@@ -19,6 +19,7 @@ MAX_DEPTH = 64
 MODE_OFF, MODE_HEURISTIC, MODE_NET = 0, 1, 2
 NORM_TWO_SIDED, NORM_DOWNSCALE = 0, 1
 PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
+LOSS_REL_L2, LOSS_LOG_MSE = 0, 1
 MISS = 0xFFFFFFFF
 NSTAGES = 8
 STAGES = ["camera", "extend", "shade", "network", "sum_q", "roulette_scan", "expand", "pass_end"]
@@ -27,7 +28,7 @@ EXPORTS = [
     "nrrs_create", "nrrs_workspace_size", "nrrs_bind_workspace", "nrrs_upload_scene", "nrrs_render",
     "nrrs_set_timing", "nrrs_train_step", "nrrs_read_image", "nrrs_reset_image", "nrrs_set_guide", "nrrs_get_guide",
     "nrrs_get_params", "nrrs_set_params", "nrrs_read_records", "nrrs_debug_rrs_expand",
-    "nrrs_debug_load_records", "nrrs_debug_trace",
+    "nrrs_debug_load_records", "nrrs_debug_read_queue", "nrrs_debug_trace",
     "nrrs_debug_philox", "nrrs_debug_mlp_forward", "nrrs_debug_mlp_grad", "nrrs_status_string",
     "nrrs_last_error", "nrrs_destroy",
 ]
@@ -38,7 +39,7 @@ class Config(C.Structure):
         ("width", C.c_uint32), ("height", C.c_uint32), ("s_batch", C.c_uint32),
         ("cap_factor", C.c_double), ("f_rate", C.c_double), ("norm_mode", C.c_int32), ("seed", C.c_uint64),
         ("net_max_depth", C.c_int32), ("precision", C.c_int32), ("records_cap", C.c_uint32),
-        ("p_train", C.c_double),
+        ("p_train", C.c_double), ("loss", C.c_int32), ("ema_decay", C.c_double),
     ]
 
 
@@ -92,6 +93,7 @@ def load():
         "nrrs_read_records": [P, P, P, P, P, P, P, P],
         "nrrs_debug_rrs_expand": [P, P, P, P, U32, U32, D, D, P, I32, U32, P, P, P, P, P, P, P],
         "nrrs_debug_load_records": [P, P, P, P, U32],
+        "nrrs_debug_read_queue": [P, I32, U32, P, P, P, P],
         "nrrs_debug_trace": [P, P, P, U32, P, P, P, P],
         "nrrs_debug_philox": [P, P, P, U32, P],
         "nrrs_debug_mlp_forward": [P, P, U32, I32, P, P],
@@ -124,7 +126,7 @@ class Renderer:
 
     def __init__(self, width, height, s_batch=1, cap_factor=2.0, f_rate=1.0, norm_mode=NORM_TWO_SIDED, seed=0,
                  net_max_depth=4, precision=PREC_FP32, records_cap=0, p_train=0.0, max_tris=1 << 16,
-                 max_materials=4096, device="cuda:0", stream=None):
+                 max_materials=4096, device="cuda:0", stream=None, loss=LOSS_REL_L2, ema_decay=0.0):
         import torch
         self.torch = torch
         self.L = load()
@@ -132,7 +134,7 @@ class Renderer:
         torch.cuda.set_device(self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.cfg = Config(width, height, s_batch, cap_factor, f_rate, norm_mode, seed, net_max_depth, precision,
-                          records_cap, p_train)
+                          records_cap, p_train, loss, ema_decay)
         self.width, self.height, self.s_batch = width, height, s_batch
         self.records_cap = records_cap
         h = C.c_void_p()
@@ -273,6 +275,11 @@ class Renderer:
         lt, ac = _c(lum_t, np.float32), _c(acc, np.float32)
         assert lt.size == ac.size == f.shape[0]
         self._check(self.L.nrrs_debug_load_records(self.h, _p(f), _p(lt), _p(ac), f.shape[0]))
+
+    def debug_read_queue(self, which, n):
+        o, d, t, h = (np.zeros((n, 4), np.float32) for _ in range(4))
+        self._check(self.L.nrrs_debug_read_queue(self.h, which, n, _p(o), _p(d), _p(t), _p(h)))
+        return o, d, t, h
 
     def debug_trace(self, rays, exclude=None):
         rays = _c(rays, np.float32).reshape(-1, 6)

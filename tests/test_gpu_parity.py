@@ -152,8 +152,9 @@ def test_white_furnace_on_gpu(nrrs_mod, scenes, D):
     st = r.render(4, D, nrrs_mod.MODE_HEURISTIC)
     img, spp = r.read_image()
     assert spp == 4
+    assert np.all(st["S"][1:D] == st["n"][1:D])       # no path escaped the closed box
+    assert np.all(st["n"][1:] == 4 * 32 * 32)
     assert np.allclose(img, furnace_value(D), rtol=1e-5, atol=0)
-    assert np.all(st["S"][1:D] == st["n"][1:D])
 
 
 def _compare_images(g, o, frag, rtol=1e-4):
@@ -218,8 +219,9 @@ def test_mlp_forward_fp32_matches_oracle(O, nrrs_mod, scenes):
     assert np.allclose(y, oy, rtol=1e-5, atol=1e-6)
 
 
-def test_mlp_grad_matches_oracle(O, nrrs_mod, scenes):
-    r = make(nrrs_mod, scenes.cornell(), 256, 256)
+@pytest.mark.parametrize("loss_kind", [0, 1])
+def test_mlp_grad_matches_oracle(O, nrrs_mod, scenes, loss_kind):
+    r = make(nrrs_mod, scenes.cornell(), 256, 256, loss=loss_kind)
     rng = np.random.default_rng(6)
     P = rng.normal(0, 0.25, size=9729).astype(np.float32)
     r.set_params(P)
@@ -227,7 +229,8 @@ def test_mlp_grad_matches_oracle(O, nrrs_mod, scenes):
     x = rng.normal(0, 1, size=(n, 20)).astype(np.float32)
     tgt = rng.uniform(0, 3, size=n).astype(np.float32)
     loss, g = r.debug_mlp_grad(x, tgt)
-    oloss, og = O.mlp_loss_grad(P.astype(np.float64), x.astype(np.float64), tgt.astype(np.float64), 0.01)
+    oloss, og = O.mlp_loss_grad(P.astype(np.float64), x.astype(np.float64), tgt.astype(np.float64), 0.01,
+                                loss_kind)
     assert loss == pytest.approx(oloss, rel=1e-5)
     bounds = [0, 1280, 1344, 5440, 5504, 9600, 9664, 9728, 9729]
     for a, b in zip(bounds[:-1], bounds[1:]):
@@ -238,7 +241,7 @@ def test_mlp_grad_matches_oracle(O, nrrs_mod, scenes):
 
 def test_training_step_matches_oracle_adam(O, nrrs_mod, scenes):
     # seeded records loaded through the test entry point; one epoch = one Adam step
-    r = make(nrrs_mod, scenes.cornell(), 8, 8, records_cap=4096)
+    r = make(nrrs_mod, scenes.cornell(), 8, 8, records_cap=4096, loss=1)
     rng = np.random.default_rng(8)
     n = 2048
     feat = rng.normal(0, 1, size=(n, 20)).astype(np.float32)
@@ -252,7 +255,7 @@ def test_training_step_matches_oracle_adam(O, nrrs_mod, scenes):
     P1, m1, v1, step1 = r.get_params()
     assert step1 == step0 + 1
     tgt = (acc / lum_t).astype(np.float32).astype(np.float64)
-    oloss, og = O.mlp_loss_grad(P0.astype(np.float64), feat.astype(np.float64), tgt, 0.01)
+    oloss, og = O.mlp_loss_grad(P0.astype(np.float64), feat.astype(np.float64), tgt, 0.01, O.LOSS_LOG_MSE)
     assert loss == pytest.approx(oloss, rel=1e-4)
     w = P0.astype(np.float64)
     m = np.zeros(9729)
@@ -302,3 +305,77 @@ def test_records_match_oracle(O, nrrs_mod, scenes):
         checked += 1
     assert checked > 0.8 * len(okey)
     assert abs(len(gkey) - len(okey)) <= 0.01 * len(okey) + 4
+
+
+@pytest.mark.parametrize("prec,rtol", [(1, 2e-3), (2, 2e-2)])
+def test_mlp_forward_matrix_core_matches_oracle_quantization(O, nrrs_mod, scenes, prec, rtol):
+    # BF16 / FP8 matrix-core inference vs the oracle evaluating the same quantization in FP64;
+    # the remaining difference is FP32 accumulation order and rare re-rounding of activations
+    r = make(nrrs_mod, scenes.cornell(), 256, 256)
+    rng = np.random.default_rng(30 + prec)
+    P = rng.normal(0, 0.25, size=9729).astype(np.float32)
+    r.set_params(P)
+    n = 16384 + 13                      # tiles of 32 with a ragged tail
+    x = rng.normal(0, 1, size=(n, 20)).astype(np.float32)
+    y, z = r.debug_mlp_forward(x, precision=prec)
+    oy, oz, near = O.mlp_forward_quant(P.astype(np.float64), x.astype(np.float64), prec, with_fragile=True)
+    err = np.abs(y - oy) / (np.abs(oy) + 1e-3)
+    # rows with a rounding decision near a midpoint may quantize the other way in float32
+    assert near.mean() < 0.05
+    assert err[~near].max() < rtol, np.quantile(err[~near], [0.5, 0.99, 0.999, 1.0])
+    assert np.median(err) < rtol / 10
+    # distance to the unquantized FP64 network, recorded for the precision comparison
+    fy, _ = O.mlp_forward(P.astype(np.float64), x.astype(np.float64))
+    rel = np.abs(y - fy) / (np.abs(fy) + 1e-3)
+    print(f"precision {prec}: median rel. deviation from the FP64 network {np.median(rel):.2e}, "
+          f"99th pct {np.quantile(rel, 0.99):.2e}")
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_net_render_matrix_core_statistics(O, nrrs_mod, scenes, prec):
+    # the matrix-core network inside the bounce loop: budget invariants hold and the image
+    # agrees in mean with the FP32-network render of the same scene
+    W = H = 64
+    D = 8
+    sc = scenes.cornell()
+    rng = np.random.default_rng(9)
+    params = rng.normal(0, 0.2, size=9729).astype(np.float32)
+    guide = rng.uniform(0.05, 2.0, size=W * H).astype(np.float32)
+    means = {}
+    for p in (0, prec):
+        r = make(nrrs_mod, sc, W, H, s_batch=4, precision=p)
+        r.set_params(params)
+        tot = []
+        for k in range(8):
+            r.set_guide(guide)
+            r.reset_image()
+            st = r.render(4, D, nrrs_mod.MODE_NET)
+            assert np.all(st["S"][1:D] <= 2 * W * H * 4)
+            img, _ = r.read_image()
+            assert np.all(np.isfinite(img))
+            tot.append((img.reshape(-1, 3) @ LUM).mean())
+        means[p] = (np.mean(tot), np.std(tot) / math.sqrt(len(tot)))
+    (m0, s0), (m1, s1) = means[0], means[prec]
+    assert abs(m0 - m1) < 4 * math.sqrt(s0 ** 2 + s1 ** 2) + 1e-3 * m0
+
+
+def test_inference_weights_follow_the_moving_average(O, nrrs_mod, scenes):
+    # with decay b, one Adam step moves the inference weights to b * P0 + (1 - b) * P1
+    b = 0.9
+    r = make(nrrs_mod, scenes.cornell(), 8, 8, records_cap=4096, ema_decay=b)
+    rng = np.random.default_rng(13)
+    n = 1024
+    feat = rng.normal(0, 1, size=(n, 20)).astype(np.float32)
+    lum_t = rng.uniform(0.05, 1.0, size=n).astype(np.float32)
+    acc = (lum_t * rng.lognormal(0, 1, size=n)).astype(np.float32)
+    r.debug_load_records(feat, lum_t, acc)
+    P0, _, _, _ = r.get_params()
+    r.train_step(n, n, 5e-3)
+    P1, _, _, _ = r.get_params()
+    x = rng.normal(0, 1, size=(4096, 20)).astype(np.float32)
+    y, _ = r.debug_mlp_forward(x)
+    Pe = b * P0.astype(np.float64) + (1 - b) * P1.astype(np.float64)
+    oy, _ = O.mlp_forward(Pe, x.astype(np.float64))
+    assert np.allclose(y, oy, rtol=1e-5, atol=1e-6)
+    oy1, _ = O.mlp_forward(P1.astype(np.float64), x.astype(np.float64))
+    assert not np.allclose(y, oy1, rtol=1e-5, atol=1e-6)

@@ -51,7 +51,11 @@ def test_status_strings(lib):
 def test_create_rejects_bad_config(lib):
     from paper_2510_07868_amd import nrrs
     h = ctypes.c_void_p()
-    bad = nrrs.Config(0, 4, 1, 2.0, 1.0, 0, 0, 4, 0, 0, 0.0)   # width 0
+    bad = nrrs.Config(0, 4, 1, 2.0, 1.0, 0, 0, 4, 0, 0, 0.0, 0, 0.0)   # width 0
     assert lib.nrrs_create(ctypes.byref(bad), None, ctypes.byref(h)) == -1
-    bad = nrrs.Config(4, 4, 1, 2.0, 1.0, 0, 0, 9, 0, 0, 0.0)   # net_max_depth > 4
+    bad = nrrs.Config(4, 4, 1, 2.0, 1.0, 0, 0, 9, 0, 0, 0.0, 0, 0.0)   # net_max_depth > 4
+    assert lib.nrrs_create(ctypes.byref(bad), None, ctypes.byref(h)) == -1
+    bad = nrrs.Config(4, 4, 1, 2.0, 1.0, 0, 0, 4, 0, 0, 0.0, 7, 0.0)   # unknown loss
+    assert lib.nrrs_create(ctypes.byref(bad), None, ctypes.byref(h)) == -1
+    bad = nrrs.Config(4, 4, 1, 2.0, 1.0, 0, 0, 4, 0, 0, 0.0, 0, 1.0)   # ema decay must be < 1
     assert lib.nrrs_create(ctypes.byref(bad), None, ctypes.byref(h)) == -1

@@ -18,6 +18,7 @@ def test_white_furnace_closed_form(O, scenes, D):
     cfg = O.make_cfg(16, 16, 2, D, mode=O.MODE_HEUR, n_passes=2)
     r = O.render(sc, cfg)
     img = r["image"].reshape(-1, 3) / 4.0
+    assert np.all(r["n"][1:] == 16 * 16 * 2 * 2)     # no path escaped the closed box
     assert np.allclose(img, furnace_value(D), rtol=1e-12, atol=0)
     # zero variance case: every factor normalises to exactly 1, no split, no kill
     assert np.all(r["S"][1:D] == r["n"][1:D]) and np.all(r["retries"] == 0)

@@ -73,6 +73,55 @@ def test_gradient_finite_differences(O):
         assert abs(num - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-8, i
 
 
+def test_relative_l2_gradient_is_the_frozen_denominator_derivative(O):
+    # with sg(y) in the denominator the gradient equals the derivative of
+    # sum (y(theta) - L)^2 / (y0^2 + eps) / n with y0 frozen at the current parameters
+    rng = np.random.default_rng(11)
+    P = rng.normal(0, 0.4, size=9729)
+    x = rng.normal(size=(5, 20))
+    tgt = rng.uniform(0.0, 3.0, size=5)
+    loss, g = O.mlp_loss_grad(P, x, tgt, 0.01, O.LOSS_REL_L2)
+    y0, _ = O.mlp_forward(P, x)
+    assert loss == pytest.approx(np.mean((y0 - tgt) ** 2 / (y0 ** 2 + 0.01)), rel=1e-14)
+    def surrogate(Q):
+        y, _ = O.mlp_forward(Q, x)
+        return np.mean((y - tgt) ** 2 / (y0 ** 2 + 0.01))
+    h = 1e-6
+    for i in np.concatenate([rng.choice(9729, 80, replace=False), [9728, 9700, 1300, 3]]):
+        Pp, Pm = P.copy(), P.copy()
+        Pp[i] += h
+        Pm[i] -= h
+        num = (surrogate(Pp) - surrogate(Pm)) / (2 * h)
+        assert abs(num - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-8, i
+
+
+def test_relative_l2_minimiser_is_the_mean(O):
+    # Bias-only network (y = softplus_mod(b4) on every row): the root of the oracle's own
+    # gradient in b4 (found by bisection) is the stationary point of each loss.  On noisy
+    # targets (5 % at 20, else 0; mean 1) the relative L2 settles at the mean, the log loss
+    # far below it (at the geometric mean of L + eps, minus eps).
+    tgt = np.zeros(400)
+    tgt[::20] = 20.0
+    x = np.zeros((tgt.size, 20))
+    expect_log = math.exp(np.mean(np.log(tgt + 0.01))) - 0.01
+    for kind, want, rel in ((O.LOSS_REL_L2, None, None), (O.LOSS_LOG_MSE, expect_log, 1e-6)):
+        lo, hi = -20.0, 20.0
+        for _ in range(60):
+            P = np.zeros(9729)
+            P[OFF["B4"]] = 0.5 * (lo + hi)
+            _, g = O.mlp_loss_grad(P, x, tgt, 0.01, kind)
+            if g[OFF["B4"]] > 0:
+                hi = P[OFF["B4"]]
+            else:
+                lo = P[OFF["B4"]]
+        y = O.softplus_mod(0.5 * (lo + hi))
+        if kind == O.LOSS_REL_L2:
+            # stationary point of sum (y - L)/(y^2 + eps) = 0 is the sample mean
+            assert y == pytest.approx(tgt.mean(), rel=1e-6)
+        else:
+            assert y == pytest.approx(want, rel=rel) and y < 0.1 * tgt.mean()
+
+
 def test_loss_value_definition(O):
     P = np.zeros(9729)
     P[OFF["B4"]] = 0.0  # y = ln 2 for every row
@@ -94,3 +143,52 @@ def test_adam_closed_form(O):
         O.adam(w, m, v, g, step, lr, 0.9, 0.999, eps)
         expect = w0 - step * lr * g / (np.abs(g) + eps)
         assert np.allclose(w, expect, rtol=1e-12, atol=1e-15)
+
+
+def test_bfloat16_rounding_special_values(O):
+    # bfloat16 keeps 8 significant bits: the spacing above 1 is 2^-7
+    assert O.round_bf16(1.0) == 1.0
+    assert O.round_bf16(1.0 + 2 ** -8) == 1.0                   # tie -> even mantissa
+    assert O.round_bf16(1.0 + 3 * 2 ** -8) == 1.0 + 2 ** -6     # tie -> even (up)
+    assert O.round_bf16(1.0 + 2 ** -8 + 2 ** -12) == 1.0 + 2 ** -7
+    assert O.round_bf16(-3.0) == -3.0
+    assert O.round_bf16(0.1) == pytest.approx(0.1, rel=2 ** -8)
+
+
+def test_e4m3_rounding_special_values(O):
+    # OCP E4M3: 3 mantissa bits, exponent bias 7, largest normal 448, subnormal step 2^-9
+    assert O.round_e4m3(448.0) == 448.0
+    assert O.round_e4m3(500.0) == 448.0 and O.round_e4m3(-1e6) == -448.0   # saturate
+    assert O.round_e4m3(1.0625) == 1.0                          # tie between 1 and 1.125 -> even
+    assert O.round_e4m3(1.1875) == 1.25                         # tie between 1.125 and 1.25 -> even
+    assert O.round_e4m3(17.0) == 16.0 and O.round_e4m3(19.0) == 20.0
+    assert O.round_e4m3(2 ** -9) == 2 ** -9                     # smallest subnormal
+    assert O.round_e4m3(2 ** -10) == 0.0                        # tie -> even (zero)
+    assert O.round_e4m3(3 * 2 ** -10) == 2 ** -8                # tie -> even (2 steps)
+    assert O.round_e4m3(2 ** -6) == 2 ** -6                     # smallest normal
+    assert O.round_e4m3(0.0) == 0.0
+
+
+def test_quantized_forward_reduces_to_exact_for_representable_weights(O):
+    # weights and inputs already on the BF16 / E4M3 grids (small integers x powers of two,
+    # activations staying representable) give the exact network output
+    rng = np.random.default_rng(21)
+    P = np.zeros(9729)
+    P[:1280] = rng.integers(-2, 3, size=1280) * 0.25
+    P[1344:5440] = rng.integers(-2, 3, size=4096) * 2.0 ** -5
+    P[5504:9600] = rng.integers(-2, 3, size=4096) * 2.0 ** -5
+    P[9664:9728] = rng.normal(size=64)
+    x = rng.integers(-2, 3, size=(50, 20)).astype(np.float64)
+    y, z = O.mlp_forward(P, x)
+    yb, zb = O.mlp_forward_quant(P, x, 1)
+    assert np.allclose(zb, z, rtol=1e-2, atol=1e-2)
+    y8, z8 = O.mlp_forward_quant(P, x, 2)
+    assert np.allclose(z8, z, rtol=0.1, atol=0.1)
+    # and quantization moves a generic network by a bounded amount
+    Pg = rng.normal(0, 0.2, size=9729)
+    xg = rng.normal(size=(200, 20))
+    yg, _ = O.mlp_forward(Pg, xg)
+    ybg, _ = O.mlp_forward_quant(Pg, xg, 1)
+    y8g, _ = O.mlp_forward_quant(Pg, xg, 2)
+    assert np.median(np.abs(ybg / yg - 1)) < 1e-2
+    assert np.median(np.abs(y8g / yg - 1)) < 6e-2
