@@ -41,8 +41,8 @@ def main():
     ap.add_argument("--width", type=int, default=512)
     ap.add_argument("--spp", type=int, default=16)
     ap.add_argument("--depth", type=int, default=16)
-    ap.add_argument("--ref-spp", type=int, default=1024)
-    ap.add_argument("--eval-renders", type=int, default=4)
+    ap.add_argument("--ref-spp", type=int, default=2048)
+    ap.add_argument("--eval-renders", type=int, default=8)
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-eff", action="store_true")
@@ -67,7 +67,8 @@ def main():
     t_scene = time.time()
     sc = scenes.heightfield(0)
     r = nrrs.Renderer(W, H, s_batch=spp, cap_factor=2.0, seed=0, net_max_depth=4, precision=prec,
-                      records_cap=rec_n, p_train=p_train, max_tris=sc.n_tris, max_materials=len(sc.mat_type))
+                      records_cap=rec_n, p_train=p_train, max_tris=sc.n_tris, max_materials=len(sc.mat_type),
+                      loss=nrrs.LOSS_REL_L2, ema_decay=0.99)
     r.upload_scene(sc)
     t_upload = time.time() - t_scene
     r.set_timing(True)
@@ -145,20 +146,28 @@ def main():
     }
 
     if not args.no_eff:
-        out["efficiency"] = efficiency(r, nrrs, spp, D, args.ref_spp, args.eval_renders)
+        def make_reference(ref_spp):
+            rr = nrrs.Renderer(W, H, s_batch=spp, cap_factor=2.0, seed=0x5EED5EED, max_tris=sc.n_tris,
+                               max_materials=len(sc.mat_type))
+            rr.upload_scene(sc)
+            rr.render(ref_spp, D, nrrs.MODE_OFF, stats=False)
+            img, _ = rr.read_image()
+            rr.close()
+            return img
+        out["efficiency"] = efficiency(r, nrrs, spp, D, args.ref_spp, args.eval_renders, make_reference)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc, W, H, D)
     print(json.dumps(out), flush=True)
 
 
-def efficiency(r, nrrs, spp, D, ref_spp, renders):
+def efficiency(r, nrrs, spp, D, ref_spp, renders, make_reference):
     """relMSE and 1/(relMSE * t) of NRRS and heuristic normalized RRS at equal spp."""
     import torch
 
     res = {}
+    guide = r.get_guide()
     for name, mode in (("nrrs", nrrs.MODE_NET), ("heuristic", nrrs.MODE_HEURISTIC)):
-        errs, times, imgs = [], [], []
-        guide = r.get_guide()
+        times, imgs = [], []
         for k in range(renders):
             r.set_guide(guide)          # every evaluation render sees the same previous frame
             r.reset_image()             # the pass counter keeps counting: fresh random numbers
@@ -170,18 +179,20 @@ def efficiency(r, nrrs, spp, D, ref_spp, renders):
             img, _ = r.read_image()
             imgs.append(img)
         res[name] = {"times": times, "imgs": imgs}
-        r.set_guide(guide)
-    r.reset_image()
+    r.set_guide(guide)
+    # reference: plain path tracing with an independent seed (no random stream shared with the
+    # evaluation renders)
     t0 = time.perf_counter()
-    r.render(ref_spp, D, nrrs.MODE_OFF, stats=False)
-    ref, _ = r.read_image()
+    ref = make_reference(ref_spp)
     t_ref = time.perf_counter() - t0
-    out = {"reference": f"plain path tracing, {ref_spp} spp, same depth", "reference_s": round(t_ref, 2),
-           "spp": spp}
+    out = {"reference": f"plain path tracing, {ref_spp} spp, same depth, independent seed",
+           "reference_s": round(t_ref, 2), "spp": spp, "renders": renders}
     for name, d in res.items():
-        rm = float(np.mean([relmse(i, ref) for i in d["imgs"]]))
+        errs = [relmse(i, ref) for i in d["imgs"]]
+        rm = float(np.mean(errs))
         t = float(np.median(d["times"]))
-        out[name] = {"relmse": rm, "render_s": round(t, 5), "efficiency": 1.0 / (rm * t)}
+        out[name] = {"relmse": rm, "relmse_se": float(np.std(errs) / np.sqrt(len(errs))), "render_s": round(t, 5),
+                     "efficiency": 1.0 / (rm * t)}
     out["nrrs_over_heuristic"] = out["nrrs"]["efficiency"] / out["heuristic"]["efficiency"]
     return out
 

@@ -174,6 +174,12 @@ int32_t nrrs_get_params(nrrs_ctx* ctx, float* master, float* adam_m, float* adam
 int32_t nrrs_set_params(nrrs_ctx* ctx, const float* master, const float* adam_m,
                         const float* adam_v, const uint64_t* step);
 
+/* How nrrs_render enqueues a pass: 1 (default) captures the pass's launch sequence once per
+ * (max_depth, mode, records on/off) into a hipGraph and replays it for every pass; 0 launches
+ * the kernels directly.  Per-stage timing, and a context on the null stream (which cannot be
+ * captured), always launch directly. */
+int32_t nrrs_set_launch_mode(nrrs_ctx* ctx, int32_t mode);
+
 /* Enable (1) or disable (0) per-stage GPU timing of nrrs_render with HIP events recorded on
  * the context stream between the stages; results appear in nrrs_render_stats. */
 int32_t nrrs_set_timing(nrrs_ctx* ctx, int32_t enabled);

@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -77,11 +79,20 @@ struct nrrs_ctx {
   // counters on the host
   uint64_t spp_total = 0, passes_done = 0, adam_step = 0;
   std::string err;
+  PassState* pass_state = nullptr;
   // stage timing
   bool timing = false;
   std::vector<hipEvent_t> events;
   std::vector<int> event_stage;
+  // launch mode: 1 = replay one captured hipGraph per pass (keyed by depth, mode, records)
+  int32_t launch_mode = 1;
+  std::map<std::tuple<uint32_t, int32_t, uint32_t>, hipGraphExec_t> graphs;
+  void drop_graphs() {
+    for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
   ~nrrs_ctx() {
+    drop_graphs();
     for (hipEvent_t e : events) hipEventDestroy(e);
   }
 };
@@ -131,6 +142,7 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
   c->alpha = k.take<double>(1);
   c->overflow = k.take<uint32_t>(1);
   c->rays = k.take<unsigned long long>(3);
+  c->pass_state = k.take<PassState>(1);
   c->st_n = k.take<unsigned long long>(NRRS_MAX_DEPTH + 1);
   c->st_s = k.take<unsigned long long>(NRRS_MAX_DEPTH + 1);
   c->st_r = k.take<unsigned long long>(NRRS_MAX_DEPTH + 1);
@@ -230,6 +242,7 @@ RenderArgs base_args(nrrs_ctx* c) {
   a.dbg_parent = nullptr;
   a.spill = c->spill;
   a.trace_blocks = c->trace_blocks;
+  a.pass_state = c->pass_state;
   return a;
 }
 
@@ -295,6 +308,7 @@ int32_t nrrs_create(const nrrs_config* cfg, void* hip_stream, nrrs_ctx** out) {
   c->nprim = nprim;
   c->cap = cap;
   c->trace_blocks = (uint32_t)prop.multiProcessorCount * extend_blocks_per_cu();
+  warm_mfma_launch_cache();
   *out = c;
   return NRRS_OK;
 }
@@ -321,6 +335,7 @@ int32_t nrrs_bind_workspace(nrrs_ctx* c, void* device_ptr, uint64_t bytes, uint6
   carve(c, (uint8_t*)device_ptr, max_tris, max_materials);
   c->ws = (uint8_t*)device_ptr;
   c->ws_bytes = bytes;
+  c->drop_graphs();
   c->max_tris = max_tris;
   c->max_mats = max_materials;
   c->bound = true;
@@ -434,10 +449,17 @@ int32_t nrrs_upload_scene(nrrs_ctx* c, const float* verts, uint64_t nv, const ui
   d.fwd_x = (float)fwd[0]; d.fwd_y = (float)fwd[1]; d.fwd_z = (float)fwd[2];
   d.rx = (float)(r[0] * th * aspect); d.ry = (float)(r[1] * th * aspect); d.rz = (float)(r[2] * th * aspect);
   d.ux = (float)(u[0] * th); d.uy = (float)(u[1] * th); d.uz = (float)(u[2] * th);
+  c->drop_graphs();  // captured passes hold the old scene in their kernel arguments
   c->bvh_order = bvh.order;
   c->orig_to_bvh.assign(nt, 0);
   for (uint64_t k = 0; k < nt; ++k) c->orig_to_bvh[bvh.order[k]] = (uint32_t)k;
   c->scene = true;
+  return NRRS_OK;
+}
+
+int32_t nrrs_set_launch_mode(nrrs_ctx* c, int32_t mode) {
+  if (!c || (mode != 0 && mode != 1)) return NRRS_EINVAL;
+  c->launch_mode = mode;
   return NRRS_OK;
 }
 
@@ -481,43 +503,84 @@ int32_t nrrs_render(nrrs_ctx* c, uint32_t spp, uint32_t max_depth, int32_t mode,
     ++n_ev;
     return NRRS_OK;
   };
-#define MARK(stage)                    \
-  do {                                 \
-    int32_t r_ = mark(stage);          \
-    if (r_ != NRRS_OK) return r_;      \
+  // One whole pass: advance the device pass state, camera, the bounce loop, statistics and
+  // the guide refresh.  Its launches depend on nothing that changes between passes.
+  auto enqueue_pass = [&](bool timed) -> int32_t {
+#define MARK(stage)                             \
+  do {                                          \
+    if (timed) {                                \
+      int32_t r_ = mark(stage);                 \
+      if (r_ != NRRS_OK) return r_;             \
+    }                                           \
   } while (0)
-  MARK(-1);
-  for (uint32_t p = 0; p < passes; ++p) {
-    a.pass = (uint32_t)(c->passes_done + p);
-    a.qin = c->qa;
-    a.qout = c->qb;
-    launch_camera(a, s);
+    RenderArgs b = a;
+    launch_begin_pass(b, (double)c->cfg.s_batch, s);
+    launch_camera(b, s);
     MARK(0);
     for (uint32_t d = 1; d <= max_depth; ++d) {
-      a.depth = d;
-      launch_extend(a, s);
+      b.depth = d;
+      launch_extend(b, s);
       MARK(1);
-      launch_shade(a, s);
+      launch_shade(b, s);
       MARK(2);
       if (d == max_depth) break;
       if (mode == NRRS_MODE_NET && d <= (uint32_t)c->cfg.net_max_depth) {
-        launch_rrsnet(a, net, s);
+        launch_rrsnet(b, net, s);
         MARK(3);
       }
-      launch_sum_q(a, s);
+      launch_sum_q(b, s);
       MARK(4);
-      launch_roulette(a, s);
+      launch_roulette(b, s);
       MARK(5);
-      launch_expand(a, s);
+      launch_expand(b, s);
       MARK(6);
-      std::swap(a.qin, a.qout);
+      std::swap(b.qin, b.qout);
     }
     launch_accumulate_stats(c->ctl, max_depth, c->st_n, c->st_s, c->st_r, c->st_sumq, c->st_f, s);
-    c->spp_total += c->cfg.s_batch;
-    launch_guide(a, (double)c->spp_total, c->guide, s);
+    launch_guide(b, c->guide, s);
     MARK(7);
-  }
 #undef MARK
+    return NRRS_OK;
+  };
+  // the device pass state continues from the host's counters
+  launch_set_pass_state(c->pass_state, (uint32_t)(c->passes_done - 1), (double)c->spp_total, s);
+  if (c->timing) {
+    int32_t r0 = mark(-1);
+    if (r0 != NRRS_OK) return r0;
+  }
+  // the null stream cannot be captured: direct launches there
+  const bool use_graph = c->launch_mode == 1 && !c->timing && s != nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    const auto key = std::make_tuple(max_depth, mode, a.records_on);
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) {
+      exec = it->second;
+    } else {
+      hipGraph_t graph = nullptr;
+      HIPC(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      const int32_t rq = enqueue_pass(false);
+      hipError_t ec = hipStreamEndCapture(s, &graph);  // always ends the capture
+      if (rq != NRRS_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return rq;
+      }
+      if (ec != hipSuccess) return fail(c, NRRS_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+      ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+      if (ec != hipSuccess) return fail(c, NRRS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ec));
+      c->graphs[key] = exec;
+    }
+  }
+  for (uint32_t p = 0; p < passes; ++p) {
+    if (use_graph) {
+      HIPC(c, hipGraphLaunch(exec, s));
+    } else {
+      const int32_t rp = enqueue_pass(c->timing);
+      if (rp != NRRS_OK) return rp;
+    }
+    c->spp_total += c->cfg.s_batch;
+  }
   c->passes_done += passes;
   HIPC(c, hipGetLastError());
   if (stats) {

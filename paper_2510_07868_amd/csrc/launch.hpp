@@ -7,6 +7,14 @@
 
 namespace nrrs {
 
+// Values that change from pass to pass live on the device so that a captured pass can be
+// replayed as is: k_begin_pass advances them at the start of every pass.
+struct PassState {
+  uint32_t pass;   // pass index keying the random numbers
+  uint32_t pad;
+  double spp;      // samples per pixel accumulated in the image after this pass
+};
+
 // Everything the per-depth kernels read about the render in progress.
 struct RenderArgs {
   DevScene sc;
@@ -36,6 +44,7 @@ struct RenderArgs {
   uint32_t* dbg_parent; // when set, the expansion also writes each child's parent index
   uint32_t* spill;      // traversal stack spill area [spill depth][trace_blocks * threads]
   uint32_t trace_blocks;
+  PassState* pass_state;  // pass index and samples per pixel so far (advanced on the device)
 };
 
 void launch_camera(const RenderArgs& a, hipStream_t s);
@@ -45,7 +54,9 @@ void launch_sum_q(const RenderArgs& a, hipStream_t s);
 void launch_roulette(const RenderArgs& a, hipStream_t s);  // count, scan, guard, offsets
 void launch_expand(const RenderArgs& a, hipStream_t s);
 void launch_parents(const RenderArgs& a, hipStream_t s);  // parent map only (test entry point)
-void launch_guide(const RenderArgs& a, double spp_total, float* guide, hipStream_t s);
+void launch_guide(const RenderArgs& a, float* guide, hipStream_t s);
+void launch_begin_pass(const RenderArgs& a, double spp_per_pass, hipStream_t s);
+void launch_set_pass_state(PassState* ps, uint32_t pass, double spp, hipStream_t s);
 void launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s);
 void launch_zero_f64(double* p, uint64_t n, hipStream_t s);
 void launch_fill_f32(float* p, uint64_t n, float v, hipStream_t s);
@@ -87,6 +98,7 @@ uint32_t packed_fp8_bytes();
 void launch_pack_weights(const float* master, uint16_t* bf16, uint8_t* fp8, float* fp8_scale, hipStream_t s);
 void launch_rrsnet_mfma(const RenderArgs& a, const NetArgs& n, hipStream_t s);
 void launch_rows_mfma(const float* x, uint32_t n, const NetArgs& net, float* y, float* z, hipStream_t s);
+void warm_mfma_launch_cache();  // occupancy queries done before any stream capture
 uint32_t mlp_grad_blocks(uint32_t n);
 
 }  // namespace nrrs

@@ -359,23 +359,31 @@ __global__ __launch_bounds__(kThreads) void k_rows_mfma(const float* x, uint32_t
   }
 }
 
+// Persistent grid: CUs x resident blocks, one cached value per kernel variant.
 template <typename K>
-uint32_t grid_for(K kernel) {
-  static uint32_t blocks = 0;
-  if (blocks == 0) {
+uint32_t grid_for(K kernel, int slot) {
+  static uint32_t blocks[4] = {0, 0, 0, 0};
+  if (blocks[slot] == 0) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       cus = 256;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kThreads, 0) != hipSuccess || per < 1) per = 1;
-    blocks = (uint32_t)(std::max(cus, 1) * per);
+    blocks[slot] = (uint32_t)(std::max(cus, 1) * per);
   }
-  return blocks;
+  return blocks[slot];
 }
 
 }  // namespace
 
 uint32_t packed_bf16_elems() { return kBfTiles * 64 * 8; }
 uint32_t packed_fp8_bytes() { return kF8Tiles * 64 * 32; }
+
+void warm_mfma_launch_cache() {
+  grid_for(k_rrsnet_mfma<1>, 0);
+  grid_for(k_rrsnet_mfma<2>, 1);
+  grid_for(k_rows_mfma<1>, 2);
+  grid_for(k_rows_mfma<2>, 3);
+}
 
 void launch_pack_weights(const float* master, uint16_t* bf16, uint8_t* fp8, float* fp8_scale, hipStream_t s) {
   hipLaunchKernelGGL(k_fp8_scales, dim3(1), dim3(256), 0, s, master, fp8_scale);
@@ -385,17 +393,17 @@ void launch_pack_weights(const float* master, uint16_t* bf16, uint8_t* fp8, floa
 
 void launch_rrsnet_mfma(const RenderArgs& a, const NetArgs& n, hipStream_t s) {
   if (n.precision == 2)
-    hipLaunchKernelGGL(k_rrsnet_mfma<2>, dim3(grid_for(k_rrsnet_mfma<2>)), dim3(kThreads), 0, s, a, n);
+    hipLaunchKernelGGL(k_rrsnet_mfma<2>, dim3(grid_for(k_rrsnet_mfma<2>, 1)), dim3(kThreads), 0, s, a, n);
   else
-    hipLaunchKernelGGL(k_rrsnet_mfma<1>, dim3(grid_for(k_rrsnet_mfma<1>)), dim3(kThreads), 0, s, a, n);
+    hipLaunchKernelGGL(k_rrsnet_mfma<1>, dim3(grid_for(k_rrsnet_mfma<1>, 0)), dim3(kThreads), 0, s, a, n);
 }
 
 void launch_rows_mfma(const float* x, uint32_t n, const NetArgs& net, float* y, float* z, hipStream_t s) {
   if (!n) return;
   if (net.precision == 2)
-    hipLaunchKernelGGL(k_rows_mfma<2>, dim3(grid_for(k_rows_mfma<2>)), dim3(kThreads), 0, s, x, n, net, y, z);
+    hipLaunchKernelGGL(k_rows_mfma<2>, dim3(grid_for(k_rows_mfma<2>, 3)), dim3(kThreads), 0, s, x, n, net, y, z);
   else
-    hipLaunchKernelGGL(k_rows_mfma<1>, dim3(grid_for(k_rows_mfma<1>)), dim3(kThreads), 0, s, x, n, net, y, z);
+    hipLaunchKernelGGL(k_rows_mfma<1>, dim3(grid_for(k_rows_mfma<1>, 2)), dim3(kThreads), 0, s, x, n, net, y, z);
 }
 
 }  // namespace nrrs

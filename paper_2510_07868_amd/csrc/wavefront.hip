@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kEntryThreads) void k_camera(RenderArgs a) {
   const uint32_t npx = a.width * a.height;
   const uint32_t pix = k % npx;
   const uint32_t px = pix % a.width, py = pix / a.width;
-  const uint2 lin = make_uint2(k, a.pass);
+  const uint2 lin = make_uint2(k, a.pass_state->pass);
   const uint4 r = draw(a.key, lin, kPurposeCamera, 0, 0);
   const float sx = 2.0f * ((float)px + unit(r.x)) / (float)a.width - 1.0f;
   const float sy = 1.0f - 2.0f * ((float)py + unit(r.y)) / (float)a.height;
@@ -585,11 +585,21 @@ __global__ __launch_bounds__(kEntryThreads) void k_expand(RenderArgs a) {
 }
 
 // ------------------------------------------------------------------------------ misc
-__global__ void k_guide(const double* image, uint32_t npx, double spp, float* guide) {
+__global__ void k_guide(const double* image, uint32_t npx, const PassState* ps, float* guide) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npx) return;
+  const double spp = ps->spp;
   const double* c = image + 3ull * p;
   guide[p] = (float)((0.2126 * c[0] + 0.7152 * c[1] + 0.0722 * c[2]) / spp);
+}
+
+__global__ void k_begin_pass(PassState* ps, double spp_per_pass) {
+  ps->pass += 1u;
+  ps->spp += spp_per_pass;
+}
+__global__ void k_set_pass_state(PassState* ps, uint32_t pass, double spp) {
+  ps->pass = pass;
+  ps->spp = spp;
 }
 
 __global__ void k_zero_u32(uint32_t* p, uint64_t n) {
@@ -664,9 +674,15 @@ void launch_parents(const RenderArgs& a, hipStream_t s) {
   if (a.cap == 0) return;
   hipLaunchKernelGGL(k_parents, dim3(blocks_for(a.cap, kEntryThreads)), dim3(kEntryThreads), 0, s, a);
 }
-void launch_guide(const RenderArgs& a, double spp_total, float* guide, hipStream_t s) {
+void launch_guide(const RenderArgs& a, float* guide, hipStream_t s) {
   const uint32_t npx = a.width * a.height;
-  hipLaunchKernelGGL(k_guide, dim3(blocks_for(npx, 256)), dim3(256), 0, s, a.image, npx, spp_total, guide);
+  hipLaunchKernelGGL(k_guide, dim3(blocks_for(npx, 256)), dim3(256), 0, s, a.image, npx, a.pass_state, guide);
+}
+void launch_begin_pass(const RenderArgs& a, double spp_per_pass, hipStream_t s) {
+  hipLaunchKernelGGL(k_begin_pass, dim3(1), dim3(1), 0, s, a.pass_state, spp_per_pass);
+}
+void launch_set_pass_state(PassState* ps, uint32_t pass, double spp, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_pass_state, dim3(1), dim3(1), 0, s, ps, pass, spp);
 }
 void launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_zero_u32, dim3(std::min<uint64_t>(blocks_for(n, 256), 4096)), dim3(256), 0, s, p, n);

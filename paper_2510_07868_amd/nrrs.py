@@ -26,7 +26,7 @@ STAGES = ["camera", "extend", "shade", "network", "sum_q", "roulette_scan", "exp
 
 EXPORTS = [
     "nrrs_create", "nrrs_workspace_size", "nrrs_bind_workspace", "nrrs_upload_scene", "nrrs_render",
-    "nrrs_set_timing", "nrrs_train_step", "nrrs_read_image", "nrrs_reset_image", "nrrs_set_guide", "nrrs_get_guide",
+    "nrrs_set_timing", "nrrs_set_launch_mode", "nrrs_train_step", "nrrs_read_image", "nrrs_reset_image", "nrrs_set_guide", "nrrs_get_guide",
     "nrrs_get_params", "nrrs_set_params", "nrrs_read_records", "nrrs_debug_rrs_expand",
     "nrrs_debug_load_records", "nrrs_debug_read_queue", "nrrs_debug_trace",
     "nrrs_debug_philox", "nrrs_debug_mlp_forward", "nrrs_debug_mlp_grad", "nrrs_status_string",
@@ -83,6 +83,7 @@ def load():
         "nrrs_upload_scene": [P, P, U64, P, U64, P, P, P, U32, P, P],
         "nrrs_render": [P, U32, U32, I32, P],
         "nrrs_set_timing": [P, I32],
+        "nrrs_set_launch_mode": [P, I32],
         "nrrs_train_step": [P, U32, U32, C.c_float, P],
         "nrrs_read_image": [P, P, P],
         "nrrs_reset_image": [P],
@@ -132,7 +133,8 @@ class Renderer:
         self.L = load()
         self.device = torch.device(device)
         torch.cuda.set_device(self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own (default priority): hipGraph capture needs a non-null stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self.cfg = Config(width, height, s_batch, cap_factor, f_rate, norm_mode, seed, net_max_depth, precision,
                           records_cap, p_train, loss, ema_decay)
         self.width, self.height, self.s_batch = width, height, s_batch
@@ -195,6 +197,9 @@ class Renderer:
                     overflow=int(st.overflow), passes=int(st.passes), timed=bool(st.timed),
                     stage_ms={k: float(st.stage_ms[i]) for i, k in enumerate(STAGES)},
                     stage_launches={k: int(st.stage_launches[i]) for i, k in enumerate(STAGES)})
+
+    def set_launch_mode(self, graphs=True):
+        self._check(self.L.nrrs_set_launch_mode(self.h, 1 if graphs else 0))
 
     def set_timing(self, enabled=True):
         self._check(self.L.nrrs_set_timing(self.h, 1 if enabled else 0))
