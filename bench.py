@@ -29,6 +29,28 @@ HBM_PEAK_GBS = 8000.0
 LUM = np.array([0.2126, 0.7152, 0.0722])
 
 
+def counted_traffic():
+    """Bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, per kernel,
+    kept only while the kernel's source file is the one the counters were taken on."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_extend_heightfield512_hbm_traffic.md")
+    out = {}
+    if not os.path.exists(path):
+        return out
+    for line in open(path):
+        if not line.startswith("traffic: "):
+            continue
+        _, kernel, nbytes, src, digest = line.split()
+        try:
+            now = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()[:16]
+        except OSError:
+            continue
+        if now == digest:
+            out[kernel] = int(nbytes)
+    return out
+
+
 def relmse(img, ref):
     return float(np.mean((img - ref) ** 2 / (ref ** 2 + 0.01)))
 
@@ -46,6 +68,8 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-eff", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU sharding of the "
@@ -53,6 +77,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
 
     from paper_2510_07868_amd import nrrs, scenes
 
@@ -115,8 +143,9 @@ def main():
     ext_ms = stage_ms["extend"] / ext_launches
     ext_bytes = (64.0 * rays + 64.0 * nodes + 48.0 * tris) / ext_launches
     achieved = ext_bytes / (ext_ms * 1e-3) / 1e9
+    traffic = counted_traffic()
     roofline = {"kernel": "k_extend", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic.get("k_extend"),
                 "avg_launch_ms": round(ext_ms, 4), "algorithmic_bytes_per_launch": int(ext_bytes),
                 "nodes_per_ray": round(nodes / max(rays, 1), 2), "tris_per_ray": round(tris / max(rays, 1), 2),
                 "grays_per_s": round(rays / (stage_ms["extend"] * 1e-3) / 1e9, 3),
@@ -131,6 +160,16 @@ def main():
                "peak": peak, "unit": "TFLOP/s", "frac": round(net_flop / (net_ms * 1e-3) / 1e12 / peak, 4),
                "avg_launch_ms": round(net_ms, 4), "rows_per_launch": int(net_rows / max(stage_n["network"], 1))}
 
+    # queue stages: counted HBM bytes per launch (rocprofv3, committed summary) over the live
+    # per-launch stage time
+    queue = {}
+    for stage, kern in (("camera", "k_camera"), ("shade", "k_shade"), ("expand", "k_expand")):
+        ms = stage_ms[stage] / max(stage_n[stage], 1)
+        b = traffic.get(kern)
+        queue[kern] = {"avg_launch_ms": round(ms, 4), "hbm_bytes_per_launch": b,
+                       "hbm_gbs": round(b / (ms * 1e-3) / 1e9, 1) if b else None,
+                       "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if b else None}
+
     out = {
         "metric": METRIC, "value": round(mpaths, 2), "unit": "Mpaths/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(secs / args.steps * 1e3, 3), "higher_is_better": True,
@@ -143,6 +182,7 @@ def main():
         "stage_ms_per_step": {s: round(stage_ms[s] / args.steps, 3) for s in nrrs.STAGES},
         "roofline": roofline,
         "network": network,
+        "queue_stages": queue,
     }
 
     if not args.no_eff:
@@ -197,18 +237,30 @@ def efficiency(r, nrrs, spp, D, ref_spp, renders, make_reference):
     return out
 
 
-def cpu_baseline(sc, W, H, D):
+def copy_calibration(torch):
+    """A plain device copy of known size: 1 GiB read + 1 GiB written per launch, five launches."""
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n, "launches": 5}))
+
+
+def cpu_baseline(sc, W, H, D, passes=16):
     import oracle
 
     osc = oracle.OracleScene(sc)
-    cfg = oracle.make_cfg(W, H, 1, D, n_passes=1, mode=oracle.MODE_HEUR, tau=0.0)
+    cfg = oracle.make_cfg(W, H, 1, D, n_passes=passes, mode=oracle.MODE_HEUR, tau=0.0)
     t0 = time.perf_counter()
     o = oracle.render(osc, cfg)
     secs = time.perf_counter() - t0
     return {"value": round(o["rays"] / secs / 1e6, 3), "unit": "Mpaths/s", "cores": oracle.num_threads(),
             "kind": "oracle", "seconds": round(secs, 2),
-            "sample": f"1 spp of the same {W}x{H} heightfield workload (one {W * H}-path wavefront, max depth {D}, "
-                      "heuristic normalized RRS), FP64 C oracle with OpenMP; BVH build excluded"}
+            "sample": f"{passes} spp of the same {W}x{H} heightfield workload ({passes} passes of one {W * H}-path "
+                      f"wavefront, max depth {D}, heuristic normalized RRS), FP64 C oracle with OpenMP; BVH build "
+                      "excluded"}
 
 
 if __name__ == "__main__":

@@ -307,10 +307,13 @@ def test_records_match_oracle(O, nrrs_mod, scenes):
     assert abs(len(gkey) - len(okey)) <= 0.01 * len(okey) + 4
 
 
-@pytest.mark.parametrize("prec,rtol,tail", [(1, 2e-3, 1.0), (2, 2e-2, 0.997)])
-def test_mlp_forward_matrix_core_matches_oracle_quantization(O, nrrs_mod, scenes, prec, rtol, tail):
-    # BF16 / FP8 matrix-core inference vs the oracle evaluating the same quantization in FP64;
-    # the remaining difference is FP32 accumulation order and rare re-rounding of activations
+@pytest.mark.parametrize("prec,rtol,max_flagged", [(1, 2e-3, 0.05), (2, 5e-3, 0.4)])
+def test_mlp_forward_matrix_core_matches_oracle_quantization(O, nrrs_mod, scenes, prec, rtol, max_flagged):
+    # BF16 / FP8 matrix-core inference vs the oracle evaluating the same quantization in FP64.
+    # Rows with a rounding decision that the matrix core's accumulation could flip are flagged
+    # by the oracle: for BF16 a few FP32 rounding errors from a midpoint; for FP8 within the
+    # bound of its in-group product alignment (13 binary places below the group's largest
+    # product), which flags about a third of these rows.  Every other row must agree.
     r = make(nrrs_mod, scenes.cornell(), 256, 256)
     rng = np.random.default_rng(30 + prec)
     P = rng.normal(0, 0.25, size=9729).astype(np.float32)
@@ -320,12 +323,10 @@ def test_mlp_forward_matrix_core_matches_oracle_quantization(O, nrrs_mod, scenes
     y, z = r.debug_mlp_forward(x, precision=prec)
     oy, oz, near = O.mlp_forward_quant(P.astype(np.float64), x.astype(np.float64), prec, with_fragile=True)
     err = np.abs(y - oy) / (np.abs(oy) + 1e-3)
-    # rows with a rounding decision near a midpoint may quantize the other way in float32; for
-    # FP8 the matrix core's accumulation also moves about 1 row in 1000 across an E4M3 midpoint
-    # that the oracle does not flag (the grid is 64x coarser than BF16's), so the FP8 bar is the
-    # 99.9th percentile
-    assert near.mean() < 0.05
-    assert np.mean(err[~near] > rtol) <= 1.0 - tail, np.quantile(err[~near], [0.5, 0.99, 0.999, 1.0])
+    print(f"precision {prec}: {near.mean():.3f} of rows flagged; unflagged rel. error quantiles "
+          f"{np.quantile(err[~near], [0.5, 0.99, 0.999, 1.0])}; flagged max {err[near].max() if near.any() else 0:.3e}")
+    assert near.mean() < max_flagged
+    assert np.all(err[~near] < rtol), np.quantile(err[~near], [0.5, 0.99, 0.999, 1.0])
     assert np.median(err) < rtol / 100
     assert err.max() < 0.5
     # distance to the unquantized FP64 network, recorded for the precision comparison
