@@ -59,7 +59,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=24)
+    ap.add_argument("--warmup", type=int, default=120)
     ap.add_argument("--width", type=int, default=512)
     ap.add_argument("--spp", type=int, default=16)
     ap.add_argument("--depth", type=int, default=16)
@@ -68,6 +68,7 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-eff", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -99,6 +100,14 @@ def main():
                       loss=nrrs.LOSS_REL_L2, ema_decay=0.99)
     r.upload_scene(sc)
     t_upload = time.time() - t_scene
+    t_tune = time.time()
+    if args.no_autotune:
+        tuning, table = r.get_tuning(), []
+    else:
+        tuning, table = r.autotune(D, with_table=True)
+    for t in table:
+        print(f"#   candidate {t}", flush=True)
+    print(f"# traversal launch {tuning} ({time.time() - t_tune:.1f}s)", flush=True)
     r.set_timing(True)
     print(f"# scene {sc.n_tris} tris, setup+BVH {t_upload:.1f}s, workspace {r.workspace_bytes / 2**30:.2f} GiB",
           flush=True)
@@ -113,7 +122,6 @@ def main():
         st, loss, n = step()
         if w % 4 == 0 or w == args.warmup - 1:
             print(f"# warmup {w}: rays {st['rays']}, records {st['records']}, loss {loss:.4f}", flush=True)
-    r.reset_image()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rays = 0
@@ -183,6 +191,7 @@ def main():
         "roofline": roofline,
         "network": network,
         "queue_stages": queue,
+        "autotuned": None if args.no_autotune else tuning,
     }
 
     if not args.no_eff:

@@ -184,6 +184,37 @@ int32_t nrrs_set_launch_mode(nrrs_ctx* ctx, int32_t mode);
  * the context stream between the stages; results appear in nrrs_render_stats. */
 int32_t nrrs_set_timing(nrrs_ctx* ctx, int32_t enabled);
 
+/* Launch parameters of the persistent traversal (extend) kernel.  The grid is
+ * blocks_per_cu * (compute units) blocks of 128 lanes, each lane one ray at a time. */
+typedef struct nrrs_tuning {
+  uint32_t extend_variant;        /* 0: a lane intersects a hit leaf at once; 1: a lane parks
+                                   * the leaf it reaches and waits, the wave intersects parked
+                                   * leaves together; 2: as 1, but lanes with a parked leaf keep
+                                   * descending meanwhile */
+  uint32_t extend_blocks_per_cu;  /* 1 .. extend_max_blocks_per_cu[variant] */
+  uint32_t extend_refill;         /* idle lanes of a wave (1..64) that make it fetch new rays */
+  uint32_t extend_leaf_batch;     /* parked leaves (1..64) that trigger intersection (1, 2) */
+  uint32_t extend_max_blocks_per_cu[3]; /* out: occupancy limit of each variant (ignored by set) */
+  float extend_ms;                /* out (nrrs_autotune): traversal time of the winner's pass */
+} nrrs_tuning;
+
+/* Current traversal launch parameters and the occupancy limits. */
+int32_t nrrs_get_tuning(const nrrs_ctx* ctx, nrrs_tuning* out);
+
+/* Set traversal launch parameters (EINVAL when out of range; the context is then unchanged).
+ * Captured pass graphs are rebuilt on the next render. */
+int32_t nrrs_set_tuning(nrrs_ctx* ctx, const nrrs_tuning* tuning);
+
+/* Autotuner: times the traversal kernel of one heuristic-RRS pass of depth max_depth on the
+ * uploaded scene for each candidate (variant x blocks per CU, then the refill threshold, then
+ * the leaf batch) with HIP events, keeps the fastest and returns it in *best (may be NULL).
+ * The first min(tried_cap, candidates) candidates with their times are written to tried
+ * (caller-owned host array, may be NULL) and the candidate count to *n_tried (may be NULL).
+ * The timing passes accumulate into the image, which is then cleared as by nrrs_reset_image;
+ * they capture no training records.  Synchronous.  ESTATE without a scene. */
+int32_t nrrs_autotune(nrrs_ctx* ctx, uint32_t max_depth, nrrs_tuning* best, nrrs_tuning* tried,
+                      uint32_t tried_cap, uint32_t* n_tried);
+
 /* Training records of the last render: count, and optionally (each may be NULL)
  * features[n*20], lum_t[n], acc[n] (descendant emission luminance), depth[n], pix[n],
  * lineage id[n] (64-bit).  The record order is not deterministic. */

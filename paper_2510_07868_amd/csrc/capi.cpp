@@ -41,8 +41,10 @@ struct nrrs_ctx {
   nrrs_config cfg{};
   hipStream_t stream = nullptr;
   uint64_t npx = 0, nprim = 0, cap = 0;
-  uint32_t trace_blocks = 0;  // persistent traversal grid
-  uint32_t* spill = nullptr;
+  uint32_t cus = 0;                 // compute units of the device
+  uint32_t ext_occ[3] = {1, 1, 1};  // resident traversal blocks per CU of each variant
+  uint32_t* spill = nullptr;        // sized for cus * max(ext_occ) blocks
+  nrrs_tuning tune{};               // launch parameters of the traversal kernel
   // workspace
   uint8_t* ws = nullptr;
   uint64_t ws_bytes = 0, max_tris = 0;
@@ -128,7 +130,8 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
       c->qb_pool_bytes = k.off - start;
     }
   }
-  c->spill = k.take<uint32_t>((uint64_t)extend_spill_depth() * c->trace_blocks * extend_threads_per_block());
+  const uint64_t max_blocks = (uint64_t)c->cus * std::max(c->ext_occ[0], std::max(c->ext_occ[1], c->ext_occ[2]));
+  c->spill = k.take<uint32_t>((uint64_t)extend_spill_depth() * max_blocks * extend_threads_per_block());
   c->hit = k.take<float4>(C);
   c->vpos = k.take<float4>(C);
   c->vnrm = k.take<float4>(C);
@@ -241,7 +244,10 @@ RenderArgs base_args(nrrs_ctx* c) {
   a.budget_base = (double)c->nprim;
   a.dbg_parent = nullptr;
   a.spill = c->spill;
-  a.trace_blocks = c->trace_blocks;
+  a.trace_blocks = c->cus * c->tune.extend_blocks_per_cu;
+  a.ext_variant = c->tune.extend_variant;
+  a.ext_refill = c->tune.extend_refill;
+  a.ext_leaf_batch = c->tune.extend_leaf_batch;
   a.pass_state = c->pass_state;
   return a;
 }
@@ -307,7 +313,14 @@ int32_t nrrs_create(const nrrs_config* cfg, void* hip_stream, nrrs_ctx** out) {
   c->npx = npx;
   c->nprim = nprim;
   c->cap = cap;
-  c->trace_blocks = (uint32_t)prop.multiProcessorCount * extend_blocks_per_cu();
+  c->cus = (uint32_t)prop.multiProcessorCount;
+  c->ext_occ[0] = extend_blocks_per_cu(0);
+  c->ext_occ[1] = extend_blocks_per_cu(1);
+  c->ext_occ[2] = extend_blocks_per_cu(2);
+  c->tune.extend_variant = 1;
+  c->tune.extend_blocks_per_cu = c->ext_occ[1];
+  c->tune.extend_refill = 16;
+  c->tune.extend_leaf_batch = 32;
   warm_mfma_launch_cache();
   *out = c;
   return NRRS_OK;
@@ -382,7 +395,7 @@ int32_t nrrs_upload_scene(nrrs_ctx* c, const float* verts, uint64_t nv, const ui
   BvhOut bvh;
   build_bvh(verts, tris, nt, bvh);
   if (bvh.n_nodes > c->max_tris + 2) return fail(c, NRRS_ENOMEM, "BVH larger than reserved");
-  if (bvh.max_depth > 62) return fail(c, NRRS_EINVAL, "BVH deeper than the traversal stack");
+  if (bvh.max_depth > kMaxBvhDepth) return fail(c, NRRS_EINVAL, "BVH deeper than the traversal stack");
   // triangles in BVH order: (v0, original index), (e1, material), (e2, 0)
   std::vector<float> tri(12 * nt);
   float amin[3] = {INFINITY, INFINITY, INFINITY}, amax[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -466,6 +479,27 @@ int32_t nrrs_set_launch_mode(nrrs_ctx* c, int32_t mode) {
 int32_t nrrs_set_timing(nrrs_ctx* c, int32_t enabled) {
   if (!c) return NRRS_EINVAL;
   c->timing = enabled != 0;
+  return NRRS_OK;
+}
+
+int32_t nrrs_get_tuning(const nrrs_ctx* c, nrrs_tuning* out) {
+  if (!c || !out) return NRRS_EINVAL;
+  *out = c->tune;
+  for (int v = 0; v < 3; ++v) out->extend_max_blocks_per_cu[v] = c->ext_occ[v];
+  return NRRS_OK;
+}
+
+int32_t nrrs_set_tuning(nrrs_ctx* c, const nrrs_tuning* t) {
+  if (!c || !t) return NRRS_EINVAL;
+  if (t->extend_variant > 2 || t->extend_blocks_per_cu < 1 ||
+      t->extend_blocks_per_cu > c->ext_occ[t->extend_variant] || t->extend_refill < 1 || t->extend_refill > 64 ||
+      t->extend_leaf_batch < 1 || t->extend_leaf_batch > 64)
+    return fail(c, NRRS_EINVAL, "tuning out of range (blocks per CU up to the variant's occupancy, lanes 1..64)");
+  c->tune.extend_variant = t->extend_variant;
+  c->tune.extend_blocks_per_cu = t->extend_blocks_per_cu;
+  c->tune.extend_refill = t->extend_refill;
+  c->tune.extend_leaf_batch = t->extend_leaf_batch;
+  c->drop_graphs();  // captured passes hold the old grid and thresholds
   return NRRS_OK;
 }
 
@@ -637,6 +671,98 @@ int32_t nrrs_reset_image(nrrs_ctx* c) {
   launch_set_f64(c->alpha, 1.0, c->stream);
   c->spp_total = 0;
   HIPC(c, hipGetLastError());
+  return NRRS_OK;
+}
+
+int32_t nrrs_autotune(nrrs_ctx* c, uint32_t max_depth, nrrs_tuning* best, nrrs_tuning* tried, uint32_t tried_cap,
+                      uint32_t* n_tried) {
+  if (!c) return NRRS_EINVAL;
+  if (!c->scene) return fail(c, NRRS_ESTATE, "upload a scene first");
+  if (max_depth < 1 || max_depth > NRRS_MAX_DEPTH) return fail(c, NRRS_EINVAL, "max_depth out of range");
+  const bool timing = c->timing;
+  const double p_train = c->cfg.p_train;
+  c->timing = true;
+  c->cfg.p_train = 0.0;  // the timing passes capture no training records
+  // one candidate: the faster of two single-pass renders, by the traversal stage's event time
+  auto measure = [&](const nrrs_tuning& t, float* ms) -> int32_t {
+    int32_t r = nrrs_set_tuning(c, &t);
+    if (r != NRRS_OK) return r;
+    float m = INFINITY;
+    for (int rep = 0; rep < 2; ++rep) {
+      nrrs_render_stats st;
+      r = nrrs_render(c, c->cfg.s_batch, max_depth, NRRS_MODE_HEURISTIC, &st);
+      if (r != NRRS_OK) return r;
+      m = std::fmin(m, (float)st.stage_ms[1]);
+    }
+    *ms = m;
+    return NRRS_OK;
+  };
+  nrrs_tuning cur = c->tune, win = c->tune;
+  float win_ms = INFINITY;
+  int32_t r = NRRS_OK;
+  uint32_t count = 0;
+  auto consider = [&](const nrrs_tuning& t) {
+    float ms = 0.0f;
+    if (r != NRRS_OK) return;
+    r = measure(t, &ms);
+    if (r != NRRS_OK) return;
+    if (tried && count < tried_cap) {
+      tried[count] = t;
+      for (int v = 0; v < 3; ++v) tried[count].extend_max_blocks_per_cu[v] = c->ext_occ[v];
+      tried[count].extend_ms = ms;
+    }
+    ++count;
+    if (ms < win_ms) {
+      win_ms = ms;
+      win = t;
+    }
+  };
+  // 1: variant x refill threshold at full occupancy; 2: fewer resident blocks per CU;
+  // 3: leaf batch (variants that park leaves)
+  for (uint32_t v = 0; v < 3; ++v) {
+    for (uint32_t refill : {16u, 32u, 48u, 64u}) {
+      nrrs_tuning t = cur;
+      t.extend_variant = v;
+      t.extend_blocks_per_cu = c->ext_occ[v];
+      t.extend_refill = refill;
+      consider(t);
+    }
+  }
+  {
+    const uint32_t occ = c->ext_occ[win.extend_variant];
+    const uint32_t b1 = std::max(1u, (3 * occ) / 4), b2 = std::max(1u, occ / 2);
+    const nrrs_tuning base = win;
+    for (uint32_t bpc : {b1, b2}) {
+      if (bpc == occ) continue;
+      nrrs_tuning t = base;
+      t.extend_blocks_per_cu = bpc;
+      consider(t);
+      if (b2 == b1) break;
+    }
+  }
+  if (win.extend_variant != 0) {
+    const nrrs_tuning base = win;
+    for (uint32_t lb : {8u, 16u, 48u, 64u}) {
+      nrrs_tuning t = base;
+      t.extend_leaf_batch = lb;
+      consider(t);
+    }
+  }
+  c->timing = timing;
+  c->cfg.p_train = p_train;
+  if (r != NRRS_OK) {
+    nrrs_set_tuning(c, &cur);
+    return r;
+  }
+  r = nrrs_set_tuning(c, &win);
+  if (r != NRRS_OK) return r;
+  r = nrrs_reset_image(c);
+  if (r != NRRS_OK) return r;
+  if (best) {
+    nrrs_get_tuning(c, best);
+    best->extend_ms = win_ms;
+  }
+  if (n_tried) *n_tried = count;
   return NRRS_OK;
 }
 

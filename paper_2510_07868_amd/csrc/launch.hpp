@@ -16,6 +16,8 @@ struct PassState {
 };
 
 // Everything the per-depth kernels read about the render in progress.
+constexpr int kMaxBvhDepth = 62;  // deepest BVH level the traversal stack is sized for
+
 struct RenderArgs {
   DevScene sc;
   Queue qin, qout;
@@ -43,7 +45,10 @@ struct RenderArgs {
   double budget_base;   // N_px of Eq. (10): primary paths of the pass
   uint32_t* dbg_parent; // when set, the expansion also writes each child's parent index
   uint32_t* spill;      // traversal stack spill area [spill depth][trace_blocks * threads]
-  uint32_t trace_blocks;
+  uint32_t trace_blocks;  // persistent traversal grid (blocks)
+  uint32_t ext_variant;   // 0: leaves intersected at once, 1: leaves parked and batched per wave
+  uint32_t ext_refill;    // idle lanes (1..64) at which a traversal wave fetches new rays
+  uint32_t ext_leaf_batch;  // parked leaves (1..64) at which a wave intersects them (variant 1)
   PassState* pass_state;  // pass index and samples per pixel so far (advanced on the device)
 };
 
@@ -65,7 +70,7 @@ void launch_accumulate_stats(const DepthCtl* ctl, uint32_t max_depth, unsigned l
                              unsigned long long* s_sum, unsigned long long* r_sum, double* sumq_last,
                              double* f_last, hipStream_t s);
 
-uint32_t extend_blocks_per_cu();
+uint32_t extend_blocks_per_cu(uint32_t variant);
 uint32_t extend_threads_per_block();
 uint32_t extend_spill_depth();
 

@@ -19,8 +19,12 @@ namespace {
 constexpr int kEntryThreads = 256;
 constexpr int kTraceThreads = 128;
 constexpr int kLdsStack = 16;     // stack entries per lane kept in LDS
-constexpr int kStackMax = 64;     // total stack entries per lane (the builder keeps the BVH shallower)
-constexpr int kRefillLanes = 16;  // a wave fetches new rays once this many lanes are idle
+constexpr int kStackMax = 96;     // total stack entries per lane
+// Modes 0 and 1 push at most one entry per tree level (depth <= kMaxBvhDepth).  Mode 2 also
+// parks extra leaf links, but only while fewer than kLeafPushLimit entries are stacked, so
+// the stack never exceeds kLeafPushLimit + 3 + kMaxBvhDepth <= kStackMax entries.
+constexpr int kLeafPushLimit = kStackMax - 3 - kMaxBvhDepth;
+static_assert(kLeafPushLimit > 0, "traversal stack too small");
 constexpr uint32_t kLeafBit = 0x80000000u;
 
 __device__ __forceinline__ uint32_t bits(float f) { return __float_as_uint(f); }
@@ -76,9 +80,13 @@ struct HitState {
 };
 
 // Moller-Trumbore with inclusive edges; closest t > tmin wins, equal t goes to the smaller
-// original triangle index.
+// original triangle index.  A division-free test with a relative margin of 1e-5 first rejects
+// triangles that the exact test (barycentrics and t from the reciprocal of the determinant)
+// would reject too; only the rest pay for the division, so the results are those of the exact
+// test alone.
 __device__ __forceinline__ void test_leaf(const DevScene& sc, uint32_t link, V3 o, V3 d, uint32_t excl,
                                           HitState& h, uint32_t& tris) {
+  constexpr float kMargin = 1e-5f;
   const uint32_t first = (link >> 3) & 0x0fffffffu;
   const uint32_t count = (link & 7u) + 1u;
   tris += count;
@@ -88,12 +96,20 @@ __device__ __forceinline__ void test_leaf(const DevScene& sc, uint32_t link, V3 
     const V3 e1 = xyz(a1), e2 = xyz(a2);
     const V3 p = cross(d, e2);
     const float det = dot(e1, p);
-    if (det == 0.0f) continue;
-    const float inv = 1.0f / det;
     const V3 s = o - xyz(a0);
+    const V3 qv = cross(s, e1);
+    // sign-normalized numerators: b1 = u / |det|, b2 = v / |det|, t = w / |det|
+    const float ad = fabsf(det);
+    const float u = copysignf(1.0f, det) * dot(s, p);
+    const float v = copysignf(1.0f, det) * dot(d, qv);
+    const float w = copysignf(1.0f, det) * dot(e2, qv);
+    const float lim = ad * (1.0f + kMargin), neg = -kMargin * ad;
+    if (ad == 0.0f || u < neg || u > lim || v < neg || u + v > lim || (w <= 0.0f && sc.tmin >= 0.0f) ||
+        w > lim * h.t)
+      continue;
+    const float inv = 1.0f / det;
     const float b1 = dot(s, p) * inv;
     if (b1 < 0.0f || b1 > 1.0f) continue;
-    const V3 qv = cross(s, e1);
     const float b2 = dot(d, qv) * inv;
     if (b2 < 0.0f || b1 + b2 > 1.0f) continue;
     const float t = dot(e2, qv) * inv;
@@ -108,13 +124,38 @@ __device__ __forceinline__ void test_leaf(const DevScene& sc, uint32_t link, V3 
   }
 }
 
-// Persistent BVH2 traversal.  Each lane holds one ray and advances it one node per loop
-// iteration (near child first); when a quarter of a wave's lanes are idle the wave takes a
-// new batch of queue entries from a per-depth counter with one atomic, so long rays do
-// not hold a whole wave idle.  The traversal stack keeps its top kLdsStack entries in LDS
-// ([depth][lane] layout: no bank conflicts) and deeper entries in a global spill area.
+// Traversal stack of one lane: the top kLdsStack entries in LDS ([depth][lane] layout: no bank
+// conflicts), deeper entries in a global spill area (entry k at spill[k * gthreads]).
+struct LaneStack {
+  uint32_t (*lds)[kTraceThreads];
+  uint32_t* spill;
+  uint32_t gthreads;
+  int tid, sp;
+  __device__ void push(uint32_t v) {
+    if (sp < kLdsStack) lds[sp][tid] = v;
+    else if (sp < kStackMax) spill[(uint64_t)(sp - kLdsStack) * gthreads] = v;
+    sp = min(sp + 1, kStackMax);
+  }
+  __device__ uint32_t pop() {
+    --sp;
+    return sp < kLdsStack ? lds[sp][tid] : spill[(uint64_t)(sp - kLdsStack) * gthreads];
+  }
+};
+
+constexpr uint32_t kNoNode = 0xFFFFFFFFu;
+
+// Persistent BVH2 traversal.  Each lane holds one ray; when a.ext_refill lanes of a wave are
+// idle the wave takes a new batch of queue entries from a per-depth counter with one atomic,
+// so long rays do not hold a whole wave idle.
+//   kMode 0: a lane intersects the triangles of a hit leaf child at once.
+//   kMode 1: a lane that reaches a leaf parks it and waits; the wave intersects the parked
+//     leaves together once a.ext_leaf_batch lanes hold one or no lane still looks for one, so
+//     the triangle loop runs with most lanes busy (leaf links share the stack).
+//   kMode 2: as 1, but a lane with a parked leaf keeps descending (further leaves go on the
+//     stack) while others still look for theirs.
+template <int kMode>
 __global__ __launch_bounds__(kTraceThreads) void k_extend(RenderArgs a) {
-  __shared__ uint32_t stack[kLdsStack][kTraceThreads];
+  __shared__ uint32_t stack_lds[kLdsStack][kTraceThreads];
   __shared__ unsigned long long cnt[3];  // rays traced, nodes visited, triangles tested
   const int tid = threadIdx.x;
   if (tid < 3) cnt[tid] = 0;
@@ -122,18 +163,18 @@ __global__ __launch_bounds__(kTraceThreads) void k_extend(RenderArgs a) {
   const DevScene& sc = a.sc;
   const uint32_t n = a.ctl[a.depth].n;
   uint32_t* work = &a.ctl[a.depth].work;
-  const uint32_t gthreads = gridDim.x * kTraceThreads;
-  uint32_t* spill = a.spill + blockIdx.x * kTraceThreads + tid;  // entry k at spill[k * gthreads]
+  LaneStack st{stack_lds, a.spill + blockIdx.x * kTraceThreads + tid, gridDim.x * kTraceThreads, tid, 0};
+  const int refill = (int)a.ext_refill;
+  const int leaf_batch = (int)a.ext_leaf_batch;
   bool active = false, exhausted = false;
-  uint32_t ray = 0, excl = 0, ni = 0;
-  int sp = 0;
+  uint32_t ray = 0, excl = 0, ni = 0, pend = 0;
   V3 o = v3(0, 0, 0), d = o, inv = o, oi = o;
   HitState h;
   uint32_t c_rays = 0, c_nodes = 0, c_tris = 0;
   for (;;) {
     if (!exhausted) {
       const uint64_t idle = __ballot(!active);
-      if (idle != 0 && (__popcll(idle) >= kRefillLanes || idle == __ballot(true))) {
+      if (idle != 0 && (__popcll(idle) >= refill || idle == __ballot(true))) {
         const int leader = __ffsll((unsigned long long)idle) - 1;
         uint32_t base = 0;
         if ((int)__lane_id() == leader) base = atomicAdd(work, (uint32_t)__popcll(idle));
@@ -160,7 +201,8 @@ __global__ __launch_bounds__(kTraceThreads) void k_extend(RenderArgs a) {
               h.prim = kMiss;
               h.orig = kMiss;
               ni = 0;
-              sp = 0;
+              pend = 0;
+              st.sp = 0;
               ray = my;
               active = true;
               ++c_rays;
@@ -173,39 +215,90 @@ __global__ __launch_bounds__(kTraceThreads) void k_extend(RenderArgs a) {
       if (exhausted) break;
       continue;
     }
-    if (!active) continue;
-    // one node: test both child boxes, intersect leaf children, descend or pop
-    ++c_nodes;
-    const float4 n0 = sc.node[4 * ni], n1 = sc.node[4 * ni + 1], n2 = sc.node[4 * ni + 2], n3 = sc.node[4 * ni + 3];
-    float tn0, tn1;
-    bool h0 = slab(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, inv, oi, h.t, tn0);
-    bool h1 = slab(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, inv, oi, h.t, tn1);
-    const uint32_t l0 = bits(n3.x), l1 = bits(n3.y);
-    if (h0 && (l0 & kLeafBit)) {
-      test_leaf(sc, l0, o, d, excl, h, c_tris);
-      h0 = false;
-    }
-    if (h1 && (l1 & kLeafBit)) {
-      test_leaf(sc, l1, o, d, excl, h, c_tris);
-      h1 = false;
-    }
-    if (h0 && h1) {
-      const bool first0 = tn0 <= tn1;
-      const uint32_t far = first0 ? l1 : l0;
-      if (sp < kLdsStack) stack[sp][tid] = far;
-      else if (sp < kStackMax) spill[(uint64_t)(sp - kLdsStack) * gthreads] = far;
-      sp = min(sp + 1, kStackMax);
-      ni = first0 ? l0 : l1;
-    } else if (h0) {
-      ni = l0;
-    } else if (h1) {
-      ni = l1;
-    } else if (sp > 0) {
-      --sp;
-      ni = sp < kLdsStack ? stack[sp][tid] : spill[(uint64_t)(sp - kLdsStack) * gthreads];
+    if constexpr (kMode == 0) {
+      if (!active) continue;
+      // one node: test both child boxes, intersect leaf children, descend or pop
+      ++c_nodes;
+      const float4 n0 = sc.node[4 * ni], n1 = sc.node[4 * ni + 1], n2 = sc.node[4 * ni + 2], n3 = sc.node[4 * ni + 3];
+      float tn0, tn1;
+      bool h0 = slab(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, inv, oi, h.t, tn0);
+      bool h1 = slab(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, inv, oi, h.t, tn1);
+      const uint32_t l0 = bits(n3.x), l1 = bits(n3.y);
+      if (h0 && (l0 & kLeafBit)) {
+        test_leaf(sc, l0, o, d, excl, h, c_tris);
+        h0 = false;
+      }
+      if (h1 && (l1 & kLeafBit)) {
+        test_leaf(sc, l1, o, d, excl, h, c_tris);
+        h1 = false;
+      }
+      if (h0 && h1) {
+        const bool first0 = tn0 <= tn1;
+        st.push(first0 ? l1 : l0);
+        ni = first0 ? l0 : l1;
+      } else if (h0) {
+        ni = l0;
+      } else if (h1) {
+        ni = l1;
+      } else if (st.sp > 0) {
+        ni = st.pop();
+      } else {
+        a.hit[ray] = make_float4(h.t, h.b1, h.b2, __uint_as_float(h.prim));
+        active = false;
+      }
     } else {
-      a.hit[ray] = make_float4(h.t, h.b1, h.b2, __uint_as_float(h.prim));
-      active = false;
+      if (active && ni != kNoNode && (kMode == 2 || pend == 0)) {
+        ++c_nodes;
+        const float4 n0 = sc.node[4 * ni], n1 = sc.node[4 * ni + 1], n2 = sc.node[4 * ni + 2],
+                     n3 = sc.node[4 * ni + 3];
+        float tn0, tn1;
+        const bool h0 = slab(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, inv, oi, h.t, tn0);
+        const bool h1 = slab(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, inv, oi, h.t, tn1);
+        const uint32_t l0 = bits(n3.x), l1 = bits(n3.y);
+        const bool first0 = tn0 <= tn1;
+        const bool f0 = h0 && (l0 & kLeafBit), f1 = h1 && (l1 & kLeafBit);
+        const bool i0 = h0 && !(l0 & kLeafBit), i1 = h1 && !(l1 & kLeafBit);
+        // leaves: the nearer one is parked if the lane has none, the others wait on the stack;
+        // a nearly full stack (possible only in mode 2) intersects them at once instead
+        if (f0 || f1) {
+          const uint32_t lnear = (f0 && (first0 || !f1)) ? l0 : l1;
+          const uint32_t lfar = (f0 && f1) ? (first0 ? l1 : l0) : 0u;
+          if (kMode == 2 && st.sp > kLeafPushLimit) {
+            if (lfar) test_leaf(sc, lfar, o, d, excl, h, c_tris);
+            test_leaf(sc, lnear, o, d, excl, h, c_tris);
+          } else {
+            if (lfar) st.push(lfar);
+            if (pend == 0) pend = lnear;
+            else st.push(lnear);
+          }
+        }
+        if (i0 && i1) {
+          ni = first0 ? l0 : l1;
+          st.push(first0 ? l1 : l0);
+        } else {
+          ni = i0 ? l0 : (i1 ? l1 : kNoNode);
+        }
+      }
+      if (active && ni == kNoNode && pend == 0) {
+        if (st.sp > 0) {
+          const uint32_t e = st.pop();
+          if (e & kLeafBit) pend = e;
+          else ni = e;
+        } else {
+          a.hit[ray] = make_float4(h.t, h.b1, h.b2, __uint_as_float(h.prim));
+          active = false;
+        }
+      }
+      const uint64_t parked = __ballot(active && pend != 0);
+      if (parked != 0) {
+        const uint64_t seeking = __ballot(active && pend == 0);
+        if (seeking == 0 || __popcll(parked) >= leaf_batch) {
+          if (active && pend != 0) {
+            test_leaf(sc, pend, o, d, excl, h, c_tris);
+            pend = 0;
+          }
+        }
+      }
     }
   }
   atomicAdd(&cnt[0], (unsigned long long)c_rays);
@@ -643,11 +736,20 @@ void launch_camera(const RenderArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_camera, dim3(blocks_for(a.nprim, kEntryThreads)), dim3(kEntryThreads), 0, s, a);
 }
 void launch_extend(const RenderArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_extend, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
+  if (a.ext_variant == 2)
+    hipLaunchKernelGGL(k_extend<2>, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
+  else if (a.ext_variant == 1)
+    hipLaunchKernelGGL(k_extend<1>, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_extend<0>, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
 }
-uint32_t extend_blocks_per_cu() {
+uint32_t extend_blocks_per_cu(uint32_t variant) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend, kTraceThreads, 0) != hipSuccess || nb < 1) nb = 1;
+  hipError_t e;
+  if (variant == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<2>, kTraceThreads, 0);
+  else if (variant == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<1>, kTraceThreads, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<0>, kTraceThreads, 0);
+  if (e != hipSuccess || nb < 1) nb = 1;
   return (uint32_t)nb;
 }
 uint32_t extend_threads_per_block() { return kTraceThreads; }

@@ -26,12 +26,26 @@ STAGES = ["camera", "extend", "shade", "network", "sum_q", "roulette_scan", "exp
 
 EXPORTS = [
     "nrrs_create", "nrrs_workspace_size", "nrrs_bind_workspace", "nrrs_upload_scene", "nrrs_render",
-    "nrrs_set_timing", "nrrs_set_launch_mode", "nrrs_train_step", "nrrs_read_image", "nrrs_reset_image", "nrrs_set_guide", "nrrs_get_guide",
+    "nrrs_set_timing", "nrrs_set_launch_mode", "nrrs_get_tuning", "nrrs_set_tuning", "nrrs_autotune",
+    "nrrs_train_step", "nrrs_read_image", "nrrs_reset_image", "nrrs_set_guide", "nrrs_get_guide",
     "nrrs_get_params", "nrrs_set_params", "nrrs_read_records", "nrrs_debug_rrs_expand",
     "nrrs_debug_load_records", "nrrs_debug_read_queue", "nrrs_debug_trace",
     "nrrs_debug_philox", "nrrs_debug_mlp_forward", "nrrs_debug_mlp_grad", "nrrs_status_string",
     "nrrs_last_error", "nrrs_destroy",
 ]
+
+
+class Tuning(C.Structure):
+    _fields_ = [
+        ("extend_variant", C.c_uint32), ("extend_blocks_per_cu", C.c_uint32), ("extend_refill", C.c_uint32),
+        ("extend_leaf_batch", C.c_uint32), ("extend_max_blocks_per_cu", C.c_uint32 * 3), ("extend_ms", C.c_float),
+    ]
+
+    def as_dict(self):
+        return {"extend_variant": self.extend_variant, "extend_blocks_per_cu": self.extend_blocks_per_cu,
+                "extend_refill": self.extend_refill, "extend_leaf_batch": self.extend_leaf_batch,
+                "extend_max_blocks_per_cu": list(self.extend_max_blocks_per_cu),
+                "extend_ms": round(float(self.extend_ms), 4)}
 
 
 class Config(C.Structure):
@@ -84,6 +98,9 @@ def load():
         "nrrs_render": [P, U32, U32, I32, P],
         "nrrs_set_timing": [P, I32],
         "nrrs_set_launch_mode": [P, I32],
+        "nrrs_get_tuning": [P, P],
+        "nrrs_set_tuning": [P, P],
+        "nrrs_autotune": [P, U32, P, P, U32, P],
         "nrrs_train_step": [P, U32, U32, C.c_float, P],
         "nrrs_read_image": [P, P, P],
         "nrrs_reset_image": [P],
@@ -203,6 +220,26 @@ class Renderer:
 
     def set_timing(self, enabled=True):
         self._check(self.L.nrrs_set_timing(self.h, 1 if enabled else 0))
+
+    def get_tuning(self):
+        t = Tuning()
+        self._check(self.L.nrrs_get_tuning(self.h, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, extend_variant, extend_blocks_per_cu, extend_refill, extend_leaf_batch, **_):
+        t = Tuning(extend_variant, extend_blocks_per_cu, extend_refill, extend_leaf_batch)
+        self._check(self.L.nrrs_set_tuning(self.h, C.byref(t)))
+
+    def autotune(self, max_depth, with_table=False):
+        """Time the traversal kernel's launch candidates on the uploaded scene and keep the fastest
+        (clears the accumulated image).  with_table: also return every candidate with its time."""
+        t = Tuning()
+        tried = (Tuning * 64)()
+        n = C.c_uint32()
+        self._check(self.L.nrrs_autotune(self.h, max_depth, C.byref(t), tried, 64, C.byref(n)))
+        if with_table:
+            return t.as_dict(), [tried[k].as_dict() for k in range(min(n.value, 64))]
+        return t.as_dict()
 
     def read_image(self):
         img = np.zeros(self.width * self.height * 3)

@@ -119,6 +119,7 @@ def test_rrs_expand_bit_exact(O, nrrs_mod, scenes, n, kind):
 
 # ----------------------------------------------------------------------------- traversal
 def test_closest_hit_matches_oracle(O, nrrs_mod, scenes):
+    # every traversal variant and launch shape the autotuner may pick gives the oracle's hits
     for sc_fn, n in ((scenes.cornell, 50000), (scenes.heightfield, 100000)):
         sc = sc_fn()
         r = make(nrrs_mod, sc, 512, 512)   # scratch for 1e5 rays
@@ -131,14 +132,44 @@ def test_closest_hit_matches_oracle(O, nrrs_mod, scenes):
         d = rng.normal(size=(n, 3))
         d /= np.linalg.norm(d, axis=1, keepdims=True)
         rays32 = np.concatenate([o, d], 1).astype(np.float32)
-        gp, gt, _, _ = r.debug_trace(rays32)
         op, ot, _, _, frag = O.trace(osc, rays32.astype(np.float64), None, tau=1e-4, with_fragile=True)
         ok = ~frag
         assert ok.mean() > 0.95
-        assert np.array_equal(gp[ok], op[ok])
         hit = ok & (op != O.MISS)
         assert hit.sum() > n // 10
-        assert np.allclose(gt[hit], ot[hit], rtol=1e-5, atol=1e-6)
+        occ = r.get_tuning()["extend_max_blocks_per_cu"]
+        for variant, bpc, refill, batch in ((0, occ[0], 16, 32), (1, occ[1], 16, 32), (1, 1, 8, 1),
+                                            (1, max(1, occ[1] // 2), 64, 64), (0, 1, 1, 1), (2, occ[2], 32, 16),
+                                            (2, 1, 1, 64), (2, max(1, occ[2] // 2), 64, 1)):
+            r.set_tuning(variant, bpc, refill, batch)
+            gp, gt, _, _ = r.debug_trace(rays32)
+            assert np.array_equal(gp[ok], op[ok]), (variant, bpc, refill, batch)
+            assert np.allclose(gt[hit], ot[hit], rtol=1e-5, atol=1e-6)
+
+
+def test_autotune_picks_a_valid_launch_and_keeps_results(O, nrrs_mod, scenes):
+    sc = scenes.cornell()
+    r = make(nrrs_mod, sc, 64, 64, s_batch=4)
+    t0 = r.get_tuning()
+    with pytest.raises(RuntimeError):
+        r.set_tuning(3, 1, 16, 32)
+    with pytest.raises(RuntimeError):
+        r.set_tuning(0, t0["extend_max_blocks_per_cu"][0] + 1, 16, 32)
+    with pytest.raises(RuntimeError):
+        r.set_tuning(1, 1, 0, 32)
+    assert r.get_tuning() == t0
+    best = r.autotune(8)
+    assert best["extend_variant"] in (0, 1, 2)
+    assert 1 <= best["extend_blocks_per_cu"] <= best["extend_max_blocks_per_cu"][best["extend_variant"]]
+    assert best["extend_ms"] > 0
+    assert r.read_image()[1] == 0                # the timing passes leave no samples behind
+    # the whole bounce loop under the chosen launch: the furnace stays exact
+    f = make(nrrs_mod, scenes.furnace(), 32, 32, s_batch=2)
+    f.autotune(8)
+    f.render(4, 8, nrrs_mod.MODE_HEURISTIC)
+    img, spp = f.read_image()
+    assert spp == 4
+    assert np.allclose(img, furnace_value(8), rtol=1e-5, atol=0)
 
 
 # ----------------------------------------------------------------------------- images
