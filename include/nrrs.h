@@ -194,6 +194,8 @@ typedef struct nrrs_tuning {
   uint32_t extend_blocks_per_cu;  /* 1 .. extend_max_blocks_per_cu[variant] */
   uint32_t extend_refill;         /* idle lanes of a wave (1..64) that make it fetch new rays */
   uint32_t extend_leaf_batch;     /* parked leaves (1..64) that trigger intersection (1, 2) */
+  uint32_t extend_chunk;          /* queue entries a wave claims per atomic (0: exactly what its
+                                   * idle lanes need; else at least this many, up to 4096) */
   uint32_t extend_max_blocks_per_cu[3]; /* out: occupancy limit of each variant (ignored by set) */
   float extend_ms;                /* out (nrrs_autotune): traversal time of the winner's pass */
 } nrrs_tuning;
@@ -206,8 +208,8 @@ int32_t nrrs_get_tuning(const nrrs_ctx* ctx, nrrs_tuning* out);
 int32_t nrrs_set_tuning(nrrs_ctx* ctx, const nrrs_tuning* tuning);
 
 /* Autotuner: times the traversal kernel of one heuristic-RRS pass of depth max_depth on the
- * uploaded scene for each candidate (variant x blocks per CU, then the refill threshold, then
- * the leaf batch) with HIP events, keeps the fastest and returns it in *best (may be NULL).
+ * uploaded scene for each candidate (variant x refill threshold, then fewer blocks per CU,
+ * then the claim chunk, then the leaf batch) with HIP events, keeps the fastest and returns it in *best (may be NULL).
  * The first min(tried_cap, candidates) candidates with their times are written to tried
  * (caller-owned host array, may be NULL) and the candidate count to *n_tried (may be NULL).
  * The timing passes accumulate into the image, which is then cleared as by nrrs_reset_image;

@@ -248,6 +248,7 @@ RenderArgs base_args(nrrs_ctx* c) {
   a.ext_variant = c->tune.extend_variant;
   a.ext_refill = c->tune.extend_refill;
   a.ext_leaf_batch = c->tune.extend_leaf_batch;
+  a.ext_chunk = c->tune.extend_chunk;
   a.pass_state = c->pass_state;
   return a;
 }
@@ -321,6 +322,7 @@ int32_t nrrs_create(const nrrs_config* cfg, void* hip_stream, nrrs_ctx** out) {
   c->tune.extend_blocks_per_cu = c->ext_occ[1];
   c->tune.extend_refill = 16;
   c->tune.extend_leaf_batch = 32;
+  c->tune.extend_chunk = 0;
   warm_mfma_launch_cache();
   *out = c;
   return NRRS_OK;
@@ -493,12 +495,14 @@ int32_t nrrs_set_tuning(nrrs_ctx* c, const nrrs_tuning* t) {
   if (!c || !t) return NRRS_EINVAL;
   if (t->extend_variant > 2 || t->extend_blocks_per_cu < 1 ||
       t->extend_blocks_per_cu > c->ext_occ[t->extend_variant] || t->extend_refill < 1 || t->extend_refill > 64 ||
-      t->extend_leaf_batch < 1 || t->extend_leaf_batch > 64)
-    return fail(c, NRRS_EINVAL, "tuning out of range (blocks per CU up to the variant's occupancy, lanes 1..64)");
+      t->extend_leaf_batch < 1 || t->extend_leaf_batch > 64 || t->extend_chunk > 4096)
+    return fail(c, NRRS_EINVAL,
+                "tuning out of range (blocks per CU up to the variant's occupancy, lanes 1..64, chunk <= 4096)");
   c->tune.extend_variant = t->extend_variant;
   c->tune.extend_blocks_per_cu = t->extend_blocks_per_cu;
   c->tune.extend_refill = t->extend_refill;
   c->tune.extend_leaf_batch = t->extend_leaf_batch;
+  c->tune.extend_chunk = t->extend_chunk;
   c->drop_graphs();  // captured passes hold the old grid and thresholds
   return NRRS_OK;
 }
@@ -738,6 +742,14 @@ int32_t nrrs_autotune(nrrs_ctx* c, uint32_t max_depth, nrrs_tuning* best, nrrs_t
       t.extend_blocks_per_cu = bpc;
       consider(t);
       if (b2 == b1) break;
+    }
+  }
+  {
+    const nrrs_tuning base = win;
+    for (uint32_t ch : {64u, 128u, 256u}) {
+      nrrs_tuning t = base;
+      t.extend_chunk = ch;
+      consider(t);
     }
   }
   if (win.extend_variant != 0) {

@@ -48,7 +48,8 @@ struct RenderArgs {
   uint32_t trace_blocks;  // persistent traversal grid (blocks)
   uint32_t ext_variant;   // 0: leaves intersected at once, 1: leaves parked and batched per wave
   uint32_t ext_refill;    // idle lanes (1..64) at which a traversal wave fetches new rays
-  uint32_t ext_leaf_batch;  // parked leaves (1..64) at which a wave intersects them (variant 1)
+  uint32_t ext_leaf_batch;  // parked leaves (1..64) at which a wave intersects them (variants 1, 2)
+  uint32_t ext_chunk;     // queue entries a traversal wave claims at once (0: just what it needs)
   PassState* pass_state;  // pass index and samples per pixel so far (advanced on the device)
 };
 

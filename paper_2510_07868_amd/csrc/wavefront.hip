@@ -166,8 +166,13 @@ __global__ __launch_bounds__(kTraceThreads) void k_extend(RenderArgs a) {
   LaneStack st{stack_lds, a.spill + blockIdx.x * kTraceThreads + tid, gridDim.x * kTraceThreads, tid, 0};
   const int refill = (int)a.ext_refill;
   const int leaf_batch = (int)a.ext_leaf_batch;
+  const uint32_t chunk = a.ext_chunk;
   bool active = false, exhausted = false;
   uint32_t ray = 0, excl = 0, ni = 0, pend = 0;
+  // wave-uniform pool of claimed queue entries not yet handed to a lane, [pool_next, pool_end);
+  // `drained` once a claim has reached the end of the queue
+  uint32_t pool_next = 0, pool_end = 0;
+  bool drained = false;
   V3 o = v3(0, 0, 0), d = o, inv = o, oi = o;
   HitState h;
   uint32_t c_rays = 0, c_nodes = 0, c_tris = 0;
@@ -175,38 +180,50 @@ __global__ __launch_bounds__(kTraceThreads) void k_extend(RenderArgs a) {
     if (!exhausted) {
       const uint64_t idle = __ballot(!active);
       if (idle != 0 && (__popcll(idle) >= refill || idle == __ballot(true))) {
-        const int leader = __ffsll((unsigned long long)idle) - 1;
-        uint32_t base = 0;
-        if ((int)__lane_id() == leader) base = atomicAdd(work, (uint32_t)__popcll(idle));
-        base = __shfl(base, leader);
-        if ((uint64_t)base + __popcll(idle) >= n) exhausted = true;
-        if (!active) {
-          const uint32_t my = base + lanes_below(idle);
-          if (my < n) {
-            const float4 th = a.qin.thr[my];
-            if (bits(th.w) & kFlagDead) {
-              a.hit[my] = make_float4(__builtin_inff(), 0.0f, 0.0f, __uint_as_float(kMiss));
-            } else {
-              const float4 og = a.qin.orig[my], dr = a.qin.dir[my];
-              o = xyz(og);
-              d = xyz(dr);
-              excl = bits(og.w);
-              const V3 dd = v3(fabsf(d.x) > 1e-20f ? d.x : copysignf(1e-20f, d.x),
-                               fabsf(d.y) > 1e-20f ? d.y : copysignf(1e-20f, d.y),
-                               fabsf(d.z) > 1e-20f ? d.z : copysignf(1e-20f, d.z));
-              inv = v3(1.0f / dd.x, 1.0f / dd.y, 1.0f / dd.z);
-              oi = v3(-o.x * inv.x, -o.y * inv.y, -o.z * inv.z);
-              h.t = __builtin_inff();
-              h.b1 = h.b2 = 0.0f;
-              h.prim = kMiss;
-              h.orig = kMiss;
-              ni = 0;
-              pend = 0;
-              st.sp = 0;
-              ray = my;
-              active = true;
-              ++c_rays;
-            }
+        const uint32_t want = (uint32_t)__popcll(idle);
+        const uint32_t rank = lanes_below(idle);  // this lane's rank among the idle lanes
+        const uint32_t have = pool_end - pool_next;
+        uint32_t my = rank < have ? pool_next + rank : 0xFFFFFFFFu;
+        if (have < want && !drained) {
+          // claim what the idle lanes still need, or a whole chunk of entries
+          const uint32_t take = max(chunk, want - have);
+          const int leader = __ffsll((unsigned long long)idle) - 1;
+          uint32_t b = 0;
+          if ((int)__lane_id() == leader) b = atomicAdd(work, take);
+          const uint32_t fresh = __shfl(b, leader);
+          const uint64_t end = (uint64_t)fresh + take;
+          drained = end >= n;
+          if (rank >= have) my = fresh + (rank - have);
+          pool_end = (uint32_t)(end < n ? end : (uint64_t)n);
+          pool_next = min(fresh + (want - have), pool_end);
+        } else {
+          pool_next += min(want, have);
+        }
+        exhausted = drained && pool_next >= pool_end;
+        if (!active && my < n) {
+          // ray data loaded together (one round trip), dead entries only write a miss
+          const float4 th = a.qin.thr[my], og = a.qin.orig[my], dr = a.qin.dir[my];
+          if (bits(th.w) & kFlagDead) {
+            a.hit[my] = make_float4(__builtin_inff(), 0.0f, 0.0f, __uint_as_float(kMiss));
+          } else {
+            o = xyz(og);
+            d = xyz(dr);
+            excl = bits(og.w);
+            const V3 dd = v3(fabsf(d.x) > 1e-20f ? d.x : copysignf(1e-20f, d.x),
+                             fabsf(d.y) > 1e-20f ? d.y : copysignf(1e-20f, d.y),
+                             fabsf(d.z) > 1e-20f ? d.z : copysignf(1e-20f, d.z));
+            inv = v3(1.0f / dd.x, 1.0f / dd.y, 1.0f / dd.z);
+            oi = v3(-o.x * inv.x, -o.y * inv.y, -o.z * inv.z);
+            h.t = __builtin_inff();
+            h.b1 = h.b2 = 0.0f;
+            h.prim = kMiss;
+            h.orig = kMiss;
+            ni = 0;
+            pend = 0;
+            st.sp = 0;
+            ray = my;
+            active = true;
+            ++c_rays;
           }
         }
       }

@@ -38,12 +38,14 @@ EXPORTS = [
 class Tuning(C.Structure):
     _fields_ = [
         ("extend_variant", C.c_uint32), ("extend_blocks_per_cu", C.c_uint32), ("extend_refill", C.c_uint32),
-        ("extend_leaf_batch", C.c_uint32), ("extend_max_blocks_per_cu", C.c_uint32 * 3), ("extend_ms", C.c_float),
+        ("extend_leaf_batch", C.c_uint32), ("extend_chunk", C.c_uint32),
+        ("extend_max_blocks_per_cu", C.c_uint32 * 3), ("extend_ms", C.c_float),
     ]
 
     def as_dict(self):
         return {"extend_variant": self.extend_variant, "extend_blocks_per_cu": self.extend_blocks_per_cu,
                 "extend_refill": self.extend_refill, "extend_leaf_batch": self.extend_leaf_batch,
+                "extend_chunk": self.extend_chunk,
                 "extend_max_blocks_per_cu": list(self.extend_max_blocks_per_cu),
                 "extend_ms": round(float(self.extend_ms), 4)}
 
@@ -226,8 +228,8 @@ class Renderer:
         self._check(self.L.nrrs_get_tuning(self.h, C.byref(t)))
         return t.as_dict()
 
-    def set_tuning(self, extend_variant, extend_blocks_per_cu, extend_refill, extend_leaf_batch, **_):
-        t = Tuning(extend_variant, extend_blocks_per_cu, extend_refill, extend_leaf_batch)
+    def set_tuning(self, extend_variant, extend_blocks_per_cu, extend_refill, extend_leaf_batch, extend_chunk=0, **_):
+        t = Tuning(extend_variant, extend_blocks_per_cu, extend_refill, extend_leaf_batch, extend_chunk)
         self._check(self.L.nrrs_set_tuning(self.h, C.byref(t)))
 
     def autotune(self, max_depth, with_table=False):

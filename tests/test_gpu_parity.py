@@ -138,12 +138,13 @@ def test_closest_hit_matches_oracle(O, nrrs_mod, scenes):
         hit = ok & (op != O.MISS)
         assert hit.sum() > n // 10
         occ = r.get_tuning()["extend_max_blocks_per_cu"]
-        for variant, bpc, refill, batch in ((0, occ[0], 16, 32), (1, occ[1], 16, 32), (1, 1, 8, 1),
-                                            (1, max(1, occ[1] // 2), 64, 64), (0, 1, 1, 1), (2, occ[2], 32, 16),
-                                            (2, 1, 1, 64), (2, max(1, occ[2] // 2), 64, 1)):
-            r.set_tuning(variant, bpc, refill, batch)
+        for variant, bpc, refill, batch, chunk in (
+                (0, occ[0], 16, 32, 0), (1, occ[1], 16, 32, 64), (1, 1, 8, 1, 0), (1, max(1, occ[1] // 2), 64, 64, 4096),
+                (0, 1, 1, 1, 1), (2, occ[2], 32, 16, 256), (2, 1, 1, 64, 0), (2, max(1, occ[2] // 2), 64, 1, 100),
+                (0, occ[0], 32, 32, 4096)):
+            r.set_tuning(variant, bpc, refill, batch, chunk)
             gp, gt, _, _ = r.debug_trace(rays32)
-            assert np.array_equal(gp[ok], op[ok]), (variant, bpc, refill, batch)
+            assert np.array_equal(gp[ok], op[ok]), (variant, bpc, refill, batch, chunk)
             assert np.allclose(gt[hit], ot[hit], rtol=1e-5, atol=1e-6)
 
 
@@ -157,6 +158,8 @@ def test_autotune_picks_a_valid_launch_and_keeps_results(O, nrrs_mod, scenes):
         r.set_tuning(0, t0["extend_max_blocks_per_cu"][0] + 1, 16, 32)
     with pytest.raises(RuntimeError):
         r.set_tuning(1, 1, 0, 32)
+    with pytest.raises(RuntimeError):
+        r.set_tuning(1, 1, 16, 32, 4097)
     assert r.get_tuning() == t0
     best = r.autotune(8)
     assert best["extend_variant"] in (0, 1, 2)
