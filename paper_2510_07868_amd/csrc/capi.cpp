@@ -171,7 +171,7 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
   c->fp8 = k.take<uint8_t>(packed_fp8_bytes());
   c->fp8_scale = k.take<float>(4);
   const uint64_t gb = mlp_grad_blocks(kMaxMinibatch);
-  c->grad_partial = k.take<float>(gb * kNParam);
+  c->grad_partial = k.take<float>(mlp_grad_scratch_floats(kMaxMinibatch));
   c->loss_partial = k.take<float>(gb);
   c->loss_accum = k.take<float>(1);
   return (k.off + 255) & ~uint64_t(255);

@@ -106,5 +106,6 @@ void launch_rrsnet_mfma(const RenderArgs& a, const NetArgs& n, hipStream_t s);
 void launch_rows_mfma(const float* x, uint32_t n, const NetArgs& net, float* y, float* z, hipStream_t s);
 void warm_mfma_launch_cache();  // occupancy queries done before any stream capture
 uint32_t mlp_grad_blocks(uint32_t n);
+uint32_t mlp_grad_scratch_floats(uint32_t max_rows);  // partials + reduction groups
 
 }  // namespace nrrs

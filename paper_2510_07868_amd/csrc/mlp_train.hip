@@ -1,0 +1,348 @@
+// Training gradient of the RRS network on the gfx950 FP32 matrix cores (v_mfma_f32_32x32x2_f32):
+// forward, loss, backward and the weight gradients of one minibatch (Sec. 5 "Training"),
+// with the statistic loss of Eq. (15) (relative L2, prediction in the denominator held
+// constant) or the squared error of log radiance.
+//
+// Layout.  A wave owns 32 rows and keeps every activation "units x rows": in the 32x32 MFMA
+// accumulator, lane l holds row l % 32 and 16 units per 32-unit tile, unit
+// 8 (v / 4) + 4 (l / 32) + v % 4 of register v.  A layer's output registers are the next
+// product's B operand unchanged: the K order of that product follows the same unit order,
+// and the weights are read from LDS in that order.  The weight gradients (K = rows) need units
+// along the lanes instead, so deltas and activations go through a padded LDS transpose.  The
+// four waves of a block add their gradients into one LDS copy in a fixed order, and the block
+// writes it as one partial; partials are summed in a fixed order, so results are
+// deterministic.
+#include <algorithm>
+
+#include "launch.hpp"
+
+namespace nrrs {
+
+namespace {
+
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int kTWaves = 4;
+constexpr int kTThreads = 64 * kTWaves;
+constexpr int kTRows = 32 * kTWaves;     // rows per block
+constexpr int kS1 = 21, kS2 = 65, kST = 33;  // padded LDS row strides (distinct banks per lane)
+constexpr int kRedGroups = 16;           // first-level groups of the partial-gradient sum
+
+// LDS carve (floats)
+constexpr int kOffW1 = 0;                         // W1 [64][kS1]
+constexpr int kOffW2 = kOffW1 + 64 * kS1;         // W2 [64][kS2]
+constexpr int kOffW3 = kOffW2 + 64 * kS2;         // W3 [64][kS2]
+constexpr int kOffB = kOffW3 + 64 * kS2;          // b1, b2, b3, w4 [64 each], b4
+constexpr int kOffScratch = kOffB + 4 * 64 + 4;   // per wave: X [32][kS1], D [64][kST], H [64][kST]
+constexpr int kWaveScratch = 32 * kS1 + 2 * 64 * kST;
+constexpr int kOffG = kOffScratch + kTWaves * kWaveScratch;  // block gradient [kNParam]
+constexpr int kOffRow = kOffG + kNParam + 3;                 // per-row loss and dz [2][kTRows]
+constexpr int kLdsFloats = kOffRow + 2 * kTRows;
+
+__device__ __forceinline__ float softplus_mod(float z) { return z < 0.0f ? log1pf(expf(z)) : 0.5f * z + 0.69314718055994531f; }
+__device__ __forceinline__ float softplus_mod_grad(float z) { return z < 0.0f ? 1.0f / (1.0f + expf(-z)) : 0.5f; }
+
+// hidden unit held by register v of tile t in lane half h
+__device__ __forceinline__ int unit_of(int t, int v, int h) { return 32 * t + 8 * (v >> 2) + 4 * h + (v & 3); }
+
+__device__ __forceinline__ f32x16 mfma(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// out = W x (units x rows) for a 64-unit input held as registers in[32] (tile-major), weights
+// W[o][i] at Ws[o * ld + i]; `transposed` reads W[i][o] instead (the backward product W^T d).
+__device__ __forceinline__ void layer64(const float* Ws, int ld, bool transposed, const float (&in)[32], int h,
+                                        int c, f32x16 (&acc)[2]) {
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    f32x16 r = {};
+#pragma unroll
+    for (int s = 0; s < 32; ++s) {
+      const int k = unit_of(s >> 4, s & 15, h);
+      const int o = 32 * t + c;
+      const float a = transposed ? Ws[k * ld + o] : Ws[o * ld + k];
+      r = mfma(a, in[s], r);
+    }
+    acc[t] = r;
+  }
+}
+
+// Gradient tile block dW[o][i] = sum_r D[o][r] H[i][r] for o in 64 units, i in `ni` tiles of 32
+// (D, H in LDS as [unit][kST]), added into the block gradient G[o * ldg + i] wave by wave.
+template <int kNi>
+__device__ __forceinline__ void weight_grad(const float* D, const float* H, int h, int c, f32x16 (&g)[2][2]) {
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < kNi; ++nt) {
+      f32x16 r = {};
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const int rr = 2 * s + h;
+        r = mfma(D[(32 * mt + c) * kST + rr], H[(32 * nt + c) * kST + rr], r);
+      }
+      g[mt][nt] = r;
+    }
+}
+
+__global__ __launch_bounds__(kTThreads) void k_mlp_grad_mfma(const float* x, const float* target,
+                                                            const uint32_t* index, uint32_t n, uint32_t n_total,
+                                                            const float* master, int32_t loss_kind,
+                                                            float* grad_partial, float* loss_partial) {
+  extern __shared__ float lds[];
+  float* W1s = lds + kOffW1;
+  float* W2s = lds + kOffW2;
+  float* W3s = lds + kOffW3;
+  float* Bs = lds + kOffB;  // b1 [0,64), b2 [64,128), b3 [128,192), w4 [192,256), b4 [256]
+  float* G = lds + kOffG;
+  float* RowLoss = lds + kOffRow;
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, h = l >> 5, c = l & 31;
+  for (int k = tid; k < 1280; k += kTThreads) W1s[(k / 20) * kS1 + k % 20] = master[kW1 + k];
+  for (int k = tid; k < 4096; k += kTThreads) {
+    W2s[(k >> 6) * kS2 + (k & 63)] = master[kW2 + k];
+    W3s[(k >> 6) * kS2 + (k & 63)] = master[kW3 + k];
+  }
+  for (int k = tid; k < 64; k += kTThreads) {
+    Bs[k] = master[kB1 + k];
+    Bs[64 + k] = master[kB2 + k];
+    Bs[128 + k] = master[kB3 + k];
+    Bs[192 + k] = master[kW4 + k];
+  }
+  if (tid == 0) Bs[256] = master[kB4];
+  for (int k = tid; k < kNParam; k += kTThreads) G[k] = 0.0f;
+  float* Xs = lds + kOffScratch + wave * kWaveScratch;  // [32 rows][kS1]
+  float* Ds = Xs + 32 * kS1;                            // [64 units][kST]
+  float* Hs = Ds + 64 * kST;                            // [64 units][kST]
+  const uint32_t row = blockIdx.x * kTRows + wave * 32 + c;
+  const bool valid = row < n;
+  const uint32_t src = valid ? (index ? index[row] : row) : 0u;
+  float xf[10];
+#pragma unroll
+  for (int s = 0; s < 10; ++s) {
+    xf[s] = valid ? x[20ull * src + 2 * s + h] : 0.0f;
+    Xs[c * kS1 + 2 * s + h] = xf[s];
+  }
+  __syncthreads();
+
+  // ---- forward: H1, H2 (post-ReLU), H3
+  f32x16 acc[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    f32x16 r = {};
+#pragma unroll
+    for (int s = 0; s < 10; ++s) r = mfma(W1s[(32 * t + c) * kS1 + 2 * s + h], xf[s], r);
+    acc[t] = r;
+  }
+  float H1[32], H2[32], H3[32];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) H1[16 * t + v] = fmaxf(acc[t][v] + Bs[unit_of(t, v, h)], 0.0f);
+  layer64(W2s, kS2, false, H1, h, c, acc);
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) H2[16 * t + v] = fmaxf(acc[t][v] + Bs[64 + unit_of(t, v, h)], 0.0f);
+  layer64(W3s, kS2, false, H2, h, c, acc);
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) H3[16 * t + v] = fmaxf(acc[t][v] + Bs[128 + unit_of(t, v, h)], 0.0f);
+
+  // ---- output, loss, dL/dz per row
+  float zp = 0.0f;
+#pragma unroll
+  for (int s = 0; s < 32; ++s) zp = fmaf(Bs[192 + unit_of(s >> 4, s & 15, h)], H3[s], zp);
+  const float z = zp + __shfl_xor(zp, 32) + Bs[256];
+  float dz = 0.0f, ls = 0.0f;
+  if (valid) {
+    const float y = softplus_mod(z);
+    const float L = target[src];
+    float dy;
+    if (loss_kind == 1) {  // squared error of log radiance
+      const float diff = logf(y + 0.01f) - logf(L + 0.01f);
+      ls = diff * diff;
+      dy = 2.0f * diff / (y + 0.01f);
+    } else {               // relative L2 with the prediction held constant in the denominator
+      const float den = y * y + 0.01f;
+      const float diff = y - L;
+      ls = diff * diff / den;
+      dy = 2.0f * diff / den;
+    }
+    dz = dy / (float)n_total * softplus_mod_grad(z);
+  }
+  if (h == 0) {
+    RowLoss[wave * 32 + c] = ls;
+    RowLoss[kTRows + wave * 32 + c] = dz;
+  }
+
+  // ---- layer 3 delta, output-layer gradients (dW4 = sum_r dz H3, db4 = sum_r dz)
+  float D[32];
+#pragma unroll
+  for (int s = 0; s < 32; ++s) {
+    const int u = unit_of(s >> 4, s & 15, h);
+    D[s] = H3[s] > 0.0f ? dz * Bs[192 + u] : 0.0f;
+    Hs[u * kST + c] = H3[s] * dz;
+    Ds[u * kST + c] = D[s];
+  }
+  __syncthreads();
+  // lane u sums its unit over the wave's 32 rows: dW4[u], db3[u]
+  float gw4 = 0.0f, gb3 = 0.0f, gb4 = 0.0f;
+  for (int r = 0; r < 32; ++r) {
+    gw4 += Hs[l * kST + r];
+    gb3 += Ds[l * kST + r];
+    gb4 += RowLoss[kTRows + wave * 32 + r];
+  }
+  __syncthreads();
+  // dW3 = D3 H2^T
+#pragma unroll
+  for (int s = 0; s < 32; ++s) Hs[unit_of(s >> 4, s & 15, h) * kST + c] = H2[s];
+  __syncthreads();
+  f32x16 g[2][2];
+  weight_grad<2>(Ds, Hs, h, c, g);
+  // D2 = (W3^T D3) * relu'(H2)
+  layer64(W3s, kS2, true, D, h, c, acc);
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) D[16 * t + v] = H2[16 * t + v] > 0.0f ? acc[t][v] : 0.0f;
+  // block sum of this wave's dW3, db3, dW4, db4 (waves in order)
+  for (int w = 0; w < kTWaves; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) G[kW3 + 64 * unit_of(mt, v, h) + 32 * nt + c] += g[mt][nt][v];
+      G[kB3 + l] += gb3;
+      G[kW4 + l] += gw4;
+      if (l == 0) G[kB4] += gb4;
+    }
+    __syncthreads();
+  }
+  // ---- layer 2: dW2 = D2 H1^T, db2, D1 = (W2^T D2) * relu'(H1)
+#pragma unroll
+  for (int s = 0; s < 32; ++s) {
+    const int u = unit_of(s >> 4, s & 15, h);
+    Ds[u * kST + c] = D[s];
+    Hs[u * kST + c] = H1[s];
+  }
+  __syncthreads();
+  float gb2 = 0.0f;
+  for (int r = 0; r < 32; ++r) gb2 += Ds[l * kST + r];
+  weight_grad<2>(Ds, Hs, h, c, g);
+  layer64(W2s, kS2, true, D, h, c, acc);
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) D[16 * t + v] = H1[16 * t + v] > 0.0f ? acc[t][v] : 0.0f;
+  for (int w = 0; w < kTWaves; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) G[kW2 + 64 * unit_of(mt, v, h) + 32 * nt + c] += g[mt][nt][v];
+      G[kB2 + l] += gb2;
+    }
+    __syncthreads();
+  }
+  // ---- layer 1: dW1 = D1 X^T (20 inputs in one 32-wide tile), db1
+#pragma unroll
+  for (int s = 0; s < 32; ++s) Ds[unit_of(s >> 4, s & 15, h) * kST + c] = D[s];
+  __syncthreads();
+  float gb1 = 0.0f;
+  for (int r = 0; r < 32; ++r) gb1 += Ds[l * kST + r];
+  f32x16 g1[2];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    f32x16 r = {};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int rr = 2 * s + h;
+      r = mfma(Ds[(32 * mt + c) * kST + rr], c < 20 ? Xs[rr * kS1 + c] : 0.0f, r);
+    }
+    g1[mt] = r;
+  }
+  for (int w = 0; w < kTWaves; ++w) {
+    if (wave == w) {
+      if (c < 20) {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) G[kW1 + 20 * unit_of(mt, v, h) + c] += g1[mt][v];
+      }
+      G[kB1 + l] += gb1;
+    }
+    __syncthreads();
+  }
+  float* gp = grad_partial + (uint64_t)blockIdx.x * kNParam;
+  for (int k = tid; k < kNParam; k += kTThreads) gp[k] = G[k];
+  if (tid == 0) {
+    float sum = 0.0f;
+    for (int r = 0; r < kTRows; ++r) sum += RowLoss[r];
+    loss_partial[blockIdx.x] = sum;
+  }
+}
+
+// Partial gradients summed in two fixed-order levels: kRedGroups groups of consecutive
+// partials, then the groups.
+__global__ void k_grad_reduce_groups(const float* gp, uint32_t nb, float* tmp) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (uint32_t)kNParam) return;
+  const uint32_t per = (nb + kRedGroups - 1) / kRedGroups;
+  const uint32_t b0 = blockIdx.y * per, b1 = min(nb, b0 + per);
+  float acc = 0.0f;
+  for (uint32_t b = b0; b < b1; ++b) acc += gp[(uint64_t)b * kNParam + k];
+  tmp[(uint64_t)blockIdx.y * kNParam + k] = acc;
+}
+
+__global__ void k_grad_reduce_final(const float* tmp, float* grad, const float* lp, uint32_t nb, float* loss_accum,
+                                    uint32_t n_rows_total) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < (uint32_t)kNParam) {
+    float acc = 0.0f;
+    for (int g = 0; g < kRedGroups; ++g) acc += tmp[(uint64_t)g * kNParam + k];
+    grad[k] = acc;
+  }
+  if (k == 0 && loss_accum) {
+    float s = 0.0f;
+    for (uint32_t b = 0; b < nb; ++b) s += lp[b];
+    *loss_accum += s / (float)n_rows_total;
+  }
+}
+
+}  // namespace
+
+uint32_t mlp_grad_blocks(uint32_t n) { return (n + kTRows - 1) / kTRows; }
+uint32_t mlp_grad_scratch_floats(uint32_t max_rows) {
+  return (mlp_grad_blocks(max_rows) + kRedGroups) * (uint32_t)kNParam;
+}
+
+void launch_mlp_grad(const float* x, const float* target, const uint32_t* index, uint32_t n, const float* master,
+                     int32_t loss_kind, float* grad_partial, float* loss_partial, uint32_t* nblocks_out,
+                     hipStream_t s) {
+  const uint32_t nb = mlp_grad_blocks(n);
+  *nblocks_out = nb;
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute((const void*)k_mlp_grad_mfma, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)(sizeof(float) * kLdsFloats));
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_mlp_grad_mfma, dim3(nb), dim3(kTThreads), sizeof(float) * kLdsFloats, s, x, target, index, n,
+                     n, master, loss_kind, grad_partial, loss_partial);
+}
+
+void launch_grad_reduce(const float* grad_partial, uint32_t nblocks, float* grad, const float* loss_partial,
+                        float* loss_accum, uint32_t n_rows_total, hipStream_t s) {
+  float* tmp = const_cast<float*>(grad_partial) + (uint64_t)nblocks * kNParam;
+  const uint32_t bx = (kNParam + 255) / 256;
+  hipLaunchKernelGGL(k_grad_reduce_groups, dim3(bx, kRedGroups), dim3(256), 0, s, grad_partial, nblocks, tmp);
+  hipLaunchKernelGGL(k_grad_reduce_final, dim3(bx), dim3(256), 0, s, tmp, grad, loss_partial, nblocks, loss_accum,
+                     n_rows_total);
+}
+
+}  // namespace nrrs
