@@ -26,6 +26,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "render efficiency 1/(relMSE·s) + Mpaths/s, NRRS vs plain norm. RRS, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X published FP32 vector peak
+OPS_PER_NODE = 52          # two slab tests: 12 FMA (24 FLOP) + 28 min/max/compare/scale
+OPS_PER_TRI = 56           # division-free Moller-Trumbore pre-test
 LUM = np.array([0.2126, 0.7152, 0.0722])
 
 
@@ -69,6 +72,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-eff", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help="traversal launch 'variant,blocks_per_cu,refill,leaf_batch,chunk' instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -101,7 +106,11 @@ def main():
     r.upload_scene(sc)
     t_upload = time.time() - t_scene
     t_tune = time.time()
-    if args.no_autotune:
+    if args.tuning:
+        v, b, rf, lb, ch = (int(t) for t in args.tuning.split(","))
+        r.set_tuning(v, b, rf, lb, ch)
+        tuning, table = r.get_tuning(), []
+    elif args.no_autotune:
         tuning, table = r.get_tuning(), []
     else:
         tuning, table = r.autotune(D, with_table=True)
@@ -144,19 +153,28 @@ def main():
     secs = t1 - t0
     mpaths = rays / secs / 1e6
 
-    # roofline of the dominant kernel (traversal): bytes the algorithm reads and writes per
-    # launch = 64 B of queue I/O per ray + 64 B per BVH node visited + 48 B per triangle tested
+    # roofline of the dominant kernel (traversal).  It is bound by vector-ALU issue (its BVH and
+    # triangles stay cache-resident: the counted HBM traffic is a small fraction of the bytes it
+    # reads), so it is measured in useful FP32 operations (FMA = 2): 52 per BVH node visited
+    # (two ray/box slab tests) and 56 per triangle tested (Moller-Trumbore division-free test).
     dom = max(nrrs.STAGES, key=lambda s: stage_ms[s])
     ext_launches = max(stage_n["extend"], 1)
     ext_ms = stage_ms["extend"] / ext_launches
+    ext_ops = (OPS_PER_NODE * nodes + OPS_PER_TRI * tris) / ext_launches
     ext_bytes = (64.0 * rays + 64.0 * nodes + 48.0 * tris) / ext_launches
-    achieved = ext_bytes / (ext_ms * 1e-3) / 1e9
     traffic = counted_traffic()
-    roofline = {"kernel": "k_extend", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic.get("k_extend"),
-                "avg_launch_ms": round(ext_ms, 4), "algorithmic_bytes_per_launch": int(ext_bytes),
+    v = tuning["extend_variant"]
+    ext_kernel = "k_extend_immediate" if v == 0 else f"k_extend<{v}>"
+    tb = traffic.get(ext_kernel)
+    achieved = ext_ops / (ext_ms * 1e-3) / 1e12
+    roofline = {"kernel": ext_kernel, "bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK, 4), "traffic": tb,
+                "avg_launch_ms": round(ext_ms, 4), "algorithmic_ops_per_launch": int(ext_ops),
+                "ops_per_node": OPS_PER_NODE, "ops_per_triangle": OPS_PER_TRI,
                 "nodes_per_ray": round(nodes / max(rays, 1), 2), "tris_per_ray": round(tris / max(rays, 1), 2),
                 "grays_per_s": round(rays / (stage_ms["extend"] * 1e-3) / 1e9, 3),
+                "node_and_triangle_bytes_gbs": round(ext_bytes / (ext_ms * 1e-3) / 1e9, 1),
+                "hbm_gbs_counted": round(tb / (ext_ms * 1e-3) / 1e9, 1) if tb else None,
                 "dominant_stage": dom}
 
     # the network stage: 19,072 useful FLOP per evaluated vertex (20-64-64-64-1)
@@ -191,7 +209,7 @@ def main():
         "roofline": roofline,
         "network": network,
         "queue_stages": queue,
-        "autotuned": None if args.no_autotune else tuning,
+        "autotuned": None if (args.no_autotune or args.tuning) else tuning,
     }
 
     if not args.no_eff:

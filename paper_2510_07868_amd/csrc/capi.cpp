@@ -42,7 +42,7 @@ struct nrrs_ctx {
   hipStream_t stream = nullptr;
   uint64_t npx = 0, nprim = 0, cap = 0;
   uint32_t cus = 0;                 // compute units of the device
-  uint32_t ext_occ[3] = {1, 1, 1};  // resident traversal blocks per CU of each variant
+  uint32_t ext_occ[4] = {1, 1, 1, 1};  // resident traversal blocks per CU of each variant
   uint32_t* spill = nullptr;        // sized for cus * max(ext_occ) blocks
   nrrs_tuning tune{};               // launch parameters of the traversal kernel
   // workspace
@@ -130,7 +130,7 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
       c->qb_pool_bytes = k.off - start;
     }
   }
-  const uint64_t max_blocks = (uint64_t)c->cus * std::max(c->ext_occ[0], std::max(c->ext_occ[1], c->ext_occ[2]));
+  const uint64_t max_blocks = (uint64_t)c->cus * *std::max_element(c->ext_occ, c->ext_occ + 4);
   c->spill = k.take<uint32_t>((uint64_t)extend_spill_depth() * max_blocks * extend_threads_per_block());
   c->hit = k.take<float4>(C);
   c->vpos = k.take<float4>(C);
@@ -315,9 +315,7 @@ int32_t nrrs_create(const nrrs_config* cfg, void* hip_stream, nrrs_ctx** out) {
   c->nprim = nprim;
   c->cap = cap;
   c->cus = (uint32_t)prop.multiProcessorCount;
-  c->ext_occ[0] = extend_blocks_per_cu(0);
-  c->ext_occ[1] = extend_blocks_per_cu(1);
-  c->ext_occ[2] = extend_blocks_per_cu(2);
+  for (uint32_t v = 0; v < 4; ++v) c->ext_occ[v] = extend_blocks_per_cu(v);
   c->tune.extend_variant = 1;
   c->tune.extend_blocks_per_cu = c->ext_occ[1];
   c->tune.extend_refill = 16;
@@ -487,13 +485,13 @@ int32_t nrrs_set_timing(nrrs_ctx* c, int32_t enabled) {
 int32_t nrrs_get_tuning(const nrrs_ctx* c, nrrs_tuning* out) {
   if (!c || !out) return NRRS_EINVAL;
   *out = c->tune;
-  for (int v = 0; v < 3; ++v) out->extend_max_blocks_per_cu[v] = c->ext_occ[v];
+  for (int v = 0; v < 4; ++v) out->extend_max_blocks_per_cu[v] = c->ext_occ[v];
   return NRRS_OK;
 }
 
 int32_t nrrs_set_tuning(nrrs_ctx* c, const nrrs_tuning* t) {
   if (!c || !t) return NRRS_EINVAL;
-  if (t->extend_variant > 2 || t->extend_blocks_per_cu < 1 ||
+  if (t->extend_variant > 3 || t->extend_blocks_per_cu < 1 ||
       t->extend_blocks_per_cu > c->ext_occ[t->extend_variant] || t->extend_refill < 1 || t->extend_refill > 64 ||
       t->extend_leaf_batch < 1 || t->extend_leaf_batch > 64 || t->extend_chunk > 4096)
     return fail(c, NRRS_EINVAL,
@@ -712,7 +710,7 @@ int32_t nrrs_autotune(nrrs_ctx* c, uint32_t max_depth, nrrs_tuning* best, nrrs_t
     if (r != NRRS_OK) return;
     if (tried && count < tried_cap) {
       tried[count] = t;
-      for (int v = 0; v < 3; ++v) tried[count].extend_max_blocks_per_cu[v] = c->ext_occ[v];
+      for (int v = 0; v < 4; ++v) tried[count].extend_max_blocks_per_cu[v] = c->ext_occ[v];
       tried[count].extend_ms = ms;
     }
     ++count;
@@ -723,7 +721,7 @@ int32_t nrrs_autotune(nrrs_ctx* c, uint32_t max_depth, nrrs_tuning* best, nrrs_t
   };
   // 1: variant x refill threshold at full occupancy; 2: fewer resident blocks per CU;
   // 3: leaf batch (variants that park leaves)
-  for (uint32_t v = 0; v < 3; ++v) {
+  for (uint32_t v = 0; v < 4; ++v) {
     for (uint32_t refill : {16u, 32u, 48u, 64u}) {
       nrrs_tuning t = cur;
       t.extend_variant = v;

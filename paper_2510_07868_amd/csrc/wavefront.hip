@@ -79,42 +79,51 @@ struct HitState {
   uint32_t prim, orig;
 };
 
-// Moller-Trumbore with inclusive edges; closest t > tmin wins, equal t goes to the smaller
-// original triangle index.  A division-free test with a relative margin of 1e-5 first rejects
+// Moller-Trumbore with inclusive edges of triangle k (BVH order) for a ray with current
+// closest distance ht.  A division-free test with a relative margin of 1e-5 first rejects
 // triangles that the exact test (barycentrics and t from the reciprocal of the determinant)
-// would reject too; only the rest pay for the division, so the results are those of the exact
-// test alone.
+// would reject too, or that lie beyond ht; only the rest pay for the division, so results are
+// those of the exact test alone.  Returns true with t, b1, b2 and the original index when the
+// ray hits the triangle at t > tmin.
+__device__ __forceinline__ bool test_tri(const DevScene& sc, uint32_t k, V3 o, V3 d, float ht, float& t, float& b1,
+                                         float& b2, uint32_t& og) {
+  constexpr float kMargin = 1e-5f;
+  const float4 a0 = sc.tri[3 * k], a1 = sc.tri[3 * k + 1], a2 = sc.tri[3 * k + 2];
+  const V3 e1 = xyz(a1), e2 = xyz(a2);
+  const V3 p = cross(d, e2);
+  const float det = dot(e1, p);
+  const V3 s = o - xyz(a0);
+  const V3 qv = cross(s, e1);
+  // sign-normalized numerators: b1 = u / |det|, b2 = v / |det|, t = w / |det|
+  const float ad = fabsf(det);
+  const float u = copysignf(1.0f, det) * dot(s, p);
+  const float v = copysignf(1.0f, det) * dot(d, qv);
+  const float w = copysignf(1.0f, det) * dot(e2, qv);
+  const float lim = ad * (1.0f + kMargin), neg = -kMargin * ad;
+  if (ad == 0.0f || u < neg || u > lim || v < neg || u + v > lim || (w <= 0.0f && sc.tmin >= 0.0f) || w > lim * ht)
+    return false;
+  const float inv = 1.0f / det;
+  b1 = dot(s, p) * inv;
+  if (b1 < 0.0f || b1 > 1.0f) return false;
+  b2 = dot(d, qv) * inv;
+  if (b2 < 0.0f || b1 + b2 > 1.0f) return false;
+  t = dot(e2, qv) * inv;
+  og = bits(a0.w);
+  return t > sc.tmin;
+}
+
+// All triangles of a leaf for one ray: closest t wins, equal t goes to the smaller original
+// triangle index.
 __device__ __forceinline__ void test_leaf(const DevScene& sc, uint32_t link, V3 o, V3 d, uint32_t excl,
                                           HitState& h, uint32_t& tris) {
-  constexpr float kMargin = 1e-5f;
   const uint32_t first = (link >> 3) & 0x0fffffffu;
   const uint32_t count = (link & 7u) + 1u;
   tris += count;
   for (uint32_t k = first; k < first + count; ++k) {
     if (k == excl) continue;
-    const float4 a0 = sc.tri[3 * k], a1 = sc.tri[3 * k + 1], a2 = sc.tri[3 * k + 2];
-    const V3 e1 = xyz(a1), e2 = xyz(a2);
-    const V3 p = cross(d, e2);
-    const float det = dot(e1, p);
-    const V3 s = o - xyz(a0);
-    const V3 qv = cross(s, e1);
-    // sign-normalized numerators: b1 = u / |det|, b2 = v / |det|, t = w / |det|
-    const float ad = fabsf(det);
-    const float u = copysignf(1.0f, det) * dot(s, p);
-    const float v = copysignf(1.0f, det) * dot(d, qv);
-    const float w = copysignf(1.0f, det) * dot(e2, qv);
-    const float lim = ad * (1.0f + kMargin), neg = -kMargin * ad;
-    if (ad == 0.0f || u < neg || u > lim || v < neg || u + v > lim || (w <= 0.0f && sc.tmin >= 0.0f) ||
-        w > lim * h.t)
-      continue;
-    const float inv = 1.0f / det;
-    const float b1 = dot(s, p) * inv;
-    if (b1 < 0.0f || b1 > 1.0f) continue;
-    const float b2 = dot(d, qv) * inv;
-    if (b2 < 0.0f || b1 + b2 > 1.0f) continue;
-    const float t = dot(e2, qv) * inv;
-    const uint32_t og = bits(a0.w);
-    if (t > sc.tmin && (t < h.t || (t == h.t && og < h.orig))) {
+    float t, b1, b2;
+    uint32_t og;
+    if (test_tri(sc, k, o, d, h.t, t, b1, b2, og) && (t < h.t || (t == h.t && og < h.orig))) {
       h.t = t;
       h.b1 = b1;
       h.b2 = b2;
@@ -122,6 +131,80 @@ __device__ __forceinline__ void test_leaf(const DevScene& sc, uint32_t link, V3 
       h.orig = og;
     }
   }
+}
+
+// Closest-hit order as one 64-bit key: t (positive float bits, order-preserving) then the
+// original triangle index.
+__device__ __forceinline__ unsigned long long hit_key(float t, uint32_t orig) {
+  return ((unsigned long long)__float_as_uint(t) << 32) | orig;
+}
+
+// The parked leaves of a wave, intersected triangle-parallel: the (lane, triangle) pairs are
+// numbered by an exclusive scan of the leaf sizes and every lane of the wave takes one pair
+// per round, reading the owner's ray through cross-lane shuffles.  Each owner's closest hit
+// is an LDS atomic minimum of hit keys; after each round the lane holding the current
+// minimum publishes triangle and barycentrics.  Same result as test_leaf on every owner.
+__device__ __forceinline__ void leaf_phase_shared(const DevScene& sc, bool mine, uint32_t link, V3 o, V3 d,
+                                                  uint32_t excl, HitState& h, uint32_t& tris,
+                                                  unsigned long long* key, float4* slot) {
+  const uint32_t lane = __lane_id();
+  const uint32_t cnt = mine ? (link & 7u) + 1u : 0u;
+  const uint32_t first = mine ? (link >> 3) & 0x0fffffffu : 0u;
+  uint32_t pre = 0, total = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const uint64_t m = __ballot((cnt >> b) & 1u);
+    pre += (uint32_t)lanes_below(m) << b;
+    total += (uint32_t)__popcll(m) << b;
+  }
+  tris += cnt;
+  const unsigned long long start = hit_key(h.t, h.orig);
+  if (mine) key[lane] = start;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (uint32_t base = 0; base < total; base += 64) {
+    const uint32_t p = base + lane;
+    // owner: the last lane whose first pair is <= p (lanes without pairs share the next prefix)
+    int own = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+      const int cand = own + step;
+      const uint32_t pc = (uint32_t)__shfl((int)pre, cand < 64 ? cand : 63);
+      if (cand < 64 && pc <= p) own = cand;
+    }
+    const uint32_t f_o = (uint32_t)__shfl((int)first, own), pre_o = (uint32_t)__shfl((int)pre, own);
+    const uint32_t ex_o = (uint32_t)__shfl((int)excl, own);
+    const V3 o_o = v3(__shfl(o.x, own), __shfl(o.y, own), __shfl(o.z, own));
+    const V3 d_o = v3(__shfl(d.x, own), __shfl(d.y, own), __shfl(d.z, own));
+    const float ht_o = __shfl(h.t, own);
+    float t = 0.0f, b1 = 0.0f, b2 = 0.0f;
+    uint32_t og = 0, k = 0;
+    bool hit = false;
+    if (p < total) {
+      k = f_o + (p - pre_o);
+      hit = k != ex_o && test_tri(sc, k, o_o, d_o, ht_o, t, b1, b2, og);
+    }
+    const unsigned long long ck = hit ? hit_key(t, og) : ~0ull;
+    if (hit) atomicMin(&key[own], ck);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (hit && key[own] == ck) slot[own] = make_float4(__uint_as_float(k), b1, b2, 0.0f);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (mine) {
+    const unsigned long long best = key[lane];
+    if (best != start) {
+      const float4 sl = slot[lane];
+      h.t = __uint_as_float((uint32_t)(best >> 32));
+      h.orig = (uint32_t)best;
+      h.prim = __float_as_uint(sl.x);
+      h.b1 = sl.y;
+      h.b2 = sl.z;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 // Traversal stack of one lane: the top kLdsStack entries in LDS ([depth][lane] layout: no bank
@@ -153,10 +236,14 @@ constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 //     the triangle loop runs with most lanes busy (leaf links share the stack).
 //   kMode 2: as 1, but a lane with a parked leaf keeps descending (further leaves go on the
 //     stack) while others still look for theirs.
+//   kMode 3: as 1, but the wave intersects the parked leaves triangle-parallel
+//     (leaf_phase_shared): all 64 lanes share the (ray, triangle) pairs.
 template <int kMode>
-__global__ __launch_bounds__(kTraceThreads) void k_extend(RenderArgs a) {
+__device__ __forceinline__ void extend_body(const RenderArgs& a) {
   __shared__ uint32_t stack_lds[kLdsStack][kTraceThreads];
   __shared__ unsigned long long cnt[3];  // rays traced, nodes visited, triangles tested
+  __shared__ unsigned long long hit_keys[kMode == 3 ? kTraceThreads : 1];
+  __shared__ float4 hit_slots[kMode == 3 ? kTraceThreads : 1];
   const int tid = threadIdx.x;
   if (tid < 3) cnt[tid] = 0;
   __syncthreads();
@@ -190,7 +277,7 @@ __global__ __launch_bounds__(kTraceThreads) void k_extend(RenderArgs a) {
           const int leader = __ffsll((unsigned long long)idle) - 1;
           uint32_t b = 0;
           if ((int)__lane_id() == leader) b = atomicAdd(work, take);
-          const uint32_t fresh = __shfl(b, leader);
+          const uint32_t fresh = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(b, leader));
           const uint64_t end = (uint64_t)fresh + take;
           drained = end >= n;
           if (rank >= have) my = fresh + (rank - have);
@@ -310,7 +397,12 @@ __global__ __launch_bounds__(kTraceThreads) void k_extend(RenderArgs a) {
       if (parked != 0) {
         const uint64_t seeking = __ballot(active && pend == 0);
         if (seeking == 0 || __popcll(parked) >= leaf_batch) {
-          if (active && pend != 0) {
+          if constexpr (kMode == 3) {
+            const int wbase = tid & ~63;
+            leaf_phase_shared(sc, active && pend != 0, pend, o, d, excl, h, c_tris, hit_keys + wbase,
+                              hit_slots + wbase);
+            if (active) pend = 0;
+          } else if (active && pend != 0) {
             test_leaf(sc, pend, o, d, excl, h, c_tris);
             pend = 0;
           }
@@ -324,6 +416,13 @@ __global__ __launch_bounds__(kTraceThreads) void k_extend(RenderArgs a) {
   __syncthreads();
   if (tid < 3 && cnt[tid]) atomicAdd(a.rays + tid, cnt[tid]);
 }
+
+// Variants that park leaves fit 72 VGPRs without spilling: 7 waves per SIMD.
+template <int kMode>
+__global__ __launch_bounds__(kTraceThreads) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_extend(RenderArgs a) {
+  extend_body<kMode>(a);
+}
+__global__ __launch_bounds__(kTraceThreads) void k_extend_immediate(RenderArgs a) { extend_body<0>(a); }
 
 // ------------------------------------------------------------------------------- shade
 __device__ __forceinline__ void emit(const RenderArgs& a, uint32_t pix, V3 t, V3 le, int4 rec) {
@@ -753,19 +852,22 @@ void launch_camera(const RenderArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_camera, dim3(blocks_for(a.nprim, kEntryThreads)), dim3(kEntryThreads), 0, s, a);
 }
 void launch_extend(const RenderArgs& a, hipStream_t s) {
-  if (a.ext_variant == 2)
+  if (a.ext_variant == 3)
+    hipLaunchKernelGGL(k_extend<3>, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
+  else if (a.ext_variant == 2)
     hipLaunchKernelGGL(k_extend<2>, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
   else if (a.ext_variant == 1)
     hipLaunchKernelGGL(k_extend<1>, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
   else
-    hipLaunchKernelGGL(k_extend<0>, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
+    hipLaunchKernelGGL(k_extend_immediate, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
 }
 uint32_t extend_blocks_per_cu(uint32_t variant) {
   int nb = 0;
   hipError_t e;
-  if (variant == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<2>, kTraceThreads, 0);
+  if (variant == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<3>, kTraceThreads, 0);
+  else if (variant == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<2>, kTraceThreads, 0);
   else if (variant == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<1>, kTraceThreads, 0);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<0>, kTraceThreads, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend_immediate, kTraceThreads, 0);
   if (e != hipSuccess || nb < 1) nb = 1;
   return (uint32_t)nb;
 }
