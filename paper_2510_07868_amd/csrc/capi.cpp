@@ -719,14 +719,15 @@ int32_t nrrs_autotune(nrrs_ctx* c, uint32_t max_depth, nrrs_tuning* best, nrrs_t
       win = t;
     }
   };
-  // 1: variant x refill threshold at full occupancy; 2: fewer resident blocks per CU;
-  // 3: leaf batch (variants that park leaves)
+  // 1: variant x refill threshold at full occupancy; 2: fewer resident blocks per CU; 3: claim
+  // chunk; 4: leaf batch (variants that park leaves)
   for (uint32_t v = 0; v < 4; ++v) {
     for (uint32_t refill : {16u, 32u, 48u, 64u}) {
       nrrs_tuning t = cur;
       t.extend_variant = v;
       t.extend_blocks_per_cu = c->ext_occ[v];
       t.extend_refill = refill;
+      t.extend_chunk = 0;
       consider(t);
     }
   }
@@ -752,7 +753,8 @@ int32_t nrrs_autotune(nrrs_ctx* c, uint32_t max_depth, nrrs_tuning* best, nrrs_t
   }
   if (win.extend_variant != 0) {
     const nrrs_tuning base = win;
-    for (uint32_t lb : {8u, 16u, 48u, 64u}) {
+    for (uint32_t lb : {8u, 16u, 32u, 48u}) {
+      if (lb == base.extend_leaf_batch) continue;
       nrrs_tuning t = base;
       t.extend_leaf_batch = lb;
       consider(t);
