@@ -191,13 +191,15 @@ typedef struct nrrs_tuning {
                                    * the leaf it reaches and waits, the wave intersects parked
                                    * leaves together; 2: as 1, but lanes with a parked leaf keep
                                    * descending meanwhile; 3: as 1, with the parked leaves'
-                                   * triangles shared out over all lanes of the wave */
+                                   * triangles shared out over all lanes of the wave; 4: as 3
+                                   * over the 4-wide tree (EINVAL if the scene's 4-wide tree
+                                   * is deeper than 30 levels) */
   uint32_t extend_blocks_per_cu;  /* 1 .. extend_max_blocks_per_cu[variant] */
   uint32_t extend_refill;         /* idle lanes of a wave (1..64) that make it fetch new rays */
-  uint32_t extend_leaf_batch;     /* parked leaves (1..64) that trigger intersection (1-3) */
+  uint32_t extend_leaf_batch;     /* parked leaves (1..64) that trigger intersection (1-4) */
   uint32_t extend_chunk;          /* queue entries a wave claims per atomic (0: exactly what its
                                    * idle lanes need; else at least this many, up to 4096) */
-  uint32_t extend_max_blocks_per_cu[4]; /* out: occupancy limit of each variant (ignored by set) */
+  uint32_t extend_max_blocks_per_cu[5]; /* out: occupancy limit of each variant (ignored by set) */
   float extend_ms;                /* out (nrrs_autotune): traversal time of the winner's pass */
 } nrrs_tuning;
 

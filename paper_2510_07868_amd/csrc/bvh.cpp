@@ -201,7 +201,90 @@ int build_bvh(const float* verts, const uint32_t* tris, uint64_t nt, BvhOut& out
     f[14] = 0.0f;
     f[15] = 0.0f;
   }
+  collapse_bvh4(out);
   return 0;
+}
+
+namespace {
+
+struct Child4 {
+  float lo[3], hi[3];
+  uint32_t link;  // BVH2 leaf link, or a BVH2 node index while collapsing
+  double area() const {
+    const double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+    return dx >= 0.0 ? 2.0 * (dx * dy + dy * dz + dz * dx) : 0.0;
+  }
+};
+
+struct Collapser {
+  const std::vector<float>* n2;
+  std::vector<float>* n4;
+  int max_depth = 0;
+
+  Child4 child_of(uint32_t node2, int c) const {
+    const float* f = &(*n2)[16ull * node2];
+    Child4 ch;
+    for (int k = 0; k < 3; ++k) {
+      ch.lo[k] = f[6 * c + k];
+      ch.hi[k] = f[6 * c + 3 + k];
+    }
+    std::memcpy(&ch.link, &f[12 + c], 4);
+    return ch;
+  }
+
+  // Builds the 4-wide node for BVH2 node `node2`; returns its index.
+  uint32_t build(uint32_t node2, int depth) {
+    if (depth > max_depth) max_depth = depth;
+    Child4 ch[4];
+    int m = 2;
+    ch[0] = child_of(node2, 0);
+    ch[1] = child_of(node2, 1);
+    while (m < 4) {
+      int best = -1;
+      double best_area = -1.0;
+      for (int k = 0; k < m; ++k)
+        if (!(ch[k].link & 0x80000000u) && ch[k].area() > best_area) {
+          best_area = ch[k].area();
+          best = k;
+        }
+      if (best < 0) break;
+      const uint32_t open = ch[best].link;
+      ch[best] = child_of(open, 0);
+      ch[m++] = child_of(open, 1);
+    }
+    const uint32_t id = (uint32_t)(n4->size() / 32);
+    n4->resize(n4->size() + 32, 0.0f);
+    uint32_t links[4];
+    for (int k = 0; k < 4; ++k) {
+      if (k >= m) {
+        links[k] = kEmptyChild4;
+        continue;
+      }
+      links[k] = (ch[k].link & 0x80000000u) ? ch[k].link : build(ch[k].link, depth + 1);
+    }
+    float* f = &(*n4)[32ull * id];
+    for (int k = 0; k < 4; ++k) {
+      const bool used = k < m;
+      for (int a = 0; a < 3; ++a) {
+        f[8 * a + k] = used ? ch[k].lo[a] : 0.0f;      // lo of axis a
+        f[8 * a + 4 + k] = used ? ch[k].hi[a] : 0.0f;  // hi of axis a
+      }
+      std::memcpy(&f[24 + k], &links[k], 4);
+      f[28 + k] = 0.0f;
+    }
+    return id;
+  }
+};
+
+}  // namespace
+
+void collapse_bvh4(BvhOut& out) {
+  out.nodes4.clear();
+  out.nodes4.reserve(out.nodes.size());
+  Collapser c{&out.nodes, &out.nodes4};
+  c.build(0, 0);
+  out.n_nodes4 = out.nodes4.size() / 32;
+  out.max_depth4 = c.max_depth + 1;
 }
 
 }  // namespace nrrs

@@ -4,6 +4,8 @@
 
 #include <vector>
 
+#include "bvh_layout.hpp"
+
 namespace nrrs {
 
 struct BvhOut {
@@ -11,10 +13,20 @@ struct BvhOut {
   std::vector<uint32_t> order;   // BVH position -> original triangle index
   uint64_t n_nodes = 0;
   int max_depth = 0;             // levels from the root to the deepest leaf
+  // The same tree collapsed to 4 children per node: 32 floats per node, child-major per
+  // component: lo.x[4], hi.x[4], lo.y[4], hi.y[4], lo.z[4], hi.z[4], link[4], unused[4].
+  std::vector<float> nodes4;
+  uint64_t n_nodes4 = 0;
+  int max_depth4 = 0;
 };
+
 
 // Child link: bit 31 set = leaf with first = (link >> 3) & 0x0fffffff and count = (link & 7) + 1
 // triangles in BVH order; otherwise the index of an internal node.  Node 0 is the root.
 int build_bvh(const float* verts, const uint32_t* tris, uint64_t nt, BvhOut& out);
+
+// Collapses out.nodes (BVH2) into out.nodes4: each 4-wide node takes the two children of a
+// BVH2 node and repeatedly opens its largest-area inner child until it has four children.
+void collapse_bvh4(BvhOut& out);
 
 }  // namespace nrrs

@@ -42,14 +42,15 @@ struct nrrs_ctx {
   hipStream_t stream = nullptr;
   uint64_t npx = 0, nprim = 0, cap = 0;
   uint32_t cus = 0;                 // compute units of the device
-  uint32_t ext_occ[4] = {1, 1, 1, 1};  // resident traversal blocks per CU of each variant
+  uint32_t ext_occ[5] = {1, 1, 1, 1, 1};  // resident traversal blocks per CU of each variant
+  bool bvh4_ok = false;             // the 4-wide tree fits the traversal stack (variant 4)
   uint32_t* spill = nullptr;        // sized for cus * max(ext_occ) blocks
   nrrs_tuning tune{};               // launch parameters of the traversal kernel
   // workspace
   uint8_t* ws = nullptr;
   uint64_t ws_bytes = 0, max_tris = 0;
   uint32_t max_mats = 0;
-  float4 *tri = nullptr, *node = nullptr, *mat = nullptr;
+  float4 *tri = nullptr, *node = nullptr, *node4 = nullptr, *mat = nullptr;
   Queue qa{}, qb{};
   uint8_t* qb_pool = nullptr;  // queue B's bytes double as scratch for the test entry points
   uint64_t qb_pool_bytes = 0;
@@ -117,6 +118,7 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
   const uint64_t C = c->cap, npx = c->npx, rc = c->cfg.records_cap;
   c->tri = k.take<float4>(3 * max_tris);
   c->node = k.take<float4>(4 * (max_tris + 2));
+  c->node4 = k.take<float4>(8 * (max_tris + 2));  // a 4-wide node per BVH2 inner node at most
   c->mat = k.take<float4>(2 * (uint64_t)max_mats);
   for (Queue* qq : {&c->qa, &c->qb}) {
     uint64_t start = (k.off + 255) & ~uint64_t(255);
@@ -130,7 +132,7 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
       c->qb_pool_bytes = k.off - start;
     }
   }
-  const uint64_t max_blocks = (uint64_t)c->cus * *std::max_element(c->ext_occ, c->ext_occ + 4);
+  const uint64_t max_blocks = (uint64_t)c->cus * *std::max_element(c->ext_occ, c->ext_occ + 5);
   c->spill = k.take<uint32_t>((uint64_t)extend_spill_depth() * max_blocks * extend_threads_per_block());
   c->hit = k.take<float4>(C);
   c->vpos = k.take<float4>(C);
@@ -315,7 +317,7 @@ int32_t nrrs_create(const nrrs_config* cfg, void* hip_stream, nrrs_ctx** out) {
   c->nprim = nprim;
   c->cap = cap;
   c->cus = (uint32_t)prop.multiProcessorCount;
-  for (uint32_t v = 0; v < 4; ++v) c->ext_occ[v] = extend_blocks_per_cu(v);
+  for (uint32_t v = 0; v < 5; ++v) c->ext_occ[v] = extend_blocks_per_cu(v);
   c->tune.extend_variant = 1;
   c->tune.extend_blocks_per_cu = c->ext_occ[1];
   c->tune.extend_refill = 16;
@@ -394,7 +396,8 @@ int32_t nrrs_upload_scene(nrrs_ctx* c, const float* verts, uint64_t nv, const ui
   if (!(camera[9] > 0.0f && camera[9] < 180.0f)) return fail(c, NRRS_EINVAL, "camera fov out of range");
   BvhOut bvh;
   build_bvh(verts, tris, nt, bvh);
-  if (bvh.n_nodes > c->max_tris + 2) return fail(c, NRRS_ENOMEM, "BVH larger than reserved");
+  if (bvh.n_nodes > c->max_tris + 2 || bvh.n_nodes4 > c->max_tris + 2)
+    return fail(c, NRRS_ENOMEM, "BVH larger than reserved");
   if (bvh.max_depth > kMaxBvhDepth) return fail(c, NRRS_EINVAL, "BVH deeper than the traversal stack");
   // triangles in BVH order: (v0, original index), (e1, material), (e2, 0)
   std::vector<float> tri(12 * nt);
@@ -426,10 +429,13 @@ int32_t nrrs_upload_scene(nrrs_ctx* c, const float* verts, uint64_t nv, const ui
   HIPC(c, hipStreamSynchronize(s));
   HIPC(c, hipMemcpy(c->tri, tri.data(), sizeof(float) * tri.size(), hipMemcpyHostToDevice));
   HIPC(c, hipMemcpy(c->node, bvh.nodes.data(), sizeof(float) * bvh.nodes.size(), hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(c->node4, bvh.nodes4.data(), sizeof(float) * bvh.nodes4.size(), hipMemcpyHostToDevice));
   HIPC(c, hipMemcpy(c->mat, mats.data(), sizeof(float) * mats.size(), hipMemcpyHostToDevice));
   DevScene& d = c->sc;
   d.tri = c->tri;
   d.node = c->node;
+  d.node4 = c->node4;
+  d.nn4 = (uint32_t)bvh.n_nodes4;
   d.mat = c->mat;
   d.nt = (uint32_t)nt;
   d.nn = (uint32_t)bvh.n_nodes;
@@ -463,6 +469,11 @@ int32_t nrrs_upload_scene(nrrs_ctx* c, const float* verts, uint64_t nv, const ui
   d.rx = (float)(r[0] * th * aspect); d.ry = (float)(r[1] * th * aspect); d.rz = (float)(r[2] * th * aspect);
   d.ux = (float)(u[0] * th); d.uy = (float)(u[1] * th); d.uz = (float)(u[2] * th);
   c->drop_graphs();  // captured passes hold the old scene in their kernel arguments
+  c->bvh4_ok = bvh.max_depth4 <= kMaxBvh4Depth;
+  if (!c->bvh4_ok && c->tune.extend_variant == 4) {
+    c->tune.extend_variant = 3;
+    c->tune.extend_blocks_per_cu = std::min(c->tune.extend_blocks_per_cu, c->ext_occ[3]);
+  }
   c->bvh_order = bvh.order;
   c->orig_to_bvh.assign(nt, 0);
   for (uint64_t k = 0; k < nt; ++k) c->orig_to_bvh[bvh.order[k]] = (uint32_t)k;
@@ -485,13 +496,15 @@ int32_t nrrs_set_timing(nrrs_ctx* c, int32_t enabled) {
 int32_t nrrs_get_tuning(const nrrs_ctx* c, nrrs_tuning* out) {
   if (!c || !out) return NRRS_EINVAL;
   *out = c->tune;
-  for (int v = 0; v < 4; ++v) out->extend_max_blocks_per_cu[v] = c->ext_occ[v];
+  for (int v = 0; v < 5; ++v) out->extend_max_blocks_per_cu[v] = c->ext_occ[v];
   return NRRS_OK;
 }
 
 int32_t nrrs_set_tuning(nrrs_ctx* c, const nrrs_tuning* t) {
   if (!c || !t) return NRRS_EINVAL;
-  if (t->extend_variant > 3 || t->extend_blocks_per_cu < 1 ||
+  if (t->extend_variant == 4 && c->scene && !c->bvh4_ok)
+    return fail(c, NRRS_EINVAL, "the scene's 4-wide tree is deeper than the traversal stack allows");
+  if (t->extend_variant > 4 || t->extend_blocks_per_cu < 1 ||
       t->extend_blocks_per_cu > c->ext_occ[t->extend_variant] || t->extend_refill < 1 || t->extend_refill > 64 ||
       t->extend_leaf_batch < 1 || t->extend_leaf_batch > 64 || t->extend_chunk > 4096)
     return fail(c, NRRS_EINVAL,
@@ -710,7 +723,7 @@ int32_t nrrs_autotune(nrrs_ctx* c, uint32_t max_depth, nrrs_tuning* best, nrrs_t
     if (r != NRRS_OK) return;
     if (tried && count < tried_cap) {
       tried[count] = t;
-      for (int v = 0; v < 4; ++v) tried[count].extend_max_blocks_per_cu[v] = c->ext_occ[v];
+      for (int v = 0; v < 5; ++v) tried[count].extend_max_blocks_per_cu[v] = c->ext_occ[v];
       tried[count].extend_ms = ms;
     }
     ++count;
@@ -721,7 +734,8 @@ int32_t nrrs_autotune(nrrs_ctx* c, uint32_t max_depth, nrrs_tuning* best, nrrs_t
   };
   // 1: variant x refill threshold at full occupancy; 2: fewer resident blocks per CU; 3: claim
   // chunk; 4: leaf batch (variants that park leaves)
-  for (uint32_t v = 0; v < 4; ++v) {
+  for (uint32_t v = 0; v < 5; ++v) {
+    if (v == 4 && !c->bvh4_ok) continue;
     for (uint32_t refill : {16u, 32u, 48u, 64u}) {
       nrrs_tuning t = cur;
       t.extend_variant = v;

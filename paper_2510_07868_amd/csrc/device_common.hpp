@@ -127,8 +127,9 @@ __device__ __forceinline__ bool sample_ggx(float a, V3 f0, V3 wo, float u1, floa
 struct DevScene {
   const float4* tri;    // 3 float4 per triangle in BVH order: (v0, orig id), (e1, material), (e2, 0)
   const float4* node;   // 4 float4 per BVH2 node (two child boxes + child links)
+  const float4* node4;  // 8 float4 per 4-wide node: lo.x, hi.x, lo.y, hi.y, lo.z, hi.z, links, unused
   const float4* mat;    // 2 float4 per material: (rho rgb, ggx alpha), (Le rgb, type)
-  uint32_t nt, nn, nm;
+  uint32_t nt, nn, nm, nn4;
   float amin_x, amin_y, amin_z, extent, tmin, offset;
   float env_r, env_g, env_b;
   float eye_x, eye_y, eye_z, fwd_x, fwd_y, fwd_z, rx, ry, rz, ux, uy, uz;  // R, U pre-scaled

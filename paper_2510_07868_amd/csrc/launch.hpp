@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "bvh_layout.hpp"
 #include "device_common.hpp"
 
 namespace nrrs {
@@ -16,7 +17,6 @@ struct PassState {
 };
 
 // Everything the per-depth kernels read about the render in progress.
-constexpr int kMaxBvhDepth = 62;  // deepest BVH level the traversal stack is sized for
 
 struct RenderArgs {
   DevScene sc;

@@ -25,6 +25,7 @@ constexpr int kStackMax = 96;     // total stack entries per lane
 // the stack never exceeds kLeafPushLimit + 3 + kMaxBvhDepth <= kStackMax entries.
 constexpr int kLeafPushLimit = kStackMax - 3 - kMaxBvhDepth;
 static_assert(kLeafPushLimit > 0, "traversal stack too small");
+static_assert(3 * kMaxBvh4Depth + 1 <= kStackMax, "traversal stack too small for the 4-wide tree");
 constexpr uint32_t kLeafBit = 0x80000000u;
 
 __device__ __forceinline__ uint32_t bits(float f) { return __float_as_uint(f); }
@@ -72,6 +73,19 @@ __device__ __forceinline__ bool slab(float lx, float ly, float lz, float hx, flo
   const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
   tnear = tn;
   return tn <= tf * 1.00000095367431640625f;
+}
+
+constexpr float kInf = __builtin_huge_valf();
+
+// (ka, la) <= (kb, lb) after the call, ordered by key
+__device__ __forceinline__ void sort2(float& ka, uint32_t& la, float& kb, uint32_t& lb) {
+  const bool sw = kb < ka;
+  const float k = sw ? kb : ka;
+  const uint32_t l = sw ? lb : la;
+  kb = sw ? ka : kb;
+  lb = sw ? la : lb;
+  ka = k;
+  la = l;
 }
 
 struct HitState {
@@ -238,12 +252,15 @@ constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 //     stack) while others still look for theirs.
 //   kMode 3: as 1, but the wave intersects the parked leaves triangle-parallel
 //     (leaf_phase_shared): all 64 lanes share the (ray, triangle) pairs.
+//   kMode 4: as 3 over the 4-wide tree: a visit tests four child boxes, pushes the hit
+//     children farthest first and pops the nearest (a leaf is parked).  At most 3 entries
+//     per level stay on the stack, so the tree must be at most kMaxBvh4Depth levels deep.
 template <int kMode>
 __device__ __forceinline__ void extend_body(const RenderArgs& a) {
   __shared__ uint32_t stack_lds[kLdsStack][kTraceThreads];
   __shared__ unsigned long long cnt[3];  // rays traced, nodes visited, triangles tested
-  __shared__ unsigned long long hit_keys[kMode == 3 ? kTraceThreads : 1];
-  __shared__ float4 hit_slots[kMode == 3 ? kTraceThreads : 1];
+  __shared__ unsigned long long hit_keys[kMode >= 3 ? kTraceThreads : 1];
+  __shared__ float4 hit_slots[kMode >= 3 ? kTraceThreads : 1];
   const int tid = threadIdx.x;
   if (tid < 3) cnt[tid] = 0;
   __syncthreads();
@@ -351,6 +368,30 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
         active = false;
       }
     } else {
+      if constexpr (kMode == 4) {
+        if (active && ni != kNoNode && pend == 0) {
+          ++c_nodes;
+          const float4* nd = sc.node4 + 8ull * ni;
+          const float4 lx = nd[0], hx = nd[1], ly = nd[2], hy = nd[3], lz = nd[4], hz = nd[5], lk = nd[6];
+          float k0, k1, k2, k3;
+          uint32_t c0 = bits(lk.x), c1 = bits(lk.y), c2 = bits(lk.z), c3 = bits(lk.w);
+          if (!(c0 != kEmptyChild4 && slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, inv, oi, h.t, k0))) k0 = kInf;
+          if (!(c1 != kEmptyChild4 && slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, inv, oi, h.t, k1))) k1 = kInf;
+          if (!(c2 != kEmptyChild4 && slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, inv, oi, h.t, k2))) k2 = kInf;
+          if (!(c3 != kEmptyChild4 && slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, inv, oi, h.t, k3))) k3 = kInf;
+          // ascending by entry distance (misses last): five compare-exchanges
+          sort2(k0, c0, k1, c1);
+          sort2(k2, c2, k3, c3);
+          sort2(k0, c0, k2, c2);
+          sort2(k1, c1, k3, c3);
+          sort2(k1, c1, k2, c2);
+          if (k3 != kInf) st.push(c3);
+          if (k2 != kInf) st.push(c2);
+          if (k1 != kInf) st.push(c1);
+          if (k0 != kInf) st.push(c0);
+          ni = kNoNode;
+        }
+      } else
       if (active && ni != kNoNode && (kMode == 2 || pend == 0)) {
         ++c_nodes;
         const float4 n0 = sc.node[4 * ni], n1 = sc.node[4 * ni + 1], n2 = sc.node[4 * ni + 2],
@@ -397,7 +438,7 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
       if (parked != 0) {
         const uint64_t seeking = __ballot(active && pend == 0);
         if (seeking == 0 || __popcll(parked) >= leaf_batch) {
-          if constexpr (kMode == 3) {
+          if constexpr (kMode >= 3) {
             const int wbase = tid & ~63;
             leaf_phase_shared(sc, active && pend != 0, pend, o, d, excl, h, c_tris, hit_keys + wbase,
                               hit_slots + wbase);
@@ -444,20 +485,18 @@ __global__ __launch_bounds__(kEntryThreads) void k_shade(RenderArgs a) {
   const uint32_t n = a.ctl[a.depth].n;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float4 th = a.qin.thr[i];
+  // the entry's queue data in one round trip (dead entries are rare)
+  const float4 th = a.qin.thr[i], dr = a.qin.dir[i], hh = a.hit[i];
+  int4 rec = a.records_on ? a.qin.rec[i] : make_int4(-1, -1, -1, -1);
   const uint32_t flags = bits(th.w);
   float q = 0.0f;
   bool want_rec = false;
   V3 t = xyz(th), p = v3(0, 0, 0), nrm = p, wo = p;
   float4 m0 = make_float4(0, 0, 0, 0);
   uint32_t type = 0, pix = 0;
-  int4 rec = make_int4(-1, -1, -1, -1);
   if (!(flags & kFlagDead)) {
-    const float4 dr = a.qin.dir[i];
     pix = bits(dr.w);
-    const float4 hh = a.hit[i];
     const uint32_t prim = bits(hh.w);
-    if (a.records_on) rec = a.qin.rec[i];
     if (prim == kMiss) {
       emit(a, pix, t, v3(a.sc.env_r, a.sc.env_g, a.sc.env_b), rec);
     } else {
@@ -754,12 +793,9 @@ __global__ __launch_bounds__(kEntryThreads) void k_parents(RenderArgs a) {
   if (s < S) a.dbg_parent[s] = find_parent(a.offs, a.ctl[a.depth].n, s);
 }
 
-__global__ __launch_bounds__(kEntryThreads) void k_expand(RenderArgs a) {
-  const uint32_t S = a.ctl[a.depth].S;
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  const uint32_t i = find_parent(a.offs, a.ctl[a.depth].n, s);
-  const uint32_t j = s - a.offs[i];
+// Child s = child j of parent i: BSDF sample, throughput divided by the parent's normalized
+// factor, origin offset along the face-forwarded normal.
+__device__ __forceinline__ void expand_child(const RenderArgs& a, uint32_t i, uint32_t s, uint32_t j) {
   const float qn = (float)(a.ctl[a.depth].F * (double)a.q[i]);
   const float4 vp = a.vpos[i], vn = a.vnrm[i], dr = a.qin.dir[i], th = a.qin.thr[i];
   const uint2 lin = a.qin.id[i];
@@ -791,6 +827,31 @@ __global__ __launch_bounds__(kEntryThreads) void k_expand(RenderArgs a) {
   a.qout.thr[s] = pack(tc, flags);
   a.qout.id[s] = make_uint2(r.z, r.w);
   if (a.records_on) a.qout.rec[s] = a.qin.rec[i];
+}
+
+// Children of a block of kEntryThreads consecutive parents: the block's offsets go to LDS and
+// each child finds its parent (the last one whose first child is <= s) by a binary search
+// there; children are written in slot order, so stores coalesce.
+__global__ __launch_bounds__(kEntryThreads) void k_expand(RenderArgs a) {
+  __shared__ uint32_t so[kEntryThreads + 1];
+  const uint32_t n = a.ctl[a.depth].n, S = a.ctl[a.depth].S;
+  const uint32_t p0 = blockIdx.x * kEntryThreads;
+  if (p0 >= n) return;  // uniform over the block
+  const uint32_t np = min((uint32_t)kEntryThreads, n - p0);
+  const uint32_t tid = threadIdx.x;
+  if (tid < np) so[tid] = a.offs[p0 + tid];
+  if (tid == 0) so[np] = p0 + np < n ? a.offs[p0 + np] : S;
+  __syncthreads();
+  const uint32_t c1 = so[np];
+  for (uint32_t s = so[0] + tid; s < c1; s += kEntryThreads) {
+    uint32_t lo = 0, hi = np;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (so[mid] <= s) lo = mid;
+      else hi = mid;
+    }
+    expand_child(a, p0 + lo, s, s - so[lo]);
+  }
 }
 
 // ------------------------------------------------------------------------------ misc
@@ -852,7 +913,9 @@ void launch_camera(const RenderArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_camera, dim3(blocks_for(a.nprim, kEntryThreads)), dim3(kEntryThreads), 0, s, a);
 }
 void launch_extend(const RenderArgs& a, hipStream_t s) {
-  if (a.ext_variant == 3)
+  if (a.ext_variant == 4)
+    hipLaunchKernelGGL(k_extend<4>, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
+  else if (a.ext_variant == 3)
     hipLaunchKernelGGL(k_extend<3>, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
   else if (a.ext_variant == 2)
     hipLaunchKernelGGL(k_extend<2>, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
@@ -864,7 +927,8 @@ void launch_extend(const RenderArgs& a, hipStream_t s) {
 uint32_t extend_blocks_per_cu(uint32_t variant) {
   int nb = 0;
   hipError_t e;
-  if (variant == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<3>, kTraceThreads, 0);
+  if (variant == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<4>, kTraceThreads, 0);
+  else if (variant == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<3>, kTraceThreads, 0);
   else if (variant == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<2>, kTraceThreads, 0);
   else if (variant == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<1>, kTraceThreads, 0);
   else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend_immediate, kTraceThreads, 0);

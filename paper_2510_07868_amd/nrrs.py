@@ -39,7 +39,7 @@ class Tuning(C.Structure):
     _fields_ = [
         ("extend_variant", C.c_uint32), ("extend_blocks_per_cu", C.c_uint32), ("extend_refill", C.c_uint32),
         ("extend_leaf_batch", C.c_uint32), ("extend_chunk", C.c_uint32),
-        ("extend_max_blocks_per_cu", C.c_uint32 * 4), ("extend_ms", C.c_float),
+        ("extend_max_blocks_per_cu", C.c_uint32 * 5), ("extend_ms", C.c_float),
     ]
 
     def as_dict(self):

@@ -141,7 +141,8 @@ def test_closest_hit_matches_oracle(O, nrrs_mod, scenes):
         for variant, bpc, refill, batch, chunk in (
                 (0, occ[0], 16, 32, 0), (1, occ[1], 16, 32, 64), (1, 1, 8, 1, 0), (1, max(1, occ[1] // 2), 64, 64, 4096),
                 (0, 1, 1, 1, 1), (2, occ[2], 32, 16, 256), (2, 1, 1, 64, 0), (2, max(1, occ[2] // 2), 64, 1, 100),
-                (0, occ[0], 32, 32, 4096), (3, occ[3], 48, 16, 0), (3, 1, 1, 1, 0), (3, max(1, occ[3] // 2), 64, 64, 64)):
+                (0, occ[0], 32, 32, 4096), (3, occ[3], 48, 16, 0), (3, 1, 1, 1, 0), (3, max(1, occ[3] // 2), 64, 64, 64),
+                (4, occ[4], 48, 8, 0), (4, 1, 1, 1, 0), (4, max(1, occ[4] // 2), 64, 64, 128), (4, occ[4], 16, 32, 0)):
             r.set_tuning(variant, bpc, refill, batch, chunk)
             gp, gt, _, _ = r.debug_trace(rays32)
             assert np.array_equal(gp[ok], op[ok]), (variant, bpc, refill, batch, chunk)
@@ -153,7 +154,7 @@ def test_autotune_picks_a_valid_launch_and_keeps_results(O, nrrs_mod, scenes):
     r = make(nrrs_mod, sc, 64, 64, s_batch=4)
     t0 = r.get_tuning()
     with pytest.raises(RuntimeError):
-        r.set_tuning(4, 1, 16, 32)
+        r.set_tuning(5, 1, 16, 32)
     with pytest.raises(RuntimeError):
         r.set_tuning(0, t0["extend_max_blocks_per_cu"][0] + 1, 16, 32)
     with pytest.raises(RuntimeError):
@@ -162,7 +163,7 @@ def test_autotune_picks_a_valid_launch_and_keeps_results(O, nrrs_mod, scenes):
         r.set_tuning(1, 1, 16, 32, 4097)
     assert r.get_tuning() == t0
     best = r.autotune(8)
-    assert best["extend_variant"] in (0, 1, 2, 3)
+    assert best["extend_variant"] in (0, 1, 2, 3, 4)
     assert 1 <= best["extend_blocks_per_cu"] <= best["extend_max_blocks_per_cu"][best["extend_variant"]]
     assert best["extend_ms"] > 0
     assert r.read_image()[1] == 0                # the timing passes leave no samples behind
