@@ -161,6 +161,7 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
   c->rec.depth = k.take<uint32_t>(rc);
   c->rec.pix = k.take<uint32_t>(rc);
   c->rec.lineage = k.take<uint2>(rc);
+  c->rec.qidx = k.take<uint32_t>(rc);
   c->rec.count = k.take<uint32_t>(1);
   c->rec.cap = (uint32_t)rc;
   c->target = k.take<float>(rc);
@@ -571,6 +572,7 @@ int32_t nrrs_render(nrrs_ctx* c, uint32_t spp, uint32_t max_depth, int32_t mode,
       launch_extend(b, s);
       MARK(1);
       launch_shade(b, s);
+      if (b.records_on && d <= (uint32_t)c->cfg.net_max_depth) launch_record_features(b, c->cfg.records_cap, s);
       MARK(2);
       if (d == max_depth) break;
       if (mode == NRRS_MODE_NET && d <= (uint32_t)c->cfg.net_max_depth) {

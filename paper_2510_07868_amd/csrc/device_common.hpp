@@ -150,6 +150,7 @@ struct Records {
   uint32_t* depth;
   uint32_t* pix;
   uint2* lineage;
+  uint32_t* qidx;  // [cap] queue slot of the record's vertex at capture (features filled later)
   uint32_t* count;
   uint32_t cap;
 };

@@ -56,6 +56,7 @@ struct RenderArgs {
 void launch_camera(const RenderArgs& a, hipStream_t s);
 void launch_extend(const RenderArgs& a, hipStream_t s);
 void launch_shade(const RenderArgs& a, hipStream_t s);
+void launch_record_features(const RenderArgs& a, uint64_t records_cap, hipStream_t s);  // after shade, same depth
 void launch_sum_q(const RenderArgs& a, hipStream_t s);
 void launch_roulette(const RenderArgs& a, hipStream_t s);  // count, scan, guard, offsets
 void launch_expand(const RenderArgs& a, hipStream_t s);

@@ -17,6 +17,7 @@ namespace nrrs {
 namespace {
 
 constexpr int kEntryThreads = 256;
+constexpr int kShadeThreads = 1024;
 constexpr int kTraceThreads = 128;
 constexpr int kLdsStack = 16;     // stack entries per lane kept in LDS
 constexpr int kStackMax = 96;     // total stack entries per lane
@@ -481,10 +482,34 @@ __device__ __forceinline__ void emit(const RenderArgs& a, uint32_t pix, V3 t, V3
   }
 }
 
-__global__ __launch_bounds__(kEntryThreads) void k_shade(RenderArgs a) {
+// Record slots for a whole block with one counter atomic: per-wave counts in LDS, a block
+// prefix by the first thread.  Every thread of the block must call it.
+__device__ __forceinline__ uint32_t block_alloc(uint32_t* counter, bool pred, uint32_t* sh) {
+  constexpr int kWaves = kShadeThreads / 64;
+  const uint64_t m = __ballot(pred);
+  const int wave = threadIdx.x >> 6;
+  if (__lane_id() == 0) sh[wave] = (uint32_t)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t c = sh[w];
+      sh[w] = tot;
+      tot += c;
+    }
+    sh[kWaves] = tot ? atomicAdd(counter, tot) : 0u;
+  }
+  __syncthreads();
+  return sh[kWaves] + sh[wave] + lanes_below(m);
+}
+
+__global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
+  __shared__ uint32_t alloc_sh[kShadeThreads / 64 + 1];
   const uint32_t n = a.ctl[a.depth].n;
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (blockIdx.x * blockDim.x >= n) return;  // uniform over the block
+  const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in_range = i0 < n;
+  const uint32_t i = in_range ? i0 : n - 1;
   // the entry's queue data in one round trip (dead entries are rare)
   const float4 th = a.qin.thr[i], dr = a.qin.dir[i], hh = a.hit[i];
   int4 rec = a.records_on ? a.qin.rec[i] : make_int4(-1, -1, -1, -1);
@@ -494,7 +519,7 @@ __global__ __launch_bounds__(kEntryThreads) void k_shade(RenderArgs a) {
   V3 t = xyz(th), p = v3(0, 0, 0), nrm = p, wo = p;
   float4 m0 = make_float4(0, 0, 0, 0);
   uint32_t type = 0, pix = 0;
-  if (!(flags & kFlagDead)) {
+  if (in_range && !(flags & kFlagDead)) {
     pix = bits(dr.w);
     const uint32_t prim = bits(hh.w);
     if (prim == kMiss) {
@@ -520,16 +545,13 @@ __global__ __launch_bounds__(kEntryThreads) void k_shade(RenderArgs a) {
       a.vnrm[i] = pack(nrm, mid);
     }
   }
-  a.q[i] = q;
-  // training record: one counter atomic per wave (converged code)
+  if (in_range) a.q[i] = q;
+  // training record: one counter atomic per block (converged code)
   if (a.records_on) {
-    const uint32_t slot = wave_alloc(a.rec.count, want_rec);
+    const uint32_t slot = block_alloc(a.rec.count, want_rec, alloc_sh);
     if (want_rec && slot < a.rec.cap) {
-      float f[20];
-      vertex_features(a.sc, p, nrm, wo, t, m0, type, a.depth, a.max_depth, f);
-      float* dst = a.rec.feat + 20ull * slot;
-#pragma unroll
-      for (int k = 0; k < 20; ++k) dst[k] = f[k];
+      // the 20 features are filled by k_record_features over the dense record slots
+      a.rec.qidx[slot] = i;
       a.rec.lum_t[slot] = lum(t);
       a.rec.acc[slot] = 0.0f;
       a.rec.depth[slot] = a.depth;
@@ -542,6 +564,23 @@ __global__ __launch_bounds__(kEntryThreads) void k_shade(RenderArgs a) {
       a.qin.rec[i] = rec;
     }
   }
+}
+
+// Features of the records captured at this depth, one thread per record slot (the shading
+// kernel only reserved the slots and noted the queue entries).
+__global__ __launch_bounds__(kEntryThreads) void k_record_features(RenderArgs a) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t cnt = min(*a.rec.count, a.rec.cap);
+  if (s >= cnt || a.rec.depth[s] != a.depth) return;
+  const uint32_t i = a.rec.qidx[s];
+  const float4 vp = a.vpos[i], vn = a.vnrm[i], dr = a.qin.dir[i], th = a.qin.thr[i];
+  const uint32_t mid = bits(vn.w);
+  const float4 m0 = a.sc.mat[2 * mid], m1 = a.sc.mat[2 * mid + 1];
+  float f[20];
+  vertex_features(a.sc, xyz(vp), xyz(vn), v3(-dr.x, -dr.y, -dr.z), xyz(th), m0, bits(m1.w), a.depth, a.max_depth, f);
+  float* dst = a.rec.feat + 20ull * s;
+#pragma unroll
+  for (int k = 0; k < 20; ++k) dst[k] = f[k];
 }
 
 // -------------------------------------------------------------------- FP64 sum of q
@@ -937,8 +976,12 @@ uint32_t extend_blocks_per_cu(uint32_t variant) {
 }
 uint32_t extend_threads_per_block() { return kTraceThreads; }
 uint32_t extend_spill_depth() { return kStackMax - kLdsStack; }
+void launch_record_features(const RenderArgs& a, uint64_t records_cap, hipStream_t s) {
+  if (records_cap)
+    hipLaunchKernelGGL(k_record_features, dim3(blocks_for(records_cap, kEntryThreads)), dim3(kEntryThreads), 0, s, a);
+}
 void launch_shade(const RenderArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_shade, dim3(blocks_for(a.cap, kEntryThreads)), dim3(kEntryThreads), 0, s, a);
+  hipLaunchKernelGGL(k_shade, dim3(blocks_for(a.cap, kShadeThreads)), dim3(kShadeThreads), 0, s, a);
 }
 void launch_sum_q(const RenderArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_sum_q_partial, dim3(kScanBlocks), dim3(kScanThreads), 0, s, a);
