@@ -1,9 +1,11 @@
 // Matrix-core inference of the RRS network on gfx950 (BF16 and FP8-E4M3, FP32 accumulate).
 //
-// Each wave evaluates 32 path vertices at a time as C[unit][vertex] = W[unit][k] * X[k][vertex]
+// Each wave evaluates path vertices in tiles of 32 as C[unit][vertex] = W[unit][k] * X[k][vertex]
 // with v_mfma_f32_32x32x16_bf16 (BF16) or v_mfma_scale_f32_32x32x64_f8f6f4 (FP8).  The weights
-// are the A operand, packed once per block into LDS in operand order; the lane pair (l, l+32) owns
-// vertex l % 32.  The hidden units of every layer are consumed in the order in which the
+// are the A operand, packed once per block into LDS in operand order.  BF16: every lane owns one
+// vertex (64 per wave step, two tiles); its own features feed the input layer of its tile
+// through weight tiles that are zero in the other lane half's K range, so no lane computes or
+// exchanges another lane's features.  FP8: the lane pair (l, l+32) owns vertex l % 32.  The hidden units of every layer are consumed in the order in which the
 // previous layer's accumulator registers hold them, so the accumulators of one layer become
 // the B operand of the next with no data exchange: the packing kernel permutes the weight
 // columns accordingly.  The 64 -> 1 output layer and the modified softplus (Sec. 5, Eq. 22)
@@ -26,7 +28,8 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef __attribute__((__vector_size__(8 * sizeof(int)))) int i32x8;
 
 constexpr int kThreads = 256;
-constexpr int kBfTiles = 20;   // layer 1: 2 unit tiles x 2 k-steps; layers 2, 3: 2 x 4
+constexpr int kBfTiles = 28;   // layer 1: 2 vertex tiles x 2 unit tiles x 3 k-steps; layers 2, 3: 2 x 4
+constexpr int kBfL1 = 12;      // first tile of layer 2
 constexpr int kF8Tiles = 6;    // 2 unit tiles x 1 k-step (K = 64) per layer
 constexpr float kE4M3Max = 448.0f;
 
@@ -99,11 +102,13 @@ __global__ void k_pack(const float* W, const float* f8scale, uint16_t* bf, uint8
   if (g < (uint32_t)kBfTiles * 64 * 8) {
     const int t = g / 512, l = (g / 8) % 64, i = g % 8, h = l / 32;
     float w = 0.0f;
-    if (t < 4) {
-      const int mt = t / 2, ks = t % 2, m = 32 * mt + l % 32, k = 16 * ks + 8 * h + i;
-      w = k < 20 ? W[kW1 + 20 * m + k] : 0.0f;
+    if (t < kBfL1) {
+      // input layer, vertex tile vt: only lane half vt carries feature 8 j + i, the other half's
+      // K range is zero
+      const int vt = t / 6, mt = (t / 3) % 2, j = t % 3, m = 32 * mt + l % 32, k = 8 * j + i;
+      w = (h == vt && k < 20) ? W[kW1 + 20 * m + k] : 0.0f;
     } else {
-      const int base = t < 12 ? kW2 : kW3, tt = (t - 4) % 8, mt = tt / 4, ks = tt % 4, m = 32 * mt + l % 32;
+      const int base = t < kBfL1 + 8 ? kW2 : kW3, tt = (t - kBfL1) % 8, mt = tt / 4, ks = tt % 4, m = 32 * mt + l % 32;
       w = W[base + 64 * m + bf16_unit(ks, h, i)];
     }
     bf[g] = to_bf16_bits(w);
@@ -168,25 +173,14 @@ __device__ __forceinline__ float output_layer(const Smem& sm, const f32x16& c0, 
   return z + sm.b4;
 }
 
-// BF16: the lane pair owning a vertex returns its output pre-activation z.
-__device__ __forceinline__ float mlp_bf16(const bf16x8* __restrict__ wl, const Smem& sm, const float f[20]) {
-  const bf16x8* w = wl + __lane_id();  // this lane's part of tile t is w[64 t]
-  const int h = (int)(__lane_id() >> 5);
-  bf16x8 x0, x1;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    x0[i] = (__bf16)(h ? f[8 + i] : f[i]);
-    x1[i] = (__bf16)((h == 0 && 16 + i < 20) ? f[(16 + i) % 20] : 0.0f);
-  }
-  f32x16 c0 = bias_tile(sm.b[0], 0, h), c1 = bias_tile(sm.b[0], 1, h);
-  c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[64 * (0)], x0, c0, 0, 0, 0);
-  c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[64 * (1)], x1, c0, 0, 0, 0);
-  c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[64 * (2)], x0, c1, 0, 0, 0);
-  c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[64 * (3)], x1, c1, 0, 0, 0);
+// Hidden layers 2, 3 and the output layer of one 32-vertex tile from its input-layer
+// accumulators; returns z of vertex l % 32 (in both lane halves).
+__device__ __forceinline__ float bf16_hidden(const bf16x8* __restrict__ w, const Smem& sm, f32x16 c0, f32x16 c1,
+                                             int h) {
 #pragma unroll
   for (int L = 1; L < 3; ++L) {
     const bf16x8 b0 = relu_bf16(c0, 0), b1 = relu_bf16(c0, 8), b2 = relu_bf16(c1, 0), b3 = relu_bf16(c1, 8);
-    const int t = 4 + 8 * (L - 1);
+    const int t = kBfL1 + 8 * (L - 1);
     c0 = bias_tile(sm.b[L], 0, h);
     c1 = bias_tile(sm.b[L], 1, h);
     c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[64 * (t + 0)], b0, c0, 0, 0, 0);
@@ -199,6 +193,32 @@ __device__ __forceinline__ float mlp_bf16(const bf16x8* __restrict__ wl, const S
     c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[64 * (t + 7)], b3, c1, 0, 0, 0);
   }
   return output_layer(sm, c0, c1, h);
+}
+
+// BF16: every lane passes its own vertex's features and gets that vertex's output
+// pre-activation z.  Lanes 0-31 form vertex tile 0, lanes 32-63 tile 1.
+__device__ __forceinline__ float mlp_bf16(const bf16x8* __restrict__ wl, const Smem& sm, const float f[20]) {
+  const bf16x8* w = wl + __lane_id();  // this lane's part of tile t is w[64 t]
+  const int h = (int)(__lane_id() >> 5);
+  bf16x8 x[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[j][i] = (__bf16)(8 * j + i < 20 ? f[(8 * j + i) % 20] : 0.0f);
+  float z[2];
+#pragma unroll
+  for (int vt = 0; vt < 2; ++vt) {
+    // re-read the weights from LDS for the second tile rather than keep them in registers
+    asm volatile("" ::: "memory");
+    f32x16 c0 = bias_tile(sm.b[0], 0, h), c1 = bias_tile(sm.b[0], 1, h);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[64 * (6 * vt + j)], x[j], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[64 * (6 * vt + 3 + j)], x[j], c1, 0, 0, 0);
+    }
+    z[vt] = bf16_hidden(w, sm, c0, c1, h);
+  }
+  return h ? z[1] : z[0];
 }
 
 // Power-of-two scale (E8M0 code) shared by the two lanes of a vertex, so that the vertex's
@@ -268,6 +288,7 @@ template <int P>
 struct Weights;
 template <>
 struct Weights<1> {
+  static constexpr int kVerts = 64;  // vertices per wave step: one per lane
   static constexpr int kBytes = kBfTiles * 64 * 16;
   const bf16x8* lds;
   __device__ void load(const NetArgs& n, void* smem) {
@@ -280,6 +301,7 @@ struct Weights<1> {
 };
 template <>
 struct Weights<2> {
+  static constexpr int kVerts = 32;  // vertices per wave step: one per lane pair
   static constexpr int kBytes = kF8Tiles * 64 * 32;
   const i32x8* lds;
   __device__ void load(const NetArgs& n, void* smem) {
@@ -299,15 +321,16 @@ __global__ __launch_bounds__(kThreads) void k_rrsnet_mfma(RenderArgs a, NetArgs 
   Weights<P> W;
   W.load(net, wsm);
   load_smem(sm, net.master, net.fp8_scale, P == 2);
+  constexpr uint32_t kV = Weights<P>::kVerts;
   const uint32_t n = a.ctl[a.depth].n;
-  const uint32_t tiles = (n + 31) / 32;
+  const uint32_t tiles = (n + kV - 1) / kV;
   const uint32_t wave = blockIdx.x * (kThreads / 64) + threadIdx.x / 64;
   const uint32_t waves = gridDim.x * (kThreads / 64);
   const uint32_t lane = __lane_id();
   for (uint32_t tile = wave; tile < tiles; tile += waves) {
     // keep the weights in LDS: re-read them every tile instead of pinning ~80 registers
     asm volatile("" ::: "memory");
-    const uint32_t i = tile * 32 + (lane & 31);
+    const uint32_t i = tile * kV + (lane & (kV - 1));
     bool active = false;
     float f[20];
     float g = 0.0f, lt = 0.0f;
@@ -327,7 +350,7 @@ __global__ __launch_bounds__(kThreads) void k_rrsnet_mfma(RenderArgs a, NetArgs 
       }
     }
     const float z = W.eval(sm, f);
-    if (active && lane < 32) {
+    if (active && lane < kV) {
       const float q = lt * softplus_mod(z) / (g + 0.01f);
       if (isfinite(q) && q > 0.0f) a.q[i] = q;
     }
@@ -341,18 +364,19 @@ __global__ __launch_bounds__(kThreads) void k_rows_mfma(const float* x, uint32_t
   Weights<P> W;
   W.load(net, wsm);
   load_smem(sm, net.master, net.fp8_scale, P == 2);
-  const uint32_t tiles = (n + 31) / 32;
+  constexpr uint32_t kV = Weights<P>::kVerts;
+  const uint32_t tiles = (n + kV - 1) / kV;
   const uint32_t wave = blockIdx.x * (kThreads / 64) + threadIdx.x / 64;
   const uint32_t waves = gridDim.x * (kThreads / 64);
   const uint32_t lane = __lane_id();
   for (uint32_t tile = wave; tile < tiles; tile += waves) {
     asm volatile("" ::: "memory");
-    const uint32_t i = tile * 32 + (lane & 31);
+    const uint32_t i = tile * kV + (lane & (kV - 1));
     float f[20];
 #pragma unroll
     for (int k = 0; k < 20; ++k) f[k] = i < n ? x[20ull * i + k] : 0.0f;
     const float z = W.eval(sm, f);
-    if (i < n && lane < 32) {
+    if (i < n && lane < kV) {
       y[i] = softplus_mod(z);
       if (zout) zout[i] = z;
     }
