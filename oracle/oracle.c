@@ -235,10 +235,12 @@ void or_scene_destroy(or_scene* s) {
 }
 
 /* ------------------------------------------------------------ intersection */
-/* Moller-Trumbore (1997).  Returns 0 for a ray parallel to the plane, else 1
- * with t, b1, b2 and the signed barycentric margin (min of the three weights). */
+/* Moller-Trumbore (1997).  Returns 0 for a ray parallel to the plane, else 1 with t, b1, b2,
+ * the signed barycentric margin (min of the three weights) and |cos| of the angle between the
+ * ray and the triangle's normal: float32 barycentrics and distances carry errors growing as
+ * 1/|cos|, so near-tie tests scale their margins by it. */
 static int tri_test(const or_scene* s, uint32_t p, const double o[3], const double d[3], double* t,
-                    double* b1, double* b2, double* margin) {
+                    double* b1, double* b2, double* margin, double* cosn) {
   const double* v = s->tri + 9 * (uint64_t)p;
   double e1[3], e2[3], pv[3], sv[3], qv[3];
   sub3(v + 3, v, e1);
@@ -253,31 +255,35 @@ static int tri_test(const or_scene* s, uint32_t p, const double o[3], const doub
   *b2 = dot3(d, qv) * inv;
   *t = dot3(e2, qv) * inv;
   *margin = fmin(*b1, fmin(*b2, 1.0 - *b1 - *b2));
+  double nv[3];
+  cross3(e1, e2, nv);
+  *cosn = fabs(det) / sqrt(dot3(nv, nv));
   return 1;
 }
 
 typedef struct {
   uint32_t prim;
-  double t, b1, b2, margin;
+  double t, b1, b2, margin, cosn;  /* margin of the winner, scaled by its |cos| */
   int ncand;
-  double cand_t[16];
+  double cand_t[16], cand_c[16];
   uint32_t cand_p[16];
 } trace_state;
 
 static void consider(const or_scene* s, uint32_t p, const double o[3], const double d[3], uint32_t excl,
                      double tau, trace_state* st) {
   if (p == excl) return;
-  double t, b1, b2, m;
-  if (!tri_test(s, p, o, d, &t, &b1, &b2, &m)) return;
+  double t, b1, b2, m, cn;
+  if (!tri_test(s, p, o, d, &t, &b1, &b2, &m, &cn)) return;
   if (m >= 0.0 && t > s->tmin) {
     if (t < st->t || (t == st->t && p < st->prim)) {
-      st->prim = p; st->t = t; st->b1 = b1; st->b2 = b2; st->margin = m;
+      st->prim = p; st->t = t; st->b1 = b1; st->b2 = b2; st->margin = m * cn; st->cosn = cn;
     }
   }
-  if (tau > 0.0 && m > -tau && t > s->tmin - tau * s->diag) {
+  if (tau > 0.0 && m * cn > -tau && t > s->tmin - tau * s->diag / fmax(cn, 1e-300)) {
     /* keep the 16 nearest candidates; a farther one cannot decide a near-tie that these miss */
     if (st->ncand < 16) {
       st->cand_t[st->ncand] = t;
+      st->cand_c[st->ncand] = cn;
       st->cand_p[st->ncand] = p;
       st->ncand++;
     } else {
@@ -286,6 +292,7 @@ static void consider(const or_scene* s, uint32_t p, const double o[3], const dou
         if (st->cand_t[i] > st->cand_t[far]) far = i;
       if (t < st->cand_t[far]) {
         st->cand_t[far] = t;
+        st->cand_c[far] = cn;
         st->cand_p[far] = p;
       }
     }
@@ -316,7 +323,7 @@ static int box_hit(const bnode* nd, const double o[3], const double d[3], double
 static int trace_one(const or_scene* s, const double o[3], const double d[3], uint32_t excl, int use_bvh,
                      double tau, uint32_t* prim, double* t, double* b1, double* b2) {
   trace_state st;
-  st.prim = MISS; st.t = INFINITY; st.b1 = st.b2 = 0.0; st.margin = 0.0; st.ncand = 0;
+  st.prim = MISS; st.t = INFINITY; st.b1 = st.b2 = 0.0; st.margin = 0.0; st.cosn = 1.0; st.ncand = 0;
   if (use_bvh && s->nodes) {
     uint32_t stack[128];
     int sp = 0;
@@ -340,7 +347,7 @@ static int trace_one(const or_scene* s, const double o[3], const double d[3], ui
   if (st.prim != MISS && (st.margin < tau || st.t < s->tmin + tau * s->diag)) return 1;
   for (int i = 0; i < st.ncand; ++i) {
     if (st.cand_p[i] == st.prim) continue;
-    if (st.prim == MISS || st.cand_t[i] < st.t + tau * s->diag) return 1;
+    if (st.prim == MISS || (st.cand_t[i] - st.t) * fmin(st.cand_c[i], st.cosn) < tau * s->diag) return 1;
   }
   return 0;
 }
@@ -968,6 +975,9 @@ static void expand_children(rctx* c, const entry* Q, const vstate* V, uint64_t n
     const double* mp = s->mpar + 7 * (uint64_t)v->mat;
     double tb[3], bb[3];
     onb(v->n, tb, bb);
+    /* the local frame switches sign convention at n_z = 0: a nonzero n_z this close to the
+     * switch may have the other sign in float32, a near-tie (an exact zero is exact there too) */
+    if (tau > 0.0 && v->n[2] != 0.0 && fabs(v->n[2]) < tau && c->fragile) c->fragile[e->pix] = 1;
     double wol[3] = {dot3(v->wo, tb), dot3(v->wo, bb), dot3(v->wo, v->n)};
     for (uint32_t j = 0; j < X[i]; ++j) {
       uint32_t r[4];
