@@ -656,6 +656,7 @@ __global__ __launch_bounds__(kScanThreads) void k_roulette_count(RenderArgs a) {
   const uint32_t beg = blockIdx.x * chunk;
   const double F = norm_factor(a, a.ctl[a.depth].sumq, *a.alpha);
   uint32_t acc = 0;
+#pragma unroll 4
   for (uint32_t base = beg; base < beg + chunk && base < n; base += kScanThreads) {
     const uint32_t i = base + threadIdx.x;
     if (i < n && i < beg + chunk) {
@@ -782,15 +783,29 @@ __global__ __launch_bounds__(kScanThreads) void k_guard_select(RenderArgs a) {
     for (int b = threadIdx.x; b < kScanBlocks; b += kScanThreads) a.boff[b] = 0;
 }
 
-// First child slot of every entry: per-tile exclusive scan plus the block's offset.
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = (int)__lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = (uint32_t)__shfl_up((int)v, off);
+    if (lane >= off) v += t;
+  }
+  return v;
+}
+
+// First child slot of every entry: per-tile exclusive scan (wave scans, then the waves'
+// totals) plus the block's offset.
 __global__ __launch_bounds__(kScanThreads) void k_offsets(RenderArgs a) {
-  __shared__ uint32_t sh[kScanThreads];
+  constexpr int kWaves = kScanThreads / 64;
+  __shared__ uint32_t wsum[2][kWaves];
   const uint32_t n = a.ctl[a.depth].n;
   const uint32_t chunk = chunk_of(n);
   const uint32_t beg = blockIdx.x * chunk;
   const double F = a.ctl[a.depth].F;
   uint32_t run = a.boff[blockIdx.x];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  int buf = 0;
   for (uint32_t base = beg; base < beg + chunk && base < n; base += kScanThreads) {
     const uint32_t i = base + tid;
     uint32_t x = 0;
@@ -798,17 +813,19 @@ __global__ __launch_bounds__(kScanThreads) void k_offsets(RenderArgs a) {
       const float q = a.q[i];
       if (q > 0.0f) x = child_count(q, F, roulette_u(a, i));
     }
-    sh[tid] = x;
+    const uint32_t incl = wave_incl_scan(x);
+    if ((tid & 63) == 63) wsum[buf][wave] = incl;
     __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-      const uint32_t v = tid >= off ? sh[tid - off] : 0u;
-      __syncthreads();
-      sh[tid] += v;
-      __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t t = wsum[buf][w];
+      before += w < wave ? t : 0u;
+      total += t;
     }
-    if (i < n && i < beg + chunk) a.offs[i] = run + sh[tid] - x;
-    run += sh[kScanThreads - 1];
-    __syncthreads();
+    if (i < n && i < beg + chunk) a.offs[i] = run + before + incl - x;
+    run += total;
+    buf ^= 1;  // the next tile writes the other buffer: one barrier per tile suffices
   }
 }
 
