@@ -96,8 +96,8 @@ def main():
     D = args.depth
     nprim = W * H * spp
     rec_n = 1 << 18
-    minibatch = 1 << 14
-    p_train = min(1.0, 0.025 * (4194304 / nprim))
+    minibatch = 1 << 13
+    p_train = min(1.0, 0.05 * (4194304 / nprim))
     t_scene = time.time()
     sc = scenes.heightfield(0)
     r = nrrs.Renderer(W, H, s_batch=spp, cap_factor=2.0, seed=0, net_max_depth=4, precision=prec,
