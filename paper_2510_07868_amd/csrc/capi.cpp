@@ -877,10 +877,9 @@ int32_t nrrs_train_step(nrrs_ctx* c, uint32_t n_records, uint32_t minibatch, flo
     uint32_t nb = 0;
     launch_mlp_grad(c->rec.feat + 20ull * b * minibatch, c->target + (uint64_t)b * minibatch, nullptr, minibatch,
                     c->master, c->cfg.loss, c->grad_partial, c->loss_partial, &nb, s);
-    launch_grad_reduce(c->grad_partial, nb, c->grad, c->loss_partial, c->loss_accum, minibatch, s);
     c->adam_step += 1;
-    launch_adam(c->master, c->adam_m, c->adam_v, c->grad, c->adam_step, lr, s);
-    launch_ema(c->infer, c->master, (float)c->cfg.ema_decay, s);
+    launch_grad_adam_ema(c->grad_partial, nb, c->grad, c->loss_partial, c->loss_accum, minibatch, c->master,
+                         c->adam_m, c->adam_v, c->adam_step, lr, c->infer, (float)c->cfg.ema_decay, s);
   }
   launch_quantize(c->infer, c->bf16, c->fp8, c->fp8_scale, s);
   HIPC(c, hipGetLastError());

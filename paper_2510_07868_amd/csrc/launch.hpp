@@ -94,9 +94,11 @@ void launch_mlp_grad(const float* x, const float* target, const uint32_t* index,
                      hipStream_t s);
 void launch_grad_reduce(const float* grad_partial, uint32_t nblocks, float* grad, const float* loss_partial,
                         float* loss_accum, uint32_t n_rows_total, hipStream_t s);
-void launch_adam(float* master, float* m, float* v, const float* grad, uint64_t step, float lr, hipStream_t s);
-// infer = decay * infer + (1 - decay) * master (decay 0: copy)
-void launch_ema(float* infer, const float* master, float decay, hipStream_t s);
+// Gradient sum (fixed order) + Adam on `master` + infer = decay * infer + (1 - decay) * master
+// (decay 0: copy) — the tail of one training step in one launch.
+void launch_grad_adam_ema(const float* grad_partial, uint32_t nblocks, float* grad, const float* loss_partial,
+                          float* loss_accum, uint32_t n_rows_total, float* master, float* m, float* v, uint64_t step,
+                          float lr, float* infer, float decay, hipStream_t s);
 void launch_quantize(const float* master, uint16_t* bf16, uint8_t* fp8, float* fp8_scale, hipStream_t s);
 void launch_record_targets(const Records& r, float* target, uint32_t n, hipStream_t s);
 // Matrix-core inference (mlp_mfma.hip): precision 1 = BF16, 2 = FP8-E4M3.

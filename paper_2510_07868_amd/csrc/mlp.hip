@@ -92,25 +92,6 @@ __global__ __launch_bounds__(kNetThreads) void k_forward_rows_f32(const float* x
 
 // ------------------------------------------------------------------------ training
 // (gradient kernels: mlp_train.hip)
-__global__ void k_adam(float* w, float* m, float* v, const float* g, uint64_t step, float lr) {
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= (uint32_t)kNParam) return;
-  const double t = (double)step;
-  const float c1 = (float)(1.0 - pow(0.9, t));
-  const float c2 = (float)(1.0 - pow(0.999, t));
-  const float gk = g[k];
-  const float mk = 0.9f * m[k] + 0.1f * gk;
-  const float vk = 0.999f * v[k] + 0.001f * gk * gk;
-  m[k] = mk;
-  v[k] = vk;
-  w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + 1e-8f);
-}
-
-__global__ void k_ema(float* infer, const float* master, float decay) {
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < (uint32_t)kNParam) infer[k] = decay > 0.0f ? fmaf(decay, infer[k] - master[k], master[k]) : master[k];
-}
-
 __global__ void k_record_targets(Records r, float* target, uint32_t n) {
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
@@ -137,14 +118,6 @@ void launch_mlp_forward_rows(const float* x, uint32_t n, const NetArgs& net, flo
   }
   hipLaunchKernelGGL(k_forward_rows_f32, dim3((n + kNetThreads - 1) / kNetThreads), dim3(kNetThreads), 0, s, x, n,
                      net.master, y, z);
-}
-
-void launch_adam(float* master, float* m, float* v, const float* grad, uint64_t step, float lr, hipStream_t s) {
-  hipLaunchKernelGGL(k_adam, dim3((kNParam + 255) / 256), dim3(256), 0, s, master, m, v, grad, step, lr);
-}
-
-void launch_ema(float* infer, const float* master, float decay, hipStream_t s) {
-  hipLaunchKernelGGL(k_ema, dim3((kNParam + 255) / 256), dim3(256), 0, s, infer, master, decay);
 }
 
 void launch_quantize(const float* master, uint16_t* bf16, uint8_t* fp8, float* fp8_scale, hipStream_t s) {

@@ -13,6 +13,7 @@
 // writes it as one partial; partials are summed in a fixed order, so results are
 // deterministic.
 #include <algorithm>
+#include <cmath>
 
 #include "launch.hpp"
 
@@ -314,7 +315,60 @@ __global__ void k_grad_reduce_final(const float* tmp, float* grad, const float* 
   }
 }
 
+// Adam (bias-corrected) on one parameter; returns the new weight.
+__device__ __forceinline__ float adam_update(float w, float& m, float& v, float g, float c1, float c2, float lr) {
+  const float mk = 0.9f * m + 0.1f * g;
+  const float vk = 0.999f * v + 0.001f * g * g;
+  m = mk;
+  v = vk;
+  return w - lr * (mk / c1) / (sqrtf(vk / c2) + 1e-8f);
+}
+
+__device__ __forceinline__ float ema_update(float infer, float w, float decay) {
+  return decay > 0.0f ? fmaf(decay, infer - w, w) : w;
+}
+
+// One training step's tail in one launch: the groups' gradient sum (fixed order), the loss,
+// Adam on the master weights and the moving average of the inference weights.
+__global__ void k_reduce_adam_ema(const float* tmp, float* grad, const float* lp, uint32_t nb, float* loss_accum,
+                                  uint32_t n_rows_total, float* w, float* m, float* v, float c1, float c2, float lr,
+                                  float* infer, float decay) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < (uint32_t)kNParam) {
+    float g = 0.0f;
+    for (int gi = 0; gi < kRedGroups; ++gi) g += tmp[(uint64_t)gi * kNParam + k];
+    grad[k] = g;
+    const float wn = adam_update(w[k], m[k], v[k], g, c1, c2, lr);
+    w[k] = wn;
+    infer[k] = ema_update(infer[k], wn, decay);
+  }
+  if (k == 0 && loss_accum) {
+    float s = 0.0f;
+    for (uint32_t b = 0; b < nb; ++b) s += lp[b];
+    *loss_accum += s / (float)n_rows_total;
+  }
+}
+
+// Bias corrections of Adam step `step` (1-based), in double before rounding.
+inline void adam_corrections(uint64_t step, float& c1, float& c2) {
+  const double t = (double)step;
+  c1 = (float)(1.0 - std::pow(0.9, t));
+  c2 = (float)(1.0 - std::pow(0.999, t));
+}
+
 }  // namespace
+
+void launch_grad_adam_ema(const float* grad_partial, uint32_t nblocks, float* grad, const float* loss_partial,
+                          float* loss_accum, uint32_t n_rows_total, float* master, float* m, float* v, uint64_t step,
+                          float lr, float* infer, float decay, hipStream_t s) {
+  float* tmp = const_cast<float*>(grad_partial) + (uint64_t)nblocks * kNParam;
+  const uint32_t bx = (kNParam + 255) / 256;
+  hipLaunchKernelGGL(k_grad_reduce_groups, dim3(bx, kRedGroups), dim3(256), 0, s, grad_partial, nblocks, tmp);
+  float c1, c2;
+  adam_corrections(step, c1, c2);
+  hipLaunchKernelGGL(k_reduce_adam_ema, dim3(bx), dim3(256), 0, s, tmp, grad, loss_partial, nblocks, loss_accum,
+                     n_rows_total, master, m, v, c1, c2, lr, infer, decay);
+}
 
 uint32_t mlp_grad_blocks(uint32_t n) { return (n + kTRows - 1) / kTRows; }
 uint32_t mlp_grad_scratch_floats(uint32_t max_rows) {
