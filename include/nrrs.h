@@ -198,7 +198,9 @@ typedef struct nrrs_tuning {
   uint32_t extend_refill;         /* idle lanes of a wave (1..64) that make it fetch new rays */
   uint32_t extend_leaf_batch;     /* parked leaves (1..64) that trigger intersection (1-4) */
   uint32_t extend_chunk;          /* queue entries a wave claims per atomic (0: exactly what its
-                                   * idle lanes need; else at least this many, up to 4096) */
+                                   * idle lanes need; else at least this many, up to 4096).
+                                   * The queue is claimed in 8 contiguous slices with a counter
+                                   * each; a wave starts in slice (block index mod 8) */
   uint32_t extend_max_blocks_per_cu[5]; /* out: occupancy limit of each variant (ignored by set) */
   float extend_ms;                /* out (nrrs_autotune): traversal time of the winner's pass */
 } nrrs_tuning;

@@ -45,6 +45,7 @@ struct nrrs_ctx {
   uint32_t ext_occ[5] = {1, 1, 1, 1, 1};  // resident traversal blocks per CU of each variant
   bool bvh4_ok = false;             // the 4-wide tree fits the traversal stack (variant 4)
   uint32_t* spill = nullptr;        // sized for cus * max(ext_occ) blocks
+  uint32_t* work = nullptr;         // traversal claim counters per depth and queue slice
   nrrs_tuning tune{};               // launch parameters of the traversal kernel
   // workspace
   uint8_t* ws = nullptr;
@@ -144,6 +145,7 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
   c->boff = k.take<uint32_t>(kScanBlocks);
   c->gsum = k.take<uint32_t>((uint64_t)kScanBlocks * kGuardSteps);
   c->ctl = k.take<DepthCtl>(NRRS_MAX_DEPTH + 2);
+  c->work = k.take<uint32_t>((uint64_t)(NRRS_MAX_DEPTH + 2) * kWorkSlices * kWorkStride);
   c->alpha = k.take<double>(1);
   c->overflow = k.take<uint32_t>(1);
   c->rays = k.take<unsigned long long>(3);
@@ -247,6 +249,7 @@ RenderArgs base_args(nrrs_ctx* c) {
   a.budget_base = (double)c->nprim;
   a.dbg_parent = nullptr;
   a.spill = c->spill;
+  a.work = c->work;
   a.trace_blocks = c->cus * c->tune.extend_blocks_per_cu;
   a.ext_variant = c->tune.extend_variant;
   a.ext_refill = c->tune.extend_refill;
@@ -319,11 +322,11 @@ int32_t nrrs_create(const nrrs_config* cfg, void* hip_stream, nrrs_ctx** out) {
   c->cap = cap;
   c->cus = (uint32_t)prop.multiProcessorCount;
   for (uint32_t v = 0; v < 5; ++v) c->ext_occ[v] = extend_blocks_per_cu(v);
-  c->tune.extend_variant = 1;
-  c->tune.extend_blocks_per_cu = c->ext_occ[1];
+  c->tune.extend_variant = 3;
+  c->tune.extend_blocks_per_cu = c->ext_occ[3];
   c->tune.extend_refill = 16;
-  c->tune.extend_leaf_batch = 32;
-  c->tune.extend_chunk = 0;
+  c->tune.extend_leaf_batch = 16;
+  c->tune.extend_chunk = 64;
   warm_mfma_launch_cache();
   *out = c;
   return NRRS_OK;
@@ -734,16 +737,17 @@ int32_t nrrs_autotune(nrrs_ctx* c, uint32_t max_depth, nrrs_tuning* best, nrrs_t
       win = t;
     }
   };
-  // 1: variant x refill threshold at full occupancy; 2: fewer resident blocks per CU; 3: claim
-  // chunk; 4: leaf batch (variants that park leaves)
+  // 1: variant x refill threshold at full occupancy (claim chunk 64, leaf batch 16); 2: fewer
+  // resident blocks per CU; 3: claim chunk; 4: leaf batch (variants that park leaves)
   for (uint32_t v = 0; v < 5; ++v) {
     if (v == 4 && !c->bvh4_ok) continue;
-    for (uint32_t refill : {16u, 32u, 48u, 64u}) {
+    for (uint32_t refill : {8u, 16u, 32u, 48u}) {
       nrrs_tuning t = cur;
       t.extend_variant = v;
       t.extend_blocks_per_cu = c->ext_occ[v];
       t.extend_refill = refill;
-      t.extend_chunk = 0;
+      t.extend_leaf_batch = 16;
+      t.extend_chunk = 64;
       consider(t);
     }
   }
@@ -761,7 +765,7 @@ int32_t nrrs_autotune(nrrs_ctx* c, uint32_t max_depth, nrrs_tuning* best, nrrs_t
   }
   {
     const nrrs_tuning base = win;
-    for (uint32_t ch : {64u, 128u, 256u}) {
+    for (uint32_t ch : {0u, 32u, 128u}) {
       nrrs_tuning t = base;
       t.extend_chunk = ch;
       consider(t);
@@ -769,7 +773,7 @@ int32_t nrrs_autotune(nrrs_ctx* c, uint32_t max_depth, nrrs_tuning* best, nrrs_t
   }
   if (win.extend_variant != 0) {
     const nrrs_tuning base = win;
-    for (uint32_t lb : {8u, 16u, 32u, 48u}) {
+    for (uint32_t lb : {8u, 16u, 24u, 32u}) {
       if (lb == base.extend_leaf_batch) continue;
       nrrs_tuning t = base;
       t.extend_leaf_batch = lb;
@@ -1014,6 +1018,7 @@ int32_t nrrs_debug_trace(nrrs_ctx* c, const float* rays, const uint32_t* exclude
   std::memset(&ctl, 0, sizeof(ctl));
   ctl.n = n;
   HIPC(c, hipMemcpy(c->ctl + 1, &ctl, sizeof(ctl), hipMemcpyHostToDevice));
+  launch_zero_u32(c->work, (uint64_t)(NRRS_MAX_DEPTH + 2) * kWorkSlices * kWorkStride, s);
   RenderArgs a = base_args(c);
   a.depth = 1;
   a.max_depth = 2;

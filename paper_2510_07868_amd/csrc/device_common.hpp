@@ -163,9 +163,14 @@ struct DepthCtl {
   uint32_t retries;    // alpha reductions applied
   double sumq;         // FP64 sum of the raw factors
   double F;            // normalization factor finally used
-  uint32_t work;       // next queue entry to hand to a traversal lane (persistent extend)
-  uint32_t pad;
+  uint32_t pad[2];
 };
+
+// The persistent traversal hands out the queue of one depth in kWorkSlices contiguous slices,
+// each with its own claim counter (counters kWorkStride words apart), so that claims are
+// spread over several addresses instead of serializing on one.
+constexpr uint32_t kWorkSlices = 8;
+constexpr uint32_t kWorkStride = 64;
 
 // ---------------------------------------------------------------------------------------
 // Wave64 helpers.

@@ -45,6 +45,7 @@ struct RenderArgs {
   double budget_base;   // N_px of Eq. (10): primary paths of the pass
   uint32_t* dbg_parent; // when set, the expansion also writes each child's parent index
   uint32_t* spill;      // traversal stack spill area [spill depth][trace_blocks * threads]
+  uint32_t* work;       // traversal claim counters [max_depth + 2][kWorkSlices][kWorkStride]
   uint32_t trace_blocks;  // persistent traversal grid (blocks)
   uint32_t ext_variant;   // 0: leaves intersected at once, 1: leaves parked and batched per wave
   uint32_t ext_refill;    // idle lanes (1..64) at which a traversal wave fetches new rays

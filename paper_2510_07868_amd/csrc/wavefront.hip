@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kEntryThreads) void k_camera(RenderArgs a) {
     a.ctl[1].n = a.nprim;
     a.ctl[a.max_depth].S = 0;
   }
-  if (k <= a.max_depth) a.ctl[k].work = 0;
+  if (k < (a.max_depth + 1) * kWorkSlices) a.work[(uint64_t)k * kWorkStride] = 0;
   if (k >= a.nprim) return;
   const uint32_t npx = a.width * a.height;
   const uint32_t pix = k % npx;
@@ -267,17 +267,21 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
   __syncthreads();
   const DevScene& sc = a.sc;
   const uint32_t n = a.ctl[a.depth].n;
-  uint32_t* work = &a.ctl[a.depth].work;
+  uint32_t* const work = a.work + (uint64_t)a.depth * kWorkSlices * kWorkStride;
   LaneStack st{stack_lds, a.spill + blockIdx.x * kTraceThreads + tid, gridDim.x * kTraceThreads, tid, 0};
   const int refill = (int)a.ext_refill;
   const int leaf_batch = (int)a.ext_leaf_batch;
   const uint32_t chunk = a.ext_chunk;
   bool active = false, exhausted = false;
   uint32_t ray = 0, excl = 0, ni = 0, pend = 0;
-  // wave-uniform pool of claimed queue entries not yet handed to a lane, [pool_next, pool_end);
-  // `drained` once a claim has reached the end of the queue
+  // wave-uniform pool of claimed queue entries not yet handed to a lane, [pool_next, pool_end).
+  // Claims start in slice blockIdx % kWorkSlices and move on to the next slice once one is
+  // used up; `drained` once every slice is.
   uint32_t pool_next = 0, pool_end = 0;
-  bool drained = false;
+  uint32_t slice = blockIdx.x % kWorkSlices, slices_left = kWorkSlices;
+  uint32_t s_lo = (uint32_t)((uint64_t)n * slice / kWorkSlices);
+  uint32_t s_hi = (uint32_t)((uint64_t)n * (slice + 1) / kWorkSlices);
+  bool drained = n == 0;
   V3 o = v3(0, 0, 0), d = o, inv = o, oi = o;
   HitState h;
   uint32_t c_rays = 0, c_nodes = 0, c_tris = 0;
@@ -290,17 +294,26 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
         const uint32_t have = pool_end - pool_next;
         uint32_t my = rank < have ? pool_next + rank : 0xFFFFFFFFu;
         if (have < want && !drained) {
-          // claim what the idle lanes still need, or a whole chunk of entries
+          // claim what the idle lanes still need, or a whole chunk of entries, from the
+          // current slice; a claim that reaches the slice's end moves on to the next slice
           const uint32_t take = max(chunk, want - have);
           const int leader = __ffsll((unsigned long long)idle) - 1;
           uint32_t b = 0;
-          if ((int)__lane_id() == leader) b = atomicAdd(work, take);
-          const uint32_t fresh = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(b, leader));
-          const uint64_t end = (uint64_t)fresh + take;
-          drained = end >= n;
-          if (rank >= have) my = fresh + (rank - have);
-          pool_end = (uint32_t)(end < n ? end : (uint64_t)n);
-          pool_next = min(fresh + (want - have), pool_end);
+          if ((int)__lane_id() == leader) b = atomicAdd(work + slice * kWorkStride, take);
+          const uint32_t off = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(b, leader));
+          const uint32_t size = s_hi - s_lo;
+          const uint32_t fresh = s_lo + min(off, size);
+          const uint32_t end = s_lo + (uint32_t)min((uint64_t)off + take, (uint64_t)size);
+          if (rank >= have) my = fresh + (rank - have) < end ? fresh + (rank - have) : 0xFFFFFFFFu;
+          pool_end = end;
+          pool_next = min(fresh + (want - have), end);
+          if (end == s_hi) {
+            --slices_left;
+            drained = slices_left == 0;
+            slice = slice + 1 == kWorkSlices ? 0 : slice + 1;
+            s_lo = (uint32_t)((uint64_t)n * slice / kWorkSlices);
+            s_hi = (uint32_t)((uint64_t)n * (slice + 1) / kWorkSlices);
+          }
         } else {
           pool_next += min(want, have);
         }
@@ -966,7 +979,9 @@ inline uint32_t blocks_for(uint64_t n, int threads) { return (uint32_t)((n + thr
 }  // namespace
 
 void launch_camera(const RenderArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_camera, dim3(blocks_for(a.nprim, kEntryThreads)), dim3(kEntryThreads), 0, s, a);
+  // enough threads for the primary rays and for clearing every depth's claim counters
+  const uint32_t nthreads = std::max(a.nprim, (a.max_depth + 1) * kWorkSlices);
+  hipLaunchKernelGGL(k_camera, dim3(blocks_for(nthreads, kEntryThreads)), dim3(kEntryThreads), 0, s, a);
 }
 void launch_extend(const RenderArgs& a, hipStream_t s) {
   if (a.ext_variant == 4)

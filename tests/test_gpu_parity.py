@@ -150,6 +150,36 @@ def test_closest_hit_matches_oracle(O, nrrs_mod, scenes):
             assert np.allclose(gt[hit], ot[hit], rtol=1e-5, atol=1e-6)
 
 
+def test_every_queue_entry_traced_once_for_small_and_ragged_batches(O, nrrs_mod, scenes):
+    # the queue is claimed in slices with a counter each: batches smaller than the slice count,
+    # ragged slice sizes and claims that cross a slice's end still give every entry its hit
+    sc = scenes.cornell()
+    r = make(nrrs_mod, sc, 64, 64)
+    osc = O.OracleScene(sc)
+    rng = np.random.default_rng(7)
+    lo = sc.verts.min(0).astype(np.float64)
+    hi = sc.verts.max(0).astype(np.float64)
+    n_max = 4099
+    o = lo + (hi - lo) * rng.uniform(0.2, 0.8, size=(n_max, 3))
+    d = rng.normal(size=(n_max, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rays32 = np.concatenate([o, d], 1).astype(np.float32)
+    away = rays32.copy()
+    away[:, :3] = (hi + 10.0).astype(np.float32)      # outside the box, pointing away: all miss
+    away[:, 3:] = np.float32(1.0 / np.sqrt(3.0))
+    op, _, _, _, frag = O.trace(osc, rays32.astype(np.float64), None, tau=1e-4, with_fragile=True)
+    assert (op[~frag] != O.MISS).mean() > 0.8           # from inside the box most rays hit a wall
+    occ = r.get_tuning()["extend_max_blocks_per_cu"]
+    for n in (1, 3, 7, 8, 9, 63, 65, 1000, 4099):
+        for variant, bpc, refill, batch, chunk in ((3, occ[3], 16, 16, 64), (3, 1, 1, 1, 0), (0, occ[0], 8, 1, 5),
+                                                   (1, 2, 64, 8, 4096)):
+            r.set_tuning(variant, bpc, refill, batch, chunk)
+            r.debug_trace(away[:n])
+            gp, _, _, _ = r.debug_trace(rays32[:n])
+            ok = ~frag[:n]
+            assert np.array_equal(gp[ok], op[:n][ok]), (n, variant, bpc, refill, batch, chunk)
+
+
 def test_autotune_picks_a_valid_launch_and_keeps_results(O, nrrs_mod, scenes):
     sc = scenes.cornell()
     r = make(nrrs_mod, sc, 64, 64, s_batch=4)
