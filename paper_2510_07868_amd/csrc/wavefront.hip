@@ -382,85 +382,92 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
         active = false;
       }
     } else {
-      if constexpr (kMode == 4) {
-        if (active && ni != kNoNode && pend == 0) {
-          ++c_nodes;
-          const float4* nd = sc.node4 + 8ull * ni;
-          const float4 lx = nd[0], hx = nd[1], ly = nd[2], hy = nd[3], lz = nd[4], hz = nd[5], lk = nd[6];
-          float k0, k1, k2, k3;
-          uint32_t c0 = bits(lk.x), c1 = bits(lk.y), c2 = bits(lk.z), c3 = bits(lk.w);
-          if (!(c0 != kEmptyChild4 && slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, inv, oi, h.t, k0))) k0 = kInf;
-          if (!(c1 != kEmptyChild4 && slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, inv, oi, h.t, k1))) k1 = kInf;
-          if (!(c2 != kEmptyChild4 && slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, inv, oi, h.t, k2))) k2 = kInf;
-          if (!(c3 != kEmptyChild4 && slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, inv, oi, h.t, k3))) k3 = kInf;
-          // ascending by entry distance (misses last): five compare-exchanges
-          sort2(k0, c0, k1, c1);
-          sort2(k2, c2, k3, c3);
-          sort2(k0, c0, k2, c2);
-          sort2(k1, c1, k3, c3);
-          sort2(k1, c1, k2, c2);
-          if (k3 != kInf) st.push(c3);
-          if (k2 != kInf) st.push(c2);
-          if (k1 != kInf) st.push(c1);
-          if (k0 != kInf) st.push(c0);
-          ni = kNoNode;
-        }
-      } else
-      if (active && ni != kNoNode && (kMode == 2 || pend == 0)) {
-        ++c_nodes;
-        const float4 n0 = sc.node[4 * ni], n1 = sc.node[4 * ni + 1], n2 = sc.node[4 * ni + 2],
-                     n3 = sc.node[4 * ni + 3];
-        float tn0, tn1;
-        const bool h0 = slab(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, inv, oi, h.t, tn0);
-        const bool h1 = slab(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, inv, oi, h.t, tn1);
-        const uint32_t l0 = bits(n3.x), l1 = bits(n3.y);
-        const bool first0 = tn0 <= tn1;
-        const bool f0 = h0 && (l0 & kLeafBit), f1 = h1 && (l1 & kLeafBit);
-        const bool i0 = h0 && !(l0 & kLeafBit), i1 = h1 && !(l1 & kLeafBit);
-        // leaves: the nearer one is parked if the lane has none, the others wait on the stack;
-        // a nearly full stack (possible only in mode 2) intersects them at once instead
-        if (f0 || f1) {
-          const uint32_t lnear = (f0 && (first0 || !f1)) ? l0 : l1;
-          const uint32_t lfar = (f0 && f1) ? (first0 ? l1 : l0) : 0u;
-          if (kMode == 2 && st.sp > kLeafPushLimit) {
-            if (lfar) test_leaf(sc, lfar, o, d, excl, h, c_tris);
-            test_leaf(sc, lnear, o, d, excl, h, c_tris);
-          } else {
-            if (lfar) st.push(lfar);
-            if (pend == 0) pend = lnear;
-            else st.push(lnear);
+      // Node phase: lanes without a parked leaf take one step each per round (visit a node, or
+      // pop the stack) until enough leaves are parked, no lane is still looking for one, or
+      // enough lanes have finished to make a refill worthwhile.
+      uint64_t parked, seeking;
+      for (;;) {
+        if (active) {
+          if constexpr (kMode == 4) {
+            if (ni != kNoNode && pend == 0) {
+              ++c_nodes;
+              const float4* nd = sc.node4 + 8ull * ni;
+              const float4 lx = nd[0], hx = nd[1], ly = nd[2], hy = nd[3], lz = nd[4], hz = nd[5], lk = nd[6];
+              float k0, k1, k2, k3;
+              uint32_t c0 = bits(lk.x), c1 = bits(lk.y), c2 = bits(lk.z), c3 = bits(lk.w);
+              if (!(c0 != kEmptyChild4 && slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, inv, oi, h.t, k0))) k0 = kInf;
+              if (!(c1 != kEmptyChild4 && slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, inv, oi, h.t, k1))) k1 = kInf;
+              if (!(c2 != kEmptyChild4 && slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, inv, oi, h.t, k2))) k2 = kInf;
+              if (!(c3 != kEmptyChild4 && slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, inv, oi, h.t, k3))) k3 = kInf;
+              // ascending by entry distance (misses last): five compare-exchanges
+              sort2(k0, c0, k1, c1);
+              sort2(k2, c2, k3, c3);
+              sort2(k0, c0, k2, c2);
+              sort2(k1, c1, k3, c3);
+              sort2(k1, c1, k2, c2);
+              if (k3 != kInf) st.push(c3);
+              if (k2 != kInf) st.push(c2);
+              if (k1 != kInf) st.push(c1);
+              if (k0 != kInf) st.push(c0);
+              ni = kNoNode;
+            }
+          } else if (ni != kNoNode && (kMode == 2 || pend == 0)) {
+            ++c_nodes;
+            const float4 n0 = sc.node[4 * ni], n1 = sc.node[4 * ni + 1], n2 = sc.node[4 * ni + 2],
+                         n3 = sc.node[4 * ni + 3];
+            float tn0, tn1;
+            const bool h0 = slab(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, inv, oi, h.t, tn0);
+            const bool h1 = slab(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, inv, oi, h.t, tn1);
+            const uint32_t l0 = bits(n3.x), l1 = bits(n3.y);
+            const bool first0 = tn0 <= tn1;
+            const bool f0 = h0 && (l0 & kLeafBit), f1 = h1 && (l1 & kLeafBit);
+            const bool i0 = h0 && !(l0 & kLeafBit), i1 = h1 && !(l1 & kLeafBit);
+            // leaves: the nearer one is parked if the lane has none, the others wait on the
+            // stack; a nearly full stack (possible only in mode 2) intersects them at once
+            if (f0 || f1) {
+              const uint32_t lnear = (f0 && (first0 || !f1)) ? l0 : l1;
+              const uint32_t lfar = (f0 && f1) ? (first0 ? l1 : l0) : 0u;
+              if (kMode == 2 && st.sp > kLeafPushLimit) {
+                if (lfar) test_leaf(sc, lfar, o, d, excl, h, c_tris);
+                test_leaf(sc, lnear, o, d, excl, h, c_tris);
+              } else {
+                if (lfar) st.push(lfar);
+                if (pend == 0) pend = lnear;
+                else st.push(lnear);
+              }
+            }
+            if (i0 && i1) {
+              ni = first0 ? l0 : l1;
+              st.push(first0 ? l1 : l0);
+            } else {
+              ni = i0 ? l0 : (i1 ? l1 : kNoNode);
+            }
+          }
+          if (ni == kNoNode && pend == 0) {
+            if (st.sp > 0) {
+              const uint32_t e = st.pop();
+              if (e & kLeafBit) pend = e;
+              else ni = e;
+            } else {
+              a.hit[ray] = make_float4(h.t, h.b1, h.b2, __uint_as_float(h.prim));
+              active = false;
+            }
           }
         }
-        if (i0 && i1) {
-          ni = first0 ? l0 : l1;
-          st.push(first0 ? l1 : l0);
-        } else {
-          ni = i0 ? l0 : (i1 ? l1 : kNoNode);
-        }
+        parked = __ballot(active && pend != 0);
+        seeking = __ballot(active && pend == 0);
+        if (seeking == 0 || __popcll(parked) >= leaf_batch) break;
+        if (!exhausted && __popcll(~(parked | seeking)) >= refill) break;
       }
-      if (active && ni == kNoNode && pend == 0) {
-        if (st.sp > 0) {
-          const uint32_t e = st.pop();
-          if (e & kLeafBit) pend = e;
-          else ni = e;
-        } else {
-          a.hit[ray] = make_float4(h.t, h.b1, h.b2, __uint_as_float(h.prim));
-          active = false;
-        }
-      }
-      const uint64_t parked = __ballot(active && pend != 0);
-      if (parked != 0) {
-        const uint64_t seeking = __ballot(active && pend == 0);
-        if (seeking == 0 || __popcll(parked) >= leaf_batch) {
-          if constexpr (kMode >= 3) {
-            const int wbase = tid & ~63;
-            leaf_phase_shared(sc, active && pend != 0, pend, o, d, excl, h, c_tris, hit_keys + wbase,
-                              hit_slots + wbase);
-            if (active) pend = 0;
-          } else if (active && pend != 0) {
-            test_leaf(sc, pend, o, d, excl, h, c_tris);
-            pend = 0;
-          }
+      if (parked != 0 && (seeking == 0 || __popcll(parked) >= leaf_batch)) {
+        if constexpr (kMode >= 3) {
+          const int wbase = tid & ~63;
+          leaf_phase_shared(sc, active && pend != 0, pend, o, d, excl, h, c_tris, hit_keys + wbase,
+                            hit_slots + wbase);
+          if (active) pend = 0;
+        } else if (active && pend != 0) {
+          test_leaf(sc, pend, o, d, excl, h, c_tris);
+          pend = 0;
         }
       }
     }
