@@ -8,9 +8,10 @@
 // 8 (v / 4) + 4 (l / 32) + v % 4 of register v.  A layer's output registers are the next
 // product's B operand unchanged: the K order of that product follows the same unit order,
 // and the weights are read from LDS in that order.  The weight gradients (K = rows) need units
-// along the lanes instead, so deltas and activations go through a padded LDS transpose.  The
-// four waves of a block add their gradients into one LDS copy in a fixed order, and the block
-// writes it as one partial; partials are summed in a fixed order, so results are
+// along the lanes instead, so deltas and activations go through a padded LDS transpose.  For
+// the weight gradients each of the four waves owns one 32x32 output tile and runs K over the
+// rows of all four waves in order; bias sums are per-wave partials added in wave order.  The
+// block writes one partial gradient; partials are summed in a fixed order, so results are
 // deterministic.
 #include <algorithm>
 #include <cmath>
@@ -36,8 +37,10 @@ constexpr int kOffW3 = kOffW2 + 64 * kS2;         // W3 [64][kS2]
 constexpr int kOffB = kOffW3 + 64 * kS2;          // b1, b2, b3, w4 [64 each], b4
 constexpr int kOffScratch = kOffB + 4 * 64 + 4;   // per wave: X [32][kS1], D [64][kST], H [64][kST]
 constexpr int kWaveScratch = 32 * kS1 + 2 * 64 * kST;
-constexpr int kOffG = kOffScratch + kTWaves * kWaveScratch;  // block gradient [kNParam]
-constexpr int kOffRow = kOffG + kNParam + 3;                 // per-row loss and dz [2][kTRows]
+constexpr int kOffBias = kOffScratch + kTWaves * kWaveScratch;  // per-wave bias sums [kTWaves][kBiasPart]
+constexpr int kBiasPart = 4 * 64 + 4;                            // b3, w4, b2, b1 [64 each], b4
+constexpr int kOffRow = kOffBias + kTWaves * kBiasPart;          // per-row loss and dz [2][kTRows]
+static_assert(kTWaves == 4, "one 32x32 weight-gradient tile per wave");
 constexpr int kLdsFloats = kOffRow + 2 * kTRows;
 
 __device__ __forceinline__ float softplus_mod(float z) { return z < 0.0f ? log1pf(expf(z)) : 0.5f * z + 0.69314718055994531f; }
@@ -45,6 +48,20 @@ __device__ __forceinline__ float softplus_mod_grad(float z) { return z < 0.0f ? 
 
 // hidden unit held by register v of tile t in lane half h
 __device__ __forceinline__ int unit_of(int t, int v, int h) { return 32 * t + 8 * (v >> 2) + 4 * h + (v & 3); }
+
+// LDS offset (floats) of parameter p; four consecutive parameters starting at a multiple of 4
+// stay in one row of one section, so they land at consecutive offsets.
+__device__ __forceinline__ int param_lds(int p) {
+  static_assert(kB1 % 4 == 0 && kW2 % 4 == 0 && kB2 % 4 == 0 && kW3 % 4 == 0 && kB3 % 4 == 0 && kW4 % 4 == 0 &&
+                    kB4 % 4 == 0 && kW4 == kB3 + 64 && kB4 == kW4 + 64,
+                "parameter sections not float4-aligned");
+  if (p < kB1) return kOffW1 + (p / 20) * kS1 + p % 20;
+  if (p < kW2) return kOffB + (p - kB1);
+  if (p < kB2) return kOffW2 + ((p - kW2) >> 6) * kS2 + ((p - kW2) & 63);
+  if (p < kW3) return kOffB + 64 + (p - kB2);
+  if (p < kB3) return kOffW3 + ((p - kW3) >> 6) * kS2 + ((p - kW3) & 63);
+  return kOffB + 128 + (p - kB3);  // b3, w4, b4
+}
 
 __device__ __forceinline__ f32x16 mfma(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
@@ -68,22 +85,25 @@ __device__ __forceinline__ void layer64(const float* Ws, int ld, bool transposed
   }
 }
 
-// Gradient tile block dW[o][i] = sum_r D[o][r] H[i][r] for o in 64 units, i in `ni` tiles of 32
-// (D, H in LDS as [unit][kST]), added into the block gradient G[o * ldg + i] wave by wave.
-template <int kNi>
-__device__ __forceinline__ void weight_grad(const float* D, const float* H, int h, int c, f32x16 (&g)[2][2]) {
+// One 32x32 tile of a weight gradient, dW[32 mt + m][32 nt + n] = sum_r D[.][r] H[.][r] over the
+// rows of all waves of the block (wave w's D and H at scratch + w * kWaveScratch, as
+// [unit][kST]; H = X rows-major [row][kS1] when `x_input`), K in wave-then-row order.
+template <bool x_input>
+__device__ __forceinline__ f32x16 weight_grad_tile(const float* scratch, int mt, int nt, int h, int c) {
+  f32x16 r = {};
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+  for (int w = 0; w < kTWaves; ++w) {
+    const float* X = scratch + w * kWaveScratch;
+    const float* D = X + 32 * kS1;
+    const float* H = D + 64 * kST;
 #pragma unroll
-    for (int nt = 0; nt < kNi; ++nt) {
-      f32x16 r = {};
-#pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        const int rr = 2 * s + h;
-        r = mfma(D[(32 * mt + c) * kST + rr], H[(32 * nt + c) * kST + rr], r);
-      }
-      g[mt][nt] = r;
+    for (int s = 0; s < 16; ++s) {
+      const int rr = 2 * s + h;
+      const float b = x_input ? (c < 20 ? X[rr * kS1 + c] : 0.0f) : H[(32 * nt + c) * kST + rr];
+      r = mfma(D[(32 * mt + c) * kST + rr], b, r);
     }
+  }
+  return r;
 }
 
 __global__ __launch_bounds__(kTThreads) void k_mlp_grad_mfma(const float* x, const float* target,
@@ -95,22 +115,34 @@ __global__ __launch_bounds__(kTThreads) void k_mlp_grad_mfma(const float* x, con
   float* W2s = lds + kOffW2;
   float* W3s = lds + kOffW3;
   float* Bs = lds + kOffB;  // b1 [0,64), b2 [64,128), b3 [128,192), w4 [192,256), b4 [256]
-  float* G = lds + kOffG;
+  float* BiasPart = lds + kOffBias;
   float* RowLoss = lds + kOffRow;
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, h = l >> 5, c = l & 31;
-  for (int k = tid; k < 1280; k += kTThreads) W1s[(k / 20) * kS1 + k % 20] = master[kW1 + k];
-  for (int k = tid; k < 4096; k += kTThreads) {
-    W2s[(k >> 6) * kS2 + (k & 63)] = master[kW2 + k];
-    W3s[(k >> 6) * kS2 + (k & 63)] = master[kW3 + k];
+  {
+    // every parameter but b4 as float4 (all section boundaries are multiples of 4), loads
+    // issued together before the LDS stores
+    constexpr int kVec = (kNParam - 1) / 4;
+    constexpr int kPer = (kVec + kTThreads - 1) / kTThreads;
+    const float4* m4 = reinterpret_cast<const float4*>(master);
+    float4 wv[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int q = tid + j * kTThreads;
+      wv[j] = q < kVec ? m4[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int q = tid + j * kTThreads;
+      if (q < kVec) {
+        float* dst = lds + param_lds(4 * q);
+        dst[0] = wv[j].x;
+        dst[1] = wv[j].y;
+        dst[2] = wv[j].z;
+        dst[3] = wv[j].w;
+      }
+    }
+    if (tid == 0) Bs[256] = master[kB4];
   }
-  for (int k = tid; k < 64; k += kTThreads) {
-    Bs[k] = master[kB1 + k];
-    Bs[64 + k] = master[kB2 + k];
-    Bs[128 + k] = master[kB3 + k];
-    Bs[192 + k] = master[kW4 + k];
-  }
-  if (tid == 0) Bs[256] = master[kB4];
-  for (int k = tid; k < kNParam; k += kTThreads) G[k] = 0.0f;
   float* Xs = lds + kOffScratch + wave * kWaveScratch;  // [32 rows][kS1]
   float* Ds = Xs + 32 * kS1;                            // [64 units][kST]
   float* Hs = Ds + 64 * kST;                            // [64 units][kST]
@@ -195,33 +227,26 @@ __global__ __launch_bounds__(kTThreads) void k_mlp_grad_mfma(const float* x, con
     gb4 += RowLoss[kTRows + wave * 32 + r];
   }
   __syncthreads();
+  float* bp = BiasPart + wave * kBiasPart;
+  bp[l] = gb3;
+  bp[64 + l] = gw4;
+  if (l == 0) bp[256] = gb4;
+  float* gp = grad_partial + (uint64_t)blockIdx.x * kNParam;
+  const int mt = wave >> 1, nt = wave & 1;  // this wave's weight-gradient tile
   // dW3 = D3 H2^T
 #pragma unroll
   for (int s = 0; s < 32; ++s) Hs[unit_of(s >> 4, s & 15, h) * kST + c] = H2[s];
   __syncthreads();
-  f32x16 g[2][2];
-  weight_grad<2>(Ds, Hs, h, c, g);
+  f32x16 g = weight_grad_tile<false>(lds + kOffScratch, mt, nt, h, c);
   // D2 = (W3^T D3) * relu'(H2)
   layer64(W3s, kS2, true, D, h, c, acc);
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int v = 0; v < 16; ++v) D[16 * t + v] = H2[16 * t + v] > 0.0f ? acc[t][v] : 0.0f;
-  // block sum of this wave's dW3, db3, dW4, db4 (waves in order)
-  for (int w = 0; w < kTWaves; ++w) {
-    if (wave == w) {
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-          for (int v = 0; v < 16; ++v) G[kW3 + 64 * unit_of(mt, v, h) + 32 * nt + c] += g[mt][nt][v];
-      G[kB3 + l] += gb3;
-      G[kW4 + l] += gw4;
-      if (l == 0) G[kB4] += gb4;
-    }
-    __syncthreads();
-  }
+  for (int v = 0; v < 16; ++v) gp[kW3 + 64 * unit_of(mt, v, h) + 32 * nt + c] = g[v];
+  __syncthreads();
   // ---- layer 2: dW2 = D2 H1^T, db2, D1 = (W2^T D2) * relu'(H1)
 #pragma unroll
   for (int s = 0; s < 32; ++s) {
@@ -232,55 +257,52 @@ __global__ __launch_bounds__(kTThreads) void k_mlp_grad_mfma(const float* x, con
   __syncthreads();
   float gb2 = 0.0f;
   for (int r = 0; r < 32; ++r) gb2 += Ds[l * kST + r];
-  weight_grad<2>(Ds, Hs, h, c, g);
+  bp[128 + l] = gb2;
+  g = weight_grad_tile<false>(lds + kOffScratch, mt, nt, h, c);
   layer64(W2s, kS2, true, D, h, c, acc);
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int v = 0; v < 16; ++v) D[16 * t + v] = H1[16 * t + v] > 0.0f ? acc[t][v] : 0.0f;
-  for (int w = 0; w < kTWaves; ++w) {
-    if (wave == w) {
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-          for (int v = 0; v < 16; ++v) G[kW2 + 64 * unit_of(mt, v, h) + 32 * nt + c] += g[mt][nt][v];
-      G[kB2 + l] += gb2;
-    }
-    __syncthreads();
-  }
-  // ---- layer 1: dW1 = D1 X^T (20 inputs in one 32-wide tile), db1
+  for (int v = 0; v < 16; ++v) gp[kW2 + 64 * unit_of(mt, v, h) + 32 * nt + c] = g[v];
+  __syncthreads();
+  // ---- layer 1: dW1 = D1 X^T (20 inputs in one 32-wide tile, waves 0 and 1), db1
 #pragma unroll
   for (int s = 0; s < 32; ++s) Ds[unit_of(s >> 4, s & 15, h) * kST + c] = D[s];
   __syncthreads();
   float gb1 = 0.0f;
   for (int r = 0; r < 32; ++r) gb1 += Ds[l * kST + r];
-  f32x16 g1[2];
+  bp[192 + l] = gb1;
+  if (wave < 2) {
+    g = weight_grad_tile<true>(lds + kOffScratch, wave, 0, h, c);
+    if (c < 20) {
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt) {
-    f32x16 r = {};
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int rr = 2 * s + h;
-      r = mfma(Ds[(32 * mt + c) * kST + rr], c < 20 ? Xs[rr * kS1 + c] : 0.0f, r);
+      for (int v = 0; v < 16; ++v) gp[kW1 + 20 * unit_of(wave, v, h) + c] = g[v];
     }
-    g1[mt] = r;
   }
-  for (int w = 0; w < kTWaves; ++w) {
-    if (wave == w) {
-      if (c < 20) {
+  __syncthreads();
+  // biases: per-wave sums added in wave order
+  if (wave == 0) {
+    float s3 = 0.0f, s4 = 0.0f, s2 = 0.0f, s1 = 0.0f;
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-          for (int v = 0; v < 16; ++v) G[kW1 + 20 * unit_of(mt, v, h) + c] += g1[mt][v];
-      }
-      G[kB1 + l] += gb1;
+    for (int w = 0; w < kTWaves; ++w) {
+      const float* q = BiasPart + w * kBiasPart;
+      s3 += q[l];
+      s4 += q[64 + l];
+      s2 += q[128 + l];
+      s1 += q[192 + l];
     }
-    __syncthreads();
+    gp[kB3 + l] = s3;
+    gp[kW4 + l] = s4;
+    gp[kB2 + l] = s2;
+    gp[kB1 + l] = s1;
+    if (l == 0) {
+      float s0 = 0.0f;
+      for (int w = 0; w < kTWaves; ++w) s0 += BiasPart[w * kBiasPart + 256];
+      gp[kB4] = s0;
+    }
   }
-  float* gp = grad_partial + (uint64_t)blockIdx.x * kNParam;
-  for (int k = tid; k < kNParam; k += kTThreads) gp[k] = G[k];
   if (tid == 0) {
     float sum = 0.0f;
     for (int r = 0; r < kTRows; ++r) sum += RowLoss[r];
@@ -328,15 +350,17 @@ __device__ __forceinline__ float ema_update(float infer, float w, float decay) {
   return decay > 0.0f ? fmaf(decay, infer - w, w) : w;
 }
 
-// One training step's tail in one launch: the groups' gradient sum (fixed order), the loss,
+// One training step's tail in one launch: the block partials summed in block order, the loss,
 // Adam on the master weights and the moving average of the inference weights.
-__global__ void k_reduce_adam_ema(const float* tmp, float* grad, const float* lp, uint32_t nb, float* loss_accum,
-                                  uint32_t n_rows_total, float* w, float* m, float* v, float c1, float c2, float lr,
-                                  float* infer, float decay) {
+__global__ __launch_bounds__(256) void k_grad_adam_ema(const float* gp, uint32_t nb, float* grad, const float* lp,
+                                                       float* loss_accum, uint32_t n_rows_total, float* w, float* m,
+                                                       float* v, float c1, float c2, float lr, float* infer,
+                                                       float decay) {
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < (uint32_t)kNParam) {
     float g = 0.0f;
-    for (int gi = 0; gi < kRedGroups; ++gi) g += tmp[(uint64_t)gi * kNParam + k];
+#pragma unroll 8
+    for (uint32_t b = 0; b < nb; ++b) g += gp[(uint64_t)b * kNParam + k];
     grad[k] = g;
     const float wn = adam_update(w[k], m[k], v[k], g, c1, c2, lr);
     w[k] = wn;
@@ -344,6 +368,7 @@ __global__ void k_reduce_adam_ema(const float* tmp, float* grad, const float* lp
   }
   if (k == 0 && loss_accum) {
     float s = 0.0f;
+#pragma unroll 8
     for (uint32_t b = 0; b < nb; ++b) s += lp[b];
     *loss_accum += s / (float)n_rows_total;
   }
@@ -361,13 +386,10 @@ inline void adam_corrections(uint64_t step, float& c1, float& c2) {
 void launch_grad_adam_ema(const float* grad_partial, uint32_t nblocks, float* grad, const float* loss_partial,
                           float* loss_accum, uint32_t n_rows_total, float* master, float* m, float* v, uint64_t step,
                           float lr, float* infer, float decay, hipStream_t s) {
-  float* tmp = const_cast<float*>(grad_partial) + (uint64_t)nblocks * kNParam;
-  const uint32_t bx = (kNParam + 255) / 256;
-  hipLaunchKernelGGL(k_grad_reduce_groups, dim3(bx, kRedGroups), dim3(256), 0, s, grad_partial, nblocks, tmp);
   float c1, c2;
   adam_corrections(step, c1, c2);
-  hipLaunchKernelGGL(k_reduce_adam_ema, dim3(bx), dim3(256), 0, s, tmp, grad, loss_partial, nblocks, loss_accum,
-                     n_rows_total, master, m, v, c1, c2, lr, infer, decay);
+  hipLaunchKernelGGL(k_grad_adam_ema, dim3((kNParam + 255) / 256), dim3(256), 0, s, grad_partial, nblocks, grad,
+                     loss_partial, loss_accum, n_rows_total, master, m, v, c1, c2, lr, infer, decay);
 }
 
 uint32_t mlp_grad_blocks(uint32_t n) { return (n + kTRows - 1) / kTRows; }

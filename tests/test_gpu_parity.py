@@ -316,13 +316,13 @@ def test_mlp_forward_fp32_matches_oracle(O, nrrs_mod, scenes):
     assert np.allclose(y, oy, rtol=1e-5, atol=1e-6)
 
 
-@pytest.mark.parametrize("loss_kind", [0, 1])
-def test_mlp_grad_matches_oracle(O, nrrs_mod, scenes, loss_kind):
+@pytest.mark.parametrize("loss_kind,n", [(0, 2048), (1, 2048), (0, 1999), (1, 77)])
+def test_mlp_grad_matches_oracle(O, nrrs_mod, scenes, loss_kind, n):
+    # whole 128-row blocks and ragged tails (rows past n add nothing)
     r = make(nrrs_mod, scenes.cornell(), 256, 256, loss=loss_kind)
     rng = np.random.default_rng(6)
     P = rng.normal(0, 0.25, size=9729).astype(np.float32)
     r.set_params(P)
-    n = 2048
     x = rng.normal(0, 1, size=(n, 20)).astype(np.float32)
     tgt = rng.uniform(0, 3, size=n).astype(np.float32)
     loss, g = r.debug_mlp_grad(x, tgt)
