@@ -1040,11 +1040,11 @@ int32_t or_render(const or_scene* s, or_cfg* cfg, const double* params, double* 
   int32_t status = 0;
   for (uint32_t pp = 0; pp < cfg->n_passes && status == 0; ++pp) {
     uint32_t pass = cfg->pass_begin + pp;
-    /* camera: primary path k covers pixel k mod (W*H) */
+    /* camera: primary path k is sample k mod s_batch of pixel floor(k / s_batch) */
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < (int64_t)nprim; ++k) {
       entry* e = &Q[k];
-      uint32_t pix = (uint32_t)(k % npx);
+      uint32_t pix = (uint32_t)(k / cfg->s_batch);
       uint32_t r[4];
       rng_block(cfg->seed, (uint32_t)k, pass, PURPOSE_CAMERA, 0, 0, r);
       camera_ray(s, cfg->width, cfg->height, pix % cfg->width, pix / cfg->width, u01(r[0]), u01(r[1]), e->o, e->d);
@@ -1186,7 +1186,7 @@ int32_t or_enumerate(const or_scene* s, const or_cfg* cfg, double* image_expect,
   uint32_t pass = cfg->pass_begin;
   for (uint64_t k = 0; k < nprim; ++k) {
     entry* e = &Q[k];
-    uint32_t pix = (uint32_t)(k % npx);
+    uint32_t pix = (uint32_t)(k / cfg->s_batch);
     uint32_t r[4];
     rng_block(cfg->seed, (uint32_t)k, pass, PURPOSE_CAMERA, 0, 0, r);
     camera_ray(s, cfg->width, cfg->height, pix % cfg->width, pix / cfg->width, u01(r[0]), u01(r[1]), e->o, e->d);

@@ -40,8 +40,9 @@ __global__ __launch_bounds__(kEntryThreads) void k_camera(RenderArgs a) {
   }
   if (k < (a.max_depth + 1) * kWorkSlices) a.work[(uint64_t)k * kWorkStride] = 0;
   if (k >= a.nprim) return;
-  const uint32_t npx = a.width * a.height;
-  const uint32_t pix = k % npx;
+  // primary path k is sample k mod s_batch of pixel k / s_batch: a pixel's paths stay adjacent
+  const uint32_t s_batch = a.nprim / (a.width * a.height);
+  const uint32_t pix = k / s_batch;
   const uint32_t px = pix % a.width, py = pix / a.width;
   const uint2 lin = make_uint2(k, a.pass_state->pass);
   const uint4 r = draw(a.key, lin, kPurposeCamera, 0, 0);
@@ -487,19 +488,43 @@ __global__ __launch_bounds__(kTraceThreads) __attribute__((amdgpu_waves_per_eu(7
 __global__ __launch_bounds__(kTraceThreads) void k_extend_immediate(RenderArgs a) { extend_body<0>(a); }
 
 // ------------------------------------------------------------------------------- shade
-__device__ __forceinline__ void emit(const RenderArgs& a, uint32_t pix, V3 t, V3 le, int4 rec) {
-  const V3 c = mul(t, le);
-  double* px = a.image + 3ull * pix;
-  atomicAdd(px + 0, (double)c.x);
-  atomicAdd(px + 1, (double)c.y);
-  atomicAdd(px + 2, (double)c.z);
-  if (a.records_on) {
-    const float l = lum(c);
-    if (rec.x >= 0) atomicAdd(a.rec.acc + rec.x, l);
-    if (rec.y >= 0) atomicAdd(a.rec.acc + rec.y, l);
-    if (rec.z >= 0) atomicAdd(a.rec.acc + rec.z, l);
-    if (rec.w >= 0) atomicAdd(a.rec.acc + rec.w, l);
+constexpr uint32_t kNoPix = 0xFFFFFFFFu;
+
+// FP64 image accumulation of one wave's emissions: lanes with the same pixel in consecutive
+// lanes (queue entries of one pixel are adjacent: primary paths are pixel-major and
+// compaction keeps parent order) are summed by a segmented scan, and the last lane of each
+// run adds the run's total with one atomic per channel.  Lanes without a pixel pass kNoPix.
+// Every lane of the wave must call it.
+__device__ __forceinline__ void image_add_wave(const RenderArgs& a, uint32_t pix, double cx, double cy, double cz) {
+  const int lane = (int)__lane_id();
+  const uint32_t prev = (uint32_t)__shfl_up((int)pix, 1);
+  const uint64_t heads = __ballot(lane == 0 || prev != pix);
+  const int start = 63 - __clzll(heads & ((2ull << lane) - 1ull));  // first lane of this run
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double tx = __shfl_up(cx, off), ty = __shfl_up(cy, off), tz = __shfl_up(cz, off);
+    if (lane - off >= start) {
+      cx += tx;
+      cy += ty;
+      cz += tz;
+    }
   }
+  const uint32_t next = (uint32_t)__shfl_down((int)pix, 1);
+  if ((lane == 63 || next != pix) && pix != kNoPix && (cx != 0.0 || cy != 0.0 || cz != 0.0)) {
+    double* px = a.image + 3ull * pix;
+    atomicAdd(px + 0, cx);
+    atomicAdd(px + 1, cy);
+    atomicAdd(px + 2, cz);
+  }
+}
+
+// Emission credited to the training records of the path's recorded vertices.
+__device__ __forceinline__ void record_emission(const RenderArgs& a, V3 c, int4 rec) {
+  const float l = lum(c);
+  if (rec.x >= 0) atomicAdd(a.rec.acc + rec.x, l);
+  if (rec.y >= 0) atomicAdd(a.rec.acc + rec.y, l);
+  if (rec.z >= 0) atomicAdd(a.rec.acc + rec.z, l);
+  if (rec.w >= 0) atomicAdd(a.rec.acc + rec.w, l);
 }
 
 // Record slots for a whole block with one counter atomic: per-wave counts in LDS, a block
@@ -536,14 +561,16 @@ __global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
   const uint32_t flags = bits(th.w);
   float q = 0.0f;
   bool want_rec = false;
-  V3 t = xyz(th), p = v3(0, 0, 0), nrm = p, wo = p;
+  V3 t = xyz(th), p = v3(0, 0, 0), nrm = p, wo = p, em = p;
   float4 m0 = make_float4(0, 0, 0, 0);
   uint32_t type = 0, pix = 0;
+  bool emits = false;
   if (in_range && !(flags & kFlagDead)) {
     pix = bits(dr.w);
     const uint32_t prim = bits(hh.w);
     if (prim == kMiss) {
-      emit(a, pix, t, v3(a.sc.env_r, a.sc.env_g, a.sc.env_b), rec);
+      em = mul(t, v3(a.sc.env_r, a.sc.env_g, a.sc.env_b));
+      emits = true;
     } else {
       const float4 a0 = a.sc.tri[3 * prim], a1 = a.sc.tri[3 * prim + 1], a2 = a.sc.tri[3 * prim + 2];
       const V3 e1 = xyz(a1), e2 = xyz(a2);
@@ -556,7 +583,10 @@ __global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
       m0 = a.sc.mat[2 * mid];
       const float4 m1 = a.sc.mat[2 * mid + 1];
       type = bits(m1.w);
-      if (front && (m1.x != 0.0f || m1.y != 0.0f || m1.z != 0.0f)) emit(a, pix, t, xyz(m1), rec);
+      if (front && (m1.x != 0.0f || m1.y != 0.0f || m1.z != 0.0f)) {
+        em = mul(t, xyz(m1));
+        emits = true;
+      }
       if (a.depth < a.max_depth && type != 2u) {
         q = a.mode == 0u ? 1.0f : lum(mul(t, xyz(m0)));
         want_rec = a.records_on && (flags & kFlagTrain) && a.depth <= a.net_max_depth && a.depth <= (uint32_t)kMaxRec;
@@ -566,6 +596,8 @@ __global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
     }
   }
   if (in_range) a.q[i] = q;
+  image_add_wave(a, in_range && !(flags & kFlagDead) ? pix : kNoPix, (double)em.x, (double)em.y, (double)em.z);
+  if (emits && a.records_on) record_emission(a, em, rec);
   // training record: one counter atomic per block (converged code)
   if (a.records_on) {
     const uint32_t slot = block_alloc(a.rec.count, want_rec, alloc_sh);
