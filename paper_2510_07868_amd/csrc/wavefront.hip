@@ -713,7 +713,9 @@ __global__ __launch_bounds__(kScanThreads) void k_roulette_count(RenderArgs a) {
     const uint32_t i = base + threadIdx.x;
     if (i < n && i < beg + chunk) {
       const float q = a.q[i];
-      if (q > 0.0f) acc += child_count(q, F, roulette_u(a, i));
+      const uint32_t x = q > 0.0f ? child_count(q, F, roulette_u(a, i)) : 0u;
+      a.offs[i] = x;  // kept for k_offsets unless the overflow guard changes the factor
+      acc += x;
     }
   }
   const uint32_t s = block_sum(acc, sh);
@@ -855,6 +857,8 @@ __global__ __launch_bounds__(kScanThreads) void k_offsets(RenderArgs a) {
   const uint32_t chunk = chunk_of(n);
   const uint32_t beg = blockIdx.x * chunk;
   const double F = a.ctl[a.depth].F;
+  // the counts k_roulette_count stored are final unless the guard chose a smaller alpha
+  const bool stored = a.ctl[a.depth].guard == 0;
   uint32_t run = a.boff[blockIdx.x];
   const int tid = threadIdx.x, wave = tid >> 6;
   int buf = 0;
@@ -862,8 +866,12 @@ __global__ __launch_bounds__(kScanThreads) void k_offsets(RenderArgs a) {
     const uint32_t i = base + tid;
     uint32_t x = 0;
     if (i < n && i < beg + chunk) {
-      const float q = a.q[i];
-      if (q > 0.0f) x = child_count(q, F, roulette_u(a, i));
+      if (stored) {
+        x = a.offs[i];
+      } else {
+        const float q = a.q[i];
+        if (q > 0.0f) x = child_count(q, F, roulette_u(a, i));
+      }
     }
     const uint32_t incl = wave_incl_scan(x);
     if ((tid & 63) == 63) wsum[buf][wave] = incl;
