@@ -60,7 +60,8 @@ __global__ __launch_bounds__(kEntryThreads) void k_camera(RenderArgs a) {
   a.qin.dir[k] = pack(d, pix);
   a.qin.thr[k] = make_float4(1.0f, 1.0f, 1.0f, __uint_as_float(flags));
   a.qin.id[k] = lin;
-  a.qin.rec[k] = make_int4(-1, -1, -1, -1);
+  // record slots travel only with training paths (every reader checks kFlagTrain first)
+  if (flags & kFlagTrain) a.qin.rec[k] = make_int4(-1, -1, -1, -1);
 }
 
 // ------------------------------------------------------------------------------ extend
@@ -557,8 +558,8 @@ __global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
   const uint32_t i = in_range ? i0 : n - 1;
   // the entry's queue data in one round trip (dead entries are rare)
   const float4 th = a.qin.thr[i], dr = a.qin.dir[i], hh = a.hit[i];
-  int4 rec = a.records_on ? a.qin.rec[i] : make_int4(-1, -1, -1, -1);
   const uint32_t flags = bits(th.w);
+  int4 rec = a.records_on && (flags & kFlagTrain) ? a.qin.rec[i] : make_int4(-1, -1, -1, -1);
   float q = 0.0f;
   bool want_rec = false;
   V3 t = xyz(th), p = v3(0, 0, 0), nrm = p, wo = p, em = p;
@@ -942,7 +943,7 @@ __device__ __forceinline__ void expand_child(const RenderArgs& a, uint32_t i, ui
   a.qout.dir[s] = pack(wi, bits(dr.w));
   a.qout.thr[s] = pack(tc, flags);
   a.qout.id[s] = make_uint2(r.z, r.w);
-  if (a.records_on) a.qout.rec[s] = a.qin.rec[i];
+  if (a.records_on && (flags & kFlagTrain)) a.qout.rec[s] = a.qin.rec[i];
 }
 
 // Children of a block of kEntryThreads consecutive parents: the block's offsets go to LDS and
