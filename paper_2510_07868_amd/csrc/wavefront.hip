@@ -549,11 +549,21 @@ __device__ __forceinline__ uint32_t block_alloc(uint32_t* counter, bool pred, ui
   return sh[kWaves] + sh[wave] + lanes_below(m);
 }
 
+constexpr uint32_t kShadeStripes = 64;
+
 __global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
   __shared__ uint32_t alloc_sh[kShadeThreads / 64 + 1];
   const uint32_t n = a.ctl[a.depth].n;
-  if (blockIdx.x * blockDim.x >= n) return;  // uniform over the block
-  const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t tiles = (n + kShadeThreads - 1) / kShadeThreads;
+  if (blockIdx.x >= tiles) return;  // uniform over the block
+  // Blocks take the queue's tiles interleaved over kShadeStripes stripes, so that the blocks
+  // that run first (and take the first record slots) cover the whole image: with a pixel's
+  // paths adjacent in the queue, tiles in plain order would give the record buffer the top
+  // rows of the image first whenever it fills up.
+  const uint32_t per = tiles / kShadeStripes;
+  const uint32_t b = blockIdx.x;
+  const uint32_t tile = b < per * kShadeStripes ? (b % kShadeStripes) * per + b / kShadeStripes : b;
+  const uint32_t i0 = tile * kShadeThreads + threadIdx.x;
   const bool in_range = i0 < n;
   const uint32_t i = in_range ? i0 : n - 1;
   // the entry's queue data in one round trip (dead entries are rare)
