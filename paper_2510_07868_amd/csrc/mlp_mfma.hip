@@ -155,10 +155,15 @@ __device__ __forceinline__ f32x16 bias_tile(const float* b, int mt, int h) {
   return c;
 }
 
+// max(x, 0) as a signed-integer maximum of the bits: the same value for every non-NaN x
+// (negative values and -0 give +0), without the NaN-quieting canonicalization an IEEE fmaxf
+// needs on each operand.
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 __device__ __forceinline__ bf16x8 relu_bf16(const f32x16& c, int first) {
   bf16x8 r;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) r[i] = (__bf16)fmaxf(c[first + i], 0.0f);
+  for (int i = 0; i < 8; ++i) r[i] = (__bf16)relu(c[first + i]);
   return r;
 }
 
@@ -166,8 +171,8 @@ __device__ __forceinline__ float output_layer(const Smem& sm, const f32x16& c0, 
   float z = 0.0f;
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
-    z = fmaf(sm.w4[acc_row(v, h)], fmaxf(c0[v], 0.0f), z);
-    z = fmaf(sm.w4[32 + acc_row(v, h)], fmaxf(c1[v], 0.0f), z);
+    z = fmaf(sm.w4[acc_row(v, h)], relu(c0[v]), z);
+    z = fmaf(sm.w4[32 + acc_row(v, h)], relu(c1[v]), z);
   }
   z += __shfl_xor(z, 32);
   return z + sm.b4;
