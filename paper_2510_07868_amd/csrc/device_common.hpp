@@ -10,7 +10,7 @@ constexpr uint32_t kMiss = 0xffffffffu;
 constexpr int kMaxRec = 4;           // training records carried per path (depths 1..4)
 constexpr int kNParam = 9729;        // 20-64-64-64-1 network
 constexpr int kGuardSteps = 32;      // alpha reductions tried in one pass of the overflow guard
-constexpr int kScanBlocks = 1024;    // blocks of the chunked reductions / scans
+constexpr int kScanBlocks = 2048;    // blocks of the chunked reductions / scans
 constexpr int kScanThreads = 256;
 constexpr uint32_t kFlagDead = 1u;   // entry was emitted below the horizon: traced as nothing
 constexpr uint32_t kFlagTrain = 2u;  // entry belongs to a training path
