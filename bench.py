@@ -54,6 +54,28 @@ def counted_traffic():
     return out
 
 
+def counted_sq():
+    """Vector-instruction counters per dispatch from the committed rocprofv3 SQ summary, per
+    kernel, kept only while the kernel's source file is the one the counters were taken on."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_extend_heightfield512_sq_counters.md")
+    out = {}
+    if not os.path.exists(path):
+        return out
+    for line in open(path):
+        if not line.startswith("sq: "):
+            continue
+        _, kernel, insts, active, thread_cycles, src, digest = line.split()
+        try:
+            now = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()[:16]
+        except OSError:
+            continue
+        if now == digest:
+            out[kernel] = (float(insts), float(active), float(thread_cycles))
+    return out
+
+
 def relmse(img, ref):
     return float(np.mean((img - ref) ** 2 / (ref ** 2 + 0.01)))
 
@@ -176,6 +198,15 @@ def main():
                 "node_and_triangle_bytes_gbs": round(ext_bytes / (ext_ms * 1e-3) / 1e9, 1),
                 "hbm_gbs_counted": round(tb / (ext_ms * 1e-3) / 1e9, 1) if tb else None,
                 "dominant_stage": dom}
+    # vector-ALU issue: wave64 FP32 instructions take 4 cycles on one of 1024 SIMDs (256 CUs x 4)
+    # at 2.4 GHz; lane use = active lanes per executed vector instruction (SQ counters)
+    sq = counted_sq().get(ext_kernel)
+    if sq:
+        insts, active, thread_cycles = sq
+        roofline["valu_issue_busy"] = round(insts * 4.0 / (1024 * 2.4e9 * ext_ms * 1e-3), 3)
+        roofline["valu_lane_use"] = round(thread_cycles / (64.0 * active), 3)
+    else:
+        roofline["valu_issue_busy"] = roofline["valu_lane_use"] = None
 
     # the network stage: 19,072 useful FLOP per evaluated vertex (20-64-64-64-1)
     net_ms = stage_ms["network"] / max(stage_n["network"], 1)
