@@ -283,6 +283,81 @@ def test_full_size_heightfield_pass_matches_oracle(O, nrrs_mod, scenes):
     assert np.abs(st["n"][1:].astype(np.int64) - o["n"][1:].astype(np.int64)).max() <= 0.001 * W * H * spp
 
 
+def _sampled_hits_match_oracle(O, r, sc, n, seed):
+    # closest hits of n random rays from inside the scene's box: same triangle as the oracle's
+    # FP64 BVH traversal except for oracle-flagged near-ties, t within 1e-5
+    osc = O.OracleScene(sc)
+    rng = np.random.default_rng(seed)
+    lo = sc.verts.min(0).astype(np.float64)
+    hi = sc.verts.max(0).astype(np.float64)
+    o = lo + (hi - lo) * rng.uniform(0.0, 1.0, size=(n, 3))
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rays32 = np.concatenate([o, d], 1).astype(np.float32)
+    op, ot, _, _, frag = O.trace(osc, rays32.astype(np.float64), None, tau=1e-4, with_fragile=True)
+    gp, gt, _, _ = r.debug_trace(rays32)
+    ok = ~frag
+    hit = ok & (op != O.MISS)
+    assert ok.mean() > 0.95 and hit.sum() > n // 10
+    assert np.array_equal(gp[ok], op[ok])
+    assert np.allclose(gt[hit], ot[hit], rtol=1e-5, atol=1e-6)
+
+
+def _assert_bounded_counts(st, n_prim, D):
+    # the queue never overflows; every depth with a positive factor sum emits B = N_prim children
+    # in expectation (two-sided normalization, alpha = 1), within 8 standard deviations' worth
+    # of the bound sqrt(N_prim) on the spread of S
+    cap = 2 * n_prim
+    assert st["overflow"] == 0 and np.all(st["retries"][1:D] == 0)
+    assert np.all(st["S"][1:D] <= cap)
+    assert np.all(st["n"][2:D + 1] == st["S"][1:D])
+    live = st["sumq"][1:D] > 0
+    dev = np.abs(st["S"][1:D].astype(np.float64) - n_prim)[live]
+    assert live.any() and np.all(dev <= 8.0 * np.sqrt(n_prim)), dev.max()
+
+
+def test_full_size_1080p_5m_triangles_fp8_pass(O, nrrs_mod, scenes):
+    # the batched configuration at full size: 1920x1080, ~5.0 M triangles, one 8-spp pass of
+    # 16,588,800 paths (capacity 33,177,600), depth 32, FP8 network at depth <= 4 after a
+    # heuristic pass gives it a pixel estimate, captured passes; properties that hold at any
+    # size, plus sampled closest hits against the oracle
+    W, H, spp, D = 1920, 1080, 8, 32
+    sc = scenes.terrain5m(0)
+    r = make(nrrs_mod, sc, W, H, s_batch=spp, precision=nrrs_mod.PREC_FP8)
+    st0 = r.render(spp, D, nrrs_mod.MODE_HEURISTIC)
+    st1 = r.render(spp, D, nrrs_mod.MODE_NET)
+    for st in (st0, st1):
+        _assert_bounded_counts(st, W * H * spp, D)
+    img, n = r.read_image()
+    assert n == 2 * spp
+    assert np.all(np.isfinite(img)) and img.min() >= 0.0 and img.mean() > 0.0
+    _sampled_hits_match_oracle(O, r, sc, 4000, 21)
+
+
+def test_full_size_room_training_frames(O, nrrs_mod, scenes):
+    # the online-training configuration at full size: 1024x1024, ~2.1 M triangles lit through
+    # a ceiling opening, depth 24, frames of 4 spp in NET mode each followed by one train_step
+    # on 2^18 records (minibatches of 2^13); properties plus sampled closest hits
+    W = H = 1024
+    spp, D = 4, 24
+    sc = scenes.room(0)
+    r = make(nrrs_mod, sc, W, H, s_batch=spp, precision=nrrs_mod.PREC_BF16, records_cap=1 << 18, p_train=0.05)
+    losses = []
+    for frame in range(4):
+        st = r.render(spp, D, nrrs_mod.MODE_NET)
+        _assert_bounded_counts(st, W * H * spp, D)
+        assert st["records"] > 0
+        n = min(st["records"], 1 << 18) // (1 << 13) * (1 << 13)
+        assert n > 0
+        losses.append(r.train_step(n, 1 << 13, 5e-3))
+    assert all(np.isfinite(losses)), losses
+    P, m, v, step = r.get_params()
+    assert step > 0 and np.all(np.isfinite(P))
+    img, nspp = r.read_image()
+    assert nspp == 4 * spp and np.all(np.isfinite(img)) and img.mean() > 0.0
+    _sampled_hits_match_oracle(O, r, sc, 4000, 23)
+
+
 def test_net_mode_matches_oracle(O, nrrs_mod, scenes):
     W = H = 32
     D = 6
