@@ -319,8 +319,11 @@ struct Weights<2> {
 };
 
 // Network factors for the vertices of one depth: persistent waves over tiles of 32 entries.
+// At most 128 VGPRs (4 waves per SIMD), so that one wave's vector epilogue overlaps other
+// waves' matrix-core work.
 template <int P>
-__global__ __launch_bounds__(kThreads) void k_rrsnet_mfma(RenderArgs a, NetArgs net) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_rrsnet_mfma(RenderArgs a,
+                                                                                                 NetArgs net) {
   __shared__ Smem sm;
   __shared__ __attribute__((aligned(16))) uint8_t wsm[Weights<P>::kBytes];
   Weights<P> W;
