@@ -585,6 +585,33 @@ def test_image_relmse_of_each_precision_vs_oracle(O, nrrs_mod, scenes):
     assert out[1] < 1.0 and out[2] < 1.0
 
 
+def test_image_relmse_of_each_precision_vs_oracle_on_the_5m_triangle_scene(O, nrrs_mod, scenes):
+    # the same study on the batched configuration's 5.0 M-triangle terrain (30 % GGX) at a
+    # resolution the FP64 oracle renders in seconds: 96x96, 4 spp per pass, 2 passes, depth 8
+    W = H = 96
+    D = 8
+    sc = scenes.terrain5m(0)
+    rng = np.random.default_rng(29)
+    params = rng.normal(0, 0.2, size=9729).astype(np.float32)
+    guide = rng.uniform(0.05, 2.0, size=W * H).astype(np.float32)
+    osc = O.OracleScene(sc)
+    o = O.render(osc, O.make_cfg(W, H, 4, D, n_passes=2, mode=O.MODE_NET, tau=0.0),
+                 params=params.astype(np.float64), guide=guide.astype(np.float64))
+    ref = o["image"].reshape(-1, 3) / 8.0
+    out = {}
+    for prec in (0, 1, 2):
+        r = make(nrrs_mod, sc, W, H, s_batch=4, precision=prec)
+        r.set_params(params)
+        for p in range(2):
+            r.set_guide(guide)
+            r.render(4, D, nrrs_mod.MODE_NET)
+        img, _ = r.read_image()
+        out[prec] = float(np.mean((img.reshape(-1, 3) - ref) ** 2 / (ref ** 2 + 0.01)))
+    print("5M-triangle scene, image relMSE vs FP64 oracle: fp32 %.3e, bf16 %.3e, fp8 %.3e" % (out[0], out[1], out[2]))
+    assert out[0] < 1e-2
+    assert out[1] < 1.0 and out[2] < 1.0
+
+
 @pytest.mark.parametrize("mode", [1, 2])
 def test_graph_replay_matches_direct_launches(nrrs_mod, scenes, mode):
     # each render replays the captured pass; between renders the program does its own eager
