@@ -352,21 +352,31 @@ __device__ __forceinline__ float ema_update(float infer, float w, float decay) {
 
 // One training step's tail in one launch: the block partials summed in block order, the loss,
 // Adam on the master weights and the moving average of the inference weights.
+// A block handles 64 parameters with 4 waves: wave s sums the partials b = s, s + 4, ...
+// (consecutive lanes read consecutive parameters), the four sums are added in wave order.
+constexpr int kTailParams = 64;
 __global__ __launch_bounds__(256) void k_grad_adam_ema(const float* gp, uint32_t nb, float* grad, const float* lp,
                                                        float* loss_accum, uint32_t n_rows_total, float* w, float* m,
                                                        float* v, float c1, float c2, float lr, float* infer,
                                                        float decay) {
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ float part[4][kTailParams];
+  const uint32_t j = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const uint32_t k = blockIdx.x * kTailParams + j;
+  float g = 0.0f;
   if (k < (uint32_t)kNParam) {
-    float g = 0.0f;
 #pragma unroll 8
-    for (uint32_t b = 0; b < nb; ++b) g += gp[(uint64_t)b * kNParam + k];
+    for (uint32_t b = sl; b < nb; b += 4) g += gp[(uint64_t)b * kNParam + k];
+  }
+  part[sl][j] = g;
+  __syncthreads();
+  if (sl == 0 && k < (uint32_t)kNParam) {
+    g = ((part[0][j] + part[1][j]) + part[2][j]) + part[3][j];
     grad[k] = g;
     const float wn = adam_update(w[k], m[k], v[k], g, c1, c2, lr);
     w[k] = wn;
     infer[k] = ema_update(infer[k], wn, decay);
   }
-  if (k == 0 && loss_accum) {
+  if (blockIdx.x == 0 && threadIdx.x == 64 && loss_accum) {
     float s = 0.0f;
 #pragma unroll 8
     for (uint32_t b = 0; b < nb; ++b) s += lp[b];
@@ -388,8 +398,8 @@ void launch_grad_adam_ema(const float* grad_partial, uint32_t nblocks, float* gr
                           float lr, float* infer, float decay, hipStream_t s) {
   float c1, c2;
   adam_corrections(step, c1, c2);
-  hipLaunchKernelGGL(k_grad_adam_ema, dim3((kNParam + 255) / 256), dim3(256), 0, s, grad_partial, nblocks, grad,
-                     loss_partial, loss_accum, n_rows_total, master, m, v, c1, c2, lr, infer, decay);
+  hipLaunchKernelGGL(k_grad_adam_ema, dim3((kNParam + kTailParams - 1) / kTailParams), dim3(256), 0, s, grad_partial,
+                     nblocks, grad, loss_partial, loss_accum, n_rows_total, master, m, v, c1, c2, lr, infer, decay);
 }
 
 uint32_t mlp_grad_blocks(uint32_t n) { return (n + kTRows - 1) / kTRows; }
