@@ -232,6 +232,29 @@ def _compare_images(g, o, frag, rtol=1e-4):
     return bad, ok
 
 
+def test_normalized_rrs_unbiased_over_a_million_realizations(nrrs_mod, scenes):
+    # 64 passes of 16,384 realizations of the 8x8, 1-spp Cornell image (1,048,576 per mode,
+    # each pass normalized together): heuristic normalized RRS has the mean image luminance
+    # of plain path tracing within 3 standard errors of the 64 independent pass means
+    lum = np.array([0.2126, 0.7152, 0.0722])
+    means = {}
+    for mode, seed in ((nrrs_mod.MODE_HEURISTIC, 5), (nrrs_mod.MODE_OFF, 6)):
+        r = make(nrrs_mod, scenes.cornell(), 8, 8, s_batch=16384, seed=seed)
+        m = []
+        for k in range(64):
+            r.reset_image()
+            st = r.render(16384, 8, mode)
+            assert st["overflow"] == 0
+            img, n = r.read_image()
+            m.append(float((img.reshape(-1, 3) @ lum).mean()))
+        means[mode] = np.array(m)
+    h, p = means[nrrs_mod.MODE_HEURISTIC], means[nrrs_mod.MODE_OFF]
+    se = math.sqrt(h.var(ddof=1) / h.size + p.var(ddof=1) / p.size)
+    print("mean luminance: normalized RRS %.6f, plain %.6f, se %.2e" % (h.mean(), p.mean(), se))
+    assert abs(h.mean() - p.mean()) < 3.0 * se
+    assert se < 0.002 * p.mean()
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_cornell_image_matches_oracle(O, nrrs_mod, scenes, mode):
     W = H = 64

@@ -87,6 +87,26 @@ def test_normalized_rrs_is_unbiased_cornell(O, scenes):
     assert se < 0.02 * p.mean()
 
 
+def test_normalized_rrs_is_unbiased_cornell_200k_realizations(O, scenes):
+    # 204,800 realizations of the 8x8, 1-spp Cornell image per mode (passes of 1024 images each,
+    # normalized together), in 20 independent chunks: heuristic normalized RRS and plain path
+    # tracing have the same mean image luminance within 3 standard errors
+    sc = O.OracleScene(scenes.cornell())
+    lum = np.array([0.2126, 0.7152, 0.0722])
+    means = {}
+    for mode, seed in ((O.MODE_HEUR, 3), (O.MODE_OFF, 4)):
+        m = []
+        for c in range(20):
+            cfg = O.make_cfg(8, 8, 1024, 8, mode=mode, pass_begin=10 * c, n_passes=10, seed=seed, tau=0.0)
+            img = O.render(sc, cfg)["image"].reshape(-1, 3)
+            m.append(float((img @ lum).mean()) / (10 * 1024))
+        means[mode] = np.array(m)
+    h, p = means[O.MODE_HEUR], means[O.MODE_OFF]
+    se = math.sqrt(h.var(ddof=1) / h.size + p.var(ddof=1) / p.size)
+    assert abs(h.mean() - p.mean()) < 3.0 * se, (h.mean(), p.mean(), se)
+    assert se < 0.005 * p.mean()
+
+
 def test_net_mode_furnace_unbiased(O, scenes):
     # Network factors make q vary per vertex (splitting + roulette happen), the estimate
     # stays unbiased: the mean matches the furnace closed form.
