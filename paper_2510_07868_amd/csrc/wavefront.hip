@@ -245,8 +245,8 @@ struct LaneStack {
 constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 
 // Persistent BVH2 traversal.  Each lane holds one ray; when a.ext_refill lanes of a wave are
-// idle the wave takes a new batch of queue entries from a per-depth counter with one atomic,
-// so long rays do not hold a whole wave idle.
+// idle the wave takes a new batch of queue entries with one atomic on the counter of its
+// current queue slice, so long rays do not hold a whole wave idle.
 //   kMode 0: a lane intersects the triangles of a hit leaf child at once.
 //   kMode 1: a lane that reaches a leaf parks it and waits; the wave intersects the parked
 //     leaves together once a.ext_leaf_batch lanes hold one or no lane still looks for one, so
