@@ -182,7 +182,10 @@ int build_bvh(const float* verts, const uint32_t* tris, uint64_t nt, BvhOut& out
   if (root_link & 0x80000000u) {
     Builder::Node r{};
     r.b[0] = all;
-    r.b[1].reset();  // empty box: never hit
+    // The second child repeats triangle 0 behind an inverted box.  Slab tests order each
+    // axis's two distances, so rays may still enter it; testing triangle 0 twice leaves the
+    // closest hit unchanged (same distance, same index).
+    r.b[1].reset();
     r.link[0] = root_link;
     r.link[1] = Builder::leaf_link(0, 1);
     B.nodes.insert(B.nodes.begin(), r);
