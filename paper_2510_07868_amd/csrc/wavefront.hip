@@ -65,17 +65,25 @@ __global__ __launch_bounds__(kEntryThreads) void k_camera(RenderArgs a) {
 }
 
 // ------------------------------------------------------------------------------ extend
-// Robust slab test: the far distance is widened by 2^-20 so that rounding never culls a box
-// that the exact ray touches.
+// Conservative slab test.  A plane distance is computed as fma(l, inv, oi) with oi = -o * inv
+// rounded once, so it errs by at most 2u |t| + u |oi| (u = 2^-24): relative to t, plus an
+// absolute part from the rounding of oi that does not shrink with t (a box near an origin far
+// from the coordinate origin).  The far distance is therefore widened by 2^-20 relative and by
+// a per-ray eps = 2^-22 max|oi| absolute, which covers both errors on both ends, so rounding
+// does not cull a box that the exact ray touches.  eps takes |oi| only over the axes the ray is
+// not nearly parallel to (|d| >= 2^-10, bounding eps by 2^-12 |o|): on a nearly parallel axis
+// |oi| is huge and would open every box.  The one case left uncovered is a box whose entry or
+// exit is decided by a face the ray runs within 2^-10 of parallel to, with the exact overlap
+// below u |o| / |d| on that axis: a grazing pass along a box face.
 __device__ __forceinline__ bool slab(float lx, float ly, float lz, float hx, float hy, float hz, V3 inv, V3 oi,
-                                     float tmax, float& tnear) {
+                                     float eps, float tmax, float& tnear) {
   const float t0x = fmaf(lx, inv.x, oi.x), t1x = fmaf(hx, inv.x, oi.x);
   const float t0y = fmaf(ly, inv.y, oi.y), t1y = fmaf(hy, inv.y, oi.y);
   const float t0z = fmaf(lz, inv.z, oi.z), t1z = fmaf(hz, inv.z, oi.z);
   const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
   const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
   tnear = tn;
-  return tn <= tf * 1.00000095367431640625f;
+  return tn <= fmaf(tf, 1.00000095367431640625f, eps);
 }
 
 constexpr float kInf = __builtin_huge_valf();
@@ -174,7 +182,7 @@ __device__ __forceinline__ void leaf_phase_shared(const DevScene& sc, bool mine,
     pre += (uint32_t)lanes_below(m) << b;
     total += (uint32_t)__popcll(m) << b;
   }
-  tris += cnt;
+  tris += total;  // wave-uniform count of the (ray, triangle) pairs
   const unsigned long long start = hit_key(h.t, h.orig);
   if (mine) key[lane] = start;
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -285,8 +293,11 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
   uint32_t s_hi = (uint32_t)((uint64_t)n * (slice + 1) / kWorkSlices);
   bool drained = n == 0;
   V3 o = v3(0, 0, 0), d = o, inv = o, oi = o;
+  float eps = 0.0f;
   HitState h;
-  uint32_t c_rays = 0, c_nodes = 0, c_tris = 0;
+  // statistics: rays and nodes counted per wave (wave-uniform, no per-lane registers);
+  // triangles per wave in the shared leaf phase, per lane where a lane tests its own leaves
+  uint32_t w_rays = 0, w_nodes = 0, w_tris = 0, c_tris = 0;
   for (;;) {
     if (!exhausted) {
       const uint64_t idle = __ballot(!active);
@@ -334,6 +345,10 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
                              fabsf(d.z) > 1e-20f ? d.z : copysignf(1e-20f, d.z));
             inv = v3(1.0f / dd.x, 1.0f / dd.y, 1.0f / dd.z);
             oi = v3(-o.x * inv.x, -o.y * inv.y, -o.z * inv.z);
+            // |oi| of axes the ray is not nearly parallel to (|d| >= 2^-10); see slab()
+            eps = fmaxf(fmaxf(fabsf(o.x) * fminf(fabsf(inv.x), 1024.0f), fabsf(o.y) * fminf(fabsf(inv.y), 1024.0f)),
+                        fabsf(o.z) * fminf(fabsf(inv.z), 1024.0f)) *
+                  0x1p-22f;
             h.t = __builtin_inff();
             h.b1 = h.b2 = 0.0f;
             h.prim = kMiss;
@@ -343,9 +358,9 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
             st.sp = 0;
             ray = my;
             active = true;
-            ++c_rays;
           }
         }
+        w_rays += (uint32_t)__popcll(__ballot(active) & idle);
       }
     }
     if (__ballot(active) == 0) {
@@ -353,13 +368,13 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
       continue;
     }
     if constexpr (kMode == 0) {
+      w_nodes += (uint32_t)__popcll(__ballot(active));
       if (!active) continue;
       // one node: test both child boxes, intersect leaf children, descend or pop
-      ++c_nodes;
       const float4 n0 = sc.node[4 * ni], n1 = sc.node[4 * ni + 1], n2 = sc.node[4 * ni + 2], n3 = sc.node[4 * ni + 3];
       float tn0, tn1;
-      bool h0 = slab(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, inv, oi, h.t, tn0);
-      bool h1 = slab(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, inv, oi, h.t, tn1);
+      bool h0 = slab(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, inv, oi, eps, h.t, tn0);
+      bool h1 = slab(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, inv, oi, eps, h.t, tn1);
       const uint32_t l0 = bits(n3.x), l1 = bits(n3.y);
       if (h0 && (l0 & kLeafBit)) {
         test_leaf(sc, l0, o, d, excl, h, c_tris);
@@ -389,18 +404,18 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
       // enough lanes have finished to make a refill worthwhile.
       uint64_t parked, seeking;
       for (;;) {
+        w_nodes += (uint32_t)__popcll(__ballot(active && ni != kNoNode && (kMode == 2 || pend == 0)));
         if (active) {
           if constexpr (kMode == 4) {
             if (ni != kNoNode && pend == 0) {
-              ++c_nodes;
               const float4* nd = sc.node4 + 8ull * ni;
               const float4 lx = nd[0], hx = nd[1], ly = nd[2], hy = nd[3], lz = nd[4], hz = nd[5], lk = nd[6];
               float k0, k1, k2, k3;
               uint32_t c0 = bits(lk.x), c1 = bits(lk.y), c2 = bits(lk.z), c3 = bits(lk.w);
-              if (!(c0 != kEmptyChild4 && slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, inv, oi, h.t, k0))) k0 = kInf;
-              if (!(c1 != kEmptyChild4 && slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, inv, oi, h.t, k1))) k1 = kInf;
-              if (!(c2 != kEmptyChild4 && slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, inv, oi, h.t, k2))) k2 = kInf;
-              if (!(c3 != kEmptyChild4 && slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, inv, oi, h.t, k3))) k3 = kInf;
+              if (!(c0 != kEmptyChild4 && slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, inv, oi, eps, h.t, k0))) k0 = kInf;
+              if (!(c1 != kEmptyChild4 && slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, inv, oi, eps, h.t, k1))) k1 = kInf;
+              if (!(c2 != kEmptyChild4 && slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, inv, oi, eps, h.t, k2))) k2 = kInf;
+              if (!(c3 != kEmptyChild4 && slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, inv, oi, eps, h.t, k3))) k3 = kInf;
               // ascending by entry distance (misses last): five compare-exchanges
               sort2(k0, c0, k1, c1);
               sort2(k2, c2, k3, c3);
@@ -414,12 +429,11 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
               ni = kNoNode;
             }
           } else if (ni != kNoNode && (kMode == 2 || pend == 0)) {
-            ++c_nodes;
             const float4 n0 = sc.node[4 * ni], n1 = sc.node[4 * ni + 1], n2 = sc.node[4 * ni + 2],
                          n3 = sc.node[4 * ni + 3];
             float tn0, tn1;
-            const bool h0 = slab(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, inv, oi, h.t, tn0);
-            const bool h1 = slab(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, inv, oi, h.t, tn1);
+            const bool h0 = slab(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, inv, oi, eps, h.t, tn0);
+            const bool h1 = slab(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, inv, oi, eps, h.t, tn1);
             const uint32_t l0 = bits(n3.x), l1 = bits(n3.y);
             const bool first0 = tn0 <= tn1;
             const bool f0 = h0 && (l0 & kLeafBit), f1 = h1 && (l1 & kLeafBit);
@@ -464,7 +478,7 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
       if (parked != 0 && (seeking == 0 || __popcll(parked) >= leaf_batch)) {
         if constexpr (kMode >= 3) {
           const int wbase = tid & ~63;
-          leaf_phase_shared(sc, active && pend != 0, pend, o, d, excl, h, c_tris, hit_keys + wbase,
+          leaf_phase_shared(sc, active && pend != 0, pend, o, d, excl, h, w_tris, hit_keys + wbase,
                             hit_slots + wbase);
           if (active) pend = 0;
         } else if (active && pend != 0) {
@@ -474,9 +488,15 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
       }
     }
   }
-  atomicAdd(&cnt[0], (unsigned long long)c_rays);
-  atomicAdd(&cnt[1], (unsigned long long)c_nodes);
-  atomicAdd(&cnt[2], (unsigned long long)c_tris);
+  if (__lane_id() == 0) {
+    atomicAdd(&cnt[0], (unsigned long long)w_rays);
+    atomicAdd(&cnt[1], (unsigned long long)w_nodes);
+  }
+  if (kMode >= 3) {
+    if (__lane_id() == 0) atomicAdd(&cnt[2], (unsigned long long)w_tris);
+  } else {
+    atomicAdd(&cnt[2], (unsigned long long)c_tris);
+  }
   __syncthreads();
   if (tid < 3 && cnt[tid]) atomicAdd(a.rays + tid, cnt[tid]);
 }
