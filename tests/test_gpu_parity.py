@@ -150,6 +150,43 @@ def test_closest_hit_matches_oracle(O, nrrs_mod, scenes):
             assert np.allclose(gt[hit], ot[hit], rtol=1e-5, atol=1e-6)
 
 
+def test_closest_hit_from_surface_points_far_from_the_coordinate_origin(O, nrrs_mod, scenes):
+    # the heightfield moved 1000 m away from the coordinate origin; rays leave points on random
+    # triangles (1e-4 m above them) into the upper half space, so the first boxes they test lie
+    # a few centimetres from origins whose coordinates are 1e3: the slab test's absolute margin
+    # for the rounding of -o/d must keep every box the exact ray touches
+    import dataclasses
+    base = scenes.heightfield(0)
+    shift = np.array([1000.0, 0.0, 1000.0], np.float32)
+    sc = dataclasses.replace(base, verts=(base.verts + shift).astype(np.float32))
+    r = make(nrrs_mod, sc, 512, 512)
+    osc = O.OracleScene(sc)
+    rng = np.random.default_rng(31)
+    n = 50000
+    tri = rng.integers(0, sc.n_tris, size=n)
+    v = sc.verts.astype(np.float64)[sc.tris[tri]]            # [n, 3, 3]
+    a, b = rng.uniform(size=(2, n))
+    swap = a + b > 1.0
+    a[swap], b[swap] = 1.0 - a[swap], 1.0 - b[swap]
+    p = v[:, 0] + a[:, None] * (v[:, 1] - v[:, 0]) + b[:, None] * (v[:, 2] - v[:, 0])
+    nrm = np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0])
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True) + 1e-300
+    nrm *= np.where(nrm[:, 1:2] < 0.0, -1.0, 1.0)
+    d = rng.normal(size=(n, 3))
+    d[:, 1] = np.abs(d[:, 1])
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = p + 1e-4 * nrm
+    rays32 = np.concatenate([o, d], 1).astype(np.float32)
+    op, ot, _, _, frag = O.trace(osc, rays32.astype(np.float64), tri.astype(np.uint32), tau=1e-4, with_fragile=True)
+    gp, gt, _, _ = r.debug_trace(rays32, tri.astype(np.uint32))
+    ok = ~frag
+    hit = ok & (op != O.MISS)
+    assert ok.mean() > 0.9 and hit.sum() > n // 20
+    bad = ok & (gp != op)
+    assert bad.sum() == 0, (np.nonzero(bad)[0][:10], bad.sum())
+    assert np.allclose(gt[hit], ot[hit], rtol=1e-5, atol=1e-6)
+
+
 def test_every_queue_entry_traced_once_for_small_and_ragged_batches(O, nrrs_mod, scenes):
     # the queue is claimed in slices with a counter each: batches smaller than the slice count,
     # ragged slice sizes and claims that cross a slice's end still give every entry its hit
