@@ -100,8 +100,8 @@ def main():
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU sharding of the "
-              "render is described in DESIGN.md and is not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the render is not sharded over "
+              "several GPUs.", file=sys.stderr)
         sys.exit(2)
 
     import torch
