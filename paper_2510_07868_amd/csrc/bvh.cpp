@@ -39,7 +39,7 @@ struct Box {
 };
 
 constexpr int kBins = 16;
-constexpr uint32_t kLeafMax = 8;   // encoding limit
+constexpr uint32_t kLeafMax = kLeafMaxTris;  // (the link encoding would allow 8)
 constexpr uint32_t kLeafTarget = 4;
 constexpr int kSahDepth = 32;      // beyond this depth, median splits bound the tree depth
 

@@ -325,7 +325,7 @@ int32_t nrrs_create(const nrrs_config* cfg, void* hip_stream, nrrs_ctx** out) {
   c->tune.extend_variant = 3;
   c->tune.extend_blocks_per_cu = c->ext_occ[3];
   c->tune.extend_refill = 16;
-  c->tune.extend_leaf_batch = 16;
+  c->tune.extend_leaf_batch = 12;
   c->tune.extend_chunk = 64;
   warm_mfma_launch_cache();
   *out = c;
@@ -403,6 +403,11 @@ int32_t nrrs_upload_scene(nrrs_ctx* c, const float* verts, uint64_t nv, const ui
   if (bvh.n_nodes > c->max_tris + 2 || bvh.n_nodes4 > c->max_tris + 2)
     return fail(c, NRRS_ENOMEM, "BVH larger than reserved");
   if (bvh.max_depth > kMaxBvhDepth) return fail(c, NRRS_EINVAL, "BVH deeper than the traversal stack");
+  for (uint64_t i = 0; i < 2 * bvh.n_nodes; ++i) {
+    uint32_t l;
+    std::memcpy(&l, &bvh.nodes[16 * (i / 2) + 12 + (i % 2)], 4);
+    if ((l & 0x80000000u) && (l & 7u) + 1u > kLeafMaxTris) return fail(c, NRRS_EINVAL, "BVH leaf too large");
+  }
   // triangles in BVH order: (v0, original index), (e1, material), (e2, 0)
   std::vector<float> tri(12 * nt);
   float amin[3] = {INFINITY, INFINITY, INFINITY}, amax[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -773,7 +778,7 @@ int32_t nrrs_autotune(nrrs_ctx* c, uint32_t max_depth, nrrs_tuning* best, nrrs_t
   }
   if (win.extend_variant != 0) {
     const nrrs_tuning base = win;
-    for (uint32_t lb : {8u, 16u, 24u, 32u}) {
+    for (uint32_t lb : {8u, 12u, 16u, 24u, 32u}) {
       if (lb == base.extend_leaf_batch) continue;
       nrrs_tuning t = base;
       t.extend_leaf_batch = lb;

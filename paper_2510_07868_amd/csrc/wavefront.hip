@@ -110,10 +110,9 @@ struct HitState {
 // would reject too, or that lie beyond ht; only the rest pay for the division, so results are
 // those of the exact test alone.  Returns true with t, b1, b2 and the original index when the
 // ray hits the triangle at t > tmin.
-__device__ __forceinline__ bool test_tri(const DevScene& sc, uint32_t k, V3 o, V3 d, float ht, float& t, float& b1,
-                                         float& b2, uint32_t& og) {
+__device__ __forceinline__ bool test_tri_data(const DevScene& sc, float4 a0, float4 a1, float4 a2, V3 o, V3 d,
+                                              float ht, float& t, float& b1, float& b2, uint32_t& og) {
   constexpr float kMargin = 1e-5f;
-  const float4 a0 = sc.tri[3 * k], a1 = sc.tri[3 * k + 1], a2 = sc.tri[3 * k + 2];
   const V3 e1 = xyz(a1), e2 = xyz(a2);
   const V3 p = cross(d, e2);
   const float det = dot(e1, p);
@@ -135,6 +134,11 @@ __device__ __forceinline__ bool test_tri(const DevScene& sc, uint32_t k, V3 o, V
   t = dot(e2, qv) * inv;
   og = bits(a0.w);
   return t > sc.tmin;
+}
+
+__device__ __forceinline__ bool test_tri(const DevScene& sc, uint32_t k, V3 o, V3 d, float ht, float& t, float& b1,
+                                         float& b2, uint32_t& og) {
+  return test_tri_data(sc, sc.tri[3 * k], sc.tri[3 * k + 1], sc.tri[3 * k + 2], o, d, ht, t, b1, b2, og);
 }
 
 // All triangles of a leaf for one ray: closest t wins, equal t goes to the smaller original
@@ -164,51 +168,51 @@ __device__ __forceinline__ unsigned long long hit_key(float t, uint32_t orig) {
   return ((unsigned long long)__float_as_uint(t) << 32) | orig;
 }
 
-// The parked leaves of a wave, intersected triangle-parallel: the (lane, triangle) pairs are
-// numbered by an exclusive scan of the leaf sizes and every lane of the wave takes one pair
-// per round, reading the owner's ray through cross-lane shuffles.  Each owner's closest hit
-// is an LDS atomic minimum of hit keys; after each round the lane holding the current
-// minimum publishes triangle and barycentrics.  Same result as test_leaf on every owner.
+// The parked leaves of a wave, intersected triangle-parallel: the parked lane of rank r among
+// the wave's parked lanes owns the group of lanes 4 (r mod 16) .. +3 in round r / 16, and lane
+// 4 (r mod 16) + k tests triangle k of its leaf (leaves hold at most kLeafMaxTris = 4
+// triangles).  The owners' lane numbers go through an LDS table indexed by rank; a lane reads
+// its owner's leaf link, starts loading its triangle, and only then fetches the owner's ray
+// through cross-lane shuffles, so the loads' latency overlaps the shuffles.  Each owner's
+// closest hit is an LDS atomic minimum of hit keys; after each round the lane holding the
+// current minimum publishes triangle and barycentrics.  Same result as test_leaf on every owner.
+static_assert(kLeafMaxTris == 4, "the leaf phase deals four lanes to each parked leaf");
 __device__ __forceinline__ void leaf_phase_shared(const DevScene& sc, bool mine, uint32_t link, V3 o, V3 d,
                                                   uint32_t excl, HitState& h, uint32_t& tris,
-                                                  unsigned long long* key, float4* slot) {
+                                                  unsigned long long* key, float4* slot, uint8_t* owner) {
   const uint32_t lane = __lane_id();
+  const uint64_t parked = __ballot(mine);
+  const uint32_t n_parked = (uint32_t)__popcll(parked);
   const uint32_t cnt = mine ? (link & 7u) + 1u : 0u;
-  const uint32_t first = mine ? (link >> 3) & 0x0fffffffu : 0u;
-  uint32_t pre = 0, total = 0;
+  uint32_t total = 0;
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const uint64_t m = __ballot((cnt >> b) & 1u);
-    pre += (uint32_t)lanes_below(m) << b;
-    total += (uint32_t)__popcll(m) << b;
-  }
+  for (int b = 0; b < 3; ++b) total += (uint32_t)__popcll(__ballot((cnt >> b) & 1u)) << b;
   tris += total;  // wave-uniform count of the (ray, triangle) pairs
   const unsigned long long start = hit_key(h.t, h.orig);
-  if (mine) key[lane] = start;
+  if (mine) {
+    key[lane] = start;
+    owner[lanes_below(parked)] = (uint8_t)lane;
+  }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  for (uint32_t base = 0; base < total; base += 64) {
-    const uint32_t p = base + lane;
-    // owner: the last lane whose first pair is <= p (lanes without pairs share the next prefix)
-    int own = 0;
-#pragma unroll
-    for (int step = 32; step >= 1; step >>= 1) {
-      const int cand = own + step;
-      const uint32_t pc = (uint32_t)__shfl((int)pre, cand < 64 ? cand : 63);
-      if (cand < 64 && pc <= p) own = cand;
-    }
-    const uint32_t f_o = (uint32_t)__shfl((int)first, own), pre_o = (uint32_t)__shfl((int)pre, own);
+  for (uint32_t r0 = 0; r0 < n_parked; r0 += 16) {
+    const uint32_t q = r0 + (lane >> 2);
+    const bool qv = q < n_parked;
+    const int own = qv ? (int)owner[q] : 0;
+    const uint32_t link_o = (uint32_t)__shfl((int)link, own);
+    const uint32_t kk = lane & 3u;
+    const bool pair = qv && kk <= (link_o & 7u);
+    const uint32_t k = ((link_o >> 3) & 0x0fffffffu) + (pair ? kk : 0u);
+    // the triangle (the owner's first one for lanes without a pair: in bounds, unused)
+    const float4 a0 = sc.tri[3 * k], a1 = sc.tri[3 * k + 1], a2 = sc.tri[3 * k + 2];
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the shuffles below
     const uint32_t ex_o = (uint32_t)__shfl((int)excl, own);
     const V3 o_o = v3(__shfl(o.x, own), __shfl(o.y, own), __shfl(o.z, own));
     const V3 d_o = v3(__shfl(d.x, own), __shfl(d.y, own), __shfl(d.z, own));
     const float ht_o = __shfl(h.t, own);
     float t = 0.0f, b1 = 0.0f, b2 = 0.0f;
-    uint32_t og = 0, k = 0;
-    bool hit = false;
-    if (p < total) {
-      k = f_o + (p - pre_o);
-      hit = k != ex_o && test_tri(sc, k, o_o, d_o, ht_o, t, b1, b2, og);
-    }
+    uint32_t og = 0;
+    const bool hit = pair && k != ex_o && test_tri_data(sc, a0, a1, a2, o_o, d_o, ht_o, t, b1, b2, og);
     const unsigned long long ck = hit ? hit_key(t, og) : ~0ull;
     if (hit) atomicMin(&key[own], ck);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -272,6 +276,7 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
   __shared__ unsigned long long cnt[3];  // rays traced, nodes visited, triangles tested
   __shared__ unsigned long long hit_keys[kMode >= 3 ? kTraceThreads : 1];
   __shared__ float4 hit_slots[kMode >= 3 ? kTraceThreads : 1];
+  __shared__ uint8_t leaf_owner[kMode >= 3 ? kTraceThreads : 1];
   const int tid = threadIdx.x;
   if (tid < 3) cnt[tid] = 0;
   __syncthreads();
@@ -479,7 +484,7 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
         if constexpr (kMode >= 3) {
           const int wbase = tid & ~63;
           leaf_phase_shared(sc, active && pend != 0, pend, o, d, excl, h, w_tris, hit_keys + wbase,
-                            hit_slots + wbase);
+                            hit_slots + wbase, leaf_owner + wbase);
           if (active) pend = 0;
         } else if (active && pend != 0) {
           test_leaf(sc, pend, o, d, excl, h, c_tris);
