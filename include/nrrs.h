@@ -122,8 +122,9 @@ int32_t nrrs_bind_workspace(nrrs_ctx* ctx, void* device_ptr, uint64_t bytes, uin
  *   rho is the Lambertian albedo or the GGX F0; camera[10] = eye xyz, look-at xyz, up xyz,
  *   vertical fov in degrees; env[3] constant radiance seen by rays that miss.
  * A triangle emits (Le) on the side of cross(v1-v0, v2-v0).  Builds a BVH on the host
- * (binned SAH) and copies it to the workspace.  EINVAL on out-of-range indices,
- * non-finite values or nt == 0; ENOMEM if nt or nm exceed the bound workspace. */
+ * (binned SAH, leaves of at most 4 triangles) and copies it to the workspace.  EINVAL on
+ * out-of-range indices, non-finite values, nt == 0 or a tree deeper than the traversal
+ * stack allows; ENOMEM if nt or nm exceed the bound workspace. */
 int32_t nrrs_upload_scene(nrrs_ctx* ctx, const float* verts, uint64_t nv, const uint32_t* tris,
                           uint64_t nt, const uint32_t* tri_mat, const uint32_t* mat_type,
                           const float* mat_params, uint32_t nm, const float* camera, const float* env);
@@ -191,7 +192,8 @@ typedef struct nrrs_tuning {
                                    * the leaf it reaches and waits, the wave intersects parked
                                    * leaves together; 2: as 1, but lanes with a parked leaf keep
                                    * descending meanwhile; 3: as 1, with the parked leaves'
-                                   * triangles shared out over all lanes of the wave; 4: as 3
+                                   * triangles shared out over all lanes of the wave (four
+                                   * lanes per leaf of at most 4 triangles); 4: as 3
                                    * over the 4-wide tree (EINVAL if the scene's 4-wide tree
                                    * is deeper than 30 levels) */
   uint32_t extend_blocks_per_cu;  /* 1 .. extend_max_blocks_per_cu[variant] */
