@@ -202,8 +202,9 @@ __device__ __forceinline__ void leaf_phase_shared(const DevScene& sc, bool mine,
     const uint32_t link_o = (uint32_t)__shfl((int)link, own);
     const uint32_t kk = lane & 3u;
     const bool pair = qv && kk <= (link_o & 7u);
-    const uint32_t k = ((link_o >> 3) & 0x0fffffffu) + (pair ? kk : 0u);
-    // the triangle (the owner's first one for lanes without a pair: in bounds, unused)
+    // the triangle: for a lane without a pair the owner's first one, or triangle 0 for a lane
+    // past the last owner (in bounds either way, result unused)
+    const uint32_t k = qv ? ((link_o >> 3) & 0x0fffffffu) + (pair ? kk : 0u) : 0u;
     const float4 a0 = sc.tri[3 * k], a1 = sc.tri[3 * k + 1], a2 = sc.tri[3 * k + 2];
     __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the shuffles below
     const uint32_t ex_o = (uint32_t)__shfl((int)excl, own);
