@@ -244,13 +244,14 @@ __device__ __forceinline__ i32x8 quant_block(const float (&x)[32], int& scale_co
   }
   e = max(-120, min(120, e));
   scale_code = 127 + e;
+  // hardware conversion (OCP E4M3, round to nearest even; the scale keeps every value within
+  // +-448, so saturation never applies): same bytes as to_e4m3
   i32x8 r;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    uint32_t word = 0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) word |= to_e4m3(ldexpf(x[4 * j + b], -e)) << (8 * b);
-    r[j] = (int)word;
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(x[4 * j], -e), ldexpf(x[4 * j + 1], -e), 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(x[4 * j + 2], -e), ldexpf(x[4 * j + 3], -e), w, true);
+    r[j] = w;
   }
   return r;
 }
