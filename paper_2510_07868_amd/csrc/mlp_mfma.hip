@@ -26,6 +26,7 @@ namespace {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef __attribute__((__vector_size__(8 * sizeof(int)))) int i32x8;
+typedef short i16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kThreads = 256;
 constexpr int kBfTiles = 28;   // layer 1: 2 vertex tiles x 2 unit tiles x 3 k-steps; layers 2, 3: 2 x 4
@@ -244,14 +245,15 @@ __device__ __forceinline__ i32x8 quant_block(const float (&x)[32], int& scale_co
   }
   e = max(-120, min(120, e));
   scale_code = 127 + e;
-  // hardware conversion (OCP E4M3, round to nearest even; the scale keeps every value within
-  // +-448, so saturation never applies): same bytes as to_e4m3
+  // hardware conversion of x / 2^e (OCP E4M3, round to nearest even; the scale keeps every
+  // value within +-448, so saturation never applies): same bytes as to_e4m3(ldexpf(x, -e))
+  const float sc = ldexpf(1.0f, e);
   i32x8 r;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    int w = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(x[4 * j], -e), ldexpf(x[4 * j + 1], -e), 0, false);
-    w = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(x[4 * j + 2], -e), ldexpf(x[4 * j + 3], -e), w, true);
-    r[j] = w;
+    const i16x2 lo = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(i16x2{0, 0}, x[4 * j], x[4 * j + 1], sc, false);
+    const i16x2 hi = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(lo, x[4 * j + 2], x[4 * j + 3], sc, true);
+    r[j] = __builtin_bit_cast(int, hi);
   }
   return r;
 }
