@@ -47,7 +47,8 @@ enum nrrs_status {
 enum nrrs_mode {
   NRRS_MODE_OFF = 0,       /* plain path tracing: factor 1, no normalization */
   NRRS_MODE_HEURISTIC = 1, /* normalized RRS with q = lum(throughput * albedo) */
-  NRRS_MODE_NET = 2        /* normalized RRS with the network factor at depth <= net_max_depth */
+  NRRS_MODE_NET = 2        /* normalized RRS with the network factor at the depths of the Mix-Depth
+                              table (nrrs_set_mix_depth; default: depth <= net_max_depth) */
 };
 
 enum nrrs_norm { NRRS_NORM_TWO_SIDED = 0, NRRS_NORM_DOWNSCALE = 1 };
@@ -72,7 +73,8 @@ typedef struct {
   double f_rate;          /* rate-control factor of Eq. (12); 1.0 = plain normalization */
   int32_t norm_mode;      /* nrrs_norm */
   uint64_t seed;          /* Philox4x32-10 key */
-  int32_t net_max_depth;  /* vertices at depth <= this use the network in NET mode (0..4) */
+  int32_t net_max_depth;  /* training records are taken at depth <= this (0..4); also the default
+                             Mix-Depth table: the network at depths 1..net_max_depth in NET mode */
   int32_t precision;      /* nrrs_precision of network inference */
   uint32_t records_cap;   /* capacity of the training-record buffer (0 = no records) */
   double p_train;         /* probability that a primary path records training vertices */
@@ -184,6 +186,15 @@ int32_t nrrs_set_launch_mode(nrrs_ctx* ctx, int32_t mode);
 /* Enable (1) or disable (0) per-stage GPU timing of nrrs_render with HIP events recorded on
  * the context stream between the stages; results appear in nrrs_render_stats. */
 int32_t nrrs_set_timing(nrrs_ctx* ctx, int32_t enabled);
+
+/* Mix-Depth (Sec. 4.3): the RRS method is chosen per bounce.  In NET mode the network factor
+ * is evaluated at depth d (1..64) when bit d-1 of net_depths is set; every other depth keeps the
+ * heuristic factor lum(throughput * albedo), normalized the same way (Sec. 4.1 Eqs. 9-10).  The
+ * table only changes inference: training records are still taken at depth <= net_max_depth.
+ * The default after nrrs_create is (1 << net_max_depth) - 1.  Setting a different table drops
+ * the captured pass graphs.  EINVAL on a NULL context or output. */
+int32_t nrrs_set_mix_depth(nrrs_ctx* ctx, uint64_t net_depths);
+int32_t nrrs_get_mix_depth(const nrrs_ctx* ctx, uint64_t* net_depths);
 
 /* Launch parameters of the persistent traversal (extend) kernel.  The grid is
  * blocks_per_cu * (compute units) blocks of 128 lanes, each lane one ray at a time. */

@@ -897,7 +897,8 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
   }
   st->rays += rays;
   /* shading, in slot order (FP64 image sums in a fixed order) */
-  int net = cfg->mode == OR_MODE_NET && depth <= (uint32_t)cfg->net_max_depth && c->params != NULL;
+  /* Mix-Depth (Sec. 4.3): the method is chosen per bounce; the network only where the table says */
+  int net = cfg->mode == OR_MODE_NET && depth <= 64 && ((cfg->net_depths >> (depth - 1)) & 1u) && c->params != NULL;
   for (uint64_t i = 0; i < n; ++i) {
     entry* e = &Q[i];
     vstate* v = &V[i];

@@ -45,6 +45,8 @@ typedef struct {
   uint32_t rec_cap;      /* capacity of the record arrays (0 = no records) */
   uint32_t update_guide; /* 1: refresh the guide image from the running mean after each pass */
   double tau;            /* near-tie margin for the fragile-pixel flags */
+  uint64_t net_depths;   /* Mix-Depth table (Sec. 4.3): NET mode evaluates the network at depth d
+                            when bit d-1 is set and keeps the heuristic factor at the other depths */
 } or_cfg;
 
 typedef struct {

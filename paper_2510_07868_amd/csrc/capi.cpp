@@ -47,6 +47,7 @@ struct nrrs_ctx {
   uint32_t* spill = nullptr;        // sized for cus * max(ext_occ) blocks
   uint32_t* work = nullptr;         // traversal claim counters per depth and queue slice
   nrrs_tuning tune{};               // launch parameters of the traversal kernel
+  uint64_t net_depths = 0;          // Mix-Depth table: bit d-1 = network factor at depth d (NET mode)
   // workspace
   uint8_t* ws = nullptr;
   uint64_t ws_bytes = 0, max_tris = 0;
@@ -316,6 +317,7 @@ int32_t nrrs_create(const nrrs_config* cfg, void* hip_stream, nrrs_ctx** out) {
   nrrs_ctx* c = new (std::nothrow) nrrs_ctx();
   if (!c) return NRRS_EINVAL;
   c->cfg = *cfg;
+  c->net_depths = (uint64_t(1) << cfg->net_max_depth) - 1;
   c->stream = (hipStream_t)hip_stream;
   c->npx = npx;
   c->nprim = nprim;
@@ -502,6 +504,19 @@ int32_t nrrs_set_timing(nrrs_ctx* c, int32_t enabled) {
   return NRRS_OK;
 }
 
+int32_t nrrs_set_mix_depth(nrrs_ctx* c, uint64_t net_depths) {
+  if (!c) return NRRS_EINVAL;
+  if (net_depths != c->net_depths) c->drop_graphs();  // captured passes hold the old launch sequence
+  c->net_depths = net_depths;
+  return NRRS_OK;
+}
+
+int32_t nrrs_get_mix_depth(const nrrs_ctx* c, uint64_t* net_depths) {
+  if (!c || !net_depths) return NRRS_EINVAL;
+  *net_depths = c->net_depths;
+  return NRRS_OK;
+}
+
 int32_t nrrs_get_tuning(const nrrs_ctx* c, nrrs_tuning* out) {
   if (!c || !out) return NRRS_EINVAL;
   *out = c->tune;
@@ -583,7 +598,7 @@ int32_t nrrs_render(nrrs_ctx* c, uint32_t spp, uint32_t max_depth, int32_t mode,
       if (b.records_on && d <= (uint32_t)c->cfg.net_max_depth) launch_record_features(b, c->cfg.records_cap, s);
       MARK(2);
       if (d == max_depth) break;
-      if (mode == NRRS_MODE_NET && d <= (uint32_t)c->cfg.net_max_depth) {
+      if (mode == NRRS_MODE_NET && ((c->net_depths >> (d - 1)) & 1u)) {
         launch_rrsnet(b, net, s);
         MARK(3);
       }

@@ -26,7 +26,7 @@ STAGES = ["camera", "extend", "shade", "network", "sum_q", "roulette_scan", "exp
 
 EXPORTS = [
     "nrrs_create", "nrrs_workspace_size", "nrrs_bind_workspace", "nrrs_upload_scene", "nrrs_render",
-    "nrrs_set_timing", "nrrs_set_launch_mode", "nrrs_get_tuning", "nrrs_set_tuning", "nrrs_autotune",
+    "nrrs_set_timing", "nrrs_set_launch_mode", "nrrs_set_mix_depth", "nrrs_get_mix_depth", "nrrs_get_tuning", "nrrs_set_tuning", "nrrs_autotune",
     "nrrs_train_step", "nrrs_read_image", "nrrs_reset_image", "nrrs_set_guide", "nrrs_get_guide",
     "nrrs_get_params", "nrrs_set_params", "nrrs_read_records", "nrrs_debug_rrs_expand",
     "nrrs_debug_load_records", "nrrs_debug_read_queue", "nrrs_debug_trace",
@@ -100,6 +100,8 @@ def load():
         "nrrs_render": [P, U32, U32, I32, P],
         "nrrs_set_timing": [P, I32],
         "nrrs_set_launch_mode": [P, I32],
+        "nrrs_set_mix_depth": [P, U64],
+        "nrrs_get_mix_depth": [P, P],
         "nrrs_get_tuning": [P, P],
         "nrrs_set_tuning": [P, P],
         "nrrs_autotune": [P, U32, P, P, U32, P],
@@ -222,6 +224,17 @@ class Renderer:
 
     def set_timing(self, enabled=True):
         self._check(self.L.nrrs_set_timing(self.h, 1 if enabled else 0))
+
+    def set_mix_depth(self, net_depths):
+        """Mix-Depth table: an int bitmask (bit d-1 = network at depth d) or an iterable of depths."""
+        if not isinstance(net_depths, int):
+            net_depths = sum(1 << (d - 1) for d in set(net_depths))
+        self._check(self.L.nrrs_set_mix_depth(self.h, C.c_uint64(net_depths)))
+
+    def get_mix_depth(self):
+        m = C.c_uint64()
+        self._check(self.L.nrrs_get_mix_depth(self.h, C.byref(m)))
+        return int(m.value)
 
     def get_tuning(self):
         t = Tuning()

@@ -439,6 +439,87 @@ def test_net_mode_matches_oracle(O, nrrs_mod, scenes):
     assert st["sumq"][1] == pytest.approx(o["sumq"][1], rel=1e-4)
 
 
+def test_mix_depth_table_matches_oracle(O, nrrs_mod, scenes):
+    # Mix-Depth (Sec. 4.3): the network at depths 1 and 3, the heuristic factor at 2, 4, 5
+    W = H = 32
+    D = 6
+    sc = scenes.cornell()
+    rng = np.random.default_rng(4)
+    params = rng.normal(0, 0.2, size=9729).astype(np.float32)
+    guide = rng.uniform(0.05, 2.0, size=W * H).astype(np.float32)
+    r = make(nrrs_mod, sc, W, H, s_batch=2)
+    assert r.get_mix_depth() == 0b1111
+    r.set_mix_depth([1, 3])
+    assert r.get_mix_depth() == 0b101
+    r.set_params(params)
+    r.set_guide(guide)
+    st = r.render(2, D, nrrs_mod.MODE_NET)
+    img, _ = r.read_image()
+    osc = O.OracleScene(sc)
+    cfg = O.make_cfg(W, H, 2, D, n_passes=1, mode=O.MODE_NET, tau=1e-4, net_depths=0b101)
+    o = O.render(osc, cfg, params=params.astype(np.float64), guide=guide.astype(np.float64))
+    bad, ok = _compare_images(img, o["image"] / 2.0, o["fragile"], rtol=2e-4)
+    assert ok.mean() > 0.85, ok.mean()
+    assert bad.sum() <= 0.002 * W * H, bad.sum()
+    assert st["sumq"][1] == pytest.approx(o["sumq"][1], rel=1e-4)
+    assert np.abs(st["n"][1:].astype(np.int64) - o["n"][1:].astype(np.int64)).max() <= max(8, 0.004 * W * H)
+
+
+def test_mix_depth_table_switch_in_graph_replay(nrrs_mod, scenes):
+    # NET mode with an empty table is the heuristic render bit for bit; changing the table
+    # drops the captured pass graphs, so replays agree with direct launches for every table
+    W = H = 64
+    D = 8
+    sc = scenes.cornell()
+    rng = np.random.default_rng(21)
+    params = rng.normal(0, 0.2, size=9729).astype(np.float32)
+    guide = rng.uniform(0.05, 2.0, size=W * H).astype(np.float32)
+    rh, rg, rd = (make(nrrs_mod, sc, W, H, s_batch=2, precision=1) for _ in range(3))
+    rd.set_launch_mode(False)
+    for r in (rh, rg, rd):
+        r.set_params(params)
+        r.set_guide(guide)
+    rg.set_mix_depth(0)
+    rd.set_mix_depth(0)
+    sh = rh.render(2, D, nrrs_mod.MODE_HEURISTIC)
+    sg = rg.render(2, D, nrrs_mod.MODE_NET)
+    rd.render(2, D, nrrs_mod.MODE_NET)
+    assert np.array_equal(rh.read_image()[0], rg.read_image()[0])
+    for key in ("n", "S", "retries"):
+        assert np.array_equal(sh[key], sg[key]), key
+    for k, mask in enumerate((0b1111, 0b0110, 0b1, 0b1111)):
+        rg.set_mix_depth(mask)
+        rd.set_mix_depth(mask)
+        sg = rg.render(2, D, nrrs_mod.MODE_NET)
+        sd = rd.render(2, D, nrrs_mod.MODE_NET)
+        ig, ng = rg.read_image()
+        idr, nd = rd.read_image()
+        assert ng == nd == 2 * (k + 2)
+        assert np.allclose(ig, idr, rtol=1e-12, atol=1e-15), mask
+        for key in ("n", "S", "retries"):
+            assert np.array_equal(sg[key], sd[key]), (mask, key)
+
+
+def test_mix_depth_brute_force_search_on_the_gpu(nrrs_mod, scenes):
+    # every table over the 3 bounces that take an RRS decision at depth 4 is scored by one
+    # timed pass against a 64-spp heuristic reference; the winner is a valid table
+    from paper_2510_07868_amd import mixdepth as M
+    W = H = 64
+    D = 4
+    sc = scenes.cornell()
+    rng = np.random.default_rng(22)
+    r = make(nrrs_mod, sc, W, H, s_batch=4, precision=1)
+    r.set_params(rng.normal(0, 0.2, size=9729).astype(np.float32))
+    r.render(64, D, nrrs_mod.MODE_HEURISTIC)
+    img, spp = r.read_image()
+    ref = img / spp
+    score = M.render_efficiency_scorer(r, D, ref, nrrs_mod.MODE_NET)
+    best, s, n = M.brute_force(D - 1, M.METHODS, score)
+    assert n == 8 and len(best) == 3 and set(best) <= set(M.METHODS)
+    assert np.isfinite(s) and s > 0
+    assert r.get_mix_depth() == M.table_to_mask((M.HEUR,) * 3)   # the last table scored
+
+
 # ----------------------------------------------------------------------------- network
 def test_mlp_forward_fp32_matches_oracle(O, nrrs_mod, scenes):
     r = make(nrrs_mod, scenes.cornell(), 256, 256)

@@ -1,0 +1,120 @@
+"""Mix-Depth (Sec. 4.3): the table searches (host logic) and the oracle's per-depth method gate.
+
+Search pins: the table counts the section states (3^6 = 729, 3^10 = 59,049, and 3^6 + 3^4 = 810
+for the segmented search with T_d = 6 over 10 bounces), the brute force returning the maximum
+found by scoring every table independently, and the segmented search holding the bounces after
+the current segment at the fallback method.
+
+Oracle pins: a NET-mode render whose table selects no depth is the heuristic render; the
+default table is depths 1..net_max_depth; bit d-1 gates exactly depth d (the factors, hence the
+FP64 sums, at depths before the first network depth are the heuristic ones, and at the first
+network depth they are the network's).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2510_07868_amd import mixdepth as M
+
+THREE = ("nrrs", "adrrs", "fixed")
+
+
+def _counting(score):
+    calls = []
+
+    def f(table):
+        calls.append(table)
+        return score(table)
+    return f, calls
+
+
+@pytest.mark.parametrize("B,count", [(6, 729), (10, 59049)])
+def test_brute_force_counts(B, count):
+    f, calls = _counting(lambda t: 0.0)
+    _, _, n = M.brute_force(B, THREE, f)
+    assert n == count == len(calls) == len(set(calls))
+
+
+def test_heuristic_search_count_depth_10_segment_6():
+    f, calls = _counting(lambda t: 0.0)
+    table, _, n = M.heuristic_search(10, 6, THREE, f, fallback="fixed")
+    assert n == 810 == len(calls)
+    assert len(table) == 10
+    # first segment: bounces 7..10 held at the fallback while 1..6 are searched
+    assert all(t[6:] == ("fixed",) * 4 for t in calls[:729])
+    assert len({t[:6] for t in calls[:729]}) == 729
+    # second segment: bounces 1..6 fixed to one combination, 7..10 searched
+    assert len({t[:6] for t in calls[729:]}) == 1
+    assert len({t[6:] for t in calls[729:]}) == 81
+
+
+def test_brute_force_finds_the_maximum_of_an_arbitrary_score():
+    rng = np.random.default_rng(5)
+    vals = {t: rng.normal() for t in itertools.product(THREE, repeat=5)}
+    best, s, _ = M.brute_force(5, THREE, vals.__getitem__)
+    assert s == max(vals.values()) and vals[best] == s
+
+
+def test_heuristic_search_is_exact_on_a_separable_score():
+    # a score that is a sum of per-bounce terms is maximized segment by segment
+    rng = np.random.default_rng(6)
+    w = {(d, m): rng.normal() for d in range(10) for m in THREE}
+    score = lambda t: sum(w[(d, m)] for d, m in enumerate(t))
+    best, s, _ = M.heuristic_search(10, 4, THREE, score, fallback="fixed")
+    expect = tuple(max(THREE, key=lambda m: w[(d, m)]) for d in range(10))
+    assert best == expect and s == pytest.approx(score(expect))
+
+
+def test_segment_longer_than_the_depth_is_the_brute_force():
+    rng = np.random.default_rng(7)
+    vals = {t: rng.normal() for t in itertools.product(THREE, repeat=4)}
+    a = M.heuristic_search(4, 6, THREE, vals.__getitem__, fallback="fixed")
+    b = M.brute_force(4, THREE, vals.__getitem__)
+    assert a == b
+
+
+def test_table_to_mask():
+    assert M.table_to_mask((M.NET,) * 4 + (M.HEUR,) * 3) == 0b1111
+    assert M.table_to_mask((M.HEUR, M.NET, M.HEUR, M.NET)) == 0b1010
+    assert M.table_to_mask(()) == 0
+
+
+def _net_render(O, sc, net_depths, mode=None, seed=0):
+    W = H = 16
+    rng = np.random.default_rng(11)
+    params = rng.normal(0, 0.3, size=O.NPARAM)
+    guide = rng.uniform(0.05, 2.0, size=W * H)
+    cfg = O.make_cfg(W, H, 2, 6, n_passes=1, mode=O.MODE_NET if mode is None else mode, tau=0.0, seed=seed,
+                     net_depths=net_depths)
+    return O.render(sc, cfg, params=params, guide=guide)
+
+
+def test_oracle_table_without_network_depths_is_the_heuristic_render(O, scenes):
+    sc = O.OracleScene(scenes.cornell())
+    a = _net_render(O, sc, 0)
+    b = _net_render(O, sc, 0, mode=O.MODE_HEUR)
+    assert np.array_equal(a["image"], b["image"])
+    assert np.array_equal(a["S"], b["S"]) and np.array_equal(a["sumq"], b["sumq"])
+
+
+def test_oracle_default_table_is_depths_up_to_net_max_depth(O):
+    assert O.make_cfg(4, 4, net_max_depth=4).net_depths == 0b1111
+    assert O.make_cfg(4, 4, net_max_depth=2).net_depths == 0b11
+    assert O.make_cfg(4, 4, net_max_depth=0).net_depths == 0
+
+
+def test_oracle_table_bit_gates_its_own_depth(O, scenes):
+    sc = O.OracleScene(scenes.cornell())
+    heur = _net_render(O, sc, 0)
+    full = _net_render(O, sc, 0b1111)
+    only2 = _net_render(O, sc, 0b10)
+    only1 = _net_render(O, sc, 0b1)
+    # depth 1 keeps the heuristic factors when only bit 1 (depth 2) is set
+    assert only2["sumq"][1] == heur["sumq"][1] and only2["S"][1] == heur["S"][1]
+    assert only2["sumq"][2] != heur["sumq"][2]
+    # bit 0 alone gives depth 1 the network factors of the full table
+    assert only1["sumq"][1] == full["sumq"][1] and only1["S"][1] == full["S"][1]
+    assert full["sumq"][1] != heur["sumq"][1]
+    # depth 2 of the depth-1-only table is the heuristic factor on the network's children
+    assert only1["sumq"][2] != full["sumq"][2]
