@@ -62,11 +62,14 @@ def relmse(img, ref):
 def render_efficiency_scorer(renderer, max_depth, reference, mode_net):
     """Score of a table: render one pass (s_batch samples per pixel) in NET mode with the table
     as the Mix-Depth mask; efficiency = 1 / (RelMSE of the pass's luminance image against
-    `reference` x GPU milliseconds of the pass).  The accumulated image is reset before each
+    `reference` (RGB or luminance per pixel, e.g. the guide image: the running mean of the
+    frames rendered so far) x GPU milliseconds of the pass).  The accumulated image is reset before each
     pass and the guide image restored, so every table starts from the same cache state; the
     caller's accumulated image is therefore lost (the search runs between training and the
     final render).  Each pass draws new samples: the estimate is as noisy as one pass."""
-    ref = np.asarray(reference, dtype=np.float64).reshape(-1, 3) @ LUM
+    ref = np.asarray(reference, dtype=np.float64)
+    if ref.size == 3 * renderer.width * renderer.height:
+        ref = ref.reshape(-1, 3) @ LUM
     guide = renderer.get_guide()
     renderer.set_timing(True)
 
@@ -75,8 +78,8 @@ def render_efficiency_scorer(renderer, max_depth, reference, mode_net):
         renderer.reset_image()
         renderer.set_guide(guide)
         st = renderer.render(renderer.s_batch, max_depth, mode_net)
-        img, spp = renderer.read_image()
-        lum = img.reshape(-1, 3) @ LUM / spp
+        img, _ = renderer.read_image()   # mean radiance of the pass
+        lum = img.reshape(-1, 3) @ LUM
         ms = sum(st["stage_ms"].values())
         return 1.0 / (max(relmse(lum, ref), 1e-30) * ms)
 

@@ -511,8 +511,8 @@ def test_mix_depth_brute_force_search_on_the_gpu(nrrs_mod, scenes):
     r = make(nrrs_mod, sc, W, H, s_batch=4, precision=1)
     r.set_params(rng.normal(0, 0.2, size=9729).astype(np.float32))
     r.render(64, D, nrrs_mod.MODE_HEURISTIC)
-    img, spp = r.read_image()
-    ref = img / spp
+    ref, spp = r.read_image()      # mean radiance over the 64 samples
+    assert spp == 64
     score = M.render_efficiency_scorer(r, D, ref, nrrs_mod.MODE_NET)
     best, s, n = M.brute_force(D - 1, M.METHODS, score)
     assert n == 8 and len(best) == 3 and set(best) <= set(M.METHODS)
