@@ -259,12 +259,24 @@ def main():
 
 
 def efficiency(r, nrrs, spp, D, ref_spp, renders, make_reference):
-    """relMSE and 1/(relMSE * t) of NRRS and heuristic normalized RRS at equal spp."""
+    """relMSE and 1/(relMSE * t) at equal spp of NRRS, NRRS with a Mix-Depth table found by the
+    segmented search (NRRS+, Sec. 4.3) and heuristic normalized RRS."""
     import torch
+    from paper_2510_07868_amd import mixdepth
 
     res = {}
     guide = r.get_guide()
-    for name, mode in (("nrrs", nrrs.MODE_NET), ("heuristic", nrrs.MODE_HEURISTIC)):
+    default = r.get_mix_depth()
+    # Mix-Depth search: one timed pass per table, scored against the guide image (the running
+    # mean of the training frames); segments of 5 bounces over the D - 1 that take a decision
+    t0 = time.perf_counter()
+    score = mixdepth.render_efficiency_scorer(r, D, guide, nrrs.MODE_NET)
+    table, _, n_tables = mixdepth.heuristic_search(D - 1, 5, mixdepth.METHODS, score, fallback=mixdepth.HEUR)
+    t_search = time.perf_counter() - t0
+    plus = mixdepth.table_to_mask(table)
+    for name, mode, mask in (("nrrs", nrrs.MODE_NET, default), ("nrrs_plus", nrrs.MODE_NET, plus),
+                             ("heuristic", nrrs.MODE_HEURISTIC, default)):
+        r.set_mix_depth(mask)
         times, imgs = [], []
         for k in range(renders):
             r.set_guide(guide)          # every evaluation render sees the same previous frame
@@ -278,6 +290,7 @@ def efficiency(r, nrrs, spp, D, ref_spp, renders, make_reference):
             imgs.append(img)
         res[name] = {"times": times, "imgs": imgs}
     r.set_guide(guide)
+    r.set_mix_depth(default)
     # reference: plain path tracing with an independent seed (no random stream shared with the
     # evaluation renders)
     t0 = time.perf_counter()
@@ -292,6 +305,10 @@ def efficiency(r, nrrs, spp, D, ref_spp, renders, make_reference):
         out[name] = {"relmse": rm, "relmse_se": float(np.std(errs) / np.sqrt(len(errs))), "render_s": round(t, 5),
                      "efficiency": 1.0 / (rm * t)}
     out["nrrs_over_heuristic"] = out["nrrs"]["efficiency"] / out["heuristic"]["efficiency"]
+    out["nrrs_plus_over_heuristic"] = out["nrrs_plus"]["efficiency"] / out["heuristic"]["efficiency"]
+    out["mix_depth"] = {"search": "segmented, T_d = 5, methods network / heuristic", "tables": n_tables,
+                        "search_s": round(t_search, 2),
+                        "network_depths": [d + 1 for d, m in enumerate(table) if m == mixdepth.NET]}
     return out
 
 

@@ -196,6 +196,14 @@ int32_t nrrs_set_timing(nrrs_ctx* ctx, int32_t enabled);
 int32_t nrrs_set_mix_depth(nrrs_ctx* ctx, uint64_t net_depths);
 int32_t nrrs_get_mix_depth(const nrrs_ctx* ctx, uint64_t* net_depths);
 
+/* The pass index the next rendered pass takes (the second word of a primary path's lineage id,
+ * so it selects the pass's random numbers; Sec. 3 wavefront passes).  It starts at 0 and each
+ * pass advances it by one.  Setting it back renders a pass on the same random numbers again
+ * (common random numbers for comparing RRS settings); the image is unaffected.  EINVAL beyond
+ * 2^32 - 1. */
+int32_t nrrs_set_pass_index(nrrs_ctx* ctx, uint64_t next_pass);
+int32_t nrrs_get_pass_index(const nrrs_ctx* ctx, uint64_t* next_pass);
+
 /* Launch parameters of the persistent traversal (extend) kernel.  The grid is
  * blocks_per_cu * (compute units) blocks of 128 lanes, each lane one ray at a time. */
 typedef struct nrrs_tuning {

@@ -511,6 +511,19 @@ int32_t nrrs_set_mix_depth(nrrs_ctx* c, uint64_t net_depths) {
   return NRRS_OK;
 }
 
+int32_t nrrs_set_pass_index(nrrs_ctx* c, uint64_t next_pass) {
+  if (!c) return NRRS_EINVAL;
+  if (next_pass > 0xFFFFFFFFull) return fail(c, NRRS_EINVAL, "pass index beyond 32 bits");
+  c->passes_done = next_pass;
+  return NRRS_OK;
+}
+
+int32_t nrrs_get_pass_index(const nrrs_ctx* c, uint64_t* next_pass) {
+  if (!c || !next_pass) return NRRS_EINVAL;
+  *next_pass = c->passes_done;
+  return NRRS_OK;
+}
+
 int32_t nrrs_get_mix_depth(const nrrs_ctx* c, uint64_t* net_depths) {
   if (!c || !net_depths) return NRRS_EINVAL;
   *net_depths = c->net_depths;

@@ -8,8 +8,8 @@ Both are host-side post-processing over a caller-supplied score (higher = better
 not touch training.
 
 `render_efficiency_scorer` is the score this renderer uses: one wavefront pass rendered with
-the table, efficiency = 1 / (RelMSE against a reference image x GPU time of the pass).  The
-methods available per bounce here are the network factor (NET) and the heuristic factor
+the table on common random numbers, efficiency = 1 / (RelMSE against a reference image x GPU
+time of the pass).  The methods available per bounce here are the network factor (NET) and the heuristic factor
 lum(throughput x albedo) (HEUR), both normalized per depth (Sec. 4.1 Eqs. 9-10).
 """
 import itertools
@@ -59,26 +59,32 @@ def relmse(img, ref):
     return float(np.mean((img - ref) ** 2 / (ref ** 2 + 0.01)))
 
 
-def render_efficiency_scorer(renderer, max_depth, reference, mode_net):
-    """Score of a table: render one pass (s_batch samples per pixel) in NET mode with the table
-    as the Mix-Depth mask; efficiency = 1 / (RelMSE of the pass's luminance image against
+def render_efficiency_scorer(renderer, max_depth, reference, mode_net, passes=1):
+    """Score of a table: render `passes` passes (s_batch samples per pixel each) in NET mode with
+    the table as the Mix-Depth mask; efficiency = 1 / (RelMSE of the luminance image against
     `reference` (RGB or luminance per pixel, e.g. the guide image: the running mean of the
-    frames rendered so far) x GPU milliseconds of the pass).  The accumulated image is reset before each
-    pass and the guide image restored, so every table starts from the same cache state; the
-    caller's accumulated image is therefore lost (the search runs between training and the
-    final render).  Each pass draws new samples: the estimate is as noisy as one pass."""
+    frames rendered so far) x GPU milliseconds of the render).
+
+    Every table is rendered on the same random numbers (common random numbers: the pass index
+    is set back to its value at the first call before each render), so two tables differ by what
+    the table changes, not by independent sampling noise.  The accumulated image is reset and
+    the guide image restored before each render, so every table starts from the same cache
+    state; the caller's accumulated image is therefore lost (the search runs between training
+    and the final render).  Afterwards the pass index is past the scored passes."""
     ref = np.asarray(reference, dtype=np.float64)
     if ref.size == 3 * renderer.width * renderer.height:
         ref = ref.reshape(-1, 3) @ LUM
     guide = renderer.get_guide()
     renderer.set_timing(True)
+    first_pass = renderer.get_pass_index()
 
     def score(table):
         renderer.set_mix_depth(table_to_mask(table))
         renderer.reset_image()
         renderer.set_guide(guide)
-        st = renderer.render(renderer.s_batch, max_depth, mode_net)
-        img, _ = renderer.read_image()   # mean radiance of the pass
+        renderer.set_pass_index(first_pass)
+        st = renderer.render(renderer.s_batch * passes, max_depth, mode_net)
+        img, _ = renderer.read_image()   # mean radiance of the render
         lum = img.reshape(-1, 3) @ LUM
         ms = sum(st["stage_ms"].values())
         return 1.0 / (max(relmse(lum, ref), 1e-30) * ms)

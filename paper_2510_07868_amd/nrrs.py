@@ -26,7 +26,8 @@ STAGES = ["camera", "extend", "shade", "network", "sum_q", "roulette_scan", "exp
 
 EXPORTS = [
     "nrrs_create", "nrrs_workspace_size", "nrrs_bind_workspace", "nrrs_upload_scene", "nrrs_render",
-    "nrrs_set_timing", "nrrs_set_launch_mode", "nrrs_set_mix_depth", "nrrs_get_mix_depth", "nrrs_get_tuning", "nrrs_set_tuning", "nrrs_autotune",
+    "nrrs_set_timing", "nrrs_set_launch_mode", "nrrs_set_mix_depth", "nrrs_get_mix_depth",
+    "nrrs_set_pass_index", "nrrs_get_pass_index", "nrrs_get_tuning", "nrrs_set_tuning", "nrrs_autotune",
     "nrrs_train_step", "nrrs_read_image", "nrrs_reset_image", "nrrs_set_guide", "nrrs_get_guide",
     "nrrs_get_params", "nrrs_set_params", "nrrs_read_records", "nrrs_debug_rrs_expand",
     "nrrs_debug_load_records", "nrrs_debug_read_queue", "nrrs_debug_trace",
@@ -102,6 +103,8 @@ def load():
         "nrrs_set_launch_mode": [P, I32],
         "nrrs_set_mix_depth": [P, U64],
         "nrrs_get_mix_depth": [P, P],
+        "nrrs_set_pass_index": [P, U64],
+        "nrrs_get_pass_index": [P, P],
         "nrrs_get_tuning": [P, P],
         "nrrs_set_tuning": [P, P],
         "nrrs_autotune": [P, U32, P, P, U32, P],
@@ -230,6 +233,14 @@ class Renderer:
         if not isinstance(net_depths, int):
             net_depths = sum(1 << (d - 1) for d in set(net_depths))
         self._check(self.L.nrrs_set_mix_depth(self.h, C.c_uint64(net_depths)))
+
+    def set_pass_index(self, next_pass):
+        self._check(self.L.nrrs_set_pass_index(self.h, C.c_uint64(next_pass)))
+
+    def get_pass_index(self):
+        m = C.c_uint64()
+        self._check(self.L.nrrs_get_pass_index(self.h, C.byref(m)))
+        return int(m.value)
 
     def get_mix_depth(self):
         m = C.c_uint64()

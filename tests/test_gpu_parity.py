@@ -500,6 +500,35 @@ def test_mix_depth_table_switch_in_graph_replay(nrrs_mod, scenes):
             assert np.array_equal(sg[key], sd[key]), (mask, key)
 
 
+def test_pass_index_selects_the_oracle_pass_and_replays_it(O, nrrs_mod, scenes):
+    # the pass index picks the random numbers of a pass: passes 5 and 6 against the oracle's
+    # passes 5 and 6, then the same two passes again after setting the index back
+    W = H = 64
+    D = 8
+    sc = scenes.cornell()
+    r = make(nrrs_mod, sc, W, H, s_batch=1)
+    assert r.get_pass_index() == 0
+    r.set_pass_index(5)
+    assert r.get_pass_index() == 5
+    st = r.render(2, D, nrrs_mod.MODE_HEURISTIC)
+    assert r.get_pass_index() == 7
+    img, spp = r.read_image()
+    assert spp == 2
+    o = O.render(O.OracleScene(sc), O.make_cfg(W, H, 1, D, pass_begin=5, n_passes=2, mode=O.MODE_HEUR, tau=1e-4))
+    bad, ok = _compare_images(img, o["image"] / 2.0, o["fragile"])
+    assert ok.mean() > 0.9, ok.mean()
+    assert bad.sum() == 0, bad.sum()
+    r.reset_image()
+    r.set_pass_index(5)
+    st2 = r.render(2, D, nrrs_mod.MODE_HEURISTIC)
+    img2, _ = r.read_image()
+    assert np.allclose(img, img2, rtol=1e-12, atol=1e-15)
+    for key in ("n", "S", "retries"):
+        assert np.array_equal(st[key], st2[key]), key
+    with pytest.raises(RuntimeError):
+        r.set_pass_index(1 << 32)
+
+
 def test_mix_depth_brute_force_search_on_the_gpu(nrrs_mod, scenes):
     # every table over the 3 bounces that take an RRS decision at depth 4 is scored by one
     # timed pass against a 64-spp heuristic reference; the winner is a valid table
