@@ -118,3 +118,58 @@ def test_oracle_table_bit_gates_its_own_depth(O, scenes):
     assert full["sumq"][1] != heur["sumq"][1]
     # depth 2 of the depth-1-only table is the heuristic factor on the network's children
     assert only1["sumq"][2] != full["sumq"][2]
+
+
+class _FakeRenderer:
+    """Host stand-in with the renderer's calls: the image of a pass depends only on its pass
+    index and the table, the way the random numbers and factors of a real pass do."""
+
+    def __init__(self):
+        self.width, self.height, self.s_batch = 4, 2, 2
+        self.pass_index, self.mask, self.guide, self.log = 9, 0b1111, np.full(8, 0.5, np.float32), []
+
+    def get_guide(self):
+        return self.guide.copy()
+
+    def set_guide(self, g):
+        self.guide = np.asarray(g, np.float32).copy()
+
+    def set_timing(self, on):
+        pass
+
+    def get_pass_index(self):
+        return self.pass_index
+
+    def set_pass_index(self, p):
+        self.pass_index = p
+
+    def set_mix_depth(self, m):
+        self.mask = m
+
+    def reset_image(self):
+        self.img = None
+
+    def render(self, spp, D, mode):
+        self.log.append((self.pass_index, self.mask, spp, float(self.guide[0])))
+        rng = np.random.default_rng(self.pass_index)
+        self.img = 0.5 + rng.normal(0, 0.1, size=(8, 3)) * (1.0 + 0.1 * bin(self.mask).count("1"))
+        self.guide[:] = 123.0          # a real pass refreshes the guide
+        self.pass_index += spp // self.s_batch
+        return {"stage_ms": {"extend": 2.0, "network": 0.5 * bin(self.mask).count("1")}}
+
+    def read_image(self):
+        return self.img.reshape(-1), 2
+
+
+def test_scorer_renders_every_table_on_the_same_pass_and_cache_state():
+    r = _FakeRenderer()
+    score = M.render_efficiency_scorer(r, 4, np.full(8, 0.5), mode_net=2)
+    tables = list(itertools.product(M.METHODS, repeat=3))
+    s = {t: score(t) for t in tables}
+    assert [e[0] for e in r.log] == [9] * 8           # common random numbers: pass 9 every time
+    assert [e[3] for e in r.log] == [0.5] * 8         # the guide restored before each pass
+    assert [e[1] for e in r.log] == [M.table_to_mask(t) for t in tables]
+    assert all(e[2] == r.s_batch for e in r.log)
+    # fewer network depths: lower error and less time in this stand-in, so a higher score
+    assert max(s, key=s.get) == (M.HEUR,) * 3
+    assert r.get_pass_index() == 10
