@@ -529,6 +529,39 @@ def test_pass_index_selects_the_oracle_pass_and_replays_it(O, nrrs_mod, scenes):
         r.set_pass_index(1 << 32)
 
 
+def test_checkpoint_resume_continues_the_render(nrrs_mod, scenes):
+    # weights, Adam state and step, guide image and pass index restore a context: a fresh
+    # context given them renders the next passes like the original one (ema_decay 0, so
+    # inference uses the weights themselves)
+    W = H = 64
+    D = 8
+    sc = scenes.cornell()
+    kw = dict(precision=1, records_cap=1 << 14, p_train=0.5, ema_decay=0.0)
+    a = make(nrrs_mod, sc, W, H, s_batch=2, **kw)
+    for _ in range(3):
+        st = a.render(2, D, nrrs_mod.MODE_NET)
+        n = min(st["records"], 1 << 14) // 1024 * 1024
+        assert n > 0
+        a.train_step(n, 1024, 5e-3)
+    w, m, v, step = a.get_params()
+    assert step > 0
+    b = make(nrrs_mod, sc, W, H, s_batch=2, **kw)
+    b.set_params(w, m, v, step)
+    b.set_guide(a.get_guide())
+    b.set_pass_index(a.get_pass_index())
+    assert b.get_params()[3] == step
+    for r in (a, b):
+        r.reset_image()
+    sa = a.render(4, D, nrrs_mod.MODE_NET)
+    sb = b.render(4, D, nrrs_mod.MODE_NET)
+    ia, _ = a.read_image()
+    ib, _ = b.read_image()
+    assert np.allclose(ia, ib, rtol=1e-12, atol=1e-15)
+    for key in ("n", "S", "retries"):
+        assert np.array_equal(sa[key], sb[key]), key
+    assert sa["sumq"][1] == sb["sumq"][1]
+
+
 def test_mix_depth_brute_force_search_on_the_gpu(nrrs_mod, scenes):
     # every table over the 3 bounces that take an RRS decision at depth 4 is scored by one
     # timed pass against a 64-spp heuristic reference; the winner is a valid table
