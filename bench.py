@@ -273,10 +273,11 @@ def efficiency(r, nrrs, spp, D, ref_spp, renders, make_reference):
     score = mixdepth.render_efficiency_scorer(r, D, guide, nrrs.MODE_NET)
     table, _, n_tables = mixdepth.heuristic_search(D - 1, 5, mixdepth.METHODS, score, fallback=mixdepth.HEUR)
     t_search = time.perf_counter() - t0
-    plus = mixdepth.table_to_mask(table)
-    for name, mode, mask in (("nrrs", nrrs.MODE_NET, default), ("nrrs_plus", nrrs.MODE_NET, plus),
-                             ("heuristic", nrrs.MODE_HEURISTIC, default)):
+    plus = (mixdepth.table_to_mask(table, mixdepth.NET), mixdepth.table_to_mask(table, mixdepth.FIXED))
+    for name, mode, (mask, fixed) in (("nrrs", nrrs.MODE_NET, (default, 0)), ("nrrs_plus", nrrs.MODE_NET, plus),
+                                      ("heuristic", nrrs.MODE_HEURISTIC, (default, 0))):
         r.set_mix_depth(mask)
+        r.set_mix_depth_fixed(fixed)
         times, imgs = [], []
         for k in range(renders):
             r.set_guide(guide)          # every evaluation render sees the same previous frame
@@ -291,6 +292,7 @@ def efficiency(r, nrrs, spp, D, ref_spp, renders, make_reference):
         res[name] = {"times": times, "imgs": imgs}
     r.set_guide(guide)
     r.set_mix_depth(default)
+    r.set_mix_depth_fixed(0)
     # reference: plain path tracing with an independent seed (no random stream shared with the
     # evaluation renders)
     t0 = time.perf_counter()
@@ -306,9 +308,10 @@ def efficiency(r, nrrs, spp, D, ref_spp, renders, make_reference):
                      "efficiency": 1.0 / (rm * t)}
     out["nrrs_over_heuristic"] = out["nrrs"]["efficiency"] / out["heuristic"]["efficiency"]
     out["nrrs_plus_over_heuristic"] = out["nrrs_plus"]["efficiency"] / out["heuristic"]["efficiency"]
-    out["mix_depth"] = {"search": "segmented, T_d = 5, methods network / heuristic", "tables": n_tables,
-                        "search_s": round(t_search, 2),
-                        "network_depths": [d + 1 for d, m in enumerate(table) if m == mixdepth.NET]}
+    out["mix_depth"] = {"search": "segmented, T_d = 5, methods network / heuristic / fixed rate",
+                        "tables": n_tables, "search_s": round(t_search, 2),
+                        "network_depths": [d + 1 for d, m in enumerate(table) if m == mixdepth.NET],
+                        "fixed_rate_depths": [d + 1 for d, m in enumerate(table) if m == mixdepth.FIXED]}
     return out
 
 

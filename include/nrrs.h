@@ -196,6 +196,14 @@ int32_t nrrs_set_timing(nrrs_ctx* ctx, int32_t enabled);
 int32_t nrrs_set_mix_depth(nrrs_ctx* ctx, uint64_t net_depths);
 int32_t nrrs_get_mix_depth(const nrrs_ctx* ctx, uint64_t* net_depths);
 
+/* Mix-Depth's third method, the fixed rate (Sec. 4.3): at depth d with bit d-1 of fixed_depths
+ * set, every vertex that continues gets the raw factor 1 in HEURISTIC and NET modes, so the
+ * normalization gives all paths at that depth one rate.  It takes precedence over the network
+ * bit of the same depth.  Default 0; setting a different value drops the captured pass graphs.
+ * EINVAL on a NULL context or output. */
+int32_t nrrs_set_mix_depth_fixed(nrrs_ctx* ctx, uint64_t fixed_depths);
+int32_t nrrs_get_mix_depth_fixed(const nrrs_ctx* ctx, uint64_t* fixed_depths);
+
 /* The pass index the next rendered pass takes (the second word of a primary path's lineage id,
  * so it selects the pass's random numbers; Sec. 3 wavefront passes).  It starts at 0 and each
  * pass advances it by one.  Setting it back renders a pass on the same random numbers again

@@ -41,7 +41,7 @@ class Cfg(C.Structure):
         ("seed", C.c_uint64),
         ("alpha", C.c_double), ("p_train", C.c_double),
         ("rec_cap", C.c_uint32), ("update_guide", C.c_uint32),
-        ("tau", C.c_double), ("net_depths", C.c_uint64),
+        ("tau", C.c_double), ("net_depths", C.c_uint64), ("fixed_depths", C.c_uint64),
     ]
 
 
@@ -191,12 +191,14 @@ def rrs_expand(q, u, budget_base, f_rate=1.0, alpha=1.0, norm_mode=NORM_TWO_SIDE
 
 def make_cfg(width, height, s_batch=1, max_depth=8, pass_begin=0, n_passes=1, mode=MODE_HEUR,
              norm_mode=NORM_TWO_SIDED, net_max_depth=4, cap_factor=2.0, f_rate=1.0, seed=0, alpha=1.0,
-             p_train=0.0, rec_cap=0, update_guide=0, tau=1e-4, frozen=0, net_depths=None) -> Cfg:
-    # Mix-Depth table (Sec. 4.3): bit d-1 set = network at depth d; default = depths 1..net_max_depth
+             p_train=0.0, rec_cap=0, update_guide=0, tau=1e-4, frozen=0, net_depths=None,
+             fixed_depths=0) -> Cfg:
+    # Mix-Depth table (Sec. 4.3): bit d-1 set = network at depth d; default = depths 1..net_max_depth;
+    # a bit of fixed_depths gives its depth the fixed rate instead (it wins over the network bit)
     if net_depths is None:
         net_depths = (1 << net_max_depth) - 1
     return Cfg(width, height, s_batch, max_depth, pass_begin, n_passes, mode, norm_mode, net_max_depth, frozen,
-               cap_factor, f_rate, seed, alpha, p_train, rec_cap, update_guide, tau, net_depths)
+               cap_factor, f_rate, seed, alpha, p_train, rec_cap, update_guide, tau, net_depths, fixed_depths)
 
 
 def render(sc: OracleScene, cfg: Cfg, params=None, guide=None, image=None, records=False):

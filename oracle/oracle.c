@@ -898,7 +898,9 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
   st->rays += rays;
   /* shading, in slot order (FP64 image sums in a fixed order) */
   /* Mix-Depth (Sec. 4.3): the method is chosen per bounce; the network only where the table says */
-  int net = cfg->mode == OR_MODE_NET && depth <= 64 && ((cfg->net_depths >> (depth - 1)) & 1u) && c->params != NULL;
+  int fixed = cfg->mode != OR_MODE_OFF && depth <= 64 && ((cfg->fixed_depths >> (depth - 1)) & 1u);
+  int net = !fixed && cfg->mode == OR_MODE_NET && depth <= 64 && ((cfg->net_depths >> (depth - 1)) & 1u) &&
+            c->params != NULL;
   for (uint64_t i = 0; i < n; ++i) {
     entry* e = &Q[i];
     vstate* v = &V[i];
@@ -930,6 +932,9 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
     } else {
       double tr[3] = {e->t[0] * mp[0], e->t[1] * mp[1], e->t[2] * mp[2]};
       v->q = lum3(tr); /* heuristic: luminance of throughput x albedo */
+      /* Mix-Depth's fixed rate (Sec. 4.3): one raw factor for every vertex that continues, so the
+       * normalization gives all of them the same expected number of children */
+      if (fixed) v->q = v->q > 0.0 ? 1.0 : 0.0;
     }
     /* training record (vertex reflected radiance target, descendants add to it) */
     if (cfg->mode != OR_MODE_OFF && e->train && depth <= (uint32_t)cfg->net_max_depth && depth <= MAXREC &&

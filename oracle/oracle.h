@@ -47,6 +47,8 @@ typedef struct {
   double tau;            /* near-tie margin for the fragile-pixel flags */
   uint64_t net_depths;   /* Mix-Depth table (Sec. 4.3): NET mode evaluates the network at depth d
                             when bit d-1 is set and keeps the heuristic factor at the other depths */
+  uint64_t fixed_depths; /* Mix-Depth's fixed rate: at depth d with bit d-1 set every vertex that
+                            continues gets the raw factor 1 (HEUR and NET modes; before the network) */
 } or_cfg;
 
 typedef struct {

@@ -48,6 +48,7 @@ struct nrrs_ctx {
   uint32_t* work = nullptr;         // traversal claim counters per depth and queue slice
   nrrs_tuning tune{};               // launch parameters of the traversal kernel
   uint64_t net_depths = 0;          // Mix-Depth table: bit d-1 = network factor at depth d (NET mode)
+  uint64_t fixed_depths = 0;        // Mix-Depth table: bit d-1 = fixed rate at depth d (wins over the network)
   // workspace
   uint8_t* ws = nullptr;
   uint64_t ws_bytes = 0, max_tris = 0;
@@ -524,6 +525,19 @@ int32_t nrrs_get_pass_index(const nrrs_ctx* c, uint64_t* next_pass) {
   return NRRS_OK;
 }
 
+int32_t nrrs_set_mix_depth_fixed(nrrs_ctx* c, uint64_t fixed_depths) {
+  if (!c) return NRRS_EINVAL;
+  if (fixed_depths != c->fixed_depths) c->drop_graphs();  // captured passes hold the old launch sequence
+  c->fixed_depths = fixed_depths;
+  return NRRS_OK;
+}
+
+int32_t nrrs_get_mix_depth_fixed(const nrrs_ctx* c, uint64_t* fixed_depths) {
+  if (!c || !fixed_depths) return NRRS_EINVAL;
+  *fixed_depths = c->fixed_depths;
+  return NRRS_OK;
+}
+
 int32_t nrrs_get_mix_depth(const nrrs_ctx* c, uint64_t* net_depths) {
   if (!c || !net_depths) return NRRS_EINVAL;
   *net_depths = c->net_depths;
@@ -611,7 +625,10 @@ int32_t nrrs_render(nrrs_ctx* c, uint32_t spp, uint32_t max_depth, int32_t mode,
       if (b.records_on && d <= (uint32_t)c->cfg.net_max_depth) launch_record_features(b, c->cfg.records_cap, s);
       MARK(2);
       if (d == max_depth) break;
-      if (mode == NRRS_MODE_NET && ((c->net_depths >> (d - 1)) & 1u)) {
+      if (mode != NRRS_MODE_OFF && ((c->fixed_depths >> (d - 1)) & 1u)) {
+        launch_fixed_factor(b, s);
+        MARK(3);
+      } else if (mode == NRRS_MODE_NET && ((c->net_depths >> (d - 1)) & 1u)) {
         launch_rrsnet(b, net, s);
         MARK(3);
       }

@@ -58,6 +58,7 @@ void launch_camera(const RenderArgs& a, hipStream_t s);
 void launch_extend(const RenderArgs& a, hipStream_t s);
 void launch_shade(const RenderArgs& a, hipStream_t s);
 void launch_record_features(const RenderArgs& a, uint64_t records_cap, hipStream_t s);  // after shade, same depth
+void launch_fixed_factor(const RenderArgs& a, hipStream_t s);  // Mix-Depth fixed rate, after shade
 void launch_sum_q(const RenderArgs& a, hipStream_t s);
 void launch_roulette(const RenderArgs& a, hipStream_t s);  // count, scan, guard, offsets
 void launch_expand(const RenderArgs& a, hipStream_t s);

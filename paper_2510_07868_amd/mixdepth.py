@@ -9,15 +9,16 @@ not touch training.
 
 `render_efficiency_scorer` is the score this renderer uses: one wavefront pass rendered with
 the table on common random numbers, efficiency = 1 / (RelMSE against a reference image x GPU
-time of the pass).  The methods available per bounce here are the network factor (NET) and the heuristic factor
-lum(throughput x albedo) (HEUR), both normalized per depth (Sec. 4.1 Eqs. 9-10).
+time of the pass).  The methods available per bounce here are the network factor (NET), the
+heuristic factor lum(throughput x albedo) (HEUR) and the fixed rate (FIXED: the same raw factor
+for every vertex that continues), all normalized per depth (Sec. 4.1 Eqs. 9-10).
 """
 import itertools
 
 import numpy as np
 
-NET, HEUR = "net", "heur"
-METHODS = (NET, HEUR)
+NET, HEUR, FIXED = "net", "heur", "fixed"
+METHODS = (NET, HEUR, FIXED)
 LUM = np.array([0.2126, 0.7152, 0.0722])
 
 
@@ -50,9 +51,9 @@ def heuristic_search(n_bounces, t_d, methods, score, fallback):
     return chosen, best_s, total
 
 
-def table_to_mask(table):
-    """NET-mode depth mask of a table: bit d-1 set where bounce d uses the network."""
-    return sum(1 << d for d, m in enumerate(table) if m == NET)
+def table_to_mask(table, method=NET):
+    """Depth mask of one method in a table: bit d-1 set where bounce d uses `method`."""
+    return sum(1 << d for d, m in enumerate(table) if m == method)
 
 
 def relmse(img, ref):
@@ -61,7 +62,7 @@ def relmse(img, ref):
 
 def render_efficiency_scorer(renderer, max_depth, reference, mode_net, passes=1):
     """Score of a table: render `passes` passes (s_batch samples per pixel each) in NET mode with
-    the table as the Mix-Depth mask; efficiency = 1 / (RelMSE of the luminance image against
+    the table's network and fixed-rate depth masks; efficiency = 1 / (RelMSE of the luminance image against
     `reference` (RGB or luminance per pixel, e.g. the guide image: the running mean of the
     frames rendered so far) x GPU milliseconds of the render).
 
@@ -79,7 +80,8 @@ def render_efficiency_scorer(renderer, max_depth, reference, mode_net, passes=1)
     first_pass = renderer.get_pass_index()
 
     def score(table):
-        renderer.set_mix_depth(table_to_mask(table))
+        renderer.set_mix_depth(table_to_mask(table, NET))
+        renderer.set_mix_depth_fixed(table_to_mask(table, FIXED))
         renderer.reset_image()
         renderer.set_guide(guide)
         renderer.set_pass_index(first_pass)

@@ -27,6 +27,7 @@ STAGES = ["camera", "extend", "shade", "network", "sum_q", "roulette_scan", "exp
 EXPORTS = [
     "nrrs_create", "nrrs_workspace_size", "nrrs_bind_workspace", "nrrs_upload_scene", "nrrs_render",
     "nrrs_set_timing", "nrrs_set_launch_mode", "nrrs_set_mix_depth", "nrrs_get_mix_depth",
+    "nrrs_set_mix_depth_fixed", "nrrs_get_mix_depth_fixed",
     "nrrs_set_pass_index", "nrrs_get_pass_index", "nrrs_get_tuning", "nrrs_set_tuning", "nrrs_autotune",
     "nrrs_train_step", "nrrs_read_image", "nrrs_reset_image", "nrrs_set_guide", "nrrs_get_guide",
     "nrrs_get_params", "nrrs_set_params", "nrrs_read_records", "nrrs_debug_rrs_expand",
@@ -103,6 +104,8 @@ def load():
         "nrrs_set_launch_mode": [P, I32],
         "nrrs_set_mix_depth": [P, U64],
         "nrrs_get_mix_depth": [P, P],
+        "nrrs_set_mix_depth_fixed": [P, U64],
+        "nrrs_get_mix_depth_fixed": [P, P],
         "nrrs_set_pass_index": [P, U64],
         "nrrs_get_pass_index": [P, P],
         "nrrs_get_tuning": [P, P],
@@ -240,6 +243,17 @@ class Renderer:
     def get_pass_index(self):
         m = C.c_uint64()
         self._check(self.L.nrrs_get_pass_index(self.h, C.byref(m)))
+        return int(m.value)
+
+    def set_mix_depth_fixed(self, fixed_depths):
+        """Depths with the fixed-rate factor: an int bitmask (bit d-1 = depth d) or an iterable of depths."""
+        if not isinstance(fixed_depths, int):
+            fixed_depths = sum(1 << (d - 1) for d in set(fixed_depths))
+        self._check(self.L.nrrs_set_mix_depth_fixed(self.h, C.c_uint64(fixed_depths)))
+
+    def get_mix_depth_fixed(self):
+        m = C.c_uint64()
+        self._check(self.L.nrrs_get_mix_depth_fixed(self.h, C.byref(m)))
         return int(m.value)
 
     def get_mix_depth(self):

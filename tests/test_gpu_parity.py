@@ -465,6 +465,34 @@ def test_mix_depth_table_matches_oracle(O, nrrs_mod, scenes):
     assert np.abs(st["n"][1:].astype(np.int64) - o["n"][1:].astype(np.int64)).max() <= max(8, 0.004 * W * H)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+def test_mix_depth_fixed_rate_matches_oracle(O, nrrs_mod, scenes, mode):
+    # the fixed rate at depths 2 and 4, the network (NET mode) or the heuristic factor elsewhere
+    W = H = 32
+    D = 6
+    sc = scenes.cornell()
+    rng = np.random.default_rng(5)
+    params = rng.normal(0, 0.2, size=9729).astype(np.float32)
+    guide = rng.uniform(0.05, 2.0, size=W * H).astype(np.float32)
+    r = make(nrrs_mod, sc, W, H, s_batch=2)
+    assert r.get_mix_depth_fixed() == 0
+    r.set_mix_depth_fixed([2, 4])
+    assert r.get_mix_depth_fixed() == 0b1010
+    r.set_params(params)
+    r.set_guide(guide)
+    st = r.render(2, D, mode)
+    img, _ = r.read_image()
+    cfg = O.make_cfg(W, H, 2, D, n_passes=1, mode=mode, tau=1e-4, fixed_depths=0b1010)
+    o = O.render(O.OracleScene(sc), cfg, params=params.astype(np.float64), guide=guide.astype(np.float64))
+    bad, ok = _compare_images(img, o["image"] / 2.0, o["fragile"], rtol=2e-4)
+    assert ok.mean() > 0.85, ok.mean()
+    assert bad.sum() <= 0.002 * W * H, bad.sum()
+    assert st["sumq"][1] == pytest.approx(o["sumq"][1], rel=1e-4)
+    # a fixed-rate depth sums ones: the number of continuing vertices, exactly
+    assert st["sumq"][2] == float(int(st["sumq"][2])) and st["sumq"][2] > 0
+    assert np.abs(st["n"][1:].astype(np.int64) - o["n"][1:].astype(np.int64)).max() <= max(8, 0.004 * W * H)
+
+
 def test_mix_depth_table_switch_in_graph_replay(nrrs_mod, scenes):
     # NET mode with an empty table is the heuristic render bit for bit; changing the table
     # drops the captured pass graphs, so replays agree with direct launches for every table
@@ -487,9 +515,11 @@ def test_mix_depth_table_switch_in_graph_replay(nrrs_mod, scenes):
     assert np.array_equal(rh.read_image()[0], rg.read_image()[0])
     for key in ("n", "S", "retries"):
         assert np.array_equal(sh[key], sg[key]), key
-    for k, mask in enumerate((0b1111, 0b0110, 0b1, 0b1111)):
+    for k, (mask, fixed) in enumerate(((0b1111, 0), (0b0110, 0b1001), (0b1, 0), (0b1111, 0b10))):
         rg.set_mix_depth(mask)
         rd.set_mix_depth(mask)
+        rg.set_mix_depth_fixed(fixed)
+        rd.set_mix_depth_fixed(fixed)
         sg = rg.render(2, D, nrrs_mod.MODE_NET)
         sd = rd.render(2, D, nrrs_mod.MODE_NET)
         ig, ng = rg.read_image()
@@ -563,7 +593,8 @@ def test_checkpoint_resume_continues_the_render(nrrs_mod, scenes):
 
 
 def test_mix_depth_brute_force_search_on_the_gpu(nrrs_mod, scenes):
-    # every table over the 3 bounces that take an RRS decision at depth 4 is scored by one
+    # every table (network / heuristic / fixed rate) over the 3 bounces that take an RRS decision
+    # at depth 4 is scored by one
     # timed pass against a 64-spp heuristic reference; the winner is a valid table
     from paper_2510_07868_amd import mixdepth as M
     W = H = 64
@@ -577,9 +608,9 @@ def test_mix_depth_brute_force_search_on_the_gpu(nrrs_mod, scenes):
     assert spp == 64
     score = M.render_efficiency_scorer(r, D, ref, nrrs_mod.MODE_NET)
     best, s, n = M.brute_force(D - 1, M.METHODS, score)
-    assert n == 8 and len(best) == 3 and set(best) <= set(M.METHODS)
+    assert n == 27 and len(best) == 3 and set(best) <= set(M.METHODS)
     assert np.isfinite(s) and s > 0
-    assert r.get_mix_depth() == M.table_to_mask((M.HEUR,) * 3)   # the last table scored
+    assert r.get_mix_depth() == 0 and r.get_mix_depth_fixed() == 0b111   # the last table scored
 
 
 # ----------------------------------------------------------------------------- network

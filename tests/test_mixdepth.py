@@ -77,16 +77,17 @@ def test_segment_longer_than_the_depth_is_the_brute_force():
 def test_table_to_mask():
     assert M.table_to_mask((M.NET,) * 4 + (M.HEUR,) * 3) == 0b1111
     assert M.table_to_mask((M.HEUR, M.NET, M.HEUR, M.NET)) == 0b1010
+    assert M.table_to_mask((M.FIXED, M.NET, M.FIXED), M.FIXED) == 0b101
     assert M.table_to_mask(()) == 0
 
 
-def _net_render(O, sc, net_depths, mode=None, seed=0):
+def _net_render(O, sc, net_depths, mode=None, seed=0, fixed_depths=0):
     W = H = 16
     rng = np.random.default_rng(11)
     params = rng.normal(0, 0.3, size=O.NPARAM)
     guide = rng.uniform(0.05, 2.0, size=W * H)
     cfg = O.make_cfg(W, H, 2, 6, n_passes=1, mode=O.MODE_NET if mode is None else mode, tau=0.0, seed=seed,
-                     net_depths=net_depths)
+                     net_depths=net_depths, fixed_depths=fixed_depths)
     return O.render(sc, cfg, params=params, guide=guide)
 
 
@@ -146,11 +147,14 @@ class _FakeRenderer:
     def set_mix_depth(self, m):
         self.mask = m
 
+    def set_mix_depth_fixed(self, m):
+        self.fixed = m
+
     def reset_image(self):
         self.img = None
 
     def render(self, spp, D, mode):
-        self.log.append((self.pass_index, self.mask, spp, float(self.guide[0])))
+        self.log.append((self.pass_index, self.mask, spp, float(self.guide[0]), self.fixed))
         rng = np.random.default_rng(self.pass_index)
         self.img = 0.5 + rng.normal(0, 0.1, size=(8, 3)) * (1.0 + 0.1 * bin(self.mask).count("1"))
         self.guide[:] = 123.0          # a real pass refreshes the guide
@@ -166,10 +170,35 @@ def test_scorer_renders_every_table_on_the_same_pass_and_cache_state():
     score = M.render_efficiency_scorer(r, 4, np.full(8, 0.5), mode_net=2)
     tables = list(itertools.product(M.METHODS, repeat=3))
     s = {t: score(t) for t in tables}
-    assert [e[0] for e in r.log] == [9] * 8           # common random numbers: pass 9 every time
-    assert [e[3] for e in r.log] == [0.5] * 8         # the guide restored before each pass
-    assert [e[1] for e in r.log] == [M.table_to_mask(t) for t in tables]
+    assert [e[0] for e in r.log] == [9] * 27          # common random numbers: pass 9 every time
+    assert [e[3] for e in r.log] == [0.5] * 27        # the guide restored before each pass
+    assert [e[1] for e in r.log] == [M.table_to_mask(t, M.NET) for t in tables]
+    assert [e[4] for e in r.log] == [M.table_to_mask(t, M.FIXED) for t in tables]
     assert all(e[2] == r.s_batch for e in r.log)
     # fewer network depths: lower error and less time in this stand-in, so a higher score
+    # (ties between heuristic and fixed keep the first table found)
     assert max(s, key=s.get) == (M.HEUR,) * 3
     assert r.get_pass_index() == 10
+
+
+def test_oracle_fixed_rate_gives_every_continuing_vertex_one_factor(O, scenes):
+    # furnace: every vertex continues; at a fixed-rate depth the raw factors sum to the number of
+    # entries (each is 1), and with the budget equal to that count every path has one child
+    sc = O.OracleScene(scenes.furnace())
+    D = 6
+    cfg = O.make_cfg(8, 8, 1, D, mode=O.MODE_HEUR, tau=0.0, fixed_depths=0b11111)
+    r = O.render(sc, cfg)
+    assert np.all(r["sumq"][1:D] == r["n"][1:D])
+    assert np.all(r["S"][1:D] == r["n"][1:D]) and np.all(r["F"][1:D] == 1.0)
+
+
+def test_oracle_fixed_rate_wins_over_the_network_and_only_at_its_depth(O, scenes):
+    sc = O.OracleScene(scenes.cornell())
+    both = _net_render(O, sc, 0b1111, fixed_depths=0b10)
+    heur_fixed = _net_render(O, sc, 0, mode=O.MODE_HEUR, fixed_depths=0b10)
+    net = _net_render(O, sc, 0b1111)
+    # depth 1 keeps the network, depth 2 is the fixed rate: a sum of ones, an integer
+    assert both["sumq"][1] == net["sumq"][1]
+    assert both["sumq"][2] == float(int(both["sumq"][2])) and both["sumq"][2] > 0
+    assert heur_fixed["sumq"][2] == float(int(heur_fixed["sumq"][2]))
+    assert net["sumq"][2] != float(int(net["sumq"][2]))
