@@ -268,10 +268,11 @@ def efficiency(r, nrrs, spp, D, ref_spp, renders, make_reference):
     guide = r.get_guide()
     default = r.get_mix_depth()
     # Mix-Depth search: one timed pass per table, scored against the guide image (the running
-    # mean of the training frames); segments of 5 bounces over the D - 1 that take a decision
+    # mean of the training frames); segments of 5 bounces over the D - 1 that take a decision,
+    # the bounces after the segment being searched held at the fixed rate
     t0 = time.perf_counter()
     score = mixdepth.render_efficiency_scorer(r, D, guide, nrrs.MODE_NET)
-    table, _, n_tables = mixdepth.heuristic_search(D - 1, 5, mixdepth.METHODS, score, fallback=mixdepth.HEUR)
+    table, _, n_tables = mixdepth.heuristic_search(D - 1, 5, mixdepth.METHODS, score, fallback=mixdepth.FIXED)
     t_search = time.perf_counter() - t0
     plus = (mixdepth.table_to_mask(table, mixdepth.NET), mixdepth.table_to_mask(table, mixdepth.FIXED))
     for name, mode, (mask, fixed) in (("nrrs", nrrs.MODE_NET, (default, 0)), ("nrrs_plus", nrrs.MODE_NET, plus),

@@ -24,7 +24,7 @@ LUM = np.array([0.2126, 0.7152, 0.0722])
 
 def brute_force(n_bounces, methods, score, prefix=(), suffix=()):
     """Score prefix + c + suffix for every c in methods^n_bounces; return (best table, best
-    score, number of tables scored).  Ties keep the first table in lexicographic order."""
+    score, number of tables scored).  Ties keep the first table in the order `methods` enumerates."""
     best, best_s, n = None, -np.inf, 0
     for combo in itertools.product(methods, repeat=n_bounces):
         table = tuple(prefix) + combo + tuple(suffix)
