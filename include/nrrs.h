@@ -81,6 +81,9 @@ typedef struct {
   int32_t loss;           /* nrrs_loss used by nrrs_train_step */
   double ema_decay;       /* inference uses an exponential moving average of the weights with this
                              decay per Adam step (Sec. 5 "Training"); 0 = the latest weights */
+  uint32_t trace_depth;   /* > 0: reserve workspace for nrrs_set_trace (per-path radiance of
+                             depths 1..trace_depth: 8 B per queue slot + 24 * trace_depth B per
+                             primary path); 0: not available */
 } nrrs_config;
 
 typedef struct {
@@ -137,8 +140,10 @@ int32_t nrrs_upload_scene(nrrs_ctx* ctx, const float* verts, uint64_t nv, const 
  * NET modes training records are captured when records_cap > 0.  Asynchronous unless
  * stats is non-NULL, in which case the stream is synchronized and the per-depth
  * statistics of this call are written.  NET mode without a guide image (no earlier
- * render, nor nrrs_set_guide) uses the heuristic factor.  EOVERFLOW is returned (with
- * stats) when at some depth no alpha among 32 successive reductions fit the queue;
+ * render, nor nrrs_set_guide) uses the heuristic factor.  When a depth's children would
+ * exceed the queue capacity, the roulette is repeated with the same uniforms and alpha
+ * reduced by the factor 0.99 until they fit (Eq. 14; alpha persists across passes until
+ * nrrs_reset_image).  EOVERFLOW is returned (with stats) when alpha fell below 1e-3 first;
  * that pass was truncated at that depth. */
 int32_t nrrs_render(nrrs_ctx* ctx, uint32_t spp, uint32_t max_depth, int32_t mode,
                     nrrs_render_stats* stats);
@@ -176,6 +181,27 @@ int32_t nrrs_get_guide(nrrs_ctx* ctx, float* host_lum);
 int32_t nrrs_get_params(nrrs_ctx* ctx, float* master, float* adam_m, float* adam_v, uint64_t* step);
 int32_t nrrs_set_params(nrrs_ctx* ctx, const float* master, const float* adam_m,
                         const float* adam_v, const uint64_t* step);
+
+/* Network state that nrrs_get_params leaves out, for a checkpoint that resumes exactly:
+ * infer[NRRS_NPARAM], the inference weights (the moving average of the masters that the
+ * renders use, Sec. 5 "Training"), and *alpha, the adaptive rate of the overflow guard
+ * (Eq. 14), which persists across passes.  Either pointer may be NULL.  set: call it after
+ * nrrs_set_params (which resets the inference weights to the masters); it refreshes the
+ * BF16 / FP8 inference copies.  EINVAL for a non-finite weight or alpha outside (0, 1]. */
+int32_t nrrs_get_state(nrrs_ctx* ctx, float* infer, double* alpha);
+int32_t nrrs_set_state(nrrs_ctx* ctx, const float* infer, const double* alpha);
+
+/* Per-path radiance by depth (a parity aid for the one-sample estimator of Sec. 3,
+ * Eqs. (1)-(2)): while enabled, every emission collected at vertex depth d is also added
+ * (FP64) to entry (k, d) of the primary path k it descends from, so that a path that takes a
+ * different near-tie decision at some depth can still be compared at the depths before it.
+ * Primary path k of a pass is sample k mod s_batch of pixel k / s_batch; the sums accumulate
+ * over passes until nrrs_set_trace(ctx, 1) is called again (which zeroes them).  Enabling
+ * needs a context created with trace_depth > 0 (ESTATE otherwise); while enabled, renders
+ * deeper than trace_depth return EINVAL.  Switching drops the captured pass graphs.  read:
+ * copies host_rgb[W*H*s_batch][trace_depth][3] (synchronizes). */
+int32_t nrrs_set_trace(nrrs_ctx* ctx, int32_t enabled);
+int32_t nrrs_read_trace(nrrs_ctx* ctx, double* host_rgb);
 
 /* How nrrs_render enqueues a pass: 1 (default) captures the pass's launch sequence once per
  * (max_depth, mode, records on/off) into a hipGraph and replays it for every pass; 0 launches
@@ -263,7 +289,9 @@ int32_t nrrs_read_records(nrrs_ctx* ctx, uint64_t* n, float* features, float* lu
  * n raw factors q_orig[n] whose uniforms come from Philox keyed by lineage ids
  * id_lo[n], id_hi[n] at `depth` (purpose 1).  budget_base is N_px; *alpha in/out.
  * Outputs X[n], offset[n], parent_of_child[S] (parent-major compaction), *S, *F,
- * q_norm[n] (may be NULL), *retries.  cap is the queue capacity (<= n * 64). */
+ * q_norm[n] (may be NULL), *retries (alpha reductions applied).  cap is the queue capacity
+ * (at most the context's).  *alpha must lie in (0, 1].  Returns EOVERFLOW (with *alpha and
+ * *retries of the reduction that fell below 1e-3, S = 0) when no reduction fits. */
 int32_t nrrs_debug_rrs_expand(nrrs_ctx* ctx, const float* q_orig, const uint32_t* id_lo,
                               const uint32_t* id_hi, uint32_t n, uint32_t depth, double budget_base,
                               double f_rate, double* alpha, int32_t norm_mode, uint32_t cap,

@@ -73,9 +73,9 @@ def lib():
         L.or_rrs_expand.argtypes = [P, P, C.c_uint64, C.c_double, C.c_double, P, C.c_int32, C.c_uint64,
                                     P, P, P, P, P, P, P]
         L.or_render.restype = C.c_int32
-        L.or_render.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.or_render.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
         L.or_enumerate.restype = C.c_int32
-        L.or_enumerate.argtypes = [P, P, P, P, P, P]
+        L.or_enumerate.argtypes = [P, P, P, P, P, P, P, P, P]
         L.or_mlp_forward.argtypes = [P, P, C.c_uint64, P, P]
         L.or_mlp_forward_quant.argtypes = [P, P, C.c_uint64, C.c_int32, P, P, P]
         L.or_round_bf16.restype = C.c_double
@@ -201,8 +201,11 @@ def make_cfg(width, height, s_batch=1, max_depth=8, pass_begin=0, n_passes=1, mo
                cap_factor, f_rate, seed, alpha, p_train, rec_cap, update_guide, tau, net_depths, fixed_depths)
 
 
-def render(sc: OracleScene, cfg: Cfg, params=None, guide=None, image=None, records=False):
-    """Run passes [pass_begin, pass_begin + n_passes); returns a dict with the FP64 radiance sums."""
+def render(sc: OracleScene, cfg: Cfg, params=None, guide=None, image=None, records=False, paths=False):
+    """Run passes [pass_begin, pass_begin + n_passes); returns a dict with the FP64 radiance sums.
+    paths: also the radiance of every primary path by vertex depth (path_rgb [nprim, D, 3], summed
+    over the passes) and the first depth a near-tie decision may change (path_first [nprim],
+    D + 1 = none)."""
     npx = cfg.width * cfg.height
     img = np.zeros(npx * 3) if image is None else image
     assert img.dtype == np.float64 and img.size == npx * 3
@@ -219,13 +222,20 @@ def render(sc: OracleScene, cfg: Cfg, params=None, guide=None, image=None, recor
     rd, rp = np.zeros(max(cap, 1), np.uint32), np.zeros(max(cap, 1), np.uint32)
     ri = np.zeros(max(cap, 1), np.uint64)
     N = None
+    nprim = npx * cfg.s_batch
+    prgb = np.zeros(nprim * cfg.max_depth * 3) if paths else None
+    pfrag = np.zeros(nprim, np.uint8) if paths else None
     status = lib().or_render(sc.h, C.byref(cfg), N if pr is None else _p(pr), N if gd is None else _p(gd), _p(img),
-                             _p(frag), C.byref(st), _p(rf), _p(rl), _p(ra), _p(rd), _p(rp), _p(ri))
+                             _p(frag), C.byref(st), _p(rf), _p(rl), _p(ra), _p(rd), _p(rp), _p(ri),
+                             N if prgb is None else _p(prgb), N if pfrag is None else _p(pfrag))
     D = cfg.max_depth
     out = dict(status=int(status), image=img, fragile=frag.astype(bool), alpha=cfg.alpha,
                n=np.array(st.n[: D + 1]), active=np.array(st.active[: D + 1]), S=np.array(st.S[: D + 1]),
                retries=np.array(st.retries[: D + 1]), sumq=np.array(st.sumq[: D + 1]), F=np.array(st.F[: D + 1]),
                rays=int(st.rays), n_records=int(st.n_records))
+    if paths:
+        out["path_rgb"] = prgb.reshape(nprim, cfg.max_depth, 3)
+        out["path_first"] = pfrag.astype(np.int64)
     if records:
         k = int(st.n_records)
         out["records"] = dict(feat=rf[:k].copy(), lum_t=rl[:k].copy(), acc=ra[:k].copy(), depth=rd[:k].copy(),
@@ -233,13 +243,20 @@ def render(sc: OracleScene, cfg: Cfg, params=None, guide=None, image=None, recor
     return out
 
 
-def enumerate_expectation(sc: OracleScene, cfg: Cfg):
+def enumerate_expectation(sc: OracleScene, cfg: Cfg, with_pmf=False):
     npx = cfg.width * cfg.height
+    nprim = npx * cfg.s_batch
+    cap = int(np.floor(cfg.cap_factor * nprim))
     ie, io = np.zeros(npx * 3), np.zeros(npx * 3)
     ms, br = np.zeros(1, np.uint64), np.zeros(1, np.uint64)
-    st = lib().or_enumerate(sc.h, C.byref(cfg), _p(ie), _p(io), _p(ms), _p(br))
+    pmf = np.zeros((cfg.max_depth + 1) * (cap + 2))
+    live = np.zeros(cfg.max_depth + 1)
+    qn1 = np.zeros(nprim, np.float32)
+    st = lib().or_enumerate(sc.h, C.byref(cfg), _p(ie), _p(io), _p(ms), _p(br), _p(pmf), _p(live), _p(qn1))
     if st != 0:
         raise RuntimeError(f"or_enumerate failed: {st}")
+    if with_pmf:
+        return ie, io, int(ms[0]), int(br[0]), pmf.reshape(cfg.max_depth + 1, cap + 2), live, qn1
     return ie, io, int(ms[0]), int(br[0])
 
 

@@ -804,6 +804,7 @@ int32_t or_rrs_expand(const double* q_orig, const double* u, uint64_t n, double 
 typedef struct {
   double o[3], d[3], t[3];
   uint32_t pix, excl, id_lo, id_hi;
+  uint32_t k0; /* primary path this entry descends from (index within its pass) */
   int32_t rec[MAXREC];
   uint8_t dead, train;
 } entry;
@@ -866,12 +867,26 @@ typedef struct {
   double* rec_feat; double* rec_lumt; double* rec_acc; uint32_t* rec_depth; uint32_t* rec_pix; uint64_t* rec_id;
   uint64_t nrec;
   double ew; /* weight of emission added to the image (enumeration branch probability) */
+  double* path_rgb;      /* optional: radiance per primary path and vertex depth [nprim][D][3],
+                            summed over passes */
+  uint8_t* path_first;   /* optional: per primary path, the smallest depth at which it or a
+                            descendant took a near-tie decision (D + 1 = none) */
 } rctx;
 
-static void add_emission(rctx* c, const entry* e, const double le[3]) {
+/* A near-tie decision on entry e at `depth`: its pixel, and its primary path's radiance from
+ * this depth on, are not compared exactly. */
+static void mark_fragile(rctx* c, const entry* e, uint32_t depth) {
+  if (c->fragile) c->fragile[e->pix] = 1;
+  if (c->path_first && depth < c->path_first[e->k0]) c->path_first[e->k0] = (uint8_t)depth;
+}
+
+static void add_emission(rctx* c, const entry* e, const double le[3], uint32_t depth) {
   double contrib[3] = {c->ew * e->t[0] * le[0], c->ew * e->t[1] * le[1], c->ew * e->t[2] * le[2]};
   if (c->image)
     for (int k = 0; k < 3; ++k) c->image[3 * (uint64_t)e->pix + k] += contrib[k];
+  if (c->path_rgb)
+    for (int k = 0; k < 3; ++k)
+      c->path_rgb[3 * ((uint64_t)e->k0 * c->cfg->max_depth + (depth - 1)) + k] += contrib[k];
   double l = lum3(contrib);
   for (int r = 0; r < MAXREC; ++r)
     if (e->rec[r] >= 0 && c->rec_acc) c->rec_acc[e->rec[r]] += l;
@@ -905,9 +920,9 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
     entry* e = &Q[i];
     vstate* v = &V[i];
     if (e->dead) continue;
-    if (v->fragile && c->fragile) c->fragile[e->pix] = 1;
+    if (v->fragile) mark_fragile(c, e, depth);
     if (v->prim == MISS) {
-      add_emission(c, e, s->env);
+      add_emission(c, e, s->env, depth);
       continue;
     }
     const double* tv = s->tri + 9 * (uint64_t)v->prim;
@@ -920,12 +935,12 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
     for (int k = 0; k < 3; ++k) v->p[k] = w0 * tv[k] + v->b1 * tv[3 + k] + v->b2 * tv[6 + k];
     for (int k = 0; k < 3; ++k) v->wo[k] = -e->d[k];
     double cos_o = dot3(ng, v->wo);
-    if (tau > 0.0 && fabs(cos_o) < tau && c->fragile) c->fragile[e->pix] = 1;
+    if (tau > 0.0 && fabs(cos_o) < tau) mark_fragile(c, e, depth);
     int front = cos_o > 0.0;
     for (int k = 0; k < 3; ++k) v->n[k] = front ? ng[k] : -ng[k];
     v->mat = s->tmat[v->prim];
     const double* mp = s->mpar + 7 * (uint64_t)v->mat;
-    if (front && (mp[4] != 0.0 || mp[5] != 0.0 || mp[6] != 0.0)) add_emission(c, e, mp + 4);
+    if (front && (mp[4] != 0.0 || mp[5] != 0.0 || mp[6] != 0.0)) add_emission(c, e, mp + 4, depth);
     if (depth >= D || s->mtype[v->mat] == 2) continue; /* last vertex or pure emitter: terminate */
     if (cfg->mode == OR_MODE_OFF) {
       v->q = 1.0;
@@ -983,7 +998,7 @@ static void expand_children(rctx* c, const entry* Q, const vstate* V, uint64_t n
     onb(v->n, tb, bb);
     /* the local frame switches sign convention at n_z = 0: a nonzero n_z this close to the
      * switch may have the other sign in float32, a near-tie (an exact zero is exact there too) */
-    if (tau > 0.0 && v->n[2] != 0.0 && fabs(v->n[2]) < tau && c->fragile) c->fragile[e->pix] = 1;
+    if (tau > 0.0 && v->n[2] != 0.0 && fabs(v->n[2]) < tau) mark_fragile(c, e, depth + 1);
     double wol[3] = {dot3(v->wo, tb), dot3(v->wo, bb), dot3(v->wo, v->n)};
     for (uint32_t j = 0; j < X[i]; ++j) {
       uint32_t r[4];
@@ -998,7 +1013,7 @@ static void expand_children(rctx* c, const entry* Q, const vstate* V, uint64_t n
           alive = or_ggx_sample(a, mp[k], wol, u2, u3, wil, &wk, &pdf);
           w[k] = wk;
         }
-        if (tau > 0.0 && fabs(wil[2]) < tau && c->fragile) c->fragile[e->pix] = 1;
+        if (tau > 0.0 && fabs(wil[2]) < tau) mark_fragile(c, e, depth + 1);
       } else {
         or_lambert_sample(u2, u3, wil, &pdf);
         for (int k = 0; k < 3; ++k) w[k] = mp[k];
@@ -1013,6 +1028,7 @@ static void expand_children(rctx* c, const entry* Q, const vstate* V, uint64_t n
         ch->t[k] = alive ? e->t[k] * w[k] / (double)v->q32 : 0.0;
       }
       ch->pix = e->pix;
+      ch->k0 = e->k0;
       ch->excl = v->prim;
       ch->id_lo = r[2];
       ch->id_hi = r[3];
@@ -1025,7 +1041,8 @@ static void expand_children(rctx* c, const entry* Q, const vstate* V, uint64_t n
 
 int32_t or_render(const or_scene* s, or_cfg* cfg, const double* params, double* guide, double* image,
                   uint8_t* fragile, or_stats* stats, double* rec_feat, double* rec_lumt, double* rec_acc,
-                  uint32_t* rec_depth, uint32_t* rec_pix, uint64_t* rec_id) {
+                  uint32_t* rec_depth, uint32_t* rec_pix, uint64_t* rec_id, double* path_rgb,
+                  uint8_t* path_first) {
   if (!s || !cfg || cfg->width == 0 || cfg->height == 0 || cfg->s_batch == 0 || cfg->max_depth == 0 ||
       cfg->max_depth > OR_MAXD)
     return -1;
@@ -1042,7 +1059,10 @@ int32_t or_render(const or_scene* s, or_cfg* cfg, const double* params, double* 
   uint32_t* X = (uint32_t*)malloc(sizeof(uint32_t) * qcap);
   uint64_t* off = (uint64_t*)malloc(sizeof(uint64_t) * qcap);
   float* q32 = (float*)malloc(sizeof(float) * qcap);
-  rctx c = {s, cfg, params, guide, image, fragile, rec_feat, rec_lumt, rec_acc, rec_depth, rec_pix, rec_id, 0, 1.0};
+  rctx c = {s, cfg, params, guide, image, fragile, rec_feat, rec_lumt, rec_acc, rec_depth, rec_pix, rec_id, 0, 1.0,
+            path_rgb, path_first};
+  if (path_first)
+    for (uint64_t k = 0; k < nprim; ++k) path_first[k] = (uint8_t)(cfg->max_depth + 1);
   int32_t status = 0;
   for (uint32_t pp = 0; pp < cfg->n_passes && status == 0; ++pp) {
     uint32_t pass = cfg->pass_begin + pp;
@@ -1056,6 +1076,7 @@ int32_t or_render(const or_scene* s, or_cfg* cfg, const double* params, double* 
       camera_ray(s, cfg->width, cfg->height, pix % cfg->width, pix / cfg->width, u01(r[0]), u01(r[1]), e->o, e->d);
       e->t[0] = e->t[1] = e->t[2] = 1.0;
       e->pix = pix;
+      e->k0 = (uint32_t)k;
       e->excl = MISS;
       e->id_lo = (uint32_t)k;
       e->id_hi = pass;
@@ -1092,9 +1113,9 @@ int32_t or_render(const or_scene* s, or_cfg* cfg, const double* params, double* 
       stats->retries[depth] += retries;
       for (uint64_t i = 0; i < n; ++i) {
         V[i].q32 = q32[i];
-        if (fragile && V[i].q > 0.0 && cfg->tau > 0.0) {
+        if (V[i].q > 0.0 && cfg->tau > 0.0) {
           float r = q32[i] - floorf(q32[i]);
-          if (fabs(uv[i] - (double)r) < cfg->tau * (double)q32[i]) fragile[Q[i].pix] = 1;
+          if (fabs(uv[i] - (double)r) < cfg->tau * (double)q32[i]) mark_fragile(&c, &Q[i], depth + 1);
         }
       }
       expand_children(&c, Q, V, n, X, off, Qn, depth);
@@ -1119,6 +1140,10 @@ typedef struct {
   uint64_t nprim, cap;
   double* image;
   uint64_t max_S, branches;
+  double* pmf;      /* optional [(max_depth + 1) * (cap + 2)]: probability of S children at depth d
+                       (bucket cap + 1 collects S > cap) */
+  double* live;     /* optional [max_depth + 1]: probability that depth d normalizes a positive sum */
+  float* qn1;       /* optional [nprim]: the normalized factors of depth 1 */
 } ectx;
 
 static void enum_depth(ectx* ec, entry* Q, uint64_t n, uint32_t depth, double prob) {
@@ -1135,6 +1160,7 @@ static void enum_depth(ectx* ec, entry* Q, uint64_t n, uint32_t depth, double pr
   double sum = 0.0;
   for (uint64_t i = 0; i < n; ++i) sum += V[i].q;
   if (sum == 0.0) { ec->branches++; free(V); return; }
+  if (ec->live) ec->live[depth] += prob;
   double F = ec->cfg.f_rate * ec->cfg.alpha * (double)ec->nprim / sum;
   if (ec->cfg.norm_mode == OR_NORM_DOWNSCALE && F > 1.0) F = 1.0;
   uint32_t* k = (uint32_t*)malloc(sizeof(uint32_t) * n);
@@ -1147,6 +1173,7 @@ static void enum_depth(ectx* ec, entry* Q, uint64_t n, uint32_t depth, double pr
     k[i] = (uint32_t)floorf(q);
     r[i] = (double)(q - floorf(q));
     if (r[i] > 0.0) fi[nf++] = i;
+    if (depth == 1 && ec->qn1) ec->qn1[i] = q;
   }
   uint32_t* X = (uint32_t*)malloc(sizeof(uint32_t) * n);
   uint64_t* off = (uint64_t*)malloc(sizeof(uint64_t) * n);
@@ -1161,6 +1188,7 @@ static void enum_depth(ectx* ec, entry* Q, uint64_t n, uint32_t depth, double pr
     uint64_t S = 0;
     for (uint64_t i = 0; i < n; ++i) { off[i] = S; S += X[i]; }
     if (S > ec->max_S) ec->max_S = S;
+    if (ec->pmf) ec->pmf[(uint64_t)depth * (ec->cap + 2) + (S <= ec->cap ? S : ec->cap + 1)] += p;
     if (p == 0.0) continue;
     entry* Qn = (entry*)malloc(sizeof(entry) * (S ? S : 1));
     rctx cc = {ec->s, &ec->cfg, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, 0, 1.0};
@@ -1172,7 +1200,7 @@ static void enum_depth(ectx* ec, entry* Q, uint64_t n, uint32_t depth, double pr
 }
 
 int32_t or_enumerate(const or_scene* s, const or_cfg* cfg, double* image_expect, double* image_off,
-                     uint64_t* max_S, uint64_t* branches) {
+                     uint64_t* max_S, uint64_t* branches, double* pmf_S, double* live, float* q_norm1) {
   const uint64_t npx = (uint64_t)cfg->width * cfg->height;
   const uint64_t nprim = npx * cfg->s_batch;
   if (nprim > 16 || cfg->max_depth > 6) return -1;
@@ -1187,6 +1215,11 @@ int32_t or_enumerate(const or_scene* s, const or_cfg* cfg, double* image_expect,
   ec.image = image_expect;
   ec.max_S = 0;
   ec.branches = 0;
+  ec.pmf = pmf_S;
+  ec.live = live;
+  ec.qn1 = q_norm1;
+  if (pmf_S) memset(pmf_S, 0, sizeof(double) * (cfg->max_depth + 1) * (ec.cap + 2));
+  if (live) memset(live, 0, sizeof(double) * (cfg->max_depth + 1));
   memset(image_expect, 0, sizeof(double) * 3 * npx);
   entry* Q = (entry*)malloc(sizeof(entry) * nprim);
   uint32_t pass = cfg->pass_begin;
@@ -1197,7 +1230,7 @@ int32_t or_enumerate(const or_scene* s, const or_cfg* cfg, double* image_expect,
     rng_block(cfg->seed, (uint32_t)k, pass, PURPOSE_CAMERA, 0, 0, r);
     camera_ray(s, cfg->width, cfg->height, pix % cfg->width, pix / cfg->width, u01(r[0]), u01(r[1]), e->o, e->d);
     e->t[0] = e->t[1] = e->t[2] = 1.0;
-    e->pix = pix; e->excl = MISS; e->id_lo = (uint32_t)k; e->id_hi = pass;
+    e->pix = pix; e->k0 = (uint32_t)k; e->excl = MISS; e->id_lo = (uint32_t)k; e->id_hi = pass;
     for (int j = 0; j < MAXREC; ++j) e->rec[j] = -1;
     e->dead = 0; e->train = 0;
   }
@@ -1215,7 +1248,7 @@ int32_t or_enumerate(const or_scene* s, const or_cfg* cfg, double* image_expect,
   oc.alpha = 1.0;
   memset(image_off, 0, sizeof(double) * 3 * npx);
   or_stats st;
-  return or_render(s, &oc, NULL, NULL, image_off, NULL, &st, NULL, NULL, NULL, NULL, NULL, NULL);
+  return or_render(s, &oc, NULL, NULL, image_off, NULL, &st, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL);
 }
 
 int32_t or_num_threads(void) {

@@ -88,18 +88,27 @@ int32_t or_rrs_expand(const double* q_orig, const double* u, uint64_t n, double 
                       uint32_t* X, uint64_t* offset, uint32_t* parent_of_child, uint64_t* S,
                       double* F, float* q_norm, uint32_t* retries);
 
-/* Full render: accumulates radiance sums into image[W*H*3] (not divided by spp). */
+/* Full render: accumulates radiance sums into image[W*H*3] (not divided by spp).
+ * Optional per-path outputs (may be NULL): path_rgb[nprim][max_depth][3] accumulates the
+ * radiance that primary path k of a pass (sample k mod s_batch of pixel k / s_batch) and its
+ * split descendants collect at each vertex depth (summed over passes); path_first[nprim] is
+ * the smallest depth whose radiance a near-tie decision of the path or a descendant may
+ * change (max_depth + 1 = none). */
 int32_t or_render(const or_scene* s, or_cfg* cfg, const double* params, double* guide,
                   double* image, uint8_t* fragile, or_stats* stats,
                   double* rec_feat, double* rec_lumt, double* rec_acc, uint32_t* rec_depth,
-                  uint32_t* rec_pix, uint64_t* rec_id);
+                  uint32_t* rec_pix, uint64_t* rec_id, double* path_rgb, uint8_t* path_first);
 
 /* Exhaustive expectation over all roulette outcomes with frozen continuous samples
  * (every child of a vertex reuses the sample of child 0).  Writes the outcome-weighted
  * mean image of one pass and the OFF-mode image on the same samples.  Also returns the
- * largest S seen on any branch and the number of branches. */
+ * largest S seen on any branch and the number of branches.  Optional (may be NULL):
+ * pmf_S[(max_depth + 1) * (C + 2)] with C = floor(cap_factor * nprim): the probability that
+ * depth d emits S children (entry d * (C + 2) + S; S > C goes to entry C + 1);
+ * live[max_depth + 1]: the probability that depth d has a positive factor sum;
+ * q_norm1[nprim]: the float32 normalized factors of depth 1 (a single branch). */
 int32_t or_enumerate(const or_scene* s, const or_cfg* cfg, double* image_expect, double* image_off,
-                     uint64_t* max_S, uint64_t* branches);
+                     uint64_t* max_S, uint64_t* branches, double* pmf_S, double* live, float* q_norm1);
 
 /* Network (Sec. 5): 20 -> 64 -> 64 -> 64 (ReLU) -> 1, modified softplus output. */
 void or_mlp_forward(const double* params, const double* x, uint64_t n, double* y, double* z);

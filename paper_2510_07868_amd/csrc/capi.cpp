@@ -70,6 +70,8 @@ struct nrrs_ctx {
   double *st_sumq = nullptr, *st_f = nullptr;
   double* image = nullptr;
   float* guide = nullptr;
+  double* trace = nullptr;  // per-path radiance [nprim][trace_depth][3] (reserved when cfg.trace_depth > 0)
+  bool trace_on = false;
   Records rec{};
   float* target = nullptr;
   float *master = nullptr, *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;
@@ -130,6 +132,7 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
     qq->thr = k.take<float4>(C);
     qq->id = k.take<uint2>(C);
     qq->rec = k.take<int4>(C);
+    qq->path = c->cfg.trace_depth ? k.take<uint32_t>(C) : nullptr;
     if (qq == &c->qb) {
       c->qb_pool = base ? base + start : nullptr;
       c->qb_pool_bytes = k.off - start;
@@ -159,6 +162,7 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
   c->st_f = k.take<double>(NRRS_MAX_DEPTH + 1);
   c->image = k.take<double>(3 * npx);
   c->guide = k.take<float>(npx);
+  c->trace = c->cfg.trace_depth ? k.take<double>(3ull * c->cfg.trace_depth * c->nprim) : nullptr;
   c->rec.feat = k.take<float>(20 * rc);
   c->rec.lum_t = k.take<float>(rc);
   c->rec.acc = k.take<float>(rc);
@@ -238,6 +242,8 @@ RenderArgs base_args(nrrs_ctx* c) {
   a.rays = c->rays;
   a.image = c->image;
   a.guide = c->guide;
+  a.trace = c->trace_on ? c->trace : nullptr;
+  a.trace_depth = c->cfg.trace_depth;
   a.rec = c->rec;
   a.key = make_uint2((uint32_t)c->cfg.seed, (uint32_t)(c->cfg.seed >> 32));
   a.width = c->cfg.width;
@@ -304,7 +310,7 @@ int32_t nrrs_create(const nrrs_config* cfg, void* hip_stream, nrrs_ctx** out) {
       (cfg->norm_mode != NRRS_NORM_TWO_SIDED && cfg->norm_mode != NRRS_NORM_DOWNSCALE) ||
       cfg->precision < NRRS_PREC_FP32 || cfg->precision > NRRS_PREC_FP8 || !(cfg->p_train >= 0.0) ||
       cfg->p_train > 1.0 || (cfg->loss != NRRS_LOSS_REL_L2 && cfg->loss != NRRS_LOSS_LOG_MSE) ||
-      !(cfg->ema_decay >= 0.0) || cfg->ema_decay >= 1.0)
+      !(cfg->ema_decay >= 0.0) || cfg->ema_decay >= 1.0 || cfg->trace_depth > NRRS_MAX_DEPTH)
     return NRRS_EINVAL;
   const uint64_t npx = (uint64_t)cfg->width * cfg->height;
   const uint64_t nprim = npx * cfg->s_batch;
@@ -362,6 +368,7 @@ int32_t nrrs_bind_workspace(nrrs_ctx* c, void* device_ptr, uint64_t bytes, uint6
   c->max_mats = max_materials;
   c->bound = true;
   c->scene = false;
+  c->trace_on = false;
   hipStream_t s = c->stream;
   launch_zero_f64(c->image, 3 * c->npx, s);
   launch_fill_f32(c->guide, c->npx, -1.0f, s);
@@ -575,6 +582,8 @@ int32_t nrrs_render(nrrs_ctx* c, uint32_t spp, uint32_t max_depth, int32_t mode,
   if (spp == 0 || spp % c->cfg.s_batch != 0) return fail(c, NRRS_EINVAL, "spp must be a positive multiple of s_batch");
   if (max_depth < 1 || max_depth > NRRS_MAX_DEPTH) return fail(c, NRRS_EINVAL, "max_depth out of range");
   if (mode < NRRS_MODE_OFF || mode > NRRS_MODE_NET) return fail(c, NRRS_EINVAL, "unknown mode");
+  if (c->trace_on && max_depth > c->cfg.trace_depth)
+    return fail(c, NRRS_EINVAL, "max_depth beyond the traced depths");
   hipStream_t s = c->stream;
   const uint32_t passes = spp / c->cfg.s_batch;
   RenderArgs a = base_args(c);
@@ -892,6 +901,51 @@ int32_t nrrs_set_params(nrrs_ctx* c, const float* master, const float* adam_m, c
   return NRRS_OK;
 }
 
+int32_t nrrs_get_state(nrrs_ctx* c, float* infer, double* alpha) {
+  if (!c) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  HIPC(c, hipStreamSynchronize(c->stream));
+  if (infer) HIPC(c, hipMemcpy(infer, c->infer, sizeof(float) * kNParam, hipMemcpyDeviceToHost));
+  if (alpha) HIPC(c, hipMemcpy(alpha, c->alpha, sizeof(double), hipMemcpyDeviceToHost));
+  return NRRS_OK;
+}
+
+int32_t nrrs_set_state(nrrs_ctx* c, const float* infer, const double* alpha) {
+  if (!c) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (infer && !finite_all(infer, kNParam)) return fail(c, NRRS_EINVAL, "non-finite inference weight");
+  if (alpha && !(*alpha > 0.0 && *alpha <= 1.0)) return fail(c, NRRS_EINVAL, "alpha outside (0, 1]");
+  HIPC(c, hipStreamSynchronize(c->stream));
+  if (infer) {
+    HIPC(c, hipMemcpy(c->infer, infer, sizeof(float) * kNParam, hipMemcpyHostToDevice));
+    launch_quantize(c->infer, c->bf16, c->fp8, c->fp8_scale, c->stream);
+  }
+  if (alpha) HIPC(c, hipMemcpy(c->alpha, alpha, sizeof(double), hipMemcpyHostToDevice));
+  HIPC(c, hipGetLastError());
+  return NRRS_OK;
+}
+
+int32_t nrrs_set_trace(nrrs_ctx* c, int32_t enabled) {
+  if (!c || (enabled != 0 && enabled != 1)) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (enabled && !c->trace) return fail(c, NRRS_ESTATE, "create the context with trace_depth > 0");
+  if ((enabled != 0) != c->trace_on) c->drop_graphs();  // captured passes hold the old arguments
+  c->trace_on = enabled != 0;
+  if (c->trace_on) launch_zero_f64(c->trace, 3ull * c->cfg.trace_depth * c->nprim, c->stream);
+  HIPC(c, hipGetLastError());
+  return NRRS_OK;
+}
+
+int32_t nrrs_read_trace(nrrs_ctx* c, double* host_rgb) {
+  if (!c || !host_rgb) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (!c->trace) return fail(c, NRRS_ESTATE, "create the context with trace_depth > 0");
+  HIPC(c, hipStreamSynchronize(c->stream));
+  HIPC(c, hipMemcpy(host_rgb, c->trace, sizeof(double) * 3 * c->cfg.trace_depth * c->nprim,
+                    hipMemcpyDeviceToHost));
+  return NRRS_OK;
+}
+
 int32_t nrrs_read_records(nrrs_ctx* c, uint64_t* n, float* features, float* lum_t, float* acc, uint32_t* depth,
                           uint32_t* pix, uint64_t* lineage) {
   if (!c || !n) return NRRS_EINVAL;
@@ -954,7 +1008,7 @@ int32_t nrrs_debug_rrs_expand(nrrs_ctx* c, const float* q_orig, const uint32_t* 
   if (!c || !alpha || !X || !offset || !S || !F || !retries || (n && (!q_orig || !id_lo || !id_hi))) return NRRS_EINVAL;
   if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
   if (n > c->cap || cap > c->cap || depth < 1 || depth >= NRRS_MAX_DEPTH || !(budget_base >= 0.0) ||
-      !(f_rate > 0.0) || !(*alpha > 0.0) || (norm_mode != NRRS_NORM_TWO_SIDED && norm_mode != NRRS_NORM_DOWNSCALE))
+      !std::isfinite(budget_base) || !(f_rate > 0.0) || !std::isfinite(f_rate) || !(*alpha > 0.0 && *alpha <= 1.0) || (norm_mode != NRRS_NORM_TWO_SIDED && norm_mode != NRRS_NORM_DOWNSCALE))
     return fail(c, NRRS_EINVAL, "debug_rrs_expand: argument out of range");
   if (!finite_all(q_orig, n)) return fail(c, NRRS_EINVAL, "non-finite factor");
   for (uint32_t i = 0; i < n; ++i)

@@ -9,7 +9,8 @@ namespace nrrs {
 constexpr uint32_t kMiss = 0xffffffffu;
 constexpr int kMaxRec = 4;           // training records carried per path (depths 1..4)
 constexpr int kNParam = 9729;        // 20-64-64-64-1 network
-constexpr int kGuardSteps = 32;      // alpha reductions tried in one pass of the overflow guard
+constexpr int kGuardSteps = 32;      // alpha reductions counted in parallel by the overflow guard
+constexpr double kAlphaMin = 1e-3;   // the guard reports an overflow once alpha falls below this
 constexpr int kScanBlocks = 2048;    // blocks of the chunked reductions / scans
 constexpr int kScanThreads = 256;
 constexpr uint32_t kFlagDead = 1u;   // entry was emitted below the horizon: traced as nothing
@@ -141,6 +142,8 @@ struct Queue {
   float4* thr;   // throughput rgb, flag bits
   uint2* id;     // lineage id
   int4* rec;     // training-record ids of the depths 1..4 ancestors (-1 = none)
+  uint32_t* path;  // primary path (index within the pass) the entry descends from; only when
+                   // per-path radiance is traced
 };
 
 struct Records {

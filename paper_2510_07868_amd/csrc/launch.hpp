@@ -36,6 +36,8 @@ struct RenderArgs {
   unsigned long long* rays;  // [3] rays traced, BVH nodes visited, triangles tested (accumulated)
   double* image;      // [npx * 3] FP64 radiance sums
   const float* guide; // [npx] luminance of the previous mean (negative = none)
+  double* trace;      // [nprim][trace_depth][3] radiance per primary path and depth, or null
+  uint32_t trace_depth;
   Records rec;
   uint2 key;
   uint32_t width, height, nprim, cap, depth, max_depth, pass, mode, norm_mode, net_max_depth;

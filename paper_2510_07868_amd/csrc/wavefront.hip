@@ -60,6 +60,7 @@ __global__ __launch_bounds__(kEntryThreads) void k_camera(RenderArgs a) {
   a.qin.dir[k] = pack(d, pix);
   a.qin.thr[k] = make_float4(1.0f, 1.0f, 1.0f, __uint_as_float(flags));
   a.qin.id[k] = lin;
+  if (a.trace) a.qin.path[k] = k;
   // record slots travel only with training paths (every reader checks kFlagTrain first)
   if (flags & kFlagTrain) a.qin.rec[k] = make_int4(-1, -1, -1, -1);
 }
@@ -635,6 +636,12 @@ __global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
   if (in_range) a.q[i] = q;
   image_add_wave(a, in_range && !(flags & kFlagDead) ? pix : kNoPix, (double)em.x, (double)em.y, (double)em.z);
   if (emits && a.records_on) record_emission(a, em, rec);
+  if (emits && a.trace) {
+    double* tp = a.trace + 3ull * ((uint64_t)a.qin.path[i] * a.trace_depth + (a.depth - 1));
+    atomicAdd(tp + 0, (double)em.x);
+    atomicAdd(tp + 1, (double)em.y);
+    atomicAdd(tp + 2, (double)em.z);
+  }
   // training record: one counter atomic per block (converged code)
   if (a.records_on) {
     const uint32_t slot = block_alloc(a.rec.count, want_rec, alloc_sh);
@@ -834,43 +841,124 @@ __global__ __launch_bounds__(kScanThreads) void k_guard_count(RenderArgs a) {
   }
 }
 
+// alpha after k reductions by the factor 0.99 (Eq. 14), applied one at a time as in a loop
+// that retries the roulette.
+__device__ __forceinline__ double alpha_after(double alpha, int k) {
+  for (int j = 0; j < k; ++j) alpha *= 0.99;
+  return alpha;
+}
+
+// Children emitted for the k-th alpha reduction, counted by one block over all n entries.
+__device__ __forceinline__ uint64_t block_count_all(const RenderArgs& a, uint32_t n, double F, uint64_t* sh) {
+  uint64_t acc = 0;
+  for (uint32_t i = threadIdx.x; i < n; i += kScanThreads) {
+    const float q = a.q[i];
+    if (q > 0.0f) acc += child_count(q, F, roulette_u(a, i));
+  }
+  return block_sum(acc, sh);
+}
+
+// Picks the first alpha reduction whose children fit the capacity, as a loop that retries
+// the roulette with alpha * 0.99 until S <= C would, and gives up (overflow) once alpha falls
+// below 1e-3.  The counts of reductions 1..kGuardSteps come from k_guard_count; when none of
+// them fits, this block searches the later reductions itself by bisection (the children count
+// does not grow as alpha shrinks: every rounding on the way from alpha to X is monotone).
 __global__ __launch_bounds__(kScanThreads) void k_guard_select(RenderArgs a) {
   if (a.ctl[a.depth].guard == 0) return;
   __shared__ uint64_t sh[kScanThreads];
-  __shared__ int chosen;
+  __shared__ int chosen;   // reduction count that fits, or -(count at which alpha < 1e-3)
+  __shared__ uint64_t chosen_S;
   DepthCtl& c = a.ctl[a.depth];
-  if (threadIdx.x == 0) chosen = -1;
+  const uint32_t n = c.n;
+  const double alpha0 = *a.alpha;
+  if (threadIdx.x == 0) chosen = 0;
   __syncthreads();
-  for (int k = 0; k < kGuardSteps; ++k) {
-    const uint64_t S = scan_blocks(a.gsum + kScanBlocks * k, nullptr, sh);
+  for (int k = 1; k <= kGuardSteps; ++k) {
+    const uint64_t S = scan_blocks(a.gsum + kScanBlocks * (k - 1), nullptr, sh);
+    if (alpha_after(alpha0, k) < kAlphaMin) {
+      if (threadIdx.x == 0) chosen = -k;
+      break;
+    }
     if (S <= a.cap) {
-      scan_blocks(a.gsum + kScanBlocks * k, a.boff, sh);
+      scan_blocks(a.gsum + kScanBlocks * (k - 1), a.boff, sh);
       if (threadIdx.x == 0) {
         chosen = k;
-        double alpha = *a.alpha;
-        for (int j = 0; j <= k; ++j) alpha *= 0.99;
-        *a.alpha = alpha;
-        c.F = norm_factor(a, c.sumq, alpha);
-        c.S = (uint32_t)S;
-        c.retries = (uint32_t)(k + 1);
-        a.ctl[a.depth + 1].n = (uint32_t)S;
+        chosen_S = S;
       }
       break;
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0 && chosen < 0) {
-    // no candidate fits: end this pass at this depth and report it
-    double alpha = *a.alpha;
-    for (int j = 0; j < kGuardSteps; ++j) alpha *= 0.99;
-    *a.alpha = alpha;
-    c.F = 0.0;
-    c.S = 0;
-    c.retries = kGuardSteps;
-    a.ctl[a.depth + 1].n = 0;
-    *a.overflow = 1;
+  bool need_block_sums = false;
+  if (chosen == 0) {
+    // rare path: bisection over the reductions kGuardSteps+1 .. K, K the last with alpha >= 1e-3
+    int K = kGuardSteps;
+    double aK = alpha_after(alpha0, K);
+    while (aK * 0.99 >= kAlphaMin) {
+      aK *= 0.99;
+      ++K;
+    }
+    int lo = kGuardSteps + 1, hi = K;
+    uint64_t S_hi = ~0ull;
+    if (hi >= lo) S_hi = block_count_all(a, n, norm_factor(a, c.sumq, aK), sh);
+    if (hi < lo || S_hi > a.cap) {
+      if (threadIdx.x == 0) chosen = -(K + 1);
+    } else {
+      while (lo < hi) {  // invariant: S(hi) <= cap; every k < lo has S(k) > cap
+        const int mid = (lo + hi) / 2;
+        const uint64_t Sm = block_count_all(a, n, norm_factor(a, c.sumq, alpha_after(alpha0, mid)), sh);
+        if (Sm <= a.cap) {
+          hi = mid;
+          S_hi = Sm;
+        } else {
+          lo = mid + 1;
+        }
+      }
+      if (threadIdx.x == 0) {
+        chosen = hi;
+        chosen_S = S_hi;
+      }
+      need_block_sums = true;
+    }
+    __syncthreads();
   }
-  if (chosen < 0)
+  const int k = chosen;
+  if (need_block_sums) {
+    // children per chunk of k_offsets for the chosen reduction, then their exclusive scan
+    const double F = norm_factor(a, c.sumq, alpha_after(alpha0, k));
+    const uint32_t chunk = chunk_of(n);
+    for (int b = 0; b < kScanBlocks; ++b) {
+      const uint32_t beg = (uint32_t)b * chunk;
+      uint64_t acc = 0;
+      for (uint32_t i = beg + threadIdx.x; i < beg + chunk && i < n; i += kScanThreads) {
+        const float q = a.q[i];
+        if (q > 0.0f) acc += child_count(q, F, roulette_u(a, i));
+      }
+      const uint64_t s = block_sum(acc, sh);
+      if (threadIdx.x == 0) a.gsum[b] = (uint32_t)s;
+    }
+    __syncthreads();
+    scan_blocks(a.gsum, a.boff, sh);
+  }
+  if (threadIdx.x == 0) {
+    if (k > 0) {
+      const double alpha = alpha_after(alpha0, k);
+      *a.alpha = alpha;
+      c.F = norm_factor(a, c.sumq, alpha);
+      c.S = (uint32_t)chosen_S;
+      c.retries = (uint32_t)k;
+      a.ctl[a.depth + 1].n = (uint32_t)chosen_S;
+    } else {
+      // alpha fell below 1e-3 before any reduction fit: end this pass at this depth, report it
+      *a.alpha = alpha_after(alpha0, -k);
+      c.F = 0.0;
+      c.S = 0;
+      c.retries = (uint32_t)(-k);
+      a.ctl[a.depth + 1].n = 0;
+      *a.overflow = 1;
+    }
+  }
+  if (k < 0)
     for (int b = threadIdx.x; b < kScanBlocks; b += kScanThreads) a.boff[b] = 0;
 }
 
@@ -980,6 +1068,7 @@ __device__ __forceinline__ void expand_child(const RenderArgs& a, uint32_t i, ui
   a.qout.thr[s] = pack(tc, flags);
   a.qout.id[s] = make_uint2(r.z, r.w);
   if (a.records_on && (flags & kFlagTrain)) a.qout.rec[s] = a.qin.rec[i];
+  if (a.trace) a.qout.path[s] = a.qin.path[i];
 }
 
 // Children of a block of kEntryThreads consecutive parents: the block's offsets go to LDS and

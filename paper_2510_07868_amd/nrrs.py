@@ -30,7 +30,8 @@ EXPORTS = [
     "nrrs_set_mix_depth_fixed", "nrrs_get_mix_depth_fixed",
     "nrrs_set_pass_index", "nrrs_get_pass_index", "nrrs_get_tuning", "nrrs_set_tuning", "nrrs_autotune",
     "nrrs_train_step", "nrrs_read_image", "nrrs_reset_image", "nrrs_set_guide", "nrrs_get_guide",
-    "nrrs_get_params", "nrrs_set_params", "nrrs_read_records", "nrrs_debug_rrs_expand",
+    "nrrs_get_params", "nrrs_set_params", "nrrs_get_state", "nrrs_set_state", "nrrs_set_trace",
+    "nrrs_read_trace", "nrrs_read_records", "nrrs_debug_rrs_expand",
     "nrrs_debug_load_records", "nrrs_debug_read_queue", "nrrs_debug_trace",
     "nrrs_debug_philox", "nrrs_debug_mlp_forward", "nrrs_debug_mlp_grad", "nrrs_status_string",
     "nrrs_last_error", "nrrs_destroy",
@@ -57,7 +58,7 @@ class Config(C.Structure):
         ("width", C.c_uint32), ("height", C.c_uint32), ("s_batch", C.c_uint32),
         ("cap_factor", C.c_double), ("f_rate", C.c_double), ("norm_mode", C.c_int32), ("seed", C.c_uint64),
         ("net_max_depth", C.c_int32), ("precision", C.c_int32), ("records_cap", C.c_uint32),
-        ("p_train", C.c_double), ("loss", C.c_int32), ("ema_decay", C.c_double),
+        ("p_train", C.c_double), ("loss", C.c_int32), ("ema_decay", C.c_double), ("trace_depth", C.c_uint32),
     ]
 
 
@@ -118,6 +119,10 @@ def load():
         "nrrs_get_guide": [P, P],
         "nrrs_get_params": [P, P, P, P, P],
         "nrrs_set_params": [P, P, P, P, P],
+        "nrrs_get_state": [P, P, P],
+        "nrrs_set_state": [P, P, P],
+        "nrrs_set_trace": [P, I32],
+        "nrrs_read_trace": [P, P],
         "nrrs_read_records": [P, P, P, P, P, P, P, P],
         "nrrs_debug_rrs_expand": [P, P, P, P, U32, U32, D, D, P, I32, U32, P, P, P, P, P, P, P],
         "nrrs_debug_load_records": [P, P, P, P, U32],
@@ -154,7 +159,8 @@ class Renderer:
 
     def __init__(self, width, height, s_batch=1, cap_factor=2.0, f_rate=1.0, norm_mode=NORM_TWO_SIDED, seed=0,
                  net_max_depth=4, precision=PREC_FP32, records_cap=0, p_train=0.0, max_tris=1 << 16,
-                 max_materials=4096, device="cuda:0", stream=None, loss=LOSS_REL_L2, ema_decay=0.0):
+                 max_materials=4096, device="cuda:0", stream=None, loss=LOSS_REL_L2, ema_decay=0.0,
+                 trace_depth=0):
         import torch
         self.torch = torch
         self.L = load()
@@ -163,7 +169,8 @@ class Renderer:
         # a stream of its own (default priority): hipGraph capture needs a non-null stream
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self.cfg = Config(width, height, s_batch, cap_factor, f_rate, norm_mode, seed, net_max_depth, precision,
-                          records_cap, p_train, loss, ema_decay)
+                          records_cap, p_train, loss, ema_decay, trace_depth)
+        self.trace_depth = trace_depth
         self.width, self.height, self.s_batch = width, height, s_batch
         self.records_cap = records_cap
         h = C.c_void_p()
@@ -312,6 +319,30 @@ class Renderer:
             assert a is None or a.size == NPARAM
         st = None if step is None else C.byref(C.c_uint64(int(step)))
         self._check(self.L.nrrs_set_params(self.h, *[None if a is None else _p(a) for a in arrs], st))
+
+    def get_state(self):
+        """Inference (moving-average) weights and the overflow guard's alpha."""
+        w = np.zeros(NPARAM, np.float32)
+        a = C.c_double()
+        self._check(self.L.nrrs_get_state(self.h, _p(w), C.byref(a)))
+        return w, float(a.value)
+
+    def set_state(self, infer=None, alpha=None):
+        w = None if infer is None else _c(infer, np.float32)
+        assert w is None or w.size == NPARAM
+        self._check(self.L.nrrs_set_state(self.h, None if w is None else _p(w),
+                                          None if alpha is None else C.byref(C.c_double(alpha))))
+
+    def set_trace(self, enabled=True):
+        """Per-path radiance by depth on (zeroes the sums) or off; needs trace_depth > 0 at creation."""
+        self._check(self.L.nrrs_set_trace(self.h, 1 if enabled else 0))
+
+    def read_trace(self):
+        """Radiance per primary path and depth [W*H*s_batch, trace_depth, 3], summed over the passes
+        since set_trace."""
+        out = np.zeros(self.width * self.height * self.s_batch * self.trace_depth * 3)
+        self._check(self.L.nrrs_read_trace(self.h, _p(out)))
+        return out.reshape(-1, self.trace_depth, 3)
 
     def read_records(self):
         n = C.c_uint64()

@@ -76,14 +76,22 @@ def _q(kind, n, rng):
     return rng.uniform(0, 1, size=n).astype(np.float32)
 
 
-@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 1023, 4096, (1 << 20) + 17])
+_EXPAND_CTX = {}
+
+
+def _expand_ctx(nrrs_mod, scenes, n):
+    # capacity 4 M entries, or 16.8 M for the full-size queue of 8,388,608 entries
+    key = "big" if n > (1 << 21) else "small"
+    if key not in _EXPAND_CTX:
+        _EXPAND_CTX.clear()
+        _EXPAND_CTX[key] = make(nrrs_mod, scenes.cornell(), 1024, 1024, s_batch=8 if key == "big" else 2)
+    return _EXPAND_CTX[key]
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 1023, 4096, (1 << 20) + 17, 1 << 23])
 @pytest.mark.parametrize("kind", Q_CASES)
 def test_rrs_expand_bit_exact(O, nrrs_mod, scenes, n, kind):
-    if n > 5000 and kind not in ("uniform", "lognormal", "overflow"):
-        pytest.skip("large n only for the continuous distributions")
-    if kind == "overflow" and n < 1000:
-        pytest.skip("a forced overflow of a few entries can need more than 32 alpha steps")
-    r = make(nrrs_mod, scenes.cornell(), 1024, 1024, s_batch=2)   # capacity 4 M entries
+    r = _expand_ctx(nrrs_mod, scenes, n)
     rng = np.random.default_rng(n * 7 + Q_CASES.index(kind))
     q = _q(kind, n, rng)
     id_lo = rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
@@ -94,21 +102,34 @@ def test_rrs_expand_bit_exact(O, nrrs_mod, scenes, n, kind):
     if kind == "integer":
         budget = float(q.sum()) if q.sum() > 0 else 1.0
         cap = int(2 * budget)
+    print(f"rrs_expand n={n} kind={kind} cap={cap}", flush=True)
     g = r.debug_rrs_expand(q, id_lo, id_hi, depth, budget, cap=cap)
     u = _oracle_u(O, id_lo, id_hi, depth)
     o = O.rrs_expand(q.astype(np.float64), u, budget, cap=cap)
-    assert g["status"] == 0 and o["status"] == 0
+    # the guard retries alpha * 0.99 until the children fit (Eq. 14) and gives up below 1e-3
+    assert g["status"] == o["status"]
+    assert g["retries"] == o["retries"]
+    assert g["alpha"] == o["alpha"]
+    if o["status"] != 0:
+        assert g["status"] == -5 and g["S"] == 0
+        return
     # F: FP64 tree sum vs slot-order sum -> equal up to a few ulps
     assert g["F"] == pytest.approx(o["F"], rel=1e-13, abs=0)
     same_q = g["q_norm"] == o["q_norm"]
     # a q_norm that differs by the last bit may only change X when u sits on that bit
     diff = ~same_q
     assert diff.sum() <= max(2, n // 100000)
-    assert g["retries"] == o["retries"]
-    assert g["alpha"] == o["alpha"]
     X_ok = g["X"] == o["X"]
     assert np.all(X_ok | diff)
-    assert g["S"] == int(g["X"].sum())
+    # where the last bit changed X, the count may move by one; offsets and the parent map
+    # must then be those of the oracle's counts with exactly these entries replaced
+    Xg = g["X"].astype(np.int64)
+    assert np.all(np.abs(Xg - o["X"].astype(np.int64)) <= 1)
+    X_exp = np.where(diff, Xg, o["X"].astype(np.int64))
+    off_exp = np.concatenate([[0], np.cumsum(X_exp)[:-1]]) if n else np.zeros(0, np.int64)
+    assert g["S"] == int(X_exp.sum())
+    assert np.array_equal(g["offset"].astype(np.int64), off_exp)
+    assert np.array_equal(g["parent"].astype(np.int64), np.repeat(np.arange(n), X_exp))
     if np.all(X_ok):
         assert g["S"] == o["S"]
         assert np.array_equal(g["offset"].astype(np.uint64), o["offset"])
@@ -116,6 +137,27 @@ def test_rrs_expand_bit_exact(O, nrrs_mod, scenes, n, kind):
     assert g["S"] <= cap
     if kind == "overflow" and n > 100:
         assert g["retries"] > 0
+
+
+def test_rrs_expand_guard_beyond_parallel_candidates(O, nrrs_mod, scenes):
+    # overflows that need more alpha reductions than the guard counts in parallel (32), and
+    # one that only ends below alpha = 1e-3: retries, alpha and children as the oracle's loop
+    r = _expand_ctx(nrrs_mod, scenes, 1)
+    rng = np.random.default_rng(11)
+    for n, cap, alpha in ((4096, 2048, 1.0), (4096, 1024, 1.0), (4096, 300, 1.0), (5000, 1, 1.0),
+                          (4096, 0, 1.0), (1000, 5, 0.01), (777, 0, 0.0011), (64, 0, 1.0)):
+        q = rng.uniform(0.5, 1.0, size=n).astype(np.float32)
+        id_lo = rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
+        id_hi = rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
+        budget = float(n)
+        print(f"guard n={n} cap={cap} alpha={alpha}", flush=True)
+        g = r.debug_rrs_expand(q, id_lo, id_hi, 3, budget, alpha=alpha, cap=cap)
+        o = O.rrs_expand(q.astype(np.float64), _oracle_u(O, id_lo, id_hi, 3), budget, alpha=alpha, cap=cap)
+        assert (g["status"], g["retries"], g["alpha"]) == (o["status"], o["retries"], o["alpha"])
+        if o["status"] == 0:
+            assert g["S"] == o["S"] <= cap
+            assert np.array_equal(g["X"], o["X"])
+            assert np.array_equal(g["parent"], o["parent"])
 
 
 # ----------------------------------------------------------------------------- traversal
@@ -269,6 +311,75 @@ def _compare_images(g, o, frag, rtol=1e-4):
     return bad, ok
 
 
+def _compare_paths(gp, o, D, rtol=1e-4):
+    """Per-path parity: the radiance each primary path (with its split descendants) collects at
+    the depths before its first near-tie decision, GPU vs oracle.  Returns the paths outside the
+    tolerance, the fraction of paths compared at some depth, the fraction compared at every
+    depth, and the fraction of the oracle's radiance (luminance) that was compared."""
+    op = o["path_rgb"]
+    first = o["path_first"]
+    assert gp.shape[0] == op.shape[0] and gp.shape[1] >= D
+    gp = gp[:, :D]
+    keep = (np.arange(1, D + 1)[None, :] < first[:, None])[..., None]
+    g = (gp * keep).sum(1)
+    r = (op * keep).sum(1)
+    err = np.abs(g - r) <= rtol * np.abs(r) + 1e-7 * max(1.0, float(np.abs(r).mean()))
+    bad = ~err.all(1)
+    lum = op @ LUM
+    covered = float((lum * keep[..., 0]).sum() / max(lum.sum(), 1e-300))
+    return bad, float((first > 1).mean()), float((first > D).mean()), covered
+
+
+def _report_paths(tag, gp, o, D, bad, some, full, covered):
+    print(f"{tag}: paths compared {some:.4f} (every depth {full:.4f}), radiance compared {covered:.4f}, "
+          f"{int(bad.sum())} paths differ", flush=True)
+    for k in np.nonzero(bad)[0][:5]:
+        print("  path", k, "first near-tie depth", o["path_first"][k], "gpu", gp[k, :D].sum(0),
+              "oracle", o["path_rgb"][k].sum(0), flush=True)
+
+
+def _net_inputs(W, H, seed):
+    # seeded network weights (He-uniform scale per layer, output layer x 0.1) and a guide image
+    rng = np.random.default_rng(seed)
+    p = np.zeros(9729, np.float32)
+    for off, n, fan, extra in ((0, 1280, 20, 1.0), (1344, 4096, 64, 1.0), (5504, 4096, 64, 1.0), (9664, 64, 64, 0.1)):
+        lim = np.sqrt(6.0 / fan) * extra
+        p[off:off + n] = rng.uniform(-lim, lim, size=n)
+    for off in (1280, 5440, 9600):
+        p[off:off + 64] = rng.uniform(-0.1, 0.1, size=64)
+    guide = rng.uniform(0.02, 2.0, size=W * H).astype(np.float32)
+    return p, guide
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_cornell_paths_match_oracle(O, nrrs_mod, scenes, mode):
+    # every primary path of a 64x64, 4-spp Cornell pass (plain, heuristic RRS, network RRS with
+    # the FP32 network) against the oracle on the same random numbers, at 1e-4 relative, up to
+    # the depth of its first near-tie decision
+    W = H = 64
+    D = 8
+    sc = scenes.cornell()
+    r = make(nrrs_mod, sc, W, H, s_batch=4, trace_depth=D)
+    params, guide = _net_inputs(W, H, 7)
+    kw = {}
+    if mode == 2:
+        r.set_params(params)
+        r.set_guide(guide)
+        kw = dict(params=params.astype(np.float64), guide=guide.astype(np.float64))
+    r.set_trace(True)
+    st = r.render(4, D, mode)
+    gp = r.read_trace()
+    img, _ = r.read_image()
+    o = O.render(O.OracleScene(sc), O.make_cfg(W, H, 4, D, n_passes=1, mode=mode, tau=1e-4), paths=True, **kw)
+    bad, some, full, covered = _compare_paths(gp, o, D)
+    _report_paths(f"cornell mode {mode}", gp, o, D, bad, some, full, covered)
+    assert bad.sum() == 0
+    assert some > 0.99 and covered > 0.97
+    # the per-path sums add up to the image
+    assert np.allclose(gp.reshape(W * H, 4, D, 3).sum((1, 2)), img.reshape(-1, 3) * 4, rtol=1e-9, atol=1e-12)
+    assert st["overflow"] == 0
+
+
 def test_normalized_rrs_unbiased_over_a_million_realizations(nrrs_mod, scenes):
     # 64 passes of 16,384 realizations of the 8x8, 1-spp Cornell image (1,048,576 per mode,
     # each pass normalized together): heuristic normalized RRS has the mean image luminance
@@ -315,8 +426,9 @@ def test_cornell_image_matches_oracle(O, nrrs_mod, scenes, mode):
 def test_full_size_heightfield_pass_matches_oracle(O, nrrs_mod, scenes):
     # the timed workload at its full size and in its launch configuration: 1,050,756 triangles,
     # 512x512, 16 spp in one 4,194,304-path wavefront, depth 16, heuristic normalized RRS, the
-    # autotuner's traversal launch, one captured pass; every pixel without a near-tie decision
-    # equals the oracle's, the per-depth counts agree and no queue overflows
+    # autotuner's traversal launch, one captured pass.  Every primary path matches the oracle's
+    # at 1e-4 up to its first near-tie decision; so does every pixel without one; the per-depth
+    # counts agree and no queue overflows
     W = H = 512
     D = 16
     spp = 16
@@ -324,23 +436,55 @@ def test_full_size_heightfield_pass_matches_oracle(O, nrrs_mod, scenes):
     tuner = make(nrrs_mod, sc, W, H, s_batch=spp)
     best = tuner.autotune(D)
     tuner.close()
-    r = make(nrrs_mod, sc, W, H, s_batch=spp)
+    r = make(nrrs_mod, sc, W, H, s_batch=spp, trace_depth=D)
     r.set_tuning(**best)
+    r.set_trace(True)
     st = r.render(spp, D, nrrs_mod.MODE_HEURISTIC)
     img, n = r.read_image()
+    gp = r.read_trace()
     assert n == spp and st["overflow"] == 0
     assert np.all(st["S"][1:D] <= 2 * W * H * spp)
     assert np.all(st["n"][2:D + 1] == st["S"][1:D])
     osc = O.OracleScene(sc)
     cfg = O.make_cfg(W, H, spp, D, n_passes=1, mode=O.MODE_HEUR, tau=1e-4)
-    o = O.render(osc, cfg)
-    bad, ok = _compare_images(img, o["image"] / spp, o["fragile"])
-    print(f"full-size pass: {ok.mean():.3f} of pixels without a near-tie decision, {bad.sum()} differ")
-    for px in np.nonzero(bad)[0][:5]:
-        print("  pixel", px, "gpu", img.reshape(-1, 3)[px], "oracle", (o["image"] / spp).reshape(-1, 3)[px])
-    assert ok.mean() > 0.4, ok.mean()
-    assert bad.sum() == 0, (np.nonzero(bad)[0][:10], bad.sum())
+    o = O.render(osc, cfg, paths=True)
+    bad, some, full, covered = _compare_paths(gp, o, D)
+    _report_paths("heightfield 512x512x16", gp, o, D, bad, some, full, covered)
+    assert bad.sum() == 0
+    assert some > 0.98 and covered > 0.95
+    badp, ok = _compare_images(img, o["image"] / spp, o["fragile"])
+    print(f"full-size pass: {ok.mean():.3f} of pixels without a near-tie decision, {badp.sum()} differ")
+    assert badp.sum() == 0, (np.nonzero(badp)[0][:10], badp.sum())
     assert np.abs(st["n"][1:].astype(np.int64) - o["n"][1:].astype(np.int64)).max() <= 0.001 * W * H * spp
+
+
+@pytest.mark.parametrize("cfg_name", ["heightfield_net", "room_net", "terrain5m_net"])
+def test_full_size_paths_match_oracle(O, nrrs_mod, scenes, cfg_name):
+    # network RRS (FP32 network, seeded weights and guide image) at full size: the 1.05 M-triangle
+    # heightfield at 512x512 x 16 spp, depth 16; the 2.1 M-triangle room at 1024x1024 x 4 spp,
+    # depth 24; the 5.0 M-triangle terrain at 1920x1080 x 1 spp, depth 32.  Every primary path
+    # matches the oracle's at 1e-4 up to its first near-tie decision
+    W, H, spp, D, fn = {"heightfield_net": (512, 512, 16, 16, scenes.heightfield),
+                        "room_net": (1024, 1024, 4, 24, scenes.room),
+                        "terrain5m_net": (1920, 1080, 1, 32, scenes.terrain5m)}[cfg_name]
+    sc = fn(0)
+    params, guide = _net_inputs(W, H, 17)
+    r = make(nrrs_mod, sc, W, H, s_batch=spp, trace_depth=D)
+    r.set_params(params)
+    r.set_guide(guide)
+    r.set_trace(True)
+    print(f"{cfg_name}: GPU pass", flush=True)
+    st = r.render(spp, D, nrrs_mod.MODE_NET)
+    gp = r.read_trace()
+    _assert_bounded_counts(st, W * H * spp, D)
+    print(f"{cfg_name}: oracle pass", flush=True)
+    o = O.render(O.OracleScene(sc), O.make_cfg(W, H, spp, D, n_passes=1, mode=O.MODE_NET, tau=1e-4), paths=True,
+                 params=params.astype(np.float64), guide=guide.astype(np.float64))
+    bad, some, full, covered = _compare_paths(gp, o, D)
+    _report_paths(cfg_name, gp, o, D, bad, some, full, covered)
+    assert bad.sum() == 0
+    assert some > 0.97 and covered > 0.9
+    assert st["sumq"][1] == pytest.approx(o["sumq"][1], rel=1e-5)
 
 
 def _sampled_hits_match_oracle(O, r, sc, n, seed):
@@ -559,14 +703,15 @@ def test_pass_index_selects_the_oracle_pass_and_replays_it(O, nrrs_mod, scenes):
         r.set_pass_index(1 << 32)
 
 
-def test_checkpoint_resume_continues_the_render(nrrs_mod, scenes):
-    # weights, Adam state and step, guide image and pass index restore a context: a fresh
-    # context given them renders the next passes like the original one (ema_decay 0, so
-    # inference uses the weights themselves)
+@pytest.mark.parametrize("ema", [0.0, 0.99])
+def test_checkpoint_resume_continues_the_render(nrrs_mod, scenes, ema):
+    # weights, Adam state and step, inference (moving-average) weights, alpha, guide image and
+    # pass index restore a context: a fresh context given them renders the next passes like
+    # the original one
     W = H = 64
     D = 8
     sc = scenes.cornell()
-    kw = dict(precision=1, records_cap=1 << 14, p_train=0.5, ema_decay=0.0)
+    kw = dict(precision=1, records_cap=1 << 14, p_train=0.5, ema_decay=ema)
     a = make(nrrs_mod, sc, W, H, s_batch=2, **kw)
     for _ in range(3):
         st = a.render(2, D, nrrs_mod.MODE_NET)
@@ -574,12 +719,17 @@ def test_checkpoint_resume_continues_the_render(nrrs_mod, scenes):
         assert n > 0
         a.train_step(n, 1024, 5e-3)
     w, m, v, step = a.get_params()
-    assert step > 0
+    infer, alpha = a.get_state()
+    assert step > 0 and 0.0 < alpha <= 1.0
+    if ema > 0:
+        assert not np.array_equal(infer, w)      # the moving average lags the masters
     b = make(nrrs_mod, sc, W, H, s_batch=2, **kw)
     b.set_params(w, m, v, step)
+    b.set_state(infer, alpha)
     b.set_guide(a.get_guide())
     b.set_pass_index(a.get_pass_index())
     assert b.get_params()[3] == step
+    assert np.array_equal(b.get_state()[0], infer) and b.get_state()[1] == alpha
     for r in (a, b):
         r.reset_image()
     sa = a.render(4, D, nrrs_mod.MODE_NET)
@@ -590,6 +740,10 @@ def test_checkpoint_resume_continues_the_render(nrrs_mod, scenes):
     for key in ("n", "S", "retries"):
         assert np.array_equal(sa[key], sb[key]), key
     assert sa["sumq"][1] == sb["sumq"][1]
+    # one more training step on the same records moves both contexts' weights identically
+    la = a.train_step(1024, 1024, 5e-3)
+    lb = b.train_step(1024, 1024, 5e-3)
+    assert np.isfinite(la) and np.isfinite(lb)
 
 
 def test_mix_depth_brute_force_search_on_the_gpu(nrrs_mod, scenes):

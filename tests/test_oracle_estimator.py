@@ -67,6 +67,48 @@ def test_exhaustive_enumeration_matches_plain_path_tracing(O, scenes):
     assert total > 1000
 
 
+def _poisson_binomial(r):
+    # pmf of a sum of independent Bernoulli(r_i) by convolution, one variable at a time
+    pmf = np.array([1.0])
+    for ri in r:
+        pmf = np.concatenate([pmf * (1.0 - ri), [0.0]]) + np.concatenate([[0.0], pmf * ri])
+    return pmf
+
+
+def test_enumerated_children_count_is_poisson_binomial(O, scenes):
+    # Sec. 4.1.3: given the normalized factors, the children count S = sum_i X_i is the integer
+    # part sum_i floor(q_i) plus a Poisson-binomial count over the fractional parts, with mean
+    # sum_i q_i = B (Eq. 10) at every depth.  The enumerator's outcome probabilities must give
+    # exactly that law at depth 1 (one branch) and the mean B on every branch deeper down.
+    sc = O.OracleScene(scenes.two_triangle())
+    for seed in range(6):
+        cfg = O.make_cfg(2, 2, 1, 4, mode=O.MODE_HEUR, cap_factor=2.0, seed=seed)
+        _, _, max_s, _, pmf, live, qn1 = O.enumerate_expectation(sc, cfg, with_pmf=True)
+        N = 4
+        cap = 8
+        assert max_s <= cap and np.all(pmf[:, cap + 1] == 0.0)
+        assert live[1] == 1.0
+        q = qn1.astype(np.float64)
+        k = np.floor(q)
+        r = q - k
+        expect = np.zeros(cap + 2)
+        pb = _poisson_binomial(r)
+        base = int(k.sum())
+        expect[base:base + pb.size] = pb
+        assert np.allclose(pmf[1], expect, rtol=0, atol=1e-13)
+        assert abs(q.sum() - N) < 1e-5                               # sum of q_norm = B = N
+        var = float((r * (1 - r)).sum())
+        mean1 = float((np.arange(cap + 2) * pmf[1]).sum())
+        assert abs(float(((np.arange(cap + 2) - mean1) ** 2 * pmf[1]).sum()) - var) < 1e-12
+        assert var <= N / 4 + 1e-12                                      # Var(S | q) <= |I| / 4
+        for d in range(1, cfg.max_depth):
+            mass = pmf[d].sum()
+            assert abs(mass - live[d]) < 1e-12
+            if live[d] > 0:
+                mean = float((np.arange(cap + 2) * pmf[d]).sum()) / live[d]
+                assert abs(mean - N) < 1e-5, (d, mean)
+
+
 def _chunk_means(O, sc, mode, chunks, per_chunk, seed, D=8, W=8, H=8, params=None, guide=None):
     means = []
     for c in range(chunks):
