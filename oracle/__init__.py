@@ -82,6 +82,8 @@ def lib():
         L.or_round_bf16.argtypes = [C.c_double]
         L.or_round_e4m3.restype = C.c_double
         L.or_round_e4m3.argtypes = [C.c_double]
+        L.or_fp8_dot_error_bound.restype = C.c_double
+        L.or_fp8_dot_error_bound.argtypes = [P, P, C.c_int32]
         L.or_mlp_loss_grad.restype = C.c_double
         L.or_mlp_loss_grad.argtypes = [P, P, P, C.c_uint64, C.c_double, C.c_int32, P]
         L.or_adam.argtypes = [P, P, P, P, C.c_uint64, C.c_uint64, C.c_double, C.c_double, C.c_double,
@@ -278,6 +280,13 @@ def round_bf16(x):
 
 def round_e4m3(x):
     return float(lib().or_round_e4m3(float(x)))
+
+
+def fp8_dot_error_bound(w, x):
+    w = _c(w, np.float64)
+    x = _c(x, np.float64)
+    assert w.size == x.size
+    return float(lib().or_fp8_dot_error_bound(_p(w), _p(x), int(w.size)))
 
 
 def mlp_forward_quant(params, x, prec, with_fragile=False):

@@ -108,6 +108,7 @@ struct or_scene {
   double cam[10];
   double env[3];
   double amin[3], amax[3], extent, diag, tmin, offset;
+  double perr_max;  /* float32 position error up to which paths are compared (near-tie flags only) */
   bnode* nodes;
   uint64_t nnodes;
   uint32_t* order;
@@ -180,6 +181,12 @@ static uint32_t bvh_build(or_scene* s, uint64_t a, uint64_t b) {
   return id;
 }
 
+static double tri_altitude(const or_scene* s, uint32_t p);
+static int cmp_double(const void* a, const void* b) {
+  const double x = *(const double*)a, y = *(const double*)b;
+  return (x > y) - (x < y);
+}
+
 or_scene* or_scene_create(const float* verts, uint64_t nv, const uint32_t* tris, uint64_t nt,
                           const uint32_t* tri_mat, const uint32_t* mat_type, const float* mat_params,
                           uint32_t nm, const float* camera, const float* env, int32_t build_bvh) {
@@ -218,6 +225,17 @@ or_scene* or_scene_create(const float* verts, uint64_t nv, const uint32_t* tris,
   s->diag = sqrt(dot3(e, e));
   s->tmin = 0.0;                   /* hits count for t > 0; child origins are offset instead */
   s->offset = 1e-5 * s->extent;     /* origin offset along the face-forwarded normal */
+  /* A quarter of the median triangle altitude: a float32 ray whose position error stays below
+   * it is traced with box paddings of at most that much; beyond it the near-tie flags stop
+   * comparing the path (median over at most 4096 evenly spaced triangles). */
+  {
+    const uint64_t ns = nt < 4096 ? nt : 4096;
+    double* h = (double*)malloc(sizeof(double) * (ns ? ns : 1));
+    for (uint64_t k = 0; k < ns; ++k) h[k] = tri_altitude(s, (uint32_t)(k * (nt / ns)));
+    qsort(h, ns, sizeof(double), cmp_double);
+    s->perr_max = ns ? 0.25 * h[ns / 2] : 0.0;
+    free(h);
+  }
   if (build_bvh) {
     s->order = (uint32_t*)malloc(sizeof(uint32_t) * nt);
     for (uint64_t i = 0; i < nt; ++i) s->order[i] = (uint32_t)i;
@@ -264,26 +282,47 @@ static int tri_test(const or_scene* s, uint32_t p, const double o[3], const doub
 typedef struct {
   uint32_t prim;
   double t, b1, b2, margin, cosn;  /* margin of the winner, scaled by its |cos| */
+  double gm;                       /* the winner's margin equivalent of the ray's position error */
   int ncand;
-  double cand_t[16], cand_c[16];
+  double cand_t[16], cand_c[16], cand_e[16];
   uint32_t cand_p[16];
+  double perr, derr;               /* float32 error bounds of the ray: origin (m), direction (rad) */
 } trace_state;
+
+/* Smallest altitude of triangle p: a position error e along its plane moves the barycentric
+ * coordinates by at most e / h. */
+static double tri_altitude(const or_scene* s, uint32_t p) {
+  const double* v = s->tri + 9 * (uint64_t)p;
+  double e1[3], e2[3], e3[3], nv[3];
+  sub3(v + 3, v, e1);
+  sub3(v + 6, v, e2);
+  sub3(v + 6, v + 3, e3);
+  cross3(e1, e2, nv);
+  double L = fmax(sqrt(dot3(e1, e1)), fmax(sqrt(dot3(e2, e2)), sqrt(dot3(e3, e3))));
+  return L > 0.0 ? sqrt(dot3(nv, nv)) / L : 0.0;
+}
 
 static void consider(const or_scene* s, uint32_t p, const double o[3], const double d[3], uint32_t excl,
                      double tau, trace_state* st) {
   if (p == excl) return;
   double t, b1, b2, m, cn;
   if (!tri_test(s, p, o, d, &t, &b1, &b2, &m, &cn)) return;
+  /* position error of the float32 ray where it meets this triangle's plane (perpendicular to the
+   * ray; in the m * cos units of the margins: e / altitude) */
+  const double err = tau > 0.0 ? st->perr + fabs(t) * st->derr : 0.0;
+  const double h = tau > 0.0 ? tri_altitude(s, p) : 0.0;
+  const double g = err > 0.0 ? (h > 0.0 ? err / h : INFINITY) : 0.0;
   if (m >= 0.0 && t > s->tmin) {
     if (t < st->t || (t == st->t && p < st->prim)) {
-      st->prim = p; st->t = t; st->b1 = b1; st->b2 = b2; st->margin = m * cn; st->cosn = cn;
+      st->prim = p; st->t = t; st->b1 = b1; st->b2 = b2; st->margin = m * cn; st->cosn = cn; st->gm = g;
     }
   }
-  if (tau > 0.0 && m * cn > -tau && t > s->tmin - tau * s->diag / fmax(cn, 1e-300)) {
+  if (tau > 0.0 && m * cn > -(tau + g) && t > s->tmin - (tau * s->diag + err) / fmax(cn, 1e-300)) {
     /* keep the 16 nearest candidates; a farther one cannot decide a near-tie that these miss */
     if (st->ncand < 16) {
       st->cand_t[st->ncand] = t;
       st->cand_c[st->ncand] = cn;
+      st->cand_e[st->ncand] = err;
       st->cand_p[st->ncand] = p;
       st->ncand++;
     } else {
@@ -293,17 +332,19 @@ static void consider(const or_scene* s, uint32_t p, const double o[3], const dou
       if (t < st->cand_t[far]) {
         st->cand_t[far] = t;
         st->cand_c[far] = cn;
+        st->cand_e[far] = err;
         st->cand_p[far] = p;
       }
     }
   }
 }
 
-static int box_hit(const bnode* nd, const double o[3], const double d[3], double tlim, double pad_rel) {
+static int box_hit(const bnode* nd, const double o[3], const double d[3], double tlim, double pad_rel,
+                   double pad_abs) {
   double tn = 0.0, tf = tlim;
   for (int a = 0; a < 3; ++a) {
     double ext = nd->hi[a] - nd->lo[a];
-    double pad = 1e-7 * (fabs(nd->lo[a]) + fabs(nd->hi[a]) + ext) + pad_rel * ext;
+    double pad = 1e-7 * (fabs(nd->lo[a]) + fabs(nd->hi[a]) + ext) + pad_rel * ext + pad_abs;
     double lo = nd->lo[a] - pad, hi = nd->hi[a] + pad;
     if (d[a] == 0.0) {
       if (o[a] < lo || o[a] > hi) return 0;
@@ -319,11 +360,15 @@ static int box_hit(const bnode* nd, const double o[3], const double d[3], double
 }
 
 /* Closest hit with t > tmin, excluding prim `excl`; ties go to the smaller prim id.
- * Returns 1 when the decision is within `tau` of changing (near-tie). */
+ * Returns 1 when the decision is within `tau` of changing (near-tie), widened by what the
+ * float32 ray's own error could move: its origin by up to perr (m) and its direction by up to
+ * derr (rad).  *gerr receives that position error at the hit, perpendicular to the ray. */
 static int trace_one(const or_scene* s, const double o[3], const double d[3], uint32_t excl, int use_bvh,
-                     double tau, uint32_t* prim, double* t, double* b1, double* b2) {
+                     double tau, double perr, double derr, uint32_t* prim, double* t, double* b1, double* b2,
+                     double* gerr) {
   trace_state st;
-  st.prim = MISS; st.t = INFINITY; st.b1 = st.b2 = 0.0; st.margin = 0.0; st.cosn = 1.0; st.ncand = 0;
+  st.prim = MISS; st.t = INFINITY; st.b1 = st.b2 = 0.0; st.margin = 0.0; st.cosn = 1.0; st.gm = 0.0; st.ncand = 0;
+  st.perr = perr; st.derr = derr;
   if (use_bvh && s->nodes) {
     uint32_t stack[128];
     int sp = 0;
@@ -331,7 +376,8 @@ static int trace_one(const or_scene* s, const double o[3], const double d[3], ui
     while (sp > 0) {
       const bnode* nd = &s->nodes[stack[--sp]];
       double lim = st.t + (tau > 0.0 ? tau * s->diag : 0.0);
-      if (!box_hit(nd, o, d, isinf(lim) ? INFINITY : lim * (1.0 + 1e-9) + 1e-12, tau)) continue;
+      double pad_abs = tau > 0.0 ? perr + (isinf(lim) ? s->diag : lim) * derr : 0.0;
+      if (!box_hit(nd, o, d, isinf(lim) ? INFINITY : lim * (1.0 + 1e-9) + 1e-12 + pad_abs, tau, pad_abs)) continue;
       if (nd->count > 0) {
         for (uint32_t i = 0; i < nd->count; ++i) consider(s, s->order[nd->first + i], o, d, excl, tau, &st);
       } else {
@@ -343,11 +389,16 @@ static int trace_one(const or_scene* s, const double o[3], const double d[3], ui
     for (uint64_t p = 0; p < s->nt; ++p) consider(s, (uint32_t)p, o, d, excl, tau, &st);
   }
   *prim = st.prim; *t = st.t; *b1 = st.b1; *b2 = st.b2;
+  if (gerr) *gerr = st.prim != MISS ? perr + st.t * derr : 0.0;
   if (tau <= 0.0) return 0;
-  if (st.prim != MISS && (st.margin < tau || st.t < s->tmin + tau * s->diag)) return 1;
+  const double werr = st.prim != MISS ? perr + st.t * derr : 0.0;
+  if (st.prim != MISS && (st.margin < tau + st.gm || st.t < s->tmin + tau * s->diag + werr / fmax(st.cosn, 1e-300)))
+    return 1;
   for (int i = 0; i < st.ncand; ++i) {
     if (st.cand_p[i] == st.prim) continue;
-    if (st.prim == MISS || (st.cand_t[i] - st.t) * fmin(st.cand_c[i], st.cosn) < tau * s->diag) return 1;
+    if (st.prim == MISS ||
+        (st.cand_t[i] - st.t) * fmin(st.cand_c[i], st.cosn) < tau * s->diag + st.cand_e[i] + werr)
+      return 1;
   }
   return 0;
 }
@@ -358,7 +409,8 @@ void or_trace(const or_scene* s, const double* rays, const uint32_t* exclude, ui
   for (int64_t i = 0; i < (int64_t)n; ++i) {
     double o[3] = {rays[6 * i], rays[6 * i + 1], rays[6 * i + 2]};
     double d[3] = {rays[6 * i + 3], rays[6 * i + 4], rays[6 * i + 5]};
-    int f = trace_one(s, o, d, exclude ? exclude[i] : MISS, use_bvh, tau, &prim[i], &t[i], &b1[i], &b2[i]);
+    int f = trace_one(s, o, d, exclude ? exclude[i] : MISS, use_bvh, tau, 0.0, 0.0, &prim[i], &t[i], &b1[i], &b2[i],
+                      NULL);
     if (fragile) fragile[i] = (uint8_t)f;
   }
 }
@@ -647,6 +699,10 @@ static double fp8_dot_error_bound(const double* w, const double* x, int n) {
   return b + 16.0 * ldexp(1.0, -24) * sabs;
 }
 
+double or_fp8_dot_error_bound(const double* w, const double* x, int32_t n) {
+  return fp8_dot_error_bound(w, x, n);
+}
+
 void or_mlp_forward_quant(const double* params, const double* x, uint64_t n, int32_t prec, double* y, double* z,
                           uint8_t* fragile) {
   /* BF16: rounding decisions this close to a midpoint (in grid steps) are near-ties, a few
@@ -801,8 +857,15 @@ int32_t or_rrs_expand(const double* q_orig, const double* u, uint64_t n, double 
 }
 
 /* ------------------------------------------------------------------ render */
+/* Unit roundoff of float32 and the bound on the throughput error up to which a path's radiance
+ * is compared at 1e-4 relative. */
+#define F32_UNIT (1.0 / 16777216.0)
+#define KERR_COMPARED 3e-5
 typedef struct {
   double o[3], d[3], t[3];
+  /* Forward error bounds of the float32 computation of the same entry (used only to flag
+   * near-ties): origin position (m), direction (rad), throughput (relative). */
+  double perr, derr, kerr;
   uint32_t pix, excl, id_lo, id_hi;
   uint32_t k0; /* primary path this entry descends from (index within its pass) */
   int32_t rec[MAXREC];
@@ -812,6 +875,8 @@ typedef struct {
 typedef struct {
   uint32_t prim;
   double thit, b1, b2;
+  double perr;  /* float32 error bound of the hit point along the surface (m) */
+  double kq;    /* relative float32 error bound of the raw factor q */
   int fragile;
   /* vertex data after shading */
   double p[3], n[3], wo[3];
@@ -906,9 +971,14 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
     v->fragile = 0;
     v->q = 0.0;
     v->q32 = 0.0f;
+    v->perr = 0.0;
+    v->kq = 0.0;
     if (Q[i].dead) { v->prim = MISS; continue; }
     rays++;
-    v->fragile = trace_one(s, Q[i].o, Q[i].d, Q[i].excl, s->nodes != NULL, tau, &v->prim, &v->thit, &v->b1, &v->b2);
+    double gerr = 0.0;
+    v->fragile = trace_one(s, Q[i].o, Q[i].d, Q[i].excl, s->nodes != NULL, tau, Q[i].perr, Q[i].derr, &v->prim,
+                           &v->thit, &v->b1, &v->b2, &gerr);
+    v->perr = gerr;
   }
   st->rays += rays;
   /* shading, in slot order (FP64 image sums in a fixed order) */
@@ -921,6 +991,9 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
     vstate* v = &V[i];
     if (e->dead) continue;
     if (v->fragile) mark_fragile(c, e, depth);
+    /* beyond KERR_COMPARED the throughput's float32 error bound is too large for the radiance
+     * from this depth on (misses included) to be compared */
+    if (tau > 0.0 && e->kerr > KERR_COMPARED) mark_fragile(c, e, depth);
     if (v->prim == MISS) {
       add_emission(c, e, s->env, depth);
       continue;
@@ -936,6 +1009,18 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
     for (int k = 0; k < 3; ++k) v->wo[k] = -e->d[k];
     double cos_o = dot3(ng, v->wo);
     if (tau > 0.0 && fabs(cos_o) < tau) mark_fragile(c, e, depth);
+    /* float32 error of the hit point: the ray's error spread along the surface, plus the
+     * rounding of its coordinates */
+    v->perr = v->perr / fmax(fabs(cos_o), 1e-12) +
+              8.0 * F32_UNIT * fmax(fabs(v->p[0]), fmax(fabs(v->p[1]), fabs(v->p[2])));
+    /* beyond a quarter of the typical triangle the traversal's flags would need wider box
+     * paddings than it gives: stop comparing the path from the children on (the bound is then
+     * held there) */
+    if (v->perr > s->perr_max) {
+      if (tau > 0.0) mark_fragile(c, e, depth + 1);
+      v->perr = s->perr_max;
+    }
+    v->kq = e->kerr + 8.0 * F32_UNIT;
     int front = cos_o > 0.0;
     for (int k = 0; k < 3; ++k) v->n[k] = front ? ng[k] : -ng[k];
     v->mat = s->tmat[v->prim];
@@ -978,6 +1063,8 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
       or_mlp_forward(c->params, f, 1, &y, &z);
       if (!isfinite(y)) continue;
       v->q = lum3(e->t) * y / (g + 0.01);
+      /* the inputs carry the hit point's error (the sine encoding scales it by 16 pi / extent) */
+      v->kq += 64.0 * v->perr / s->extent;
     }
   }
   (void)pass;
@@ -1027,6 +1114,24 @@ static void expand_children(rctx* c, const entry* Q, const vstate* V, uint64_t n
         ch->d[k] = wi[k];
         ch->t[k] = alive ? e->t[k] * w[k] / (double)v->q32 : 0.0;
       }
+      /* float32 error bounds of the child: the hit point's (and the offset's rounding); a cosine
+       * sample takes a fresh direction in the triangle's frame, a GGX sample carries the incoming
+       * direction's error through the visible-normal map (stretched by up to 1 / alpha) and into
+       * the Smith terms (growing as 1 / |cos|) */
+      ch->perr = v->perr + 4.0 * F32_UNIT * fmax(fabs(v->p[0]), fmax(fabs(v->p[1]), fabs(v->p[2])));
+      if (s->mtype[v->mat] == 1) {
+        /* reflection keeps an angular error; the visible-normal sample moves with the incoming
+         * direction by at most about alpha times its change */
+        ch->derr = e->derr * (1.0 + 2.0 * mp[3]) + 16.0 * F32_UNIT;
+        ch->kerr = e->kerr + 8.0 * F32_UNIT + e->derr * (2.0 / fmax(fabs(wol[2]), 1e-12) + 2.0 / fmax(fabs(wil[2]), 1e-12));
+      } else {
+        ch->derr = 16.0 * F32_UNIT;
+        ch->kerr = e->kerr + 8.0 * F32_UNIT;
+      }
+      if (ch->derr * s->diag > s->perr_max) {
+        if (tau > 0.0) mark_fragile(c, e, depth + 1);
+        ch->derr = s->perr_max / s->diag;
+      }
       ch->pix = e->pix;
       ch->k0 = e->k0;
       ch->excl = v->prim;
@@ -1075,6 +1180,9 @@ int32_t or_render(const or_scene* s, or_cfg* cfg, const double* params, double* 
       rng_block(cfg->seed, (uint32_t)k, pass, PURPOSE_CAMERA, 0, 0, r);
       camera_ray(s, cfg->width, cfg->height, pix % cfg->width, pix / cfg->width, u01(r[0]), u01(r[1]), e->o, e->d);
       e->t[0] = e->t[1] = e->t[2] = 1.0;
+      e->perr = F32_UNIT * fmax(fabs(e->o[0]), fmax(fabs(e->o[1]), fabs(e->o[2])));
+      e->derr = 16.0 * F32_UNIT;
+      e->kerr = 0.0;
       e->pix = pix;
       e->k0 = (uint32_t)k;
       e->excl = MISS;
@@ -1115,7 +1223,8 @@ int32_t or_render(const or_scene* s, or_cfg* cfg, const double* params, double* 
         V[i].q32 = q32[i];
         if (V[i].q > 0.0 && cfg->tau > 0.0) {
           float r = q32[i] - floorf(q32[i]);
-          if (fabs(uv[i] - (double)r) < cfg->tau * (double)q32[i]) mark_fragile(&c, &Q[i], depth + 1);
+          /* within the decision margin, or within the float32 error bound of the factor */
+          if (fabs(uv[i] - (double)r) < (cfg->tau + V[i].kq) * (double)q32[i]) mark_fragile(&c, &Q[i], depth + 1);
         }
       }
       expand_children(&c, Q, V, n, X, off, Qn, depth);
@@ -1230,6 +1339,7 @@ int32_t or_enumerate(const or_scene* s, const or_cfg* cfg, double* image_expect,
     rng_block(cfg->seed, (uint32_t)k, pass, PURPOSE_CAMERA, 0, 0, r);
     camera_ray(s, cfg->width, cfg->height, pix % cfg->width, pix / cfg->width, u01(r[0]), u01(r[1]), e->o, e->d);
     e->t[0] = e->t[1] = e->t[2] = 1.0;
+    e->perr = e->derr = e->kerr = 0.0;
     e->pix = pix; e->k0 = (uint32_t)k; e->excl = MISS; e->id_lo = (uint32_t)k; e->id_hi = pass;
     for (int j = 0; j < MAXREC; ++j) e->rec[j] = -1;
     e->dead = 0; e->train = 0;

@@ -123,6 +123,9 @@ void or_mlp_forward(const double* params, const double* x, uint64_t n, double* y
  * round those the other way. */
 double or_round_bf16(double x);
 double or_round_e4m3(double x);
+/* Bound on the distance of an FP8 matrix-core dot product of E4M3 codes w[n], x[n] from its
+ * exact value (the near-tie margin of the FP8 quantized forward). */
+double or_fp8_dot_error_bound(const double* w, const double* x, int32_t n);
 void or_mlp_forward_quant(const double* params, const double* x, uint64_t n, int32_t prec, double* y, double* z,
                           uint8_t* fragile);
 

@@ -192,3 +192,76 @@ def test_quantized_forward_reduces_to_exact_for_representable_weights(O):
     y8g, _ = O.mlp_forward_quant(Pg, xg, 2)
     assert np.median(np.abs(ybg / yg - 1)) < 1e-2
     assert np.median(np.abs(y8g / yg - 1)) < 6e-2
+
+
+# ------------------------------------------------------------- near-tie flags of the quantized forward
+# A row is flagged when one of its rounding decisions (an activation's BF16 / E4M3 rounding, or
+# the power-of-two scale of a vertex's FP8 activations) lies within the accumulation error of
+# the matrix core from changing.  These rows are built so that one layer-1 (or layer-2)
+# activation sits exactly on, just off, or far from such a decision; every other activation is 0.
+def _one_unit_net(w1=0.0, b1=0.0, w2=0.0, b2=0.0):
+    P = np.zeros(9729)
+    P[0] = w1           # W1[0][0]
+    P[1280] = b1        # b1[0]
+    P[1344] = w2        # W2[0][0]
+    P[5440] = b2        # b2[0]
+    P[9664] = 1.0       # W4[0]: y depends on unit 0 of layer 3
+    P[5504] = 1.0       # W3[0][0]
+    return P
+
+
+def _flag(O, P, x0, prec):
+    x = np.zeros((1, 20))
+    x[0, 0] = x0
+    _, _, near = O.mlp_forward_quant(P, x, prec, with_fragile=True)
+    return bool(near[0])
+
+
+def test_bf16_flag_on_off_and_far_from_a_midpoint(O):
+    # layer 1: out = 1 * 1 + b; BF16 spacing in [1, 2) is 2^-7, so 1 + 2^-8 is a midpoint
+    ulp = 2.0 ** -7
+    assert _flag(O, _one_unit_net(w1=1.0, b1=0.5 * ulp), 1.0, 1)                 # on the midpoint
+    assert _flag(O, _one_unit_net(w1=1.0, b1=0.5 * ulp + 1e-4 * ulp), 1.0, 1)    # 1e-4 grid steps off
+    assert not _flag(O, _one_unit_net(w1=1.0, b1=0.5 * ulp + 1e-3 * ulp), 1.0, 1)  # 1e-3 steps off
+    assert not _flag(O, _one_unit_net(w1=1.0, b1=0.25 * ulp), 1.0, 1)           # far
+    assert not _flag(O, _one_unit_net(w1=1.0, b1=0.0), 1.0, 1)                  # on the grid
+    # layer 2: layer 1 gives exactly 1, layer 2 out = 1 + b2 with the same construction
+    assert _flag(O, _one_unit_net(w1=1.0, w2=1.0, b2=0.5 * ulp), 1.0, 1)
+    assert not _flag(O, _one_unit_net(w1=1.0, w2=1.0, b2=0.3 * ulp), 1.0, 1)
+    # a negative pre-activation is clamped by ReLU to 0: nothing to round
+    assert not _flag(O, _one_unit_net(w1=-1.0, b1=0.5 * ulp - 2.0), 1.0, 1)
+
+
+def test_fp8_flag_on_off_and_far_from_a_midpoint(O):
+    # W1[0][0] = 448 * 2^-9 gives the layer scale 2^-9 exactly (code 448); x0 = 1 is code 256 at
+    # block scale 2^-8, so layer-1 out = 0.875 + b exactly.  out = 272 * 2^-9 lies in [256, 448]
+    # of its block scale 2^-9, on the midpoint of 256 and 288
+    w1 = 448.0 * 2.0 ** -9
+    unit = 2.0 ** -9
+    assert _flag(O, _one_unit_net(w1=w1, b1=272 * unit - w1), 1.0, 2)            # on the midpoint
+    assert not _flag(O, _one_unit_net(w1=w1, b1=273 * unit - w1), 1.0, 2)        # 1/32 of a step off
+    assert not _flag(O, _one_unit_net(w1=w1, b1=264 * unit - w1), 1.0, 2)        # a quarter step off
+    # the scale boundary: out = 448 * 2^-9 makes amax / 448 exactly 2^-9, where the vertex's
+    # power-of-two scale switches
+    assert _flag(O, _one_unit_net(w1=w1, b1=0.0), 1.0, 2)
+    assert not _flag(O, _one_unit_net(w1=w1, b1=3 * unit), 1.0, 2)              # 0.7 % above it
+    assert not _flag(O, _one_unit_net(w1=w1, b1=-40 * unit), 1.0, 2)            # 9 % below it
+
+
+def test_fp8_dot_error_bound_closed_forms(O):
+    # products that are multiples of 2^(floor(log2 max|p|) - 13) cost only the FP32 group-sum term
+    e32 = 2.0 ** -24
+    w = np.array([1.0, 1.0, 2.0])
+    x = np.array([256.0, 8.0, 0.5])             # products 256, 8, 1; unit 2^-5
+    assert O.fp8_dot_error_bound(w, x) == pytest.approx(16 * e32 * 265.0, rel=1e-15)
+    # a product below the unit may vanish whole
+    x2 = np.array([256.0, 2.0 ** -6, 0.0])
+    assert O.fp8_dot_error_bound(w, x2) == pytest.approx(2.0 ** -6 + 16 * e32 * (256 + 2.0 ** -6), rel=1e-15)
+    # a product above the unit that is not a multiple of it loses at most one unit
+    x3 = np.array([256.0, 1.0 + 2.0 ** -6, 0.0])
+    assert O.fp8_dot_error_bound(w, x3) == pytest.approx(2.0 ** -5 + 16 * e32 * (257 + 2.0 ** -6), rel=1e-15)
+    # scale invariance (powers of two) and the empty / all-zero dot product
+    assert O.fp8_dot_error_bound(w, 4 * x3) == pytest.approx(4 * O.fp8_dot_error_bound(w, x3), rel=1e-15)
+    assert O.fp8_dot_error_bound(w, np.zeros(3)) == 0.0
+    # signs do not matter
+    assert O.fp8_dot_error_bound(-w, x3) == O.fp8_dot_error_bound(w, x3)
