@@ -6,10 +6,16 @@ A step is one NRRS frame over the 512x512 heightfield workload (about 1.05 M tri
 expansion, FP64 pixel accumulation, training-record capture) followed by one train_step
 on 2^18 records.  `value` is rays extended per second (Mpaths/s) over the timed steps.
 
-Also reported, outside the timed region: the render efficiency 1/(relMSE * t) of the
-trained network (NRRS) and of plain heuristic normalized RRS at equal spp against a
-high-spp reference, the roofline of the dominant kernel from HIP events recorded on the
-render stream, and the CPU oracle timed on a bounded sample of the same workload.
+The network is first trained online for --train-frames frames (120 by default, whatever
+--warmup is); the timed steps replay one captured hipGraph per pass (the library's default
+launch path).  Also reported, outside the timed region: a per-stage breakdown from steps
+with HIP events recorded on the render stream after every stage (direct launches), the
+roofline of the dominant kernel from those events, the render efficiency 1/(relMSE * t) of
+the trained network (NRRS), of NRRS with a searched Mix-Depth table (NRRS+) and of plain
+heuristic normalized RRS at equal spp against a high-spp reference, the online-training
+configuration (1024^2 room, 32 frames of 4 spp: trained vs untrained network vs heuristic),
+the batched 1920x1080 configuration (5 M triangles, FP8 / BF16 / FP32 network), and the CPU
+oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -26,7 +32,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "render efficiency 1/(relMSE·s) + Mpaths/s, NRRS vs plain norm. RRS, 1 GPU"
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X published FP32 vector peak
+FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X published FP32 vector peak (packed FP32)
+FP32_UNPACKED_PEAK = 78.6  # TFLOP/s without packed FP32 (256 CUs x 128 FLOP/clk x 2.4 GHz)
 OPS_PER_NODE = 52          # two slab tests: 12 FMA (24 FLOP) + 28 min/max/compare/scale
 OPS_PER_TRI = 56           # division-free Moller-Trumbore pre-test
 LUM = np.array([0.2126, 0.7152, 0.0722])
@@ -84,7 +91,11 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=120)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--train-frames", type=int, default=120,
+                    help="online-training frames (render + train_step) run before warmup, whatever --warmup is")
+    ap.add_argument("--stage-steps", type=int, default=4,
+                    help="extra steps with per-stage HIP events (direct launches) for the stage breakdown")
     ap.add_argument("--width", type=int, default=512)
     ap.add_argument("--spp", type=int, default=16)
     ap.add_argument("--depth", type=int, default=16)
@@ -93,6 +104,8 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-eff", action="store_true")
+    ap.add_argument("--no-room", action="store_true", help="skip the 1024^2 room online-training study")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 1920x1080 5 M-triangle batched render")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default=None,
                     help="traversal launch 'variant,blocks_per_cu,refill,leaf_batch,chunk' instead of autotuning")
@@ -139,7 +152,6 @@ def main():
     for t in table:
         print(f"#   candidate {t}", flush=True)
     print(f"# traversal launch {tuning} ({time.time() - t_tune:.1f}s)", flush=True)
-    r.set_timing(True)
     print(f"# scene {sc.n_tris} tris, setup+BVH {t_upload:.1f}s, workspace {r.workspace_bytes / 2**30:.2f} GiB",
           flush=True)
 
@@ -149,55 +161,77 @@ def main():
         loss = r.train_step(n, minibatch, 5e-3) if n > 0 else float("nan")
         return st, loss, n
 
+    # online training of the network (one NET frame + one train_step per frame), then warmup
+    t_train = time.perf_counter()
+    for f in range(args.train_frames):
+        st, loss, n = step()
+        if f % 20 == 0 or f == args.train_frames - 1:
+            print(f"# training frame {f}: rays {st['rays']}, records {st['records']}, loss {loss:.4f}", flush=True)
+    t_train = time.perf_counter() - t_train
     for w in range(args.warmup):
         st, loss, n = step()
-        if w % 4 == 0 or w == args.warmup - 1:
-            print(f"# warmup {w}: rays {st['rays']}, records {st['records']}, loss {loss:.4f}", flush=True)
+        print(f"# warmup {w}: rays {st['rays']}, records {st['records']}, loss {loss:.4f}", flush=True)
+
+    # timed region: the product's default launch path (one captured hipGraph replayed per pass)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rays = 0
-    stage_ms = {k: 0.0 for k in nrrs.STAGES}
-    stage_n = {k: 0 for k in nrrs.STAGES}
-    nodes = tris = 0
-    net_rows = 0
     for k in range(args.steps):
         st, loss, n = step()
-        net_rows += int(sum(st["n"][1:5]))
         rays += st["rays"]
-        nodes += st["nodes_visited"]
-        tris += st["tris_tested"]
-        for s in nrrs.STAGES:
-            stage_ms[s] += st["stage_ms"][s]
-            stage_n[s] += st["stage_launches"][s]
         print(f"# step {k}: rays {st['rays']}, loss {loss:.4f}, trained on {n}", flush=True)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    secs = t1 - t0
+    secs = time.perf_counter() - t0
     mpaths = rays / secs / 1e6
+
+    # stage breakdown: the same steps with HIP events recorded on the render stream after every
+    # stage (direct launches, since event-separated stages are not captured)
+    r.set_timing(True)
+    stage_ms = {k: 0.0 for k in nrrs.STAGES}
+    stage_n = {k: 0 for k in nrrs.STAGES}
+    nodes = tris = s_rays = 0
+    net_rows = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.stage_steps):
+        st, loss, n = step()
+        net_rows += int(sum(st["n"][1:5]))
+        s_rays += st["rays"]
+        nodes += st["nodes_visited"]
+        tris += st["tris_tested"]
+        for s_ in nrrs.STAGES:
+            stage_ms[s_] += st["stage_ms"][s_]
+            stage_n[s_] += st["stage_launches"][s_]
+    torch.cuda.synchronize()
+    direct_secs = time.perf_counter() - t0
+    r.set_timing(False)
+    n_stage = max(args.stage_steps, 1)
 
     # roofline of the dominant kernel (traversal).  It is bound by vector-ALU issue (its BVH and
     # triangles stay cache-resident: the counted HBM traffic is a small fraction of the bytes it
     # reads), so it is measured in useful FP32 operations (FMA = 2): 52 per BVH node visited
     # (two ray/box slab tests) and 56 per triangle tested (Moller-Trumbore division-free test).
-    dom = max(nrrs.STAGES, key=lambda s: stage_ms[s])
+    dom = max(nrrs.STAGES, key=lambda s_: stage_ms[s_])
     ext_launches = max(stage_n["extend"], 1)
     ext_ms = stage_ms["extend"] / ext_launches
     ext_ops = (OPS_PER_NODE * nodes + OPS_PER_TRI * tris) / ext_launches
-    ext_bytes = (64.0 * rays + 64.0 * nodes + 48.0 * tris) / ext_launches
+    ext_bytes = (64.0 * s_rays + 64.0 * nodes + 48.0 * tris) / ext_launches
     traffic = counted_traffic()
     v = tuning["extend_variant"]
-    ext_kernel = "k_extend_immediate" if v == 0 else f"k_extend<{v}>"
+    # the event-timed steps run the traversal variant that also counts nodes and triangles
+    ext_kernel = "k_extend_immediate<true>" if v == 0 else f"k_extend<{v},true>"
     tb = traffic.get(ext_kernel)
     achieved = ext_ops / (ext_ms * 1e-3) / 1e12
     roofline = {"kernel": ext_kernel, "bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK, 4), "traffic": tb,
                 "avg_launch_ms": round(ext_ms, 4), "algorithmic_ops_per_launch": int(ext_ops),
                 "ops_per_node": OPS_PER_NODE, "ops_per_triangle": OPS_PER_TRI,
-                "nodes_per_ray": round(nodes / max(rays, 1), 2), "tris_per_ray": round(tris / max(rays, 1), 2),
-                "grays_per_s": round(rays / (stage_ms["extend"] * 1e-3) / 1e9, 3),
+                "frac_of_unpacked_fp32_peak": round(achieved / FP32_UNPACKED_PEAK, 4),
+                "nodes_per_ray": round(nodes / max(s_rays, 1), 2), "tris_per_ray": round(tris / max(s_rays, 1), 2),
+                "grays_per_s": round(s_rays / (stage_ms["extend"] * 1e-3) / 1e9, 3),
                 "node_and_triangle_bytes_gbs": round(ext_bytes / (ext_ms * 1e-3) / 1e9, 1),
                 "hbm_gbs_counted": round(tb / (ext_ms * 1e-3) / 1e9, 1) if tb else None,
-                "dominant_stage": dom}
+                "dominant_stage": dom, "timed_on": f"{args.stage_steps} event-timed steps after the timed region"}
     # vector-ALU issue: wave64 FP32 instructions take 4 cycles on one of 1024 SIMDs (256 CUs x 4)
     # at 2.4 GHz; lane use = active lanes per executed vector instruction (SQ counters)
     sq = counted_sq().get(ext_kernel)
@@ -226,6 +260,15 @@ def main():
         queue[kern] = {"avg_launch_ms": round(ms, 4), "hbm_bytes_per_launch": b,
                        "hbm_gbs": round(b / (ms * 1e-3) / 1e9, 1) if b else None,
                        "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if b else None}
+    for stage, kerns in (("sum_q", ("k_sum_q_partial", "k_sum_q_final")),
+                         ("roulette_scan", ("k_roulette_count", "k_roulette_scan", "k_guard_count",
+                                            "k_guard_select", "k_offsets"))):
+        ms = stage_ms[stage] / max(stage_n[stage], 1)
+        b = [traffic.get(k) for k in kerns]
+        tot = sum(x for x in b if x) if any(b) else None
+        queue["+".join(kerns)] = {"avg_launch_ms": round(ms, 4), "hbm_bytes_per_launch": tot,
+                                  "hbm_gbs": round(tot / (ms * 1e-3) / 1e9, 1) if tot else None,
+                                  "frac": round(tot / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if tot else None}
 
     out = {
         "metric": METRIC, "value": round(mpaths, 2), "unit": "Mpaths/s", "n_gpus": 1, "steps": args.steps,
@@ -235,8 +278,13 @@ def main():
         "config": {"workload": f"heightfield {sc.n_tris} tris, {W}x{H}, {spp} spp in one {nprim}-path wavefront, "
                                f"max depth {D}, NRRS (network at depth<=4) + train_step(2^18 records)",
                    "width": W, "height": H, "spp": spp, "max_depth": D, "triangles": sc.n_tris,
-                   "queue_capacity": 2 * nprim, "parallelism": "single GPU"},
-        "stage_ms_per_step": {s: round(stage_ms[s] / args.steps, 3) for s in nrrs.STAGES},
+                   "queue_capacity": 2 * nprim, "parallelism": "single GPU",
+                   "launch": "one captured hipGraph per pass, replayed"},
+        "training": {"frames": args.train_frames, "seconds": round(t_train, 2), "p_train": p_train,
+                     "records_per_frame": rec_n, "minibatch": minibatch, "lr": 5e-3, "loss": "relative L2",
+                     "ema_decay": 0.99},
+        "direct_launch_ms_per_step": round(direct_secs / n_stage * 1e3, 3),
+        "stage_ms_per_step": {s_: round(stage_ms[s_] / n_stage, 3) for s_ in nrrs.STAGES},
         "roofline": roofline,
         "network": network,
         "queue_stages": queue,
@@ -253,6 +301,14 @@ def main():
             rr.close()
             return img
         out["efficiency"] = efficiency(r, nrrs, spp, D, args.ref_spp, args.eval_renders, make_reference)
+        out["efficiency"]["trained_frames"] = args.train_frames
+    r.close()
+    del r
+    torch.cuda.empty_cache()
+    if not args.no_room:
+        out["room_online_training"] = room_study(nrrs, scenes, torch)
+    if not args.no_batched:
+        out["batched_1080p"] = batched_study(nrrs, scenes, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc, W, H, D)
     print(json.dumps(out), flush=True)
@@ -313,6 +369,162 @@ def efficiency(r, nrrs, spp, D, ref_spp, renders, make_reference):
                         "tables": n_tables, "search_s": round(t_search, 2),
                         "network_depths": [d + 1 for d, m in enumerate(table) if m == mixdepth.NET],
                         "fixed_rate_depths": [d + 1 for d, m in enumerate(table) if m == mixdepth.FIXED]}
+    return out
+
+
+def _timed_render(r, torch, spp, D, mode, train=None):
+    """One frame: render (+ one train_step when `train` = (records cap, minibatch, lr)); wall
+    time with the stream drained on both sides."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = r.render(spp, D, mode)
+    if train is not None:
+        cap, mb, lr = train
+        n = min(st["records"], cap) // mb * mb
+        if n > 0:
+            r.train_step(n, mb, lr)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, st
+
+
+def _reference(nrrs, sc, W, H, s_batch, D, ref_spp, seed):
+    """Plain path tracing (no roulette) with an independent seed, as two halves: their mean is the
+    reference and their difference estimates the reference's own noise."""
+    halves = []
+    for k in range(2):
+        rr = nrrs.Renderer(W, H, s_batch=s_batch, cap_factor=2.0, seed=seed + k, max_tris=sc.n_tris,
+                           max_materials=len(sc.mat_type))
+        rr.upload_scene(sc)
+        rr.render(ref_spp // 2, D, nrrs.MODE_OFF, stats=False)
+        img, _ = rr.read_image()
+        rr.close()
+        halves.append(img)
+    return 0.5 * (halves[0] + halves[1]), 0.25 * (halves[0] - halves[1]) ** 2
+
+
+def _relmse_pair(img, ref, ref_var):
+    """relMSE against the reference, and the same with the reference's estimated variance taken out."""
+    den = ref ** 2 + 0.01
+    return float(np.mean((img - ref) ** 2 / den)), float(np.mean(((img - ref) ** 2 - ref_var) / den))
+
+
+def room_study(nrrs, scenes, torch, frames=32, trials=3, ref_spp=1024):
+    """The online-training configuration: 1024x1024 room (~2.1 M triangles) lit only through a
+    0.5 m^2 ceiling opening, depth 24, 32 frames of 4 spp.  NRRS ("trained"): every NET frame is
+    followed by one train_step on 2^18 records (minibatches of 2^13, BF16 inference, FP32
+    masters).  "untrained": the same NET frames with the initial weights and no training.
+    "heuristic": plain normalized RRS.  The image is the mean of the 32 frames (128 spp); time is
+    render + training; efficiency = 1 / (relMSE * time).  Each method runs `trials` times on
+    fresh random numbers, from the initial weights and no pixel estimate."""
+    W = H = 1024
+    spp, D = 4, 24
+    rec_n, mb, lr = 1 << 18, 1 << 13, 5e-3
+    t_setup = time.perf_counter()
+    sc = scenes.room(0)
+    r = nrrs.Renderer(W, H, s_batch=spp, cap_factor=2.0, seed=0, net_max_depth=4, precision=nrrs.PREC_BF16,
+                      records_cap=rec_n, p_train=0.05, max_tris=sc.n_tris, max_materials=len(sc.mat_type),
+                      loss=nrrs.LOSS_REL_L2, ema_decay=0.99)
+    r.upload_scene(sc)
+    tuning = r.autotune(D)
+    t_setup = time.perf_counter() - t_setup
+    w0, m0, v0, _ = r.get_params()
+    none = np.full(W * H, -1.0, np.float32)
+    res = {k: {"relmse": [], "relmse_ref_noise_removed": [], "seconds": [], "rays": []}
+           for k in ("trained", "untrained", "heuristic")}
+    imgs = {}
+    for trial in range(trials):
+        for name, mode, train in (("trained", nrrs.MODE_NET, (rec_n, mb, lr)), ("untrained", nrrs.MODE_NET, None),
+                                  ("heuristic", nrrs.MODE_HEURISTIC, None)):
+            r.set_params(w0, m0, v0, 0)
+            r.set_state(infer=w0, alpha=1.0)
+            r.set_guide(none)
+            r.reset_image()
+            secs = 0.0
+            rays = 0
+            for f in range(frames):
+                dt, st = _timed_render(r, torch, spp, D, mode, train)
+                secs += dt
+                rays += st["rays"]
+            img, n = r.read_image()
+            imgs.setdefault(name, []).append(img)
+            res[name]["seconds"].append(secs)
+            res[name]["rays"].append(rays)
+            print(f"# room trial {trial} {name}: {secs:.2f}s, {rays / secs / 1e6:.0f} Mpaths/s", flush=True)
+    r.close()
+    t_ref = time.perf_counter()
+    ref, ref_var = _reference(nrrs, sc, W, H, 16, D, ref_spp, 0x5EED0000)
+    t_ref = time.perf_counter() - t_ref
+    out = {"workload": f"room {sc.n_tris} tris, {W}x{H}, {frames} frames x {spp} spp, max depth {D}",
+           "reference": f"plain path tracing, {ref_spp} spp in two independent halves",
+           "reference_s": round(t_ref, 1), "setup_s": round(t_setup, 1), "trials": trials,
+           "traversal_launch": tuning}
+    for name, d in res.items():
+        for img in imgs[name]:
+            a, b = _relmse_pair(img, ref, ref_var)
+            d["relmse"].append(a)
+            d["relmse_ref_noise_removed"].append(b)
+        rm, rm_c, t = (float(np.mean(d[k])) for k in ("relmse", "relmse_ref_noise_removed", "seconds"))
+        out[name] = {"relmse": rm, "relmse_se": float(np.std(d["relmse"]) / np.sqrt(trials)),
+                     "relmse_ref_noise_removed": rm_c, "seconds": round(t, 3),
+                     "mpaths_per_s": round(float(np.sum(d["rays"]) / np.sum(d["seconds"]) / 1e6), 1),
+                     "efficiency": 1.0 / (rm * t)}
+    out["trained_over_heuristic"] = out["trained"]["efficiency"] / out["heuristic"]["efficiency"]
+    out["untrained_over_heuristic"] = out["untrained"]["efficiency"] / out["heuristic"]["efficiency"]
+    out["trained_over_untrained"] = out["trained"]["efficiency"] / out["untrained"]["efficiency"]
+    return out
+
+
+def batched_study(nrrs, scenes, torch, spp=64, s_batch=8, D=32, train_frames=48, ref_spp=512):
+    """The batched configuration: 1920x1080, ~5.0 M triangles (heightfield + 2000 boxes), depth
+    32, 64 spp in passes of 8 spp (16.6 M-path wavefronts), one captured hipGraph per pass,
+    autotuned traversal.  The network trains online for `train_frames` 8-spp frames, then the
+    64-spp render runs with its FP8, BF16 and FP32 inference (same weights and pixel estimate)
+    and with heuristic normalized RRS: time, Mpaths/s and relMSE against plain path tracing."""
+    W, H = 1920, 1080
+    rec_n, mb, lr = 1 << 18, 1 << 13, 5e-3
+    t_setup = time.perf_counter()
+    sc = scenes.terrain5m(0)
+    r = nrrs.Renderer(W, H, s_batch=s_batch, cap_factor=2.0, seed=0, net_max_depth=4, precision=nrrs.PREC_FP8,
+                      records_cap=rec_n, p_train=0.05 * 4194304 / (W * H * s_batch), max_tris=sc.n_tris,
+                      max_materials=len(sc.mat_type), loss=nrrs.LOSS_REL_L2, ema_decay=0.99)
+    r.upload_scene(sc)
+    tuning = r.autotune(D)
+    t_setup = time.perf_counter() - t_setup
+    t_train = time.perf_counter()
+    for f in range(train_frames):
+        _timed_render(r, torch, s_batch, D, nrrs.MODE_NET, (rec_n, mb, lr))
+    t_train = time.perf_counter() - t_train
+    guide = r.get_guide()
+    out = {"workload": f"terrain {sc.n_tris} tris, {W}x{H}, {spp} spp in passes of {s_batch} spp "
+                       f"({W * H * s_batch}-path wavefronts), max depth {D}",
+           "setup_s": round(t_setup, 1), "training_frames": train_frames, "training_s": round(t_train, 2),
+           "traversal_launch": tuning}
+    imgs = {}
+    for name, mode, prec in (("fp8", nrrs.MODE_NET, nrrs.PREC_FP8), ("bf16", nrrs.MODE_NET, nrrs.PREC_BF16),
+                             ("fp32", nrrs.MODE_NET, nrrs.PREC_FP32), ("heuristic", nrrs.MODE_HEURISTIC, None)):
+        if prec is not None:
+            r.set_precision(prec)
+        r.set_guide(guide)
+        r.reset_image()
+        r.render(s_batch, D, mode, stats=False)   # capture this configuration's pass graph
+        r.reset_image()
+        dt, st = _timed_render(r, torch, spp, D, mode)
+        img, n = r.read_image()
+        imgs[name] = img
+        out[name] = {"seconds": round(dt, 4), "mpaths_per_s": round(st["rays"] / dt / 1e6, 1), "rays": st["rays"]}
+        print(f"# batched {name}: {dt:.3f}s, {st['rays'] / dt / 1e6:.0f} Mpaths/s", flush=True)
+    r.close()
+    t_ref = time.perf_counter()
+    ref, ref_var = _reference(nrrs, sc, W, H, s_batch, D, ref_spp, 0x5EED1000)
+    out["reference"] = f"plain path tracing, {ref_spp} spp in two independent halves"
+    out["reference_s"] = round(time.perf_counter() - t_ref, 1)
+    for name, img in imgs.items():
+        a, b = _relmse_pair(img, ref, ref_var)
+        out[name]["relmse"] = a
+        out[name]["relmse_ref_noise_removed"] = b
+        out[name]["efficiency"] = 1.0 / (a * out[name]["seconds"])
+    for name in ("fp8", "bf16", "fp32"):
+        out[f"{name}_over_heuristic"] = out[name]["efficiency"] / out["heuristic"]["efficiency"]
     return out
 
 

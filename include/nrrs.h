@@ -203,6 +203,12 @@ int32_t nrrs_set_state(nrrs_ctx* ctx, const float* infer, const double* alpha);
 int32_t nrrs_set_trace(nrrs_ctx* ctx, int32_t enabled);
 int32_t nrrs_read_trace(nrrs_ctx* ctx, double* host_rgb);
 
+/* Precision of the network factor for the following renders (NRRS_PREC_FP32 / BF16 / FP8,
+ * Sec. 5 "Network Architecture"; all three weight copies are kept current by every
+ * parameter update, so a switch needs no conversion).  EINVAL for another value.  Captured
+ * pass graphs are rebuilt on the next render. */
+int32_t nrrs_set_precision(nrrs_ctx* ctx, int32_t precision);
+
 /* How nrrs_render enqueues a pass: 1 (default) captures the pass's launch sequence once per
  * (max_depth, mode, records on/off) into a hipGraph and replays it for every pass; 0 launches
  * the kernels directly.  Per-stage timing, and a context on the null stream (which cannot be
@@ -298,6 +304,15 @@ int32_t nrrs_debug_rrs_expand(nrrs_ctx* ctx, const float* q_orig, const uint32_t
                               uint32_t* X, uint32_t* offset, uint32_t* parent_of_child,
                               uint32_t* S, double* F, float* q_norm, uint32_t* retries);
 
+/* Test entry point: normalization factors given by the caller.  With n > 0, renders in
+ * HEURISTIC / NET mode use F[d-1] (host, finite, >= 0) at depth d = 1..n in place of the
+ * factor of Eqs. (10)-(14) (the overflow guard then cannot lower it); renders deeper than
+ * n + 1 return EINVAL.  n = 0 restores the computed factors.  The factor couples every path
+ * of a depth, so a near-tie decision on one path moves it for all the others; a comparison
+ * path by path against another implementation gives both the same factors.  Captured pass
+ * graphs are rebuilt on the next render.  Synchronizes the stream. */
+int32_t nrrs_debug_set_norm_factors(nrrs_ctx* ctx, const double* F, uint32_t n);
+
 /* Replace the record buffer with n host records: features[n*20], lum_t[n], acc[n] (the
  * target is acc / lum_t).  ENOMEM if n > records_cap. */
 int32_t nrrs_debug_load_records(nrrs_ctx* ctx, const float* features, const float* lum_t,
@@ -324,6 +339,14 @@ int32_t nrrs_debug_philox(nrrs_ctx* ctx, const uint32_t* ctr, const uint32_t* ke
  * current parameters in the given nrrs_precision. */
 int32_t nrrs_debug_mlp_forward(nrrs_ctx* ctx, const float* x, uint32_t n, int32_t precision,
                                float* y, float* z);
+
+/* The matrix-core forward of nrrs_debug_mlp_forward (precision NRRS_PREC_BF16 or NRRS_PREC_FP8
+ * only), also giving the bit patterns of every quantized operand: codes[n][3][64] (host) holds
+ * per row the inputs (0..19, the rest 0), hidden layer 1 and hidden layer 2 in unit order (BF16
+ * bits, or the E4M3 code in the low byte), scale_exp[n][3] (host) the FP8 block-scale exponents
+ * of those three operands (0 for BF16), y[n] the output.  Sec. 5 "Network Architecture". */
+int32_t nrrs_debug_mlp_codes(nrrs_ctx* ctx, const float* x, uint32_t n, int32_t precision, float* y,
+                             uint16_t* codes, int8_t* scale_exp);
 
 /* Loss (the configured nrrs_loss) and its gradient grad[NRRS_NPARAM] over n (features x[n*20],
  * target[n]) rows with the current FP32 masters; no parameter update. */

@@ -78,6 +78,7 @@ def lib():
         L.or_enumerate.argtypes = [P, P, P, P, P, P, P, P, P]
         L.or_mlp_forward.argtypes = [P, P, C.c_uint64, P, P]
         L.or_mlp_forward_quant.argtypes = [P, P, C.c_uint64, C.c_int32, P, P, P]
+        L.or_mlp_forward_quant_codes.argtypes = [P, P, C.c_uint64, C.c_int32, P, P, P, P, P, P]
         L.or_round_bf16.restype = C.c_double
         L.or_round_bf16.argtypes = [C.c_double]
         L.or_round_e4m3.restype = C.c_double
@@ -299,6 +300,22 @@ def mlp_forward_quant(params, x, prec, with_fragile=False):
     if with_fragile:
         return y, z, frag.astype(bool)
     return y, z
+
+
+def mlp_forward_quant_codes(params, x, prec):
+    """Quantized forward with the codes of every quantized layer (inputs, hidden 1, hidden 2):
+    returns y, z, row near-tie flags, codes [n, 3, 64] (uint16 bit patterns), per-activation
+    near-tie flags [n, 3, 64] and FP8 block-scale exponents [n, 3]."""
+    P = _c(params, np.float64)
+    x = _c(x, np.float64).reshape(-1, 20)
+    n = x.shape[0]
+    y, z = np.zeros(n), np.zeros(n)
+    frag = np.zeros(n, np.uint8)
+    codes = np.zeros((n, 3, 64), np.uint16)
+    near = np.zeros((n, 3, 64), np.uint8)
+    se = np.zeros((n, 3), np.int8)
+    lib().or_mlp_forward_quant_codes(_p(P), _p(x), n, int(prec), _p(y), _p(z), _p(frag), _p(codes), _p(near), _p(se))
+    return y, z, frag.astype(bool), codes, near.astype(bool), se
 
 
 def mlp_loss_grad(params, x, target, eps=0.01, kind=LOSS_LOG_MSE):

@@ -699,12 +699,36 @@ static double fp8_dot_error_bound(const double* w, const double* x, int n) {
   return b + 16.0 * ldexp(1.0, -24) * sabs;
 }
 
+/* Bit patterns of values already on the E4M3 / BF16 grids (the codes the matrix cores read). */
+static uint16_t e4m3_bits(double v) {
+  uint16_t sign = v < 0.0 ? 0x80 : 0;
+  double a = fabs(v);
+  if (a == 0.0) return sign;
+  int e;
+  double m = frexp(a, &e); /* a = m 2^e, m in [0.5, 1) */
+  int be = e - 1 + 7;      /* biased exponent of 1.xxx 2^(e-1) */
+  if (be <= 0) return (uint16_t)(sign | (uint16_t)nearbyint(a * 512.0)); /* subnormal: k 2^-9 */
+  int mant = (int)nearbyint((m * 2.0 - 1.0) * 8.0);
+  return (uint16_t)(sign | (be << 3) | mant);
+}
+static uint16_t bf16_bits(double v) {
+  float f = (float)v;
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  return (uint16_t)(u >> 16);
+}
+
 double or_fp8_dot_error_bound(const double* w, const double* x, int32_t n) {
   return fp8_dot_error_bound(w, x, n);
 }
 
 void or_mlp_forward_quant(const double* params, const double* x, uint64_t n, int32_t prec, double* y, double* z,
                           uint8_t* fragile) {
+  or_mlp_forward_quant_codes(params, x, n, prec, y, z, fragile, NULL, NULL, NULL);
+}
+
+void or_mlp_forward_quant_codes(const double* params, const double* x, uint64_t n, int32_t prec, double* y,
+                                double* z, uint8_t* fragile, uint16_t* codes, uint8_t* near_act, int8_t* scale_exp) {
   /* BF16: rounding decisions this close to a midpoint (in grid steps) are near-ties, a few
    * times the FP32 accumulation error relative to the grid's spacing.  FP8: a decision is a
    * near-tie when the midpoint lies within fp8_dot_error_bound of the exact pre-activation. */
@@ -731,8 +755,15 @@ void or_mlp_forward_quant(const double* params, const double* x, uint64_t n, int
     int kin = 20;
     int near = 0;
     for (int i = 0; i < 20; ++i) in[i] = (double)(float)x[20 * r + i];
+    uint16_t* cr = codes ? codes + 192 * r : NULL;
+    uint8_t* nr = near_act ? near_act + 192 * r : NULL;
+    if (cr) memset(cr, 0, sizeof(uint16_t) * 192);
+    if (nr) memset(nr, 0, 192);
+    if (scale_exp) scale_exp[3 * r] = scale_exp[3 * r + 1] = scale_exp[3 * r + 2] = 0;
     if (prec == 1) {
       for (int i = 0; i < 20; ++i) in[i] = or_round_bf16(in[i]);
+      if (cr)
+        for (int i = 0; i < 20; ++i) cr[i] = bf16_bits(in[i]);
     } else {
       double amax = 0.0;
       for (int i = 0; i < 20; ++i) amax = fmax(amax, fabs(in[i]));
@@ -740,7 +771,9 @@ void or_mlp_forward_quant(const double* params, const double* x, uint64_t n, int
       for (int i = 0; i < 20; ++i) {
         code[i] = or_round_e4m3(in[i] / bs_in);
         in[i] = code[i] * bs_in;
+        if (cr) cr[i] = e4m3_bits(code[i]);
       }
+      if (scale_exp) scale_exp[3 * r] = (int8_t)ilogb(bs_in);
     }
     for (int L = 0; L < 3; ++L) {
       const double* Wl = Wq + woff[L];
@@ -755,8 +788,11 @@ void or_mlp_forward_quant(const double* params, const double* x, uint64_t n, int
       if (L < 2) {
         if (prec == 1) {
           for (int o = 0; o < 64; ++o) {
-            if (out[o] > 0.0 && midpoint_gap_bf16(out[o]) < gap) near = 1;
+            const int na = out[o] > 0.0 && midpoint_gap_bf16(out[o]) < gap;
+            if (na) near = 1;
             in[o] = or_round_bf16(out[o]);
+            if (cr) cr[64 * (L + 1) + o] = bf16_bits(in[o]);
+            if (nr) nr[64 * (L + 1) + o] = (uint8_t)na;
           }
         } else {
           /* one power-of-two scale for the vertex's 64 activations */
@@ -767,18 +803,24 @@ void or_mlp_forward_quant(const double* params, const double* x, uint64_t n, int
           }
           double bs = block_scale(amax);
           double ratio = amax / 448.0;
+          int scale_near = 0;
           if (ratio > 0.0) {
             /* the scale changes where amax / 448 crosses a power of two */
             int e;
             frexp(ratio, &e);
             const double tol = 1e-6 * ratio + amax_err / 448.0;
-            if (ratio - ldexp(1.0, e - 1) <= tol || ldexp(1.0, e) - ratio <= tol) near = 1;
+            if (ratio - ldexp(1.0, e - 1) <= tol || ldexp(1.0, e) - ratio <= tol) scale_near = near = 1;
           }
           for (int o = 0; o < 64; ++o) {
-            if (out[o] > 0.0 && midpoint_dist_e4m3(out[o] / bs) * bs <= err[o] + 1e-6 * out[o]) near = 1;
+            const int na = out[o] > 0.0 && midpoint_dist_e4m3(out[o] / bs) * bs <= err[o] + 1e-6 * out[o];
+            if (na) near = 1;
             code[o] = or_round_e4m3(out[o] / bs);
             in[o] = code[o] * bs;
+            if (cr) cr[64 * (L + 1) + o] = e4m3_bits(code[o]);
+            /* a scale that may change changes every code of the layer */
+            if (nr) nr[64 * (L + 1) + o] = (uint8_t)(na || scale_near);
           }
+          if (scale_exp) scale_exp[3 * r + L + 1] = (int8_t)ilogb(bs);
           bs_in = bs;
         }
         kin = 64;
@@ -1062,7 +1104,10 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
       features(s, e, v, depth, D, f);
       or_mlp_forward(c->params, f, 1, &y, &z);
       if (!isfinite(y)) continue;
-      v->q = lum3(e->t) * y / (g + 0.01);
+      /* the ADRRS ratio, held within [q_h / 8, 64 q_h] of the heuristic factor q_h of the vertex */
+      const double qr = lum3(e->t) * y / (g + 0.01);
+      if (!isfinite(qr)) continue;
+      v->q = fmin(fmax(qr, 0.125 * v->q), 64.0 * v->q);
       /* the inputs carry the hit point's error (the sine encoding scales it by 16 pi / extent) */
       v->kq += 64.0 * v->perr / s->extent;
     }

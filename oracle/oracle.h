@@ -128,6 +128,13 @@ double or_round_e4m3(double x);
 double or_fp8_dot_error_bound(const double* w, const double* x, int32_t n);
 void or_mlp_forward_quant(const double* params, const double* x, uint64_t n, int32_t prec, double* y, double* z,
                           uint8_t* fragile);
+/* As or_mlp_forward_quant, also giving per row (each may be NULL): codes[192] = the bit
+ * patterns (E4M3 in the low byte, or BF16) of the quantized inputs (0..19) and of the two
+ * quantized hidden layers (64..127, 128..191); near_act[192] = 1 where that activation's
+ * rounding, or its layer's power-of-two scale, is a near-tie; scale_exp[3] = the FP8 block
+ * scale exponent of the inputs and of each hidden layer. */
+void or_mlp_forward_quant_codes(const double* params, const double* x, uint64_t n, int32_t prec, double* y,
+                                double* z, uint8_t* fragile, uint16_t* codes, uint8_t* near_act, int8_t* scale_exp);
 
 /* Training losses of the radiance estimate y against the one-sample target L:
  *   OR_LOSS_REL_L2:  mean((y - L)^2 / (sg(y)^2 + eps)), the relative L2 of Sec. 4.2.2 (Eq. 15)

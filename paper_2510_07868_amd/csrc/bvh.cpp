@@ -38,7 +38,7 @@ struct Box {
   }
 };
 
-constexpr int kBins = 16;
+constexpr int kBins = 32;
 constexpr uint32_t kLeafMax = kLeafMaxTris;  // (the link encoding would allow 8)
 constexpr uint32_t kLeafTarget = 4;
 constexpr int kSahDepth = 32;      // beyond this depth, median splits bound the tree depth

@@ -68,6 +68,8 @@ struct nrrs_ctx {
   unsigned long long* rays = nullptr;
   unsigned long long *st_n = nullptr, *st_s = nullptr, *st_r = nullptr;
   double *st_sumq = nullptr, *st_f = nullptr;
+  double* f_fixed = nullptr;  // [NRRS_MAX_DEPTH + 1] normalization factors given by nrrs_debug_set_norm_factors
+  uint32_t f_fixed_n = 0;     // depths 1..f_fixed_n use them (0: computed)
   double* image = nullptr;
   float* guide = nullptr;
   double* trace = nullptr;  // per-path radiance [nprim][trace_depth][3] (reserved when cfg.trace_depth > 0)
@@ -160,6 +162,7 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
   c->st_r = k.take<unsigned long long>(NRRS_MAX_DEPTH + 1);
   c->st_sumq = k.take<double>(NRRS_MAX_DEPTH + 1);
   c->st_f = k.take<double>(NRRS_MAX_DEPTH + 1);
+  c->f_fixed = k.take<double>(NRRS_MAX_DEPTH + 1);
   c->image = k.take<double>(3 * npx);
   c->guide = k.take<float>(npx);
   c->trace = c->cfg.trace_depth ? k.take<double>(3ull * c->cfg.trace_depth * c->nprim) : nullptr;
@@ -255,6 +258,7 @@ RenderArgs base_args(nrrs_ctx* c) {
   a.p_train = (float)c->cfg.p_train;
   a.f_rate = c->cfg.f_rate;
   a.budget_base = (double)c->nprim;
+  a.F_fixed = c->f_fixed_n ? c->f_fixed : nullptr;
   a.dbg_parent = nullptr;
   a.spill = c->spill;
   a.work = c->work;
@@ -263,6 +267,7 @@ RenderArgs base_args(nrrs_ctx* c) {
   a.ext_refill = c->tune.extend_refill;
   a.ext_leaf_batch = c->tune.extend_leaf_batch;
   a.ext_chunk = c->tune.extend_chunk;
+  a.count_work = c->timing ? 1u : 0u;
   a.pass_state = c->pass_state;
   return a;
 }
@@ -558,6 +563,14 @@ int32_t nrrs_get_tuning(const nrrs_ctx* c, nrrs_tuning* out) {
   return NRRS_OK;
 }
 
+int32_t nrrs_set_precision(nrrs_ctx* c, int32_t precision) {
+  if (!c) return NRRS_EINVAL;
+  if (precision < NRRS_PREC_FP32 || precision > NRRS_PREC_FP8) return fail(c, NRRS_EINVAL, "unknown precision");
+  if (precision != c->cfg.precision) c->drop_graphs();  // captured passes hold the old network launch
+  c->cfg.precision = precision;
+  return NRRS_OK;
+}
+
 int32_t nrrs_set_tuning(nrrs_ctx* c, const nrrs_tuning* t) {
   if (!c || !t) return NRRS_EINVAL;
   if (t->extend_variant == 4 && c->scene && !c->bvh4_ok)
@@ -584,6 +597,8 @@ int32_t nrrs_render(nrrs_ctx* c, uint32_t spp, uint32_t max_depth, int32_t mode,
   if (mode < NRRS_MODE_OFF || mode > NRRS_MODE_NET) return fail(c, NRRS_EINVAL, "unknown mode");
   if (c->trace_on && max_depth > c->cfg.trace_depth)
     return fail(c, NRRS_EINVAL, "max_depth beyond the traced depths");
+  if (c->f_fixed_n && mode != NRRS_MODE_OFF && max_depth > c->f_fixed_n + 1)
+    return fail(c, NRRS_EINVAL, "max_depth beyond the depths with a given normalization factor");
   hipStream_t s = c->stream;
   const uint32_t passes = spp / c->cfg.s_batch;
   RenderArgs a = base_args(c);
@@ -1060,6 +1075,23 @@ int32_t nrrs_debug_rrs_expand(nrrs_ctx* c, const float* q_orig, const uint32_t* 
   return NRRS_OK;
 }
 
+int32_t nrrs_debug_set_norm_factors(nrrs_ctx* c, const double* F, uint32_t n) {
+  if (!c || (n && !F)) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (n >= NRRS_MAX_DEPTH) return fail(c, NRRS_EINVAL, "more factors than depths");
+  for (uint32_t d = 0; d < n; ++d)
+    if (!(F[d] >= 0.0) || !std::isfinite(F[d])) return fail(c, NRRS_EINVAL, "factor not finite and >= 0");
+  HIPC(c, hipStreamSynchronize(c->stream));
+  if (n) {
+    std::vector<double> h(NRRS_MAX_DEPTH + 1, 0.0);
+    for (uint32_t d = 0; d < n; ++d) h[d + 1] = F[d];
+    HIPC(c, hipMemcpy(c->f_fixed, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
+  }
+  if ((n != 0) != (c->f_fixed_n != 0)) c->drop_graphs();  // captured passes hold the old arguments
+  c->f_fixed_n = n;
+  return NRRS_OK;
+}
+
 int32_t nrrs_debug_load_records(nrrs_ctx* c, const float* features, const float* lum_t, const float* acc,
                                 uint32_t n) {
   if (!c || (n && (!features || !lum_t || !acc))) return NRRS_EINVAL;
@@ -1177,6 +1209,31 @@ int32_t nrrs_debug_mlp_forward(nrrs_ctx* c, const float* x, uint32_t n, int32_t 
   HIPC(c, hipGetLastError());
   HIPC(c, hipMemcpy(y, py, sizeof(float) * n, hipMemcpyDeviceToHost));
   if (z) HIPC(c, hipMemcpy(z, pz, sizeof(float) * n, hipMemcpyDeviceToHost));
+  return NRRS_OK;
+}
+
+int32_t nrrs_debug_mlp_codes(nrrs_ctx* c, const float* x, uint32_t n, int32_t precision, float* y, uint16_t* codes,
+                             int8_t* scale_exp) {
+  if (!c || (n && (!x || !y || !codes || !scale_exp))) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (precision != NRRS_PREC_BF16 && precision != NRRS_PREC_FP8)
+    return fail(c, NRRS_EINVAL, "codes exist for the BF16 and FP8 networks only");
+  if ((uint64_t)n * 480 + 4096 > c->qb_pool_bytes) return fail(c, NRRS_ENOMEM, "too many rows for the scratch space");
+  if (n == 0) return NRRS_OK;
+  hipStream_t s = c->stream;
+  HIPC(c, hipStreamSynchronize(s));
+  Carve k{c->qb_pool};
+  float* px = k.take<float>(20ull * n);
+  float* py = k.take<float>(n);
+  uint16_t* pc = k.take<uint16_t>(192ull * n);
+  int8_t* pse = k.take<int8_t>(3ull * n);
+  HIPC(c, hipMemcpy(px, x, sizeof(float) * 20 * n, hipMemcpyHostToDevice));
+  launch_codes_mfma(px, n, net_args(c, precision), py, pc, pse, s);
+  HIPC(c, hipStreamSynchronize(s));
+  HIPC(c, hipGetLastError());
+  HIPC(c, hipMemcpy(y, py, sizeof(float) * n, hipMemcpyDeviceToHost));
+  HIPC(c, hipMemcpy(codes, pc, sizeof(uint16_t) * 192 * n, hipMemcpyDeviceToHost));
+  HIPC(c, hipMemcpy(scale_exp, pse, 3ull * n, hipMemcpyDeviceToHost));
   return NRRS_OK;
 }
 

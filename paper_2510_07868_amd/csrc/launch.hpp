@@ -45,6 +45,8 @@ struct RenderArgs {
   float p_train;
   double f_rate;
   double budget_base;   // N_px of Eq. (10): primary paths of the pass
+  const double* F_fixed;  // test entry point: normalization factor per depth given by the caller
+                          // (used as is in place of Eqs. 10-14), or null: computed
   uint32_t* dbg_parent; // when set, the expansion also writes each child's parent index
   uint32_t* spill;      // traversal stack spill area [spill depth][trace_blocks * threads]
   uint32_t* work;       // traversal claim counters [max_depth + 2][kWorkSlices][kWorkStride]
@@ -53,6 +55,7 @@ struct RenderArgs {
   uint32_t ext_refill;    // idle lanes (1..64) at which a traversal wave fetches new rays
   uint32_t ext_leaf_batch;  // parked leaves (1..64) at which a wave intersects them (variants 1, 2)
   uint32_t ext_chunk;     // queue entries a traversal wave claims at once (0: just what it needs)
+  uint32_t count_work;    // 1: the traversal also counts BVH nodes visited and triangles tested
   PassState* pass_state;  // pass index and samples per pixel so far (advanced on the device)
 };
 
@@ -111,6 +114,10 @@ uint32_t packed_fp8_bytes();
 void launch_pack_weights(const float* master, uint16_t* bf16, uint8_t* fp8, float* fp8_scale, hipStream_t s);
 void launch_rrsnet_mfma(const RenderArgs& a, const NetArgs& n, hipStream_t s);
 void launch_rows_mfma(const float* x, uint32_t n, const NetArgs& net, float* y, float* z, hipStream_t s);
+// Test entry point: also the bit patterns of every quantized layer's values ([n][3][64]: inputs,
+// hidden 1, hidden 2) and, for FP8, their block-scale exponents ([n][3]).
+void launch_codes_mfma(const float* x, uint32_t n, const NetArgs& net, float* y, uint16_t* codes, int8_t* scale_exp,
+                       hipStream_t s);
 void warm_mfma_launch_cache();  // occupancy queries done before any stream capture
 uint32_t mlp_grad_blocks(uint32_t n);
 uint32_t mlp_grad_scratch_floats(uint32_t max_rows);  // partials + reduction groups

@@ -72,8 +72,7 @@ __global__ __launch_bounds__(kNetThreads) void k_rrsnet_f32(RenderArgs a, const 
   vertex_features(a.sc, xyz(vp), xyz(vn), v3(-dr.x, -dr.y, -dr.z), xyz(th), m0, __float_as_uint(m1.w), a.depth,
                   a.max_depth, f);
   const float y = softplus_mod(mlp_row_f32(sw, f));
-  const float q = lum(xyz(th)) * y / (g + 0.01f);
-  if (isfinite(q) && q > 0.0f) a.q[i] = q;
+  a.q[i] = network_factor(lum(xyz(th)), y, g, q0);
 }
 
 __global__ __launch_bounds__(kNetThreads) void k_forward_rows_f32(const float* x, uint32_t n, const float* master,

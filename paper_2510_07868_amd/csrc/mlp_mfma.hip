@@ -161,11 +161,22 @@ __device__ __forceinline__ f32x16 bias_tile(const float* b, int mt, int h) {
 // needs on each operand.
 __device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
 
+// ReLU after the BF16 rounding, as a packed 16-bit integer maximum of each value pair with 0:
+// a BF16 value with the sign bit set reads as a negative integer, so every negative value (and
+// -0) becomes +0 and every other value is kept; rounding to nearest commutes with max(x, 0),
+// so the bits equal those of rounding the ReLU output, at half the vector instructions.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef short i16x2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ bf16x8 relu_bf16(const f32x16& c, int first) {
-  bf16x8 r;
+  int r[4];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) r[i] = (__bf16)relu(c[first + i]);
-  return r;
+  for (int k = 0; k < 4; ++k) {
+    // one packed round-to-nearest-even conversion per pair, then the packed ReLU
+    const bf16x2v b = __builtin_convertvector((f32x2){c[first + 2 * k], c[first + 2 * k + 1]}, bf16x2v);
+    r[k] = __builtin_bit_cast(int, __builtin_elementwise_max(__builtin_bit_cast(i16x2v, b), (i16x2v)0));
+  }
+  return __builtin_bit_cast(bf16x8, r);
 }
 
 __device__ __forceinline__ float output_layer(const Smem& sm, const f32x16& c0, const f32x16& c1, int h) {
@@ -181,11 +192,27 @@ __device__ __forceinline__ float output_layer(const Smem& sm, const f32x16& c0, 
 
 // Hidden layers 2, 3 and the output layer of one 32-vertex tile from its input-layer
 // accumulators; returns z of vertex l % 32 (in both lane halves).
+// Test entry point only: the BF16 bit patterns of this lane's 32 activations of hidden layer L
+// (row crow of the vertex whose column the lane holds), in unit order.
+__device__ __forceinline__ void store_codes_bf16(uint16_t* crow, int L, int h, bf16x8 b0, bf16x8 b1, bf16x8 b2,
+                                                 bf16x8 b3) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    crow[64 * L + acc_row(i, h)] = __builtin_bit_cast(uint16_t, b0[i]);
+    crow[64 * L + acc_row(8 + i, h)] = __builtin_bit_cast(uint16_t, b1[i]);
+    crow[64 * L + 32 + acc_row(i, h)] = __builtin_bit_cast(uint16_t, b2[i]);
+    crow[64 * L + 32 + acc_row(8 + i, h)] = __builtin_bit_cast(uint16_t, b3[i]);
+  }
+}
+
+template <bool kCodes = false>
 __device__ __forceinline__ float bf16_hidden(const bf16x8* __restrict__ w, const Smem& sm, f32x16 c0, f32x16 c1,
-                                             int h) {
+                                             int h, uint16_t* crow = nullptr) {
 #pragma unroll
   for (int L = 1; L < 3; ++L) {
     const bf16x8 b0 = relu_bf16(c0, 0), b1 = relu_bf16(c0, 8), b2 = relu_bf16(c1, 0), b3 = relu_bf16(c1, 8);
+    if constexpr (kCodes)
+      if (crow) store_codes_bf16(crow, L, h, b0, b1, b2, b3);
     const int t = kBfL1 + 8 * (L - 1);
     c0 = bias_tile(sm.b[L], 0, h);
     c1 = bias_tile(sm.b[L], 1, h);
@@ -203,7 +230,10 @@ __device__ __forceinline__ float bf16_hidden(const bf16x8* __restrict__ w, const
 
 // BF16: every lane passes its own vertex's features and gets that vertex's output
 // pre-activation z.  Lanes 0-31 form vertex tile 0, lanes 32-63 tile 1.
-__device__ __forceinline__ float mlp_bf16(const bf16x8* __restrict__ wl, const Smem& sm, const float f[20]) {
+// cstep (test entry point only): code rows of the step's 64 vertices, of which nleft exist.
+template <bool kCodes = false>
+__device__ __forceinline__ float mlp_bf16(const bf16x8* __restrict__ wl, const Smem& sm, const float f[20],
+                                          uint16_t* cstep = nullptr, uint32_t nleft = 0) {
   const bf16x8* w = wl + __lane_id();  // this lane's part of tile t is w[64 t]
   const int h = (int)(__lane_id() >> 5);
   bf16x8 x[3];
@@ -211,6 +241,13 @@ __device__ __forceinline__ float mlp_bf16(const bf16x8* __restrict__ wl, const S
   for (int j = 0; j < 3; ++j)
 #pragma unroll
     for (int i = 0; i < 8; ++i) x[j][i] = (__bf16)(8 * j + i < 20 ? f[(8 * j + i) % 20] : 0.0f);
+  if constexpr (kCodes) {
+    if (__lane_id() < nleft)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) cstep[192 * __lane_id() + 8 * j + i] = __builtin_bit_cast(uint16_t, x[j][i]);
+  }
   float z[2];
 #pragma unroll
   for (int vt = 0; vt < 2; ++vt) {
@@ -222,7 +259,12 @@ __device__ __forceinline__ float mlp_bf16(const bf16x8* __restrict__ wl, const S
       c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[64 * (6 * vt + j)], x[j], c0, 0, 0, 0);
       c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[64 * (6 * vt + 3 + j)], x[j], c1, 0, 0, 0);
     }
-    z[vt] = bf16_hidden(w, sm, c0, c1, h);
+    uint16_t* crow = nullptr;
+    if constexpr (kCodes) {
+      const uint32_t v = 32u * vt + (__lane_id() & 31u);  // the vertex whose column this lane holds
+      if (v < nleft) crow = cstep + 192ull * v;
+    }
+    z[vt] = bf16_hidden<kCodes>(w, sm, c0, c1, h, crow);
   }
   return h ? z[1] : z[0];
 }
@@ -258,7 +300,20 @@ __device__ __forceinline__ i32x8 quant_block(const float (&x)[32], int& scale_co
   return r;
 }
 
-__device__ __forceinline__ float mlp_fp8(const i32x8* __restrict__ wl, const Smem& sm, const float f[20]) {
+// Test entry point only: this lane's 32 E4M3 codes of layer L (0 = inputs) and the layer's
+// block-scale exponent, into row crow of the lane pair's vertex.
+__device__ __forceinline__ void store_codes_fp8(uint16_t* crow, int8_t* serow, int L, int h, const i32x8& xb, int sx) {
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const uint16_t b = (uint16_t)(((uint32_t)xb[i / 4] >> (8 * (i % 4))) & 0xFFu);
+    crow[64 * L + (L == 0 ? 32 * h + i : fp8_unit(h, i))] = b;
+  }
+  if (h == 0) serow[L] = (int8_t)(sx - 127);
+}
+
+template <bool kCodes = false>
+__device__ __forceinline__ float mlp_fp8(const i32x8* __restrict__ wl, const Smem& sm, const float f[20],
+                                         uint16_t* crow = nullptr, int8_t* serow = nullptr) {
   const i32x8* w = wl + __lane_id();  // this lane's part of tile t is w[64 t]
   const int h = (int)(__lane_id() >> 5);
   float x[32];
@@ -266,6 +321,8 @@ __device__ __forceinline__ float mlp_fp8(const i32x8* __restrict__ wl, const Sme
   for (int i = 0; i < 32; ++i) x[i] = (h == 0 && i < 20) ? f[i % 20] : 0.0f;
   int sx;
   i32x8 xb = quant_block(x, sx);
+  if constexpr (kCodes)
+    if (crow) store_codes_fp8(crow, serow, 0, h, xb, sx);
   f32x16 c0 = {}, c1 = {};
   c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(w[64 * (0)], xb, c0, 0, 0, 0, 127, 0, sx);
   c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(w[64 * (1)], xb, c1, 0, 0, 0, 127, 0, sx);
@@ -278,6 +335,8 @@ __device__ __forceinline__ float mlp_fp8(const i32x8* __restrict__ wl, const Sme
       x[16 + v] = fmaxf(fmaf(c1[v], sm.s[L - 1], sm.b[L - 1][32 + acc_row(v, h)]), 0.0f);
     }
     xb = quant_block(x, sx);
+    if constexpr (kCodes)
+      if (crow) store_codes_fp8(crow, serow, L, h, xb, sx);
     c0 = f32x16{};
     c1 = f32x16{};
     c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(w[64 * (2 * L)], xb, c0, 0, 0, 0, 127, 0, sx);
@@ -306,6 +365,10 @@ struct Weights<1> {
     lds = reinterpret_cast<const bf16x8*>(smem);
   }
   __device__ float eval(const Smem& sm, const float f[20]) const { return mlp_bf16(lds, sm, f); }
+  // test entry point: also the codes of the step's vertices (rows cstep, nleft of them)
+  __device__ float eval_codes(const Smem& sm, const float f[20], uint16_t* cstep, int8_t*, uint32_t nleft) const {
+    return mlp_bf16<true>(lds, sm, f, cstep, nleft);
+  }
 };
 template <>
 struct Weights<2> {
@@ -319,6 +382,15 @@ struct Weights<2> {
     lds = reinterpret_cast<const i32x8*>(smem);
   }
   __device__ float eval(const Smem& sm, const float f[20]) const { return mlp_fp8(lds, sm, f); }
+  __device__ float eval_codes(const Smem& sm, const float f[20], uint16_t* cstep, int8_t* sestep,
+                              uint32_t nleft) const {
+    // every lane runs the same code (matrix-core and cross-lane operations need the whole
+    // wave); only the stores of lanes past the last vertex are skipped
+    const uint32_t v = __lane_id() & 31u;  // the lane pair's vertex
+    uint16_t* crow = v < nleft ? cstep + 192ull * v : nullptr;
+    int8_t* serow = v < nleft ? sestep + 3ull * v : nullptr;
+    return mlp_fp8<true>(lds, sm, f, crow, serow);
+  }
 };
 
 // Network factors for the vertices of one depth: persistent waves over tiles of 32 entries.
@@ -344,10 +416,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
     const uint32_t i = tile * kV + (lane & (kV - 1));
     bool active = false;
     float f[20];
-    float g = 0.0f, lt = 0.0f;
+    float g = 0.0f, lt = 0.0f, qh = 0.0f;
 #pragma unroll
     for (int k = 0; k < 20; ++k) f[k] = 0.0f;
-    if (i < n && a.q[i] > 0.0f) {
+    if (i < n) qh = a.q[i];
+    if (i < n && qh > 0.0f) {
       const float4 dr = a.qin.dir[i];
       g = a.guide[__float_as_uint(dr.w)];
       if (g >= 0.0f) {
@@ -361,15 +434,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))
       }
     }
     const float z = W.eval(sm, f);
-    if (active && lane < kV) {
-      const float q = lt * softplus_mod(z) / (g + 0.01f);
-      if (isfinite(q) && q > 0.0f) a.q[i] = q;
-    }
+    if (active && lane < kV) a.q[i] = network_factor(lt, softplus_mod(z), g, qh);
   }
 }
 
-template <int P>
-__global__ __launch_bounds__(kThreads) void k_rows_mfma(const float* x, uint32_t n, NetArgs net, float* y, float* zout) {
+template <int P, bool kCodes = false>
+__global__ __launch_bounds__(kThreads) void k_rows_mfma(const float* x, uint32_t n, NetArgs net, float* y, float* zout,
+                                                      uint16_t* codes = nullptr, int8_t* scale_exp = nullptr) {
   __shared__ Smem sm;
   __shared__ __attribute__((aligned(16))) uint8_t wsm[Weights<P>::kBytes];
   Weights<P> W;
@@ -386,7 +457,11 @@ __global__ __launch_bounds__(kThreads) void k_rows_mfma(const float* x, uint32_t
     float f[20];
 #pragma unroll
     for (int k = 0; k < 20; ++k) f[k] = i < n ? x[20ull * i + k] : 0.0f;
-    const float z = W.eval(sm, f);
+    float z;
+    if constexpr (kCodes)
+      z = W.eval_codes(sm, f, codes + 192ull * tile * kV, scale_exp + 3ull * tile * kV, n - tile * kV);
+    else
+      z = W.eval(sm, f);
     if (i < n && lane < kV) {
       y[i] = softplus_mod(z);
       if (zout) zout[i] = z;
@@ -431,6 +506,18 @@ void launch_rrsnet_mfma(const RenderArgs& a, const NetArgs& n, hipStream_t s) {
     hipLaunchKernelGGL(k_rrsnet_mfma<2>, dim3(grid_for(k_rrsnet_mfma<2>, 1)), dim3(kThreads), 0, s, a, n);
   else
     hipLaunchKernelGGL(k_rrsnet_mfma<1>, dim3(grid_for(k_rrsnet_mfma<1>, 0)), dim3(kThreads), 0, s, a, n);
+}
+
+void launch_codes_mfma(const float* x, uint32_t n, const NetArgs& net, float* y, uint16_t* codes, int8_t* scale_exp,
+                       hipStream_t s) {
+  if (!n) return;
+  const uint32_t blocks = (n + 4 * 32 - 1) / (4 * 32);
+  if (net.precision == 2)
+    hipLaunchKernelGGL((k_rows_mfma<2, true>), dim3(blocks), dim3(kThreads), 0, s, x, n, net, y, nullptr, codes,
+                       scale_exp);
+  else
+    hipLaunchKernelGGL((k_rows_mfma<1, true>), dim3(blocks), dim3(kThreads), 0, s, x, n, net, y, nullptr, codes,
+                       scale_exp);
 }
 
 void launch_rows_mfma(const float* x, uint32_t n, const NetArgs& net, float* y, float* z, hipStream_t s) {

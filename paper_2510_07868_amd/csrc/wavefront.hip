@@ -10,6 +10,7 @@
 #include <algorithm>
 
 #include "features.hpp"
+#include "claim.hpp"
 #include "launch.hpp"
 
 namespace nrrs {
@@ -178,17 +179,20 @@ __device__ __forceinline__ unsigned long long hit_key(float t, uint32_t orig) {
 // closest hit is an LDS atomic minimum of hit keys; after each round the lane holding the
 // current minimum publishes triangle and barycentrics.  Same result as test_leaf on every owner.
 static_assert(kLeafMaxTris == 4, "the leaf phase deals four lanes to each parked leaf");
+template <bool kCount>
 __device__ __forceinline__ void leaf_phase_shared(const DevScene& sc, bool mine, uint32_t link, V3 o, V3 d,
                                                   uint32_t excl, HitState& h, uint32_t& tris,
                                                   unsigned long long* key, float4* slot, uint8_t* owner) {
   const uint32_t lane = __lane_id();
   const uint64_t parked = __ballot(mine);
   const uint32_t n_parked = (uint32_t)__popcll(parked);
-  const uint32_t cnt = mine ? (link & 7u) + 1u : 0u;
-  uint32_t total = 0;
+  if constexpr (kCount) {
+    const uint32_t cnt = mine ? (link & 7u) + 1u : 0u;
+    uint32_t total = 0;
 #pragma unroll
-  for (int b = 0; b < 3; ++b) total += (uint32_t)__popcll(__ballot((cnt >> b) & 1u)) << b;
-  tris += total;  // wave-uniform count of the (ray, triangle) pairs
+    for (int b = 0; b < 3; ++b) total += (uint32_t)__popcll(__ballot((cnt >> b) & 1u)) << b;
+    tris += total;  // wave-uniform count of the (ray, triangle) pairs
+  }
   const unsigned long long start = hit_key(h.t, h.orig);
   if (mine) {
     key[lane] = start;
@@ -252,7 +256,12 @@ struct LaneStack {
   }
   __device__ uint32_t pop() {
     --sp;
-    return sp < kLdsStack ? lds[sp][tid] : spill[(uint64_t)(sp - kLdsStack) * gthreads];
+    // the LDS entry is read unconditionally (clamped index) and the spill area only past it,
+    // so the common case is a plain LDS read rather than a generic-address load
+    typedef __attribute__((address_space(1))) const uint32_t GlobalU32;
+    uint32_t v = lds[sp < kLdsStack ? sp : kLdsStack - 1][tid];
+    if (sp >= kLdsStack) v = ((GlobalU32*)spill)[(uint64_t)(sp - kLdsStack) * gthreads];
+    return v;
   }
 };
 
@@ -272,7 +281,7 @@ constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 //   kMode 4: as 3 over the 4-wide tree: a visit tests four child boxes, pushes the hit
 //     children farthest first and pops the nearest (a leaf is parked).  At most 3 entries
 //     per level stay on the stack, so the tree must be at most kMaxBvh4Depth levels deep.
-template <int kMode>
+template <int kMode, bool kCount>
 __device__ __forceinline__ void extend_body(const RenderArgs& a) {
   __shared__ uint32_t stack_lds[kLdsStack][kTraceThreads];
   __shared__ unsigned long long cnt[3];  // rays traced, nodes visited, triangles tested
@@ -291,14 +300,9 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
   const uint32_t chunk = a.ext_chunk;
   bool active = false, exhausted = false;
   uint32_t ray = 0, excl = 0, ni = 0, pend = 0;
-  // wave-uniform pool of claimed queue entries not yet handed to a lane, [pool_next, pool_end).
-  // Claims start in slice blockIdx % kWorkSlices and move on to the next slice once one is
-  // used up; `drained` once every slice is.
-  uint32_t pool_next = 0, pool_end = 0;
-  uint32_t slice = blockIdx.x % kWorkSlices, slices_left = kWorkSlices;
-  uint32_t s_lo = (uint32_t)((uint64_t)n * slice / kWorkSlices);
-  uint32_t s_hi = (uint32_t)((uint64_t)n * (slice + 1) / kWorkSlices);
-  bool drained = n == 0;
+  // wave-uniform pool of claimed queue entries not yet handed to a lane (claim.hpp); claims
+  // start in slice blockIdx % kWorkSlices and move on to the next slice once one is used up
+  ClaimState cs = claim_start(n, blockIdx.x, kWorkSlices);
   V3 o = v3(0, 0, 0), d = o, inv = o, oi = o;
   float eps = 0.0f;
   HitState h;
@@ -311,33 +315,19 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
       if (idle != 0 && (__popcll(idle) >= refill || idle == __ballot(true))) {
         const uint32_t want = (uint32_t)__popcll(idle);
         const uint32_t rank = lanes_below(idle);  // this lane's rank among the idle lanes
-        const uint32_t have = pool_end - pool_next;
-        uint32_t my = rank < have ? pool_next + rank : 0xFFFFFFFFu;
-        if (have < want && !drained) {
-          // claim what the idle lanes still need, or a whole chunk of entries, from the
-          // current slice; a claim that reaches the slice's end moves on to the next slice
-          const uint32_t take = max(chunk, want - have);
+        // claim what the idle lanes still need, or a whole chunk of entries, from the current
+        // slice with one atomic; the returned range is clamped to the slice
+        const bool claim = claim_needed(cs, want);
+        uint32_t off = 0, take = 0;
+        if (claim) {
+          take = claim_amount(cs, want, chunk);
           const int leader = __ffsll((unsigned long long)idle) - 1;
           uint32_t b = 0;
-          if ((int)__lane_id() == leader) b = atomicAdd(work + slice * kWorkStride, take);
-          const uint32_t off = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(b, leader));
-          const uint32_t size = s_hi - s_lo;
-          const uint32_t fresh = s_lo + min(off, size);
-          const uint32_t end = s_lo + (uint32_t)min((uint64_t)off + take, (uint64_t)size);
-          if (rank >= have) my = fresh + (rank - have) < end ? fresh + (rank - have) : 0xFFFFFFFFu;
-          pool_end = end;
-          pool_next = min(fresh + (want - have), end);
-          if (end == s_hi) {
-            --slices_left;
-            drained = slices_left == 0;
-            slice = slice + 1 == kWorkSlices ? 0 : slice + 1;
-            s_lo = (uint32_t)((uint64_t)n * slice / kWorkSlices);
-            s_hi = (uint32_t)((uint64_t)n * (slice + 1) / kWorkSlices);
-          }
-        } else {
-          pool_next += min(want, have);
+          if ((int)__lane_id() == leader) b = atomicAdd(work + cs.slice * kWorkStride, take);
+          off = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(b, leader));
         }
-        exhausted = drained && pool_next >= pool_end;
+        const uint32_t my = claim_hand_out(cs, n, kWorkSlices, want, rank, claim, off, take);
+        exhausted = claim_exhausted(cs);
         if (!active && my < n) {
           // ray data loaded together (one round trip), dead entries only write a miss
           const float4 th = a.qin.thr[my], og = a.qin.orig[my], dr = a.qin.dir[my];
@@ -375,7 +365,7 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
       continue;
     }
     if constexpr (kMode == 0) {
-      w_nodes += (uint32_t)__popcll(__ballot(active));
+      if constexpr (kCount) w_nodes += (uint32_t)__popcll(__ballot(active));
       if (!active) continue;
       // one node: test both child boxes, intersect leaf children, descend or pop
       const float4 n0 = sc.node[4 * ni], n1 = sc.node[4 * ni + 1], n2 = sc.node[4 * ni + 2], n3 = sc.node[4 * ni + 3];
@@ -410,8 +400,10 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
       // pop the stack) until enough leaves are parked, no lane is still looking for one, or
       // enough lanes have finished to make a refill worthwhile.
       uint64_t parked, seeking;
-      for (;;) {
-        w_nodes += (uint32_t)__popcll(__ballot(active && ni != kNoNode && (kMode == 2 || pend == 0)));
+      // one step of every lane without a parked leaf: visit a node, or pop the stack
+      auto node_step = [&]() {
+        if constexpr (kCount)
+          w_nodes += (uint32_t)__popcll(__ballot(active && ni != kNoNode && (kMode == 2 || pend == 0)));
         if (active) {
           if constexpr (kMode == 4) {
             if (ni != kNoNode && pend == 0) {
@@ -477,6 +469,13 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
             }
           }
         }
+      };
+      // two steps per check of the wave-wide exit conditions: a lane that parks a leaf or
+      // finishes in the first step only idles through the second, and the ballots, counts and
+      // branches of the check are paid once per two node visits
+      for (;;) {
+        node_step();
+        node_step();
         parked = __ballot(active && pend != 0);
         seeking = __ballot(active && pend == 0);
         if (seeking == 0 || __popcll(parked) >= leaf_batch) break;
@@ -485,7 +484,7 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
       if (parked != 0 && (seeking == 0 || __popcll(parked) >= leaf_batch)) {
         if constexpr (kMode >= 3) {
           const int wbase = tid & ~63;
-          leaf_phase_shared(sc, active && pend != 0, pend, o, d, excl, h, w_tris, hit_keys + wbase,
+          leaf_phase_shared<kCount>(sc, active && pend != 0, pend, o, d, excl, h, w_tris, hit_keys + wbase,
                             hit_slots + wbase, leaf_owner + wbase);
           if (active) pend = 0;
         } else if (active && pend != 0) {
@@ -508,12 +507,14 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
   if (tid < 3 && cnt[tid]) atomicAdd(a.rays + tid, cnt[tid]);
 }
 
-// Variants that park leaves fit 72 VGPRs without spilling: 7 waves per SIMD.
-template <int kMode>
+// Variants that park leaves fit 72 VGPRs without spilling: 7 waves per SIMD.  kCount: BVH
+// nodes visited and triangles tested are counted too (per-stage timing runs only).
+template <int kMode, bool kCount>
 __global__ __launch_bounds__(kTraceThreads) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_extend(RenderArgs a) {
-  extend_body<kMode>(a);
+  extend_body<kMode, kCount>(a);
 }
-__global__ __launch_bounds__(kTraceThreads) void k_extend_immediate(RenderArgs a) { extend_body<0>(a); }
+template <bool kCount>
+__global__ __launch_bounds__(kTraceThreads) void k_extend_immediate(RenderArgs a) { extend_body<0, kCount>(a); }
 
 // ------------------------------------------------------------------------------- shade
 constexpr uint32_t kNoPix = 0xFFFFFFFFu;
@@ -716,6 +717,10 @@ __global__ __launch_bounds__(kScanThreads) void k_sum_q_partial(RenderArgs a) {
   if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
 }
 
+// The partial sums added in a fixed tree by one block.  (A single launch in which the last
+// block to finish adds the partials needs every block to publish its partial with a
+// device-wide release, which on the eight-XCD MI355X writes back each XCD's L2: measured four
+// times slower than this second launch.)
 __global__ __launch_bounds__(kScanThreads) void k_sum_q_final(RenderArgs a) {
   __shared__ double sh[kScanThreads];
   double acc = 0.0;
@@ -728,6 +733,7 @@ __global__ __launch_bounds__(kScanThreads) void k_sum_q_final(RenderArgs a) {
 // Normalization factor for a given alpha (Eqs. 10, 12-14; Sec. 5 downscale variant).
 __device__ __forceinline__ double norm_factor(const RenderArgs& a, double sumq, double alpha) {
   if (a.mode == 0u) return 1.0;
+  if (a.F_fixed) return a.F_fixed[a.depth];
   if (!(sumq > 0.0)) return 0.0;
   double F = (a.f_rate * alpha) * a.budget_base / sumq;
   if (a.norm_mode == 1u && F > 1.0) F = 1.0;
@@ -743,27 +749,6 @@ __device__ __forceinline__ uint32_t child_count(float q, double F, float u) {
 
 __device__ __forceinline__ float roulette_u(const RenderArgs& a, uint32_t i) {
   return unit(draw(a.key, a.qin.id[i], kPurposeRoulette, a.depth, 0).x);
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_roulette_count(RenderArgs a) {
-  __shared__ uint32_t sh[kScanThreads];
-  const uint32_t n = a.ctl[a.depth].n;
-  const uint32_t chunk = chunk_of(n);
-  const uint32_t beg = blockIdx.x * chunk;
-  const double F = norm_factor(a, a.ctl[a.depth].sumq, *a.alpha);
-  uint32_t acc = 0;
-#pragma unroll 4
-  for (uint32_t base = beg; base < beg + chunk && base < n; base += kScanThreads) {
-    const uint32_t i = base + threadIdx.x;
-    if (i < n && i < beg + chunk) {
-      const float q = a.q[i];
-      const uint32_t x = q > 0.0f ? child_count(q, F, roulette_u(a, i)) : 0u;
-      a.offs[i] = x;  // kept for k_offsets unless the overflow guard changes the factor
-      acc += x;
-    }
-  }
-  const uint32_t s = block_sum(acc, sh);
-  if (threadIdx.x == 0) a.bsum[blockIdx.x] = s;
 }
 
 // Exclusive scan of kScanBlocks values by one block of kScanThreads threads (4 per thread).
@@ -798,6 +783,7 @@ __device__ __forceinline__ uint64_t scan_blocks(const uint32_t* in, uint32_t* ou
   return total;
 }
 
+// Offsets of the blocks' children, the total S, and whether the overflow guard runs.
 __global__ __launch_bounds__(kScanThreads) void k_roulette_scan(RenderArgs a) {
   __shared__ uint64_t sh[kScanThreads];
   const uint64_t S = scan_blocks(a.bsum, a.boff, sh);
@@ -815,30 +801,25 @@ __global__ __launch_bounds__(kScanThreads) void k_roulette_scan(RenderArgs a) {
   }
 }
 
-// Overflow guard, only active when the first count overflowed: counts for the next
-// kGuardSteps values alpha * 0.99^k, k = 1..kGuardSteps (Eq. 14 applied repeatedly).
-__global__ __launch_bounds__(kScanThreads) void k_guard_count(RenderArgs a) {
-  if (a.ctl[a.depth].guard == 0) return;
+__global__ __launch_bounds__(kScanThreads) void k_roulette_count(RenderArgs a) {
   __shared__ uint32_t sh[kScanThreads];
   const uint32_t n = a.ctl[a.depth].n;
   const uint32_t chunk = chunk_of(n);
   const uint32_t beg = blockIdx.x * chunk;
-  const double sumq = a.ctl[a.depth].sumq;
-  double alpha = *a.alpha;
-  for (int k = 0; k < kGuardSteps; ++k) {
-    alpha *= 0.99;
-    const double F = norm_factor(a, sumq, alpha);
-    uint32_t acc = 0;
-    for (uint32_t base = beg; base < beg + chunk && base < n; base += kScanThreads) {
-      const uint32_t i = base + threadIdx.x;
-      if (i < n && i < beg + chunk) {
-        const float q = a.q[i];
-        if (q > 0.0f) acc += child_count(q, F, roulette_u(a, i));
-      }
+  const double F = norm_factor(a, a.ctl[a.depth].sumq, *a.alpha);
+  uint32_t acc = 0;
+#pragma unroll 4
+  for (uint32_t base = beg; base < beg + chunk && base < n; base += kScanThreads) {
+    const uint32_t i = base + threadIdx.x;
+    if (i < n && i < beg + chunk) {
+      const float q = a.q[i];
+      const uint32_t x = q > 0.0f ? child_count(q, F, roulette_u(a, i)) : 0u;
+      a.offs[i] = x;  // kept for k_offsets unless the overflow guard changes the factor
+      acc += x;
     }
-    const uint32_t s = block_sum(acc, sh);
-    if (threadIdx.x == 0) a.gsum[kScanBlocks * k + blockIdx.x] = s;
   }
+  const uint32_t s = block_sum(acc, sh);
+  if (threadIdx.x == 0) a.bsum[blockIdx.x] = s;
 }
 
 // alpha after k reductions by the factor 0.99 (Eq. 14), applied one at a time as in a loop
@@ -889,8 +870,10 @@ __global__ __launch_bounds__(kScanThreads) void k_guard_select(RenderArgs a) {
     }
   }
   __syncthreads();
+  const int first = chosen;
+  __syncthreads();  // every wave holds the first loop's result before thread 0 may change it
   bool need_block_sums = false;
-  if (chosen == 0) {
+  if (first == 0) {
     // rare path: bisection over the reductions kGuardSteps+1 .. K, K the last with alpha >= 1e-3
     int K = kGuardSteps;
     double aK = alpha_after(alpha0, K);
@@ -960,6 +943,32 @@ __global__ __launch_bounds__(kScanThreads) void k_guard_select(RenderArgs a) {
   }
   if (k < 0)
     for (int b = threadIdx.x; b < kScanBlocks; b += kScanThreads) a.boff[b] = 0;
+}
+
+// Overflow guard, only active when the first count overflowed: counts for the next
+// kGuardSteps values alpha * 0.99^k, k = 1..kGuardSteps (Eq. 14 applied repeatedly).
+__global__ __launch_bounds__(kScanThreads) void k_guard_count(RenderArgs a) {
+  if (a.ctl[a.depth].guard == 0) return;
+  __shared__ uint32_t sh[kScanThreads];
+  const uint32_t n = a.ctl[a.depth].n;
+  const uint32_t chunk = chunk_of(n);
+  const uint32_t beg = blockIdx.x * chunk;
+  const double sumq = a.ctl[a.depth].sumq;
+  double alpha = *a.alpha;
+  for (int k = 0; k < kGuardSteps; ++k) {
+    alpha *= 0.99;
+    const double F = norm_factor(a, sumq, alpha);
+    uint32_t acc = 0;
+    for (uint32_t base = beg; base < beg + chunk && base < n; base += kScanThreads) {
+      const uint32_t i = base + threadIdx.x;
+      if (i < n && i < beg + chunk) {
+        const float q = a.q[i];
+        if (q > 0.0f) acc += child_count(q, F, roulette_u(a, i));
+      }
+    }
+    const uint32_t s = block_sum(acc, sh);
+    if (threadIdx.x == 0) a.gsum[kScanBlocks * k + blockIdx.x] = s;
+  }
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave.
@@ -1156,26 +1165,27 @@ void launch_camera(const RenderArgs& a, hipStream_t s) {
   const uint32_t nthreads = std::max(a.nprim, (a.max_depth + 1) * kWorkSlices);
   hipLaunchKernelGGL(k_camera, dim3(blocks_for(nthreads, kEntryThreads)), dim3(kEntryThreads), 0, s, a);
 }
+template <bool kCount>
+void launch_extend_t(const RenderArgs& a, hipStream_t s) {
+  const dim3 g(a.trace_blocks), b(kTraceThreads);
+  if (a.ext_variant == 4) hipLaunchKernelGGL((k_extend<4, kCount>), g, b, 0, s, a);
+  else if (a.ext_variant == 3) hipLaunchKernelGGL((k_extend<3, kCount>), g, b, 0, s, a);
+  else if (a.ext_variant == 2) hipLaunchKernelGGL((k_extend<2, kCount>), g, b, 0, s, a);
+  else if (a.ext_variant == 1) hipLaunchKernelGGL((k_extend<1, kCount>), g, b, 0, s, a);
+  else hipLaunchKernelGGL(k_extend_immediate<kCount>, g, b, 0, s, a);
+}
 void launch_extend(const RenderArgs& a, hipStream_t s) {
-  if (a.ext_variant == 4)
-    hipLaunchKernelGGL(k_extend<4>, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
-  else if (a.ext_variant == 3)
-    hipLaunchKernelGGL(k_extend<3>, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
-  else if (a.ext_variant == 2)
-    hipLaunchKernelGGL(k_extend<2>, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
-  else if (a.ext_variant == 1)
-    hipLaunchKernelGGL(k_extend<1>, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_extend_immediate, dim3(a.trace_blocks), dim3(kTraceThreads), 0, s, a);
+  if (a.count_work) launch_extend_t<true>(a, s);
+  else launch_extend_t<false>(a, s);
 }
 uint32_t extend_blocks_per_cu(uint32_t variant) {
   int nb = 0;
   hipError_t e;
-  if (variant == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<4>, kTraceThreads, 0);
-  else if (variant == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<3>, kTraceThreads, 0);
-  else if (variant == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<2>, kTraceThreads, 0);
-  else if (variant == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<1>, kTraceThreads, 0);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend_immediate, kTraceThreads, 0);
+  if (variant == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<4, false>, kTraceThreads, 0);
+  else if (variant == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<3, false>, kTraceThreads, 0);
+  else if (variant == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<2, false>, kTraceThreads, 0);
+  else if (variant == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<1, false>, kTraceThreads, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend_immediate<false>, kTraceThreads, 0);
   if (e != hipSuccess || nb < 1) nb = 1;
   return (uint32_t)nb;
 }

@@ -26,14 +26,14 @@ STAGES = ["camera", "extend", "shade", "network", "sum_q", "roulette_scan", "exp
 
 EXPORTS = [
     "nrrs_create", "nrrs_workspace_size", "nrrs_bind_workspace", "nrrs_upload_scene", "nrrs_render",
-    "nrrs_set_timing", "nrrs_set_launch_mode", "nrrs_set_mix_depth", "nrrs_get_mix_depth",
+    "nrrs_set_timing", "nrrs_set_launch_mode", "nrrs_set_precision", "nrrs_set_mix_depth", "nrrs_get_mix_depth",
     "nrrs_set_mix_depth_fixed", "nrrs_get_mix_depth_fixed",
     "nrrs_set_pass_index", "nrrs_get_pass_index", "nrrs_get_tuning", "nrrs_set_tuning", "nrrs_autotune",
     "nrrs_train_step", "nrrs_read_image", "nrrs_reset_image", "nrrs_set_guide", "nrrs_get_guide",
     "nrrs_get_params", "nrrs_set_params", "nrrs_get_state", "nrrs_set_state", "nrrs_set_trace",
     "nrrs_read_trace", "nrrs_read_records", "nrrs_debug_rrs_expand",
-    "nrrs_debug_load_records", "nrrs_debug_read_queue", "nrrs_debug_trace",
-    "nrrs_debug_philox", "nrrs_debug_mlp_forward", "nrrs_debug_mlp_grad", "nrrs_status_string",
+    "nrrs_debug_set_norm_factors", "nrrs_debug_load_records", "nrrs_debug_read_queue", "nrrs_debug_trace",
+    "nrrs_debug_philox", "nrrs_debug_mlp_forward", "nrrs_debug_mlp_codes", "nrrs_debug_mlp_grad", "nrrs_status_string",
     "nrrs_last_error", "nrrs_destroy",
 ]
 
@@ -103,6 +103,7 @@ def load():
         "nrrs_render": [P, U32, U32, I32, P],
         "nrrs_set_timing": [P, I32],
         "nrrs_set_launch_mode": [P, I32],
+        "nrrs_set_precision": [P, I32],
         "nrrs_set_mix_depth": [P, U64],
         "nrrs_get_mix_depth": [P, P],
         "nrrs_set_mix_depth_fixed": [P, U64],
@@ -125,11 +126,13 @@ def load():
         "nrrs_read_trace": [P, P],
         "nrrs_read_records": [P, P, P, P, P, P, P, P],
         "nrrs_debug_rrs_expand": [P, P, P, P, U32, U32, D, D, P, I32, U32, P, P, P, P, P, P, P],
+        "nrrs_debug_set_norm_factors": [P, P, U32],
         "nrrs_debug_load_records": [P, P, P, P, U32],
         "nrrs_debug_read_queue": [P, I32, U32, P, P, P, P],
         "nrrs_debug_trace": [P, P, P, U32, P, P, P, P],
         "nrrs_debug_philox": [P, P, P, U32, P],
         "nrrs_debug_mlp_forward": [P, P, U32, I32, P, P],
+        "nrrs_debug_mlp_codes": [P, P, U32, I32, P, P, P],
         "nrrs_debug_mlp_grad": [P, P, P, U32, P, P],
     }
     for name, args in sig.items():
@@ -234,6 +237,9 @@ class Renderer:
 
     def set_launch_mode(self, graphs=True):
         self._check(self.L.nrrs_set_launch_mode(self.h, 1 if graphs else 0))
+
+    def set_precision(self, precision):
+        self._check(self.L.nrrs_set_precision(self.h, precision))
 
     def set_timing(self, enabled=True):
         self._check(self.L.nrrs_set_timing(self.h, 1 if enabled else 0))
@@ -383,6 +389,15 @@ class Renderer:
         return dict(status=int(code), X=X[:n], offset=off[:n], parent=par[: S.value].copy(), S=int(S.value),
                     F=float(F.value), q_norm=qn[:n], alpha=float(a.value), retries=int(r.value))
 
+    def debug_set_norm_factors(self, F=None):
+        """Normalization factor per depth (F[d-1] at depth d) used instead of the computed one;
+        None restores the computed factors."""
+        if F is None:
+            self._check(self.L.nrrs_debug_set_norm_factors(self.h, None, 0))
+            return
+        f = _c(F, np.float64)
+        self._check(self.L.nrrs_debug_set_norm_factors(self.h, _p(f), f.size))
+
     def debug_load_records(self, feat, lum_t, acc):
         f = _c(feat, np.float32).reshape(-1, 20)
         lt, ac = _c(lum_t, np.float32), _c(acc, np.float32)
@@ -416,6 +431,17 @@ class Renderer:
         y, z = np.zeros(n, np.float32), np.zeros(n, np.float32)
         self._check(self.L.nrrs_debug_mlp_forward(self.h, _p(x), n, precision, _p(y), _p(z)))
         return y, z
+
+    def debug_mlp_codes(self, x, precision):
+        """Matrix-core forward with the bit patterns of every quantized operand: y [n], codes
+        [n, 3, 64] (uint16) and FP8 block-scale exponents [n, 3]."""
+        xx = _c(x, np.float32).reshape(-1, 20)
+        n = xx.shape[0]
+        y = np.zeros(max(n, 1), np.float32)
+        codes = np.zeros((max(n, 1), 3, 64), np.uint16)
+        se = np.zeros((max(n, 1), 3), np.int8)
+        self._check(self.L.nrrs_debug_mlp_codes(self.h, _p(xx), n, precision, _p(y), _p(codes), _p(se)))
+        return y[:n], codes[:n], se[:n]
 
     def debug_mlp_grad(self, x, target):
         x = _c(x, np.float32).reshape(-1, 20)
