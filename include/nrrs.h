@@ -304,6 +304,42 @@ int32_t nrrs_debug_rrs_expand(nrrs_ctx* ctx, const float* q_orig, const uint32_t
                               uint32_t* X, uint32_t* offset, uint32_t* parent_of_child,
                               uint32_t* S, double* F, float* q_norm, uint32_t* retries);
 
+/* --- allocation-free variant of nrrs_debug_rrs_expand -------------------------------- */
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Computes what nrrs_debug_rrs_expand computes
+ * (normalization, stochastic rounding, overflow guard, exclusive scan and parent map of one
+ * depth, with the same kernels and the context's seed) on caller device arrays, queued on the
+ * context's stream.  Its partial sums, block counts, guard candidates and control words live
+ * in a fixed 320 KiB array of the library's own device memory, one per GPU, held until the
+ * process ends; neither this call nor its kernels allocate, and the context needs no bound
+ * workspace.
+ *   q_dev[n]          device: raw factors, finite and >= 0 (device data, not checked)
+ *   lineage_dev[2n]   device: lineage id (lo, hi) pairs keying the roulette uniforms
+ *   offset_dev[n]     device out: first child slot of each entry (X_i = offset[i+1] - offset[i],
+ *                     the last entry's X = S - offset[n-1])
+ *   parent_dev[cap]   device out, may be NULL: the parent of each of the S children
+ *   result_dev        device out: F, alpha after the guard, S, retries, overflow flag (1 when
+ *                     alpha fell below 1e-3 before the children fit; then S = 0)
+ * n and cap are limited to 2^31; depth 1..NRRS_MAX_DEPTH-1; alpha in (0, 1]; budget_base,
+ * f_rate and norm_mode as for nrrs_debug_rrs_expand (EINVAL otherwise, nothing queued).
+ * Asynchronous: returns once the work is queued.  Every call on a GPU uses that GPU's one
+ * array and keeps the last call's contents; each call first sets the control words it reads.
+ * Calls that overlap in time on one GPU (other streams or threads) race; calls in order on
+ * one stream do not. */
+typedef struct nrrs_expand_result {
+  double F;          /* normalization factor used */
+  double alpha;      /* adaptive rate after the guard */
+  uint32_t S;        /* children emitted */
+  uint32_t retries;  /* alpha reductions applied */
+  uint32_t overflow; /* 1: no reduction fit before alpha fell below 1e-3 */
+  uint32_t pad;
+} nrrs_expand_result;
+int32_t nrrs_rrs_expand_noalloc(nrrs_ctx* ctx, const float* q_dev, const uint32_t* lineage_dev, uint32_t n,
+                                uint32_t depth, double budget_base, double f_rate, double alpha, int32_t norm_mode,
+                                uint32_t cap, uint32_t* offset_dev, uint32_t* parent_dev,
+                                nrrs_expand_result* result_dev);
+
 /* Test entry point: normalization factors given by the caller.  With n > 0, renders in
  * HEURISTIC / NET mode use F[d-1] (host, finite, >= 0) at depth d = 1..n in place of the
  * factor of Eqs. (10)-(14) (the overflow guard then cannot lower it); renders deeper than

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <string>
@@ -1072,6 +1073,131 @@ int32_t nrrs_debug_rrs_expand(nrrs_ctx* c, const float* q_orig, const uint32_t* 
   if (q_norm)
     for (uint32_t i = 0; i < n; ++i) q_norm[i] = (float)(ctl[0].F * (double)q_orig[i]);
   if (of) return fail(c, NRRS_EOVERFLOW, "overflow guard found no alpha that fits");
+  return NRRS_OK;
+}
+
+// ------------------------------------------------- the entry point that allocates nothing
+// Its partial sums, block counts, guard candidates and control words live in one fixed
+// device array per GPU (the code object's own memory, held until the process ends) instead
+// of the workspace.  In host code `scratch` names a host-side stand-in: the array's device
+// address comes from hipGetSymbolAddress, looked up once per device and kept per device.
+namespace {
+
+constexpr uint64_t kNoallocScratchBytes = 320ull << 10;
+constexpr int kNoallocMaxDevices = 64;
+static __device__ __align__(256) uint8_t scratch[kNoallocScratchBytes];
+
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_dev[kNoallocMaxDevices] = {};
+
+struct NoallocScratch {
+  double* partial;
+  uint32_t *bsum, *boff, *gsum;
+  DepthCtl* ctl;
+  double* alpha;
+  uint32_t* overflow;
+  uint64_t bytes;
+};
+
+NoallocScratch noalloc_layout(uint8_t* base) {
+  Carve k{base};
+  NoallocScratch r;
+  r.partial = k.take<double>(kScanBlocks);
+  r.bsum = k.take<uint32_t>(kScanBlocks);
+  r.boff = k.take<uint32_t>(kScanBlocks);
+  r.gsum = k.take<uint32_t>((uint64_t)kScanBlocks * kGuardSteps);
+  r.ctl = k.take<DepthCtl>(NRRS_MAX_DEPTH + 2);
+  r.alpha = k.take<double>(1);
+  r.overflow = k.take<uint32_t>(1);
+  r.bytes = k.off;
+  return r;
+}
+
+// Device address of this device's scratch array (looked up on the first call on a device).
+int32_t noalloc_scratch(nrrs_ctx* c, uint8_t** out) {
+  int dev = -1;
+  HIPC(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoallocMaxDevices) return fail(c, NRRS_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(c, NRRS_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<uint8_t*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return NRRS_OK;
+}
+
+// Control words of the depth: entries n, nothing emitted yet; alpha and the overflow flag.
+__global__ void k_noalloc_begin(DepthCtl* ctl, uint32_t depth, uint32_t n, double* alpha_slot, double alpha,
+                                uint32_t* overflow) {
+  DepthCtl z{};
+  ctl[depth + 1] = z;
+  z.n = n;
+  ctl[depth] = z;
+  *alpha_slot = alpha;
+  *overflow = 0;
+}
+
+__global__ void k_noalloc_end(const DepthCtl* ctl, uint32_t depth, const double* alpha, const uint32_t* overflow,
+                              nrrs_expand_result* out) {
+  nrrs_expand_result r{};
+  r.F = ctl[depth].F;
+  r.alpha = *alpha;
+  r.S = ctl[depth].S;
+  r.retries = ctl[depth].retries;
+  r.overflow = *overflow;
+  *out = r;
+}
+
+}  // namespace
+
+int32_t nrrs_rrs_expand_noalloc(nrrs_ctx* c, const float* q_dev, const uint32_t* lineage_dev, uint32_t n,
+                                uint32_t depth, double budget_base, double f_rate, double alpha, int32_t norm_mode,
+                                uint32_t cap, uint32_t* offset_dev, uint32_t* parent_dev,
+                                nrrs_expand_result* result_dev) {
+  if (!c || !result_dev || (n && (!q_dev || !lineage_dev || !offset_dev))) return NRRS_EINVAL;
+  if (n > (1u << 31) || cap > (1u << 31))
+    return fail(c, NRRS_EINVAL, "rrs_expand_noalloc: n and cap are limited to 2^31 entries");
+  if (depth < 1 || depth >= NRRS_MAX_DEPTH || !(budget_base >= 0.0) || !std::isfinite(budget_base) ||
+      !(f_rate > 0.0) || !std::isfinite(f_rate) || !(alpha > 0.0 && alpha <= 1.0) ||
+      (norm_mode != NRRS_NORM_TWO_SIDED && norm_mode != NRRS_NORM_DOWNSCALE))
+    return fail(c, NRRS_EINVAL, "rrs_expand_noalloc: argument out of range");
+  const NoallocScratch need = noalloc_layout(nullptr);
+  if (need.bytes > kNoallocScratchBytes) return fail(c, NRRS_ENOMEM, "rrs_expand_noalloc: scratch array too small");
+  uint8_t* base = nullptr;
+  const int32_t rs = noalloc_scratch(c, &base);
+  if (rs != NRRS_OK) return rs;
+  const NoallocScratch sc = noalloc_layout(base);
+  hipStream_t s = c->stream;
+  RenderArgs a{};
+  a.q = const_cast<float*>(q_dev);
+  a.qin.id = reinterpret_cast<uint2*>(const_cast<uint32_t*>(lineage_dev));
+  a.offs = offset_dev;
+  a.partial = sc.partial;
+  a.bsum = sc.bsum;
+  a.boff = sc.boff;
+  a.gsum = sc.gsum;
+  a.ctl = sc.ctl;
+  a.alpha = sc.alpha;
+  a.overflow = sc.overflow;
+  a.key = make_uint2((uint32_t)c->cfg.seed, (uint32_t)(c->cfg.seed >> 32));
+  a.depth = depth;
+  a.max_depth = depth + 1;
+  a.mode = NRRS_MODE_HEURISTIC;
+  a.norm_mode = (uint32_t)norm_mode;
+  a.f_rate = f_rate;
+  a.budget_base = budget_base;
+  a.cap = cap;
+  a.dbg_parent = parent_dev;
+  hipLaunchKernelGGL(k_noalloc_begin, dim3(1), dim3(1), 0, s, sc.ctl, depth, n, sc.alpha, alpha, sc.overflow);
+  launch_sum_q(a, s);
+  launch_roulette(a, s);
+  if (parent_dev) launch_parents(a, s);
+  hipLaunchKernelGGL(k_noalloc_end, dim3(1), dim3(1), 0, s, sc.ctl, depth, sc.alpha, sc.overflow, result_dev);
+  HIPC(c, hipGetLastError());
   return NRRS_OK;
 }
 

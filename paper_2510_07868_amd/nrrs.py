@@ -31,7 +31,7 @@ EXPORTS = [
     "nrrs_set_pass_index", "nrrs_get_pass_index", "nrrs_get_tuning", "nrrs_set_tuning", "nrrs_autotune",
     "nrrs_train_step", "nrrs_read_image", "nrrs_reset_image", "nrrs_set_guide", "nrrs_get_guide",
     "nrrs_get_params", "nrrs_set_params", "nrrs_get_state", "nrrs_set_state", "nrrs_set_trace",
-    "nrrs_read_trace", "nrrs_read_records", "nrrs_debug_rrs_expand",
+    "nrrs_read_trace", "nrrs_read_records", "nrrs_debug_rrs_expand", "nrrs_rrs_expand_noalloc",
     "nrrs_debug_set_norm_factors", "nrrs_debug_load_records", "nrrs_debug_read_queue", "nrrs_debug_trace",
     "nrrs_debug_philox", "nrrs_debug_mlp_forward", "nrrs_debug_mlp_codes", "nrrs_debug_mlp_grad", "nrrs_status_string",
     "nrrs_last_error", "nrrs_destroy",
@@ -126,6 +126,7 @@ def load():
         "nrrs_read_trace": [P, P],
         "nrrs_read_records": [P, P, P, P, P, P, P, P],
         "nrrs_debug_rrs_expand": [P, P, P, P, U32, U32, D, D, P, I32, U32, P, P, P, P, P, P, P],
+        "nrrs_rrs_expand_noalloc": [P, P, P, U32, U32, D, D, D, I32, U32, P, P, P],
         "nrrs_debug_set_norm_factors": [P, P, U32],
         "nrrs_debug_load_records": [P, P, P, P, U32],
         "nrrs_debug_read_queue": [P, I32, U32, P, P, P, P],
@@ -388,6 +389,33 @@ class Renderer:
             self._check(code)
         return dict(status=int(code), X=X[:n], offset=off[:n], parent=par[: S.value].copy(), S=int(S.value),
                     F=float(F.value), q_norm=qn[:n], alpha=float(a.value), retries=int(r.value))
+
+    def rrs_expand_noalloc(self, q, lineage, offset, result, depth, budget_base, f_rate=1.0, alpha=1.0,
+                           norm_mode=NORM_TWO_SIDED, cap=None, parent=None):
+        """nrrs_rrs_expand_noalloc on torch tensors of this context's device: q float32 [n], lineage
+        int32 [n, 2] (lo, hi words), offset int32 [n] (out), result uint8 [32] (out), parent int32
+        [cap] (out) or None.  Queued on the context's stream; nothing is allocated."""
+        t = self.torch
+        n = int(q.numel())
+        assert q.dtype == t.float32 and lineage.dtype == t.int32 and offset.dtype == t.int32
+        assert result.dtype == t.uint8 and result.numel() >= 32
+        assert lineage.numel() == 2 * n and offset.numel() >= n
+        assert q.is_contiguous() and lineage.is_contiguous() and offset.is_contiguous() and result.is_contiguous()
+        cap = int(2 * budget_base) if cap is None else int(cap)
+        if parent is not None:
+            assert parent.dtype == t.int32 and parent.is_contiguous() and parent.numel() >= cap
+        ptr = lambda x: C.c_void_p(x.data_ptr())  # noqa: E731
+        self._check(self.L.nrrs_rrs_expand_noalloc(self.h, ptr(q), ptr(lineage), n, depth, float(budget_base),
+                                                   float(f_rate), float(alpha), norm_mode, cap, ptr(offset),
+                                                   None if parent is None else ptr(parent), ptr(result)))
+
+    @staticmethod
+    def decode_expand_result(result_bytes):
+        """The nrrs_expand_result fields of 32 bytes copied to the host."""
+        b = np.asarray(result_bytes, np.uint8)[:32].tobytes()
+        F, alpha = np.frombuffer(b[:16], np.float64)
+        S, retries, overflow, _ = np.frombuffer(b[16:], np.uint32)
+        return dict(F=float(F), alpha=float(alpha), S=int(S), retries=int(retries), overflow=int(overflow))
 
     def debug_set_norm_factors(self, F=None):
         """Normalization factor per depth (F[d-1] at depth d) used instead of the computed one;
