@@ -26,7 +26,7 @@ def build(force: bool = True) -> str:
         tmp = LIB_PATH + ".tmp"
         subprocess.run(
             ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
-             "-Wall", "-o", tmp, os.path.join(_HERE, "oracle.c"), "-lm"],
+             "-Wall", "-o", tmp, os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "nrrs_train.c"), "-lm"],
             check=True)
         os.replace(tmp, LIB_PATH)
     return LIB_PATH

@@ -161,6 +161,42 @@ int32_t or_ggx_sample(double alpha, double f0, const double wo[3], double u1, do
 double or_ggx_eval_cos(double alpha, double f0, const double wo[3], const double wi[3]);
 void or_lambert_sample(double u1, double u2, double wi[3], double* pdf);
 
+/* ------------------------------------------------ NRRS training proper (nrrs_train.c)
+ * StatNet and the NRRS variant of RRSNet (Sec. 4.2.1), their losses (Sec. 4.2.2, Eqs. 15-21)
+ * and encodings (Sec. 5).  Records: raw[7] = position in the scene box scaled to [0, 1]^3,
+ * unit outgoing direction w_o (world), remapped roughness 1 - exp(-alpha). */
+#define OR_HG_LEVELS 8
+#define OR_HG_FEAT 2
+#define OR_HG_BASE 16
+#define OR_STAT_RAW 7
+#define OR_STAT_IN 32   /* 16 hash grid + 8 one-blob direction + 8 one-blob roughness */
+#define OR_STAT_OUT 2   /* luminance mean and variance of the reflected radiance */
+#define OR_RRS_IN 7     /* Box-Cox of m, E[L^2], t (RGB), I; remapped roughness */
+void or_oneblob(double s, int32_t bins, double* out);
+void or_hashgrid_encode(const double* table, uint32_t log2T, const double* p, double* out);
+void or_hashgrid_backward(uint32_t log2T, const double* p, const double* dout, double* dtable);
+double or_hashgrid_cell_margin(const double* p);
+void or_statnet_encode(const double* table, uint32_t log2T, const double* raw, double* enc);
+uint64_t or_mlp32_nparams(int32_t in, int32_t out);
+void or_mlp32_forward(const double* P, int32_t in, int32_t out, const double* x, double* y);
+void or_mlp32_backward(const double* P, int32_t in, int32_t out, const double* x, const double* dy, double* dP,
+                       double* dx);
+void or_statnet_forward(const double* P, const double* table, uint32_t log2T, const double* raw, double* mv);
+double or_statnet_loss_grad(const double* P, const double* table, uint32_t log2T, const double* raw,
+                            const double* target, uint64_t n, double eps, double* dP, double* dtable);
+void or_rrs_inputs(const double* mv, const double* t, double I, double rho, double* x);
+double or_nrrs_factor(const double* Ps, const double* Pr, const double* table, uint32_t log2T, const double* raw,
+                      const double* t, double I, double* mv_out, double* z_out);
+double or_nrrs_dloss_dq(double wpx, uint32_t k, double lum_t, const double* mv, double q_norm, double F,
+                        double q_nrrs, double g_rrs);
+double or_nrrs_pixel_weights(const double* cur, double* acc, const double* ref, uint32_t w, uint32_t h,
+                             int32_t first, double a_mix, int32_t radius, double var_scale, double g_avg,
+                             double g_min, double eps, double* E, double* wpx);
+double or_rrsnet_nrrs_grad(const double* Pr, const double* Ps, const double* table, uint32_t log2T,
+                           const double* raw, const double* t_rgb, const double* I_px, const double* lum_t,
+                           const double* q_norm, const double* F, const uint32_t* pix, const uint32_t* k_pix,
+                           const double* wpx, uint64_t n, int32_t step, double g_rrs, double eps, double* dPr);
+
 #ifdef __cplusplus
 }
 #endif
