@@ -701,7 +701,7 @@ static double fp8_dot_error_bound(const double* w, const double* x, int n) {
 
 /* Bit patterns of values already on the E4M3 / BF16 grids (the codes the matrix cores read). */
 static uint16_t e4m3_bits(double v) {
-  uint16_t sign = v < 0.0 ? 0x80 : 0;
+  uint16_t sign = signbit(v) ? 0x80 : 0; /* a negative value rounded to zero keeps its sign */
   double a = fabs(v);
   if (a == 0.0) return sign;
   int e;
@@ -778,17 +778,29 @@ void or_mlp_forward_quant_codes(const double* params, const double* x, uint64_t 
     for (int L = 0; L < 3; ++L) {
       const double* Wl = Wq + woff[L];
       const double* bl = params + (L == 0 ? B1 : (L == 1 ? B2 : B3));
+      int relu_near[64];
       for (int o = 0; o < 64; ++o) {
-        double acc = 0.0;
-        for (int i = 0; i < kin; ++i) acc += Wl[kin * o + i] * in[i];
+        double acc = 0.0, mag = 0.0;
+        for (int i = 0; i < kin; ++i) {
+          acc += Wl[kin * o + i] * in[i];
+          mag += fabs(Wl[kin * o + i] * in[i]);
+        }
         out[o] = acc * wscale[L] + bl[o];
         err[o] = prec == 2 ? fp8_dot_error_bound(Wl + kin * o, code, kin) * wscale[L] * bs_in : 0.0;
+        /* the ReLU decision max(pre, 0) is a near-tie when the exact pre-activation lies within
+         * the float32 error of zero: BF16 products are exact in float32, so the bound is that of
+         * summing kin products and the bias in any order (gamma_{kin+1} of the magnitudes); FP8
+         * adds the rounding of the scale-and-bias step to its dot-product bound */
+        const double u = ldexp(1.0, -24), g = (kin + 1) * u / (1.0 - (kin + 1) * u);
+        const double eb = prec == 2 ? err[o] + 2.0 * u * (fabs(acc * wscale[L]) + fabs(bl[o]))
+                                    : g * (mag * wscale[L] + fabs(bl[o]));
+        relu_near[o] = eb > 0.0 && fabs(out[o]) <= eb; /* all-zero terms sum to exactly 0 anywhere */
       }
-      for (int o = 0; o < 64; ++o) out[o] = fmax(out[o], 0.0);
+      for (int o = 0; o < 64; ++o) out[o] = out[o] > 0.0 ? out[o] : 0.0;
       if (L < 2) {
         if (prec == 1) {
           for (int o = 0; o < 64; ++o) {
-            const int na = out[o] > 0.0 && midpoint_gap_bf16(out[o]) < gap;
+            const int na = (out[o] > 0.0 && midpoint_gap_bf16(out[o]) < gap) || relu_near[o];
             if (na) near = 1;
             in[o] = or_round_bf16(out[o]);
             if (cr) cr[64 * (L + 1) + o] = bf16_bits(in[o]);
@@ -812,7 +824,8 @@ void or_mlp_forward_quant_codes(const double* params, const double* x, uint64_t 
             if (ratio - ldexp(1.0, e - 1) <= tol || ldexp(1.0, e) - ratio <= tol) scale_near = near = 1;
           }
           for (int o = 0; o < 64; ++o) {
-            const int na = out[o] > 0.0 && midpoint_dist_e4m3(out[o] / bs) * bs <= err[o] + 1e-6 * out[o];
+            const int na = (out[o] > 0.0 && midpoint_dist_e4m3(out[o] / bs) * bs <= err[o] + 1e-6 * out[o]) ||
+                           relu_near[o];
             if (na) near = 1;
             code[o] = or_round_e4m3(out[o] / bs);
             in[o] = code[o] * bs;

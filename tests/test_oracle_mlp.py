@@ -265,3 +265,38 @@ def test_fp8_dot_error_bound_closed_forms(O):
     assert O.fp8_dot_error_bound(w, np.zeros(3)) == 0.0
     # signs do not matter
     assert O.fp8_dot_error_bound(-w, x3) == O.fp8_dot_error_bound(w, x3)
+
+
+def test_relu_decision_within_the_float32_error_of_zero_is_a_near_tie(O):
+    # layer 1: pre = 1 * 1 + b1.  The float32 sum of the product and the bias may land on either
+    # side of 0 when the exact value lies within the summation bound (21 terms' gamma of the
+    # magnitudes, ~2.5e-6 here); an exact 0 from all-zero terms is no tie
+    assert _flag(O, _one_unit_net(w1=1.0, b1=-1.0), 1.0, 1)                 # exactly 0
+    assert _flag(O, _one_unit_net(w1=1.0, b1=-1.0 - 1e-7), 1.0, 1)         # just below
+    assert _flag(O, _one_unit_net(w1=1.0, b1=-1.0 + 1e-7), 1.0, 1)         # just above
+    assert not _flag(O, _one_unit_net(w1=1.0, b1=-1.0 - 1e-4), 1.0, 1)     # clearly negative
+    assert not _flag(O, _one_unit_net(w1=1.0, b1=-1.0 + 2.0 ** -10), 1.0, 1)  # clearly positive, on the grid
+    # the flag is per activation: the codes call marks unit 0 of layer 1 (index 64 + 0) only
+    P = _one_unit_net(w1=1.0, b1=-1.0)
+    x = np.zeros((1, 20))
+    x[0, 0] = 1.0
+    _, _, near, codes, near_act, _ = O.mlp_forward_quant_codes(P, x, 1)
+    assert near[0] and near_act[0, 1, 0] and near_act[0, 1, 1:].sum() == 0 and near_act[0, 0].sum() == 0
+    # FP8: the same decision against the FP8 dot-product bound (layer-1 out = 0.875 + b1 exactly,
+    # as in the midpoint test above)
+    w1 = 448.0 * 2.0 ** -9
+    assert _flag(O, _one_unit_net(w1=w1, b1=-0.875), 1.0, 2)                # exactly 0
+    assert not _flag(O, _one_unit_net(w1=w1, b1=-0.885), 1.0, 2)            # 0.01 below: far
+
+
+def test_e4m3_code_of_a_negative_value_rounded_to_zero_keeps_the_sign(O):
+    # x0 = 1 sets the input block scale 2^-8; x1 = -2^-20 scales to -2^-12, below half the
+    # smallest subnormal (2^-10): it rounds to zero and keeps its sign (code 0x80); +0 is 0x00
+    P = _one_unit_net(w1=1.0)
+    x = np.zeros((1, 20))
+    x[0, 0] = 1.0
+    x[0, 1] = -(2.0 ** -20)
+    _, _, _, codes, _, se = O.mlp_forward_quant_codes(P, x, 2)
+    assert se[0, 0] == -8
+    assert codes[0, 0, 1] == 0x80 and codes[0, 0, 2] == 0x00
+    assert codes[0, 0, 0] == 0x78  # 1 / 2^-8 = 256 = 1.0 x 2^8: exponent 8 + 7 = 15, mantissa 0
