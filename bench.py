@@ -107,6 +107,9 @@ def main():
     ap.add_argument("--no-room", action="store_true", help="skip the 1024^2 room online-training study")
     ap.add_argument("--no-batched", action="store_true", help="skip the 1920x1080 5 M-triangle batched render")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-nrrs", action="store_true", help="skip the NRRS-proper (StatNet + RRSNet) study")
+    ap.add_argument("--nrrs-frames", type=int, default=120,
+                    help="online-training frames of the NRRS-proper study (the first third in step 1)")
     ap.add_argument("--tuning", default=None,
                     help="traversal launch 'variant,blocks_per_cu,refill,leaf_batch,chunk' instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -300,11 +303,23 @@ def main():
             img, _ = rr.read_image()
             rr.close()
             return img
-        out["efficiency"] = efficiency(r, nrrs, spp, D, args.ref_spp, args.eval_renders, make_reference)
+        refs = {}
+
+        def reference_once(ref_spp):
+            if ref_spp not in refs:
+                refs[ref_spp] = make_reference(ref_spp)
+            return refs[ref_spp]
+        out["efficiency"] = efficiency(r, nrrs, spp, D, args.ref_spp, args.eval_renders, reference_once)
         out["efficiency"]["trained_frames"] = args.train_frames
     r.close()
     del r
     torch.cuda.empty_cache()
+    if not args.no_eff and not args.no_nrrs:
+        out["nrrs_proper"] = nrrs_proper_study(nrrs, sc, torch, W, H, spp, D, args.nrrs_frames, args.eval_renders,
+                                               reference_once(args.ref_spp), p_train, tuning)
+        out["nrrs_proper"]["over_heuristic_in_the_efficiency_study"] = (
+            out["nrrs_proper"]["nrrs"]["efficiency"] / out["efficiency"]["heuristic"]["efficiency"])
+        torch.cuda.empty_cache()
     if not args.no_room:
         out["room_online_training"] = room_study(nrrs, scenes, torch)
     if not args.no_batched:
@@ -370,6 +385,70 @@ def efficiency(r, nrrs, spp, D, ref_spp, renders, make_reference):
                         "network_depths": [d + 1 for d, m in enumerate(table) if m == mixdepth.NET],
                         "fixed_rate_depths": [d + 1 for d, m in enumerate(table) if m == mixdepth.FIXED]}
     return out
+
+
+def nrrs_proper_study(nrrs, sc, torch, W, H, spp, D, frames, renders, ref, p_train, tuning):
+    """NRRS proper (Sec. 4.2): StatNet + RRSNet factors at depths 1-4, trained online for
+    `frames` frames (render + one train_step_nrrs each; RRSNet fitted to 1 for the first third,
+    then by the pixel-variance loss of Eq. 16), then relMSE and 1/(relMSE * t) at equal spp
+    against heuristic normalized RRS on the same context, guide and reference."""
+    rec_n = 1 << 18
+    r = nrrs.Renderer(W, H, s_batch=spp, cap_factor=2.0, seed=0, net_max_depth=4, records_cap=rec_n,
+                      p_train=p_train, max_tris=sc.n_tris, max_materials=len(sc.mat_type), ema_decay=0.99,
+                      hash_log2=19)
+    r.upload_scene(sc)
+    if tuning:
+        r.set_tuning(tuning["extend_variant"], tuning["extend_blocks_per_cu"], tuning["extend_refill"],
+                     tuning["extend_leaf_batch"], tuning["extend_chunk"])
+    step1 = max(1, frames // 3)
+    hist = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_train = 0.0
+    for f in range(frames):
+        st = r.render(spp, D, nrrs.MODE_NRRS)
+        n = min(st["records"], rec_n)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lo = r.train_step_nrrs(n, 1 if f < step1 else 2)
+        torch.cuda.synchronize()
+        t_train += time.perf_counter() - t1
+        if f % 20 == 0 or f == frames - 1:
+            print(f"# nrrs frame {f}: records {n}, StatNet loss {lo['loss_stat']:.4f}, "
+                  f"RRSNet loss {lo['loss_rrs']:.4g}, E_avg {lo['e_avg']:.4g}", flush=True)
+            hist.append({"frame": f, "loss_stat": lo["loss_stat"], "loss_rrs": lo["loss_rrs"], "e_avg": lo["e_avg"]})
+    t_frames = time.perf_counter() - t0
+    guide = r.get_guide()
+    res = {}
+    for name, mode in (("nrrs", nrrs.MODE_NRRS), ("heuristic", nrrs.MODE_HEURISTIC)):
+        times, errs = [], []
+        for k in range(renders):
+            r.set_guide(guide)
+            r.reset_image()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r.render(spp, D, mode, stats=False)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            img, _ = r.read_image()
+            errs.append(relmse(img, ref))
+        rm, t = float(np.mean(errs)), float(np.median(times))
+        res[name] = {"relmse": rm, "relmse_se": float(np.std(errs) / np.sqrt(len(errs))), "render_s": round(t, 5),
+                     "efficiency": 1.0 / (rm * t)}
+    # per-stage time of an NRRS render (the factor kernel is the network stage)
+    r.set_timing(True)
+    r.set_guide(guide)
+    st = r.render(spp, D, nrrs.MODE_NRRS)
+    r.set_timing(False)
+    r.close()
+    return {"method": "StatNet (hash grid 8 x 2, 2^19 entries per level) + RRSNet (NRRS inputs), 32-wide "
+                      "3-hidden-layer MLPs, FP32; one Adam step per frame (lr 5e-3 / 3e-4), gammas 0.01 / "
+                      "0.05 / 0.01, error image mixed 0.5 and box-filtered (radius 2)",
+            "frames": frames, "step1_frames": step1, "train_s": round(t_frames, 2),
+            "train_step_ms": round(1e3 * t_train / frames, 3), "history": hist,
+            "nrrs": res["nrrs"], "heuristic": res["heuristic"],
+            "nrrs_over_heuristic": res["nrrs"]["efficiency"] / res["heuristic"]["efficiency"],
+            "stage_ms": {k: round(v, 3) for k, v in st["stage_ms"].items()}}
 
 
 def _timed_render(r, torch, spp, D, mode, train=None):

@@ -47,8 +47,10 @@ enum nrrs_status {
 enum nrrs_mode {
   NRRS_MODE_OFF = 0,       /* plain path tracing: factor 1, no normalization */
   NRRS_MODE_HEURISTIC = 1, /* normalized RRS with q = lum(throughput * albedo) */
-  NRRS_MODE_NET = 2        /* normalized RRS with the network factor at the depths of the Mix-Depth
+  NRRS_MODE_NET = 2,       /* normalized RRS with the network factor at the depths of the Mix-Depth
                               table (nrrs_set_mix_depth; default: depth <= net_max_depth) */
+  NRRS_MODE_NRRS = 3       /* normalized RRS with the NRRS factor (StatNet + RRSNet, Sec. 4.2) at the
+                              depths of the Mix-Depth table; needs hash_log2 > 0 at creation */
 };
 
 enum nrrs_norm { NRRS_NORM_TWO_SIDED = 0, NRRS_NORM_DOWNSCALE = 1 };
@@ -84,6 +86,9 @@ typedef struct {
   uint32_t trace_depth;   /* > 0: reserve workspace for nrrs_set_trace (per-path radiance of
                              depths 1..trace_depth: 8 B per queue slot + 24 * trace_depth B per
                              primary path); 0: not available */
+  uint32_t hash_log2;     /* > 0 (14..22): reserve NRRS proper (Sec. 4.2): StatNet's hash grid of
+                             2^hash_log2 entries per level, StatNet, RRSNet and their training
+                             state (about 80 * 2^hash_log2 B); 0: not available */
 } nrrs_config;
 
 typedef struct {
@@ -190,6 +195,76 @@ int32_t nrrs_set_params(nrrs_ctx* ctx, const float* master, const float* adam_m,
  * BF16 / FP8 inference copies.  EINVAL for a non-finite weight or alpha outside (0, 1]. */
 int32_t nrrs_get_state(nrrs_ctx* ctx, float* infer, double* alpha);
 int32_t nrrs_set_state(nrrs_ctx* ctx, const float* infer, const double* alpha);
+
+/* --- NRRS proper (Sec. 4.2; Sec. 5 "Network Architecture", "Input Encoding", "Training") ------
+ * Needs a context created with hash_log2 > 0 (ESTATE otherwise).
+ * StatNet: hash grid of the vertex position (8 levels x 2 features, coarsest resolution 16,
+ * doubling per level; dense where a level's corners fit the 2^hash_log2 entries, else the
+ * spatial hash) + one-blob w_o (theta / pi and phi / 2pi + 1/2, 4 bins each) + one-blob remapped
+ * roughness (8 bins) -> 32 -> 32 -> 32 -> 2 (leaky ReLU 0.01): the luminance mean m and variance
+ * v of the radiance reflected at the vertex.  RRSNet: Box-Cox (lambda 1/2) of m, v + m^2, the
+ * throughput (rgb) and the pixel value, and the remapped roughness -> 32 -> 32 -> 32 -> 1,
+ * modified softplus (Eq. 22): the RRS factor.  Parameter vectors: W1[32][in], b1[32], W2[32][32],
+ * b2, W3[32][32], b3, W4[out][32], b4 (NRRS_STAT_NPARAM, NRRS_RRS_NPARAM floats); hash grid
+ * [8][2^hash_log2][2] floats.  Renders in NRRS_MODE_NRRS use the inference copies (the moving
+ * average of the masters with cfg.ema_decay per Adam step). */
+#define NRRS_STAT_NPARAM 3234
+#define NRRS_RRS_NPARAM 2401
+
+/* Set (masters and inference copies; Adam moments and step cleared) or get (masters) the NRRS
+ * networks from host arrays; any pointer may be NULL to skip that part.  set: EINVAL for a
+ * non-finite value. */
+int32_t nrrs_set_nrrs_params(nrrs_ctx* ctx, const float* stat, const float* rrs, const float* table);
+int32_t nrrs_get_nrrs_params(nrrs_ctx* ctx, float* stat, float* rrs, float* table);
+
+typedef struct {
+  float lr_stat, lr_rrs;      /* Adam learning rates (the paper's 0.005 and 0.0003) */
+  float g_avg, g_min, g_rrs;  /* gamma1 (L_avg), gamma2 (L_min), gamma3 (L_rrs) of Eq. (16) */
+  float a_mix;                /* temporal mix of the error image, Eq. (23), in (0, 1] */
+  int32_t radius;             /* box-filter radius (pixels, 0..8) of the error image, in place of
+                                 the paper's denoiser */
+  int32_t rrs_step;           /* 1: RRSNet fitted to the output 1; 2: trained by Eq. (16) */
+} nrrs_nrrs_train;
+
+typedef struct {
+  float loss_stat;  /* Eq. (15), mean over the records */
+  float loss_rrs;   /* step 1: relative L2 to 1 (mean); step 2: gamma3 L_rrs (sum) */
+  double e_avg;     /* mean relative pixel error E_avg of the frame (Eq. 20) */
+  uint32_t records; /* records used */
+  uint32_t rrs_trained;  /* 0 when step 2 had no previous frame to compare with */
+} nrrs_nrrs_loss;
+
+/* One NRRS training step over the records of the frame rendered since the previous call (or
+ * since the image was reset): one Adam step of StatNet (Eq. 15; hash grid and MLP) over all
+ * of them, then one of RRSNet with StatNet's updated weights.  Step 2 also forms the frame's
+ * pixel error: the frame's luminance per pixel against the mean of the previous frames, mixed
+ * over frames (Eq. 23), box-filtered, and turned into the derivative of gamma1 L_avg +
+ * gamma2 L_min with respect to each pixel's variance, which reaches each record's factor through
+ * Eqs. (17)-(18) (shared by the pixel's records).  The error image is taken at the variance of a
+ * one-sample pixel estimate: the squared error scaled by the frame's samples per pixel (and by
+ * (2 - a) / a once mixed).  n_records: how many of the captured records to use (<= the count
+ * captured, <= records_cap).  Synchronous when out != NULL. */
+int32_t nrrs_train_step_nrrs(nrrs_ctx* ctx, uint32_t n_records, const nrrs_nrrs_train* hp, nrrs_nrrs_loss* out);
+
+/* Test entry points (host arrays, synchronous).
+ * nrrs_debug_nrrs_forward: StatNet (m, v) into mv[2n], the factor into q[n] and, if enc is
+ * not NULL, StatNet's 32 inputs into enc[32n], for vertices raw[7n] = (position in [0,1]^3,
+ * w_o, remapped roughness), throughput t[3n] and pixel value I[n], with the inference copies.
+ * nrrs_debug_nrrs_grads: the gradients (no Adam step) of StatNet (Eq. 15, mean over n; MLP
+ * into g_stat, hash grid into g_table) and of RRSNet (rrs_step 1 or 2) for records given as
+ * raw[7n], I[n], StatNet target L[n], lum_t[n], t[3n], q_norm[n], F[n], pix[n] and per-pixel
+ * wpx[npx], k[npx] (pix < npx), with the masters; losses as in nrrs_nrrs_loss.
+ * nrrs_debug_pixel_error: the pixel-error stage on host images cur, ref (< 0: no reference)
+ * and acc (in/out) of w x h pixels: E[w h], wpx[w h] and *e_avg. */
+int32_t nrrs_debug_nrrs_forward(nrrs_ctx* ctx, const float* raw, const float* t, const float* I, uint32_t n,
+                                float* mv, float* q, float* enc);
+int32_t nrrs_debug_nrrs_grads(nrrs_ctx* ctx, const float* raw, const float* I, const float* L, const float* lum_t,
+                              const float* t, const float* q_norm, const float* F, const uint32_t* pix, uint32_t n,
+                              const float* wpx, const uint32_t* k, uint32_t npx, int32_t rrs_step, float g_rrs,
+                              float* g_stat, float* g_rrs_out, float* g_table, float* loss_stat, float* loss_rrs);
+int32_t nrrs_debug_pixel_error(nrrs_ctx* ctx, const float* cur, float* acc, const float* ref, uint32_t w, uint32_t h,
+                               int32_t first, float a_mix, int32_t radius, float var_scale, float g_avg, float g_min,
+                               float* E, float* wpx, double* e_avg);
 
 /* Per-path radiance by depth (a parity aid for the one-sample estimator of Sec. 3,
  * Eqs. (1)-(2)): while enabled, every emission collected at vertex depth d is also added

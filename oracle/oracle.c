@@ -779,6 +779,7 @@ void or_mlp_forward_quant_codes(const double* params, const double* x, uint64_t 
       const double* Wl = Wq + woff[L];
       const double* bl = params + (L == 0 ? B1 : (L == 1 ? B2 : B3));
       int relu_near[64];
+      double ebv[64];
       for (int o = 0; o < 64; ++o) {
         double acc = 0.0, mag = 0.0;
         for (int i = 0; i < kin; ++i) {
@@ -795,16 +796,26 @@ void or_mlp_forward_quant_codes(const double* params, const double* x, uint64_t 
         const double eb = prec == 2 ? err[o] + 2.0 * u * (fabs(acc * wscale[L]) + fabs(bl[o]))
                                     : g * (mag * wscale[L] + fabs(bl[o]));
         relu_near[o] = eb > 0.0 && fabs(out[o]) <= eb; /* all-zero terms sum to exactly 0 anywhere */
+        ebv[o] = eb;
       }
       for (int o = 0; o < 64; ++o) out[o] = out[o] > 0.0 ? out[o] : 0.0;
       if (L < 2) {
         if (prec == 1) {
           for (int o = 0; o < 64; ++o) {
-            const int na = (out[o] > 0.0 && midpoint_gap_bf16(out[o]) < gap) || relu_near[o];
+            /* row flag (output comparisons, which have their own tolerance): a rounding within
+             * 2e-4 grid steps of its midpoint, or a ReLU near-tie.  Activation flag (code-by-code
+             * comparisons, which are exact): also a midpoint within the float32 summation bound
+             * of the exact value, which matters where the terms cancel (a small activation from
+             * large products) */
+            const double mg = midpoint_gap_bf16(out[o]);
+            const int na = (out[o] > 0.0 && mg < gap) || relu_near[o];
+            int e2;
+            frexp(out[o], &e2);
+            const int na_act = na || (out[o] > 0.0 && mg * ldexp(1.0, e2 - 8) <= ebv[o]);
             if (na) near = 1;
             in[o] = or_round_bf16(out[o]);
             if (cr) cr[64 * (L + 1) + o] = bf16_bits(in[o]);
-            if (nr) nr[64 * (L + 1) + o] = (uint8_t)na;
+            if (nr) nr[64 * (L + 1) + o] = (uint8_t)na_act;
           }
         } else {
           /* one power-of-two scale for the vertex's 64 activations */
@@ -1041,6 +1052,8 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
   int fixed = cfg->mode != OR_MODE_OFF && depth <= 64 && ((cfg->fixed_depths >> (depth - 1)) & 1u);
   int net = !fixed && cfg->mode == OR_MODE_NET && depth <= 64 && ((cfg->net_depths >> (depth - 1)) & 1u) &&
             c->params != NULL;
+  int nrrs = !fixed && cfg->mode == OR_MODE_NRRS && depth <= 64 && ((cfg->net_depths >> (depth - 1)) & 1u) &&
+             c->params != NULL && cfg->hash_log2 > 0;
   for (uint64_t i = 0; i < n; ++i) {
     entry* e = &Q[i];
     vstate* v = &V[i];
@@ -1123,6 +1136,52 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
       v->q = fmin(fmax(qr, 0.125 * v->q), 64.0 * v->q);
       /* the inputs carry the hit point's error (the sine encoding scales it by 16 pi / extent) */
       v->kq += 64.0 * v->perr / s->extent;
+    }
+  }
+  if (nrrs) {
+    /* NRRS (Sec. 4.2): StatNet's statistics of the vertex, then RRSNet's factor, with the pixel's
+     * previous mean as I_px; no pixel history keeps the heuristic */
+    const double* Ps = c->params;
+    const double* Pr = Ps + OR_STAT_NPARAM;
+    const double* Tb = Pr + OR_RRS_NPARAM;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < (int64_t)n; ++i) {
+      entry* e = &Q[i];
+      vstate* v = &V[i];
+      if (e->dead || v->q <= 0.0 || v->prim == MISS) continue;
+      double g = c->guide ? c->guide[e->pix] : -1.0;
+      if (!(g >= 0.0)) continue;
+      const double* mp = s->mpar + 7 * (uint64_t)v->mat;
+      double raw[7];
+      for (int k = 0; k < 3; ++k) raw[k] = (v->p[k] - s->amin[k]) / s->extent;
+      for (int k = 0; k < 3; ++k) raw[3 + k] = v->wo[k];
+      raw[6] = 1.0 - exp(-(s->mtype[v->mat] == 1 ? mp[3] : 1.0));
+      const double q = or_nrrs_factor(Ps, Pr, Tb, cfg->hash_log2, raw, e->t, g, NULL, NULL);
+      if (!(q >= 1e-20 && q < 3e38)) continue; /* a factor out of range keeps the heuristic */
+      /* float32 error of the factor from its inputs' errors: the change of q when the position
+       * moves by twice its error bound, the direction by twice its bound, the throughput by
+       * twice its relative bound (central differences, summed: about four times the linear
+       * estimate) */
+      double dq = 0.0;
+      for (int k = 0; k < 6; ++k) {
+        const double h = k < 3 ? 2.0 * v->perr / s->extent : 2.0 * e->derr;
+        double rp[7], rm[7];
+        memcpy(rp, raw, sizeof(rp));
+        memcpy(rm, raw, sizeof(rm));
+        rp[k] += h;
+        rm[k] -= h;
+        dq += fabs(or_nrrs_factor(Ps, Pr, Tb, cfg->hash_log2, rp, e->t, g, NULL, NULL) -
+                   or_nrrs_factor(Ps, Pr, Tb, cfg->hash_log2, rm, e->t, g, NULL, NULL));
+      }
+      double tp[3], tm[3];
+      for (int k = 0; k < 3; ++k) {
+        tp[k] = e->t[k] * (1.0 + 2.0 * e->kerr);
+        tm[k] = e->t[k] * (1.0 - 2.0 * e->kerr);
+      }
+      dq += fabs(or_nrrs_factor(Ps, Pr, Tb, cfg->hash_log2, raw, tp, g, NULL, NULL) -
+                 or_nrrs_factor(Ps, Pr, Tb, cfg->hash_log2, raw, tm, g, NULL, NULL));
+      v->q = q;
+      v->kq += dq / q;
     }
   }
   (void)pass;

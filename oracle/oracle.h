@@ -26,10 +26,12 @@ extern "C" {
 #endif
 
 #define OR_NPARAM 9729   /* 20-64-64-64-1 MLP */
+#define OR_STAT_NPARAM 3234 /* StatNet: 32 -> 32 -> 32 -> 32 -> 2 */
+#define OR_RRS_NPARAM 2401  /* RRSNet (NRRS): 7 -> 32 -> 32 -> 32 -> 1 */
 #define OR_NFEAT 20
 #define OR_MAXD 64
 
-enum { OR_MODE_OFF = 0, OR_MODE_HEUR = 1, OR_MODE_NET = 2 };
+enum { OR_MODE_OFF = 0, OR_MODE_HEUR = 1, OR_MODE_NET = 2, OR_MODE_NRRS = 3 };
 enum { OR_NORM_TWO_SIDED = 0, OR_NORM_DOWNSCALE = 1 };
 
 typedef struct or_scene or_scene;
@@ -49,6 +51,9 @@ typedef struct {
                             when bit d-1 is set and keeps the heuristic factor at the other depths */
   uint64_t fixed_depths; /* Mix-Depth's fixed rate: at depth d with bit d-1 set every vertex that
                             continues gets the raw factor 1 (HEUR and NET modes; before the network) */
+  uint32_t hash_log2;    /* NRRS mode (Sec. 4.2): params = StatNet (OR_STAT_NPARAM), RRSNet
+                            (OR_RRS_NPARAM) and the hash grid [8][2^hash_log2][2], concatenated; the
+                            NRRS factor replaces the heuristic at the depths of net_depths */
 } or_cfg;
 
 typedef struct {

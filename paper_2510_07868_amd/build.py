@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnrrs.so")
-SOURCES = ["wavefront.hip", "mlp.hip", "mlp_mfma.hip", "mlp_train.hip", "mix_depth.hip", "capi.cpp", "bvh.cpp"]
+SOURCES = ["wavefront.hip", "mlp.hip", "mlp_mfma.hip", "mlp_train.hip", "mix_depth.hip", "nrrs_net.hip", "capi.cpp",
+           "bvh.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-atomics",
           # keep packed-FP32 instructions out of the generated code

@@ -83,6 +83,18 @@ struct nrrs_ctx {
   uint8_t* fp8 = nullptr;
   float* fp8_scale = nullptr;
   float *grad_partial = nullptr, *loss_partial = nullptr, *loss_accum = nullptr;
+  // NRRS proper (reserved when cfg.hash_log2 > 0): StatNet, RRSNet and the hash grid, each as
+  // master, inference copy, Adam moments and gradient; gradient partials; per-pixel error state
+  struct NetState {
+    float *w = nullptr, *infer = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+  };
+  NetState nstat{}, nrrs_net{}, ntab{};
+  uint64_t ntab_n = 0;  // floats of the hash grid
+  float *npartial = nullptr, *nloss_part = nullptr, *nloss = nullptr;
+  double *lum_start = nullptr, *pix_part = nullptr, *eavg = nullptr;
+  float *pcur = nullptr, *pref = nullptr, *pacc = nullptr, *pEp = nullptr, *pE = nullptr, *pwpx = nullptr;
+  uint32_t* kpix = nullptr;
+  uint64_t nrrs_step = 0, nrrs_rstep = 0, nrrs_frames = 0, nrrs_spp_start = 0;
   // scene
   bool bound = false, scene = false;
   DevScene sc{};
@@ -189,6 +201,40 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
   c->grad_partial = k.take<float>(mlp_grad_scratch_floats(kMaxMinibatch));
   c->loss_partial = k.take<float>(gb);
   c->loss_accum = k.take<float>(1);
+  if (c->cfg.hash_log2) {
+    c->rec.nraw = k.take<float>(8 * rc);
+    c->rec.ntq = k.take<float4>(rc);
+    c->rec.nqf = k.take<float2>(rc);
+    c->ntab_n = (uint64_t)kHgLevels * kHgFeat << c->cfg.hash_log2;
+    auto state = [&](nrrs_ctx::NetState& st, uint64_t n) {
+      st.w = k.take<float>(n);
+      st.infer = k.take<float>(n);
+      st.m = k.take<float>(n);
+      st.v = k.take<float>(n);
+      st.g = k.take<float>(n);
+    };
+    state(c->nstat, kStatParams);
+    state(c->nrrs_net, kRrsParams);
+    state(c->ntab, c->ntab_n);
+    const uint64_t nb = nrrs_grad_blocks((uint32_t)std::max<uint64_t>(rc, 1));
+    c->npartial = k.take<float>(nb * std::max(kStatParams, kRrsParams));
+    c->nloss_part = k.take<float>(nb);
+    c->nloss = k.take<float>(2);
+    c->lum_start = k.take<double>(npx);
+    c->pix_part = k.take<double>(2 * ((npx + 255) / 256));
+    c->eavg = k.take<double>(1);
+    c->pcur = k.take<float>(npx);
+    c->pref = k.take<float>(npx);
+    c->pacc = k.take<float>(npx);
+    c->pEp = k.take<float>(npx);
+    c->pE = k.take<float>(npx);
+    c->pwpx = k.take<float>(npx);
+    c->kpix = k.take<uint32_t>(npx);
+  } else {
+    c->rec.nraw = nullptr;
+    c->rec.ntq = nullptr;
+    c->rec.nqf = nullptr;
+  }
   return (k.off + 255) & ~uint64_t(255);
 }
 
@@ -224,6 +270,64 @@ void init_params(uint64_t seed, std::vector<float>& w) {
       w[l.off + k] = (2.0f * u - 1.0f) * lim;
     }
   }
+}
+
+// NRRS networks: He-uniform hidden layers (leaky ReLU), output layers scaled by 0.1, zero
+// biases except RRSNet's output bias 2 (1 - ln 2), which starts the factor at 1 (Eq. 22 at
+// z >= 0: z / 2 + ln 2); hash-grid features uniform in [-1e-4, 1e-4].  Philox counters
+// (index, stream, 7, 0) keep the three vectors independent of the NET weights.
+void init_nrrs_params(uint64_t seed, std::vector<float>& stat, std::vector<float>& rrs, std::vector<float>& table,
+                      uint64_t table_n) {
+  auto uni = [&](uint32_t stream, uint64_t i) {
+    uint32_t c[4] = {(uint32_t)i, stream, 7u, (uint32_t)(i >> 32)};
+    philox_host(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return (float)(c[0] >> 8) * 0x1.0p-24f;
+  };
+  auto mlp = [&](std::vector<float>& w, int in, int out, uint32_t stream) {
+    w.assign(mlp32_params(in, out), 0.0f);
+    const int fan_in[4] = {in, 32, 32, 32}, fan_out[4] = {32, 32, 32, out};
+    uint64_t o = 0;
+    for (int L = 0; L < 4; ++L) {
+      const float lim = std::sqrt(6.0f / (float)fan_in[L]) * (L == 3 ? 0.1f : 1.0f);
+      for (int k = 0; k < fan_in[L] * fan_out[L]; ++k) w[o + k] = (2.0f * uni(stream, o + k) - 1.0f) * lim;
+      o += (uint64_t)fan_in[L] * fan_out[L] + fan_out[L];
+    }
+  };
+  mlp(stat, kStatIn, kStatOut, 1u);
+  mlp(rrs, kRrsIn, 1, 2u);
+  rrs[kRrsParams - 1] = 2.0f * (1.0f - 0.69314718055994531f);
+  table.resize(table_n);
+  for (uint64_t k = 0; k < table_n; ++k) table[k] = (2.0f * uni(3u, k) - 1.0f) * 1e-4f;
+}
+
+int32_t upload_nrrs_state(nrrs_ctx* c, const float* stat, const float* rrs, const float* table) {
+  hipStream_t s = c->stream;
+  auto put = [&](nrrs_ctx::NetState& st, const float* src, uint64_t n) -> int32_t {
+    if (!src) return NRRS_OK;
+    HIPC(c, hipMemcpyAsync(st.w, src, sizeof(float) * n, hipMemcpyHostToDevice, s));
+    HIPC(c, hipMemcpyAsync(st.infer, src, sizeof(float) * n, hipMemcpyHostToDevice, s));
+    launch_zero_u32((uint32_t*)st.m, n, s);
+    launch_zero_u32((uint32_t*)st.v, n, s);
+    launch_zero_u32((uint32_t*)st.g, n, s);
+    return NRRS_OK;
+  };
+  int32_t r = put(c->nstat, stat, kStatParams);
+  if (r == NRRS_OK) r = put(c->nrrs_net, rrs, kRrsParams);
+  if (r == NRRS_OK) r = put(c->ntab, table, c->ntab_n);
+  if (r != NRRS_OK) return r;
+  HIPC(c, hipStreamSynchronize(s));
+  c->nrrs_step = 0;
+  c->nrrs_rstep = 0;
+  return NRRS_OK;
+}
+
+NrrsNet nrrs_net_args(nrrs_ctx* c, bool inference) {
+  NrrsNet n{};
+  n.stat = inference ? c->nstat.infer : c->nstat.w;
+  n.rrs = inference ? c->nrrs_net.infer : c->nrrs_net.w;
+  n.table = inference ? c->ntab.infer : c->ntab.w;
+  n.log2T = c->cfg.hash_log2;
+  return n;
 }
 
 RenderArgs base_args(nrrs_ctx* c) {
@@ -316,7 +420,8 @@ int32_t nrrs_create(const nrrs_config* cfg, void* hip_stream, nrrs_ctx** out) {
       (cfg->norm_mode != NRRS_NORM_TWO_SIDED && cfg->norm_mode != NRRS_NORM_DOWNSCALE) ||
       cfg->precision < NRRS_PREC_FP32 || cfg->precision > NRRS_PREC_FP8 || !(cfg->p_train >= 0.0) ||
       cfg->p_train > 1.0 || (cfg->loss != NRRS_LOSS_REL_L2 && cfg->loss != NRRS_LOSS_LOG_MSE) ||
-      !(cfg->ema_decay >= 0.0) || cfg->ema_decay >= 1.0 || cfg->trace_depth > NRRS_MAX_DEPTH)
+      !(cfg->ema_decay >= 0.0) || cfg->ema_decay >= 1.0 || cfg->trace_depth > NRRS_MAX_DEPTH ||
+      (cfg->hash_log2 != 0 && (cfg->hash_log2 < 14 || cfg->hash_log2 > 22)))
     return NRRS_EINVAL;
   const uint64_t npx = (uint64_t)cfg->width * cfg->height;
   const uint64_t nprim = npx * cfg->s_batch;
@@ -393,6 +498,16 @@ int32_t nrrs_bind_workspace(nrrs_ctx* c, void* device_ptr, uint64_t bytes, uint6
   c->spp_total = 0;
   c->passes_done = 0;
   c->adam_step = 0;
+  if (c->cfg.hash_log2) {
+    std::vector<float> ws_, wr_, wt_;
+    init_nrrs_params(c->cfg.seed, ws_, wr_, wt_, c->ntab_n);
+    const int32_t r = upload_nrrs_state(c, ws_.data(), wr_.data(), wt_.data());
+    if (r != NRRS_OK) return r;
+    launch_zero_f64(c->lum_start, c->npx, s);
+    c->nrrs_frames = 0;
+    c->nrrs_spp_start = 0;
+    HIPC(c, hipStreamSynchronize(s));
+  }
   return NRRS_OK;
 }
 
@@ -595,7 +710,9 @@ int32_t nrrs_render(nrrs_ctx* c, uint32_t spp, uint32_t max_depth, int32_t mode,
   if (!c->scene) return fail(c, NRRS_ESTATE, "upload a scene first");
   if (spp == 0 || spp % c->cfg.s_batch != 0) return fail(c, NRRS_EINVAL, "spp must be a positive multiple of s_batch");
   if (max_depth < 1 || max_depth > NRRS_MAX_DEPTH) return fail(c, NRRS_EINVAL, "max_depth out of range");
-  if (mode < NRRS_MODE_OFF || mode > NRRS_MODE_NET) return fail(c, NRRS_EINVAL, "unknown mode");
+  if (mode < NRRS_MODE_OFF || mode > NRRS_MODE_NRRS) return fail(c, NRRS_EINVAL, "unknown mode");
+  if (mode == NRRS_MODE_NRRS && !c->cfg.hash_log2)
+    return fail(c, NRRS_ESTATE, "NRRS mode needs a context created with hash_log2 > 0");
   if (c->trace_on && max_depth > c->cfg.trace_depth)
     return fail(c, NRRS_EINVAL, "max_depth beyond the traced depths");
   if (c->f_fixed_n && mode != NRRS_MODE_OFF && max_depth > c->f_fixed_n + 1)
@@ -607,6 +724,8 @@ int32_t nrrs_render(nrrs_ctx* c, uint32_t spp, uint32_t max_depth, int32_t mode,
   a.mode = (uint32_t)mode;
   a.records_on = (mode != NRRS_MODE_OFF && c->cfg.records_cap > 0 && c->cfg.p_train > 0.0) ? 1u : 0u;
   const NetArgs net = net_args(c, c->cfg.precision);
+  const NrrsNet nnet = c->cfg.hash_log2 ? nrrs_net_args(c, true) : NrrsNet{};
+  const uint32_t nrrs_blocks = c->cus * 2;  // persistent grid of the NRRS factor kernel
   if (a.records_on) launch_zero_u32(a.rec.count, 1, s);
   launch_zero_u32((uint32_t*)c->st_n, 2 * (NRRS_MAX_DEPTH + 1), s);
   launch_zero_u32((uint32_t*)c->st_s, 2 * (NRRS_MAX_DEPTH + 1), s);
@@ -656,10 +775,14 @@ int32_t nrrs_render(nrrs_ctx* c, uint32_t spp, uint32_t max_depth, int32_t mode,
       } else if (mode == NRRS_MODE_NET && ((c->net_depths >> (d - 1)) & 1u)) {
         launch_rrsnet(b, net, s);
         MARK(3);
+      } else if (mode == NRRS_MODE_NRRS && ((c->net_depths >> (d - 1)) & 1u)) {
+        launch_nrrs_factor(b, nnet, nrrs_blocks, s);
+        MARK(3);
       }
       launch_sum_q(b, s);
       MARK(4);
       launch_roulette(b, s);
+      if (b.records_on && b.rec.nqf && d <= (uint32_t)c->cfg.net_max_depth) launch_record_qnorm(b, s);
       MARK(5);
       launch_expand(b, s);
       MARK(6);
@@ -765,6 +888,11 @@ int32_t nrrs_reset_image(nrrs_ctx* c) {
   launch_zero_f64(c->image, 3 * c->npx, c->stream);
   launch_set_f64(c->alpha, 1.0, c->stream);
   c->spp_total = 0;
+  if (c->cfg.hash_log2) {
+    launch_zero_f64(c->lum_start, c->npx, c->stream);
+    c->nrrs_frames = 0;
+    c->nrrs_spp_start = 0;
+  }
   HIPC(c, hipGetLastError());
   return NRRS_OK;
 }
@@ -1013,6 +1141,253 @@ int32_t nrrs_train_step(nrrs_ctx* c, uint32_t n_records, uint32_t minibatch, flo
     HIPC(c, hipMemcpy(&l, c->loss_accum, 4, hipMemcpyDeviceToHost));
     *loss_or_null = l / (float)batches;
   }
+  return NRRS_OK;
+}
+
+// ------------------------------------------------------------------------- NRRS proper
+int32_t nrrs_set_nrrs_params(nrrs_ctx* c, const float* stat, const float* rrs, const float* table) {
+  if (!c) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (!c->cfg.hash_log2) return fail(c, NRRS_ESTATE, "context created without NRRS (hash_log2 = 0)");
+  if ((stat && !finite_all(stat, kStatParams)) || (rrs && !finite_all(rrs, kRrsParams)) ||
+      (table && !finite_all(table, c->ntab_n)))
+    return fail(c, NRRS_EINVAL, "non-finite NRRS parameter");
+  HIPC(c, hipStreamSynchronize(c->stream));
+  return upload_nrrs_state(c, stat, rrs, table);
+}
+
+int32_t nrrs_get_nrrs_params(nrrs_ctx* c, float* stat, float* rrs, float* table) {
+  if (!c) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (!c->cfg.hash_log2) return fail(c, NRRS_ESTATE, "context created without NRRS (hash_log2 = 0)");
+  HIPC(c, hipStreamSynchronize(c->stream));
+  if (stat) HIPC(c, hipMemcpy(stat, c->nstat.w, sizeof(float) * kStatParams, hipMemcpyDeviceToHost));
+  if (rrs) HIPC(c, hipMemcpy(rrs, c->nrrs_net.w, sizeof(float) * kRrsParams, hipMemcpyDeviceToHost));
+  if (table) HIPC(c, hipMemcpy(table, c->ntab.w, sizeof(float) * c->ntab_n, hipMemcpyDeviceToHost));
+  return NRRS_OK;
+}
+
+namespace {
+bool train_args_ok(const nrrs_nrrs_train* hp) {
+  auto pos = [](float x) { return x > 0.0f && std::isfinite(x); };
+  auto nonneg = [](float x) { return x >= 0.0f && std::isfinite(x); };
+  return hp && pos(hp->lr_stat) && pos(hp->lr_rrs) && nonneg(hp->g_avg) && nonneg(hp->g_min) &&
+         nonneg(hp->g_rrs) && hp->a_mix > 0.0f && hp->a_mix <= 1.0f && hp->radius >= 0 && hp->radius <= 8 &&
+         (hp->rrs_step == 1 || hp->rrs_step == 2);
+}
+}  // namespace
+
+int32_t nrrs_train_step_nrrs(nrrs_ctx* c, uint32_t n_records, const nrrs_nrrs_train* hp, nrrs_nrrs_loss* out) {
+  if (!c) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (!c->cfg.hash_log2) return fail(c, NRRS_ESTATE, "context created without NRRS (hash_log2 = 0)");
+  if (!train_args_ok(hp)) return fail(c, NRRS_EINVAL, "NRRS training parameters out of range");
+  if (n_records == 0 || n_records > c->cfg.records_cap) return fail(c, NRRS_EINVAL, "n_records out of range");
+  hipStream_t s = c->stream;
+  HIPC(c, hipStreamSynchronize(s));
+  uint32_t cnt = 0;
+  HIPC(c, hipMemcpy(&cnt, c->rec.count, 4, hipMemcpyDeviceToHost));
+  if (std::min<uint32_t>(cnt, c->cfg.records_cap) < n_records)
+    return fail(c, NRRS_ESTATE, "fewer records captured than requested");
+  if (c->spp_total <= c->nrrs_spp_start) return fail(c, NRRS_ESTATE, "no frame rendered since the last step");
+  const NrrsRows r{c->rec.nraw, c->rec.lum_t, c->rec.acc, nullptr, c->rec.ntq, c->rec.nqf, c->rec.pix, n_records};
+  const uint32_t nb = nrrs_grad_blocks(n_records);
+  const float decay = (float)c->cfg.ema_decay, eps = 0.01f;
+  // StatNet (hash grid and MLP), Eq. (15)
+  launch_statnet_grad(r, c->nstat.w, c->ntab.w, c->cfg.hash_log2, eps, c->npartial, c->nloss_part, c->ntab.g, s);
+  launch_partial_sum(c->npartial, nb, kStatParams, c->nstat.g, c->nloss_part, c->nloss, s);
+  c->nrrs_step += 1;
+  launch_adam(c->nstat.w, c->nstat.m, c->nstat.v, c->nstat.g, kStatParams, c->nrrs_step, hp->lr_stat, c->nstat.infer,
+              decay, false, s);
+  launch_adam(c->ntab.w, c->ntab.m, c->ntab.v, c->ntab.g, c->ntab_n, c->nrrs_step, hp->lr_stat, c->ntab.infer, decay,
+              true, s);
+  // the frame's pixel error (kept up to date in both steps so that step 2 starts mixed)
+  const double spp_frame = (double)(c->spp_total - c->nrrs_spp_start);
+  const bool first = c->nrrs_frames == 0;
+  const bool has_ref = c->nrrs_spp_start > 0;
+  launch_frame_lum(c->image, c->lum_start, (uint32_t)c->npx, spp_frame, (double)c->nrrs_spp_start, c->pcur, c->pref,
+                   s);
+  PixelErrArgs pe{};
+  pe.cur = c->pcur;
+  pe.ref = c->pref;
+  pe.acc = c->pacc;
+  pe.Ep = c->pEp;
+  pe.E = c->pE;
+  pe.wpx = c->pwpx;
+  pe.part = c->pix_part;
+  pe.eavg = c->eavg;
+  pe.w = c->cfg.width;
+  pe.h = c->cfg.height;
+  pe.first = first ? 1u : 0u;
+  pe.radius = hp->radius;
+  pe.a_mix = hp->a_mix;
+  // variance of a one-sample pixel estimate from the squared error of the mixed frame estimate
+  pe.var_scale = (float)(spp_frame * (first ? 1.0 : (2.0 - hp->a_mix) / hp->a_mix));
+  pe.g_avg = hp->g_avg;
+  pe.g_min = hp->g_min;
+  pe.eps = eps;
+  launch_pixel_error(pe, s);
+  launch_count_pix(c->rec.pix, n_records, c->kpix, (uint32_t)c->npx, s);
+  c->nrrs_frames += 1;
+  c->nrrs_spp_start = c->spp_total;
+  // RRSNet with StatNet's updated weights
+  const bool rrs_train = hp->rrs_step == 1 || has_ref;
+  if (rrs_train) {
+    launch_rrsnet_grad(r, c->nstat.w, c->ntab.w, c->cfg.hash_log2, c->nrrs_net.w, hp->rrs_step, c->pwpx, c->kpix,
+                       hp->g_rrs, eps, c->npartial, c->nloss_part, s);
+    launch_partial_sum(c->npartial, nb, kRrsParams, c->nrrs_net.g, c->nloss_part, c->nloss + 1, s);
+    c->nrrs_rstep += 1;
+    launch_adam(c->nrrs_net.w, c->nrrs_net.m, c->nrrs_net.v, c->nrrs_net.g, kRrsParams, c->nrrs_rstep, hp->lr_rrs,
+                c->nrrs_net.infer, decay, false, s);
+  }
+  HIPC(c, hipGetLastError());
+  if (out) {
+    HIPC(c, hipStreamSynchronize(s));
+    float l[2] = {0.0f, 0.0f};
+    HIPC(c, hipMemcpy(l, c->nloss, sizeof(l), hipMemcpyDeviceToHost));
+    HIPC(c, hipMemcpy(&out->e_avg, c->eavg, sizeof(double), hipMemcpyDeviceToHost));
+    out->loss_stat = l[0];
+    out->loss_rrs = rrs_train ? l[1] : 0.0f;
+    out->records = n_records;
+    out->rrs_trained = rrs_train ? 1u : 0u;
+  }
+  return NRRS_OK;
+}
+
+int32_t nrrs_debug_nrrs_forward(nrrs_ctx* c, const float* raw, const float* t, const float* I, uint32_t n, float* mv,
+                                float* q, float* enc) {
+  if (!c || (n && (!raw || !t || !I || !mv || !q))) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (!c->cfg.hash_log2) return fail(c, NRRS_ESTATE, "context created without NRRS (hash_log2 = 0)");
+  if ((uint64_t)n * 4 * 46 + 4096 > c->qb_pool_bytes) return fail(c, NRRS_ENOMEM, "too many rows for the scratch space");
+  if (n == 0) return NRRS_OK;
+  hipStream_t s = c->stream;
+  HIPC(c, hipStreamSynchronize(s));
+  Carve k{c->qb_pool};
+  float* praw = k.take<float>(7ull * n);
+  float* pt = k.take<float>(3ull * n);
+  float* pI = k.take<float>(n);
+  float* pmv = k.take<float>(2ull * n);
+  float* pq = k.take<float>(n);
+  float* penc = enc ? k.take<float>(32ull * n) : nullptr;
+  HIPC(c, hipMemcpy(praw, raw, sizeof(float) * 7 * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(pt, t, sizeof(float) * 3 * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(pI, I, sizeof(float) * n, hipMemcpyHostToDevice));
+  launch_nrrs_rows(praw, pt, pI, n, nrrs_net_args(c, true), pmv, pq, penc, s);
+  HIPC(c, hipStreamSynchronize(s));
+  HIPC(c, hipGetLastError());
+  HIPC(c, hipMemcpy(mv, pmv, sizeof(float) * 2 * n, hipMemcpyDeviceToHost));
+  HIPC(c, hipMemcpy(q, pq, sizeof(float) * n, hipMemcpyDeviceToHost));
+  if (enc) HIPC(c, hipMemcpy(enc, penc, sizeof(float) * 32 * n, hipMemcpyDeviceToHost));
+  return NRRS_OK;
+}
+
+int32_t nrrs_debug_nrrs_grads(nrrs_ctx* c, const float* raw, const float* I, const float* L, const float* lum_t,
+                              const float* t, const float* q_norm, const float* F, const uint32_t* pix, uint32_t n,
+                              const float* wpx, const uint32_t* kk, uint32_t npx, int32_t rrs_step, float g_rrs,
+                              float* g_stat, float* g_rrs_out, float* g_table, float* loss_stat, float* loss_rrs) {
+  if (!c || n == 0 || !raw || !I || !L || !lum_t || !t || !q_norm || !F || !pix || npx == 0 || !wpx || !kk ||
+      !g_stat || !g_rrs_out || !g_table || !loss_stat || !loss_rrs || (rrs_step != 1 && rrs_step != 2) ||
+      !(g_rrs >= 0.0f))
+    return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (!c->cfg.hash_log2) return fail(c, NRRS_ESTATE, "context created without NRRS (hash_log2 = 0)");
+  if (n > c->cfg.records_cap) return fail(c, NRRS_EINVAL, "n beyond records_cap");
+  for (uint32_t i = 0; i < n; ++i)
+    if (pix[i] >= npx) return fail(c, NRRS_EINVAL, "pixel index beyond npx");
+  if ((uint64_t)n * 4 * 18 + (uint64_t)npx * 8 + 8192 > c->qb_pool_bytes)
+    return fail(c, NRRS_ENOMEM, "too many rows for the scratch space");
+  hipStream_t s = c->stream;
+  HIPC(c, hipStreamSynchronize(s));
+  std::vector<float> rows(8ull * n), tq(4ull * n), qf(2ull * n);
+  for (uint32_t i = 0; i < n; ++i) {
+    for (int k = 0; k < 7; ++k) rows[8ull * i + k] = raw[7ull * i + k];
+    rows[8ull * i + 7] = I[i];
+    for (int k = 0; k < 3; ++k) tq[4ull * i + k] = t[3ull * i + k];
+    tq[4ull * i + 3] = 0.0f;
+    qf[2ull * i] = q_norm[i];
+    qf[2ull * i + 1] = F[i];
+  }
+  Carve k{c->qb_pool};
+  float* prow = k.take<float>(8ull * n);
+  float* pL = k.take<float>(n);
+  float* plum = k.take<float>(n);
+  float4* ptq = k.take<float4>(n);
+  float2* pqf = k.take<float2>(n);
+  uint32_t* ppix = k.take<uint32_t>(n);
+  float* pw = k.take<float>(npx);
+  uint32_t* pk = k.take<uint32_t>(npx);
+  HIPC(c, hipMemcpy(prow, rows.data(), sizeof(float) * 8 * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(pL, L, sizeof(float) * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(plum, lum_t, sizeof(float) * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(ptq, tq.data(), sizeof(float) * 4 * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(pqf, qf.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(ppix, pix, sizeof(uint32_t) * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(pw, wpx, sizeof(float) * npx, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(pk, kk, sizeof(uint32_t) * npx, hipMemcpyHostToDevice));
+  const NrrsRows r{prow, plum, nullptr, pL, ptq, pqf, ppix, n};
+  const uint32_t nb = nrrs_grad_blocks(n);
+  launch_zero_u32((uint32_t*)c->ntab.g, c->ntab_n, s);
+  launch_statnet_grad(r, c->nstat.w, c->ntab.w, c->cfg.hash_log2, 0.01f, c->npartial, c->nloss_part, c->ntab.g, s);
+  launch_partial_sum(c->npartial, nb, kStatParams, c->nstat.g, c->nloss_part, c->nloss, s);
+  launch_rrsnet_grad(r, c->nstat.w, c->ntab.w, c->cfg.hash_log2, c->nrrs_net.w, rrs_step, pw, pk, g_rrs, 0.01f,
+                     c->npartial, c->nloss_part, s);
+  launch_partial_sum(c->npartial, nb, kRrsParams, c->nrrs_net.g, c->nloss_part, c->nloss + 1, s);
+  HIPC(c, hipStreamSynchronize(s));
+  HIPC(c, hipGetLastError());
+  float l[2];
+  HIPC(c, hipMemcpy(g_stat, c->nstat.g, sizeof(float) * kStatParams, hipMemcpyDeviceToHost));
+  HIPC(c, hipMemcpy(g_rrs_out, c->nrrs_net.g, sizeof(float) * kRrsParams, hipMemcpyDeviceToHost));
+  HIPC(c, hipMemcpy(g_table, c->ntab.g, sizeof(float) * c->ntab_n, hipMemcpyDeviceToHost));
+  HIPC(c, hipMemcpy(l, c->nloss, sizeof(l), hipMemcpyDeviceToHost));
+  *loss_stat = l[0];
+  *loss_rrs = l[1];
+  // leave the training state as it was: the grid gradient starts each step at zero
+  launch_zero_u32((uint32_t*)c->ntab.g, c->ntab_n, s);
+  HIPC(c, hipStreamSynchronize(s));
+  return NRRS_OK;
+}
+
+int32_t nrrs_debug_pixel_error(nrrs_ctx* c, const float* cur, float* acc, const float* ref, uint32_t w, uint32_t h,
+                               int32_t first, float a_mix, int32_t radius, float var_scale, float g_avg, float g_min,
+                               float* E, float* wpx, double* e_avg) {
+  if (!c || !cur || !acc || !ref || !E || !wpx || !e_avg || w == 0 || h == 0 || !(a_mix > 0.0f && a_mix <= 1.0f) ||
+      radius < 0 || radius > 8)
+    return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (!c->cfg.hash_log2) return fail(c, NRRS_ESTATE, "context created without NRRS (hash_log2 = 0)");
+  const uint64_t npx = (uint64_t)w * h;
+  if (npx > c->npx) return fail(c, NRRS_EINVAL, "image larger than the context's");
+  hipStream_t s = c->stream;
+  HIPC(c, hipStreamSynchronize(s));
+  HIPC(c, hipMemcpy(c->pcur, cur, sizeof(float) * npx, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(c->pref, ref, sizeof(float) * npx, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(c->pacc, acc, sizeof(float) * npx, hipMemcpyHostToDevice));
+  PixelErrArgs pe{};
+  pe.cur = c->pcur;
+  pe.ref = c->pref;
+  pe.acc = c->pacc;
+  pe.Ep = c->pEp;
+  pe.E = c->pE;
+  pe.wpx = c->pwpx;
+  pe.part = c->pix_part;
+  pe.eavg = c->eavg;
+  pe.w = w;
+  pe.h = h;
+  pe.first = first ? 1u : 0u;
+  pe.radius = radius;
+  pe.a_mix = a_mix;
+  pe.var_scale = var_scale;
+  pe.g_avg = g_avg;
+  pe.g_min = g_min;
+  pe.eps = 0.01f;
+  launch_pixel_error(pe, s);
+  HIPC(c, hipStreamSynchronize(s));
+  HIPC(c, hipGetLastError());
+  HIPC(c, hipMemcpy(acc, c->pacc, sizeof(float) * npx, hipMemcpyDeviceToHost));
+  HIPC(c, hipMemcpy(E, c->pE, sizeof(float) * npx, hipMemcpyDeviceToHost));
+  HIPC(c, hipMemcpy(wpx, c->pwpx, sizeof(float) * npx, hipMemcpyDeviceToHost));
+  HIPC(c, hipMemcpy(e_avg, c->eavg, sizeof(double), hipMemcpyDeviceToHost));
   return NRRS_OK;
 }
 

@@ -156,6 +156,11 @@ struct Records {
   uint32_t* qidx;  // [cap] queue slot of the record's vertex at capture (features filled later)
   uint32_t* count;
   uint32_t cap;
+  // NRRS training (reserved only with a hash grid): StatNet / RRSNet inputs of the vertex and
+  // the factor the renderer applied
+  float* nraw;     // [cap][8] position in the scene box scaled to [0,1]^3, w_o, remapped roughness, I_px
+  float4* ntq;     // [cap] throughput (rgb), unused
+  float2* nqf;     // [cap] normalized factor q_norm = F q and the normalization factor F
 };
 
 // Per-depth control block on the device (one per depth of a pass).

@@ -119,6 +119,77 @@ void launch_rows_mfma(const float* x, uint32_t n, const NetArgs& net, float* y, 
 void launch_codes_mfma(const float* x, uint32_t n, const NetArgs& net, float* y, uint16_t* codes, int8_t* scale_exp,
                        hipStream_t s);
 void warm_mfma_launch_cache();  // occupancy queries done before any stream capture
+
+// NRRS proper (nrrs_net.hip): StatNet and the NRRS variant of RRSNet, both in -> 32 -> 32 -> 32
+// -> out with leaky ReLU, and the multiresolution hash grid of StatNet's position input.
+constexpr int kHgLevels = 8, kHgFeat = 2, kHgBase = 16;
+constexpr int kStatRaw = 7, kStatIn = 32, kStatOut = 2, kRrsIn = 7;
+constexpr uint32_t mlp32_params(int in, int out) { return 32u * in + 32u + 2u * (32u * 32u + 32u) + 32u * out + out; }
+constexpr uint32_t kStatParams = mlp32_params(kStatIn, kStatOut);  // 3234
+constexpr uint32_t kRrsParams = mlp32_params(kRrsIn, 1);           // 2401
+struct NrrsNet {
+  const float* stat;   // StatNet parameters
+  const float* rrs;    // RRSNet parameters
+  const float* table;  // hash grid [kHgLevels][2^log2T][kHgFeat]
+  uint32_t log2T;
+};
+void launch_nrrs_factor(const RenderArgs& a, const NrrsNet& n, uint32_t blocks, hipStream_t s);
+void launch_record_qnorm(const RenderArgs& a, hipStream_t s);  // after the roulette of the depth
+// Test entry point: StatNet outputs, RRS factor and (optional) StatNet encodings of n vertices.
+void launch_nrrs_rows(const float* raw, const float* t, const float* I, uint32_t n, const NrrsNet& net, float* mv,
+                      float* q, float* enc, hipStream_t s);
+// Training records as the gradient kernels read them (device arrays; n rows).
+struct NrrsRows {
+  const float* raw;     // [n][8] (stride 8): raw StatNet inputs (7), pixel value I
+  const float* lum_t;   // [n]
+  const float* acc;     // [n] descendant emission luminance (StatNet target = acc / lum_t), or null
+  const float* target;  // [n] StatNet target given directly (used when acc is null)
+  const float4* tq;     // [n] throughput rgb
+  const float2* qf;     // [n] q_norm, F
+  const uint32_t* pix;  // [n]
+  uint32_t n;
+};
+uint32_t nrrs_grad_blocks(uint32_t n);
+// StatNet gradient of Eq. (15) (mean over the rows): block partials [blocks][kStatParams], block
+// losses, and hash-grid gradients added atomically into gtable (zeroed by the caller).
+void launch_statnet_grad(const NrrsRows& r, const float* stat, const float* table, uint32_t log2T, float eps,
+                         float* partial, float* loss_part, float* gtable, hipStream_t s);
+// RRSNet gradient: step 1 fits the output 1 (mean relative L2); step 2 transfers the pixel
+// gradient wpx / k (Eqs. 17-18) and adds the bound loss (Eq. 21).
+void launch_rrsnet_grad(const NrrsRows& r, const float* stat, const float* table, uint32_t log2T, const float* rrs,
+                        int32_t step, const float* wpx, const uint32_t* kpix, float g_rrs, float eps, float* partial,
+                        float* loss_part, hipStream_t s);
+// Fixed-order sum of the block partials into grad, and of the block losses into *loss.
+void launch_partial_sum(const float* partial, uint32_t nblocks, uint32_t np, float* grad, const float* loss_part,
+                        float* loss, hipStream_t s);
+// Adam (bias-corrected, step >= 1) on np parameters, the moving average of the inference copy
+// (decay 0: copy) and, when zero_grad, the gradient cleared for the next step.
+void launch_adam(float* w, float* m, float* v, float* grad, uint64_t np, uint64_t step, float lr, float* infer,
+                 float decay, bool zero_grad, hipStream_t s);
+// Pixel error of the frame (Sec. 5 "Tackle Low Spp", Eqs. 19-20, 23): from the luminance of the
+// current frame cur and of the previous frames ref (< 0: none) per pixel, with the temporally
+// mixed acc updated in place: E (box filter of radius r), E_avg into *eavg (double), and the
+// derivative wpx of gamma1 L_avg + gamma2 L_min with respect to the pixel variance.
+struct PixelErrArgs {
+  const float* cur;
+  const float* ref;
+  float* acc;
+  float* Ep;     // scratch [npx]
+  float* E;      // [npx]
+  float* wpx;    // [npx]
+  double* part;  // scratch [2 * pixel blocks]
+  double* eavg;  // [1]
+  uint32_t w, h, first;
+  int32_t radius;
+  float a_mix, var_scale, g_avg, g_min, eps;
+};
+void launch_pixel_error(const PixelErrArgs& p, hipStream_t s);
+// Frame luminances from the FP64 image sums: cur = (lum(image) - lum_start) / spp_frame,
+// ref = lum_start / spp_start (or -1 when spp_start = 0); lum_start <- lum(image).
+void launch_frame_lum(const double* image, double* lum_start, uint32_t npx, double spp_frame, double spp_start,
+                      float* cur, float* ref, hipStream_t s);
+// Records per pixel: kpix zeroed, then one count per row.
+void launch_count_pix(const uint32_t* pix, uint32_t n, uint32_t* kpix, uint32_t npx, hipStream_t s);
 uint32_t mlp_grad_blocks(uint32_t n);
 uint32_t mlp_grad_scratch_floats(uint32_t max_rows);  // partials + reduction groups
 

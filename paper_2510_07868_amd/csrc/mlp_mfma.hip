@@ -194,14 +194,19 @@ __device__ __forceinline__ float output_layer(const Smem& sm, const f32x16& c0, 
 // accumulators; returns z of vertex l % 32 (in both lane halves).
 // Test entry point only: the BF16 bit patterns of this lane's 32 activations of hidden layer L
 // (row crow of the vertex whose column the lane holds), in unit order.
+// The whole vector is reinterpreted at once: with this compiler, a bit cast of one subscripted
+// element of these vectors returned the first element for every index.
+typedef __attribute__((__vector_size__(8 * sizeof(uint16_t)))) uint16_t u16x8;
 __device__ __forceinline__ void store_codes_bf16(uint16_t* crow, int L, int h, bf16x8 b0, bf16x8 b1, bf16x8 b2,
                                                  bf16x8 b3) {
+  const u16x8 u0 = __builtin_bit_cast(u16x8, b0), u1 = __builtin_bit_cast(u16x8, b1);
+  const u16x8 u2 = __builtin_bit_cast(u16x8, b2), u3 = __builtin_bit_cast(u16x8, b3);
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    crow[64 * L + acc_row(i, h)] = __builtin_bit_cast(uint16_t, b0[i]);
-    crow[64 * L + acc_row(8 + i, h)] = __builtin_bit_cast(uint16_t, b1[i]);
-    crow[64 * L + 32 + acc_row(i, h)] = __builtin_bit_cast(uint16_t, b2[i]);
-    crow[64 * L + 32 + acc_row(8 + i, h)] = __builtin_bit_cast(uint16_t, b3[i]);
+    crow[64 * L + acc_row(i, h)] = u0[i];
+    crow[64 * L + acc_row(8 + i, h)] = u1[i];
+    crow[64 * L + 32 + acc_row(i, h)] = u2[i];
+    crow[64 * L + 32 + acc_row(8 + i, h)] = u3[i];
   }
 }
 
@@ -244,9 +249,11 @@ __device__ __forceinline__ float mlp_bf16(const bf16x8* __restrict__ wl, const S
   if constexpr (kCodes) {
     if (__lane_id() < nleft)
 #pragma unroll
-      for (int j = 0; j < 3; ++j)
+      for (int j = 0; j < 3; ++j) {
+        const u16x8 u = __builtin_bit_cast(u16x8, x[j]);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) cstep[192 * __lane_id() + 8 * j + i] = __builtin_bit_cast(uint16_t, x[j][i]);
+        for (int i = 0; i < 8; ++i) cstep[192 * __lane_id() + 8 * j + i] = u[i];
+      }
   }
   float z[2];
 #pragma unroll

