@@ -388,10 +388,14 @@ def efficiency(r, nrrs, spp, D, ref_spp, renders, make_reference):
 
 
 def nrrs_proper_study(nrrs, sc, torch, W, H, spp, D, frames, renders, ref, p_train, tuning):
-    """NRRS proper (Sec. 4.2): StatNet + RRSNet factors at depths 1-4, trained online for
-    `frames` frames (render + one train_step_nrrs each; RRSNet fitted to 1 for the first third,
-    then by the pixel-variance loss of Eq. 16), then relMSE and 1/(relMSE * t) at equal spp
-    against heuristic normalized RRS on the same context, guide and reference."""
+    """NRRS proper (Sec. 4.2): StatNet + RRSNet (NRRS inputs) and the AID-NRRS RRSNet, both trained
+    online for `frames` frames (render + one train_step_nrrs each, both RRSNets per step; fitted
+    to 1 for the first third, then by the pixel-variance loss of Eq. 16), then relMSE and
+    1/(relMSE * t) at equal spp against heuristic normalized RRS on the same context, guide and
+    reference: each with the factor at depths 1-4, and with the per-bounce table found by the
+    segmented Mix-Depth search (Sec. 4.3) over {the factor, heuristic, fixed rate}."""
+    from paper_2510_07868_amd import mixdepth
+
     rec_n = 1 << 18
     r = nrrs.Renderer(W, H, s_batch=spp, cap_factor=2.0, seed=0, net_max_depth=4, records_cap=rec_n,
                       p_train=p_train, max_tris=sc.n_tris, max_materials=len(sc.mat_type), ema_decay=0.99,
@@ -406,11 +410,12 @@ def nrrs_proper_study(nrrs, sc, torch, W, H, spp, D, frames, renders, ref, p_tra
     t0 = time.perf_counter()
     t_train = 0.0
     for f in range(frames):
-        st = r.render(spp, D, nrrs.MODE_NRRS)
+        # frames alternate the two factors so that both RRSNets see their own renders' records
+        st = r.render(spp, D, nrrs.MODE_NRRS if f % 2 == 0 else nrrs.MODE_AID)
         n = min(st["records"], rec_n)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        lo = r.train_step_nrrs(n, 1 if f < step1 else 2)
+        lo = r.train_step_nrrs(n, 1 if f < step1 else 2, variant=2)
         torch.cuda.synchronize()
         t_train += time.perf_counter() - t1
         if f % 20 == 0 or f == frames - 1:
@@ -419,8 +424,20 @@ def nrrs_proper_study(nrrs, sc, torch, W, H, spp, D, frames, renders, ref, p_tra
             hist.append({"frame": f, "loss_stat": lo["loss_stat"], "loss_rrs": lo["loss_rrs"], "e_avg": lo["e_avg"]})
     t_frames = time.perf_counter() - t0
     guide = r.get_guide()
+    default = r.get_mix_depth()
+    tables = {}
+    t0 = time.perf_counter()
+    for name, mode in (("nrrs", nrrs.MODE_NRRS), ("aid", nrrs.MODE_AID)):
+        score = mixdepth.render_efficiency_scorer(r, D, guide, mode)
+        table, _, _ = mixdepth.heuristic_search(D - 1, 5, mixdepth.METHODS, score, fallback=mixdepth.FIXED)
+        tables[name] = (mixdepth.table_to_mask(table, mixdepth.NET), mixdepth.table_to_mask(table, mixdepth.FIXED))
+    t_search = time.perf_counter() - t0
     res = {}
-    for name, mode in (("nrrs", nrrs.MODE_NRRS), ("heuristic", nrrs.MODE_HEURISTIC)):
+    for name, mode, (mask, fixed) in (("nrrs", nrrs.MODE_NRRS, (default, 0)), ("nrrs_plus", nrrs.MODE_NRRS, tables["nrrs"]),
+                                      ("aid", nrrs.MODE_AID, (default, 0)), ("aid_plus", nrrs.MODE_AID, tables["aid"]),
+                                      ("heuristic", nrrs.MODE_HEURISTIC, (default, 0))):
+        r.set_mix_depth(mask)
+        r.set_mix_depth_fixed(fixed)
         times, errs = [], []
         for k in range(renders):
             r.set_guide(guide)
@@ -435,20 +452,28 @@ def nrrs_proper_study(nrrs, sc, torch, W, H, spp, D, frames, renders, ref, p_tra
         rm, t = float(np.mean(errs)), float(np.median(times))
         res[name] = {"relmse": rm, "relmse_se": float(np.std(errs) / np.sqrt(len(errs))), "render_s": round(t, 5),
                      "efficiency": 1.0 / (rm * t)}
+        if mask != default or fixed:
+            res[name]["factor_depths"] = [d + 1 for d in range(64) if (mask >> d) & 1 and not (fixed >> d) & 1]
+            res[name]["fixed_rate_depths"] = [d + 1 for d in range(64) if (fixed >> d) & 1]
+    r.set_mix_depth(default)
+    r.set_mix_depth_fixed(0)
     # per-stage time of an NRRS render (the factor kernel is the network stage)
     r.set_timing(True)
     r.set_guide(guide)
     st = r.render(spp, D, nrrs.MODE_NRRS)
     r.set_timing(False)
     r.close()
-    return {"method": "StatNet (hash grid 8 x 2, 2^19 entries per level) + RRSNet (NRRS inputs), 32-wide "
-                      "3-hidden-layer MLPs, FP32; one Adam step per frame (lr 5e-3 / 3e-4), gammas 0.01 / "
-                      "0.05 / 0.01, error image mixed 0.5 and box-filtered (radius 2)",
-            "frames": frames, "step1_frames": step1, "train_s": round(t_frames, 2),
-            "train_step_ms": round(1e3 * t_train / frames, 3), "history": hist,
-            "nrrs": res["nrrs"], "heuristic": res["heuristic"],
-            "nrrs_over_heuristic": res["nrrs"]["efficiency"] / res["heuristic"]["efficiency"],
-            "stage_ms": {k: round(v, 3) for k, v in st["stage_ms"].items()}}
+    out = {"method": "StatNet (hash grid 8 x 2, 2^19 entries per level) + RRSNet with NRRS inputs, and the AID-NRRS "
+                     "RRSNet (its own hash grid + one-blob inputs); 32-wide 3-hidden-layer MLPs, FP32; one Adam step "
+                     "per frame (lr 5e-3 / 3e-4), gammas 0.01 / 0.05 / 0.01, error image mixed 0.5 and box-filtered "
+                     "(radius 2)",
+           "frames": frames, "step1_frames": step1, "train_s": round(t_frames, 2),
+           "train_step_ms": round(1e3 * t_train / frames, 3), "mix_depth_search_s": round(t_search, 2),
+           "history": hist, "stage_ms_nrrs": {k: round(v, 3) for k, v in st["stage_ms"].items()}}
+    out.update(res)
+    for k in ("nrrs", "nrrs_plus", "aid", "aid_plus"):
+        out[f"{k}_over_heuristic"] = res[k]["efficiency"] / res["heuristic"]["efficiency"]
+    return out
 
 
 def _timed_render(r, torch, spp, D, mode, train=None):

@@ -49,8 +49,10 @@ enum nrrs_mode {
   NRRS_MODE_HEURISTIC = 1, /* normalized RRS with q = lum(throughput * albedo) */
   NRRS_MODE_NET = 2,       /* normalized RRS with the network factor at the depths of the Mix-Depth
                               table (nrrs_set_mix_depth; default: depth <= net_max_depth) */
-  NRRS_MODE_NRRS = 3       /* normalized RRS with the NRRS factor (StatNet + RRSNet, Sec. 4.2) at the
+  NRRS_MODE_NRRS = 3,      /* normalized RRS with the NRRS factor (StatNet + RRSNet, Sec. 4.2) at the
                               depths of the Mix-Depth table; needs hash_log2 > 0 at creation */
+  NRRS_MODE_AID = 4        /* as NRRS_MODE_NRRS with the AID-NRRS RRSNet (its own hash grid and
+                              one-blob inputs, no StatNet at inference; Sec. 4.2.1) */
 };
 
 enum nrrs_norm { NRRS_NORM_TWO_SIDED = 0, NRRS_NORM_DOWNSCALE = 1 };
@@ -210,6 +212,7 @@ int32_t nrrs_set_state(nrrs_ctx* ctx, const float* infer, const double* alpha);
  * average of the masters with cfg.ema_decay per Adam step). */
 #define NRRS_STAT_NPARAM 3234
 #define NRRS_RRS_NPARAM 2401
+#define NRRS_AID_NPARAM 3201 /* AID-NRRS RRSNet: 32 -> 32 -> 32 -> 32 -> 1 */
 
 /* Set (masters and inference copies; Adam moments and step cleared) or get (masters) the NRRS
  * networks from host arrays; any pointer may be NULL to skip that part.  set: EINVAL for a
@@ -224,6 +227,9 @@ typedef struct {
   int32_t radius;             /* box-filter radius (pixels, 0..8) of the error image, in place of
                                  the paper's denoiser */
   int32_t rrs_step;           /* 1: RRSNet fitted to the output 1; 2: trained by Eq. (16) */
+  int32_t variant;            /* which RRSNet trains: 0 NRRS (StatNet's statistics as inputs), 1 AID-NRRS
+                                 (its own hash grid + one-blob inputs; StatNet only supervises), 2 both
+                                 (loss_rrs then reports the AID-NRRS one) */
 } nrrs_nrrs_train;
 
 typedef struct {
@@ -246,7 +252,21 @@ typedef struct {
  * captured, <= records_cap).  Synchronous when out != NULL. */
 int32_t nrrs_train_step_nrrs(nrrs_ctx* ctx, uint32_t n_records, const nrrs_nrrs_train* hp, nrrs_nrrs_loss* out);
 
+/* AID-NRRS RRSNet (Sec. 4.2.1; Sec. 5 "Input Encoding"): inputs = its own hash grid of the
+ * position (same shape as StatNet's, 16) + one-blob w_o (8) + Box-Cox of the throughput (3) and
+ * of the pixel value (1) + one-blob remapped roughness with 4 bins (4) -> 32 -> 32 -> 32 -> 1,
+ * modified softplus.  Set (masters and inference copies; its Adam state cleared) or get
+ * (masters) aid[NRRS_AID_NPARAM] and its hash grid table_r (layout as StatNet's); either
+ * pointer may be NULL. */
+int32_t nrrs_set_aid_params(nrrs_ctx* ctx, const float* aid, const float* table_r);
+int32_t nrrs_get_aid_params(nrrs_ctx* ctx, float* aid, float* table_r);
+
 /* Test entry points (host arrays, synchronous).
+ * nrrs_debug_aid_forward: the AID-NRRS factor q[n] (and, if enc is not NULL, its 32 inputs
+ * enc[32n]) with the inference copies, vertices as in nrrs_debug_nrrs_forward.
+ * nrrs_debug_aid_grads: the AID-NRRS RRSNet's gradients (no Adam step): MLP into g_aid, its hash
+ * grid into g_table_r, loss as nrrs_nrrs_loss.loss_rrs; StatNet (masters) supplies the
+ * statistics of step 2; records as in nrrs_debug_nrrs_grads.
  * nrrs_debug_nrrs_forward: StatNet (m, v) into mv[2n], the factor into q[n] and, if enc is
  * not NULL, StatNet's 32 inputs into enc[32n], for vertices raw[7n] = (position in [0,1]^3,
  * w_o, remapped roughness), throughput t[3n] and pixel value I[n], with the inference copies.
@@ -262,6 +282,12 @@ int32_t nrrs_debug_nrrs_grads(nrrs_ctx* ctx, const float* raw, const float* I, c
                               const float* t, const float* q_norm, const float* F, const uint32_t* pix, uint32_t n,
                               const float* wpx, const uint32_t* k, uint32_t npx, int32_t rrs_step, float g_rrs,
                               float* g_stat, float* g_rrs_out, float* g_table, float* loss_stat, float* loss_rrs);
+int32_t nrrs_debug_aid_forward(nrrs_ctx* ctx, const float* raw, const float* t, const float* I, uint32_t n, float* q,
+                               float* enc);
+int32_t nrrs_debug_aid_grads(nrrs_ctx* ctx, const float* raw, const float* I, const float* lum_t, const float* t,
+                             const float* q_norm, const float* F, const uint32_t* pix, uint32_t n, const float* wpx,
+                             const uint32_t* k, uint32_t npx, int32_t rrs_step, float g_rrs, float* g_aid,
+                             float* g_table_r, float* loss);
 int32_t nrrs_debug_pixel_error(nrrs_ctx* ctx, const float* cur, float* acc, const float* ref, uint32_t w, uint32_t h,
                                int32_t first, float a_mix, int32_t radius, float var_scale, float g_avg, float g_min,
                                float* E, float* wpx, double* e_avg);

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 NPARAM = 9729
 MAXD = 64
-MODE_OFF, MODE_HEUR, MODE_NET, MODE_NRRS = 0, 1, 2, 3
+MODE_OFF, MODE_HEUR, MODE_NET, MODE_NRRS, MODE_AID = 0, 1, 2, 3, 4
 NORM_TWO_SIDED, NORM_DOWNSCALE = 0, 1
 MISS = 0xFFFFFFFF
 
@@ -42,7 +42,7 @@ class Cfg(C.Structure):
         ("alpha", C.c_double), ("p_train", C.c_double),
         ("rec_cap", C.c_uint32), ("update_guide", C.c_uint32),
         ("tau", C.c_double), ("net_depths", C.c_uint64), ("fixed_depths", C.c_uint64),
-        ("hash_log2", C.c_uint32),
+        ("hash_log2", C.c_uint32), ("nee", C.c_uint32),
     ]
 
 
@@ -105,6 +105,8 @@ def lib():
         L.or_ggx_sample.argtypes = [C.c_double, C.c_double, P, C.c_double, C.c_double, P, P, P]
         L.or_ggx_eval_cos.restype = C.c_double
         L.or_ggx_eval_cos.argtypes = [C.c_double, C.c_double, P, P]
+        L.or_ggx_pdf.restype = C.c_double
+        L.or_ggx_pdf.argtypes = [C.c_double, P, P]
         L.or_lambert_sample.argtypes = [C.c_double, C.c_double, P, P]
         _lib = L
     return _lib
@@ -196,14 +198,14 @@ def rrs_expand(q, u, budget_base, f_rate=1.0, alpha=1.0, norm_mode=NORM_TWO_SIDE
 def make_cfg(width, height, s_batch=1, max_depth=8, pass_begin=0, n_passes=1, mode=MODE_HEUR,
              norm_mode=NORM_TWO_SIDED, net_max_depth=4, cap_factor=2.0, f_rate=1.0, seed=0, alpha=1.0,
              p_train=0.0, rec_cap=0, update_guide=0, tau=1e-4, frozen=0, net_depths=None,
-             fixed_depths=0, hash_log2=0) -> Cfg:
+             fixed_depths=0, hash_log2=0, nee=0) -> Cfg:
     # Mix-Depth table (Sec. 4.3): bit d-1 set = network at depth d; default = depths 1..net_max_depth;
     # a bit of fixed_depths gives its depth the fixed rate instead (it wins over the network bit)
     if net_depths is None:
         net_depths = (1 << net_max_depth) - 1
     return Cfg(width, height, s_batch, max_depth, pass_begin, n_passes, mode, norm_mode, net_max_depth, frozen,
                cap_factor, f_rate, seed, alpha, p_train, rec_cap, update_guide, tau, net_depths, fixed_depths,
-               hash_log2)
+               hash_log2, nee)
 
 
 def render(sc: OracleScene, cfg: Cfg, params=None, guide=None, image=None, records=False, paths=False):
@@ -364,6 +366,10 @@ def ggx_sample(alpha, f0, wo, u1, u2):
     ok = lib().or_ggx_sample(float(alpha), float(f0), _p(_c(wo, np.float64)), float(u1), float(u2), _p(wi), _p(w),
                              _p(pdf))
     return bool(ok), wi, float(w[0]), float(pdf[0])
+
+
+def ggx_pdf(alpha, wo, wi):
+    return float(lib().or_ggx_pdf(float(alpha), _p(_c(wo, np.float64)), _p(_c(wi, np.float64))))
 
 
 def ggx_eval_cos(alpha, f0, wo, wi):

@@ -401,3 +401,65 @@ double or_rrsnet_nrrs_grad(const double* Pr, const double* Ps, const double* tab
   }
   return step == 1 ? (n ? loss / (double)n : 0.0) : loss;
 }
+
+/* ------------------------------------------------------------- RRSNet (AID-NRRS variant)
+ * Sec. 4.2.1 and Sec. 5 "Input Encoding": RRSNet reads the vertex itself instead of StatNet's
+ * statistics, through an input module of its own: a hash grid of p (same shape as StatNet's,
+ * separate trainable table) (16), one-blob of w_o's spherical coordinates with 4 bins each (8),
+ * Box-Cox of the throughput (3) and of the pixel value (1), one-blob of the remapped roughness
+ * with 4 bins (4): 32 inputs -> 32 -> 32 -> 32 -> 1, modified softplus.  StatNet only
+ * supervises: its statistics enter the gradient transfer, not the factor. */
+void or_aid_encode(const double* table, uint32_t log2T, const double* raw, const double* t, double I, double* enc) {
+  or_hashgrid_encode(table, log2T, raw, enc);
+  double wz = raw[5];
+  if (wz > 1.0) wz = 1.0;
+  if (wz < -1.0) wz = -1.0;
+  or_oneblob(acos(wz) / M_PI, 4, enc + 16);
+  or_oneblob(atan2(raw[4], raw[3]) / (2.0 * M_PI) + 0.5, 4, enc + 20);
+  enc[24] = box_cox(t[0]);
+  enc[25] = box_cox(t[1]);
+  enc[26] = box_cox(t[2]);
+  enc[27] = box_cox(I);
+  or_oneblob(raw[6], 4, enc + 28);
+}
+
+double or_aid_factor(const double* Pa, const double* table, uint32_t log2T, const double* raw, const double* t,
+                     double I, double* z_out) {
+  double enc[OR_AID_IN], z;
+  or_aid_encode(table, log2T, raw, t, I, enc);
+  or_mlp32_forward(Pa, OR_AID_IN, 1, enc, &z);
+  if (z_out) *z_out = z;
+  return or_softplus_mod(z);
+}
+
+/* AID-NRRS RRSNet gradient: as or_rrsnet_nrrs_grad (step 1 toward 1, step 2 the transfer of
+ * Eqs. 17-18 with StatNet's statistics), into the MLP (dPa) and its own hash grid (dtable). */
+double or_aid_grad(const double* Pa, const double* table_r, const double* Ps, const double* table_s, uint32_t log2T,
+                   const double* raw, const double* t_rgb, const double* I_px, const double* lum_t,
+                   const double* q_norm, const double* F, const uint32_t* pix, const uint32_t* k_pix,
+                   const double* wpx, uint64_t n, int32_t step, double g_rrs, double eps, double* dPa,
+                   double* dtable_r) {
+  double loss = 0.0;
+  for (uint64_t r = 0; r < n; ++r) {
+    const double* rr = raw + OR_STAT_RAW * r;
+    double enc[OR_AID_IN], denc[OR_AID_IN], z;
+    or_aid_encode(table_r, log2T, rr, t_rgb + 3 * r, I_px[r], enc);
+    or_mlp32_forward(Pa, OR_AID_IN, 1, enc, &z);
+    const double q = or_softplus_mod(z);
+    double dq;
+    if (step == 1) {
+      loss += (q - 1.0) * (q - 1.0) / (1.0 + eps);
+      dq = 2.0 * (q - 1.0) / (1.0 + eps) / (double)n;
+    } else {
+      if (!(q_norm[r] > 0.0)) continue;
+      double mv[OR_STAT_OUT];
+      or_statnet_forward(Ps, table_s, log2T, rr, mv);
+      loss += g_rrs * (q - q_norm[r]) * (q - q_norm[r]);
+      dq = or_nrrs_dloss_dq(wpx[pix[r]], k_pix[pix[r]], lum_t[r], mv, q_norm[r], F[r], q, g_rrs);
+    }
+    const double dz = dq * or_softplus_mod_grad(z);
+    or_mlp32_backward(Pa, OR_AID_IN, 1, enc, &dz, dPa, denc);
+    if (dtable_r) or_hashgrid_backward(log2T, rr, denc, dtable_r);
+  }
+  return step == 1 ? (n ? loss / (double)n : 0.0) : loss;
+}

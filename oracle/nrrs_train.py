@@ -12,7 +12,7 @@ import numpy as np
 from . import _c, _p, lib as _base_lib
 
 HG_LEVELS, HG_FEAT, HG_BASE = 8, 2, 16
-STAT_RAW, STAT_IN, STAT_OUT, RRS_IN = 7, 32, 2, 7
+STAT_RAW, STAT_IN, STAT_OUT, RRS_IN, AID_IN = 7, 32, 2, 7, 32
 
 _ready = False
 
@@ -44,6 +44,11 @@ def lib():
         L.or_nrrs_pixel_weights.argtypes = [P, P, P, U32, U32, I32, D, I32, D, D, D, D, P, P]
         L.or_rrsnet_nrrs_grad.restype = D
         L.or_rrsnet_nrrs_grad.argtypes = [P, P, P, U32, P, P, P, P, P, P, P, P, P, U64, I32, D, D, P]
+        L.or_aid_encode.argtypes = [P, U32, P, P, D, P]
+        L.or_aid_factor.restype = D
+        L.or_aid_factor.argtypes = [P, P, U32, P, P, D, P]
+        L.or_aid_grad.restype = D
+        L.or_aid_grad.argtypes = [P, P, P, P, U32, P, P, P, P, P, P, P, P, P, U64, I32, D, D, P, P]
         _ready = True
     return L
 
@@ -184,3 +189,43 @@ def rrsnet_nrrs_grad(Pr, Ps, table, log2T: int, raw, t_rgb, I_px, lum_t, q_norm,
     loss = lib().or_rrsnet_nrrs_grad(_p(Pr), _p(Ps), _p(tb), int(log2T), _p(raw), *[_p(a) for a in args],
                                      _p(pix), _p(k_pix), _p(wpx), n, int(step), float(g_rrs), float(eps), _p(dPr))
     return float(loss), dPr
+
+
+def aid_encode(table, log2T: int, raw, t, I) -> np.ndarray:
+    tb = _c(table, np.float64)
+    raw = _c(raw, np.float64).reshape(-1, STAT_RAW)
+    t = _c(t, np.float64).reshape(-1, 3)
+    I = _c(I, np.float64).ravel()
+    out = np.zeros((raw.shape[0], AID_IN))
+    for r in range(raw.shape[0]):
+        lib().or_aid_encode(_p(tb), int(log2T), _p(raw[r]), _p(t[r]), float(I[r]), _p(out[r]))
+    return out
+
+
+def aid_factor(Pa, table, log2T: int, raw, t, I):
+    """AID-NRRS factor q and pre-activation z per vertex."""
+    Pa, tb = _c(Pa, np.float64), _c(table, np.float64)
+    raw = _c(raw, np.float64).reshape(-1, STAT_RAW)
+    t = _c(t, np.float64).reshape(-1, 3)
+    I = _c(I, np.float64).ravel()
+    n = raw.shape[0]
+    q, z = np.zeros(n), np.zeros(n)
+    zz = C.c_double()
+    for r in range(n):
+        q[r] = lib().or_aid_factor(_p(Pa), _p(tb), int(log2T), _p(raw[r]), _p(t[r]), float(I[r]), C.byref(zz))
+        z[r] = zz.value
+    return q, z
+
+
+def aid_grad(Pa, table_r, Ps, table_s, log2T: int, raw, t_rgb, I_px, lum_t, q_norm, F, pix, k_pix, wpx, step: int,
+             g_rrs=0.01, eps=0.01):
+    Pa, tr, Ps, ts = (_c(a, np.float64) for a in (Pa, table_r, Ps, table_s))
+    raw = _c(raw, np.float64).reshape(-1, STAT_RAW)
+    n = raw.shape[0]
+    args = [_c(t_rgb, np.float64).reshape(-1, 3), _c(I_px, np.float64), _c(lum_t, np.float64),
+            _c(q_norm, np.float64), _c(F, np.float64)]
+    pix, k_pix, wpx = _c(pix, np.uint32), _c(k_pix, np.uint32), _c(wpx, np.float64)
+    dPa, dT = np.zeros_like(Pa), np.zeros_like(tr)
+    loss = lib().or_aid_grad(_p(Pa), _p(tr), _p(Ps), _p(ts), int(log2T), _p(raw), *[_p(a) for a in args], _p(pix),
+                             _p(k_pix), _p(wpx), n, int(step), float(g_rrs), float(eps), _p(dPa), _p(dT))
+    return float(loss), dPa, dT

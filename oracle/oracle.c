@@ -31,6 +31,7 @@
 #define PURPOSE_ROULETTE 1u
 #define PURPOSE_CHILD 2u
 #define PURPOSE_TRAIN 3u
+#define PURPOSE_NEE 4u
 
 static const double LUM[3] = {0.2126, 0.7152, 0.0722}; /* Rec. 709 luminance */
 
@@ -112,6 +113,13 @@ struct or_scene {
   bnode* nodes;
   uint64_t nnodes;
   uint32_t* order;
+  /* lights for next-event estimation: the triangles whose material emits, chosen with
+   * probability proportional to lum(L_e) x area (CDF over them), a point uniform on the chosen
+   * triangle; lpdf[p] = that probability per unit area (lum(L_e) / sum), 0 for non-emitters */
+  uint32_t nl;
+  uint32_t* light_tri;
+  double* light_cdf;  /* nl + 1 entries, 0 .. 1 */
+  double* lpdf;       /* nt */
 };
 
 static void tri_bounds(const or_scene* s, uint32_t p, double lo[3], double hi[3]) {
@@ -236,6 +244,34 @@ or_scene* or_scene_create(const float* verts, uint64_t nv, const uint32_t* tris,
     s->perr_max = ns ? 0.25 * h[ns / 2] : 0.0;
     free(h);
   }
+  {
+    s->lpdf = (double*)calloc(nt, sizeof(double));
+    s->light_tri = (uint32_t*)malloc(sizeof(uint32_t) * nt);
+    s->light_cdf = (double*)malloc(sizeof(double) * (nt + 1));
+    double total = 0.0;
+    s->nl = 0;
+    s->light_cdf[0] = 0.0;
+    for (uint64_t i = 0; i < nt; ++i) {
+      const double* mp = s->mpar + 7 * (uint64_t)s->tmat[i];
+      const double le = lum3(mp + 4);
+      if (!(le > 0.0)) continue;
+      const double* v = s->tri + 9 * i;
+      double e1[3], e2[3], cr[3];
+      sub3(v + 3, v, e1);
+      sub3(v + 6, v, e2);
+      cross3(e1, e2, cr);
+      const double area = 0.5 * sqrt(dot3(cr, cr));
+      if (!(area > 0.0)) continue;
+      total += le * area;
+      s->light_tri[s->nl] = (uint32_t)i;
+      s->light_cdf[++s->nl] = total;
+    }
+    for (uint32_t k = 1; k <= s->nl; ++k) s->light_cdf[k] /= total;
+    for (uint32_t k = 0; k < s->nl; ++k) {
+      const uint32_t i = s->light_tri[k];
+      s->lpdf[i] = lum3(s->mpar + 7 * (uint64_t)s->tmat[i] + 4) / total;
+    }
+  }
   if (build_bvh) {
     s->order = (uint32_t*)malloc(sizeof(uint32_t) * nt);
     for (uint64_t i = 0; i < nt; ++i) s->order[i] = (uint32_t)i;
@@ -249,6 +285,7 @@ or_scene* or_scene_create(const float* verts, uint64_t nv, const uint32_t* tris,
 void or_scene_destroy(or_scene* s) {
   if (!s) return;
   free(s->tri); free(s->tmat); free(s->mtype); free(s->mpar); free(s->nodes); free(s->order);
+  free(s->lpdf); free(s->light_tri); free(s->light_cdf);
   free(s);
 }
 
@@ -502,6 +539,16 @@ void or_lambert_sample(double u1, double u2, double wi[3], double* pdf) {
   wi[2] = sqrt(fmax(0.0, 1.0 - u1));
   *pdf = wi[2] / M_PI;
 }
+
+/* Solid-angle pdf of visible-normal GGX sampling for the direction wi (local frame). */
+static double ggx_pdf(double alpha, const double wo[3], const double wi[3]) {
+  if (wo[2] <= 0.0 || wi[2] <= 0.0) return 0.0;
+  double h[3] = {wo[0] + wi[0], wo[1] + wi[1], wo[2] + wi[2]};
+  normalize3(h);
+  return or_ggx_G1(alpha, wo) * or_ggx_D(alpha, h) / (4.0 * wo[2]);
+}
+
+double or_ggx_pdf(double alpha, const double wo[3], const double wi[3]) { return ggx_pdf(alpha, wo, wi); }
 
 /* ---------------------------------------------------------------- network */
 #define W1 0
@@ -934,6 +981,7 @@ typedef struct {
   double perr, derr, kerr;
   uint32_t pix, excl, id_lo, id_hi;
   uint32_t k0; /* primary path this entry descends from (index within its pass) */
+  double pdfb;  /* solid-angle pdf with which the BSDF sampled this entry's direction (0: camera) */
   int32_t rec[MAXREC];
   uint8_t dead, train;
 } entry;
@@ -949,6 +997,10 @@ typedef struct {
   uint32_t mat;
   double q;
   float q32;
+  /* next-event estimation at this vertex: radiance arriving from the light sample (before the
+   * throughput), and whether a near-tie decision took part in it */
+  double nee[3];
+  uint8_t has_nee, nee_fragile;
 } vstate;
 
 static void camera_ray(const or_scene* s, uint32_t W, uint32_t H, uint32_t px, uint32_t py, double u0, double u1,
@@ -1039,6 +1091,8 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
     v->q32 = 0.0f;
     v->perr = 0.0;
     v->kq = 0.0;
+    v->has_nee = 0;
+    v->nee_fragile = 0;
     if (Q[i].dead) { v->prim = MISS; continue; }
     rays++;
     double gerr = 0.0;
@@ -1052,8 +1106,9 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
   int fixed = cfg->mode != OR_MODE_OFF && depth <= 64 && ((cfg->fixed_depths >> (depth - 1)) & 1u);
   int net = !fixed && cfg->mode == OR_MODE_NET && depth <= 64 && ((cfg->net_depths >> (depth - 1)) & 1u) &&
             c->params != NULL;
-  int nrrs = !fixed && cfg->mode == OR_MODE_NRRS && depth <= 64 && ((cfg->net_depths >> (depth - 1)) & 1u) &&
-             c->params != NULL && cfg->hash_log2 > 0;
+  int nrrs = !fixed && (cfg->mode == OR_MODE_NRRS || cfg->mode == OR_MODE_AID) && depth <= 64 &&
+             ((cfg->net_depths >> (depth - 1)) & 1u) && c->params != NULL && cfg->hash_log2 > 0;
+  const int aid = cfg->mode == OR_MODE_AID;
   for (uint64_t i = 0; i < n; ++i) {
     entry* e = &Q[i];
     vstate* v = &V[i];
@@ -1093,7 +1148,17 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
     for (int k = 0; k < 3; ++k) v->n[k] = front ? ng[k] : -ng[k];
     v->mat = s->tmat[v->prim];
     const double* mp = s->mpar + 7 * (uint64_t)v->mat;
-    if (front && (mp[4] != 0.0 || mp[5] != 0.0 || mp[6] != 0.0)) add_emission(c, e, mp + 4, depth);
+    if (front && (mp[4] != 0.0 || mp[5] != 0.0 || mp[6] != 0.0)) {
+      if (cfg->nee && depth > 1 && e->pdfb > 0.0) {
+        /* a BSDF-sampled hit on a light: power-heuristic weight against light sampling */
+        const double pl = s->lpdf[v->prim] * v->thit * v->thit / cos_o;
+        const double w = e->pdfb * e->pdfb / (e->pdfb * e->pdfb + pl * pl);
+        const double le[3] = {w * mp[4], w * mp[5], w * mp[6]};
+        add_emission(c, e, le, depth);
+      } else {
+        add_emission(c, e, mp + 4, depth);
+      }
+    }
     if (depth >= D || s->mtype[v->mat] == 2) continue; /* last vertex or pure emitter: terminate */
     if (cfg->mode == OR_MODE_OFF) {
       v->q = 1.0;
@@ -1115,6 +1180,90 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
       c->rec_pix[r] = e->pix;
       c->rec_id[r] = ((uint64_t)e->id_hi << 32) | e->id_lo;
       e->rec[depth - 1] = (int32_t)r;
+    }
+  }
+  if (cfg->nee && s->nl > 0) {
+    /* next-event estimation at every vertex that may continue (d < D, not a pure emitter): one
+     * light sample, a shadow ray from the offset hit point, power-heuristic weight against the
+     * BSDF's sampling of the same direction */
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < (int64_t)n; ++i) {
+      entry* e = &Q[i];
+      vstate* v = &V[i];
+      if (e->dead || v->prim == MISS || depth >= D || s->mtype[v->mat] == 2) continue;
+      uint32_t r[4];
+      rng_block(cfg->seed, e->id_lo, e->id_hi, PURPOSE_NEE, depth, 0, r);
+      const double u0 = u01(r[0]), u1 = u01(r[1]), u2 = u01(r[2]);
+      uint32_t lo = 0, hi = s->nl - 1; /* smallest k with cdf[k + 1] > u0 */
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (s->light_cdf[mid + 1] > u0) hi = mid; else lo = mid + 1;
+      }
+      int frag = 0;
+      /* the float32 CDF may put a boundary this close to u0 on the other side */
+      if (tau > 0.0 && ((lo > 0 && u0 - s->light_cdf[lo] < 1e-6) || s->light_cdf[lo + 1] - u0 < 1e-6)) frag = 1;
+      const uint32_t lt = s->light_tri[lo];
+      const double* tv = s->tri + 9 * (uint64_t)lt;
+      double e1[3], e2[3], ng[3], y[3];
+      sub3(tv + 3, tv, e1);
+      sub3(tv + 6, tv, e2);
+      cross3(e1, e2, ng);
+      normalize3(ng);
+      const double su = sqrt(u1);
+      const double b1 = su * (1.0 - u2), b2 = su * u2;
+      for (int k = 0; k < 3; ++k) y[k] = tv[k] + b1 * e1[k] + b2 * e2[k];
+      double o[3], d[3];
+      for (int k = 0; k < 3; ++k) o[k] = v->p[k] + s->offset * v->n[k];
+      sub3(y, o, d);
+      const double dist = sqrt(dot3(d, d));
+      if (!(dist > 0.0)) continue;
+      for (int k = 0; k < 3; ++k) d[k] /= dist;
+      const double cos_x = dot3(v->n, d), cos_l = -dot3(ng, d);
+      if (tau > 0.0 && (fabs(cos_x) < tau || fabs(cos_l) < tau)) frag = 1;
+      /* a light point this close to the vertex: the float32 direction (from two rounded points)
+       * carries a relative error beyond the comparison's reach */
+      if (tau > 0.0 && (v->perr + 2.0 * F32_UNIT * s->extent) / dist > 2e-5) frag = 1;
+      v->nee_fragile = (uint8_t)frag;
+      if (cos_x <= 0.0 || cos_l <= 0.0) continue;
+      /* BSDF value (times cos) and sampling pdf of d at the vertex */
+      const double* mp = s->mpar + 7 * (uint64_t)v->mat;
+      double tb[3], bb[3];
+      onb(v->n, tb, bb);
+      const double wol[3] = {dot3(v->wo, tb), dot3(v->wo, bb), dot3(v->wo, v->n)};
+      const double wil[3] = {dot3(d, tb), dot3(d, bb), cos_x};
+      double fc[3], pb;
+      if (s->mtype[v->mat] == 1) {
+        for (int k = 0; k < 3; ++k) fc[k] = or_ggx_eval_cos(mp[3], mp[k], wol, wil);
+        pb = ggx_pdf(mp[3], wol, wil);
+      } else {
+        for (int k = 0; k < 3; ++k) fc[k] = mp[k] / M_PI * cos_x;
+        pb = cos_x / M_PI;
+      }
+      const double pl = s->lpdf[lt] * dist * dist / cos_l;
+      const double w = pl * pl / (pl * pl + pb * pb);
+      /* visibility: nothing closer than the light point (shortened by 1e-4 of the distance) */
+      uint32_t prim;
+      double th, hb1, hb2, gerr;
+      const double derr = 2.0 * v->perr / dist + 16.0 * F32_UNIT;
+      int tf = trace_one(s, o, d, v->prim, s->nodes != NULL, tau, v->perr, derr, &prim, &th, &hb1, &hb2, &gerr);
+      const double tmax = dist * (1.0 - 1e-4);
+      if (tau > 0.0 && (tf || (prim != MISS && fabs(th - tmax) < tau * tmax + v->perr + derr * th))) frag = 1;
+      v->nee_fragile = (uint8_t)frag;
+      if (prim != MISS && th < tmax) continue; /* occluded */
+      const double* le = s->mpar + 7 * (uint64_t)s->tmat[lt] + 4;
+      for (int k = 0; k < 3; ++k) v->nee[k] = fc[k] * le[k] * w / pl;
+      v->has_nee = 1;
+    }
+    /* in slot order: the radiance (with the vertex's throughput) to the image, the path and the
+     * records of the vertex's ancestors (its own record does not see its own light sample) */
+    for (uint64_t i = 0; i < n; ++i) {
+      entry* e = &Q[i];
+      vstate* v = &V[i];
+      if (v->nee_fragile) mark_fragile(c, e, depth);
+      if (!v->has_nee) continue;
+      entry anc = *e;
+      if (depth <= MAXREC) anc.rec[depth - 1] = -1;
+      add_emission(c, &anc, v->nee, depth);
     }
   }
   if (net) {
@@ -1140,7 +1289,8 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
   }
   if (nrrs) {
     /* NRRS (Sec. 4.2): StatNet's statistics of the vertex, then RRSNet's factor, with the pixel's
-     * previous mean as I_px; no pixel history keeps the heuristic */
+     * previous mean as I_px; AID-NRRS: the AID RRSNet alone (params = its MLP and hash grid); no
+     * pixel history keeps the heuristic */
     const double* Ps = c->params;
     const double* Pr = Ps + OR_STAT_NPARAM;
     const double* Tb = Pr + OR_RRS_NPARAM;
@@ -1156,7 +1306,9 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
       for (int k = 0; k < 3; ++k) raw[k] = (v->p[k] - s->amin[k]) / s->extent;
       for (int k = 0; k < 3; ++k) raw[3 + k] = v->wo[k];
       raw[6] = 1.0 - exp(-(s->mtype[v->mat] == 1 ? mp[3] : 1.0));
-      const double q = or_nrrs_factor(Ps, Pr, Tb, cfg->hash_log2, raw, e->t, g, NULL, NULL);
+#define FACTOR(RAW, T) (aid ? or_aid_factor(Ps, Ps + OR_AID_NPARAM, cfg->hash_log2, RAW, T, g, NULL) \
+                            : or_nrrs_factor(Ps, Pr, Tb, cfg->hash_log2, RAW, T, g, NULL, NULL))
+      const double q = FACTOR(raw, e->t);
       if (!(q >= 1e-20 && q < 3e38)) continue; /* a factor out of range keeps the heuristic */
       /* float32 error of the factor from its inputs' errors: the change of q when the position
        * moves by twice its error bound, the direction by twice its bound, the throughput by
@@ -1170,16 +1322,15 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
         memcpy(rm, raw, sizeof(rm));
         rp[k] += h;
         rm[k] -= h;
-        dq += fabs(or_nrrs_factor(Ps, Pr, Tb, cfg->hash_log2, rp, e->t, g, NULL, NULL) -
-                   or_nrrs_factor(Ps, Pr, Tb, cfg->hash_log2, rm, e->t, g, NULL, NULL));
+        dq += fabs(FACTOR(rp, e->t) - FACTOR(rm, e->t));
       }
       double tp[3], tm[3];
       for (int k = 0; k < 3; ++k) {
         tp[k] = e->t[k] * (1.0 + 2.0 * e->kerr);
         tm[k] = e->t[k] * (1.0 - 2.0 * e->kerr);
       }
-      dq += fabs(or_nrrs_factor(Ps, Pr, Tb, cfg->hash_log2, raw, tp, g, NULL, NULL) -
-                 or_nrrs_factor(Ps, Pr, Tb, cfg->hash_log2, raw, tm, g, NULL, NULL));
+      dq += fabs(FACTOR(raw, tp) - FACTOR(raw, tm));
+#undef FACTOR
       v->q = q;
       v->kq += dq / q;
     }
@@ -1223,6 +1374,7 @@ static void expand_children(rctx* c, const entry* Q, const vstate* V, uint64_t n
         for (int k = 0; k < 3; ++k) w[k] = mp[k];
       }
       entry* ch = &Qn[off[i] + j];
+      ch->pdfb = pdf;
       double wi[3];
       for (int k = 0; k < 3; ++k) wi[k] = wil[0] * tb[k] + wil[1] * bb[k] + wil[2] * v->n[k];
       normalize3(wi);
@@ -1300,6 +1452,7 @@ int32_t or_render(const or_scene* s, or_cfg* cfg, const double* params, double* 
       e->perr = F32_UNIT * fmax(fabs(e->o[0]), fmax(fabs(e->o[1]), fabs(e->o[2])));
       e->derr = 16.0 * F32_UNIT;
       e->kerr = 0.0;
+      e->pdfb = 0.0;
       e->pix = pix;
       e->k0 = (uint32_t)k;
       e->excl = MISS;
@@ -1457,6 +1610,7 @@ int32_t or_enumerate(const or_scene* s, const or_cfg* cfg, double* image_expect,
     camera_ray(s, cfg->width, cfg->height, pix % cfg->width, pix / cfg->width, u01(r[0]), u01(r[1]), e->o, e->d);
     e->t[0] = e->t[1] = e->t[2] = 1.0;
     e->perr = e->derr = e->kerr = 0.0;
+    e->pdfb = 0.0;
     e->pix = pix; e->k0 = (uint32_t)k; e->excl = MISS; e->id_lo = (uint32_t)k; e->id_hi = pass;
     for (int j = 0; j < MAXREC; ++j) e->rec[j] = -1;
     e->dead = 0; e->train = 0;

@@ -28,10 +28,11 @@ extern "C" {
 #define OR_NPARAM 9729   /* 20-64-64-64-1 MLP */
 #define OR_STAT_NPARAM 3234 /* StatNet: 32 -> 32 -> 32 -> 32 -> 2 */
 #define OR_RRS_NPARAM 2401  /* RRSNet (NRRS): 7 -> 32 -> 32 -> 32 -> 1 */
+#define OR_AID_NPARAM 3201  /* RRSNet (AID-NRRS): 32 -> 32 -> 32 -> 32 -> 1 */
 #define OR_NFEAT 20
 #define OR_MAXD 64
 
-enum { OR_MODE_OFF = 0, OR_MODE_HEUR = 1, OR_MODE_NET = 2, OR_MODE_NRRS = 3 };
+enum { OR_MODE_OFF = 0, OR_MODE_HEUR = 1, OR_MODE_NET = 2, OR_MODE_NRRS = 3, OR_MODE_AID = 4 };
 enum { OR_NORM_TWO_SIDED = 0, OR_NORM_DOWNSCALE = 1 };
 
 typedef struct or_scene or_scene;
@@ -53,7 +54,10 @@ typedef struct {
                             continues gets the raw factor 1 (HEUR and NET modes; before the network) */
   uint32_t hash_log2;    /* NRRS mode (Sec. 4.2): params = StatNet (OR_STAT_NPARAM), RRSNet
                             (OR_RRS_NPARAM) and the hash grid [8][2^hash_log2][2], concatenated; the
-                            NRRS factor replaces the heuristic at the depths of net_depths */
+                            NRRS factor replaces the heuristic at the depths of net_depths; AID mode:
+                            params = the AID-NRRS RRSNet (OR_AID_NPARAM) and its hash grid */
+  uint32_t nee;          /* 1: next-event estimation at every vertex that may continue (one light
+                            sample, shadow ray, power-heuristic MIS with the BSDF-sampled hits) */
 } or_cfg;
 
 typedef struct {
@@ -164,6 +168,8 @@ double or_ggx_G2(double alpha, const double wo[3], const double wi[3]);
 int32_t or_ggx_sample(double alpha, double f0, const double wo[3], double u1, double u2,
                       double wi[3], double* weight, double* pdf);
 double or_ggx_eval_cos(double alpha, double f0, const double wo[3], const double wi[3]);
+/* Solid-angle pdf of the visible-normal sampling of or_ggx_sample for the direction wi. */
+double or_ggx_pdf(double alpha, const double wo[3], const double wi[3]);
 void or_lambert_sample(double u1, double u2, double wi[3], double* pdf);
 
 /* ------------------------------------------------ NRRS training proper (nrrs_train.c)
@@ -197,6 +203,15 @@ double or_nrrs_dloss_dq(double wpx, uint32_t k, double lum_t, const double* mv, 
 double or_nrrs_pixel_weights(const double* cur, double* acc, const double* ref, uint32_t w, uint32_t h,
                              int32_t first, double a_mix, int32_t radius, double var_scale, double g_avg,
                              double g_min, double eps, double* E, double* wpx);
+#define OR_AID_IN 32    /* AID-NRRS RRSNet inputs: 16 hash grid + 8 one-blob w_o + 4 Box-Cox + 4 one-blob */
+void or_aid_encode(const double* table, uint32_t log2T, const double* raw, const double* t, double I, double* enc);
+double or_aid_factor(const double* Pa, const double* table, uint32_t log2T, const double* raw, const double* t,
+                     double I, double* z_out);
+double or_aid_grad(const double* Pa, const double* table_r, const double* Ps, const double* table_s, uint32_t log2T,
+                   const double* raw, const double* t_rgb, const double* I_px, const double* lum_t,
+                   const double* q_norm, const double* F, const uint32_t* pix, const uint32_t* k_pix,
+                   const double* wpx, uint64_t n, int32_t step, double g_rrs, double eps, double* dPa,
+                   double* dtable_r);
 double or_rrsnet_nrrs_grad(const double* Pr, const double* Ps, const double* table, uint32_t log2T,
                            const double* raw, const double* t_rgb, const double* I_px, const double* lum_t,
                            const double* q_norm, const double* F, const uint32_t* pix, const uint32_t* k_pix,

@@ -88,13 +88,13 @@ struct nrrs_ctx {
   struct NetState {
     float *w = nullptr, *infer = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
   };
-  NetState nstat{}, nrrs_net{}, ntab{};
+  NetState nstat{}, nrrs_net{}, ntab{}, naid{}, ntab_r{};  // naid, ntab_r: the AID-NRRS RRSNet
   uint64_t ntab_n = 0;  // floats of the hash grid
-  float *npartial = nullptr, *nloss_part = nullptr, *nloss = nullptr;
+  float *npartial = nullptr, *nloss_part = nullptr, *nloss = nullptr, *ngroups = nullptr;
   double *lum_start = nullptr, *pix_part = nullptr, *eavg = nullptr;
   float *pcur = nullptr, *pref = nullptr, *pacc = nullptr, *pEp = nullptr, *pE = nullptr, *pwpx = nullptr;
   uint32_t* kpix = nullptr;
-  uint64_t nrrs_step = 0, nrrs_rstep = 0, nrrs_frames = 0, nrrs_spp_start = 0;
+  uint64_t nrrs_step = 0, nrrs_rstep = 0, nrrs_astep = 0, nrrs_frames = 0, nrrs_spp_start = 0;
   // scene
   bool bound = false, scene = false;
   DevScene sc{};
@@ -216,10 +216,13 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
     state(c->nstat, kStatParams);
     state(c->nrrs_net, kRrsParams);
     state(c->ntab, c->ntab_n);
+    state(c->naid, kAidParams);
+    state(c->ntab_r, c->ntab_n);
     const uint64_t nb = nrrs_grad_blocks((uint32_t)std::max<uint64_t>(rc, 1));
-    c->npartial = k.take<float>(nb * std::max(kStatParams, kRrsParams));
+    c->npartial = k.take<float>(nb * std::max(kStatParams, std::max(kRrsParams, kAidParams)));
     c->nloss_part = k.take<float>(nb);
     c->nloss = k.take<float>(2);
+    c->ngroups = k.take<float>((uint64_t)nrrs_sum_groups() * std::max(kStatParams, std::max(kRrsParams, kAidParams)));
     c->lum_start = k.take<double>(npx);
     c->pix_part = k.take<double>(2 * ((npx + 255) / 256));
     c->eavg = k.take<double>(1);
@@ -277,7 +280,7 @@ void init_params(uint64_t seed, std::vector<float>& w) {
 // z >= 0: z / 2 + ln 2); hash-grid features uniform in [-1e-4, 1e-4].  Philox counters
 // (index, stream, 7, 0) keep the three vectors independent of the NET weights.
 void init_nrrs_params(uint64_t seed, std::vector<float>& stat, std::vector<float>& rrs, std::vector<float>& table,
-                      uint64_t table_n) {
+                      uint64_t table_n, std::vector<float>& aid, std::vector<float>& table_r) {
   auto uni = [&](uint32_t stream, uint64_t i) {
     uint32_t c[4] = {(uint32_t)i, stream, 7u, (uint32_t)(i >> 32)};
     philox_host(c, (uint32_t)seed, (uint32_t)(seed >> 32));
@@ -296,11 +299,16 @@ void init_nrrs_params(uint64_t seed, std::vector<float>& stat, std::vector<float
   mlp(stat, kStatIn, kStatOut, 1u);
   mlp(rrs, kRrsIn, 1, 2u);
   rrs[kRrsParams - 1] = 2.0f * (1.0f - 0.69314718055994531f);
+  mlp(aid, kAidIn, 1, 4u);
+  aid[kAidParams - 1] = 2.0f * (1.0f - 0.69314718055994531f);
   table.resize(table_n);
+  table_r.resize(table_n);
   for (uint64_t k = 0; k < table_n; ++k) table[k] = (2.0f * uni(3u, k) - 1.0f) * 1e-4f;
+  for (uint64_t k = 0; k < table_n; ++k) table_r[k] = (2.0f * uni(5u, k) - 1.0f) * 1e-4f;
 }
 
-int32_t upload_nrrs_state(nrrs_ctx* c, const float* stat, const float* rrs, const float* table) {
+int32_t upload_nrrs_state(nrrs_ctx* c, const float* stat, const float* rrs, const float* table,
+                          const float* aid = nullptr, const float* table_r = nullptr) {
   hipStream_t s = c->stream;
   auto put = [&](nrrs_ctx::NetState& st, const float* src, uint64_t n) -> int32_t {
     if (!src) return NRRS_OK;
@@ -314,10 +322,13 @@ int32_t upload_nrrs_state(nrrs_ctx* c, const float* stat, const float* rrs, cons
   int32_t r = put(c->nstat, stat, kStatParams);
   if (r == NRRS_OK) r = put(c->nrrs_net, rrs, kRrsParams);
   if (r == NRRS_OK) r = put(c->ntab, table, c->ntab_n);
+  if (r == NRRS_OK) r = put(c->naid, aid, kAidParams);
+  if (r == NRRS_OK) r = put(c->ntab_r, table_r, c->ntab_n);
   if (r != NRRS_OK) return r;
   HIPC(c, hipStreamSynchronize(s));
-  c->nrrs_step = 0;
-  c->nrrs_rstep = 0;
+  if (stat || table) c->nrrs_step = 0;
+  if (rrs) c->nrrs_rstep = 0;
+  if (aid || table_r) c->nrrs_astep = 0;
   return NRRS_OK;
 }
 
@@ -326,6 +337,8 @@ NrrsNet nrrs_net_args(nrrs_ctx* c, bool inference) {
   n.stat = inference ? c->nstat.infer : c->nstat.w;
   n.rrs = inference ? c->nrrs_net.infer : c->nrrs_net.w;
   n.table = inference ? c->ntab.infer : c->ntab.w;
+  n.aid = inference ? c->naid.infer : c->naid.w;
+  n.table_r = inference ? c->ntab_r.infer : c->ntab_r.w;
   n.log2T = c->cfg.hash_log2;
   return n;
 }
@@ -499,9 +512,9 @@ int32_t nrrs_bind_workspace(nrrs_ctx* c, void* device_ptr, uint64_t bytes, uint6
   c->passes_done = 0;
   c->adam_step = 0;
   if (c->cfg.hash_log2) {
-    std::vector<float> ws_, wr_, wt_;
-    init_nrrs_params(c->cfg.seed, ws_, wr_, wt_, c->ntab_n);
-    const int32_t r = upload_nrrs_state(c, ws_.data(), wr_.data(), wt_.data());
+    std::vector<float> ws_, wr_, wt_, wa_, wtr_;
+    init_nrrs_params(c->cfg.seed, ws_, wr_, wt_, c->ntab_n, wa_, wtr_);
+    const int32_t r = upload_nrrs_state(c, ws_.data(), wr_.data(), wt_.data(), wa_.data(), wtr_.data());
     if (r != NRRS_OK) return r;
     launch_zero_f64(c->lum_start, c->npx, s);
     c->nrrs_frames = 0;
@@ -710,8 +723,8 @@ int32_t nrrs_render(nrrs_ctx* c, uint32_t spp, uint32_t max_depth, int32_t mode,
   if (!c->scene) return fail(c, NRRS_ESTATE, "upload a scene first");
   if (spp == 0 || spp % c->cfg.s_batch != 0) return fail(c, NRRS_EINVAL, "spp must be a positive multiple of s_batch");
   if (max_depth < 1 || max_depth > NRRS_MAX_DEPTH) return fail(c, NRRS_EINVAL, "max_depth out of range");
-  if (mode < NRRS_MODE_OFF || mode > NRRS_MODE_NRRS) return fail(c, NRRS_EINVAL, "unknown mode");
-  if (mode == NRRS_MODE_NRRS && !c->cfg.hash_log2)
+  if (mode < NRRS_MODE_OFF || mode > NRRS_MODE_AID) return fail(c, NRRS_EINVAL, "unknown mode");
+  if ((mode == NRRS_MODE_NRRS || mode == NRRS_MODE_AID) && !c->cfg.hash_log2)
     return fail(c, NRRS_ESTATE, "NRRS mode needs a context created with hash_log2 > 0");
   if (c->trace_on && max_depth > c->cfg.trace_depth)
     return fail(c, NRRS_EINVAL, "max_depth beyond the traced depths");
@@ -775,8 +788,8 @@ int32_t nrrs_render(nrrs_ctx* c, uint32_t spp, uint32_t max_depth, int32_t mode,
       } else if (mode == NRRS_MODE_NET && ((c->net_depths >> (d - 1)) & 1u)) {
         launch_rrsnet(b, net, s);
         MARK(3);
-      } else if (mode == NRRS_MODE_NRRS && ((c->net_depths >> (d - 1)) & 1u)) {
-        launch_nrrs_factor(b, nnet, nrrs_blocks, s);
+      } else if ((mode == NRRS_MODE_NRRS || mode == NRRS_MODE_AID) && ((c->net_depths >> (d - 1)) & 1u)) {
+        launch_nrrs_factor(b, nnet, nrrs_blocks, mode == NRRS_MODE_AID, s);
         MARK(3);
       }
       launch_sum_q(b, s);
@@ -1167,13 +1180,33 @@ int32_t nrrs_get_nrrs_params(nrrs_ctx* c, float* stat, float* rrs, float* table)
   return NRRS_OK;
 }
 
+int32_t nrrs_set_aid_params(nrrs_ctx* c, const float* aid, const float* table_r) {
+  if (!c) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (!c->cfg.hash_log2) return fail(c, NRRS_ESTATE, "context created without NRRS (hash_log2 = 0)");
+  if ((aid && !finite_all(aid, kAidParams)) || (table_r && !finite_all(table_r, c->ntab_n)))
+    return fail(c, NRRS_EINVAL, "non-finite AID-NRRS parameter");
+  HIPC(c, hipStreamSynchronize(c->stream));
+  return upload_nrrs_state(c, nullptr, nullptr, nullptr, aid, table_r);
+}
+
+int32_t nrrs_get_aid_params(nrrs_ctx* c, float* aid, float* table_r) {
+  if (!c) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (!c->cfg.hash_log2) return fail(c, NRRS_ESTATE, "context created without NRRS (hash_log2 = 0)");
+  HIPC(c, hipStreamSynchronize(c->stream));
+  if (aid) HIPC(c, hipMemcpy(aid, c->naid.w, sizeof(float) * kAidParams, hipMemcpyDeviceToHost));
+  if (table_r) HIPC(c, hipMemcpy(table_r, c->ntab_r.w, sizeof(float) * c->ntab_n, hipMemcpyDeviceToHost));
+  return NRRS_OK;
+}
+
 namespace {
 bool train_args_ok(const nrrs_nrrs_train* hp) {
   auto pos = [](float x) { return x > 0.0f && std::isfinite(x); };
   auto nonneg = [](float x) { return x >= 0.0f && std::isfinite(x); };
   return hp && pos(hp->lr_stat) && pos(hp->lr_rrs) && nonneg(hp->g_avg) && nonneg(hp->g_min) &&
          nonneg(hp->g_rrs) && hp->a_mix > 0.0f && hp->a_mix <= 1.0f && hp->radius >= 0 && hp->radius <= 8 &&
-         (hp->rrs_step == 1 || hp->rrs_step == 2);
+         (hp->rrs_step == 1 || hp->rrs_step == 2) && hp->variant >= 0 && hp->variant <= 2;
 }
 }  // namespace
 
@@ -1195,7 +1228,7 @@ int32_t nrrs_train_step_nrrs(nrrs_ctx* c, uint32_t n_records, const nrrs_nrrs_tr
   const float decay = (float)c->cfg.ema_decay, eps = 0.01f;
   // StatNet (hash grid and MLP), Eq. (15)
   launch_statnet_grad(r, c->nstat.w, c->ntab.w, c->cfg.hash_log2, eps, c->npartial, c->nloss_part, c->ntab.g, s);
-  launch_partial_sum(c->npartial, nb, kStatParams, c->nstat.g, c->nloss_part, c->nloss, s);
+  launch_partial_sum(c->npartial, nb, kStatParams, c->nstat.g, c->nloss_part, c->nloss, c->ngroups, s);
   c->nrrs_step += 1;
   launch_adam(c->nstat.w, c->nstat.m, c->nstat.v, c->nstat.g, kStatParams, c->nrrs_step, hp->lr_stat, c->nstat.infer,
               decay, false, s);
@@ -1232,13 +1265,24 @@ int32_t nrrs_train_step_nrrs(nrrs_ctx* c, uint32_t n_records, const nrrs_nrrs_tr
   c->nrrs_spp_start = c->spp_total;
   // RRSNet with StatNet's updated weights
   const bool rrs_train = hp->rrs_step == 1 || has_ref;
-  if (rrs_train) {
+  if (rrs_train && (hp->variant == 0 || hp->variant == 2)) {
     launch_rrsnet_grad(r, c->nstat.w, c->ntab.w, c->cfg.hash_log2, c->nrrs_net.w, hp->rrs_step, c->pwpx, c->kpix,
                        hp->g_rrs, eps, c->npartial, c->nloss_part, s);
-    launch_partial_sum(c->npartial, nb, kRrsParams, c->nrrs_net.g, c->nloss_part, c->nloss + 1, s);
+    launch_partial_sum(c->npartial, nb, kRrsParams, c->nrrs_net.g, c->nloss_part, c->nloss + 1, c->ngroups, s);
     c->nrrs_rstep += 1;
     launch_adam(c->nrrs_net.w, c->nrrs_net.m, c->nrrs_net.v, c->nrrs_net.g, kRrsParams, c->nrrs_rstep, hp->lr_rrs,
                 c->nrrs_net.infer, decay, false, s);
+  }
+  if (rrs_train && (hp->variant == 1 || hp->variant == 2)) {
+    // AID-NRRS: RRSNet's MLP and its own hash grid (StatNet's statistics supervise)
+    launch_aid_grad(r, c->nstat.w, c->ntab.w, c->cfg.hash_log2, c->naid.w, c->ntab_r.w, hp->rrs_step, c->pwpx,
+                    c->kpix, hp->g_rrs, eps, c->npartial, c->nloss_part, c->ntab_r.g, s);
+    launch_partial_sum(c->npartial, nb, kAidParams, c->naid.g, c->nloss_part, c->nloss + 1, c->ngroups, s);
+    c->nrrs_astep += 1;
+    launch_adam(c->naid.w, c->naid.m, c->naid.v, c->naid.g, kAidParams, c->nrrs_astep, hp->lr_rrs, c->naid.infer,
+                decay, false, s);
+    launch_adam(c->ntab_r.w, c->ntab_r.m, c->ntab_r.v, c->ntab_r.g, c->ntab_n, c->nrrs_astep, hp->lr_rrs,
+                c->ntab_r.infer, decay, true, s);
   }
   HIPC(c, hipGetLastError());
   if (out) {
@@ -1277,6 +1321,32 @@ int32_t nrrs_debug_nrrs_forward(nrrs_ctx* c, const float* raw, const float* t, c
   HIPC(c, hipStreamSynchronize(s));
   HIPC(c, hipGetLastError());
   HIPC(c, hipMemcpy(mv, pmv, sizeof(float) * 2 * n, hipMemcpyDeviceToHost));
+  HIPC(c, hipMemcpy(q, pq, sizeof(float) * n, hipMemcpyDeviceToHost));
+  if (enc) HIPC(c, hipMemcpy(enc, penc, sizeof(float) * 32 * n, hipMemcpyDeviceToHost));
+  return NRRS_OK;
+}
+
+int32_t nrrs_debug_aid_forward(nrrs_ctx* c, const float* raw, const float* t, const float* I, uint32_t n, float* q,
+                               float* enc) {
+  if (!c || (n && (!raw || !t || !I || !q))) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (!c->cfg.hash_log2) return fail(c, NRRS_ESTATE, "context created without NRRS (hash_log2 = 0)");
+  if ((uint64_t)n * 4 * 44 + 4096 > c->qb_pool_bytes) return fail(c, NRRS_ENOMEM, "too many rows for the scratch space");
+  if (n == 0) return NRRS_OK;
+  hipStream_t s = c->stream;
+  HIPC(c, hipStreamSynchronize(s));
+  Carve k{c->qb_pool};
+  float* praw = k.take<float>(7ull * n);
+  float* pt = k.take<float>(3ull * n);
+  float* pI = k.take<float>(n);
+  float* pq = k.take<float>(n);
+  float* penc = enc ? k.take<float>(32ull * n) : nullptr;
+  HIPC(c, hipMemcpy(praw, raw, sizeof(float) * 7 * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(pt, t, sizeof(float) * 3 * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(pI, I, sizeof(float) * n, hipMemcpyHostToDevice));
+  launch_aid_rows(praw, pt, pI, n, nrrs_net_args(c, true), pq, penc, s);
+  HIPC(c, hipStreamSynchronize(s));
+  HIPC(c, hipGetLastError());
   HIPC(c, hipMemcpy(q, pq, sizeof(float) * n, hipMemcpyDeviceToHost));
   if (enc) HIPC(c, hipMemcpy(enc, penc, sizeof(float) * 32 * n, hipMemcpyDeviceToHost));
   return NRRS_OK;
@@ -1329,10 +1399,10 @@ int32_t nrrs_debug_nrrs_grads(nrrs_ctx* c, const float* raw, const float* I, con
   const uint32_t nb = nrrs_grad_blocks(n);
   launch_zero_u32((uint32_t*)c->ntab.g, c->ntab_n, s);
   launch_statnet_grad(r, c->nstat.w, c->ntab.w, c->cfg.hash_log2, 0.01f, c->npartial, c->nloss_part, c->ntab.g, s);
-  launch_partial_sum(c->npartial, nb, kStatParams, c->nstat.g, c->nloss_part, c->nloss, s);
+  launch_partial_sum(c->npartial, nb, kStatParams, c->nstat.g, c->nloss_part, c->nloss, c->ngroups, s);
   launch_rrsnet_grad(r, c->nstat.w, c->ntab.w, c->cfg.hash_log2, c->nrrs_net.w, rrs_step, pw, pk, g_rrs, 0.01f,
                      c->npartial, c->nloss_part, s);
-  launch_partial_sum(c->npartial, nb, kRrsParams, c->nrrs_net.g, c->nloss_part, c->nloss + 1, s);
+  launch_partial_sum(c->npartial, nb, kRrsParams, c->nrrs_net.g, c->nloss_part, c->nloss + 1, c->ngroups, s);
   HIPC(c, hipStreamSynchronize(s));
   HIPC(c, hipGetLastError());
   float l[2];
@@ -1344,6 +1414,62 @@ int32_t nrrs_debug_nrrs_grads(nrrs_ctx* c, const float* raw, const float* I, con
   *loss_rrs = l[1];
   // leave the training state as it was: the grid gradient starts each step at zero
   launch_zero_u32((uint32_t*)c->ntab.g, c->ntab_n, s);
+  HIPC(c, hipStreamSynchronize(s));
+  return NRRS_OK;
+}
+
+int32_t nrrs_debug_aid_grads(nrrs_ctx* c, const float* raw, const float* I, const float* lum_t, const float* t,
+                             const float* q_norm, const float* F, const uint32_t* pix, uint32_t n, const float* wpx,
+                             const uint32_t* kk, uint32_t npx, int32_t rrs_step, float g_rrs, float* g_aid,
+                             float* g_table_r, float* loss) {
+  if (!c || n == 0 || !raw || !I || !lum_t || !t || !q_norm || !F || !pix || npx == 0 || !wpx || !kk || !g_aid ||
+      !g_table_r || !loss || (rrs_step != 1 && rrs_step != 2) || !(g_rrs >= 0.0f))
+    return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "no workspace");
+  if (!c->cfg.hash_log2) return fail(c, NRRS_ESTATE, "context created without NRRS (hash_log2 = 0)");
+  if (n > c->cfg.records_cap) return fail(c, NRRS_EINVAL, "n beyond records_cap");
+  for (uint32_t i = 0; i < n; ++i)
+    if (pix[i] >= npx) return fail(c, NRRS_EINVAL, "pixel index beyond npx");
+  if ((uint64_t)n * 4 * 18 + (uint64_t)npx * 8 + 8192 > c->qb_pool_bytes)
+    return fail(c, NRRS_ENOMEM, "too many rows for the scratch space");
+  hipStream_t s = c->stream;
+  HIPC(c, hipStreamSynchronize(s));
+  std::vector<float> rows(8ull * n), tq(4ull * n), qf(2ull * n);
+  for (uint32_t i = 0; i < n; ++i) {
+    for (int k = 0; k < 7; ++k) rows[8ull * i + k] = raw[7ull * i + k];
+    rows[8ull * i + 7] = I[i];
+    for (int k = 0; k < 3; ++k) tq[4ull * i + k] = t[3ull * i + k];
+    tq[4ull * i + 3] = 0.0f;
+    qf[2ull * i] = q_norm[i];
+    qf[2ull * i + 1] = F[i];
+  }
+  Carve k{c->qb_pool};
+  float* prow = k.take<float>(8ull * n);
+  float* plum = k.take<float>(n);
+  float4* ptq = k.take<float4>(n);
+  float2* pqf = k.take<float2>(n);
+  uint32_t* ppix = k.take<uint32_t>(n);
+  float* pw = k.take<float>(npx);
+  uint32_t* pk = k.take<uint32_t>(npx);
+  HIPC(c, hipMemcpy(prow, rows.data(), sizeof(float) * 8 * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(plum, lum_t, sizeof(float) * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(ptq, tq.data(), sizeof(float) * 4 * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(pqf, qf.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(ppix, pix, sizeof(uint32_t) * n, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(pw, wpx, sizeof(float) * npx, hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(pk, kk, sizeof(uint32_t) * npx, hipMemcpyHostToDevice));
+  const NrrsRows r{prow, plum, nullptr, nullptr, ptq, pqf, ppix, n};
+  const uint32_t nb = nrrs_grad_blocks(n);
+  launch_zero_u32((uint32_t*)c->ntab_r.g, c->ntab_n, s);
+  launch_aid_grad(r, c->nstat.w, c->ntab.w, c->cfg.hash_log2, c->naid.w, c->ntab_r.w, rrs_step, pw, pk, g_rrs, 0.01f,
+                  c->npartial, c->nloss_part, c->ntab_r.g, s);
+  launch_partial_sum(c->npartial, nb, kAidParams, c->naid.g, c->nloss_part, c->nloss + 1, c->ngroups, s);
+  HIPC(c, hipStreamSynchronize(s));
+  HIPC(c, hipGetLastError());
+  HIPC(c, hipMemcpy(g_aid, c->naid.g, sizeof(float) * kAidParams, hipMemcpyDeviceToHost));
+  HIPC(c, hipMemcpy(g_table_r, c->ntab_r.g, sizeof(float) * c->ntab_n, hipMemcpyDeviceToHost));
+  HIPC(c, hipMemcpy(loss, c->nloss + 1, sizeof(float), hipMemcpyDeviceToHost));
+  launch_zero_u32((uint32_t*)c->ntab_r.g, c->ntab_n, s);
   HIPC(c, hipStreamSynchronize(s));
   return NRRS_OK;
 }

@@ -15,7 +15,8 @@ constexpr int kScanBlocks = 2048;    // blocks of the chunked reductions / scans
 constexpr int kScanThreads = 256;
 constexpr uint32_t kFlagDead = 1u;   // entry was emitted below the horizon: traced as nothing
 constexpr uint32_t kFlagTrain = 2u;  // entry belongs to a training path
-constexpr uint32_t kPurposeCamera = 0u, kPurposeRoulette = 1u, kPurposeChild = 2u, kPurposeTrain = 3u;
+constexpr uint32_t kPurposeCamera = 0u, kPurposeRoulette = 1u, kPurposeChild = 2u, kPurposeTrain = 3u,
+                   kPurposeNee = 4u;
 constexpr float kLumR = 0.2126f, kLumG = 0.7152f, kLumB = 0.0722f;  // Rec. 709
 
 // Parameter vector offsets: W1[64][20], b1, W2[64][64], b2, W3[64][64], b3, W4[64], b4.
@@ -123,6 +124,31 @@ __device__ __forceinline__ bool sample_ggx(float a, V3 f0, V3 wo, float u1, floa
   return true;
 }
 
+// GGX normal distribution, the visible-normal sampling pdf of a reflected direction (solid
+// angle: G1(wo) D(h) / (4 wo.z)) and f cos per channel (D G2 F / (4 wo.z)) — what light
+// sampling needs to weigh a direction the BSDF could also have sampled.
+__device__ __forceinline__ float ggx_D(float a, V3 h) {
+  const float a2 = a * a;
+  const float d = h.z * h.z * (a2 - 1.0f) + 1.0f;
+  return a2 / (3.14159265358979323846f * d * d);
+}
+
+__device__ __forceinline__ float ggx_pdf(float a, V3 wo, V3 wi) {
+  if (wo.z <= 0.0f || wi.z <= 0.0f) return 0.0f;
+  const V3 h = normalized(wo + wi);
+  return ggx_D(a, h) / ((1.0f + ggx_lambda(a, wo)) * 4.0f * wo.z);
+}
+
+__device__ __forceinline__ V3 ggx_eval_cos(float a, V3 f0, V3 wo, V3 wi) {
+  if (wo.z <= 0.0f || wi.z <= 0.0f) return v3(0.0f, 0.0f, 0.0f);
+  const V3 h = normalized(wo + wi);
+  const float g2 = 1.0f / (1.0f + ggx_lambda(a, wo) + ggx_lambda(a, wi));
+  const float m = 1.0f - dot(wo, h);
+  const float m5 = (m * m) * (m * m) * m;
+  const float k = ggx_D(a, h) * g2 / (4.0f * wo.z);
+  return v3(k * (f0.x + (1.0f - f0.x) * m5), k * (f0.y + (1.0f - f0.y) * m5), k * (f0.z + (1.0f - f0.z) * m5));
+}
+
 // ---------------------------------------------------------------------------------------
 // Device views of the scene and the queues.
 struct DevScene {
@@ -134,6 +160,13 @@ struct DevScene {
   float amin_x, amin_y, amin_z, extent, tmin, offset;
   float env_r, env_g, env_b;
   float eye_x, eye_y, eye_z, fwd_x, fwd_y, fwd_z, rx, ry, rz, ux, uy, uz;  // R, U pre-scaled
+  // lights for next-event estimation: emitting triangles (BVH indices), chosen with probability
+  // proportional to lum(L_e) x area through the CDF; lpdf = that probability per unit area for
+  // every triangle (0 for non-emitters)
+  const uint32_t* light_tri;
+  const float* light_cdf;  // nl + 1 entries, 0 .. 1
+  const float* lpdf;       // per triangle (BVH order)
+  uint32_t nl;
 };
 
 struct Queue {
@@ -144,6 +177,8 @@ struct Queue {
   int4* rec;     // training-record ids of the depths 1..4 ancestors (-1 = none)
   uint32_t* path;  // primary path (index within the pass) the entry descends from; only when
                    // per-path radiance is traced
+  float* pdf;      // solid-angle pdf with which the BSDF sampled the entry's direction (0 for a
+                   // camera ray); only with next-event estimation
 };
 
 struct Records {

@@ -56,12 +56,18 @@ struct RenderArgs {
   uint32_t ext_leaf_batch;  // parked leaves (1..64) at which a wave intersects them (variants 1, 2)
   uint32_t ext_chunk;     // queue entries a traversal wave claims at once (0: just what it needs)
   uint32_t count_work;    // 1: the traversal also counts BVH nodes visited and triangles tested
+  uint32_t nee;           // 1: next-event estimation (shadow rays through the traversal kernel)
+  uint32_t* work_nee;     // the shadow rays' claim counters (shape of work)
   PassState* pass_state;  // pass index and samples per pixel so far (advanced on the device)
 };
 
 void launch_camera(const RenderArgs& a, hipStream_t s);
 void launch_extend(const RenderArgs& a, hipStream_t s);
 void launch_shade(const RenderArgs& a, hipStream_t s);
+// Next-event estimation of one depth after launch_shade: the shadow rays shade wrote into the
+// out-queue slots (origin, direction, contribution, shortened light distance) traced by the
+// traversal kernel, then the unoccluded contributions added to image, records and paths.
+void launch_nee(const RenderArgs& a, hipStream_t s);
 void launch_record_features(const RenderArgs& a, uint64_t records_cap, hipStream_t s);  // after shade, same depth
 void launch_fixed_factor(const RenderArgs& a, hipStream_t s);  // Mix-Depth fixed rate, after shade
 void launch_sum_q(const RenderArgs& a, hipStream_t s);
@@ -127,13 +133,20 @@ constexpr int kStatRaw = 7, kStatIn = 32, kStatOut = 2, kRrsIn = 7;
 constexpr uint32_t mlp32_params(int in, int out) { return 32u * in + 32u + 2u * (32u * 32u + 32u) + 32u * out + out; }
 constexpr uint32_t kStatParams = mlp32_params(kStatIn, kStatOut);  // 3234
 constexpr uint32_t kRrsParams = mlp32_params(kRrsIn, 1);           // 2401
+constexpr int kAidIn = 32;                                         // AID-NRRS RRSNet inputs
+constexpr uint32_t kAidParams = mlp32_params(kAidIn, 1);           // 3201
 struct NrrsNet {
-  const float* stat;   // StatNet parameters
-  const float* rrs;    // RRSNet parameters
-  const float* table;  // hash grid [kHgLevels][2^log2T][kHgFeat]
+  const float* stat;     // StatNet parameters
+  const float* rrs;      // RRSNet parameters (NRRS inputs)
+  const float* table;    // StatNet's hash grid [kHgLevels][2^log2T][kHgFeat]
+  const float* aid;      // RRSNet parameters (AID-NRRS inputs)
+  const float* table_r;  // the AID-NRRS RRSNet's own hash grid (same shape)
   uint32_t log2T;
 };
-void launch_nrrs_factor(const RenderArgs& a, const NrrsNet& n, uint32_t blocks, hipStream_t s);
+// aid = false: StatNet + NRRS RRSNet; true: the AID-NRRS RRSNet alone.
+void launch_nrrs_factor(const RenderArgs& a, const NrrsNet& n, uint32_t blocks, bool aid, hipStream_t s);
+void launch_aid_rows(const float* raw, const float* t, const float* I, uint32_t n, const NrrsNet& net, float* q,
+                     float* enc, hipStream_t s);  // test entry point
 void launch_record_qnorm(const RenderArgs& a, hipStream_t s);  // after the roulette of the depth
 // Test entry point: StatNet outputs, RRS factor and (optional) StatNet encodings of n vertices.
 void launch_nrrs_rows(const float* raw, const float* t, const float* I, uint32_t n, const NrrsNet& net, float* mv,
@@ -159,9 +172,16 @@ void launch_statnet_grad(const NrrsRows& r, const float* stat, const float* tabl
 void launch_rrsnet_grad(const NrrsRows& r, const float* stat, const float* table, uint32_t log2T, const float* rrs,
                         int32_t step, const float* wpx, const uint32_t* kpix, float g_rrs, float eps, float* partial,
                         float* loss_part, hipStream_t s);
-// Fixed-order sum of the block partials into grad, and of the block losses into *loss.
+// AID-NRRS RRSNet gradient (steps as launch_rrsnet_grad; StatNet's statistics only in step 2):
+// block partials [blocks][kAidParams] and its hash-grid gradients added into gtable_r.
+void launch_aid_grad(const NrrsRows& r, const float* stat, const float* table, uint32_t log2T, const float* aid,
+                     const float* table_r, int32_t step, const float* wpx, const uint32_t* kpix, float g_rrs,
+                     float eps, float* partial, float* loss_part, float* gtable_r, hipStream_t s);
+// Fixed-order sum of the block partials into grad (through group_sums, scratch of
+// nrrs_sum_groups() * np floats), and of the block losses into *loss.
 void launch_partial_sum(const float* partial, uint32_t nblocks, uint32_t np, float* grad, const float* loss_part,
-                        float* loss, hipStream_t s);
+                        float* loss, float* group_sums, hipStream_t s);
+uint32_t nrrs_sum_groups();
 // Adam (bias-corrected, step >= 1) on np parameters, the moving average of the inference copy
 // (decay 0: copy) and, when zero_grad, the gradient cleared for the next step.
 void launch_adam(float* w, float* m, float* v, float* grad, uint64_t np, uint64_t step, float lr, float* infer,

@@ -152,6 +152,42 @@ __device__ __forceinline__ void statnet_encode(const float* __restrict__ table, 
   for (int k = 0; k < 16; ++k) enc[16 + k] = ob[k];
 }
 
+// The 32 AID-NRRS RRSNet inputs: its own hash grid of p (16), one-blob w_o (8), Box-Cox of the
+// throughput (3) and of the pixel value (1), one-blob of the remapped roughness with 4 bins (4).
+__device__ __forceinline__ void aid_encode(const float* __restrict__ table, uint32_t log2T, const float (&raw)[7],
+                                           float tx, float ty, float tz, float I, float (&enc)[32]) {
+  const uint64_t T = 1ull << log2T;
+#pragma unroll
+  for (int l = 0; l < kHgLevels; ++l) {
+    Corner8 c;
+    hg_corners(raw[0], raw[1], raw[2], l, log2T, c);
+    const float2* tl = reinterpret_cast<const float2*>(table + (uint64_t)l * T * kHgFeat);
+    float e0 = 0.0f, e1 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float2 v = tl[c.idx[k]];
+      e0 = fmaf(c.w[k], v.x, e0);
+      e1 = fmaf(c.w[k], v.y, e1);
+    }
+    enc[2 * l] = e0;
+    enc[2 * l + 1] = e1;
+  }
+  const float theta = acosf(fminf(fmaxf(raw[5], -1.0f), 1.0f));
+  const float phi = atan2f(raw[4], raw[3]);
+  float ob[12];
+  oneblob(theta * 0.31830988618379067f, 4, ob);
+  oneblob(phi * 0.15915494309189535f + 0.5f, 4, ob + 4);
+  oneblob(raw[6], 4, ob + 8);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) enc[16 + k] = ob[k];
+  enc[24] = box_cox(tx);
+  enc[25] = box_cox(ty);
+  enc[26] = box_cox(tz);
+  enc[27] = box_cox(I);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) enc[28 + k] = ob[8 + k];
+}
+
 __device__ __forceinline__ void rrs_inputs(float m, float v, float tx, float ty, float tz, float I, float rho,
                                            float (&x)[7]) {
   const float mp = fmaxf(m, 0.0f), vp = fmaxf(v, 0.0f);
@@ -200,11 +236,19 @@ __device__ __forceinline__ void load_lds(float* dst, const float* src, uint32_t 
 // ------------------------------------------------------------------ inference
 // The NRRS factor of every vertex of the depth that has a raw factor and a pixel history; a
 // non-finite (or underflowed) factor keeps the heuristic one.  Persistent grid.
+// Weights in LDS, read by all lanes at once.  (Scalar loads of the weights from global memory,
+// with the weights as the FMAs' scalar operand, measured 1.9x slower: 22.5 KB of weights per
+// vertex batch stream through the 16 KB scalar cache.)
+template <bool kAid>
 __global__ __launch_bounds__(kT) void k_nrrs_factor(RenderArgs a, NrrsNet net) {
-  __shared__ float ps[kStatParams];
-  __shared__ float pr[kRrsParams];
-  load_lds(ps, net.stat, kStatParams);
-  load_lds(pr, net.rrs, kRrsParams);
+  __shared__ float ps[kAid ? kAidParams : kStatParams];
+  __shared__ float pr[kAid ? 1 : kRrsParams];
+  if constexpr (kAid) {
+    load_lds(ps, net.aid, kAidParams);
+  } else {
+    load_lds(ps, net.stat, kStatParams);
+    load_lds(pr, net.rrs, kRrsParams);
+  }
   __syncthreads();
   const uint32_t n = a.ctl[a.depth].n;
   for (uint32_t i = blockIdx.x * kT + threadIdx.x; i < n; i += gridDim.x * kT) {
@@ -220,8 +264,16 @@ __global__ __launch_bounds__(kT) void k_nrrs_factor(RenderArgs a, NrrsNet net) {
     const float4 m0 = a.sc.mat[2 * mid], m1 = a.sc.mat[2 * mid + 1];
     float raw[7];
     vertex_raw(a.sc, vp, dr, m0, __float_as_uint(m1.w), raw);
-    float m, v;
-    const float q = softplus_mod(nrrs_z(ps, pr, net.table, net.log2T, raw, th.x, th.y, th.z, g, m, v));
+    float q;
+    if constexpr (kAid) {
+      float enc[32], h1[32], h2[32], h3[32], z[1];
+      aid_encode(net.table_r, net.log2T, raw, th.x, th.y, th.z, g, enc);
+      mlp32<kAidIn, 1>(ps, enc, h1, h2, h3, z);
+      q = softplus_mod(z[0]);
+    } else {
+      float m, v;
+      q = softplus_mod(nrrs_z(ps, pr, net.table, net.log2T, raw, th.x, th.y, th.z, g, m, v));
+    }
     a.q[i] = (q >= 1e-20f && q < 3.0e38f) ? q : q0;
   }
 }
@@ -246,6 +298,26 @@ __global__ __launch_bounds__(kT) void k_nrrs_rows(const float* raw_in, const flo
   if (enc_out) {
     float enc[32];
     statnet_encode(net.table, net.log2T, raw, enc);
+#pragma unroll
+    for (int k = 0; k < 32; ++k) enc_out[32ull * i + k] = enc[k];
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_aid_rows(const float* raw_in, const float* t, const float* I, uint32_t n,
+                                                 NrrsNet net, float* q_out, float* enc_out) {
+  __shared__ float pa[kAidParams];
+  load_lds(pa, net.aid, kAidParams);
+  __syncthreads();
+  const uint32_t i = blockIdx.x * kT + threadIdx.x;
+  if (i >= n) return;
+  float raw[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) raw[k] = raw_in[7ull * i + k];
+  float enc[32], h1[32], h2[32], h3[32], z[1];
+  aid_encode(net.table_r, net.log2T, raw, t[3ull * i], t[3ull * i + 1], t[3ull * i + 2], I[i], enc);
+  mlp32<kAidIn, 1>(pa, enc, h1, h2, h3, z);
+  q_out[i] = softplus_mod(z[0]);
+  if (enc_out) {
 #pragma unroll
     for (int k = 0; k < 32; ++k) enc_out[32ull * i + k] = enc[k];
   }
@@ -528,12 +600,98 @@ __global__ __launch_bounds__(kTG) void k_rrsnet_grad(NrrsRows r, const float* st
   block_loss(li, t.D, loss_part + blockIdx.x);
 }
 
-__global__ void k_partial_sum(const float* partial, uint32_t nb, uint32_t np, float* grad, const float* loss_part,
+__global__ __launch_bounds__(kTG) void k_aid_grad(NrrsRows r, const float* stat, const float* table, uint32_t log2T,
+                                                  const float* aid, const float* table_r, int32_t step,
+                                                  const float* wpx, const uint32_t* kpix, float g_rrs, float eps,
+                                                  float* partial, float* loss_part, float* gtable_r) {
+  __shared__ float ps[kStatParams];
+  __shared__ float pa[kAidParams];
+  __shared__ GradTiles t;
+  if (step != 1) load_lds(ps, stat, kStatParams);
+  load_lds(pa, aid, kAidParams);
+  __syncthreads();
+  const uint32_t row = blockIdx.x * kTG + threadIdx.x;
+  const bool valid = row < r.n;
+  float raw[7] = {0, 0, 0, 0, 0, 0, 0}, I = 0.0f;
+  float4 tq = make_float4(0, 0, 0, 0);
+  if (valid) {
+    load_raw(r, row, raw, I);
+    tq = r.tq[row];
+  }
+  // StatNet supervises only: its statistics enter the transfer of step 2 (uniform branch)
+  float mv[2] = {0.0f, 0.0f};
+  if (step != 1) {
+    float enc[32], h1[32], h2[32], h3[32];
+    statnet_encode(table, log2T, raw, enc);
+    mlp32<kStatIn, kStatOut>(ps, enc, h1, h2, h3, mv);
+  }
+  asm volatile("" ::: "memory");
+  float z[1];
+  {
+    float enc[32];
+    aid_encode(table_r, log2T, raw, tq.x, tq.y, tq.z, I, enc);
+    forward_rows<kAidIn, 1>(pa, enc, t, z);
+  }
+  const float q = softplus_mod(z[0]);
+  float dq = 0.0f, li = 0.0f;
+  if (valid) {
+    if (step == 1) {
+      const float inv_n = 1.0f / (float)r.n;
+      dq = 2.0f * (q - 1.0f) / (1.0f + eps) * inv_n;
+      li = (q - 1.0f) * (q - 1.0f) / (1.0f + eps) * inv_n;
+    } else {
+      const float2 qf = r.qf[row];
+      if (qf.x > 0.0f) {
+        const uint32_t p = r.pix[row];
+        const uint32_t k = kpix[p];
+        const float m = fmaxf(mv[0], 0.0f), v = fmaxf(mv[1], 0.0f);
+        const float S = qf.x < 1.0f ? v + m * m : v;
+        const float lt = r.lum_t[row];
+        const float dvar = -(lt * lt) * S / (qf.x * qf.x);
+        dq = (k ? wpx[p] / (float)k : 0.0f) * dvar * qf.y + 2.0f * g_rrs * (q - qf.x);
+        li = g_rrs * (q - qf.x) * (q - qf.x);
+      }
+    }
+  }
+  float dy[1] = {dq * softplus_mod_grad(z[0])};
+  float dx[32];
+  backward_rows<kAidIn, 1>(pa, dy, t, partial + (uint64_t)blockIdx.x * kAidParams, dx);
+  block_loss(li, t.D, loss_part + blockIdx.x);
+  if (valid && dy[0] != 0.0f) {
+    const uint64_t T = 1ull << log2T;
+#pragma unroll
+    for (int l = 0; l < kHgLevels; ++l) {
+      Corner8 c;
+      hg_corners(raw[0], raw[1], raw[2], l, log2T, c);
+      float* gl = gtable_r + (uint64_t)l * T * kHgFeat;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        atomicAdd(gl + 2ull * c.idx[k], c.w[k] * dx[2 * l]);
+        atomicAdd(gl + 2ull * c.idx[k] + 1, c.w[k] * dx[2 * l + 1]);
+      }
+    }
+  }
+}
+
+// Fixed-order sum of the block partials: group g (of kSumGroups) adds blocks g, g + G, ... in
+// order, then the groups are added in order — a fixed tree, with G times the parallelism of a
+// plain loop over the blocks (one thread per parameter alone left most of the chip idle).
+constexpr uint32_t kSumGroups = 32;
+__global__ __launch_bounds__(256) void k_partial_sum_groups(const float* partial, uint32_t nb, uint32_t np,
+                                                            float* group_sums) {
+  const uint32_t p = blockIdx.x * 256 + threadIdx.x, g = blockIdx.y;
+  if (p >= np) return;
+  float s = 0.0f;
+  for (uint32_t b = g; b < nb; b += kSumGroups) s += partial[(uint64_t)b * np + p];
+  group_sums[(uint64_t)g * np + p] = s;
+}
+
+__global__ void k_partial_sum(const float* group_sums, uint32_t nb, uint32_t np, float* grad, const float* loss_part,
                               float* loss) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < np) {
     float s = 0.0f;
-    for (uint32_t b = 0; b < nb; ++b) s += partial[(uint64_t)b * np + p];
+    for (uint32_t g = 0; g < kSumGroups; ++g) s += group_sums[(uint64_t)g * np + p];
     grad[p] = s;
   }
   if (p == 0 && loss) {
@@ -654,8 +812,25 @@ inline uint32_t blocks_of(uint64_t n, uint32_t t) { return (uint32_t)((n + t - 1
 
 }  // namespace
 
-void launch_nrrs_factor(const RenderArgs& a, const NrrsNet& n, uint32_t blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_nrrs_factor, dim3(std::max(blocks, 1u)), dim3(kT), 0, s, a, n);
+void launch_nrrs_factor(const RenderArgs& a, const NrrsNet& n, uint32_t blocks, bool aid, hipStream_t s) {
+  if (aid)
+    hipLaunchKernelGGL(k_nrrs_factor<true>, dim3(std::max(blocks, 1u)), dim3(kT), 0, s, a, n);
+  else
+    hipLaunchKernelGGL(k_nrrs_factor<false>, dim3(std::max(blocks, 1u)), dim3(kT), 0, s, a, n);
+}
+
+void launch_aid_rows(const float* raw, const float* t, const float* I, uint32_t n, const NrrsNet& net, float* q,
+                     float* enc, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_aid_rows, dim3(blocks_of(n, kT)), dim3(kT), 0, s, raw, t, I, n, net, q, enc);
+}
+
+void launch_aid_grad(const NrrsRows& r, const float* stat, const float* table, uint32_t log2T, const float* aid,
+                     const float* table_r, int32_t step, const float* wpx, const uint32_t* kpix, float g_rrs,
+                     float eps, float* partial, float* loss_part, float* gtable_r, hipStream_t s) {
+  if (!r.n) return;
+  hipLaunchKernelGGL(k_aid_grad, dim3(blocks_of(r.n, kTG)), dim3(kTG), 0, s, r, stat, table, log2T, aid, table_r,
+                     step, wpx, kpix, g_rrs, eps, partial, loss_part, gtable_r);
 }
 
 void launch_record_qnorm(const RenderArgs& a, hipStream_t s) {
@@ -686,10 +861,14 @@ void launch_rrsnet_grad(const NrrsRows& r, const float* stat, const float* table
 }
 
 void launch_partial_sum(const float* partial, uint32_t nblocks, uint32_t np, float* grad, const float* loss_part,
-                        float* loss, hipStream_t s) {
-  hipLaunchKernelGGL(k_partial_sum, dim3(blocks_of(np, 256)), dim3(256), 0, s, partial, nblocks, np, grad, loss_part,
-                     loss);
+                        float* loss, float* group_sums, hipStream_t s) {
+  hipLaunchKernelGGL(k_partial_sum_groups, dim3(blocks_of(np, 256), kSumGroups), dim3(256), 0, s, partial, nblocks,
+                     np, group_sums);
+  hipLaunchKernelGGL(k_partial_sum, dim3(blocks_of(np, 256)), dim3(256), 0, s, group_sums, nblocks, np, grad,
+                     loss_part, loss);
 }
+
+uint32_t nrrs_sum_groups() { return kSumGroups; }
 
 void launch_adam(float* w, float* m, float* v, float* grad, uint64_t np, uint64_t step, float lr, float* infer,
                  float decay, bool zero_grad, hipStream_t s) {

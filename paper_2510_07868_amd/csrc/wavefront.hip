@@ -39,7 +39,10 @@ __global__ __launch_bounds__(kEntryThreads) void k_camera(RenderArgs a) {
     a.ctl[1].n = a.nprim;
     a.ctl[a.max_depth].S = 0;
   }
-  if (k < (a.max_depth + 1) * kWorkSlices) a.work[(uint64_t)k * kWorkStride] = 0;
+  if (k < (a.max_depth + 1) * kWorkSlices) {
+    a.work[(uint64_t)k * kWorkStride] = 0;
+    if (a.nee) a.work_nee[(uint64_t)k * kWorkStride] = 0;
+  }
   if (k >= a.nprim) return;
   // primary path k is sample k mod s_batch of pixel k / s_batch: a pixel's paths stay adjacent
   const uint32_t s_batch = a.nprim / (a.width * a.height);
@@ -62,6 +65,7 @@ __global__ __launch_bounds__(kEntryThreads) void k_camera(RenderArgs a) {
   a.qin.thr[k] = make_float4(1.0f, 1.0f, 1.0f, __uint_as_float(flags));
   a.qin.id[k] = lin;
   if (a.trace) a.qin.path[k] = k;
+  if (a.nee) a.qin.pdf[k] = 0.0f;
   // record slots travel only with training paths (every reader checks kFlagTrain first)
   if (flags & kFlagTrain) a.qin.rec[k] = make_int4(-1, -1, -1, -1);
 }
@@ -577,6 +581,105 @@ __device__ __forceinline__ uint32_t block_alloc(uint32_t* counter, bool pred, ui
   return sh[kWaves] + sh[wave] + lanes_below(m);
 }
 
+// Next-event estimation at a vertex that may continue: one light (probability lum(L_e) x area
+// through the CDF), a point uniform on it, the BSDF's f cos toward it and the power-heuristic
+// weight against the BSDF's own sampling of that direction.  The shadow ray goes to the
+// out-queue slot i (origin offset along the face-forwarded normal, excluded triangle in the
+// origin's w; direction and pixel; contribution t f cos L_e w / pdf_light and flags; the light
+// distance shortened by 1e-4 as float bits in id.x), to be traced by the traversal kernel.
+__device__ __forceinline__ void nee_shadow_ray(const RenderArgs& a, uint32_t i, V3 p, V3 nrm, V3 wo, V3 t, float4 m0,
+                                               uint32_t type, uint32_t pix, uint32_t prim) {
+  const uint32_t dead = kFlagDead;
+  if (a.sc.nl == 0u) {
+    a.qout.thr[i] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(dead));
+    return;
+  }
+  const uint4 r = draw(a.key, a.qin.id[i], kPurposeNee, a.depth, 0);
+  const float u0 = unit(r.x), u1 = unit(r.y), u2 = unit(r.z);
+  uint32_t lo = 0, hi = a.sc.nl - 1u;  // smallest k with cdf[k + 1] > u0
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (a.sc.light_cdf[mid + 1] > u0) hi = mid;
+    else lo = mid + 1;
+  }
+  const uint32_t lt = a.sc.light_tri[lo];
+  const float4 l0 = a.sc.tri[3 * lt], l1 = a.sc.tri[3 * lt + 1], l2 = a.sc.tri[3 * lt + 2];
+  const V3 e1 = xyz(l1), e2 = xyz(l2);
+  const V3 ngl = normalized(cross(e1, e2));
+  const float su = sqrtf(u1);
+  const float b1 = su * (1.0f - u2), b2 = su * u2;
+  const V3 y = xyz(l0) + b1 * e1 + b2 * e2;
+  const float eps = a.sc.offset;
+  const V3 o = v3(fmaf(eps, nrm.x, p.x), fmaf(eps, nrm.y, p.y), fmaf(eps, nrm.z, p.z));
+  V3 d = y - o;
+  const float dist = sqrtf(dot(d, d));
+  const float cos_x = dot(nrm, d) / dist, cos_l = -dot(ngl, d) / dist;
+  if (!(dist > 0.0f) || cos_x <= 0.0f || cos_l <= 0.0f) {
+    a.qout.thr[i] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(dead));
+    return;
+  }
+  d = (1.0f / dist) * d;
+  V3 fc;
+  float pb;
+  V3 tb, bb;
+  basis(nrm, tb, bb);
+  const V3 wol = v3(dot(wo, tb), dot(wo, bb), dot(wo, nrm));
+  const V3 wil = v3(dot(d, tb), dot(d, bb), cos_x);
+  if (type == 1u) {
+    fc = ggx_eval_cos(m0.w, xyz(m0), wol, wil);
+    pb = ggx_pdf(m0.w, wol, wil);
+  } else {
+    fc = (cos_x * 0.31830988618379067f) * xyz(m0);
+    pb = cos_x * 0.31830988618379067f;
+  }
+  const float pl = a.sc.lpdf[lt] * dist * dist / cos_l;
+  const float w = pl * pl / (pl * pl + pb * pb);
+  const float4 lm = a.sc.mat[2 * bits(l1.w) + 1];
+  const float k = w / pl;
+  const V3 c = v3(t.x * fc.x * lm.x * k, t.y * fc.y * lm.y * k, t.z * fc.z * lm.z * k);
+  a.qout.orig[i] = make_float4(o.x, o.y, o.z, __uint_as_float(prim));
+  a.qout.dir[i] = pack(d, pix);
+  a.qout.thr[i] = pack(c, 0u);
+  a.qout.id[i] = make_uint2(__float_as_uint(dist * (1.0f - 1e-4f)), 0u);
+}
+
+// The unoccluded light samples of the depth: the shadow ray's closest hit (written over the
+// out-queue's record slots) lies beyond the shortened light distance.  Their contributions go
+// to the image, to the vertex's ancestors' records (the vertex's own record does not see its
+// own light sample) and to the per-path radiance.
+__global__ __launch_bounds__(kShadeThreads) void k_nee_resolve(RenderArgs a) {
+  const uint32_t n = a.ctl[a.depth].n;
+  const uint32_t i0 = blockIdx.x * kShadeThreads + threadIdx.x;
+  if (blockIdx.x * kShadeThreads >= n) return;  // uniform over the block
+  const bool in_range = i0 < n;
+  const uint32_t i = in_range ? i0 : n - 1;
+  const float4 th = a.qout.thr[i];
+  bool lit = false;
+  uint32_t pix = kNoPix;
+  if (in_range && !(bits(th.w) & kFlagDead)) {
+    const float4 hh = reinterpret_cast<const float4*>(a.qout.rec)[i];
+    const float tmax = __uint_as_float(a.qout.id[i].x);
+    lit = bits(hh.w) == kMiss || hh.x >= tmax;
+    if (lit) pix = bits(a.qout.dir[i].w);
+  }
+  const V3 c = lit ? xyz(th) : v3(0.0f, 0.0f, 0.0f);
+  image_add_wave(a, pix, (double)c.x, (double)c.y, (double)c.z);
+  if (lit && a.records_on && (bits(a.qin.thr[i].w) & kFlagTrain)) {
+    int4 rec = a.qin.rec[i];
+    if (a.depth == 1u) rec.x = -1;
+    else if (a.depth == 2u) rec.y = -1;
+    else if (a.depth == 3u) rec.z = -1;
+    else if (a.depth == 4u) rec.w = -1;
+    record_emission(a, c, rec);
+  }
+  if (lit && a.trace) {
+    double* tp = a.trace + 3ull * ((uint64_t)a.qin.path[i] * a.trace_depth + (a.depth - 1));
+    atomicAdd(tp + 0, (double)c.x);
+    atomicAdd(tp + 1, (double)c.y);
+    atomicAdd(tp + 2, (double)c.z);
+  }
+}
+
 constexpr uint32_t kShadeStripes = 64;
 
 __global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
@@ -603,7 +706,7 @@ __global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
   V3 t = xyz(th), p = v3(0, 0, 0), nrm = p, wo = p, em = p;
   float4 m0 = make_float4(0, 0, 0, 0);
   uint32_t type = 0, pix = 0;
-  bool emits = false;
+  bool emits = false, nee_written = false;
   if (in_range && !(flags & kFlagDead)) {
     pix = bits(dr.w);
     const uint32_t prim = bits(hh.w);
@@ -625,15 +728,29 @@ __global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
       if (front && (m1.x != 0.0f || m1.y != 0.0f || m1.z != 0.0f)) {
         em = mul(t, xyz(m1));
         emits = true;
+        if (a.nee && a.depth > 1u) {
+          // a BSDF-sampled hit on a light: power-heuristic weight against light sampling
+          const float pb = a.qin.pdf[i];
+          if (pb > 0.0f) {
+            const float pl = a.sc.lpdf[prim] * hh.x * hh.x / dot(ng, wo);
+            em = (pb * pb / (pb * pb + pl * pl)) * em;
+          }
+        }
       }
       if (a.depth < a.max_depth && type != 2u) {
         q = a.mode == 0u ? 1.0f : lum(mul(t, xyz(m0)));
         want_rec = a.records_on && (flags & kFlagTrain) && a.depth <= a.net_max_depth && a.depth <= (uint32_t)kMaxRec;
+        if (a.nee) {
+          nee_shadow_ray(a, i, p, nrm, wo, t, m0, type, pix, prim);
+          nee_written = true;
+        }
       }
       a.vpos[i] = pack(p, prim);
       a.vnrm[i] = pack(nrm, mid);
     }
   }
+  // slots without a light sample carry a dead shadow ray (the traversal skips them)
+  if (a.nee && in_range && !nee_written) a.qout.thr[i] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(kFlagDead));
   if (in_range) a.q[i] = q;
   image_add_wave(a, in_range && !(flags & kFlagDead) ? pix : kNoPix, (double)em.x, (double)em.y, (double)em.z);
   if (emits && a.records_on) record_emission(a, em, rec);
@@ -1093,6 +1210,7 @@ __device__ __forceinline__ void expand_child(const RenderArgs& a, uint32_t i, ui
   a.qout.id[s] = make_uint2(r.z, r.w);
   if (a.records_on && (flags & kFlagTrain)) a.qout.rec[s] = a.qin.rec[i];
   if (a.trace) a.qout.path[s] = a.qin.path[i];
+  if (a.nee) a.qout.pdf[s] = bits(m1.w) == 1u ? ggx_pdf(m0.w, wol, wil) : wil.z * 0.31830988618379067f;
 }
 
 // Children of a block of kEntryThreads consecutive parents: the block's offsets go to LDS and
@@ -1212,6 +1330,27 @@ void launch_record_features(const RenderArgs& a, uint64_t records_cap, hipStream
 }
 void launch_shade(const RenderArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_shade, dim3(blocks_for(a.cap, kShadeThreads)), dim3(kShadeThreads), 0, s, a);
+}
+
+void launch_nee(const RenderArgs& a, hipStream_t s) {
+  // the shadow rays sit in the out-queue's origin / direction / throughput slots; the traversal
+  // writes their closest hits over the out-queue's record slots, with claim counters and work
+  // counters of their own
+  RenderArgs b = a;
+  b.qin.orig = a.qout.orig;
+  b.qin.dir = a.qout.dir;
+  b.qin.thr = a.qout.thr;
+  b.qin.id = a.qout.id;
+  b.qin.rec = a.qout.rec;
+  b.qin.path = nullptr;
+  b.qin.pdf = nullptr;
+  b.hit = reinterpret_cast<float4*>(a.qout.rec);
+  b.work = a.work_nee;
+  b.rays = a.rays + 3;
+  b.count_work = 0u;
+  b.trace = nullptr;
+  launch_extend(b, s);
+  hipLaunchKernelGGL(k_nee_resolve, dim3(blocks_for(a.cap, kShadeThreads)), dim3(kShadeThreads), 0, s, a);
 }
 void launch_sum_q(const RenderArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_sum_q_partial, dim3(kScanBlocks), dim3(kScanThreads), 0, s, a);

@@ -16,8 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnrrs.so")
 NPARAM = 9729
 MAX_DEPTH = 64
-MODE_OFF, MODE_HEURISTIC, MODE_NET, MODE_NRRS = 0, 1, 2, 3
-STAT_NPARAM, RRS_NPARAM = 3234, 2401
+MODE_OFF, MODE_HEURISTIC, MODE_NET, MODE_NRRS, MODE_AID = 0, 1, 2, 3, 4
+STAT_NPARAM, RRS_NPARAM, AID_NPARAM = 3234, 2401, 3201
 HG_LEVELS, HG_FEAT = 8, 2
 NORM_TWO_SIDED, NORM_DOWNSCALE = 0, 1
 PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
@@ -37,7 +37,8 @@ EXPORTS = [
     "nrrs_debug_set_norm_factors", "nrrs_debug_load_records", "nrrs_debug_read_queue", "nrrs_debug_trace",
     "nrrs_debug_philox", "nrrs_debug_mlp_forward", "nrrs_debug_mlp_codes", "nrrs_debug_mlp_grad",
     "nrrs_set_nrrs_params", "nrrs_get_nrrs_params", "nrrs_train_step_nrrs", "nrrs_debug_nrrs_forward",
-    "nrrs_debug_nrrs_grads", "nrrs_debug_pixel_error", "nrrs_status_string",
+    "nrrs_debug_nrrs_grads", "nrrs_debug_pixel_error", "nrrs_set_aid_params", "nrrs_get_aid_params",
+    "nrrs_debug_aid_forward", "nrrs_debug_aid_grads", "nrrs_status_string",
     "nrrs_last_error", "nrrs_destroy",
 ]
 
@@ -71,6 +72,7 @@ class NrrsTrain(C.Structure):
     _fields_ = [
         ("lr_stat", C.c_float), ("lr_rrs", C.c_float), ("g_avg", C.c_float), ("g_min", C.c_float),
         ("g_rrs", C.c_float), ("a_mix", C.c_float), ("radius", C.c_int32), ("rrs_step", C.c_int32),
+        ("variant", C.c_int32),
     ]
 
 
@@ -161,6 +163,10 @@ def load():
         "nrrs_debug_nrrs_grads": [P, P, P, P, P, P, P, P, P, U32, P, P, U32, I32, C.c_float, P, P, P, P, P],
         "nrrs_debug_pixel_error": [P, P, P, P, U32, U32, I32, C.c_float, I32, C.c_float, C.c_float, C.c_float,
                                    P, P, P],
+        "nrrs_set_aid_params": [P, P, P],
+        "nrrs_get_aid_params": [P, P, P],
+        "nrrs_debug_aid_forward": [P, P, P, P, U32, P, P],
+        "nrrs_debug_aid_grads": [P, P, P, P, P, P, P, P, U32, P, P, U32, I32, C.c_float, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -505,12 +511,48 @@ class Renderer:
         return st, rr, tb
 
     def train_step_nrrs(self, n_records, rrs_step, lr_stat=5e-3, lr_rrs=3e-4, g_avg=0.01, g_min=0.05, g_rrs=0.01,
-                        a_mix=0.5, radius=2):
-        hp = NrrsTrain(lr_stat, lr_rrs, g_avg, g_min, g_rrs, a_mix, radius, rrs_step)
+                        a_mix=0.5, radius=2, variant=0):
+        hp = NrrsTrain(lr_stat, lr_rrs, g_avg, g_min, g_rrs, a_mix, radius, rrs_step, variant)
         out = NrrsLoss()
         self._check(self.L.nrrs_train_step_nrrs(self.h, n_records, C.byref(hp), C.byref(out)))
         return dict(loss_stat=float(out.loss_stat), loss_rrs=float(out.loss_rrs), e_avg=float(out.e_avg),
                     records=int(out.records), rrs_trained=bool(out.rrs_trained))
+
+    def set_aid_params(self, aid=None, table_r=None):
+        a = [None if v is None else _c(v, np.float32) for v in (aid, table_r)]
+        for v, n in zip(a, (AID_NPARAM, self.table_size())):
+            if v is not None and v.size != n:
+                raise ValueError(f"expected {n} values, got {v.size}")
+        self._check(self.L.nrrs_set_aid_params(self.h, *[None if v is None else _p(v) for v in a]))
+
+    def get_aid_params(self):
+        pa, tr = np.zeros(AID_NPARAM, np.float32), np.zeros(self.table_size(), np.float32)
+        self._check(self.L.nrrs_get_aid_params(self.h, _p(pa), _p(tr)))
+        return pa, tr
+
+    def debug_aid_forward(self, raw, t, I, with_enc=False):
+        raw = _c(raw, np.float32).reshape(-1, 7)
+        n = raw.shape[0]
+        t = _c(t, np.float32).reshape(n, 3)
+        I = _c(I, np.float32).reshape(n)
+        q = np.zeros(max(n, 1), np.float32)
+        enc = np.zeros((max(n, 1), 32), np.float32) if with_enc else None
+        self._check(self.L.nrrs_debug_aid_forward(self.h, _p(raw), _p(t), _p(I), n, _p(q),
+                                                  _p(enc) if with_enc else None))
+        return (q[:n], enc[:n]) if with_enc else q[:n]
+
+    def debug_aid_grads(self, raw, I, lum_t, t, q_norm, F, pix, wpx, k, rrs_step, g_rrs=0.01):
+        raw = _c(raw, np.float32).reshape(-1, 7)
+        n = raw.shape[0]
+        arrs = [_c(I, np.float32), _c(lum_t, np.float32), _c(t, np.float32).reshape(n, 3), _c(q_norm, np.float32),
+                _c(F, np.float32)]
+        pix = _c(pix, np.uint32)
+        wpx, k = _c(wpx, np.float32), _c(k, np.uint32)
+        ga, gt = np.zeros(AID_NPARAM, np.float32), np.zeros(self.table_size(), np.float32)
+        loss = C.c_float()
+        self._check(self.L.nrrs_debug_aid_grads(self.h, _p(raw), *[_p(a) for a in arrs], _p(pix), n, _p(wpx), _p(k),
+                                                wpx.size, rrs_step, float(g_rrs), _p(ga), _p(gt), C.byref(loss)))
+        return dict(g_aid=ga, g_table_r=gt, loss=float(loss.value))
 
     def debug_nrrs_forward(self, raw, t, I, with_enc=False):
         raw = _c(raw, np.float32).reshape(-1, 7)

@@ -225,3 +225,105 @@ def test_nrrs_cornell_paths_match_oracle(O, nrrs_mod, scenes):
     assert not np.allclose(o["sumq"][1:5], oh["sumq"][1:5], rtol=1e-3)
     assert st["overflow"] == 0
     r.close()
+
+
+# ------------------------------------------------------------------ AID-NRRS
+def test_aid_forward_matches_oracle(N, nrrs_mod, scenes):
+    r = make(nrrs_mod, scenes)
+    rng = np.random.default_rng(31)
+    Pa = _he(rng, 32, 1)
+    Tr = rng.normal(0, 0.5, size=8 * 2 * (1 << LOG2T)).astype(np.float32)
+    r.set_aid_params(Pa, Tr)
+    n = 2000 + 37
+    raw = raw_rows(rng, n)
+    t = rng.uniform(0.05, 1.0, size=(n, 3)).astype(np.float32)
+    I = rng.lognormal(-1, 0.7, size=n).astype(np.float32)
+    q, enc = r.debug_aid_forward(raw, t, I, with_enc=True)
+    d = lambda a: np.asarray(a, np.float64)
+    oenc = N.aid_encode(d(Tr), LOG2T, d(raw), d(t), d(I))
+    oq, _ = N.aid_factor(d(Pa), d(Tr), LOG2T, d(raw), d(t), d(I))
+    assert np.allclose(enc, oenc, rtol=1e-5, atol=2e-6), np.abs(enc - oenc).max()
+    assert np.allclose(q, oq, rtol=1e-4, atol=1e-6), np.abs(q / oq - 1).max()
+    r.close()
+
+
+@pytest.mark.parametrize("step", [1, 2])
+def test_aid_gradients_match_oracle(N, nrrs_mod, scenes, step):
+    r = make(nrrs_mod, scenes)
+    Ps, _, T = params(33, nrrs_mod)
+    Ps[-2:] = [0.4, 0.2]
+    T *= 0.2
+    rng = np.random.default_rng(34 + step)
+    Pa = _he(rng, 32, 1)
+    Tr = (rng.normal(0, 0.3, size=8 * 2 * (1 << LOG2T))).astype(np.float32)
+    r.set_nrrs_params(Ps, None, T)
+    r.set_aid_params(Pa, Tr)
+    n, npx = 1000 + 29, 97
+    raw = raw_rows(rng, n)
+    I = rng.lognormal(-1, 0.5, size=n).astype(np.float32)
+    lum_t = rng.uniform(0.05, 1.0, size=n).astype(np.float32)
+    t = rng.uniform(0.05, 1.0, size=(n, 3)).astype(np.float32)
+    qn = rng.uniform(0.2, 2.5, size=n).astype(np.float32)
+    qn[:7] = 0.0
+    F = rng.uniform(0.5, 1.5, size=n).astype(np.float32)
+    pix = rng.integers(0, npx, size=n).astype(np.uint32)
+    k = np.bincount(pix, minlength=npx).astype(np.uint32)
+    wpx = rng.normal(0.5, 1.0, size=npx).astype(np.float32)
+    g = r.debug_aid_grads(raw, I, lum_t, t, qn, F, pix, wpx, k, step, g_rrs=0.01)
+    d = lambda a: np.asarray(a, np.float64)
+    ol, odPa, odT = N.aid_grad(d(Pa), d(Tr), d(Ps), d(T), LOG2T, d(raw), d(t), d(I), d(lum_t), d(qn), d(F), pix, k,
+                               d(wpx), step, g_rrs=0.01, eps=0.01)
+
+    def close(a, b, tol):
+        err = np.abs(a - b).max() / np.abs(b).max()
+        assert err <= tol, err
+
+    assert g["loss"] == pytest.approx(ol, rel=1e-4, abs=1e-7)
+    close(g["g_aid"], odPa, 2e-5)
+    close(g["g_table_r"], odT, 2e-5)
+    r.close()
+
+
+def test_aid_cornell_paths_match_oracle(O, nrrs_mod, scenes):
+    # the AID-NRRS factor in a 64x64, 4-spp Cornell pass, path by path against the oracle
+    from test_gpu_parity import _compare_paths, _report_paths
+    W = H = 64
+    D = 8
+    sc = scenes.cornell()
+    r = nrrs_mod.Renderer(W, H, s_batch=4, max_tris=max(sc.n_tris, 64), max_materials=max(len(sc.mat_type), 4),
+                          trace_depth=D, hash_log2=LOG2T)
+    r.upload_scene(sc)
+    rng = np.random.default_rng(41)
+    Pa = _he(rng, 32, 1)
+    Pa[-1] = 2.0 * (1.0 - np.log(2.0))
+    Tr = rng.uniform(-0.3, 0.3, size=8 * 2 * (1 << LOG2T)).astype(np.float32)
+    guide = rng.uniform(0.02, 2.0, size=W * H).astype(np.float32)
+    r.set_aid_params(Pa, Tr)
+    r.set_guide(guide)
+    r.set_trace(True)
+    st = r.render(4, D, nrrs_mod.MODE_AID)
+    gp = r.read_trace()
+    params = np.concatenate([Pa, Tr]).astype(np.float64)
+    o = O.render(O.OracleScene(sc), O.make_cfg(W, H, 4, D, n_passes=1, mode=O.MODE_AID, tau=1e-4, hash_log2=LOG2T),
+                 paths=True, params=params, guide=guide.astype(np.float64))
+    bad, some, full, covered = _compare_paths(gp, o, D)
+    _report_paths("cornell AID-NRRS", gp, o, D, bad, some, full, covered)
+    assert bad.sum() == 0
+    assert some > 0.99 and covered > 0.9
+    assert st["overflow"] == 0
+    r.close()
+
+
+def test_aid_training_loop_runs(nrrs_mod, scenes):
+    r = make(nrrs_mod, scenes, W=64, H=48, s_batch=4, records_cap=1 << 15, p_train=0.25)
+    for f in range(8):
+        st = r.render(4, 6, nrrs_mod.MODE_AID)
+        n = min(st["records"], 1 << 15)
+        out = r.train_step_nrrs(n, 1 if f < 4 else 2, variant=1)
+        assert np.isfinite(out["loss_stat"]) and np.isfinite(out["loss_rrs"])
+        assert out["rrs_trained"]
+    pa, tr = r.get_aid_params()
+    assert np.all(np.isfinite(pa)) and np.all(np.isfinite(tr))
+    pa0 = r.get_nrrs_params()[1]
+    assert np.all(np.isfinite(pa0))
+    r.close()

@@ -1006,8 +1006,10 @@ def test_matrix_core_codes_match_oracle_layer_by_layer(O, nrrs_mod, scenes, prec
         clean &= ~onear[:, L, :width].any(1)
     assert all(len(b) == 0 for b in bads), [b[:5] for b in bads]
     assert se_bad == 0
-    # rows with no near-tie anywhere: the output agrees within the FP32 accumulation error
-    ok = ~near_row
+    # rows whose every quantized operand is robust (identical codes in all layers): the output
+    # agrees within the FP32 accumulation error of the last layers
+    ok = clean
+    assert ok.mean() > 0.3
     assert np.all(np.abs(y[ok] - oy[ok]) <= 2e-4 * (np.abs(oy[ok]) + 1e-3))
     assert fracs[0] == 1.0 and fracs[1] > min_l1 and fracs[2] > min_l2
 

@@ -392,3 +392,58 @@ def test_nrrs_factor_is_statnet_then_rrsnet_with_the_modified_softplus():
     assert np.allclose(z, N.mlp32_forward(Pr, 7, 1, x)[:, 0])
     # Eq. (22): ln(1 + e^z) below 0, z / 2 + ln 2 above; continuous at 0
     assert np.allclose(q, np.where(z < 0, np.log1p(np.exp(np.minimum(z, 0))), 0.5 * z + np.log(2)))
+
+
+# ------------------------------------------------------------- AID-NRRS RRSNet
+def test_aid_encoding_layout():
+    rng = np.random.default_rng(14)
+    t = _table(rng)
+    raw = _raw(rng, 4)
+    tr = rng.uniform(0.1, 1, size=(4, 3))
+    I = rng.uniform(0.1, 2, size=4)
+    enc = N.aid_encode(t, LOG2T, raw, tr, I)
+    assert np.allclose(enc[:, :16], N.hashgrid_encode(t, LOG2T, raw[:, :3]))
+    for r in range(4):
+        assert np.allclose(enc[r, 16:20], N.oneblob(np.arccos(raw[r, 5]) / np.pi, 4))
+        assert np.allclose(enc[r, 20:24], N.oneblob(np.arctan2(raw[r, 4], raw[r, 3]) / (2 * np.pi) + 0.5, 4))
+        assert np.allclose(enc[r, 24:27], 2 * (np.sqrt(tr[r]) - 1))
+        assert enc[r, 27] == pytest.approx(2 * (np.sqrt(I[r]) - 1))
+        assert np.allclose(enc[r, 28:32], N.oneblob(raw[r, 6], 4))
+
+
+@pytest.mark.parametrize("step", [1, 2])
+def test_aid_gradient_matches_finite_differences(step):
+    # step 1: the derivative of the mean relative L2 to 1; step 2: the transferred pixel gradient
+    # held fixed plus the bound loss, through the MLP and RRSNet's own hash grid
+    rng = np.random.default_rng(15 + step)
+    ts, tr = _table(rng) * 0.1, _table(rng) * 0.3
+    Ps = rng.normal(0, 0.3, size=N.mlp32_nparams(32, 2))
+    Pa = rng.normal(0, 0.2, size=N.mlp32_nparams(32, 1))
+    R = _records(rng, 5, 3)
+    k = np.bincount(R["pix"], minlength=3).astype(np.uint32)
+    wpx = np.array([0.7, -0.2, 1.5])
+    g3 = 0.01
+    loss, dPa, dT = N.aid_grad(Pa, tr, Ps, ts, LOG2T, R["raw"], R["t_rgb"], R["I_px"], R["lum_t"], R["q_norm"], R["F"],
+                               R["pix"], k, wpx, step, g_rrs=g3)
+    mv = N.statnet_forward(Ps, ts, LOG2T, R["raw"])
+    m, v = np.maximum(mv[:, 0], 0), np.maximum(mv[:, 1], 0)
+    S = np.where(R["q_norm"] < 1, v + m * m, v)
+    A = wpx[R["pix"]] / k[R["pix"]] * R["F"] * (-(R["lum_t"] ** 2) * S / R["q_norm"] ** 2)
+
+    def G(PP, TT):
+        q, _ = N.aid_factor(PP, TT, LOG2T, R["raw"], R["t_rgb"], R["I_px"])
+        if step == 1:
+            return float(np.mean((q - 1.0) ** 2 / 1.01))
+        return float(np.sum(A * q + g3 * (q - R["q_norm"]) ** 2))
+
+    h = 1e-6
+    for j in rng.choice(Pa.size, 25, replace=False):
+        e = np.zeros_like(Pa)
+        e[j] = h
+        assert dPa[j] == pytest.approx((G(Pa + e, tr) - G(Pa - e, tr)) / (2 * h), rel=1e-5, abs=1e-9)
+    nz = np.flatnonzero(dT)
+    assert nz.size > 0
+    for j in nz[:: max(1, nz.size // 15)]:
+        e = np.zeros_like(tr)
+        e[j] = h
+        assert dT[j] == pytest.approx((G(Pa, tr + e) - G(Pa, tr - e)) / (2 * h), rel=1e-5, abs=1e-9)
