@@ -91,6 +91,13 @@ typedef struct {
   uint32_t hash_log2;     /* > 0 (14..22): reserve NRRS proper (Sec. 4.2): StatNet's hash grid of
                              2^hash_log2 entries per level, StatNet, RRSNet and their training
                              state (about 80 * 2^hash_log2 B); 0: not available */
+  uint32_t nee;           /* 1: next-event estimation (the paper's experiments enable it, Sec. 6): at
+                             every vertex that may continue, one light sample (an emitting triangle
+                             with probability lum(L_e) x area, a point uniform on it), a shadow ray
+                             from the offset hit point, and power-heuristic MIS against the BSDF's
+                             sampling (also weighting the BSDF-sampled light hits); its contribution
+                             reaches the image, the ancestors' training records and the per-path
+                             radiance at the vertex's depth.  0: off */
 } nrrs_config;
 
 typedef struct {

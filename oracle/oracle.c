@@ -1247,7 +1247,11 @@ static void extend_and_shade(rctx* c, entry* Q, vstate* V, uint64_t n, uint32_t 
       const double derr = 2.0 * v->perr / dist + 16.0 * F32_UNIT;
       int tf = trace_one(s, o, d, v->prim, s->nodes != NULL, tau, v->perr, derr, &prim, &th, &hb1, &hb2, &gerr);
       const double tmax = dist * (1.0 - 1e-4);
-      if (tau > 0.0 && (tf || (prim != MISS && fabs(th - tmax) < tau * tmax + v->perr + derr * th))) frag = 1;
+      /* the light's own hit lies 1e-4 dist beyond tmax, as far as the general near-tie margin tau:
+       * this comparison takes the margin of its float32 error instead (origin and direction
+       * errors plus a few units in the last place of t and tmax, far below 1e-5 t) */
+      const double tol_t = fmin(tau, 1e-5) * tmax + v->perr + derr * th;
+      if (tau > 0.0 && (tf || (prim != MISS && fabs(th - tmax) < tol_t))) frag = 1;
       v->nee_fragile = (uint8_t)frag;
       if (prim != MISS && th < tmax) continue; /* occluded */
       const double* le = s->mpar + 7 * (uint64_t)s->tmat[lt] + 4;

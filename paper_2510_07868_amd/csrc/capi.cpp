@@ -69,6 +69,9 @@ struct nrrs_ctx {
   unsigned long long* rays = nullptr;
   unsigned long long *st_n = nullptr, *st_s = nullptr, *st_r = nullptr;
   double *st_sumq = nullptr, *st_f = nullptr;
+  uint32_t* work_nee = nullptr;  // shadow-ray claim counters (next-event estimation)
+  uint32_t* light_tri = nullptr;  // NEE light list (BVH indices), its CDF and per-triangle pdf
+  float *light_cdf = nullptr, *lpdf = nullptr;
   double* f_fixed = nullptr;  // [NRRS_MAX_DEPTH + 1] normalization factors given by nrrs_debug_set_norm_factors
   uint32_t f_fixed_n = 0;     // depths 1..f_fixed_n use them (0: computed)
   double* image = nullptr;
@@ -148,6 +151,7 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
     qq->id = k.take<uint2>(C);
     qq->rec = k.take<int4>(C);
     qq->path = c->cfg.trace_depth ? k.take<uint32_t>(C) : nullptr;
+    qq->pdf = c->cfg.nee ? k.take<float>(C) : nullptr;
     if (qq == &c->qb) {
       c->qb_pool = base ? base + start : nullptr;
       c->qb_pool_bytes = k.off - start;
@@ -166,9 +170,13 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
   c->gsum = k.take<uint32_t>((uint64_t)kScanBlocks * kGuardSteps);
   c->ctl = k.take<DepthCtl>(NRRS_MAX_DEPTH + 2);
   c->work = k.take<uint32_t>((uint64_t)(NRRS_MAX_DEPTH + 2) * kWorkSlices * kWorkStride);
+  c->work_nee = c->cfg.nee ? k.take<uint32_t>((uint64_t)(NRRS_MAX_DEPTH + 2) * kWorkSlices * kWorkStride) : nullptr;
+  c->light_tri = c->cfg.nee ? k.take<uint32_t>(max_tris) : nullptr;
+  c->light_cdf = c->cfg.nee ? k.take<float>(max_tris + 1) : nullptr;
+  c->lpdf = c->cfg.nee ? k.take<float>(max_tris) : nullptr;
   c->alpha = k.take<double>(1);
   c->overflow = k.take<uint32_t>(1);
-  c->rays = k.take<unsigned long long>(3);
+  c->rays = k.take<unsigned long long>(6);  // rays, nodes, triangles; the same for shadow rays
   c->pass_state = k.take<PassState>(1);
   c->st_n = k.take<unsigned long long>(NRRS_MAX_DEPTH + 1);
   c->st_s = k.take<unsigned long long>(NRRS_MAX_DEPTH + 1);
@@ -386,6 +394,8 @@ RenderArgs base_args(nrrs_ctx* c) {
   a.ext_leaf_batch = c->tune.extend_leaf_batch;
   a.ext_chunk = c->tune.extend_chunk;
   a.count_work = c->timing ? 1u : 0u;
+  a.nee = c->cfg.nee;
+  a.work_nee = c->work_nee;
   a.pass_state = c->pass_state;
   return a;
 }
@@ -434,7 +444,7 @@ int32_t nrrs_create(const nrrs_config* cfg, void* hip_stream, nrrs_ctx** out) {
       cfg->precision < NRRS_PREC_FP32 || cfg->precision > NRRS_PREC_FP8 || !(cfg->p_train >= 0.0) ||
       cfg->p_train > 1.0 || (cfg->loss != NRRS_LOSS_REL_L2 && cfg->loss != NRRS_LOSS_LOG_MSE) ||
       !(cfg->ema_decay >= 0.0) || cfg->ema_decay >= 1.0 || cfg->trace_depth > NRRS_MAX_DEPTH ||
-      (cfg->hash_log2 != 0 && (cfg->hash_log2 < 14 || cfg->hash_log2 > 22)))
+      (cfg->hash_log2 != 0 && (cfg->hash_log2 < 14 || cfg->hash_log2 > 22)) || cfg->nee > 1)
     return NRRS_EINVAL;
   const uint64_t npx = (uint64_t)cfg->width * cfg->height;
   const uint64_t nprim = npx * cfg->s_batch;
@@ -578,8 +588,51 @@ int32_t nrrs_upload_scene(nrrs_ctx* c, const float* verts, uint64_t nv, const ui
     for (int k = 0; k < 3; ++k) mats[8ull * m + 4 + k] = mat_params[7ull * m + 4 + k];
     std::memcpy(&mats[8ull * m + 7], &mat_type[m], 4);
   }
+  // next-event estimation's lights: the emitting triangles (BVH order), chosen with probability
+  // lum(L_e) x area (CDF in double, stored in float), and lum(L_e) / sum as the pdf per unit
+  // area of every triangle (0 for the rest)
+  // (listed in the scene's own triangle order, so that a uniform picks the same light whatever
+  // the BVH order; each entry holds the triangle's BVH index)
+  std::vector<uint32_t> light_tri;
+  std::vector<float> light_cdf(1, 0.0f), lpdf;
+  if (c->cfg.nee) {
+    lpdf.assign(nt, 0.0f);
+    std::vector<uint32_t> to_bvh(nt);
+    for (uint64_t k = 0; k < nt; ++k) to_bvh[bvh.order[k]] = (uint32_t)k;
+    std::vector<double> cum;
+    double total = 0.0;
+    for (uint64_t t = 0; t < nt; ++t) {
+      const uint32_t k = to_bvh[t];
+      const float* le = mat_params + 7ull * tri_mat[t] + 4;
+      const double l = 0.2126 * le[0] + 0.7152 * le[1] + 0.0722 * le[2];
+      if (!(l > 0.0)) continue;
+      const float* e1 = &tri[12 * k + 4];
+      const float* e2 = &tri[12 * k + 8];
+      const double cx = (double)e1[1] * e2[2] - (double)e1[2] * e2[1];
+      const double cy = (double)e1[2] * e2[0] - (double)e1[0] * e2[2];
+      const double cz = (double)e1[0] * e2[1] - (double)e1[1] * e2[0];
+      const double area = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+      if (!(area > 0.0)) continue;
+      total += l * area;
+      light_tri.push_back((uint32_t)k);
+      cum.push_back(total);
+    }
+    for (double v : cum) light_cdf.push_back((float)(v / total));
+    if (!light_tri.empty()) light_cdf.back() = 1.0f;
+    for (uint32_t k : light_tri) {
+      const float* le = mat_params + 7ull * tri_mat[bvh.order[k]] + 4;
+      lpdf[k] = (float)((0.2126 * le[0] + 0.7152 * le[1] + 0.0722 * le[2]) / total);
+    }
+  }
   hipStream_t s = c->stream;
   HIPC(c, hipStreamSynchronize(s));
+  if (c->cfg.nee) {
+    if (!light_tri.empty()) {
+      HIPC(c, hipMemcpy(c->light_tri, light_tri.data(), 4 * light_tri.size(), hipMemcpyHostToDevice));
+      HIPC(c, hipMemcpy(c->light_cdf, light_cdf.data(), 4 * light_cdf.size(), hipMemcpyHostToDevice));
+    }
+    HIPC(c, hipMemcpy(c->lpdf, lpdf.data(), 4 * lpdf.size(), hipMemcpyHostToDevice));
+  }
   HIPC(c, hipMemcpy(c->tri, tri.data(), sizeof(float) * tri.size(), hipMemcpyHostToDevice));
   HIPC(c, hipMemcpy(c->node, bvh.nodes.data(), sizeof(float) * bvh.nodes.size(), hipMemcpyHostToDevice));
   HIPC(c, hipMemcpy(c->node4, bvh.nodes4.data(), sizeof(float) * bvh.nodes4.size(), hipMemcpyHostToDevice));
@@ -593,6 +646,10 @@ int32_t nrrs_upload_scene(nrrs_ctx* c, const float* verts, uint64_t nv, const ui
   d.nt = (uint32_t)nt;
   d.nn = (uint32_t)bvh.n_nodes;
   d.nm = nm;
+  d.light_tri = c->light_tri;
+  d.light_cdf = c->light_cdf;
+  d.lpdf = c->lpdf;
+  d.nl = (uint32_t)light_tri.size();
   d.amin_x = amin[0];
   d.amin_y = amin[1];
   d.amin_z = amin[2];
@@ -743,7 +800,7 @@ int32_t nrrs_render(nrrs_ctx* c, uint32_t spp, uint32_t max_depth, int32_t mode,
   launch_zero_u32((uint32_t*)c->st_n, 2 * (NRRS_MAX_DEPTH + 1), s);
   launch_zero_u32((uint32_t*)c->st_s, 2 * (NRRS_MAX_DEPTH + 1), s);
   launch_zero_u32((uint32_t*)c->st_r, 2 * (NRRS_MAX_DEPTH + 1), s);
-  launch_zero_u32((uint32_t*)c->rays, 6, s);
+  launch_zero_u32((uint32_t*)c->rays, 12, s);
   launch_zero_u32(c->overflow, 1, s);
   // stage timing: one event before the first launch and one after every stage
   size_t n_ev = 0;
@@ -780,6 +837,7 @@ int32_t nrrs_render(nrrs_ctx* c, uint32_t spp, uint32_t max_depth, int32_t mode,
       MARK(1);
       launch_shade(b, s);
       if (b.records_on && d <= (uint32_t)c->cfg.net_max_depth) launch_record_features(b, c->cfg.records_cap, s);
+      if (c->cfg.nee && d < max_depth) launch_nee(b, s);
       MARK(2);
       if (d == max_depth) break;
       if (mode != NRRS_MODE_OFF && ((c->fixed_depths >> (d - 1)) & 1u)) {

@@ -64,7 +64,7 @@ class Config(C.Structure):
         ("cap_factor", C.c_double), ("f_rate", C.c_double), ("norm_mode", C.c_int32), ("seed", C.c_uint64),
         ("net_max_depth", C.c_int32), ("precision", C.c_int32), ("records_cap", C.c_uint32),
         ("p_train", C.c_double), ("loss", C.c_int32), ("ema_decay", C.c_double), ("trace_depth", C.c_uint32),
-        ("hash_log2", C.c_uint32),
+        ("hash_log2", C.c_uint32), ("nee", C.c_uint32),
     ]
 
 
@@ -196,7 +196,7 @@ class Renderer:
     def __init__(self, width, height, s_batch=1, cap_factor=2.0, f_rate=1.0, norm_mode=NORM_TWO_SIDED, seed=0,
                  net_max_depth=4, precision=PREC_FP32, records_cap=0, p_train=0.0, max_tris=1 << 16,
                  max_materials=4096, device="cuda:0", stream=None, loss=LOSS_REL_L2, ema_decay=0.0,
-                 trace_depth=0, hash_log2=0):
+                 trace_depth=0, hash_log2=0, nee=0):
         import torch
         self.torch = torch
         self.L = load()
@@ -205,7 +205,7 @@ class Renderer:
         # a stream of its own (default priority): hipGraph capture needs a non-null stream
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self.cfg = Config(width, height, s_batch, cap_factor, f_rate, norm_mode, seed, net_max_depth, precision,
-                          records_cap, p_train, loss, ema_decay, trace_depth, hash_log2)
+                          records_cap, p_train, loss, ema_decay, trace_depth, hash_log2, nee)
         self.trace_depth = trace_depth
         self.hash_log2 = hash_log2
         self.width, self.height, self.s_batch = width, height, s_batch
