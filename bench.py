@@ -618,6 +618,23 @@ def batched_study(nrrs, scenes, torch, spp=64, s_batch=8, D=32, train_frames=48,
         out[name] = {"seconds": round(dt, 4), "mpaths_per_s": round(st["rays"] / dt / 1e6, 1), "rays": st["rays"]}
         print(f"# batched {name}: {dt:.3f}s, {st['rays'] / dt / 1e6:.0f} Mpaths/s", flush=True)
     r.close()
+    # the same scene with its 2000 boxes as instances of one unit box (two-level traversal),
+    # heuristic normalized RRS over the same 64 spp
+    isc = scenes.terrain5m_instanced(0)
+    ri = nrrs.Renderer(W, H, s_batch=s_batch, cap_factor=2.0, seed=0, max_tris=isc.workspace_tris,
+                       max_materials=len(isc.base.mat_type))
+    ri.upload_scene(isc)
+    tuning_i = ri.autotune(D)
+    ri.render(s_batch, D, nrrs.MODE_HEURISTIC, stats=False)
+    ri.reset_image()
+    dt, st = _timed_render(ri, torch, spp, D, nrrs.MODE_HEURISTIC)
+    imgs["instanced_heuristic"], _ = ri.read_image()
+    ri.close()
+    out["instanced_heuristic"] = {"seconds": round(dt, 4), "mpaths_per_s": round(st["rays"] / dt / 1e6, 1),
+                                  "rays": st["rays"], "traversal_launch": tuning_i,
+                                  "triangles_stored": int(isc.base.n_tris + isc.mesh_tris.shape[0]),
+                                  "instances": int(isc.inst_mesh.shape[0])}
+    print(f"# batched instanced heuristic: {dt:.3f}s, {st['rays'] / dt / 1e6:.0f} Mpaths/s", flush=True)
     t_ref = time.perf_counter()
     ref, ref_var = _reference(nrrs, sc, W, H, s_batch, D, ref_spp, 0x5EED1000)
     out["reference"] = f"plain path tracing, {ref_spp} spp in two independent halves"
@@ -629,6 +646,7 @@ def batched_study(nrrs, scenes, torch, spp=64, s_batch=8, D=32, train_frames=48,
         out[name]["efficiency"] = 1.0 / (a * out[name]["seconds"])
     for name in ("fp8", "bf16", "fp32"):
         out[f"{name}_over_heuristic"] = out[name]["efficiency"] / out["heuristic"]["efficiency"]
+    out["instanced_time_over_flat"] = out["instanced_heuristic"]["seconds"] / out["heuristic"]["seconds"]
     return out
 
 

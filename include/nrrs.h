@@ -148,6 +148,48 @@ int32_t nrrs_upload_scene(nrrs_ctx* ctx, const float* verts, uint64_t nv, const 
                           uint64_t nt, const uint32_t* tri_mat, const uint32_t* mat_type,
                           const float* mat_params, uint32_t nm, const float* camera, const float* env);
 
+/* Instanced geometry for nrrs_upload_scene_instanced (host arrays, copied during the call).
+ *   Meshes in object space: mesh_verts[mesh_nv*3]; mesh_tris[*3] vertex indices and
+ *   mesh_tri_mat[] materials of all meshes' triangles concatenated; mesh m is triangles
+ *   [mesh_tri_begin[m], mesh_tri_begin[m+1]) (n_meshes + 1 entries, the first 0, each mesh
+ *   non-empty).
+ *   Instances: inst_mesh[n_inst] the mesh; inst_xform[n_inst*12] the object-to-world affine
+ *   map as a row-major 3x4 matrix (world = A * object + t, A invertible; det A < 0 mirrors the
+ *   emitting side with the triangles); inst_mat[n_inst] a material for all of the instance's
+ *   triangles, or NRRS_NO_MATERIAL to keep the mesh's own. */
+#define NRRS_NO_MATERIAL 0xFFFFFFFFu
+typedef struct nrrs_instances {
+  const float* mesh_verts;
+  uint64_t mesh_nv;
+  const uint32_t* mesh_tris;
+  const uint32_t* mesh_tri_mat;
+  const uint64_t* mesh_tri_begin;
+  uint32_t n_meshes;
+  const uint32_t* inst_mesh;
+  const float* inst_xform;
+  const uint32_t* inst_mat;
+  uint32_t n_inst;
+} nrrs_instances;
+
+/* Upload a two-level scene: the base mesh (as in nrrs_upload_scene, world space; nt may be 0)
+ * plus instances of object-space meshes (the paper's batched scenes instance their boxes,
+ * Sec. 6; its wavefront renderer traces them through two-level hardware trees, Sec. 3).  One
+ * BVH per mesh and one for the base mesh (binned SAH, leaves of at most 4 triangles), and a
+ * BVH over the instances' world boxes (the base mesh one of them, with the identity map);
+ * rays are moved into each instance's object space during traversal, a mesh is stored once.
+ * Renders equal those of the flattened scene (base triangles, then every instance's mesh
+ * triangles in mesh order, at world positions ((a00 x + a01 y) + a02 z) + t0, ... rounded to
+ * float) up to float32 rounding; nrrs_debug_trace numbers triangles in that flattened order.
+ * The workspace must hold nt + (all meshes' triangles) + 3 per instance (+ 3 for the base
+ * mesh) in max_tris.  Traversal variants 2 and 4 are not available for such scenes (the
+ * tuning switches to variant 3).  EINVAL on bad indices, non-finite values, a singular map,
+ * 2^26 instances or more, more than 2^31 triangles after flattening, or trees together deeper
+ * than the traversal stack; ENOMEM if the workspace is too small. */
+int32_t nrrs_upload_scene_instanced(nrrs_ctx* ctx, const float* verts, uint64_t nv, const uint32_t* tris,
+                                    uint64_t nt, const uint32_t* tri_mat, const uint32_t* mat_type,
+                                    const float* mat_params, uint32_t nm, const float* camera,
+                                    const float* env, const nrrs_instances* instances);
+
 /* Render spp samples per pixel (spp a multiple of s_batch: spp / s_batch wavefront passes)
  * with paths of at most max_depth vertices (1..64) and the given nrrs_mode.  Radiance is
  * accumulated in FP64 per pixel across calls until nrrs_reset_image.  In HEURISTIC and

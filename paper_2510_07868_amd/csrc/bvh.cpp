@@ -164,7 +164,14 @@ struct Builder {
 
 }  // namespace
 
-int build_bvh(const float* verts, const uint32_t* tris, uint64_t nt, BvhOut& out) {
+namespace {
+
+// The tree over items with boxes tb and centroids cen (3 per item).
+void build_tree(const std::vector<Box>& tb, const std::vector<float>& cen, uint64_t nt, BvhOut& out, bool wide);
+
+}  // namespace
+
+int build_bvh(const float* verts, const uint32_t* tris, uint64_t nt, BvhOut& out, bool wide) {
   std::vector<Box> tb(nt);
   std::vector<float> cen(3 * nt);
   for (uint64_t i = 0; i < nt; ++i) {
@@ -172,6 +179,27 @@ int build_bvh(const float* verts, const uint32_t* tris, uint64_t nt, BvhOut& out
     for (int c = 0; c < 3; ++c) tb[i].grow(verts + 3 * (uint64_t)tris[3 * i + c]);
     for (int k = 0; k < 3; ++k) cen[3 * i + k] = 0.5f * (tb[i].lo[k] + tb[i].hi[k]);
   }
+  build_tree(tb, cen, nt, out, wide);
+  return 0;
+}
+
+int build_bvh_boxes(const float* boxes, uint64_t n, BvhOut& out) {
+  std::vector<Box> tb(n);
+  std::vector<float> cen(3 * n);
+  for (uint64_t i = 0; i < n; ++i) {
+    for (int k = 0; k < 3; ++k) {
+      tb[i].lo[k] = boxes[6 * i + k];
+      tb[i].hi[k] = boxes[6 * i + 3 + k];
+      cen[3 * i + k] = 0.5f * (tb[i].lo[k] + tb[i].hi[k]);
+    }
+  }
+  build_tree(tb, cen, n, out, false);
+  return 0;
+}
+
+namespace {
+
+void build_tree(const std::vector<Box>& tb, const std::vector<float>& cen, uint64_t nt, BvhOut& out, bool wide) {
   out.order.resize(nt);
   for (uint64_t i = 0; i < nt; ++i) out.order[i] = (uint32_t)i;
   Builder B{&tb, &cen, &out.order, {}};
@@ -204,9 +232,10 @@ int build_bvh(const float* verts, const uint32_t* tris, uint64_t nt, BvhOut& out
     f[14] = 0.0f;
     f[15] = 0.0f;
   }
-  collapse_bvh4(out);
-  return 0;
+  if (wide) collapse_bvh4(out);
 }
+
+}  // namespace
 
 namespace {
 

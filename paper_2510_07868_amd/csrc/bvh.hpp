@@ -23,7 +23,12 @@ struct BvhOut {
 
 // Child link: bit 31 set = leaf with first = (link >> 3) & 0x0fffffff and count = (link & 7) + 1
 // triangles in BVH order; otherwise the index of an internal node.  Node 0 is the root.
-int build_bvh(const float* verts, const uint32_t* tris, uint64_t nt, BvhOut& out);
+// wide: also collapse the tree into out.nodes4.
+int build_bvh(const float* verts, const uint32_t* tris, uint64_t nt, BvhOut& out, bool wide = true);
+
+// The same binned-SAH tree over axis-aligned boxes (6 floats per item: lo xyz, hi xyz); leaf
+// links then index items in out.order.  No 4-wide copy.
+int build_bvh_boxes(const float* boxes, uint64_t n, BvhOut& out);
 
 // Collapses out.nodes (BVH2) into out.nodes4: each 4-wide node takes the two children of a
 // BVH2 node and repeatedly opens its largest-area inner child until it has four children.

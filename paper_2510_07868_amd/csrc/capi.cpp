@@ -43,7 +43,9 @@ struct nrrs_ctx {
   hipStream_t stream = nullptr;
   uint64_t npx = 0, nprim = 0, cap = 0;
   uint32_t cus = 0;                 // compute units of the device
-  uint32_t ext_occ[5] = {1, 1, 1, 1, 1};  // resident traversal blocks per CU of each variant
+  uint32_t ext_occ[5] = {1, 1, 1, 1, 1};  // resident traversal blocks per CU of each variant (0: not
+                                          // available for the current scene)
+  uint32_t ext_occ_flat[5] = {1, 1, 1, 1, 1}, ext_occ_inst[5] = {1, 1, 0, 1, 0};  // one- / two-level scenes
   bool bvh4_ok = false;             // the 4-wide tree fits the traversal stack (variant 4)
   uint32_t* spill = nullptr;        // sized for cus * max(ext_occ) blocks
   uint32_t* work = nullptr;         // traversal claim counters per depth and queue slice
@@ -70,8 +72,8 @@ struct nrrs_ctx {
   unsigned long long *st_n = nullptr, *st_s = nullptr, *st_r = nullptr;
   double *st_sumq = nullptr, *st_f = nullptr;
   uint32_t* work_nee = nullptr;  // shadow-ray claim counters (next-event estimation)
-  uint32_t* light_tri = nullptr;  // NEE light list (BVH indices), its CDF and per-triangle pdf
-  float *light_cdf = nullptr, *lpdf = nullptr;
+  float4* light_geo = nullptr;  // NEE light list (world-space triangles) and its CDF
+  float* light_cdf = nullptr;
   double* f_fixed = nullptr;  // [NRRS_MAX_DEPTH + 1] normalization factors given by nrrs_debug_set_norm_factors
   uint32_t f_fixed_n = 0;     // depths 1..f_fixed_n use them (0: computed)
   double* image = nullptr;
@@ -157,7 +159,8 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
       c->qb_pool_bytes = k.off - start;
     }
   }
-  const uint64_t max_blocks = (uint64_t)c->cus * *std::max_element(c->ext_occ, c->ext_occ + 5);
+  const uint64_t max_blocks = (uint64_t)c->cus * std::max(*std::max_element(c->ext_occ_flat, c->ext_occ_flat + 5),
+                                                          *std::max_element(c->ext_occ_inst, c->ext_occ_inst + 5));
   c->spill = k.take<uint32_t>((uint64_t)extend_spill_depth() * max_blocks * extend_threads_per_block());
   c->hit = k.take<float4>(C);
   c->vpos = k.take<float4>(C);
@@ -171,9 +174,8 @@ uint64_t carve(nrrs_ctx* c, uint8_t* base, uint64_t max_tris, uint32_t max_mats)
   c->ctl = k.take<DepthCtl>(NRRS_MAX_DEPTH + 2);
   c->work = k.take<uint32_t>((uint64_t)(NRRS_MAX_DEPTH + 2) * kWorkSlices * kWorkStride);
   c->work_nee = c->cfg.nee ? k.take<uint32_t>((uint64_t)(NRRS_MAX_DEPTH + 2) * kWorkSlices * kWorkStride) : nullptr;
-  c->light_tri = c->cfg.nee ? k.take<uint32_t>(max_tris) : nullptr;
+  c->light_geo = c->cfg.nee ? k.take<float4>(3 * max_tris) : nullptr;
   c->light_cdf = c->cfg.nee ? k.take<float>(max_tris + 1) : nullptr;
-  c->lpdf = c->cfg.nee ? k.take<float>(max_tris) : nullptr;
   c->alpha = k.take<double>(1);
   c->overflow = k.take<uint32_t>(1);
   c->rays = k.take<unsigned long long>(6);  // rays, nodes, triangles; the same for shadow rays
@@ -464,7 +466,10 @@ int32_t nrrs_create(const nrrs_config* cfg, void* hip_stream, nrrs_ctx** out) {
   c->nprim = nprim;
   c->cap = cap;
   c->cus = (uint32_t)prop.multiProcessorCount;
-  for (uint32_t v = 0; v < 5; ++v) c->ext_occ[v] = extend_blocks_per_cu(v);
+  for (uint32_t v = 0; v < 5; ++v) {
+    c->ext_occ_flat[v] = c->ext_occ[v] = extend_blocks_per_cu(v, false);
+    c->ext_occ_inst[v] = (v == 0 || v == 1 || v == 3) ? extend_blocks_per_cu(v, true) : 0u;
+  }
   c->tune.extend_variant = 3;
   c->tune.extend_blocks_per_cu = c->ext_occ[3];
   c->tune.extend_refill = 16;
@@ -534,132 +539,120 @@ int32_t nrrs_bind_workspace(nrrs_ctx* c, void* device_ptr, uint64_t bytes, uint6
   return NRRS_OK;
 }
 
-int32_t nrrs_upload_scene(nrrs_ctx* c, const float* verts, uint64_t nv, const uint32_t* tris, uint64_t nt,
-                          const uint32_t* tri_mat, const uint32_t* mat_type, const float* mat_params, uint32_t nm,
-                          const float* camera, const float* env) {
-  if (!c) return NRRS_EINVAL;
-  if (!c->bound) return fail(c, NRRS_ESTATE, "bind a workspace first");
-  if (!verts || !tris || !tri_mat || !mat_type || !mat_params || !camera || !env || nt == 0 || nv == 0 || nm == 0)
-    return fail(c, NRRS_EINVAL, "null array or empty scene");
-  if (nt > c->max_tris || nm > c->max_mats) return fail(c, NRRS_ENOMEM, "scene larger than the bound workspace");
-  if (!finite_all(verts, 3 * nv) || !finite_all(mat_params, 7ull * nm) || !finite_all(camera, 10) ||
-      !finite_all(env, 3))
-    return fail(c, NRRS_EINVAL, "non-finite scene value");
+namespace {
+
+// A scene ready for the device: triangle slots (12 floats: v0, tag; e1, material; e2, 0), tree
+// nodes (16 floats), the optional 4-wide copy, instance records (28 floats) with their uid index,
+// the flattened triangles' world geometry for the light list, and the uid <-> flattened-index
+// maps of the debug entry points.
+struct SceneHost {
+  std::vector<float> tri, nodes, nodes4, inst;
+  std::vector<uint32_t> inst_uid;  // (first uid, record) pairs, ascending
+  uint64_t n_nodes4 = 0;
+  bool bvh4_ok = false;
+  uint32_t root = 0, nt_base = 0, n_inst = 0;
+  float amin[3] = {INFINITY, INFINITY, INFINITY}, amax[3] = {-INFINITY, -INFINITY, -INFINITY};
+  std::vector<float> light_geo;  // 12 floats per emitting triangle, flattened order
+  std::vector<double> light_w;   // lum(L_e) x area of each
+  std::vector<uint32_t> uid_to_flat, flat_to_uid;
+};
+
+void grow_bounds(SceneHost& h, const float* p) {
+  for (int a = 0; a < 3; ++a) {
+    h.amin[a] = std::fmin(h.amin[a], p[a]);
+    h.amax[a] = std::fmax(h.amax[a], p[a]);
+  }
+}
+
+// The light list entry of a world-space triangle (v0, v1, v2 as float) with material m.
+void add_light(SceneHost& h, const float* v0, const float* v1, const float* v2, uint32_t m, const float* mat_params) {
+  const float* le = mat_params + 7ull * m + 4;
+  const double l = 0.2126 * le[0] + 0.7152 * le[1] + 0.0722 * le[2];
+  if (!(l > 0.0)) return;
+  float g[12];
+  for (int a = 0; a < 3; ++a) {
+    g[a] = v0[a];
+    g[4 + a] = v1[a] - v0[a];
+    g[8 + a] = v2[a] - v0[a];
+  }
+  std::memcpy(&g[3], &m, 4);
+  std::memcpy(&g[7], &m, 4);
+  g[11] = 0.0f;
+  const double cx = (double)g[5] * g[10] - (double)g[6] * g[9];
+  const double cy = (double)g[6] * g[8] - (double)g[4] * g[10];
+  const double cz = (double)g[4] * g[9] - (double)g[5] * g[8];
+  const double area = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+  if (!(area > 0.0)) return;
+  h.light_geo.insert(h.light_geo.end(), g, g + 12);
+  h.light_w.push_back(l * area);
+}
+
+// Checks shared by both uploads: a triangle list over nv vertices with materials below nm.
+int32_t check_mesh(nrrs_ctx* c, const float* verts, uint64_t nv, const uint32_t* tris, uint64_t nt,
+                   const uint32_t* tri_mat, uint32_t nm) {
+  if (!finite_all(verts, 3 * nv)) return fail(c, NRRS_EINVAL, "non-finite scene value");
   for (uint64_t i = 0; i < 3 * nt; ++i)
     if (tris[i] >= nv) return fail(c, NRRS_EINVAL, "triangle vertex index out of range");
   for (uint64_t i = 0; i < nt; ++i)
     if (tri_mat[i] >= nm) return fail(c, NRRS_EINVAL, "triangle material out of range");
-  for (uint32_t m = 0; m < nm; ++m)
-    if (mat_type[m] > NRRS_MAT_EMITTER) return fail(c, NRRS_EINVAL, "unknown material type");
-  if (!(camera[9] > 0.0f && camera[9] < 180.0f)) return fail(c, NRRS_EINVAL, "camera fov out of range");
-  BvhOut bvh;
-  build_bvh(verts, tris, nt, bvh);
-  if (bvh.n_nodes > c->max_tris + 2 || bvh.n_nodes4 > c->max_tris + 2)
-    return fail(c, NRRS_ENOMEM, "BVH larger than reserved");
-  if (bvh.max_depth > kMaxBvhDepth) return fail(c, NRRS_EINVAL, "BVH deeper than the traversal stack");
-  for (uint64_t i = 0; i < 2 * bvh.n_nodes; ++i) {
+  return NRRS_OK;
+}
+
+int32_t check_tree(nrrs_ctx* c, const BvhOut& b) {
+  if (b.max_depth > kMaxBvhDepth) return fail(c, NRRS_EINVAL, "BVH deeper than the traversal stack");
+  for (uint64_t i = 0; i < 2 * b.n_nodes; ++i) {
     uint32_t l;
-    std::memcpy(&l, &bvh.nodes[16 * (i / 2) + 12 + (i % 2)], 4);
+    std::memcpy(&l, &b.nodes[16 * (i / 2) + 12 + (i % 2)], 4);
     if ((l & 0x80000000u) && (l & 7u) + 1u > kLeafMaxTris) return fail(c, NRRS_EINVAL, "BVH leaf too large");
   }
-  // triangles in BVH order: (v0, original index), (e1, material), (e2, 0)
-  std::vector<float> tri(12 * nt);
-  float amin[3] = {INFINITY, INFINITY, INFINITY}, amax[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (uint64_t k = 0; k < nt; ++k) {
-    const uint32_t t = bvh.order[k];
-    const float* v0 = verts + 3ull * tris[3 * t];
-    const float* v1 = verts + 3ull * tris[3 * t + 1];
-    const float* v2 = verts + 3ull * tris[3 * t + 2];
-    float* o = &tri[12 * k];
-    for (int a = 0; a < 3; ++a) {
-      o[a] = v0[a];
-      o[4 + a] = v1[a] - v0[a];
-      o[8 + a] = v2[a] - v0[a];
-      amin[a] = std::fmin(amin[a], std::fmin(v0[a], std::fmin(v1[a], v2[a])));
-      amax[a] = std::fmax(amax[a], std::fmax(v0[a], std::fmax(v1[a], v2[a])));
+  return NRRS_OK;
+}
+
+// Appends tree b to h.nodes: inner links move by the node offset, leaf links by first_slot
+// (their triangles' or instances' first index), instance leaves get kInstLeaf.
+void append_tree(SceneHost& h, const BvhOut& b, uint32_t first_slot, bool inst_leaves) {
+  const uint32_t off = (uint32_t)(h.nodes.size() / 16);
+  const size_t at = h.nodes.size();
+  h.nodes.insert(h.nodes.end(), b.nodes.begin(), b.nodes.end());
+  for (uint64_t i = 0; i < b.n_nodes; ++i)
+    for (int c = 0; c < 2; ++c) {
+      float* f = &h.nodes[at + 16 * i + 12 + c];
+      uint32_t l;
+      std::memcpy(&l, f, 4);
+      if (l & 0x80000000u) {
+        const uint32_t first = ((l >> 3) & 0x0fffffffu) + first_slot;
+        l = 0x80000000u | (first << 3) | (l & 3u) | (inst_leaves ? kInstLeaf : 0u);
+      } else {
+        l += off;
+      }
+      std::memcpy(f, &l, 4);
     }
-    std::memcpy(&o[3], &t, 4);
-    std::memcpy(&o[7], &tri_mat[t], 4);
-    o[11] = 0.0f;
-  }
+}
+
+// Uploads h with the materials, camera and environment (validated by the caller).
+int32_t commit_scene(nrrs_ctx* c, SceneHost& h, const uint32_t* mat_type, const float* mat_params, uint32_t nm,
+                     const float* camera, const float* env) {
+  const uint64_t n_nodes = h.nodes.size() / 16;
+  if (n_nodes > c->max_tris + 2 || h.n_nodes4 > c->max_tris + 2) return fail(c, NRRS_ENOMEM, "BVH larger than reserved");
+  if (h.tri.size() + h.inst.size() + (h.inst_uid.size() + 3) / 4 * 4 > 12 * c->max_tris)
+    return fail(c, NRRS_ENOMEM, "triangles and instances larger than the bound workspace");
+  if (c->cfg.nee && h.light_w.size() > c->max_tris) return fail(c, NRRS_ENOMEM, "more lights than the workspace holds");
   std::vector<float> mats(8ull * nm);
   for (uint32_t m = 0; m < nm; ++m) {
     for (int k = 0; k < 4; ++k) mats[8ull * m + k] = mat_params[7ull * m + k];
     for (int k = 0; k < 3; ++k) mats[8ull * m + 4 + k] = mat_params[7ull * m + 4 + k];
     std::memcpy(&mats[8ull * m + 7], &mat_type[m], 4);
   }
-  // next-event estimation's lights: the emitting triangles (BVH order), chosen with probability
-  // lum(L_e) x area (CDF in double, stored in float), and lum(L_e) / sum as the pdf per unit
-  // area of every triangle (0 for the rest)
-  // (listed in the scene's own triangle order, so that a uniform picks the same light whatever
-  // the BVH order; each entry holds the triangle's BVH index)
-  std::vector<uint32_t> light_tri;
-  std::vector<float> light_cdf(1, 0.0f), lpdf;
+  // next-event estimation: lights chosen with probability lum(L_e) x area (CDF in double, stored
+  // in float, last entry 1), pdf per unit area lum(L_e) / sum
+  std::vector<float> light_cdf(1, 0.0f);
+  double total = 0.0;
   if (c->cfg.nee) {
-    lpdf.assign(nt, 0.0f);
-    std::vector<uint32_t> to_bvh(nt);
-    for (uint64_t k = 0; k < nt; ++k) to_bvh[bvh.order[k]] = (uint32_t)k;
     std::vector<double> cum;
-    double total = 0.0;
-    for (uint64_t t = 0; t < nt; ++t) {
-      const uint32_t k = to_bvh[t];
-      const float* le = mat_params + 7ull * tri_mat[t] + 4;
-      const double l = 0.2126 * le[0] + 0.7152 * le[1] + 0.0722 * le[2];
-      if (!(l > 0.0)) continue;
-      const float* e1 = &tri[12 * k + 4];
-      const float* e2 = &tri[12 * k + 8];
-      const double cx = (double)e1[1] * e2[2] - (double)e1[2] * e2[1];
-      const double cy = (double)e1[2] * e2[0] - (double)e1[0] * e2[2];
-      const double cz = (double)e1[0] * e2[1] - (double)e1[1] * e2[0];
-      const double area = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
-      if (!(area > 0.0)) continue;
-      total += l * area;
-      light_tri.push_back((uint32_t)k);
-      cum.push_back(total);
-    }
+    for (double w : h.light_w) cum.push_back(total += w);
     for (double v : cum) light_cdf.push_back((float)(v / total));
-    if (!light_tri.empty()) light_cdf.back() = 1.0f;
-    for (uint32_t k : light_tri) {
-      const float* le = mat_params + 7ull * tri_mat[bvh.order[k]] + 4;
-      lpdf[k] = (float)((0.2126 * le[0] + 0.7152 * le[1] + 0.0722 * le[2]) / total);
-    }
+    if (!h.light_w.empty()) light_cdf.back() = 1.0f;
   }
-  hipStream_t s = c->stream;
-  HIPC(c, hipStreamSynchronize(s));
-  if (c->cfg.nee) {
-    if (!light_tri.empty()) {
-      HIPC(c, hipMemcpy(c->light_tri, light_tri.data(), 4 * light_tri.size(), hipMemcpyHostToDevice));
-      HIPC(c, hipMemcpy(c->light_cdf, light_cdf.data(), 4 * light_cdf.size(), hipMemcpyHostToDevice));
-    }
-    HIPC(c, hipMemcpy(c->lpdf, lpdf.data(), 4 * lpdf.size(), hipMemcpyHostToDevice));
-  }
-  HIPC(c, hipMemcpy(c->tri, tri.data(), sizeof(float) * tri.size(), hipMemcpyHostToDevice));
-  HIPC(c, hipMemcpy(c->node, bvh.nodes.data(), sizeof(float) * bvh.nodes.size(), hipMemcpyHostToDevice));
-  HIPC(c, hipMemcpy(c->node4, bvh.nodes4.data(), sizeof(float) * bvh.nodes4.size(), hipMemcpyHostToDevice));
-  HIPC(c, hipMemcpy(c->mat, mats.data(), sizeof(float) * mats.size(), hipMemcpyHostToDevice));
-  DevScene& d = c->sc;
-  d.tri = c->tri;
-  d.node = c->node;
-  d.node4 = c->node4;
-  d.nn4 = (uint32_t)bvh.n_nodes4;
-  d.mat = c->mat;
-  d.nt = (uint32_t)nt;
-  d.nn = (uint32_t)bvh.n_nodes;
-  d.nm = nm;
-  d.light_tri = c->light_tri;
-  d.light_cdf = c->light_cdf;
-  d.lpdf = c->lpdf;
-  d.nl = (uint32_t)light_tri.size();
-  d.amin_x = amin[0];
-  d.amin_y = amin[1];
-  d.amin_z = amin[2];
-  const double ex = amax[0] - amin[0], ey = amax[1] - amin[1], ez = amax[2] - amin[2];
-  d.extent = (float)std::fmax(ex, std::fmax(ey, ez));
-  d.tmin = 0.0f;                                  // hits count for t > 0 ...
-  d.offset = (float)(1e-5 * d.extent);             // ... because child origins leave the surface
-  d.env_r = env[0];
-  d.env_g = env[1];
-  d.env_b = env[2];
   // camera basis in double, then handed to the kernels in float
   const double eye[3] = {camera[0], camera[1], camera[2]};
   double fwd[3] = {camera[3] - eye[0], camera[4] - eye[1], camera[5] - eye[2]};
@@ -672,6 +665,52 @@ int32_t nrrs_upload_scene(nrrs_ctx* c, const float* verts, uint64_t nv, const ui
   if (!(l > 0.0)) return fail(c, NRRS_EINVAL, "camera up is parallel to the view direction");
   for (double& x : r) x /= l;
   const double u[3] = {r[1] * fwd[2] - r[2] * fwd[1], r[2] * fwd[0] - r[0] * fwd[2], r[0] * fwd[1] - r[1] * fwd[0]};
+  hipStream_t s = c->stream;
+  HIPC(c, hipStreamSynchronize(s));
+  if (c->cfg.nee && !h.light_w.empty()) {
+    HIPC(c, hipMemcpy(c->light_geo, h.light_geo.data(), 4 * h.light_geo.size(), hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(c->light_cdf, light_cdf.data(), 4 * light_cdf.size(), hipMemcpyHostToDevice));
+  }
+  // instance records and their uid index follow the triangles in the triangle region
+  float4* inst_dev = c->tri + h.tri.size() / 4;
+  uint32_t* uid_dev = reinterpret_cast<uint32_t*>(inst_dev + h.inst.size() / 4);
+  HIPC(c, hipMemcpy(c->tri, h.tri.data(), sizeof(float) * h.tri.size(), hipMemcpyHostToDevice));
+  if (h.n_inst) {
+    HIPC(c, hipMemcpy(inst_dev, h.inst.data(), sizeof(float) * h.inst.size(), hipMemcpyHostToDevice));
+    HIPC(c, hipMemcpy(uid_dev, h.inst_uid.data(), sizeof(uint32_t) * h.inst_uid.size(), hipMemcpyHostToDevice));
+  }
+  HIPC(c, hipMemcpy(c->node, h.nodes.data(), sizeof(float) * h.nodes.size(), hipMemcpyHostToDevice));
+  if (h.n_nodes4)
+    HIPC(c, hipMemcpy(c->node4, h.nodes4.data(), sizeof(float) * h.nodes4.size(), hipMemcpyHostToDevice));
+  HIPC(c, hipMemcpy(c->mat, mats.data(), sizeof(float) * mats.size(), hipMemcpyHostToDevice));
+  DevScene& d = c->sc;
+  d.tri = c->tri;
+  d.node = c->node;
+  d.node4 = c->node4;
+  d.nn4 = (uint32_t)h.n_nodes4;
+  d.mat = c->mat;
+  d.nt = (uint32_t)(h.tri.size() / 12);
+  d.nn = (uint32_t)n_nodes;
+  d.nm = nm;
+  d.light_geo = c->light_geo;
+  d.light_cdf = c->light_cdf;
+  d.nl = c->cfg.nee ? (uint32_t)h.light_w.size() : 0u;
+  d.light_scale = d.nl ? (float)(1.0 / total) : 0.0f;
+  d.inst = h.n_inst ? inst_dev : nullptr;
+  d.inst_uid = h.n_inst ? uid_dev : nullptr;
+  d.n_inst = h.n_inst;
+  d.root = h.root;
+  d.nt_base = h.nt_base;
+  d.amin_x = h.amin[0];
+  d.amin_y = h.amin[1];
+  d.amin_z = h.amin[2];
+  const double ex = h.amax[0] - h.amin[0], ey = h.amax[1] - h.amin[1], ez = h.amax[2] - h.amin[2];
+  d.extent = (float)std::fmax(ex, std::fmax(ey, ez));
+  d.tmin = 0.0f;                                  // hits count for t > 0 ...
+  d.offset = (float)(1e-5 * d.extent);             // ... because child origins leave the surface
+  d.env_r = env[0];
+  d.env_g = env[1];
+  d.env_b = env[2];
   const double th = std::tan((double)camera[9] * M_PI / 360.0);
   const double aspect = (double)c->cfg.width / (double)c->cfg.height;
   d.eye_x = (float)eye[0]; d.eye_y = (float)eye[1]; d.eye_z = (float)eye[2];
@@ -679,16 +718,293 @@ int32_t nrrs_upload_scene(nrrs_ctx* c, const float* verts, uint64_t nv, const ui
   d.rx = (float)(r[0] * th * aspect); d.ry = (float)(r[1] * th * aspect); d.rz = (float)(r[2] * th * aspect);
   d.ux = (float)(u[0] * th); d.uy = (float)(u[1] * th); d.uz = (float)(u[2] * th);
   c->drop_graphs();  // captured passes hold the old scene in their kernel arguments
-  c->bvh4_ok = bvh.max_depth4 <= kMaxBvh4Depth;
-  if (!c->bvh4_ok && c->tune.extend_variant == 4) {
-    c->tune.extend_variant = 3;
-    c->tune.extend_blocks_per_cu = std::min(c->tune.extend_blocks_per_cu, c->ext_occ[3]);
-  }
-  c->bvh_order = bvh.order;
-  c->orig_to_bvh.assign(nt, 0);
-  for (uint64_t k = 0; k < nt; ++k) c->orig_to_bvh[bvh.order[k]] = (uint32_t)k;
+  // the traversal variants of this kind of scene, and a tuning that fits them
+  for (int v = 0; v < 5; ++v) c->ext_occ[v] = h.n_inst ? c->ext_occ_inst[v] : c->ext_occ_flat[v];
+  c->bvh4_ok = h.bvh4_ok;
+  if (!c->bvh4_ok) c->ext_occ[4] = 0;
+  if (c->ext_occ[c->tune.extend_variant] == 0) c->tune.extend_variant = 3;
+  c->tune.extend_blocks_per_cu = std::max(1u, std::min(c->tune.extend_blocks_per_cu, c->ext_occ[c->tune.extend_variant]));
+  c->bvh_order.swap(h.uid_to_flat);
+  c->orig_to_bvh.swap(h.flat_to_uid);
   c->scene = true;
   return NRRS_OK;
+}
+
+int32_t check_common(nrrs_ctx* c, const uint32_t* mat_type, const float* mat_params, uint32_t nm,
+                     const float* camera, const float* env) {
+  if (!mat_type || !mat_params || !camera || !env || nm == 0) return fail(c, NRRS_EINVAL, "null array or no material");
+  if (nm > c->max_mats) return fail(c, NRRS_ENOMEM, "scene larger than the bound workspace");
+  if (!finite_all(mat_params, 7ull * nm) || !finite_all(camera, 10) || !finite_all(env, 3))
+    return fail(c, NRRS_EINVAL, "non-finite scene value");
+  for (uint32_t m = 0; m < nm; ++m)
+    if (mat_type[m] > NRRS_MAT_EMITTER) return fail(c, NRRS_EINVAL, "unknown material type");
+  if (!(camera[9] > 0.0f && camera[9] < 180.0f)) return fail(c, NRRS_EINVAL, "camera fov out of range");
+  return NRRS_OK;
+}
+
+// Triangles of one tree into h.tri, in the tree's order, starting at slot first; tag = the
+// original index (stored_index false) or the slot itself (true).
+void append_tris(SceneHost& h, const float* verts, const uint32_t* tris, const uint32_t* tri_mat, const BvhOut& b,
+                 bool stored_index) {
+  const uint32_t first = (uint32_t)(h.tri.size() / 12);
+  const uint64_t nt = b.order.size();
+  h.tri.resize(h.tri.size() + 12 * nt);
+  for (uint64_t k = 0; k < nt; ++k) {
+    const uint32_t t = b.order[k];
+    const float* v0 = verts + 3ull * tris[3 * t];
+    const float* v1 = verts + 3ull * tris[3 * t + 1];
+    const float* v2 = verts + 3ull * tris[3 * t + 2];
+    float* o = &h.tri[12 * (first + k)];
+    for (int a = 0; a < 3; ++a) {
+      o[a] = v0[a];
+      o[4 + a] = v1[a] - v0[a];
+      o[8 + a] = v2[a] - v0[a];
+    }
+    const uint32_t tag = stored_index ? first + (uint32_t)k : t;
+    std::memcpy(&o[3], &tag, 4);
+    std::memcpy(&o[7], &tri_mat[t], 4);
+    o[11] = 0.0f;
+  }
+}
+
+}  // namespace
+
+int32_t nrrs_upload_scene(nrrs_ctx* c, const float* verts, uint64_t nv, const uint32_t* tris, uint64_t nt,
+                          const uint32_t* tri_mat, const uint32_t* mat_type, const float* mat_params, uint32_t nm,
+                          const float* camera, const float* env) {
+  if (!c) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "bind a workspace first");
+  if (!verts || !tris || !tri_mat || nt == 0 || nv == 0) return fail(c, NRRS_EINVAL, "null array or empty scene");
+  if (int32_t e = check_common(c, mat_type, mat_params, nm, camera, env)) return e;
+  if (nt > c->max_tris) return fail(c, NRRS_ENOMEM, "scene larger than the bound workspace");
+  if (int32_t e = check_mesh(c, verts, nv, tris, nt, tri_mat, nm)) return e;
+  BvhOut bvh;
+  build_bvh(verts, tris, nt, bvh, true);
+  if (int32_t e = check_tree(c, bvh)) return e;
+  SceneHost h;
+  append_tris(h, verts, tris, tri_mat, bvh, false);
+  h.nodes = std::move(bvh.nodes);
+  h.nodes4 = std::move(bvh.nodes4);
+  h.n_nodes4 = bvh.n_nodes4;
+  h.bvh4_ok = bvh.max_depth4 <= kMaxBvh4Depth;
+  h.nt_base = (uint32_t)nt;
+  h.flat_to_uid.assign(nt, 0);
+  for (uint64_t k = 0; k < nt; ++k) h.flat_to_uid[bvh.order[k]] = (uint32_t)k;
+  for (uint64_t t = 0; t < nt; ++t) {
+    const float* v[3] = {verts + 3ull * tris[3 * t], verts + 3ull * tris[3 * t + 1], verts + 3ull * tris[3 * t + 2]};
+    for (const float* p : v) grow_bounds(h, p);
+    // lights listed in the scene's own triangle order, so that a uniform picks the same light
+    // whatever the BVH order
+    if (c->cfg.nee) add_light(h, v[0], v[1], v[2], tri_mat[t], mat_params);
+  }
+  h.uid_to_flat = std::move(bvh.order);
+  return commit_scene(c, h, mat_type, mat_params, nm, camera, env);
+}
+
+int32_t nrrs_upload_scene_instanced(nrrs_ctx* c, const float* verts, uint64_t nv, const uint32_t* tris, uint64_t nt,
+                                    const uint32_t* tri_mat, const uint32_t* mat_type, const float* mat_params,
+                                    uint32_t nm, const float* camera, const float* env, const nrrs_instances* in) {
+  if (!c) return NRRS_EINVAL;
+  if (!c->bound) return fail(c, NRRS_ESTATE, "bind a workspace first");
+  if (!in) return fail(c, NRRS_EINVAL, "no instance description");
+  if (nt && (!verts || !tris || !tri_mat || nv == 0)) return fail(c, NRRS_EINVAL, "null array in the base mesh");
+  if (int32_t e = check_common(c, mat_type, mat_params, nm, camera, env)) return e;
+  const uint32_t nmesh = in->n_meshes, ninst = in->n_inst;
+  if (nmesh == 0 || ninst == 0 || !in->mesh_verts || !in->mesh_tris || !in->mesh_tri_mat || !in->mesh_tri_begin ||
+      !in->inst_mesh || !in->inst_xform || !in->inst_mat || in->mesh_nv == 0)
+    return fail(c, NRRS_EINVAL, "null array or no mesh / instance");
+  const uint64_t* beg = in->mesh_tri_begin;
+  if (beg[0] != 0) return fail(c, NRRS_EINVAL, "mesh_tri_begin[0] must be 0");
+  for (uint32_t m = 0; m < nmesh; ++m)
+    if (beg[m + 1] <= beg[m]) return fail(c, NRRS_EINVAL, "every mesh needs at least one triangle");
+  const uint64_t mesh_nt = beg[nmesh];
+  if (ninst >= (1u << 26)) return fail(c, NRRS_EINVAL, "too many instances");
+  const uint64_t n_rec = ninst + (nt ? 1 : 0);
+  if (nt + mesh_nt + 3 * n_rec > c->max_tris) return fail(c, NRRS_ENOMEM, "scene larger than the bound workspace");
+  if (nt && check_mesh(c, verts, nv, tris, nt, tri_mat, nm)) return NRRS_EINVAL;
+  if (int32_t e = check_mesh(c, in->mesh_verts, in->mesh_nv, in->mesh_tris, mesh_nt, in->mesh_tri_mat, nm)) return e;
+  uint64_t flat = nt;
+  for (uint32_t j = 0; j < ninst; ++j) {
+    if (in->inst_mesh[j] >= nmesh) return fail(c, NRRS_EINVAL, "instance mesh out of range");
+    if (in->inst_mat[j] != NRRS_NO_MATERIAL && in->inst_mat[j] >= nm)
+      return fail(c, NRRS_EINVAL, "instance material out of range");
+    if (!finite_all(in->inst_xform + 12ull * j, 12)) return fail(c, NRRS_EINVAL, "non-finite instance transform");
+    flat += beg[in->inst_mesh[j] + 1] - beg[in->inst_mesh[j]];
+  }
+  if (flat >= (1ull << 31)) return fail(c, NRRS_EINVAL, "more than 2^31 triangles after instancing");
+  SceneHost h;
+  h.nt_base = (uint32_t)nt;
+  // the base mesh and each mesh: trees of their own, triangles in tree order
+  BvhOut base;
+  int max_blas_depth = 0;
+  if (nt) {
+    build_bvh(verts, tris, nt, base, false);
+    if (int32_t e = check_tree(c, base)) return e;
+    append_tris(h, verts, tris, tri_mat, base, false);
+    append_tree(h, base, 0, false);
+    max_blas_depth = base.max_depth;
+  }
+  std::vector<BvhOut> mesh(nmesh);
+  std::vector<uint32_t> mesh_first(nmesh), mesh_root(nmesh);
+  for (uint32_t m = 0; m < nmesh; ++m) {
+    build_bvh(in->mesh_verts, in->mesh_tris + 3 * beg[m], beg[m + 1] - beg[m], mesh[m], false);
+    if (int32_t e = check_tree(c, mesh[m])) return e;
+    mesh_first[m] = (uint32_t)(h.tri.size() / 12);
+    mesh_root[m] = (uint32_t)(h.nodes.size() / 16);
+    append_tris(h, in->mesh_verts, in->mesh_tris + 3 * beg[m], in->mesh_tri_mat + beg[m], mesh[m], true);
+    append_tree(h, mesh[m], mesh_first[m], false);
+    max_blas_depth = std::max(max_blas_depth, mesh[m].max_depth);
+  }
+  // records: the base mesh (identity) first, then the instances; world boxes for the top tree
+  struct Rec {
+    double fwd[12], inv[12];
+    uint32_t root, uoff, mat, uid;
+  };
+  std::vector<Rec> recs;
+  std::vector<float> boxes;
+  auto root_box = [&](const BvhOut& b, double lo[3], double hi[3]) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::fmin(b.nodes[a], b.nodes[6 + a]);
+      hi[a] = std::fmax(b.nodes[3 + a], b.nodes[9 + a]);
+    }
+  };
+  auto push_box = [&](const double lo[3], const double hi[3]) {
+    for (int a = 0; a < 3; ++a) boxes.push_back(std::nextafter((float)lo[a], -INFINITY));
+    for (int a = 0; a < 3; ++a) boxes.push_back(std::nextafter((float)hi[a], INFINITY));
+  };
+  if (nt) {
+    Rec r{};
+    for (int k = 0; k < 3; ++k) r.fwd[5 * k] = r.inv[5 * k] = 1.0;  // identity, no translation
+    r.root = 0;  // the base tree went in first
+    r.uoff = 0;
+    r.mat = NRRS_NO_MATERIAL;
+    r.uid = 0;
+    recs.push_back(r);
+    double lo[3], hi[3];
+    root_box(base, lo, hi);
+    push_box(lo, hi);
+  }
+  uint32_t uid = (uint32_t)nt;
+  for (uint32_t j = 0; j < ninst; ++j) {
+    const float* x = in->inst_xform + 12ull * j;
+    Rec r{};
+    for (int k = 0; k < 12; ++k) r.fwd[k] = x[k];
+    // inverse of the 3x3 part and of the translation, in double
+    const double* M = r.fwd;
+    const double a00 = M[0], a01 = M[1], a02 = M[2], a10 = M[4], a11 = M[5], a12 = M[6], a20 = M[8], a21 = M[9],
+                 a22 = M[10];
+    const double c00 = a11 * a22 - a12 * a21, c01 = a02 * a21 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+    const double c10 = a12 * a20 - a10 * a22, c11 = a00 * a22 - a02 * a20, c12 = a02 * a10 - a00 * a12;
+    const double c20 = a10 * a21 - a11 * a20, c21 = a01 * a20 - a00 * a21, c22 = a00 * a11 - a01 * a10;
+    const double det = a00 * c00 + a01 * c10 + a02 * c20;
+    const double scale = std::fmax(std::fabs(a00) + std::fabs(a01) + std::fabs(a02),
+                                   std::fmax(std::fabs(a10) + std::fabs(a11) + std::fabs(a12),
+                                             std::fabs(a20) + std::fabs(a21) + std::fabs(a22)));
+    if (!(std::fabs(det) > 1e-12 * scale * scale * scale)) return fail(c, NRRS_EINVAL, "singular instance transform");
+    const double inv3[9] = {c00 / det, c01 / det, c02 / det, c10 / det, c11 / det, c12 / det,
+                            c20 / det, c21 / det, c22 / det};
+    // rows of A^-1, each with the translation's component in w: the kernels map a point as
+    // A^-1 (p - t), subtracting first, so that the rounding scales with |p - t| rather than |p|
+    for (int row = 0; row < 3; ++row) {
+      for (int k = 0; k < 3; ++k) r.inv[4 * row + k] = inv3[3 * row + k];
+      r.inv[4 * row + 3] = M[4 * row + 3];
+    }
+    const uint32_t m = in->inst_mesh[j];
+    r.root = mesh_root[m];
+    r.uoff = uid - mesh_first[m];  // (modulo 2^32)
+    r.mat = in->inst_mat[j];
+    r.uid = uid;
+    recs.push_back(r);
+    // world box: the eight corners of the mesh's root box moved by the transform
+    double blo[3], bhi[3], lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    root_box(mesh[m], blo, bhi);
+    for (int corner = 0; corner < 8; ++corner) {
+      const double p[3] = {(corner & 1) ? bhi[0] : blo[0], (corner & 2) ? bhi[1] : blo[1], (corner & 4) ? bhi[2] : blo[2]};
+      for (int a = 0; a < 3; ++a) {
+        const double w = M[4 * a] * p[0] + M[4 * a + 1] * p[1] + M[4 * a + 2] * p[2] + M[4 * a + 3];
+        lo[a] = std::fmin(lo[a], w);
+        hi[a] = std::fmax(hi[a], w);
+      }
+    }
+    // and a relative allowance for the float32 transform of rays into object space
+    const double pad = 1e-6 * std::fmax(std::fmax(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]);
+    for (int a = 0; a < 3; ++a) {
+      lo[a] -= pad;
+      hi[a] += pad;
+    }
+    push_box(lo, hi);
+    uid += (uint32_t)(beg[m + 1] - beg[m]);
+  }
+  BvhOut top;
+  build_bvh_boxes(boxes.data(), recs.size(), top);
+  if (top.max_depth + max_blas_depth + 2 > kMaxBvhDepth)
+    return fail(c, NRRS_EINVAL, "instance tree and mesh trees together deeper than the traversal stack");
+  h.root = (uint32_t)(h.nodes.size() / 16);
+  append_tree(h, top, 0, true);
+  // records in the top tree's order (a leaf lists consecutive records)
+  h.n_inst = (uint32_t)recs.size();
+  h.inst.resize(28ull * recs.size());
+  std::vector<std::pair<uint32_t, uint32_t>> by_uid;
+  for (uint32_t k = 0; k < recs.size(); ++k) {
+    const Rec& r = recs[top.order[k]];
+    float* f = &h.inst[28ull * k];
+    for (int q = 0; q < 12; ++q) f[q] = (float)r.inv[q];
+    for (int q = 0; q < 12; ++q) f[12 + q] = (float)r.fwd[q];
+    std::memcpy(&f[24], &r.root, 4);
+    std::memcpy(&f[25], &r.uoff, 4);
+    std::memcpy(&f[26], &r.mat, 4);
+    std::memcpy(&f[27], &r.uid, 4);
+    by_uid.push_back({r.uid, k});
+  }
+  std::sort(by_uid.begin(), by_uid.end());
+  for (const auto& p : by_uid) {
+    h.inst_uid.push_back(p.first);
+    h.inst_uid.push_back(p.second);
+  }
+  // flattened order: the base triangles, then each instance's mesh triangles in the mesh's own
+  // order; world vertices are ((m0 x + m1 y) + m2 z) + t in double, rounded to float
+  h.uid_to_flat.resize(flat);
+  h.flat_to_uid.resize(flat);
+  for (uint64_t k = 0; k < nt; ++k) {
+    h.uid_to_flat[k] = base.order[k];
+    h.flat_to_uid[base.order[k]] = (uint32_t)k;
+  }
+  for (uint64_t t = 0; t < nt; ++t) {
+    const float* v[3] = {verts + 3ull * tris[3 * t], verts + 3ull * tris[3 * t + 1], verts + 3ull * tris[3 * t + 2]};
+    for (const float* p : v) grow_bounds(h, p);
+    if (c->cfg.nee) add_light(h, v[0], v[1], v[2], tri_mat[t], mat_params);
+  }
+  uid = (uint32_t)nt;
+  for (uint32_t j = 0; j < ninst; ++j) {
+    const uint32_t m = in->inst_mesh[j];
+    const float* x = in->inst_xform + 12ull * j;
+    const uint64_t n_m = beg[m + 1] - beg[m];
+    for (uint64_t k = 0; k < n_m; ++k) {
+      h.uid_to_flat[uid + k] = uid + mesh[m].order[k];
+      h.flat_to_uid[uid + mesh[m].order[k]] = uid + (uint32_t)k;
+    }
+    for (uint64_t i = 0; i < n_m; ++i) {
+      const uint32_t* tv = in->mesh_tris + 3 * (beg[m] + i);
+      float w[3][3];
+      for (int q = 0; q < 3; ++q) {
+        const float* p = in->mesh_verts + 3ull * tv[q];
+        for (int a = 0; a < 3; ++a) {
+          const double s0 = (double)x[4 * a] * p[0];
+          const double s1 = (double)x[4 * a + 1] * p[1];
+          const double s2 = (double)x[4 * a + 2] * p[2];
+          const double s01 = s0 + s1;
+          const double s012 = s01 + s2;
+          w[q][a] = (float)(s012 + (double)x[4 * a + 3]);
+        }
+        grow_bounds(h, w[q]);
+      }
+      const uint32_t mt = in->inst_mat[j] != NRRS_NO_MATERIAL ? in->inst_mat[j] : in->mesh_tri_mat[beg[m] + i];
+      if (c->cfg.nee) add_light(h, w[0], w[1], w[2], mt, mat_params);
+    }
+    uid += (uint32_t)n_m;
+  }
+  h.bvh4_ok = false;
+  return commit_scene(c, h, mat_type, mat_params, nm, camera, env);
 }
 
 int32_t nrrs_set_launch_mode(nrrs_ctx* c, int32_t mode) {
@@ -1014,7 +1330,7 @@ int32_t nrrs_autotune(nrrs_ctx* c, uint32_t max_depth, nrrs_tuning* best, nrrs_t
   // 1: variant x refill threshold at full occupancy (claim chunk 64, leaf batch 16); 2: fewer
   // resident blocks per CU; 3: claim chunk; 4: leaf batch (variants that park leaves)
   for (uint32_t v = 0; v < 5; ++v) {
-    if (v == 4 && !c->bvh4_ok) continue;
+    if (c->ext_occ[v] == 0) continue;  // not available for this scene
     for (uint32_t refill : {8u, 16u, 32u, 48u}) {
       nrrs_tuning t = cur;
       t.extend_variant = v;

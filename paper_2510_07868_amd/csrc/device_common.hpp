@@ -160,14 +160,28 @@ struct DevScene {
   float amin_x, amin_y, amin_z, extent, tmin, offset;
   float env_r, env_g, env_b;
   float eye_x, eye_y, eye_z, fwd_x, fwd_y, fwd_z, rx, ry, rz, ux, uy, uz;  // R, U pre-scaled
-  // lights for next-event estimation: emitting triangles (BVH indices), chosen with probability
-  // proportional to lum(L_e) x area through the CDF; lpdf = that probability per unit area for
-  // every triangle (0 for non-emitters)
-  const uint32_t* light_tri;
+  // lights for next-event estimation: the emitting triangles in world space (3 float4 each, the
+  // layout of tri), chosen with probability lum(L_e) x area through the CDF; that probability
+  // per unit area is lum(L_e) x light_scale (light_scale = 1 / sum of lum(L_e) x area)
+  const float4* light_geo;
   const float* light_cdf;  // nl + 1 entries, 0 .. 1
-  const float* lpdf;       // per triangle (BVH order)
+  float light_scale;
   uint32_t nl;
+  // Two-level scenes (n_inst > 0): the traversal starts at node `root` of a tree over
+  // instances, whose leaves (kInstLeaf set) list up to four instances; each instance is 7
+  // float4: the rows of A^-1 with the translation t's components in w (a world point p maps to
+  // A^-1 (p - t)), the rows of the object-to-world map (A | t), and (object tree's root link,
+  // uid offset, material or kNoMat, first uid) as bits.
+  // A hit's primitive id (uid) is the tri index k below nt_base (the non-instanced triangles),
+  // else k + uid offset of its instance; inst_uid holds (first uid, record) pairs ascending by uid.
+  const float4* inst;
+  const uint32_t* inst_uid;
+  uint32_t n_inst, root, nt_base;
 };
+
+constexpr uint32_t kInstLeaf = 4u;        // in a leaf link of the instance tree
+constexpr uint32_t kExitInst = 0xFFFFFFFEu;  // stack entry: leave the instance, back to world space
+constexpr uint32_t kNoMat = 0xFFFFFFFFu;     // instance keeps its triangles' own materials
 
 struct Queue {
   float4* orig;  // origin xyz, excluded triangle (BVH index) bits

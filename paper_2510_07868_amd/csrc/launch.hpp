@@ -85,7 +85,7 @@ void launch_accumulate_stats(const DepthCtl* ctl, uint32_t max_depth, unsigned l
                              unsigned long long* s_sum, unsigned long long* r_sum, double* sumq_last,
                              double* f_last, hipStream_t s);
 
-uint32_t extend_blocks_per_cu(uint32_t variant);
+uint32_t extend_blocks_per_cu(uint32_t variant, bool inst);  // inst: the two-level traversal
 uint32_t extend_threads_per_block();
 uint32_t extend_spill_depth();
 

@@ -149,21 +149,23 @@ __device__ __forceinline__ bool test_tri(const DevScene& sc, uint32_t k, V3 o, V
 
 // All triangles of a leaf for one ray: closest t wins, equal t goes to the smaller original
 // triangle index.
+// In an instance, uoff turns the triangle's index k into its primitive id k + uoff and its
+// stored index (k itself) into the tie-break key; outside instances uoff is 0.
 __device__ __forceinline__ void test_leaf(const DevScene& sc, uint32_t link, V3 o, V3 d, uint32_t excl,
-                                          HitState& h, uint32_t& tris) {
+                                          HitState& h, uint32_t& tris, uint32_t uoff = 0u) {
   const uint32_t first = (link >> 3) & 0x0fffffffu;
   const uint32_t count = (link & 7u) + 1u;
   tris += count;
   for (uint32_t k = first; k < first + count; ++k) {
-    if (k == excl) continue;
+    if (k + uoff == excl) continue;
     float t, b1, b2;
     uint32_t og;
-    if (test_tri(sc, k, o, d, h.t, t, b1, b2, og) && (t < h.t || (t == h.t && og < h.orig))) {
+    if (test_tri(sc, k, o, d, h.t, t, b1, b2, og) && (t < h.t || (t == h.t && og + uoff < h.orig))) {
       h.t = t;
       h.b1 = b1;
       h.b2 = b2;
-      h.prim = k;
-      h.orig = og;
+      h.prim = k + uoff;
+      h.orig = og + uoff;
     }
   }
 }
@@ -183,10 +185,11 @@ __device__ __forceinline__ unsigned long long hit_key(float t, uint32_t orig) {
 // closest hit is an LDS atomic minimum of hit keys; after each round the lane holding the
 // current minimum publishes triangle and barycentrics.  Same result as test_leaf on every owner.
 static_assert(kLeafMaxTris == 4, "the leaf phase deals four lanes to each parked leaf");
-template <bool kCount>
+template <bool kCount, bool kInst>
 __device__ __forceinline__ void leaf_phase_shared(const DevScene& sc, bool mine, uint32_t link, V3 o, V3 d,
                                                   uint32_t excl, HitState& h, uint32_t& tris,
-                                                  unsigned long long* key, float4* slot, uint8_t* owner) {
+                                                  unsigned long long* key, float4* slot, uint8_t* owner,
+                                                  uint32_t uoff) {
   const uint32_t lane = __lane_id();
   const uint64_t parked = __ballot(mine);
   const uint32_t n_parked = (uint32_t)__popcll(parked);
@@ -220,14 +223,15 @@ __device__ __forceinline__ void leaf_phase_shared(const DevScene& sc, bool mine,
     const V3 o_o = v3(__shfl(o.x, own), __shfl(o.y, own), __shfl(o.z, own));
     const V3 d_o = v3(__shfl(d.x, own), __shfl(d.y, own), __shfl(d.z, own));
     const float ht_o = __shfl(h.t, own);
+    const uint32_t uo = kInst ? (uint32_t)__shfl((int)uoff, own) : 0u;
     float t = 0.0f, b1 = 0.0f, b2 = 0.0f;
     uint32_t og = 0;
-    const bool hit = pair && k != ex_o && test_tri_data(sc, a0, a1, a2, o_o, d_o, ht_o, t, b1, b2, og);
-    const unsigned long long ck = hit ? hit_key(t, og) : ~0ull;
+    const bool hit = pair && k + uo != ex_o && test_tri_data(sc, a0, a1, a2, o_o, d_o, ht_o, t, b1, b2, og);
+    const unsigned long long ck = hit ? hit_key(t, og + uo) : ~0ull;
     if (hit) atomicMin(&key[own], ck);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    if (hit && key[own] == ck) slot[own] = make_float4(__uint_as_float(k), b1, b2, 0.0f);
+    if (hit && key[own] == ck) slot[own] = make_float4(__uint_as_float(k + uo), b1, b2, 0.0f);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
@@ -285,8 +289,16 @@ constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 //   kMode 4: as 3 over the 4-wide tree: a visit tests four child boxes, pushes the hit
 //     children farthest first and pops the nearest (a leaf is parked).  At most 3 entries
 //     per level stay on the stack, so the tree must be at most kMaxBvh4Depth levels deep.
-template <int kMode, bool kCount>
+// kInst (modes 0, 1, 3): a two-level scene.  The walk starts in the tree over instances; a
+// lane that reaches one of its leaves enters the leaf's first instance: it pushes the leaf's
+// other instances and a kExitInst mark, moves its ray into the instance's object space (the
+// direction is not renormalized, so distances t stay those of the world ray) and walks the
+// instance's own tree from its root.  Popping the mark restores the world ray.  Parked leaves
+// are tested with the lane's ray of the moment, which is the object-space ray of the leaf's
+// instance: a lane does not step while it holds a parked leaf.
+template <int kMode, bool kCount, bool kInst>
 __device__ __forceinline__ void extend_body(const RenderArgs& a) {
+  static_assert(!kInst || kMode == 0 || kMode == 1 || kMode == 3, "instances in modes 0, 1 and 3 only");
   __shared__ uint32_t stack_lds[kLdsStack][kTraceThreads];
   __shared__ unsigned long long cnt[3];  // rays traced, nodes visited, triangles tested
   __shared__ unsigned long long hit_keys[kMode >= 3 ? kTraceThreads : 1];
@@ -309,7 +321,47 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
   ClaimState cs = claim_start(n, blockIdx.x, kWorkSlices);
   V3 o = v3(0, 0, 0), d = o, inv = o, oi = o;
   float eps = 0.0f;
+  V3 wo = o, wd = o;   // the world ray while the lane walks an instance (kInst)
+  uint32_t uoff = 0u;  // primitive id offset of the instance being walked (kInst)
   HitState h;
+  // reciprocal direction, -o/d and the slab test's absolute widening of the lane's ray
+  auto prep_ray = [&]() {
+    const V3 dd = v3(fabsf(d.x) > 1e-20f ? d.x : copysignf(1e-20f, d.x),
+                     fabsf(d.y) > 1e-20f ? d.y : copysignf(1e-20f, d.y),
+                     fabsf(d.z) > 1e-20f ? d.z : copysignf(1e-20f, d.z));
+    inv = v3(1.0f / dd.x, 1.0f / dd.y, 1.0f / dd.z);
+    oi = v3(-o.x * inv.x, -o.y * inv.y, -o.z * inv.z);
+    // |oi| of axes the ray is not nearly parallel to (|d| >= 2^-10); see slab()
+    eps = fmaxf(fmaxf(fabsf(o.x) * fminf(fabsf(inv.x), 1024.0f), fabsf(o.y) * fminf(fabsf(inv.y), 1024.0f)),
+                fabsf(o.z) * fminf(fabsf(inv.z), 1024.0f)) *
+          0x1p-22f;
+  };
+  // a leaf of the lane's current tree holding triangles (not instances)
+  auto tri_leaf = [](uint32_t l) { return (l & kLeafBit) && (!kInst || !(l & kInstLeaf)); };
+  // enter the first instance of the instance leaf ni (kInst)
+  auto enter_instance = [&]() {
+    const uint32_t first = (ni >> 3) & 0x0fffffffu, cnt = (ni & 3u) + 1u;
+    if (cnt > 1u) st.push(kLeafBit | ((first + 1u) << 3) | kInstLeaf | (cnt - 2u));
+    st.push(kExitInst);
+    const float4* rec = sc.inst + 7ull * first;
+    const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2], info = rec[6];
+    wo = o;
+    wd = d;
+    const V3 oc = v3(wo.x - r0.w, wo.y - r1.w, wo.z - r2.w);  // origin minus the translation, first
+    o = v3(fmaf(r0.x, oc.x, fmaf(r0.y, oc.y, r0.z * oc.z)), fmaf(r1.x, oc.x, fmaf(r1.y, oc.y, r1.z * oc.z)),
+           fmaf(r2.x, oc.x, fmaf(r2.y, oc.y, r2.z * oc.z)));
+    d = v3(fmaf(r0.x, wd.x, fmaf(r0.y, wd.y, r0.z * wd.z)), fmaf(r1.x, wd.x, fmaf(r1.y, wd.y, r1.z * wd.z)),
+           fmaf(r2.x, wd.x, fmaf(r2.y, wd.y, r2.z * wd.z)));
+    prep_ray();
+    uoff = bits(info.y);
+    ni = bits(info.x);
+  };
+  auto leave_instance = [&]() {
+    o = wo;
+    d = wd;
+    prep_ray();
+    uoff = 0u;
+  };
   // statistics: rays and nodes counted per wave (wave-uniform, no per-lane registers);
   // triangles per wave in the shared leaf phase, per lane where a lane tests its own leaves
   uint32_t w_rays = 0, w_nodes = 0, w_tris = 0, c_tris = 0;
@@ -341,20 +393,13 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
             o = xyz(og);
             d = xyz(dr);
             excl = bits(og.w);
-            const V3 dd = v3(fabsf(d.x) > 1e-20f ? d.x : copysignf(1e-20f, d.x),
-                             fabsf(d.y) > 1e-20f ? d.y : copysignf(1e-20f, d.y),
-                             fabsf(d.z) > 1e-20f ? d.z : copysignf(1e-20f, d.z));
-            inv = v3(1.0f / dd.x, 1.0f / dd.y, 1.0f / dd.z);
-            oi = v3(-o.x * inv.x, -o.y * inv.y, -o.z * inv.z);
-            // |oi| of axes the ray is not nearly parallel to (|d| >= 2^-10); see slab()
-            eps = fmaxf(fmaxf(fabsf(o.x) * fminf(fabsf(inv.x), 1024.0f), fabsf(o.y) * fminf(fabsf(inv.y), 1024.0f)),
-                        fabsf(o.z) * fminf(fabsf(inv.z), 1024.0f)) *
-                  0x1p-22f;
+            prep_ray();
+            uoff = 0u;
             h.t = __builtin_inff();
             h.b1 = h.b2 = 0.0f;
             h.prim = kMiss;
             h.orig = kMiss;
-            ni = 0;
+            ni = kInst ? sc.root : 0u;
             pend = 0;
             st.sp = 0;
             ray = my;
@@ -371,18 +416,24 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
     if constexpr (kMode == 0) {
       if constexpr (kCount) w_nodes += (uint32_t)__popcll(__ballot(active));
       if (!active) continue;
+      if constexpr (kInst) {
+        if (ni & kLeafBit) {  // an instance leaf: one step to enter its first instance
+          enter_instance();
+          continue;
+        }
+      }
       // one node: test both child boxes, intersect leaf children, descend or pop
       const float4 n0 = sc.node[4 * ni], n1 = sc.node[4 * ni + 1], n2 = sc.node[4 * ni + 2], n3 = sc.node[4 * ni + 3];
       float tn0, tn1;
       bool h0 = slab(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, inv, oi, eps, h.t, tn0);
       bool h1 = slab(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, inv, oi, eps, h.t, tn1);
       const uint32_t l0 = bits(n3.x), l1 = bits(n3.y);
-      if (h0 && (l0 & kLeafBit)) {
-        test_leaf(sc, l0, o, d, excl, h, c_tris);
+      if (h0 && tri_leaf(l0)) {
+        test_leaf(sc, l0, o, d, excl, h, c_tris, uoff);
         h0 = false;
       }
-      if (h1 && (l1 & kLeafBit)) {
-        test_leaf(sc, l1, o, d, excl, h, c_tris);
+      if (h1 && tri_leaf(l1)) {
+        test_leaf(sc, l1, o, d, excl, h, c_tris, uoff);
         h1 = false;
       }
       if (h0 && h1) {
@@ -393,11 +444,21 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
         ni = l0;
       } else if (h1) {
         ni = l1;
-      } else if (st.sp > 0) {
-        ni = st.pop();
       } else {
-        a.hit[ray] = make_float4(h.t, h.b1, h.b2, __uint_as_float(h.prim));
-        active = false;
+        for (;;) {
+          if (st.sp == 0) {
+            a.hit[ray] = make_float4(h.t, h.b1, h.b2, __uint_as_float(h.prim));
+            active = false;
+            break;
+          }
+          const uint32_t e = st.pop();
+          if (kInst && e == kExitInst) {
+            leave_instance();
+            continue;
+          }
+          ni = e;
+          break;
+        }
       }
     } else {
       // Node phase: lanes without a parked leaf take one step each per round (visit a node, or
@@ -431,6 +492,8 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
               if (k0 != kInf) st.push(c0);
               ni = kNoNode;
             }
+          } else if (kInst && ni != kNoNode && pend == 0 && (ni & kLeafBit)) {
+            enter_instance();
           } else if (ni != kNoNode && (kMode == 2 || pend == 0)) {
             const float4 n0 = sc.node[4 * ni], n1 = sc.node[4 * ni + 1], n2 = sc.node[4 * ni + 2],
                          n3 = sc.node[4 * ni + 3];
@@ -439,16 +502,16 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
             const bool h1 = slab(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, inv, oi, eps, h.t, tn1);
             const uint32_t l0 = bits(n3.x), l1 = bits(n3.y);
             const bool first0 = tn0 <= tn1;
-            const bool f0 = h0 && (l0 & kLeafBit), f1 = h1 && (l1 & kLeafBit);
-            const bool i0 = h0 && !(l0 & kLeafBit), i1 = h1 && !(l1 & kLeafBit);
+            const bool f0 = h0 && tri_leaf(l0), f1 = h1 && tri_leaf(l1);
+            const bool i0 = h0 && !tri_leaf(l0), i1 = h1 && !tri_leaf(l1);
             // leaves: the nearer one is parked if the lane has none, the others wait on the
             // stack; a nearly full stack (possible only in mode 2) intersects them at once
             if (f0 || f1) {
               const uint32_t lnear = (f0 && (first0 || !f1)) ? l0 : l1;
               const uint32_t lfar = (f0 && f1) ? (first0 ? l1 : l0) : 0u;
               if (kMode == 2 && st.sp > kLeafPushLimit) {
-                if (lfar) test_leaf(sc, lfar, o, d, excl, h, c_tris);
-                test_leaf(sc, lnear, o, d, excl, h, c_tris);
+                if (lfar) test_leaf(sc, lfar, o, d, excl, h, c_tris, uoff);
+                test_leaf(sc, lnear, o, d, excl, h, c_tris, uoff);
               } else {
                 if (lfar) st.push(lfar);
                 if (pend == 0) pend = lnear;
@@ -465,7 +528,8 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
           if (ni == kNoNode && pend == 0) {
             if (st.sp > 0) {
               const uint32_t e = st.pop();
-              if (e & kLeafBit) pend = e;
+              if (kInst && e == kExitInst) leave_instance();
+              else if (tri_leaf(e)) pend = e;
               else ni = e;
             } else {
               a.hit[ray] = make_float4(h.t, h.b1, h.b2, __uint_as_float(h.prim));
@@ -488,11 +552,11 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
       if (parked != 0 && (seeking == 0 || __popcll(parked) >= leaf_batch)) {
         if constexpr (kMode >= 3) {
           const int wbase = tid & ~63;
-          leaf_phase_shared<kCount>(sc, active && pend != 0, pend, o, d, excl, h, w_tris, hit_keys + wbase,
-                            hit_slots + wbase, leaf_owner + wbase);
+          leaf_phase_shared<kCount, kInst>(sc, active && pend != 0, pend, o, d, excl, h, w_tris,
+                                           hit_keys + wbase, hit_slots + wbase, leaf_owner + wbase, uoff);
           if (active) pend = 0;
         } else if (active && pend != 0) {
-          test_leaf(sc, pend, o, d, excl, h, c_tris);
+          test_leaf(sc, pend, o, d, excl, h, c_tris, uoff);
           pend = 0;
         }
       }
@@ -515,10 +579,16 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
 // nodes visited and triangles tested are counted too (per-stage timing runs only).
 template <int kMode, bool kCount>
 __global__ __launch_bounds__(kTraceThreads) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_extend(RenderArgs a) {
-  extend_body<kMode, kCount>(a);
+  extend_body<kMode, kCount, false>(a);
 }
 template <bool kCount>
-__global__ __launch_bounds__(kTraceThreads) void k_extend_immediate(RenderArgs a) { extend_body<0, kCount>(a); }
+__global__ __launch_bounds__(kTraceThreads) void k_extend_immediate(RenderArgs a) { extend_body<0, kCount, false>(a); }
+// Two-level scenes: the world ray kept beside the object-space one needs more registers (105,
+// 4 waves per SIMD, no spills; at 96 registers the parked variants spilled).
+template <int kMode, bool kCount>
+__global__ __launch_bounds__(kTraceThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_extend_inst(RenderArgs a) {
+  extend_body<kMode, kCount, true>(a);
+}
 
 // ------------------------------------------------------------------------------- shade
 constexpr uint32_t kNoPix = 0xFFFFFFFFu;
@@ -581,6 +651,37 @@ __device__ __forceinline__ uint32_t block_alloc(uint32_t* counter, bool pred, ui
   return sh[kWaves] + sh[wave] + lanes_below(m);
 }
 
+// The world-space triangle of primitive id `prim` (v0, e1, e2 in a0..a2, material in a1.w): the
+// stored one, or for a triangle of an instance (two-level scenes, prim >= nt_base) its object-
+// space copy moved by the instance's transform (the instance's material, unless it keeps the
+// triangle's own).  Barycentrics are those of the object-space hit.
+__device__ __forceinline__ void world_tri(const DevScene& sc, uint32_t prim, float4& a0, float4& a1, float4& a2) {
+  if (sc.n_inst == 0u || prim < sc.nt_base) {
+    a0 = sc.tri[3 * prim];
+    a1 = sc.tri[3 * prim + 1];
+    a2 = sc.tri[3 * prim + 2];
+    return;
+  }
+  uint32_t lo = 0, hi = sc.n_inst - 1u;  // the last instance whose first uid is <= prim
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1u) >> 1;
+    if (sc.inst_uid[2 * mid] <= prim) lo = mid;
+    else hi = mid - 1u;
+  }
+  const float4* rec = sc.inst + 7ull * sc.inst_uid[2 * lo + 1];
+  const float4 f0 = rec[3], f1 = rec[4], f2 = rec[5], info = rec[6];
+  const uint32_t k = prim - bits(info.y);
+  const float4 b0 = sc.tri[3 * k], b1 = sc.tri[3 * k + 1], b2 = sc.tri[3 * k + 2];
+  const uint32_t mat = bits(info.z) != kNoMat ? bits(info.z) : bits(b1.w);
+  a0 = make_float4(fmaf(f0.x, b0.x, fmaf(f0.y, b0.y, fmaf(f0.z, b0.z, f0.w))),
+                   fmaf(f1.x, b0.x, fmaf(f1.y, b0.y, fmaf(f1.z, b0.z, f1.w))),
+                   fmaf(f2.x, b0.x, fmaf(f2.y, b0.y, fmaf(f2.z, b0.z, f2.w))), b0.w);
+  a1 = make_float4(fmaf(f0.x, b1.x, fmaf(f0.y, b1.y, f0.z * b1.z)), fmaf(f1.x, b1.x, fmaf(f1.y, b1.y, f1.z * b1.z)),
+                   fmaf(f2.x, b1.x, fmaf(f2.y, b1.y, f2.z * b1.z)), __uint_as_float(mat));
+  a2 = make_float4(fmaf(f0.x, b2.x, fmaf(f0.y, b2.y, f0.z * b2.z)), fmaf(f1.x, b2.x, fmaf(f1.y, b2.y, f1.z * b2.z)),
+                   fmaf(f2.x, b2.x, fmaf(f2.y, b2.y, f2.z * b2.z)), 0.0f);
+}
+
 // Next-event estimation at a vertex that may continue: one light (probability lum(L_e) x area
 // through the CDF), a point uniform on it, the BSDF's f cos toward it and the power-heuristic
 // weight against the BSDF's own sampling of that direction.  The shadow ray goes to the
@@ -602,8 +703,7 @@ __device__ __forceinline__ void nee_shadow_ray(const RenderArgs& a, uint32_t i, 
     if (a.sc.light_cdf[mid + 1] > u0) hi = mid;
     else lo = mid + 1;
   }
-  const uint32_t lt = a.sc.light_tri[lo];
-  const float4 l0 = a.sc.tri[3 * lt], l1 = a.sc.tri[3 * lt + 1], l2 = a.sc.tri[3 * lt + 2];
+  const float4 l0 = a.sc.light_geo[3 * lo], l1 = a.sc.light_geo[3 * lo + 1], l2 = a.sc.light_geo[3 * lo + 2];
   const V3 e1 = xyz(l1), e2 = xyz(l2);
   const V3 ngl = normalized(cross(e1, e2));
   const float su = sqrtf(u1);
@@ -632,9 +732,9 @@ __device__ __forceinline__ void nee_shadow_ray(const RenderArgs& a, uint32_t i, 
     fc = (cos_x * 0.31830988618379067f) * xyz(m0);
     pb = cos_x * 0.31830988618379067f;
   }
-  const float pl = a.sc.lpdf[lt] * dist * dist / cos_l;
-  const float w = pl * pl / (pl * pl + pb * pb);
   const float4 lm = a.sc.mat[2 * bits(l1.w) + 1];
+  const float pl = lum(xyz(lm)) * a.sc.light_scale * dist * dist / cos_l;
+  const float w = pl * pl / (pl * pl + pb * pb);
   const float k = w / pl;
   const V3 c = v3(t.x * fc.x * lm.x * k, t.y * fc.y * lm.y * k, t.z * fc.z * lm.z * k);
   a.qout.orig[i] = make_float4(o.x, o.y, o.z, __uint_as_float(prim));
@@ -714,7 +814,8 @@ __global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
       em = mul(t, v3(a.sc.env_r, a.sc.env_g, a.sc.env_b));
       emits = true;
     } else {
-      const float4 a0 = a.sc.tri[3 * prim], a1 = a.sc.tri[3 * prim + 1], a2 = a.sc.tri[3 * prim + 2];
+      float4 a0, a1, a2;
+      world_tri(a.sc, prim, a0, a1, a2);
       const V3 e1 = xyz(a1), e2 = xyz(a2);
       const uint32_t mid = bits(a1.w);
       const V3 ng = normalized(cross(e1, e2));
@@ -732,7 +833,7 @@ __global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
           // a BSDF-sampled hit on a light: power-heuristic weight against light sampling
           const float pb = a.qin.pdf[i];
           if (pb > 0.0f) {
-            const float pl = a.sc.lpdf[prim] * hh.x * hh.x / dot(ng, wo);
+            const float pl = lum(xyz(m1)) * a.sc.light_scale * hh.x * hh.x / dot(ng, wo);
             em = (pb * pb / (pb * pb + pl * pl)) * em;
           }
         }
@@ -1301,6 +1402,12 @@ void launch_camera(const RenderArgs& a, hipStream_t s) {
 template <bool kCount>
 void launch_extend_t(const RenderArgs& a, hipStream_t s) {
   const dim3 g(a.trace_blocks), b(kTraceThreads);
+  if (a.sc.n_inst) {  // two-level scene: modes 0, 1 and 3 (the tuning keeps to these)
+    if (a.ext_variant == 0) hipLaunchKernelGGL((k_extend_inst<0, kCount>), g, b, 0, s, a);
+    else if (a.ext_variant == 1) hipLaunchKernelGGL((k_extend_inst<1, kCount>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_extend_inst<3, kCount>), g, b, 0, s, a);
+    return;
+  }
   if (a.ext_variant == 4) hipLaunchKernelGGL((k_extend<4, kCount>), g, b, 0, s, a);
   else if (a.ext_variant == 3) hipLaunchKernelGGL((k_extend<3, kCount>), g, b, 0, s, a);
   else if (a.ext_variant == 2) hipLaunchKernelGGL((k_extend<2, kCount>), g, b, 0, s, a);
@@ -1311,10 +1418,13 @@ void launch_extend(const RenderArgs& a, hipStream_t s) {
   if (a.count_work) launch_extend_t<true>(a, s);
   else launch_extend_t<false>(a, s);
 }
-uint32_t extend_blocks_per_cu(uint32_t variant) {
+uint32_t extend_blocks_per_cu(uint32_t variant, bool inst) {
   int nb = 0;
   hipError_t e;
-  if (variant == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<4, false>, kTraceThreads, 0);
+  if (inst && variant == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend_inst<0, false>, kTraceThreads, 0);
+  else if (inst && variant == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend_inst<1, false>, kTraceThreads, 0);
+  else if (inst) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend_inst<3, false>, kTraceThreads, 0);
+  else if (variant == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<4, false>, kTraceThreads, 0);
   else if (variant == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<3, false>, kTraceThreads, 0);
   else if (variant == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<2, false>, kTraceThreads, 0);
   else if (variant == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_extend<1, false>, kTraceThreads, 0);

@@ -27,7 +27,8 @@ NSTAGES = 8
 STAGES = ["camera", "extend", "shade", "network", "sum_q", "roulette_scan", "expand", "pass_end"]
 
 EXPORTS = [
-    "nrrs_create", "nrrs_workspace_size", "nrrs_bind_workspace", "nrrs_upload_scene", "nrrs_render",
+    "nrrs_create", "nrrs_workspace_size", "nrrs_bind_workspace", "nrrs_upload_scene",
+    "nrrs_upload_scene_instanced", "nrrs_render",
     "nrrs_set_timing", "nrrs_set_launch_mode", "nrrs_set_precision", "nrrs_set_mix_depth", "nrrs_get_mix_depth",
     "nrrs_set_mix_depth_fixed", "nrrs_get_mix_depth_fixed",
     "nrrs_set_pass_index", "nrrs_get_pass_index", "nrrs_get_tuning", "nrrs_set_tuning", "nrrs_autotune",
@@ -83,6 +84,15 @@ class NrrsLoss(C.Structure):
     ]
 
 
+class Instances(C.Structure):
+    """nrrs_instances: object-space meshes and their instances."""
+    _fields_ = [
+        ("mesh_verts", C.c_void_p), ("mesh_nv", C.c_uint64), ("mesh_tris", C.c_void_p),
+        ("mesh_tri_mat", C.c_void_p), ("mesh_tri_begin", C.c_void_p), ("n_meshes", C.c_uint32),
+        ("inst_mesh", C.c_void_p), ("inst_xform", C.c_void_p), ("inst_mat", C.c_void_p), ("n_inst", C.c_uint32),
+    ]
+
+
 class RenderStats(C.Structure):
     _fields_ = [
         ("max_depth", C.c_uint32), ("passes", C.c_uint32),
@@ -121,6 +131,7 @@ def load():
         "nrrs_workspace_size": [P, U64, U32, P],
         "nrrs_bind_workspace": [P, P, U64, U64, U32],
         "nrrs_upload_scene": [P, P, U64, P, U64, P, P, P, U32, P, P],
+        "nrrs_upload_scene_instanced": [P, P, U64, P, U64, P, P, P, U32, P, P, P],
         "nrrs_render": [P, U32, U32, I32, P],
         "nrrs_set_timing": [P, I32],
         "nrrs_set_launch_mode": [P, I32],
@@ -243,6 +254,8 @@ class Renderer:
 
     # ---------------------------------------------------------------- API
     def upload_scene(self, scene):
+        if hasattr(scene, "inst_mesh"):
+            return self._upload_instanced(scene)
         v = _c(scene.verts, np.float32)
         t = _c(scene.tris, np.uint32)
         tm = _c(scene.tri_mat, np.uint32)
@@ -252,6 +265,25 @@ class Renderer:
         env = _c(scene.env, np.float32)
         self._check(self.L.nrrs_upload_scene(self.h, _p(v), v.shape[0], _p(t), t.shape[0], _p(tm), _p(mt), _p(mp),
                                              mt.shape[0], _p(cam), _p(env)))
+
+    def _upload_instanced(self, scene):
+        b = scene.base
+        v = _c(b.verts, np.float32).reshape(-1, 3)
+        t = _c(b.tris, np.uint32).reshape(-1, 3)
+        tm = _c(b.tri_mat, np.uint32)
+        mt = _c(b.mat_type, np.uint32)
+        mp = _c(b.mat_params, np.float32)
+        cam = _c(b.camera, np.float32)
+        env = _c(b.env, np.float32)
+        keep = [_c(scene.mesh_verts, np.float32).reshape(-1, 3), _c(scene.mesh_tris, np.uint32),
+                _c(scene.mesh_tri_mat, np.uint32), _c(scene.mesh_tri_begin, np.uint64),
+                _c(scene.inst_mesh, np.uint32), _c(scene.inst_xform, np.float32), _c(scene.inst_mat, np.uint32)]
+        mv, mtr, mtm, mb, im, ix, imat = keep
+        inst = Instances(_p(mv), mv.shape[0], _p(mtr), _p(mtm), _p(mb), mb.shape[0] - 1, _p(im), _p(ix), _p(imat),
+                         im.shape[0])
+        self._check(self.L.nrrs_upload_scene_instanced(
+            self.h, _p(v), v.shape[0], _p(t), t.shape[0], _p(tm), _p(mt), _p(mp), mt.shape[0], _p(cam), _p(env),
+            C.byref(inst)))
 
     def render(self, spp, max_depth, mode, stats=True):
         st = RenderStats()
