@@ -782,6 +782,9 @@ __global__ __launch_bounds__(kShadeThreads) void k_nee_resolve(RenderArgs a) {
 
 constexpr uint32_t kShadeStripes = 64;
 
+// kNee: next-event estimation on (a.nee); kInst: a two-level scene (a.sc.n_inst > 0).  The
+// variants keep the code of the options a context does not use out of the kernel.
+template <bool kNee, bool kInst>
 __global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
   __shared__ uint32_t alloc_sh[kShadeThreads / 64 + 1];
   const uint32_t n = a.ctl[a.depth].n;
@@ -815,7 +818,13 @@ __global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
       emits = true;
     } else {
       float4 a0, a1, a2;
-      world_tri(a.sc, prim, a0, a1, a2);
+      if constexpr (kInst) {
+        world_tri(a.sc, prim, a0, a1, a2);
+      } else {
+        a0 = a.sc.tri[3 * prim];
+        a1 = a.sc.tri[3 * prim + 1];
+        a2 = a.sc.tri[3 * prim + 2];
+      }
       const V3 e1 = xyz(a1), e2 = xyz(a2);
       const uint32_t mid = bits(a1.w);
       const V3 ng = normalized(cross(e1, e2));
@@ -829,7 +838,7 @@ __global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
       if (front && (m1.x != 0.0f || m1.y != 0.0f || m1.z != 0.0f)) {
         em = mul(t, xyz(m1));
         emits = true;
-        if (a.nee && a.depth > 1u) {
+        if (kNee && a.depth > 1u) {
           // a BSDF-sampled hit on a light: power-heuristic weight against light sampling
           const float pb = a.qin.pdf[i];
           if (pb > 0.0f) {
@@ -841,7 +850,7 @@ __global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
       if (a.depth < a.max_depth && type != 2u) {
         q = a.mode == 0u ? 1.0f : lum(mul(t, xyz(m0)));
         want_rec = a.records_on && (flags & kFlagTrain) && a.depth <= a.net_max_depth && a.depth <= (uint32_t)kMaxRec;
-        if (a.nee) {
+        if constexpr (kNee) {
           nee_shadow_ray(a, i, p, nrm, wo, t, m0, type, pix, prim);
           nee_written = true;
         }
@@ -851,7 +860,7 @@ __global__ __launch_bounds__(kShadeThreads) void k_shade(RenderArgs a) {
     }
   }
   // slots without a light sample carry a dead shadow ray (the traversal skips them)
-  if (a.nee && in_range && !nee_written) a.qout.thr[i] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(kFlagDead));
+  if (kNee && in_range && !nee_written) a.qout.thr[i] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(kFlagDead));
   if (in_range) a.q[i] = q;
   image_add_wave(a, in_range && !(flags & kFlagDead) ? pix : kNoPix, (double)em.x, (double)em.y, (double)em.z);
   if (emits && a.records_on) record_emission(a, em, rec);
@@ -1439,7 +1448,11 @@ void launch_record_features(const RenderArgs& a, uint64_t records_cap, hipStream
     hipLaunchKernelGGL(k_record_features, dim3(blocks_for(records_cap, kEntryThreads)), dim3(kEntryThreads), 0, s, a);
 }
 void launch_shade(const RenderArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_shade, dim3(blocks_for(a.cap, kShadeThreads)), dim3(kShadeThreads), 0, s, a);
+  const dim3 g(blocks_for(a.cap, kShadeThreads)), b(kShadeThreads);
+  if (a.nee && a.sc.n_inst) hipLaunchKernelGGL((k_shade<true, true>), g, b, 0, s, a);
+  else if (a.nee) hipLaunchKernelGGL((k_shade<true, false>), g, b, 0, s, a);
+  else if (a.sc.n_inst) hipLaunchKernelGGL((k_shade<false, true>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_shade<false, false>), g, b, 0, s, a);
 }
 
 void launch_nee(const RenderArgs& a, hipStream_t s) {
