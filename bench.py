@@ -83,6 +83,29 @@ def counted_sq():
     return out
 
 
+def counted_mfma():
+    """Matrix-core busy cycles, active cycles and vector instructions per dispatch from the
+    committed rocprofv3 summary of the network kernel, kept only while its source file is the one
+    the counters were taken on."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_rrsnet_mfma_heightfield512_mfma_counters.md")
+    out = {}
+    if not os.path.exists(path):
+        return out
+    for line in open(path):
+        if not line.startswith("mfma: "):
+            continue
+        _, kernel, busy, gui, valu, src, digest = line.split()
+        try:
+            now = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()[:16]
+        except OSError:
+            continue
+        if now == digest:
+            out[kernel] = (float(busy), float(gui), float(valu))
+    return out
+
+
 def relmse(img, ref):
     return float(np.mean((img - ref) ** 2 / (ref ** 2 + 0.01)))
 
@@ -253,11 +276,20 @@ def main():
                "bound": "alu" if args.precision == "fp32" else "mfma", "achieved": round(net_flop / (net_ms * 1e-3) / 1e12, 2),
                "peak": peak, "unit": "TFLOP/s", "frac": round(net_flop / (net_ms * 1e-3) / 1e12 / peak, 4),
                "avg_launch_ms": round(net_ms, 4), "rows_per_launch": int(net_rows / max(stage_n["network"], 1))}
+    # matrix-core busy share and vector-issue share of the kernel's cycles (committed counters:
+    # busy cycles summed over the 1024 SIMDs, active cycles summed over the 8 XCDs)
+    mc = counted_mfma().get({"bf16": "k_rrsnet_mfma<1>", "fp8": "k_rrsnet_mfma<2>"}.get(args.precision, ""))
+    if mc:
+        busy, gui, valu = mc
+        network["mfma_busy_share"] = round(busy / (gui / 8.0 * 1024.0), 3)
+        network["valu_issue_share"] = round(valu * 4.0 / (gui / 8.0 * 1024.0), 3)
+    else:
+        network["mfma_busy_share"] = network["valu_issue_share"] = None
 
     # queue stages: counted HBM bytes per launch (rocprofv3, committed summary) over the live
     # per-launch stage time
     queue = {}
-    for stage, kern in (("camera", "k_camera"), ("shade", "k_shade"), ("expand", "k_expand")):
+    for stage, kern in (("camera", "k_camera"), ("shade", "k_shade<false,false>"), ("expand", "k_expand")):
         ms = stage_ms[stage] / max(stage_n[stage], 1)
         b = traffic.get(kern)
         queue[kern] = {"avg_launch_ms": round(ms, 4), "hbm_bytes_per_launch": b,
