@@ -80,6 +80,68 @@ __device__ __forceinline__ void mlp32(const float* P, const float (&x)[IN], floa
   }
 }
 
+// Inference copies of the weights in LDS keep each hidden layer input-major, Wt[i][o]: the 32
+// weights of one input are contiguous, so a layer runs input by input with 32 accumulators and
+// only the weights of the next few inputs in flight.  Each output is still b + sum over inputs
+// in ascending order, FMA by FMA: the same values as hidden().
+template <int K>
+__device__ __forceinline__ void hidden_t(const float* __restrict__ Wt, const float* __restrict__ b,
+                                         const float (&x)[K], float (&y)[32]) {
+  float acc[32];
+#pragma unroll
+  for (int o = 0; o < 32; ++o) acc[o] = b[o];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+#pragma unroll
+    for (int o = 0; o < 32; ++o) acc[o] = fmaf(Wt[i * 32 + o], x[i], acc[o]);
+    // no weight reads hoisted past the next input: they would each hold a register
+    asm volatile("" ::: "memory");
+  }
+#pragma unroll
+  for (int o = 0; o < 32; ++o) y[o] = leaky(acc[o]);
+}
+
+// Inference through in -> 32 -> 32 -> 32 -> out with input-major hidden weights (the layout
+// load_lds_t writes); the activations are not kept.
+template <int IN, int OUT>
+__device__ __forceinline__ void mlp32_t(const float* P, const float (&x)[IN], float (&y)[OUT]) {
+  using Lo = L32<IN, OUT>;
+  float ha[32], hb[32];
+  hidden_t<IN>(P + Lo::W1, P + Lo::B1, x, ha);
+  asm volatile("" ::: "memory");
+  hidden_t<32>(P + Lo::W2, P + Lo::B2, ha, hb);
+  asm volatile("" ::: "memory");
+  hidden_t<32>(P + Lo::W3, P + Lo::B3, hb, ha);
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int k = 0; k < OUT; ++k) {
+    float acc = P[Lo::B4 + k];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) acc = fmaf(P[Lo::W4 + 32 * k + i], ha[i], acc);
+    y[k] = acc;
+  }
+}
+
+// The parameters of an in -> 32 -> 32 -> 32 -> out network into LDS with the three hidden
+// weight matrices input-major (biases and output weights as stored).
+template <int IN, int OUT>
+__device__ __forceinline__ void load_lds_t(float* dst, const float* src) {
+  using Lo = L32<IN, OUT>;
+  for (int k = threadIdx.x; k < Lo::N; k += blockDim.x) {
+    int at = k;
+    if (k < Lo::B1) {
+      at = (k % IN) * 32 + k / IN;  // W1[o][i] -> [i][o]
+    } else if (k >= Lo::W2 && k < Lo::B2) {
+      const int j = k - Lo::W2;
+      at = Lo::W2 + (j % 32) * 32 + j / 32;
+    } else if (k >= Lo::W3 && k < Lo::B3) {
+      const int j = k - Lo::W3;
+      at = Lo::W3 + (j % 32) * 32 + j / 32;
+    }
+    dst[at] = src[k];
+  }
+}
+
 // ------------------------------------------------------------------ encodings
 // Hash grid (Sec. 5 "Input Encoding"): level l has resolution R = 16 * 2^l; p lies in cell
 // c = min(floor(p R), R - 1) per axis and reads the trilinear interpolation of its 8 corners.
@@ -106,11 +168,12 @@ __device__ __forceinline__ void hg_corners(float px, float py, float pz, int l, 
   const uint64_t side = (uint64_t)R + 1;
   const bool dense = side * side * side <= (1ull << log2T);
   const uint32_t mask = (1u << log2T) - 1u;
+  const uint32_t side32 = R + 1u;  // a dense level's corner index fits 32 bits (below 2^log2T)
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const uint32_t dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
     const uint32_t x = ci[0] + dx, y = ci[1] + dy, z = ci[2] + dz;
-    c.idx[k] = dense ? (uint32_t)(x + side * (y + side * z)) : ((x * 1u) ^ (y * 2654435761u) ^ (z * 805459861u)) & mask;
+    c.idx[k] = dense ? x + side32 * (y + side32 * z) : ((x * 1u) ^ (y * 2654435761u) ^ (z * 805459861u)) & mask;
     c.w[k] = (dx ? f[0] : 1.0f - f[0]) * (dy ? f[1] : 1.0f - f[1]) * (dz ? f[2] : 1.0f - f[2]);
   }
 }
@@ -141,6 +204,8 @@ __device__ __forceinline__ void statnet_encode(const float* __restrict__ table, 
     }
     enc[2 * l] = e0;
     enc[2 * l + 1] = e1;
+    // at most two levels' 16 corner loads in flight: all 64 at once held 128 registers
+    if (l & 1) asm volatile("" ::: "memory");
   }
   const float theta = acosf(fminf(fmaxf(raw[5], -1.0f), 1.0f));
   const float phi = atan2f(raw[4], raw[3]);
@@ -171,6 +236,7 @@ __device__ __forceinline__ void aid_encode(const float* __restrict__ table, uint
     }
     enc[2 * l] = e0;
     enc[2 * l + 1] = e1;
+    if (l & 1) asm volatile("" ::: "memory");  // as in statnet_encode
   }
   const float theta = acosf(fminf(fmaxf(raw[5], -1.0f), 1.0f));
   const float phi = atan2f(raw[4], raw[3]);
@@ -239,15 +305,19 @@ __device__ __forceinline__ void load_lds(float* dst, const float* src, uint32_t 
 // Weights in LDS, read by all lanes at once.  (Scalar loads of the weights from global memory,
 // with the weights as the FMAs' scalar operand, measured 1.9x slower: 22.5 KB of weights per
 // vertex batch stream through the 16 KB scalar cache.)
-template <bool kAid>
-__global__ __launch_bounds__(kT) void k_nrrs_factor(RenderArgs a, NrrsNet net) {
+// At most 128 VGPRs (4 waves per SIMD) to hide the hash-grid gathers; the input-major layers
+// and a table size known at compile time fit that without spilling.
+template <bool kAid, uint32_t kLog2T>
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_nrrs_factor(RenderArgs a,
+                                                                                                NrrsNet net) {
+  constexpr uint32_t log2T = kLog2T;  // equal to net.log2T (the launch picks the build)
   __shared__ float ps[kAid ? kAidParams : kStatParams];
   __shared__ float pr[kAid ? 1 : kRrsParams];
   if constexpr (kAid) {
-    load_lds(ps, net.aid, kAidParams);
+    load_lds_t<kAidIn, 1>(ps, net.aid);
   } else {
-    load_lds(ps, net.stat, kStatParams);
-    load_lds(pr, net.rrs, kRrsParams);
+    load_lds_t<kStatIn, kStatOut>(ps, net.stat);
+    load_lds_t<kRrsIn, 1>(pr, net.rrs);
   }
   __syncthreads();
   const uint32_t n = a.ctl[a.depth].n;
@@ -266,13 +336,17 @@ __global__ __launch_bounds__(kT) void k_nrrs_factor(RenderArgs a, NrrsNet net) {
     vertex_raw(a.sc, vp, dr, m0, __float_as_uint(m1.w), raw);
     float q;
     if constexpr (kAid) {
-      float enc[32], h1[32], h2[32], h3[32], z[1];
-      aid_encode(net.table_r, net.log2T, raw, th.x, th.y, th.z, g, enc);
-      mlp32<kAidIn, 1>(ps, enc, h1, h2, h3, z);
+      float enc[32], z[1];
+      aid_encode(net.table_r, log2T, raw, th.x, th.y, th.z, g, enc);
+      mlp32_t<kAidIn, 1>(ps, enc, z);
       q = softplus_mod(z[0]);
     } else {
-      float m, v;
-      q = softplus_mod(nrrs_z(ps, pr, net.table, net.log2T, raw, th.x, th.y, th.z, g, m, v));
+      float enc[32], mv[2], x[7], z[1];
+      statnet_encode(net.table, log2T, raw, enc);
+      mlp32_t<kStatIn, kStatOut>(ps, enc, mv);
+      rrs_inputs(mv[0], mv[1], th.x, th.y, th.z, g, raw[6], x);
+      mlp32_t<kRrsIn, 1>(pr, x, z);
+      q = softplus_mod(z[0]);
     }
     a.q[i] = (q >= 1e-20f && q < 3.0e38f) ? q : q0;
   }
@@ -812,11 +886,28 @@ inline uint32_t blocks_of(uint64_t n, uint32_t t) { return (uint32_t)((n + t - 1
 
 }  // namespace
 
+template <uint32_t L>
+void launch_factor_t(const RenderArgs& a, const NrrsNet& n, dim3 g, bool aid, hipStream_t s) {
+  if (aid) hipLaunchKernelGGL((k_nrrs_factor<true, L>), g, dim3(kT), 0, s, a, n);
+  else hipLaunchKernelGGL((k_nrrs_factor<false, L>), g, dim3(kT), 0, s, a, n);
+}
+
 void launch_nrrs_factor(const RenderArgs& a, const NrrsNet& n, uint32_t blocks, bool aid, hipStream_t s) {
-  if (aid)
-    hipLaunchKernelGGL(k_nrrs_factor<true>, dim3(std::max(blocks, 1u)), dim3(kT), 0, s, a, n);
-  else
-    hipLaunchKernelGGL(k_nrrs_factor<false>, dim3(std::max(blocks, 1u)), dim3(kT), 0, s, a, n);
+  // one build per table size (2^14 .. 2^22 entries per level, the sizes a context accepts):
+  // with the level layout known, the dense / hashed choice and the level offsets are constants
+  // and the kernel fits 4 waves per SIMD without spilling
+  const dim3 g(std::max(blocks, 1u));
+  switch (n.log2T) {
+    case 14: launch_factor_t<14>(a, n, g, aid, s); break;
+    case 15: launch_factor_t<15>(a, n, g, aid, s); break;
+    case 16: launch_factor_t<16>(a, n, g, aid, s); break;
+    case 17: launch_factor_t<17>(a, n, g, aid, s); break;
+    case 18: launch_factor_t<18>(a, n, g, aid, s); break;
+    case 19: launch_factor_t<19>(a, n, g, aid, s); break;
+    case 20: launch_factor_t<20>(a, n, g, aid, s); break;
+    case 21: launch_factor_t<21>(a, n, g, aid, s); break;
+    default: launch_factor_t<22>(a, n, g, aid, s); break;
+  }
 }
 
 void launch_aid_rows(const float* raw, const float* t, const float* I, uint32_t n, const NrrsNet& net, float* q,

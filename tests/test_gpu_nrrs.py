@@ -189,7 +189,8 @@ def _he(rng, n_in, n_out):
     return np.concatenate(p).astype(np.float32)
 
 
-def test_nrrs_cornell_paths_match_oracle(O, nrrs_mod, scenes):
+@pytest.mark.parametrize("log2t", [LOG2T, 19])  # (19: the benchmark's table size)
+def test_nrrs_cornell_paths_match_oracle(O, nrrs_mod, scenes, log2t):
     # every primary path of a 64x64, 4-spp Cornell pass in NRRS mode (StatNet + RRSNet factors at
     # depths 1-4) against the oracle on the same random numbers, at 1e-4 relative, up to the depth
     # of its first near-tie decision (the oracle widens the roulette's near-tie margin by the
@@ -199,12 +200,12 @@ def test_nrrs_cornell_paths_match_oracle(O, nrrs_mod, scenes):
     D = 8
     sc = scenes.cornell()
     r = nrrs_mod.Renderer(W, H, s_batch=4, max_tris=max(sc.n_tris, 64), max_materials=max(len(sc.mat_type), 4),
-                          trace_depth=D, hash_log2=LOG2T)
+                          trace_depth=D, hash_log2=log2t)
     r.upload_scene(sc)
     rng = np.random.default_rng(21)
     Ps, Pr = _he(rng, 32, 2), _he(rng, 7, 1)
     Pr[-1] = 2.0 * (1.0 - np.log(2.0))  # factors around 1
-    T = rng.uniform(-0.3, 0.3, size=8 * 2 * (1 << LOG2T)).astype(np.float32)
+    T = rng.uniform(-0.3, 0.3, size=8 * 2 * (1 << log2t)).astype(np.float32)
     guide = rng.uniform(0.02, 2.0, size=W * H).astype(np.float32)
     r.set_nrrs_params(Ps, Pr, T)
     r.set_guide(guide)
@@ -213,7 +214,7 @@ def test_nrrs_cornell_paths_match_oracle(O, nrrs_mod, scenes):
     gp = r.read_trace()
     img, _ = r.read_image()
     params = np.concatenate([Ps, Pr, T]).astype(np.float64)
-    o = O.render(O.OracleScene(sc), O.make_cfg(W, H, 4, D, n_passes=1, mode=O.MODE_NRRS, tau=1e-4, hash_log2=LOG2T),
+    o = O.render(O.OracleScene(sc), O.make_cfg(W, H, 4, D, n_passes=1, mode=O.MODE_NRRS, tau=1e-4, hash_log2=log2t),
                  paths=True, params=params, guide=guide.astype(np.float64))
     bad, some, full, covered = _compare_paths(gp, o, D)
     _report_paths("cornell NRRS", gp, o, D, bad, some, full, covered)
@@ -284,19 +285,20 @@ def test_aid_gradients_match_oracle(N, nrrs_mod, scenes, step):
     r.close()
 
 
-def test_aid_cornell_paths_match_oracle(O, nrrs_mod, scenes):
+@pytest.mark.parametrize("log2t", [LOG2T, 19])
+def test_aid_cornell_paths_match_oracle(O, nrrs_mod, scenes, log2t):
     # the AID-NRRS factor in a 64x64, 4-spp Cornell pass, path by path against the oracle
     from test_gpu_parity import _compare_paths, _report_paths
     W = H = 64
     D = 8
     sc = scenes.cornell()
     r = nrrs_mod.Renderer(W, H, s_batch=4, max_tris=max(sc.n_tris, 64), max_materials=max(len(sc.mat_type), 4),
-                          trace_depth=D, hash_log2=LOG2T)
+                          trace_depth=D, hash_log2=log2t)
     r.upload_scene(sc)
     rng = np.random.default_rng(41)
     Pa = _he(rng, 32, 1)
     Pa[-1] = 2.0 * (1.0 - np.log(2.0))
-    Tr = rng.uniform(-0.3, 0.3, size=8 * 2 * (1 << LOG2T)).astype(np.float32)
+    Tr = rng.uniform(-0.3, 0.3, size=8 * 2 * (1 << log2t)).astype(np.float32)
     guide = rng.uniform(0.02, 2.0, size=W * H).astype(np.float32)
     r.set_aid_params(Pa, Tr)
     r.set_guide(guide)
@@ -304,7 +306,7 @@ def test_aid_cornell_paths_match_oracle(O, nrrs_mod, scenes):
     st = r.render(4, D, nrrs_mod.MODE_AID)
     gp = r.read_trace()
     params = np.concatenate([Pa, Tr]).astype(np.float64)
-    o = O.render(O.OracleScene(sc), O.make_cfg(W, H, 4, D, n_passes=1, mode=O.MODE_AID, tau=1e-4, hash_log2=LOG2T),
+    o = O.render(O.OracleScene(sc), O.make_cfg(W, H, 4, D, n_passes=1, mode=O.MODE_AID, tau=1e-4, hash_log2=log2t),
                  paths=True, params=params, guide=guide.astype(np.float64))
     bad, some, full, covered = _compare_paths(gp, o, D)
     _report_paths("cornell AID-NRRS", gp, o, D, bad, some, full, covered)
