@@ -20,7 +20,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-at
 
 
 # matrix-core kernels: MFMA accumulators in VGPRs (no copies out of AGPRs for the epilogues)
-PER_FILE = {"mlp_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+PER_FILE = {"mlp_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"], "nrrs_net.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _compile(src: str) -> str:

@@ -1111,9 +1111,9 @@ int32_t nrrs_render(nrrs_ctx* c, uint32_t spp, uint32_t max_depth, int32_t mode,
   a.records_on = (mode != NRRS_MODE_OFF && c->cfg.records_cap > 0 && c->cfg.p_train > 0.0) ? 1u : 0u;
   const NetArgs net = net_args(c, c->cfg.precision);
   const NrrsNet nnet = c->cfg.hash_log2 ? nrrs_net_args(c, true) : NrrsNet{};
-  // persistent grid of the NRRS factor kernel: 4 blocks of 4 waves per CU, the 4 waves per SIMD
-  // its registers allow (22.5 KB of weights in LDS per block)
-  const uint32_t nrrs_blocks = c->cus * 4;
+  // persistent grid of the NRRS factor kernel: 5 blocks of 4 waves per CU, the 5 waves per SIMD
+  // its registers allow (at most 22.7 KB of weights in LDS per block)
+  const uint32_t nrrs_blocks = c->cus * 5;
   if (a.records_on) launch_zero_u32(a.rec.count, 1, s);
   launch_zero_u32((uint32_t*)c->st_n, 2 * (NRRS_MAX_DEPTH + 1), s);
   launch_zero_u32((uint32_t*)c->st_s, 2 * (NRRS_MAX_DEPTH + 1), s);

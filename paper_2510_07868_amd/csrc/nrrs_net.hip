@@ -11,8 +11,10 @@
 // one-sample transfer of Eqs. (17)-(18), shared by the pixel's samples, plus the bound loss of
 // Eq. (21).  The per-pixel error uses the temporal mix of Eq. (23) and a box filter.
 //
-// Layout: one thread per vertex or record; weights in LDS (read by all lanes at once); the
-// hash grid in HBM ([level][2^log2T][2] floats, gathered per corner).  Weight gradients are
+// Layout: inference evaluates 64 vertices per wave, each lane encoding its own vertex, with the
+// networks' layers on the FP32 matrix cores; training runs one thread per record with the
+// weights in LDS (read by all lanes at once); the hash grid lives in HBM ([level][2^log2T][2]
+// floats, gathered per corner).  Weight gradients are
 // reduced per block through LDS tiles of the per-record activations and deltas in a fixed
 // order, then over blocks in block order; hash-grid gradients are added atomically.
 #include <algorithm>
@@ -80,65 +82,124 @@ __device__ __forceinline__ void mlp32(const float* P, const float (&x)[IN], floa
   }
 }
 
-// Inference copies of the weights in LDS keep each hidden layer input-major, Wt[i][o]: the 32
-// weights of one input are contiguous, so a layer runs input by input with 32 accumulators and
-// only the weights of the next few inputs in flight.  Each output is still b + sum over inputs
-// in ascending order, FMA by FMA: the same values as hidden().
-template <int K>
-__device__ __forceinline__ void hidden_t(const float* __restrict__ Wt, const float* __restrict__ b,
-                                         const float (&x)[K], float (&y)[32]) {
-  float acc[32];
-#pragma unroll
-  for (int o = 0; o < 32; ++o) acc[o] = b[o];
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-#pragma unroll
-    for (int o = 0; o < 32; ++o) acc[o] = fmaf(Wt[i * 32 + o], x[i], acc[o]);
-    // no weight reads hoisted past the next input: they would each hold a register
-    asm volatile("" ::: "memory");
-  }
-#pragma unroll
-  for (int o = 0; o < 32; ++o) y[o] = leaky(acc[o]);
-}
+// ------------------------------------------------------------------ matrix-core inference
+// A wave evaluates 64 vertices, one per lane, as two tiles of 32 on the FP32 matrix cores
+// (v_mfma_f32_32x32x2_f32): M = the 32 units of a layer, N = a tile's 32 vertices, K = the
+// layer's inputs two at a time.  Lane l computes the inputs of vertex l (tile l / 32, column
+// l % 32) and, as an MFMA operand, serves column c = l % 32 of both tiles in lane half h = l / 32:
+// A[m = c][k = h] (weights) and B[k = h][n = c] (inputs).  Register v of an accumulator holds
+// unit 8 (v / 4) + 4 h + v % 4 of column c, so a layer's leaky-ReLU outputs are the next layer's
+// B operands unchanged when that layer's weights are taken in the same unit order.  The first
+// layer's inputs of a tile's column come from the two lanes of that column: one exchange across
+// the lane halves per input pair.  The weights sit in LDS in operand order (each lane reads its
+// own contiguous run).  FP32 products and FP32 accumulation, as the vector path; only the order
+// of the additions differs.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// Inference through in -> 32 -> 32 -> 32 -> out with input-major hidden weights (the layout
-// load_lds_t writes); the activations are not kept.
-template <int IN, int OUT>
-__device__ __forceinline__ void mlp32_t(const float* P, const float (&x)[IN], float (&y)[OUT]) {
-  using Lo = L32<IN, OUT>;
-  float ha[32], hb[32];
-  hidden_t<IN>(P + Lo::W1, P + Lo::B1, x, ha);
-  asm volatile("" ::: "memory");
-  hidden_t<32>(P + Lo::W2, P + Lo::B2, ha, hb);
-  asm volatile("" ::: "memory");
-  hidden_t<32>(P + Lo::W3, P + Lo::B3, hb, ha);
-  asm volatile("" ::: "memory");
-#pragma unroll
-  for (int k = 0; k < OUT; ++k) {
-    float acc = P[Lo::B4 + k];
-#pragma unroll
-    for (int i = 0; i < 32; ++i) acc = fmaf(P[Lo::W4 + 32 * k + i], ha[i], acc);
-    y[k] = acc;
-  }
-}
+__device__ __forceinline__ int acc_unit(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
 
-// The parameters of an in -> 32 -> 32 -> 32 -> out network into LDS with the three hidden
-// weight matrices input-major (biases and output weights as stored).
+// LDS image of an in -> 32 -> 32 -> 32 -> out network in operand order (floats):
+//   W1 [h][c][S]: W1[c][2s + h] (0 past the inputs), S = ceil(in / 2) input pairs
+//   W2, W3 [h][c][16]: W[c][acc_unit(s, h)];  B1, B2, B3 [h][16]: b[acc_unit(v, h)]
+//   W4 [o][h][16]: W4[o][acc_unit(v, h)];  B4 [o]
 template <int IN, int OUT>
-__device__ __forceinline__ void load_lds_t(float* dst, const float* src) {
+struct Img {
+  static constexpr int S = (IN + 1) / 2;
+  static constexpr int W1 = 0, W2 = W1 + 64 * S, W3 = W2 + 1024, B1 = W3 + 1024, B2 = B1 + 32, B3 = B2 + 32,
+                       W4 = B3 + 32, B4 = W4 + 32 * OUT, N = B4 + OUT;
+};
+
+template <int IN, int OUT>
+__device__ __forceinline__ void load_img(float* dst, const float* P) {
   using Lo = L32<IN, OUT>;
-  for (int k = threadIdx.x; k < Lo::N; k += blockDim.x) {
-    int at = k;
-    if (k < Lo::B1) {
-      at = (k % IN) * 32 + k / IN;  // W1[o][i] -> [i][o]
-    } else if (k >= Lo::W2 && k < Lo::B2) {
-      const int j = k - Lo::W2;
-      at = Lo::W2 + (j % 32) * 32 + j / 32;
-    } else if (k >= Lo::W3 && k < Lo::B3) {
-      const int j = k - Lo::W3;
-      at = Lo::W3 + (j % 32) * 32 + j / 32;
+  using Im = Img<IN, OUT>;
+  for (int d = threadIdx.x; d < Im::N; d += blockDim.x) {
+    float v = 0.0f;
+    if (d < Im::W2) {
+      const int s = d % Im::S, c = (d / Im::S) % 32, h = d / (Im::S * 32), k = 2 * s + h;
+      if (k < IN) v = P[Lo::W1 + c * IN + k];
+    } else if (d < Im::B1) {
+      const bool second = d < Im::W3;
+      const int j = d - (second ? Im::W2 : Im::W3);
+      const int s = j % 16, c = (j / 16) % 32, h = j / 512;
+      v = P[(second ? Lo::W2 : Lo::W3) + c * 32 + acc_unit(s, h)];
+    } else if (d < Im::W4) {
+      const int L = (d - Im::B1) / 32, j = (d - Im::B1) % 32;
+      v = P[(L == 0 ? Lo::B1 : L == 1 ? Lo::B2 : Lo::B3) + acc_unit(j % 16, j / 16)];
+    } else if (d < Im::B4) {
+      const int j = d - Im::W4, o = j / 32, h = (j / 16) % 2;
+      v = P[Lo::W4 + o * 32 + acc_unit(j % 16, h)];
+    } else {
+      v = P[Lo::B4 + (d - Im::B4)];
     }
-    dst[at] = src[k];
+    dst[d] = v;
+  }
+}
+
+__device__ __forceinline__ f32x16 mfma_f32(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// The network on the wave's 64 vertices: x = this lane's vertex's inputs; returns the outputs
+// of this lane's vertex.  All 64 lanes must call it together (inactive lanes with finite
+// inputs, e.g. zeros).
+template <int IN, int OUT>
+__device__ __forceinline__ void mlp_mfma(const float* I, const float (&x)[IN], float (&y)[OUT]) {
+  using Im = Img<IN, OUT>;
+  const int l = (int)__lane_id(), h = l >> 5, c = l & 31;
+  f32x16 a0, a1;
+  // layer 1: the pair (2s, 2s + 1) of tile 0 is (own, partner's) in half 0 and (partner's, own)
+  // in half 1; the lane sends the value its partner lacks
+  {
+    const float* w = I + Im::W1 + (h * 32 + c) * Im::S;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) a0[v] = a1[v] = I[Im::B1 + h * 16 + v];
+#pragma unroll
+    for (int s = 0; s < Im::S; ++s) {
+      const float lo = x[2 * s], hi = 2 * s + 1 < IN ? x[2 * s + 1] : 0.0f;
+      const float recv = __shfl_xor(h ? lo : hi, 32);
+      const float wk = w[s];
+      a0 = mfma_f32(wk, h ? recv : lo, a0);  // tile 0: vertex c's input 2s + h
+      a1 = mfma_f32(wk, h ? hi : recv, a1);  // tile 1: vertex 32 + c's input 2s + h
+    }
+  }
+  float h0[16], h1[16];
+#pragma unroll
+  for (int L = 0; L < 2; ++L) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      h0[v] = leaky(a0[v]);
+      h1[v] = leaky(a1[v]);
+    }
+    asm volatile("" ::: "memory");
+    const float* w = I + (L == 0 ? Im::W2 : Im::W3) + (h * 32 + c) * 16;
+    const float* b = I + (L == 0 ? Im::B2 : Im::B3) + h * 16;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) a0[v] = a1[v] = b[v];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const float wk = w[s];
+      a0 = mfma_f32(wk, h0[s], a0);
+      a1 = mfma_f32(wk, h1[s], a1);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    h0[v] = leaky(a0[v]);
+    h1[v] = leaky(a1[v]);
+  }
+#pragma unroll
+  for (int o = 0; o < OUT; ++o) {
+    const float* w = I + Im::W4 + (o * 2 + h) * 16;
+    float p0 = 0.0f, p1 = 0.0f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      p0 = fmaf(w[v], h0[v], p0);
+      p1 = fmaf(w[v], h1[v], p1);
+    }
+    p0 += __shfl_xor(p0, 32);
+    p1 += __shfl_xor(p1, 32);
+    y[o] = (h ? p1 : p0) + I[Im::B4 + o];
   }
 }
 
@@ -280,98 +341,113 @@ __device__ __forceinline__ void vertex_raw(const DevScene& sc, float4 vp, float4
   raw[6] = 1.0f - expf(-(type == 1u ? m0.w : 1.0f));
 }
 
-// StatNet then RRSNet for one vertex: (m, v) and the pre-activation z of the factor.
-__device__ __forceinline__ float nrrs_z(const float* ps, const float* pr, const float* table, uint32_t log2T,
-                                        const float (&raw)[7], float tx, float ty, float tz, float I, float& m,
-                                        float& v) {
-  float enc[32], h1[32], h2[32], h3[32], mv[2];
-  statnet_encode(table, log2T, raw, enc);
-  mlp32<kStatIn, kStatOut>(ps, enc, h1, h2, h3, mv);
-  m = mv[0];
-  v = mv[1];
-  float x[7], z[1];
-  rrs_inputs(m, v, tx, ty, tz, I, raw[6], x);
-  mlp32<kRrsIn, 1>(pr, x, h1, h2, h3, z);
-  return z[0];
-}
-
 __device__ __forceinline__ void load_lds(float* dst, const float* src, uint32_t n) {
   for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
 }
 
 // ------------------------------------------------------------------ inference
 // The NRRS factor of every vertex of the depth that has a raw factor and a pixel history; a
-// non-finite (or underflowed) factor keeps the heuristic one.  Persistent grid.
-// Weights in LDS, read by all lanes at once.  (Scalar loads of the weights from global memory,
-// with the weights as the FMAs' scalar operand, measured 1.9x slower: 22.5 KB of weights per
-// vertex batch stream through the 16 KB scalar cache.)
-// At most 128 VGPRs (4 waves per SIMD) to hide the hash-grid gathers; the input-major layers
-// and a table size known at compile time fit that without spilling.
+// non-finite (or underflowed) factor keeps the heuristic one.  Persistent waves over groups of
+// 64 vertices: each lane encodes its vertex (hash-grid gathers, one-blob, Box-Cox), then the
+// wave runs the networks on the matrix cores (mlp_mfma), weights in LDS in operand order.  At
+// most 96 VGPRs (5 waves per SIMD) to hide the gathers; a build per table size keeps the
+// encodings' level layout constant, which that budget needs.
 template <bool kAid, uint32_t kLog2T>
-__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_nrrs_factor(RenderArgs a,
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_nrrs_factor(RenderArgs a,
                                                                                                 NrrsNet net) {
   constexpr uint32_t log2T = kLog2T;  // equal to net.log2T (the launch picks the build)
-  __shared__ float ps[kAid ? kAidParams : kStatParams];
-  __shared__ float pr[kAid ? 1 : kRrsParams];
+  using IS = Img<kAid ? kAidIn : kStatIn, kAid ? 1 : kStatOut>;
+  using IR = Img<kRrsIn, 1>;
+  __shared__ float ps[IS::N];
+  __shared__ float pr[kAid ? 1 : IR::N];
   if constexpr (kAid) {
-    load_lds_t<kAidIn, 1>(ps, net.aid);
+    load_img<kAidIn, 1>(ps, net.aid);
   } else {
-    load_lds_t<kStatIn, kStatOut>(ps, net.stat);
-    load_lds_t<kRrsIn, 1>(pr, net.rrs);
+    load_img<kStatIn, kStatOut>(ps, net.stat);
+    load_img<kRrsIn, 1>(pr, net.rrs);
   }
   __syncthreads();
   const uint32_t n = a.ctl[a.depth].n;
-  for (uint32_t i = blockIdx.x * kT + threadIdx.x; i < n; i += gridDim.x * kT) {
-    // re-read the weights from LDS every vertex instead of hoisting thousands of them
-    asm volatile("" ::: "memory");
-    const float q0 = a.q[i];
-    if (!(q0 > 0.0f)) continue;
-    const float4 dr = a.qin.dir[i];
-    const float g = a.guide[__float_as_uint(dr.w)];
-    if (!(g >= 0.0f)) continue;  // no pixel history: keep the heuristic factor
-    const float4 th = a.qin.thr[i], vp = a.vpos[i], vn = a.vnrm[i];
-    const uint32_t mid = __float_as_uint(vn.w);
-    const float4 m0 = a.sc.mat[2 * mid], m1 = a.sc.mat[2 * mid + 1];
-    float raw[7];
-    vertex_raw(a.sc, vp, dr, m0, __float_as_uint(m1.w), raw);
-    float q;
-    if constexpr (kAid) {
-      float enc[32], z[1];
-      aid_encode(net.table_r, log2T, raw, th.x, th.y, th.z, g, enc);
-      mlp32_t<kAidIn, 1>(ps, enc, z);
-      q = softplus_mod(z[0]);
-    } else {
-      float enc[32], mv[2], x[7], z[1];
-      statnet_encode(net.table, log2T, raw, enc);
-      mlp32_t<kStatIn, kStatOut>(ps, enc, mv);
-      rrs_inputs(mv[0], mv[1], th.x, th.y, th.z, g, raw[6], x);
-      mlp32_t<kRrsIn, 1>(pr, x, z);
-      q = softplus_mod(z[0]);
+  const uint32_t groups = (n + 63) / 64;
+  const uint32_t waves = gridDim.x * (kT / 64);
+  // the group index is the same for the whole wave: every lane reaches the matrix-core code
+  for (uint32_t gi = blockIdx.x * (kT / 64) + threadIdx.x / 64; gi < groups; gi += waves) {
+    asm volatile("" ::: "memory");  // weights re-read from LDS each group, not held in registers
+    const uint32_t i = gi * 64 + __lane_id();
+    bool active = false;
+    float q0 = 0.0f, g = 0.0f, rho = 0.0f;
+    float4 th = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float enc[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) enc[k] = 0.0f;
+    if (i < n) {
+      q0 = a.q[i];
+      if (q0 > 0.0f) {
+        const float4 dr = a.qin.dir[i];
+        const float gp = a.guide[__float_as_uint(dr.w)];
+        if (gp >= 0.0f) {  // else no pixel history: the heuristic factor stays
+          active = true;
+          g = gp;
+          th = a.qin.thr[i];
+          const float4 vp = a.vpos[i], vn = a.vnrm[i];
+          const uint32_t mid = __float_as_uint(vn.w);
+          const float4 m0 = a.sc.mat[2 * mid], m1 = a.sc.mat[2 * mid + 1];
+          float raw[7];
+          vertex_raw(a.sc, vp, dr, m0, __float_as_uint(m1.w), raw);
+          rho = raw[6];
+          if constexpr (kAid) aid_encode(net.table_r, log2T, raw, th.x, th.y, th.z, g, enc);
+          else statnet_encode(net.table, log2T, raw, enc);
+        }
+      }
     }
-    a.q[i] = (q >= 1e-20f && q < 3.0e38f) ? q : q0;
+    float z[1];
+    if constexpr (kAid) {
+      mlp_mfma<kAidIn, 1>(ps, enc, z);
+    } else {
+      float mv[2], x[7];
+      mlp_mfma<kStatIn, kStatOut>(ps, enc, mv);
+      rrs_inputs(mv[0], mv[1], th.x, th.y, th.z, g, rho, x);
+      mlp_mfma<kRrsIn, 1>(pr, x, z);
+    }
+    const float q = softplus_mod(z[0]);
+    if (active) a.q[i] = (q >= 1e-20f && q < 3.0e38f) ? q : q0;
   }
 }
 
+// Test entry points: the same networks on given rows, 64 rows per wave (the grid covers whole
+// waves; rows past n compute on zeros and write nothing).
 __global__ __launch_bounds__(kT) void k_nrrs_rows(const float* raw_in, const float* t, const float* I, uint32_t n,
                                                   NrrsNet net, float* mv_out, float* q_out, float* enc_out) {
-  __shared__ float ps[kStatParams];
-  __shared__ float pr[kRrsParams];
-  load_lds(ps, net.stat, kStatParams);
-  load_lds(pr, net.rrs, kRrsParams);
+  using IS = Img<kStatIn, kStatOut>;
+  using IR = Img<kRrsIn, 1>;
+  __shared__ float ps[IS::N];
+  __shared__ float pr[IR::N];
+  load_img<kStatIn, kStatOut>(ps, net.stat);
+  load_img<kRrsIn, 1>(pr, net.rrs);
   __syncthreads();
   const uint32_t i = blockIdx.x * kT + threadIdx.x;
-  if (i >= n) return;
-  float raw[7];
+  const bool active = i < n;
+  float raw[7], enc[32], tx = 0.0f, ty = 0.0f, tz = 0.0f, Iv = 0.0f;
 #pragma unroll
-  for (int k = 0; k < 7; ++k) raw[k] = raw_in[7ull * i + k];
-  float m, v;
-  const float z = nrrs_z(ps, pr, net.table, net.log2T, raw, t[3ull * i], t[3ull * i + 1], t[3ull * i + 2], I[i], m, v);
-  mv_out[2ull * i] = m;
-  mv_out[2ull * i + 1] = v;
-  q_out[i] = softplus_mod(z);
-  if (enc_out) {
-    float enc[32];
+  for (int k = 0; k < 7; ++k) raw[k] = active ? raw_in[7ull * i + k] : 0.0f;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) enc[k] = 0.0f;
+  if (active) {
+    tx = t[3ull * i];
+    ty = t[3ull * i + 1];
+    tz = t[3ull * i + 2];
+    Iv = I[i];
     statnet_encode(net.table, net.log2T, raw, enc);
+  }
+  float mv[2], x[7], z[1];
+  mlp_mfma<kStatIn, kStatOut>(ps, enc, mv);
+  rrs_inputs(mv[0], mv[1], tx, ty, tz, Iv, raw[6], x);
+  mlp_mfma<kRrsIn, 1>(pr, x, z);
+  if (!active) return;
+  mv_out[2ull * i] = mv[0];
+  mv_out[2ull * i + 1] = mv[1];
+  q_out[i] = softplus_mod(z[0]);
+  if (enc_out) {
 #pragma unroll
     for (int k = 0; k < 32; ++k) enc_out[32ull * i + k] = enc[k];
   }
@@ -379,17 +455,21 @@ __global__ __launch_bounds__(kT) void k_nrrs_rows(const float* raw_in, const flo
 
 __global__ __launch_bounds__(kT) void k_aid_rows(const float* raw_in, const float* t, const float* I, uint32_t n,
                                                  NrrsNet net, float* q_out, float* enc_out) {
-  __shared__ float pa[kAidParams];
-  load_lds(pa, net.aid, kAidParams);
+  using IA = Img<kAidIn, 1>;
+  __shared__ float pa[IA::N];
+  load_img<kAidIn, 1>(pa, net.aid);
   __syncthreads();
   const uint32_t i = blockIdx.x * kT + threadIdx.x;
-  if (i >= n) return;
-  float raw[7];
+  const bool active = i < n;
+  float raw[7], enc[32];
 #pragma unroll
-  for (int k = 0; k < 7; ++k) raw[k] = raw_in[7ull * i + k];
-  float enc[32], h1[32], h2[32], h3[32], z[1];
-  aid_encode(net.table_r, net.log2T, raw, t[3ull * i], t[3ull * i + 1], t[3ull * i + 2], I[i], enc);
-  mlp32<kAidIn, 1>(pa, enc, h1, h2, h3, z);
+  for (int k = 0; k < 7; ++k) raw[k] = active ? raw_in[7ull * i + k] : 0.0f;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) enc[k] = 0.0f;
+  if (active) aid_encode(net.table_r, net.log2T, raw, t[3ull * i], t[3ull * i + 1], t[3ull * i + 2], I[i], enc);
+  float z[1];
+  mlp_mfma<kAidIn, 1>(pa, enc, z);
+  if (!active) return;
   q_out[i] = softplus_mod(z[0]);
   if (enc_out) {
 #pragma unroll
@@ -895,7 +975,7 @@ void launch_factor_t(const RenderArgs& a, const NrrsNet& n, dim3 g, bool aid, hi
 void launch_nrrs_factor(const RenderArgs& a, const NrrsNet& n, uint32_t blocks, bool aid, hipStream_t s) {
   // one build per table size (2^14 .. 2^22 entries per level, the sizes a context accepts):
   // with the level layout known, the dense / hashed choice and the level offsets are constants
-  // and the kernel fits 4 waves per SIMD without spilling
+  // and the kernel fits 5 waves per SIMD without spilling
   const dim3 g(std::max(blocks, 1u));
   switch (n.log2T) {
     case 14: launch_factor_t<14>(a, n, g, aid, s); break;
