@@ -321,7 +321,8 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
   ClaimState cs = claim_start(n, blockIdx.x, kWorkSlices);
   V3 o = v3(0, 0, 0), d = o, inv = o, oi = o;
   float eps = 0.0f;
-  V3 wo = o, wd = o;   // the world ray while the lane walks an instance (kInst)
+  // the world ray while the lane walks an instance (kInst), kept in LDS rather than registers
+  __shared__ float world_lds[kInst ? 6 : 1][kInst ? kTraceThreads : 1];
   uint32_t uoff = 0u;  // primitive id offset of the instance being walked (kInst)
   HitState h;
   // reciprocal direction, -o/d and the slab test's absolute widening of the lane's ray
@@ -345,9 +346,16 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
     st.push(kExitInst);
     const float4* rec = sc.inst + 7ull * first;
     const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2], info = rec[6];
-    wo = o;
-    wd = d;
-    const V3 oc = v3(wo.x - r0.w, wo.y - r1.w, wo.z - r2.w);  // origin minus the translation, first
+    if constexpr (kInst) {
+      world_lds[0][tid] = o.x;
+      world_lds[1][tid] = o.y;
+      world_lds[2][tid] = o.z;
+      world_lds[3][tid] = d.x;
+      world_lds[4][tid] = d.y;
+      world_lds[5][tid] = d.z;
+    }
+    const V3 oc = v3(o.x - r0.w, o.y - r1.w, o.z - r2.w);  // origin minus the translation, first
+    const V3 wd = d;
     o = v3(fmaf(r0.x, oc.x, fmaf(r0.y, oc.y, r0.z * oc.z)), fmaf(r1.x, oc.x, fmaf(r1.y, oc.y, r1.z * oc.z)),
            fmaf(r2.x, oc.x, fmaf(r2.y, oc.y, r2.z * oc.z)));
     d = v3(fmaf(r0.x, wd.x, fmaf(r0.y, wd.y, r0.z * wd.z)), fmaf(r1.x, wd.x, fmaf(r1.y, wd.y, r1.z * wd.z)),
@@ -357,8 +365,10 @@ __device__ __forceinline__ void extend_body(const RenderArgs& a) {
     ni = bits(info.x);
   };
   auto leave_instance = [&]() {
-    o = wo;
-    d = wd;
+    if constexpr (kInst) {
+      o = v3(world_lds[0][tid], world_lds[1][tid], world_lds[2][tid]);
+      d = v3(world_lds[3][tid], world_lds[4][tid], world_lds[5][tid]);
+    }
     prep_ray();
     uoff = 0u;
   };
@@ -583,10 +593,10 @@ __global__ __launch_bounds__(kTraceThreads) __attribute__((amdgpu_waves_per_eu(7
 }
 template <bool kCount>
 __global__ __launch_bounds__(kTraceThreads) void k_extend_immediate(RenderArgs a) { extend_body<0, kCount, false>(a); }
-// Two-level scenes: the world ray kept beside the object-space one needs more registers (105,
-// 4 waves per SIMD, no spills; at 96 registers the parked variants spilled).
+// Two-level scenes: the saved world ray sits in LDS, the instance state in registers (89-94,
+// 5 waves per SIMD, no spills; with the world ray in registers the kernel needed 105).
 template <int kMode, bool kCount>
-__global__ __launch_bounds__(kTraceThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_extend_inst(RenderArgs a) {
+__global__ __launch_bounds__(kTraceThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_extend_inst(RenderArgs a) {
   extend_body<kMode, kCount, true>(a);
 }
 
