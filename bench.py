@@ -346,6 +346,11 @@ def main():
     r.close()
     del r
     torch.cuda.empty_cache()
+    if not args.no_eff:
+        out["log_loss_network"] = log_loss_study(nrrs, sc, torch, W, H, spp, D, prec, args.train_frames,
+                                                 args.eval_renders, reference_once(args.ref_spp), p_train, tuning,
+                                                 out["efficiency"]["heuristic"]["efficiency"])
+        torch.cuda.empty_cache()
     if not args.no_eff and not args.no_nrrs:
         out["nrrs_proper"] = nrrs_proper_study(nrrs, sc, torch, W, H, spp, D, args.nrrs_frames, args.eval_renders,
                                                reference_once(args.ref_spp), p_train, tuning)
@@ -417,6 +422,43 @@ def efficiency(r, nrrs, spp, D, ref_spp, renders, make_reference):
                         "network_depths": [d + 1 for d, m in enumerate(table) if m == mixdepth.NET],
                         "fixed_rate_depths": [d + 1 for d, m in enumerate(table) if m == mixdepth.FIXED]}
     return out
+
+
+def log_loss_study(nrrs, sc, torch, W, H, spp, D, prec, frames, renders, ref, p_train, tuning, heuristic_eff):
+    """The same network, schedule and evaluation as the efficiency study, trained with the squared
+    error of log radiance (the online-training configuration's loss) instead of the relative L2
+    of Eq. (15): relMSE, render time and efficiency over the heuristic of the efficiency study."""
+    rec_n, minibatch = 1 << 18, 1 << 13
+    r = nrrs.Renderer(W, H, s_batch=spp, cap_factor=2.0, seed=0, net_max_depth=4, precision=prec,
+                      records_cap=rec_n, p_train=p_train, max_tris=sc.n_tris, max_materials=len(sc.mat_type),
+                      loss=nrrs.LOSS_LOG_MSE, ema_decay=0.99)
+    r.upload_scene(sc)
+    r.set_tuning(tuning["extend_variant"], tuning["extend_blocks_per_cu"], tuning["extend_refill"],
+                 tuning["extend_leaf_batch"], tuning["extend_chunk"])
+    for f in range(frames):
+        st = r.render(spp, D, nrrs.MODE_NET)
+        n = min(st["records"], rec_n) // minibatch * minibatch
+        if n > 0:
+            r.train_step(n, minibatch, 5e-3)
+    guide = r.get_guide()
+    times, errs = [], []
+    for k in range(renders):
+        r.set_guide(guide)
+        r.reset_image()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r.render(spp, D, nrrs.MODE_NET, stats=False)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        img, _ = r.read_image()
+        errs.append(relmse(img, ref))
+    r.close()
+    rm, t = float(np.mean(errs)), float(np.median(times))
+    eff = 1.0 / (rm * t)
+    print(f"# log-loss network: relMSE {rm:.4f}, {t * 1e3:.2f} ms, {eff / heuristic_eff:.3f}x heuristic", flush=True)
+    return {"loss": "squared error of log radiance", "trained_frames": frames, "relmse": rm,
+            "relmse_se": float(np.std(errs) / np.sqrt(len(errs))), "render_s": round(t, 5), "efficiency": eff,
+            "over_heuristic": eff / heuristic_eff}
 
 
 def nrrs_proper_study(nrrs, sc, torch, W, H, spp, D, frames, renders, ref, p_train, tuning):
@@ -701,8 +743,16 @@ def cpu_baseline(sc, W, H, D, passes=16):
     t0 = time.perf_counter()
     o = oracle.render(osc, cfg)
     secs = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": round(o["rays"] / secs / 1e6, 3), "unit": "Mpaths/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "seconds": round(secs, 2),
+            "kind": "oracle", "seconds": round(secs, 2), "cpu_model": cpu,
             "sample": f"{passes} spp of the same {W}x{H} heightfield workload ({passes} passes of one {W * H}-path "
                       f"wavefront, max depth {D}, heuristic normalized RRS), FP64 C oracle with OpenMP; BVH build "
                       "excluded"}
