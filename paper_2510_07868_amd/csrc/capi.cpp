@@ -742,8 +742,8 @@ int32_t check_common(nrrs_ctx* c, const uint32_t* mat_type, const float* mat_par
   return NRRS_OK;
 }
 
-// Triangles of one tree into h.tri, in the tree's order, starting at slot first; tag = the
-// original index (stored_index false) or the slot itself (true).
+// Appends the triangles of one tree to h.tri in the tree's order; the tag (a0.w) is the
+// triangle's original index (stored_index false) or its own slot in h.tri (true).
 void append_tris(SceneHost& h, const float* verts, const uint32_t* tris, const uint32_t* tri_mat, const BvhOut& b,
                  bool stored_index) {
   const uint32_t first = (uint32_t)(h.tri.size() / 12);
@@ -821,7 +821,8 @@ int32_t nrrs_upload_scene_instanced(nrrs_ctx* c, const float* verts, uint64_t nv
   if (ninst >= (1u << 26)) return fail(c, NRRS_EINVAL, "too many instances");
   const uint64_t n_rec = ninst + (nt ? 1 : 0);
   if (nt + mesh_nt + 3 * n_rec > c->max_tris) return fail(c, NRRS_ENOMEM, "scene larger than the bound workspace");
-  if (nt && check_mesh(c, verts, nv, tris, nt, tri_mat, nm)) return NRRS_EINVAL;
+  if (nt)
+    if (int32_t e = check_mesh(c, verts, nv, tris, nt, tri_mat, nm)) return e;
   if (int32_t e = check_mesh(c, in->mesh_verts, in->mesh_nv, in->mesh_tris, mesh_nt, in->mesh_tri_mat, nm)) return e;
   uint64_t flat = nt;
   for (uint32_t j = 0; j < ninst; ++j) {
