@@ -334,6 +334,31 @@ def instance_field(seed: int = 0, n: int = 64) -> InstancedScene:
     return b.build_instanced("instance_field", cam, 0.05)
 
 
+def instances_only(seed: int = 0) -> InstancedScene:
+    """No base mesh: a floor (a flattened unit box), 24 boxes and two emitting quads, all
+    instances — the quads of one emitting mesh placed twice, so that the light list is made of
+    instance triangles."""
+    rng = np.random.default_rng(seed)
+    b = _Builder()
+    grey = b.material(MAT_LAMBERT, 0.6)
+    light = b.material(MAT_EMITTER, 0.0, 1.0, 12.0)
+    box = b.unit_box_mesh()
+    # a unit quad in the xz plane facing -y (down), emitting
+    quad = b.object_mesh([[-0.5, 0.0, -0.5], [0.5, 0.0, -0.5], [0.5, 0.0, 0.5], [-0.5, 0.0, 0.5]],
+                         [[0, 1, 2], [0, 2, 3]], light)
+    b.instance(box, _yaw_box_xform((2.0, -0.05, 2.0), (4.0, 0.1, 4.0), 0.0), grey)
+    for _ in range(24):
+        sx, sy, sz = rng.uniform(0.1, 0.6, size=3)
+        x, z = rng.uniform(0.3, 3.7, size=2)
+        m = b.material(MAT_GGX, rng.uniform(0.2, 0.9, size=3), float(rng.uniform(0.1, 0.5))) if rng.uniform() < 0.3 \
+            else b.material(MAT_LAMBERT, rng.uniform(0.1, 0.9, size=3))
+        b.instance(box, _yaw_box_xform((x, sy / 2, z), (sx, sy, sz), float(rng.uniform(0, 2 * math.pi))), m)
+    for c in ((1.2, 2.5, 1.5), (2.8, 2.5, 2.6)):
+        b.instance(quad, _yaw_box_xform(c, (0.7, 1.0, 0.7), 0.3))
+    cam = (2.0, 1.6, -2.0, 2.0, 0.4, 2.0, 0.0, 1.0, 0.0, 55.0)
+    return b.build_instanced("instances_only", cam, 0.02)
+
+
 def furnace(albedo: float = 0.7, emission: float = 1.0) -> Scene:
     """Closed grey box plus the Cornell boxes; every surface reflects ``albedo`` and emits ``emission``."""
     b = _Builder()
@@ -506,5 +531,6 @@ SCENES = {
     "cornell_instanced": cornell_instanced,
     "instance_field": instance_field,
     "terrain5m_instanced": terrain5m_instanced,
+    "instances_only": instances_only,
 }
 

@@ -6,7 +6,8 @@ oracle traces the flattened world-space triangles.  Closest hits: same triangle 
 flattened numbering) and t within 1e-5 (plus the effect of the flattened corners' float32
 rounding) outside the oracle's near-ties, for every traversal
 variant available to such scenes; per-path radiance within 1e-4 relative up to each path's
-first near-tie decision, with and without next-event estimation.
+first near-tie decision, with and without next-event estimation, also for a scene made of
+instances only (its lights too).
 """
 import numpy as np
 import pytest
@@ -62,7 +63,7 @@ def _rays(sc, n, seed):
     return np.concatenate([o, d], 1).astype(np.float32)
 
 
-@pytest.mark.parametrize("name", ["cornell_instanced", "instance_field"])
+@pytest.mark.parametrize("name", ["cornell_instanced", "instance_field", "instances_only"])
 def test_instanced_closest_hits_match_the_flattened_oracle(O, nrrs_mod, scenes, name):
     isc = getattr(scenes, name)()
     flat = isc.flatten()
@@ -140,7 +141,8 @@ def _compare_paths(gp, o, D, rtol=1e-4):
 
 @pytest.mark.parametrize("name,mode,nee", [("cornell_instanced", 0, 0), ("cornell_instanced", 1, 0),
                                            ("cornell_instanced", 1, 1), ("instance_field", 1, 0),
-                                           ("instance_field", 1, 1)])
+                                           ("instance_field", 1, 1), ("instances_only", 1, 0),
+                                           ("instances_only", 1, 1)])
 def test_instanced_paths_match_the_flattened_oracle(O, nrrs_mod, scenes, name, mode, nee):
     # every primary path of a 64x64, 4-spp pass against the oracle on the flattened scene at
     # 1e-4 relative up to its first near-tie decision
