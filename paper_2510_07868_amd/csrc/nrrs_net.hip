@@ -544,86 +544,61 @@ __device__ __forceinline__ void tback(const float* __restrict__ W, const float (
 }
 
 // Per-record layer inputs of a block in LDS: H[0] = x, H[1..3] = hidden activations; D = deltas.
+// LDS of a gradient block: one layer's inputs and that layer's deltas, a row per record (the
+// hidden activations stay in the records' registers between the forward and the backward, so
+// the two tiles serve every layer in turn and several blocks fit a CU).
 struct GradTiles {
-  float H[4][kTG * kPad];
-  float D[kTG * kPad];
+  float A[kTG * kPad];
+  float D[kTG * kPad];  // also the block's loss scratch
 };
 
-// Forward of the block's rows, keeping each layer's input in its LDS row; returns the outputs.
+// Backward of the block's rows from the output gradients dy, given each record's inputs x and
+// hidden activations h1..h3 (as mlp32 leaves them): the block's weight gradients (layer-by-layer
+// outer products of deltas and layer inputs) into `part`; dL/dx into dx.
 template <int IN, int OUT>
-__device__ __forceinline__ void forward_rows(const float* P, const float (&x)[IN], GradTiles& t, float (&y)[OUT]) {
+__device__ __forceinline__ void backward_rows(const float* P, const float (&x)[IN], const float (&h1)[32],
+                                              const float (&h2)[32], const float (&h3)[32], const float (&dy)[OUT],
+                                              GradTiles& t, float* part, float (&dx)[IN]) {
   using Lo = L32<IN, OUT>;
-  put_row(t.H[0], x);
-  {
-    float h[32];
-    hidden<IN>(P + Lo::W1, P + Lo::B1, x, h);
-    put_row(t.H[1], h);
-  }
-  asm volatile("" ::: "memory");
-  {
-    float a[32], h[32];
-    get_row(t.H[1], a);
-    hidden<32>(P + Lo::W2, P + Lo::B2, a, h);
-    put_row(t.H[2], h);
-  }
-  asm volatile("" ::: "memory");
-  float a[32], h[32];
-  get_row(t.H[2], a);
-  hidden<32>(P + Lo::W3, P + Lo::B3, a, h);
-  put_row(t.H[3], h);
-#pragma unroll
-  for (int k = 0; k < OUT; ++k) {
-    float acc = P[Lo::B4 + k];
-#pragma unroll
-    for (int i = 0; i < 32; ++i) acc = fmaf(P[Lo::W4 + 32 * k + i], h[i], acc);
-    y[k] = acc;
-  }
-}
-
-// Backward of the block's rows from the output gradients dy: the block's weight gradients
-// (layer-by-layer outer products of deltas and layer inputs) into `part`; dL/dx into dx.
-template <int IN, int OUT>
-__device__ __forceinline__ void backward_rows(const float* P, const float (&dy)[OUT], GradTiles& t, float* part,
-                                              float (&dx)[IN]) {
-  using Lo = L32<IN, OUT>;
-  float d[32], h[32];
-  get_row(t.H[3], h);
+  float d[32];
 #pragma unroll
   for (int i = 0; i < 32; ++i) {
     float s = 0.0f;
 #pragma unroll
     for (int k = 0; k < OUT; ++k) s = fmaf(P[Lo::W4 + 32 * k + i], dy[k], s);
-    d[i] = s * dleaky(h[i]);
+    d[i] = s * dleaky(h3[i]);
   }
+  put_row(t.A, h3);
   put_row(t.D, dy);
   __syncthreads();
-  tile_outer<OUT, 32>(t.H[3], t.D, part + Lo::W4, part + Lo::B4);
+  tile_outer<OUT, 32>(t.A, t.D, part + Lo::W4, part + Lo::B4);
   __syncthreads();
+  put_row(t.A, h2);
   put_row(t.D, d);  // delta of hidden layer 3
   __syncthreads();
-  tile_outer<32, 32>(t.H[2], t.D, part + Lo::W3, part + Lo::B3);
+  tile_outer<32, 32>(t.A, t.D, part + Lo::W3, part + Lo::B3);
   __syncthreads();
   {
     float g[32];
     tback<32>(P + Lo::W3, d, g);
-    get_row(t.H[2], h);
 #pragma unroll
-    for (int i = 0; i < 32; ++i) d[i] = g[i] * dleaky(h[i]);
+    for (int i = 0; i < 32; ++i) d[i] = g[i] * dleaky(h2[i]);
   }
+  put_row(t.A, h1);
   put_row(t.D, d);  // delta of hidden layer 2
   __syncthreads();
-  tile_outer<32, 32>(t.H[1], t.D, part + Lo::W2, part + Lo::B2);
+  tile_outer<32, 32>(t.A, t.D, part + Lo::W2, part + Lo::B2);
   __syncthreads();
   {
     float g[32];
     tback<32>(P + Lo::W2, d, g);
-    get_row(t.H[1], h);
 #pragma unroll
-    for (int i = 0; i < 32; ++i) d[i] = g[i] * dleaky(h[i]);
+    for (int i = 0; i < 32; ++i) d[i] = g[i] * dleaky(h1[i]);
   }
+  put_row(t.A, x);
   put_row(t.D, d);  // delta of hidden layer 1
   __syncthreads();
-  tile_outer<32, IN>(t.H[0], t.D, part + Lo::W1, part + Lo::B1);
+  tile_outer<32, IN>(t.A, t.D, part + Lo::W1, part + Lo::B1);
   __syncthreads();
   tback<IN>(P + Lo::W1, d, dx);
 }
@@ -648,6 +623,48 @@ __device__ __forceinline__ void load_raw(const NrrsRows& r, uint32_t row, float 
   I = p[7];
 }
 
+// Hash-grid gradient scatter of one level for the wave's records: (a, b) times each corner's
+// weight added at the corner's two features.  The coarse levels are shared by many records (at
+// level 0 every corner collects hundreds per step), so there the wave first adds the values of
+// lanes with the same corner and issues one atomic per distinct corner; at the fine levels each
+// lane adds its own.  (Per-lane atomics already add in no fixed order.)
+constexpr int kAggLevels = 3;
+__device__ __forceinline__ void scatter_level(float* gl, const Corner8& c, float a, float b, bool on, int l) {
+  if (l >= kAggLevels) {
+    if (on) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        atomicAdd(gl + 2ull * c.idx[k], c.w[k] * a);
+        atomicAdd(gl + 2ull * c.idx[k] + 1, c.w[k] * b);
+      }
+    }
+    return;
+  }
+  const uint32_t lane = __lane_id();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t idx = c.idx[k];
+    const float va = c.w[k] * a, vb = c.w[k] * b;
+    uint64_t pending = __ballot(on);
+    while (pending) {  // wave-uniform: one round per distinct corner among the pending lanes
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const uint32_t key = (uint32_t)__shfl((int)idx, leader);
+      const bool mine = ((pending >> lane) & 1ull) && idx == key;
+      float sa = mine ? va : 0.0f, sb = mine ? vb : 0.0f;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        sa += __shfl_xor(sa, o);
+        sb += __shfl_xor(sb, o);
+      }
+      if ((int)lane == leader) {
+        atomicAdd(gl + 2ull * key, sa);
+        atomicAdd(gl + 2ull * key + 1, sb);
+      }
+      pending &= ~__ballot(mine);
+    }
+  }
+}
+
 __global__ __launch_bounds__(kTG) void k_statnet_grad(NrrsRows r, const float* stat, const float* table, uint32_t log2T,
                                                       float eps, float* partial, float* loss_part, float* gtable) {
   __shared__ float ps[kStatParams];
@@ -666,12 +683,9 @@ __global__ __launch_bounds__(kTG) void k_statnet_grad(NrrsRows r, const float* s
       L = r.target[row];
     }
   }
-  float mv[2];
-  {
-    float enc[32];
-    statnet_encode(table, log2T, raw, enc);
-    forward_rows<kStatIn, kStatOut>(ps, enc, t, mv);
-  }
+  float mv[2], enc[32], h1[32], h2[32], h3[32];
+  statnet_encode(table, log2T, raw, enc);
+  mlp32<kStatIn, kStatOut>(ps, enc, h1, h2, h3, mv);
   const float inv_n = 1.0f / (float)r.n;
   const float em = mv[0] - L;
   const float v1 = (L - mv[0]) * (L - mv[0]);  // one-sample variance about sg(m)
@@ -681,20 +695,15 @@ __global__ __launch_bounds__(kTG) void k_statnet_grad(NrrsRows r, const float* s
   dy[1] = valid ? 2.0f * ev / (v1 * v1 + eps) * inv_n : 0.0f;
   const float li = valid ? (em * em / (L * L + eps) + ev * ev / (v1 * v1 + eps)) * inv_n : 0.0f;
   float denc[32];
-  backward_rows<kStatIn, kStatOut>(ps, dy, t, partial + (uint64_t)blockIdx.x * kStatParams, denc);
+  backward_rows<kStatIn, kStatOut>(ps, enc, h1, h2, h3, dy, t, partial + (uint64_t)blockIdx.x * kStatParams, denc);
   block_loss(li, t.D, loss_part + blockIdx.x);
-  if (valid) {
+  {
     const uint64_t T = 1ull << log2T;
 #pragma unroll
     for (int l = 0; l < kHgLevels; ++l) {
       Corner8 c;
       hg_corners(raw[0], raw[1], raw[2], l, log2T, c);
-      float* gl = gtable + (uint64_t)l * T * kHgFeat;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        atomicAdd(gl + 2ull * c.idx[k], c.w[k] * denc[2 * l]);
-        atomicAdd(gl + 2ull * c.idx[k] + 1, c.w[k] * denc[2 * l + 1]);
-      }
+      scatter_level(gtable + (uint64_t)l * T * kHgFeat, c, denc[2 * l], denc[2 * l + 1], valid, l);
     }
   }
 }
@@ -724,9 +733,9 @@ __global__ __launch_bounds__(kTG) void k_rrsnet_grad(NrrsRows r, const float* st
     statnet_encode(table, log2T, raw, enc);
     mlp32<kStatIn, kStatOut>(ps, enc, h1, h2, h3, mv);
   }
-  float x[7], z[1];
+  float x[7], z[1], g1[32], g2[32], g3[32];
   rrs_inputs(mv[0], mv[1], tq.x, tq.y, tq.z, I, raw[6], x);
-  forward_rows<kRrsIn, 1>(pr, x, t, z);
+  mlp32<kRrsIn, 1>(pr, x, g1, g2, g3, z);
   const float q = softplus_mod(z[0]);
   float dq = 0.0f, li = 0.0f;
   if (valid) {
@@ -750,7 +759,7 @@ __global__ __launch_bounds__(kTG) void k_rrsnet_grad(NrrsRows r, const float* st
   }
   float dy[1] = {dq * softplus_mod_grad(z[0])};
   float dx[7];
-  backward_rows<kRrsIn, 1>(pr, dy, t, partial + (uint64_t)blockIdx.x * kRrsParams, dx);
+  backward_rows<kRrsIn, 1>(pr, x, g1, g2, g3, dy, t, partial + (uint64_t)blockIdx.x * kRrsParams, dx);
   block_loss(li, t.D, loss_part + blockIdx.x);
 }
 
@@ -780,12 +789,9 @@ __global__ __launch_bounds__(kTG) void k_aid_grad(NrrsRows r, const float* stat,
     mlp32<kStatIn, kStatOut>(ps, enc, h1, h2, h3, mv);
   }
   asm volatile("" ::: "memory");
-  float z[1];
-  {
-    float enc[32];
-    aid_encode(table_r, log2T, raw, tq.x, tq.y, tq.z, I, enc);
-    forward_rows<kAidIn, 1>(pa, enc, t, z);
-  }
+  float z[1], enc[32], g1[32], g2[32], g3[32];
+  aid_encode(table_r, log2T, raw, tq.x, tq.y, tq.z, I, enc);
+  mlp32<kAidIn, 1>(pa, enc, g1, g2, g3, z);
   const float q = softplus_mod(z[0]);
   float dq = 0.0f, li = 0.0f;
   if (valid) {
@@ -809,20 +815,16 @@ __global__ __launch_bounds__(kTG) void k_aid_grad(NrrsRows r, const float* stat,
   }
   float dy[1] = {dq * softplus_mod_grad(z[0])};
   float dx[32];
-  backward_rows<kAidIn, 1>(pa, dy, t, partial + (uint64_t)blockIdx.x * kAidParams, dx);
+  backward_rows<kAidIn, 1>(pa, enc, g1, g2, g3, dy, t, partial + (uint64_t)blockIdx.x * kAidParams, dx);
   block_loss(li, t.D, loss_part + blockIdx.x);
-  if (valid && dy[0] != 0.0f) {
+  {
     const uint64_t T = 1ull << log2T;
+    const bool on = valid && dy[0] != 0.0f;
 #pragma unroll
     for (int l = 0; l < kHgLevels; ++l) {
       Corner8 c;
       hg_corners(raw[0], raw[1], raw[2], l, log2T, c);
-      float* gl = gtable_r + (uint64_t)l * T * kHgFeat;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        atomicAdd(gl + 2ull * c.idx[k], c.w[k] * dx[2 * l]);
-        atomicAdd(gl + 2ull * c.idx[k] + 1, c.w[k] * dx[2 * l + 1]);
-      }
+      scatter_level(gtable_r + (uint64_t)l * T * kHgFeat, c, dx[2 * l], dx[2 * l + 1], on, l);
     }
   }
 }
