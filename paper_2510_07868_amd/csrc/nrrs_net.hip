@@ -370,35 +370,54 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(5, 8))) void
   const uint32_t n = a.ctl[a.depth].n;
   const uint32_t groups = (n + 63) / 64;
   const uint32_t waves = gridDim.x * (kT / 64);
-  // the group index is the same for the whole wave: every lane reaches the matrix-core code
-  for (uint32_t gi = blockIdx.x * (kT / 64) + threadIdx.x / 64; gi < groups; gi += waves) {
+  const uint32_t lane = __lane_id();
+  // Entries that take the learned factor (q > 0 and a pixel with history) are gathered per wave
+  // into full groups of 64 before the encodings and the matrix-core layers: a third to a half of
+  // a bounce's queue is paths that just ended, and a group computes all 64 columns either way.
+  // A column's result does not depend on the other columns of its tile.
+  __shared__ uint32_t pick[kT / 64][128];
+  uint32_t* const buf = pick[threadIdx.x / 64];
+  uint32_t gi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kT / 64) + threadIdx.x / 64));
+  uint32_t cnt = 0;  // gathered entries not yet computed (wave-uniform, below 128)
+  for (;;) {
+    while (cnt < 64 && gi < groups) {
+      const uint32_t j = gi * 64 + lane;
+      bool take = false;
+      if (j < n && a.q[j] > 0.0f) take = a.guide[__float_as_uint(a.qin.dir[j].w)] >= 0.0f;
+      const uint64_t m = __ballot(take);
+      if (take) buf[cnt + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = j;
+      cnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)(cnt + (uint32_t)__popcll(m)));
+      gi += waves;
+    }
+    if (cnt == 0) break;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const bool active = lane < cnt;
+    const uint32_t i = active ? buf[lane] : 0u;
+    const bool moves = lane + 64 < cnt;
+    const uint32_t rest = moves ? buf[lane + 64] : 0u;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (moves) buf[lane] = rest;  // the entries past the first 64 move to the front
+    cnt = cnt > 64 ? cnt - 64 : 0;
     asm volatile("" ::: "memory");  // weights re-read from LDS each group, not held in registers
-    const uint32_t i = gi * 64 + __lane_id();
-    bool active = false;
-    float q0 = 0.0f, g = 0.0f, rho = 0.0f;
+    float g = 0.0f, rho = 0.0f;
     float4 th = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     float enc[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k) enc[k] = 0.0f;
-    if (i < n) {
-      q0 = a.q[i];
-      if (q0 > 0.0f) {
-        const float4 dr = a.qin.dir[i];
-        const float gp = a.guide[__float_as_uint(dr.w)];
-        if (gp >= 0.0f) {  // else no pixel history: the heuristic factor stays
-          active = true;
-          g = gp;
-          th = a.qin.thr[i];
-          const float4 vp = a.vpos[i], vn = a.vnrm[i];
-          const uint32_t mid = __float_as_uint(vn.w);
-          const float4 m0 = a.sc.mat[2 * mid], m1 = a.sc.mat[2 * mid + 1];
-          float raw[7];
-          vertex_raw(a.sc, vp, dr, m0, __float_as_uint(m1.w), raw);
-          rho = raw[6];
-          if constexpr (kAid) aid_encode(net.table_r, log2T, raw, th.x, th.y, th.z, g, enc);
-          else statnet_encode(net.table, log2T, raw, enc);
-        }
-      }
+    if (active) {
+      const float4 dr = a.qin.dir[i];
+      g = a.guide[__float_as_uint(dr.w)];
+      if constexpr (kAid) th = a.qin.thr[i];
+      const float4 vp = a.vpos[i], vn = a.vnrm[i];
+      const uint32_t mid = __float_as_uint(vn.w);
+      const float4 m0 = a.sc.mat[2 * mid], m1 = a.sc.mat[2 * mid + 1];
+      float raw[7];
+      vertex_raw(a.sc, vp, dr, m0, __float_as_uint(m1.w), raw);
+      rho = raw[6];
+      if constexpr (kAid) aid_encode(net.table_r, log2T, raw, th.x, th.y, th.z, g, enc);
+      else statnet_encode(net.table, log2T, raw, enc);
     }
     float z[1];
     if constexpr (kAid) {
@@ -406,11 +425,12 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(5, 8))) void
     } else {
       float mv[2], x[7];
       mlp_mfma<kStatIn, kStatOut>(ps, enc, mv);
+      if (active) th = a.qin.thr[i];  // read after StatNet: not held through its layers
       rrs_inputs(mv[0], mv[1], th.x, th.y, th.z, g, rho, x);
       mlp_mfma<kRrsIn, 1>(pr, x, z);
     }
     const float q = softplus_mod(z[0]);
-    if (active) a.q[i] = (q >= 1e-20f && q < 3.0e38f) ? q : q0;
+    if (active && q >= 1e-20f && q < 3.0e38f) a.q[i] = q;  // else the heuristic factor stays
   }
 }
 
