@@ -189,8 +189,10 @@ def _he(rng, n_in, n_out):
     return np.concatenate(p).astype(np.float32)
 
 
-@pytest.mark.parametrize("log2t", [LOG2T, 19])  # (19: the benchmark's table size)
-def test_nrrs_cornell_paths_match_oracle(O, nrrs_mod, scenes, log2t):
+# (19: the benchmark's table size; history 0.5: half the pixels, at random, have no history and
+# keep the heuristic factor, so the kernel's groups gather live entries from ragged runs)
+@pytest.mark.parametrize("log2t,history", [(LOG2T, 1.0), (19, 1.0), (LOG2T, 0.5)])
+def test_nrrs_cornell_paths_match_oracle(O, nrrs_mod, scenes, log2t, history):
     # every primary path of a 64x64, 4-spp Cornell pass in NRRS mode (StatNet + RRSNet factors at
     # depths 1-4) against the oracle on the same random numbers, at 1e-4 relative, up to the depth
     # of its first near-tie decision (the oracle widens the roulette's near-tie margin by the
@@ -207,6 +209,7 @@ def test_nrrs_cornell_paths_match_oracle(O, nrrs_mod, scenes, log2t):
     Pr[-1] = 2.0 * (1.0 - np.log(2.0))  # factors around 1
     T = rng.uniform(-0.3, 0.3, size=8 * 2 * (1 << log2t)).astype(np.float32)
     guide = rng.uniform(0.02, 2.0, size=W * H).astype(np.float32)
+    guide[rng.random(W * H) >= history] = -1.0  # no history: the heuristic factor stays
     r.set_nrrs_params(Ps, Pr, T)
     r.set_guide(guide)
     r.set_trace(True)
@@ -285,8 +288,8 @@ def test_aid_gradients_match_oracle(N, nrrs_mod, scenes, step):
     r.close()
 
 
-@pytest.mark.parametrize("log2t", [LOG2T, 19])
-def test_aid_cornell_paths_match_oracle(O, nrrs_mod, scenes, log2t):
+@pytest.mark.parametrize("log2t,history", [(LOG2T, 1.0), (19, 1.0), (LOG2T, 0.5)])
+def test_aid_cornell_paths_match_oracle(O, nrrs_mod, scenes, log2t, history):
     # the AID-NRRS factor in a 64x64, 4-spp Cornell pass, path by path against the oracle
     from test_gpu_parity import _compare_paths, _report_paths
     W = H = 64
@@ -300,6 +303,7 @@ def test_aid_cornell_paths_match_oracle(O, nrrs_mod, scenes, log2t):
     Pa[-1] = 2.0 * (1.0 - np.log(2.0))
     Tr = rng.uniform(-0.3, 0.3, size=8 * 2 * (1 << log2t)).astype(np.float32)
     guide = rng.uniform(0.02, 2.0, size=W * H).astype(np.float32)
+    guide[rng.random(W * H) >= history] = -1.0
     r.set_aid_params(Pa, Tr)
     r.set_guide(guide)
     r.set_trace(True)
